@@ -1,0 +1,205 @@
+"""Pins of the oracle's edge intersections (eq. 3-4 of the paper).
+
+For an axis edge st with Inside[s] != Inside[t] the record holds
+lambda = 1 - u*, where u* is the first parameter along s + u (t - s) at which
+the label changes, the outward unit normal there and the patch that carries
+it.  Checked against: closed-form roots for one sphere and for the saddle of
+two atoms, the label function alone (bisection, no surfaces involved), the
+gradient of the distance to the admissible probe set, and volume and area
+integrals.
+"""
+import math
+
+import numpy as np
+import pytest
+
+RHO = 1.4
+
+
+def grid_axes(lo, h, dims):
+    return [lo[a] + np.arange(dims[a]) * h for a in range(3)]
+
+
+def key_to_points(keys, lo, h, dims):
+    nx, ny, nz = dims
+    axis = keys % 3
+    idx = keys // 3
+    i = idx % nx
+    j = (idx // nx) % ny
+    k = idx // (nx * ny)
+    s = np.stack([lo[0] + i * h, lo[1] + j * h, lo[2] + k * h], axis=1)
+    e = np.eye(3)[axis]
+    return s, e, axis
+
+
+def test_single_sphere_roots_and_normals(oracle_mod):
+    c = np.array([0.1, -0.23, 0.37])
+    r = 1.6
+    o = oracle_mod.Oracle(c[None], [r], RHO)
+    lo = np.array([-4.0, -4.0, -4.0])
+    h = 0.2
+    dims = (41, 41, 41)
+    L = o.labels_grid(lo, h, dims)
+    keys = oracle_mod.crossing_keys(L)
+    rec = o.edges(lo, h, dims, keys)
+    assert np.all(rec["status"] == 1) and np.all(rec["type"] == 1)
+    s, e, axis = key_to_points(keys, lo, h, dims)
+    w = s - c
+    # |w + u h e|^2 = r^2; the root inside [0, 1]
+    b = 2 * h * np.sum(w * e, axis=1)
+    cc = np.sum(w * w, axis=1) - r * r
+    disc = b * b - 4 * h * h * cc
+    u1 = (-b - np.sqrt(disc)) / (2 * h * h)
+    u2 = (-b + np.sqrt(disc)) / (2 * h * h)
+    u = np.where((u1 >= 0) & (u1 <= 1), u1, u2)
+    assert np.allclose(1 - rec["lam"], u, atol=1e-12)
+    p = s + (u * h)[:, None] * e
+    assert np.allclose(rec["normal"], (p - c) / r, atol=1e-12)
+    assert np.all(rec["atoms"][:, 0] == 0)
+
+
+def test_two_atom_saddle_roots_closed_form(oracle_mod):
+    """Atoms on the x axis: on an x-edge that meets the saddle, the root lies
+    on the profile circle of radius rho around (a, R):
+    xi = a -+ sqrt(rho^2 - (eta - R)^2)."""
+    r1, r2, d = 1.7, 1.55, 3.9
+    s1, s2 = r1 + RHO, r2 + RHO
+    c = np.array([[0.0, 0.0, 0.0], [d, 0.0, 0.0]])
+    o = oracle_mod.Oracle(c, [r1, r2], RHO)
+    a = (s1 * s1 - s2 * s2 + d * d) / (2 * d)
+    R = math.sqrt(s1 * s1 - a * a)
+    lo = np.array([-4.0, -4.03, -4.07])
+    h = 0.1
+    dims = (int(round((d + 8) / h)) + 1, 82, 82)
+    L = o.labels_grid(lo, h, dims)
+    keys = oracle_mod.crossing_keys(L)
+    rec = o.edges(lo, h, dims, keys)
+    sad = (rec["type"] == 2) & (keys % 3 == 0)
+    assert sad.sum() > 50
+    s, e, _ = key_to_points(keys[sad], lo, h, dims)
+    eta = np.hypot(s[:, 1], s[:, 2])
+    u = 1 - rec["lam"][sad]
+    xi = s[:, 0] + u * h
+    off = np.sqrt(RHO * RHO - (eta - R) ** 2)
+    err = np.minimum(np.abs(xi - (a - off)), np.abs(xi - (a + off)))
+    assert np.max(err) < 1e-9
+    # normal towards the probe centre on the circle
+    p = s + (u * h)[:, None] * e
+    q = np.stack([np.full(len(p), a), R * p[:, 1] / eta, R * p[:, 2] / eta], axis=1)
+    want = (q - p) / np.linalg.norm(q - p, axis=1, keepdims=True)
+    assert np.allclose(rec["normal"][sad], want, atol=1e-9)
+
+
+def _molecule(n, seed, h):
+    from eses_inputs import molecule
+    return molecule(n, seed, h)
+
+
+@pytest.mark.parametrize("n,seed,h", [(40, 21, 0.35), (120, 22, 0.5)])
+def test_edges_against_label_bisection(oracle_mod, n, seed, h):
+    """u* from bisection of the label function alone (no surface enumeration)."""
+    m = _molecule(n, seed, h)
+    o = oracle_mod.Oracle(m.centres, m.radii, m.probe)
+    L = o.labels_grid(m.lo, m.spacing, m.dims)
+    keys = oracle_mod.crossing_keys(L)
+    rng = np.random.default_rng(seed)
+    pick = np.sort(rng.choice(len(keys), size=min(800, len(keys)), replace=False))
+    keys = keys[pick]
+    rec = o.edges(m.lo, m.spacing, m.dims, keys)
+    assert np.all(rec["status"] == 1)
+    assert set(np.unique(rec["type"])) == {1, 2, 3}
+    s, e, _ = key_to_points(keys, m.lo, m.spacing, m.dims)
+    K = 256
+    us = np.linspace(0.0, 1.0, K + 1)
+    pts = s[:, None, :] + (us[None, :, None] * m.spacing) * e[:, None, :]
+    lab = o.labels_points(pts.reshape(-1, 3)).reshape(len(keys), K + 1)
+    first = np.argmax(lab != lab[:, :1], axis=1)
+    assert np.all(lab[np.arange(len(keys)), first] != lab[:, 0])
+    lo_u = us[first - 1]
+    hi_u = us[first]
+    L0 = lab[:, 0]
+    for _ in range(48):
+        mid = 0.5 * (lo_u + hi_u)
+        lm = o.labels_points(s + (mid * m.spacing)[:, None] * e)
+        same = lm == L0
+        lo_u = np.where(same, mid, lo_u)
+        hi_u = np.where(same, hi_u, mid)
+    ustar = 1 - rec["lam"]
+    # an interval of 1/256 can hide two crossings; the oracle reports the first
+    # change, so it may only be at or before the sampled one
+    close = np.abs(ustar - 0.5 * (lo_u + hi_u)) * m.spacing < 1e-9
+    assert close.mean() > 0.995
+    assert np.all(ustar <= hi_u + 1e-12)
+
+
+def test_normals_are_distance_gradients(oracle_mod):
+    """At a surface point the outward normal is -grad dist(x, A)."""
+    m = _molecule(80, 31, 0.45)
+    o = oracle_mod.Oracle(m.centres, m.radii, m.probe)
+    L = o.labels_grid(m.lo, m.spacing, m.dims)
+    keys = oracle_mod.crossing_keys(L)
+    rng = np.random.default_rng(2)
+    keys = np.sort(rng.choice(keys, size=600, replace=False))
+    rec = o.edges(m.lo, m.spacing, m.dims, keys)
+    s, e, _ = key_to_points(keys, m.lo, m.spacing, m.dims)
+    p = s + ((1 - rec["lam"]) * m.spacing)[:, None] * e
+    eps = 1e-6
+    grad = np.zeros_like(p)
+    for a in range(3):
+        dp = np.zeros(3)
+        dp[a] = eps
+        fp, _ = o.dist_points(p + dp, 10.0)
+        fm, _ = o.dist_points(p - dp, 10.0)
+        grad[:, a] = (fp - fm) / (2 * eps)
+    dist, _ = o.dist_points(p, 10.0)
+    on = np.abs(dist - RHO) < 1e-9
+    assert on.mean() > 0.99
+    smooth = on & (np.abs(np.linalg.norm(grad, axis=1) - 1) < 1e-3)
+    assert smooth.mean() > 0.95
+    assert np.allclose(rec["normal"][smooth], -grad[smooth], atol=2e-4)
+    assert np.allclose(np.linalg.norm(rec["normal"], axis=1), 1.0, atol=1e-12)
+
+
+def line_volume(L, keys, lam, h, axis):
+    """Volume from crossings along lines of one axis: h^2 * sum of inside lengths."""
+    nz, ny, nx = L.shape
+    A = np.moveaxis(L, 2 - axis, -1).astype(np.float64)  # lines along the last axis
+    inside_full = (A[..., :-1] * A[..., 1:]).sum() * h
+    sel = keys % 3 == axis
+    u = 1 - lam[sel]
+    idx = keys[sel] // 3
+    Ls = L.reshape(-1)[idx]
+    part = np.where(Ls == 1, u, 1 - u) * h
+    return h * h * (inside_full + part.sum())
+
+
+def test_volume_and_area_single_sphere(oracle_mod):
+    r = 1.8
+    c = np.array([0.013, -0.021, 0.007])
+    o = oracle_mod.Oracle(c[None], [r], RHO)
+    h = 0.1
+    lo = np.array([-2.5, -2.5, -2.5])
+    dims = (51, 51, 51)
+    L = o.labels_grid(lo, h, dims)
+    keys = oracle_mod.crossing_keys(L)
+    rec = o.edges(lo, h, dims, keys)
+    V = 4 / 3 * math.pi * r ** 3
+    for axis in range(3):
+        assert abs(line_volume(L, keys, rec["lam"], h, axis) / V - 1) < 2e-3
+    area = h * h * np.sum(np.abs(rec["normal"][np.arange(len(keys)), keys % 3]))
+    assert abs(area / (4 * math.pi * r * r) - 1) < 1e-2
+
+
+def test_volume_consistent_across_axes(oracle_mod):
+    """The enclosed volume does not depend on the line direction used to
+    integrate it (divergence theorem); a reversed lambda or a wrong root
+    breaks the agreement."""
+    m = _molecule(150, 41, 0.3)
+    o = oracle_mod.Oracle(m.centres, m.radii, m.probe)
+    L = o.labels_grid(m.lo, m.spacing, m.dims)
+    keys = oracle_mod.crossing_keys(L)
+    rec = o.edges(m.lo, m.spacing, m.dims, keys)
+    vols = [line_volume(L, keys, rec["lam"], m.spacing, a) for a in range(3)]
+    assert max(vols) / min(vols) - 1 < 2e-3
+    cnt = L.sum() * m.spacing ** 3
+    assert abs(vols[0] / cnt - 1) < 0.05
