@@ -1,0 +1,198 @@
+/*
+ * eses.h -- C-ABI of the MI355X (gfx950) Eulerian solvent-excluded surface
+ * hot path.
+ *
+ * The method (Zhao, Wang, Tong, Wei, arXiv 1809.04352) takes a list of atoms
+ * with centres c_i and van der Waals radii r_i (eq. 1), a probe radius rho, a
+ * grid spacing h and a box, and produces
+ *   - Inside[i,j,k] = 1 iff grid point (i,j,k) lies in M, the volume enclosed
+ *     by the solvent-excluded surface (SES) (eq. 2), and
+ *   - for each grid edge whose two ends carry different labels, the point
+ *     where the surface crosses it, p = lambda s + (1 - lambda) t (eq. 3-4),
+ *     with its outward normal and the patch it lies on.
+ * The SES is the boundary of the union of the probe balls that overlap no atom
+ * (section 1): with s_i = r_i + rho, U the union of the open balls B(c_i, s_i)
+ * and A = R^3 \ U the admissible probe centres, M = { x : dist(x, A) >= rho }.
+ * Its patches are convex (probe touching one atom), saddle (two) and concave
+ * (three or more) (section 1).  The concave-patch probe positions -- points on
+ * three SAS spheres that lie in A -- are produced on the way and exported.
+ *
+ * Conventions shared by every call:
+ *   - Grid point (i,j,k) is x = lo + (i,j,k) h, each coordinate evaluated as
+ *     fl(lo_a + fl(i h)) in FP64 (no fused multiply-add).  dims[a] =
+ *     ceil((hi_a - lo_a) / h) + 1 (the padded bounding box of section 2.3).
+ *   - Labels are uint8, 1 = inside M, laid out labels[i + nx (j + ny k)]
+ *     (x fastest).  A point at distance exactly rho from A is inside (M is
+ *     closed).  Probe-accessible interior cavities count as solvent.
+ *   - Edge key = 3 * (i + nx (j + ny k)) + axis for the edge from s = (i,j,k)
+ *     to t = s + e_axis; only the six-neighbour axis edges exist.  lambda is
+ *     the weight of s in eq. 4 (1 at s, 0 at t) and marks the FIRST label
+ *     change walking from s.  Records are sorted by key.
+ *   - Normals are unit vectors pointing out of M into the solvent.
+ *   - patch_type: 1 convex (atoms[0] = the atom), 2 saddle (atoms[0..1], the
+ *     pair), 3 concave (atoms[0..2], the probe's three atoms); unused atom
+ *     slots are -1.  Atom ids are the caller's indices, ascending.
+ *   - Concave probe positions are reported once per atom triple (a<b<c) and
+ *     side: sign = +1 iff (p - c_a) . ((c_b - c_a) x (c_c - c_a)) > 0.  A
+ *     probe touching a fourth atom is admissible (|p - c| >= s non-strict).
+ *
+ * Memory and streams: every pointer inside eses_molecule, and every output
+ * buffer, is DEVICE memory owned by the caller; it must stay valid until the
+ * work queued on `stream` (a hipStream_t, NULL = the default stream) has
+ * finished.  The candidates handle and its device workspace are owned by the
+ * library and released by eses_free_candidates.  Calls that return counts to
+ * the host synchronise `stream`.
+ *
+ * Errors: every call returns an eses_status; nothing throws across the ABI.
+ * On failure eses_last_error() holds a message (thread-local, valid until the
+ * next call on the same thread).
+ */
+#ifndef ESES_H
+#define ESES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ESES_OK = 0,
+    ESES_EINVAL = -1,     /* bad argument: null, non-finite, n <= 0, dims < 2 ... */
+    ESES_ENOMEM = -2,     /* device allocation failed; message holds the bytes */
+    ESES_ECAPACITY = -3,  /* output capacity too small; required count returned */
+    ESES_EDEVICE = -4,    /* a HIP runtime call failed */
+    ESES_EINTERNAL = -5   /* an internal list overflowed or a kernel reported
+                             an inconsistency */
+} eses_status;
+
+typedef enum {
+    ESES_FP64 = 0,        /* every inside/outside test in FP64 */
+    ESES_FP32_RECHECK = 1 /* FP32 tests with a rounding-error bound per test;
+                             points whose margin is below the bound are
+                             re-tested in FP64 */
+} eses_precision;
+
+/* One molecule: the paper's problem statement (eq. 1, probe radius, grid
+ * spacing, box).  centres: device, [n_atoms][3] float64, angstrom.
+ * radii: device, [n_atoms] float64, finite and > 0.  probe_radius and spacing
+ * finite and > 0.  bbox_lo/bbox_hi: host values; grid point (0,0,0) = bbox_lo
+ * and dims = ceil((hi - lo) / h) + 1 >= 2 per axis. */
+typedef struct {
+    const double *centers;
+    const double *radii;
+    int64_t n_atoms;
+    double probe_radius;
+    double spacing;
+    double bbox_lo[3];
+    double bbox_hi[3];
+} eses_molecule;
+
+/* Tuning knobs; pass NULL for defaults.  Results never depend on them. */
+typedef struct {
+    int32_t tile;          /* tile edge in grid points: 4 or 8 (default 8) */
+    int32_t reserved[7];   /* must be zero */
+} eses_config;
+
+typedef struct eses_candidates eses_candidates; /* opaque, library-owned */
+
+/* Counts describing one molecule's candidate set. */
+typedef struct {
+    int64_t n_atoms;
+    int32_t dims[3];
+    int64_t n_points;
+    int64_t n_neighbour_pairs;   /* ordered pairs i != j with overlapping SAS balls */
+    int64_t n_circles;           /* unordered pairs whose SAS spheres meet in a circle */
+    int64_t n_vertices;          /* concave probe positions (exposed three-sphere points) */
+    int64_t n_exposed_faces;     /* atoms whose SAS sphere has an admissible point */
+    int64_t n_exposed_circles;   /* circles with an admissible point */
+    int64_t n_tiles;
+    int64_t tile_list_entries;   /* total per-tile candidate entries */
+} eses_candidate_stats;
+
+typedef struct {
+    int64_t n_points;
+    int64_t n_inside;
+    int64_t n_rechecked;         /* FP32_RECHECK: points re-tested in FP64 */
+    /* Work of the FP64 decision procedure, counted by a separate statistics
+     * pass over the same points (run only when stats are requested): */
+    int64_t n_shell;             /* points inside an SAS ball but in no van der Waals ball */
+    int64_t tests_atom;          /* point-atom ball tests */
+    int64_t tests_vertex;        /* point-probe (concave) tests */
+    int64_t tests_face;          /* face reach tests */
+    int64_t tests_face_cut;      /* face admissibility half-space tests */
+    int64_t tests_circle;        /* circle reach tests */
+    int64_t tests_circle_cut;    /* circle admissibility half-space tests */
+} eses_classify_stats;
+
+/* Structure-of-arrays output of eses_edge_intersections for one molecule.
+ * All arrays are device memory of `capacity` records. */
+typedef struct {
+    int64_t *key;          /* [capacity] edge key, ascending */
+    double *lambda;        /* [capacity] weight of s, eq. 4 */
+    double *normal;        /* [capacity][3] outward unit normal */
+    uint8_t *patch_type;   /* [capacity] 1 convex, 2 saddle, 3 concave */
+    int32_t *atoms;        /* [capacity][3] atom ids, -1 unused */
+    int64_t capacity;
+} eses_isect_soa;
+
+/* Host helper: the padded bounding box of the van der Waals spheres,
+ * lo = min(c - r) - margin, hi = max(c + r) + margin (section 2.3).
+ * centers_host [n][3] and radii_host [n] are HOST arrays. */
+eses_status eses_bbox_from_atoms(const double *centers_host, const double *radii_host, int64_t n,
+                                 double margin, double lo[3], double hi[3]);
+
+/* Host helper: dims[a] = ceil((hi_a - lo_a) / spacing) + 1 of a molecule. */
+eses_status eses_grid_dims(const eses_molecule *mol, int32_t dims[3]);
+
+/* Stage 1 of the method (section 2.2: the grid and the analytic patches).
+ * Bins the atoms, finds overlapping SAS pairs and their circles, enumerates
+ * the concave probe positions (three-sphere points in A), marks which faces
+ * and circles have admissible points, and builds per-tile candidate lists
+ * for tiles of `tile`^3 grid points (the blocks of section 2.3, with the
+ * half-open ownership of section 2.5).  Synchronises `stream` to size its
+ * workspace.  On success *out is a new handle. */
+eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
+                                  const eses_config *cfg, void *stream, eses_candidates **out);
+
+/* Counts of molecule `mol` of a built handle (host). */
+eses_status eses_candidates_info(const eses_candidates *c, int32_t mol, eses_candidate_stats *st);
+
+/* Copies the concave probe positions of molecule `mol` into device buffers:
+ * p [capacity][3] float64, atoms [capacity][3] int32 (ascending caller ids),
+ * sign [capacity] int8.  *count (host) receives the number of positions; if
+ * it exceeds capacity the first `capacity` are written and ESES_ECAPACITY is
+ * returned.  Order: deterministic, unspecified.  Synchronises `stream`. */
+eses_status eses_copy_vertices(const eses_candidates *c, int32_t mol, double *p, int32_t *atoms,
+                               int8_t *sign, int64_t capacity, int64_t *count, void *stream);
+
+/* Stage 2 (eq. 2): labels every grid point of every molecule.
+ * labels: host array of n_mols DEVICE pointers, each [nx*ny*nz] uint8.
+ * stats: host array of n_mols entries or NULL (non-NULL synchronises). */
+eses_status eses_classify(eses_candidates *c, eses_precision prec, uint8_t *const *labels,
+                          eses_classify_stats *stats, void *stream);
+
+/* Stage 3 (eq. 3-4): records for every edge whose end labels differ.
+ * labels: host array of n_mols DEVICE pointers (as written by eses_classify).
+ * out: host array of n_mols SoA descriptors.  counts: host [n_mols], receives
+ * the number of crossing edges per molecule; records beyond a molecule's
+ * capacity are dropped and ESES_ECAPACITY is returned.  Synchronises. */
+eses_status eses_edge_intersections(eses_candidates *c, const uint8_t *const *labels,
+                                    const eses_isect_soa *out, int64_t *counts, void *stream);
+
+/* Releases the handle and its device workspace.  Call after the work queued
+ * with it has finished.  NULL is ignored. */
+void eses_free_candidates(eses_candidates *c);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *eses_last_error(void);
+
+/* Library version string. */
+const char *eses_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ESES_H */

@@ -539,19 +539,21 @@ void orc_dist_points(void *h, long count, const double *x, double cap, double *o
 
 /* -------------------------------------------------------------- edges */
 
-/* Real roots in [0, 1] of a polynomial of degree <= 4 (coefficients c[0..4],
+/* Real roots in [0, 1] of a polynomial of degree n <= 4 (coefficients c[0..n],
  * ascending), isolated by subdividing its Bernstein form on [0, 1] (the
  * number of sign changes of the Bernstein coefficients bounds the number of
  * roots) and refined by bisection.  Long double throughout. */
 typedef long double ld;
 
-static ld horner4(const ld c[5], ld u) {
-    return (((c[4] * u + c[3]) * u + c[2]) * u + c[1]) * u + c[0];
+static ld horner(const ld *c, int n, ld u) {
+    ld v = c[n];
+    for (int q = n - 1; q >= 0; q--) v = v * u + c[q];
+    return v;
 }
 
-static int sign_changes(const ld b[5]) {
+static int sign_changes(const ld *b, int n) {
     int v = 0, last = 0;
-    for (int q = 0; q < 5; q++) {
+    for (int q = 0; q <= n; q++) {
         int sg = b[q] > 0 ? 1 : (b[q] < 0 ? -1 : 0);
         if (sg == 0) continue;
         if (last != 0 && sg != last) v++;
@@ -564,17 +566,17 @@ static void add_root(double *roots, int *nr, int cap, ld u) {
     if (*nr < cap) roots[(*nr)++] = (double)u;
 }
 
-static void isolate(const ld c[5], const ld b[5], ld a, ld w, int depth, double *roots, int *nr,
-                    int cap) {
-    int v = sign_changes(b);
+static void isolate(const ld *c, int n, const ld *b, ld a, ld w, int depth, double *roots,
+                    int *nr, int cap) {
+    int v = sign_changes(b, n);
     if (v == 0) return;
-    if (v == 1 && b[0] != 0 && b[4] != 0) {
+    if (v == 1 && b[0] != 0 && b[n] != 0) {
         ld x0 = a, x1 = a + w;
-        ld f0 = horner4(c, x0);
+        ld f0 = horner(c, n, x0);
         for (int it = 0; it < 200 && x1 - x0 > 0; it++) {
             ld m = 0.5L * (x0 + x1);
             if (m <= x0 || m >= x1) break;
-            ld fm = horner4(c, m);
+            ld fm = horner(c, n, m);
             if (fm == 0) {
                 x0 = x1 = m;
                 break;
@@ -596,41 +598,53 @@ static void isolate(const ld c[5], const ld b[5], ld a, ld w, int depth, double 
     }
     /* de Casteljau split at the midpoint */
     ld t[5][5];
-    for (int q = 0; q < 5; q++) t[0][q] = b[q];
-    for (int r = 1; r < 5; r++)
-        for (int q = 0; q < 5 - r; q++) t[r][q] = 0.5L * (t[r - 1][q] + t[r - 1][q + 1]);
+    for (int q = 0; q <= n; q++) t[0][q] = b[q];
+    for (int r = 1; r <= n; r++)
+        for (int q = 0; q <= n - r; q++) t[r][q] = 0.5L * (t[r - 1][q] + t[r - 1][q + 1]);
     ld L[5], Rb[5];
-    for (int q = 0; q < 5; q++) {
+    for (int q = 0; q <= n; q++) {
         L[q] = t[q][0];
-        Rb[q] = t[4 - q][q];
+        Rb[q] = t[n - q][q];
     }
     ld mid = a + 0.5L * w;
-    ld fmid = horner4(c, mid);
+    ld fmid = horner(c, n, mid);
     if (fmid == 0) add_root(roots, nr, cap, mid);
-    /* the midpoint value is exact zero only when recorded above; a tiny
-     * nonzero Bernstein endpoint is handled by the recursion */
-    L[4] = fmid;
+    L[n] = fmid;
     Rb[0] = fmid;
-    isolate(c, L, a, 0.5L * w, depth + 1, roots, nr, cap);
-    isolate(c, Rb, mid, 0.5L * w, depth + 1, roots, nr, cap);
+    isolate(c, n, L, a, 0.5L * w, depth + 1, roots, nr, cap);
+    isolate(c, n, Rb, mid, 0.5L * w, depth + 1, roots, nr, cap);
 }
 
-static int quartic_roots01(const ld c[5], double *roots, int cap) {
-    /* Bernstein coefficients of degree 4 on [0,1]: b_k = sum_{i<=k} C(k,i)/C(4,i) c_i */
+static int poly_roots01(const ld *c, int n, double *roots, int cap) {
     static const ld binom[5][5] = {{1, 0, 0, 0, 0}, {1, 1, 0, 0, 0}, {1, 2, 1, 0, 0},
                                    {1, 3, 3, 1, 0}, {1, 4, 6, 4, 1}};
     ld b[5];
-    for (int k = 0; k < 5; k++) {
+    for (int k = 0; k <= n; k++) {
         b[k] = 0;
-        for (int i = 0; i <= k; i++) b[k] += binom[k][i] / binom[4][i] * c[i];
+        for (int i = 0; i <= k; i++) b[k] += binom[k][i] / binom[n][i] * c[i];
     }
     int nr = 0;
     if (c[0] == 0) add_root(roots, &nr, cap, 0.0L);
-    ld f1 = horner4(c, 1.0L);
+    ld f1 = horner(c, n, 1.0L);
     if (f1 == 0) add_root(roots, &nr, cap, 1.0L);
     b[0] = c[0];
-    b[4] = f1;
-    isolate(c, b, 0.0L, 1.0L, 0, roots, &nr, cap);
+    b[n] = f1;
+    isolate(c, n, b, 0.0L, 1.0L, 0, roots, &nr, cap);
+    return nr;
+}
+
+/* Roots in [0, 1] of the quartic g: its sign changes, plus every critical
+ * point (root of g') where g vanishes to within rounding -- a root of even
+ * multiplicity, which is where a line runs through the self-intersection of
+ * a spindle torus on its axis (the torus quartic is then a perfect square). */
+static int quartic_roots01(const ld c[5], double *roots, int cap) {
+    int nr = poly_roots01(c, 4, roots, cap);
+    ld d[4] = {c[1], 2 * c[2], 3 * c[3], 4 * c[4]};
+    double cp[4];
+    int nc = poly_roots01(d, 3, cp, 4);
+    ld scale = fabsl(c[0]) + fabsl(c[1]) + fabsl(c[2]) + fabsl(c[3]) + fabsl(c[4]);
+    for (int q = 0; q < nc; q++)
+        if (fabsl(horner(c, 4, (ld)cp[q])) <= 1e-15L * scale) add_root(roots, &nr, cap, cp[q]);
     return nr;
 }
 
@@ -745,8 +759,8 @@ static int edge_record(const oracle_t *o, const double lo[3], double hs, const i
                b2 = H * H - H * H * (ld)n[axis] * n[axis];
             ld cf[5] = {a0 * a0 - 4 * RR * b0, 2 * a0 * a1 - 4 * RR * b1,
                         a1 * a1 + 2 * a0 * a2 - 4 * RR * b2, 2 * a1 * a2, a2 * a2};
-            double qr[8];
-            int nq = quartic_roots01(cf, qr, 8);
+            double qr[12];
+            int nq = quartic_roots01(cf, qr, 12);
             for (int t = 0; t < nq; t++) {
                 /* keep the branch at distance rho from the near circle point */
                 double x[3];

@@ -1,0 +1,592 @@
+// C-ABI of the ESES hot path: argument checks, workspace, launch order and
+// the count read-backs that size the lists (see include/eses.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/eses.h"
+#include "eses_device.h"
+#include "launch.h"
+
+using namespace eses;
+
+namespace {
+
+thread_local std::string g_err;
+
+void set_err(const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+
+struct Status {
+    eses_status s;
+};
+
+#define CK(call)                                                                     \
+    do {                                                                             \
+        hipError_t e_ = (call);                                                      \
+        if (e_ != hipSuccess) {                                                      \
+            set_err("%s failed: %s", #call, hipGetErrorString(e_));                  \
+            return ESES_EDEVICE;                                                     \
+        }                                                                            \
+    } while (0)
+
+#define CKS(expr)                        \
+    do {                                 \
+        eses_status s_ = (expr);         \
+        if (s_ != ESES_OK) return s_;    \
+    } while (0)
+
+// Device workspace of one molecule: every buffer allocated on the stream and
+// released together.
+struct Arena {
+    std::vector<void *> ptrs;
+    hipStream_t st = nullptr;
+
+    template <typename T>
+    eses_status alloc(T **p, long long count) {
+        size_t bytes = sizeof(T) * (size_t)(count > 0 ? count : 1);
+        bytes = (bytes + 255) & ~(size_t)255;
+        void *q = nullptr;
+        hipError_t e = hipMallocAsync(&q, bytes, st);
+        if (e != hipSuccess || !q) {
+            (void)hipGetLastError();
+            set_err("device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+            return ESES_ENOMEM;
+        }
+        ptrs.push_back(q);
+        *p = (T *)q;
+        return ESES_OK;
+    }
+
+    void release() {
+        for (void *p : ptrs) (void)hipFreeAsync(p, st);
+        ptrs.clear();
+    }
+};
+
+struct MolState {
+    Mol m{};
+    Arena arena;
+    Arena scratch;  // build-time temporaries
+    eses_candidate_stats stats{};
+};
+
+}  // namespace
+
+struct eses_candidates {
+    std::vector<MolState *> mols;
+    hipStream_t stream = nullptr;
+};
+
+namespace {
+
+bool finite3(const double *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+eses_status dims_of(const eses_molecule *m, int32_t dims[3]) {
+    if (!m) {
+        set_err("molecule is NULL");
+        return ESES_EINVAL;
+    }
+    if (!(std::isfinite(m->spacing) && m->spacing > 0.0)) {
+        set_err("spacing must be finite and > 0");
+        return ESES_EINVAL;
+    }
+    if (!finite3(m->bbox_lo) || !finite3(m->bbox_hi)) {
+        set_err("bounding box must be finite");
+        return ESES_EINVAL;
+    }
+    for (int a = 0; a < 3; ++a) {
+        double ext = (m->bbox_hi[a] - m->bbox_lo[a]) / m->spacing;
+        if (!(ext > 0.0) || !(ext < 2.0e9)) {
+            set_err("box extent along axis %d must be positive and below 2e9 spacings", a);
+            return ESES_EINVAL;
+        }
+        dims[a] = (int32_t)std::ceil(ext) + 1;
+        if (dims[a] < 2) {
+            set_err("fewer than 2 grid points along axis %d", a);
+            return ESES_EINVAL;
+        }
+    }
+    return ESES_OK;
+}
+
+template <typename T>
+eses_status d2h(T *host, const T *dev, size_t count, hipStream_t st) {
+    CK(hipMemcpyAsync(host, dev, sizeof(T) * count, hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    return ESES_OK;
+}
+
+// Stage 1 for one molecule.
+eses_status build_one(const eses_molecule *in, int tile, MolState *S, hipStream_t st) {
+    Mol &m = S->m;
+    Arena &A = S->arena;
+    Arena &T = S->scratch;
+    A.st = st;
+    T.st = st;
+    if (!in->centers || !in->radii) {
+        set_err("centers and radii must be device pointers");
+        return ESES_EINVAL;
+    }
+    if (in->n_atoms < 1 || in->n_atoms > (1LL << 27)) {
+        set_err("n_atoms must be in [1, 2^27]");
+        return ESES_EINVAL;
+    }
+    if (!(std::isfinite(in->probe_radius) && in->probe_radius > 0.0)) {
+        set_err("probe_radius must be finite and > 0");
+        return ESES_EINVAL;
+    }
+    int32_t dims[3];
+    CKS(dims_of(in, dims));
+    m.n = (int)in->n_atoms;
+    m.rho = in->probe_radius;
+    m.h = in->spacing;
+    for (int a = 0; a < 3; ++a) {
+        m.lo[a] = in->bbox_lo[a];
+        m.dims[a] = dims[a];
+    }
+    m.npts = (long long)dims[0] * dims[1] * dims[2];
+    m.in_c = in->centers;
+    m.in_r = in->radii;
+    m.tile = tile;
+    for (int a = 0; a < 3; ++a) m.tdims[a] = (dims[a] + tile - 1) / tile;
+    long long ntiles = (long long)m.tdims[0] * m.tdims[1] * m.tdims[2];
+    if (ntiles > (1LL << 30)) {
+        set_err("grid too large: %lld tiles", ntiles);
+        return ESES_EINVAL;
+    }
+    m.ntiles = (int)ntiles;
+
+    CKS(A.alloc(&m.diag, 4));
+    CK(fill_i32(m.diag, 4, 0, st));
+
+    // bounds and input validation
+    double *dbounds;
+    int *dbad;
+    CKS(T.alloc(&dbounds, 8));
+    CKS(T.alloc(&dbad, 1));
+    CK(launch_bounds(in->centers, in->radii, m.n, dbounds, dbad, st));
+    double hb[8];
+    int hbad = 0;
+    CKS(d2h(hb, dbounds, 7, st));
+    CKS(d2h(&hbad, dbad, 1, st));
+    if (hbad) {
+        set_err("centres must be finite and radii finite and > 0");
+        return ESES_EINVAL;
+    }
+    m.smax = hb[6] + m.rho;
+    m.cell = 2.0 * m.smax;
+    for (;;) {
+        long long nc = 1;
+        for (int a = 0; a < 3; ++a) {
+            m.clo[a] = hb[a];
+            m.nc[a] = (int)std::floor((hb[3 + a] - hb[a]) / m.cell) + 1;
+            nc *= m.nc[a];
+        }
+        if (nc <= 4LL * m.n + 64) {
+            m.ncell = (int)nc;
+            break;
+        }
+        m.cell *= 1.5;  // sparse input: coarser cells keep the table small
+    }
+
+    // binning
+    int *cell_id, *cnt, *fillb, *slot, *tmp;
+    long long tmp_elems = scan_tmp_elems((long long)std::max<long long>(
+        std::max<long long>(m.n, m.ncell), std::max<long long>(ntiles, 1)) * 4 + 64);
+    CKS(T.alloc(&tmp, tmp_elems));
+    CKS(T.alloc(&cell_id, m.n));
+    CKS(T.alloc(&cnt, m.ncell + 1));
+    CKS(T.alloc(&fillb, m.ncell + 1));
+    CKS(T.alloc(&slot, m.n));
+    CKS(A.alloc(&m.cell_start, m.ncell + 1));
+    CKS(A.alloc(&m.atom, m.n));
+    CKS(A.alloc(&m.orig, m.n));
+    CK(fill_i32(cnt, m.ncell + 1, 0, st));
+    CK(launch_cell_count(m, cell_id, cnt, st));
+    CK(scan_i32(cnt, m.ncell, m.cell_start, tmp, st));
+    CK(hipMemcpyAsync(fillb, m.cell_start, sizeof(int) * (m.ncell + 1), hipMemcpyDeviceToDevice, st));
+    CK(launch_cell_scatter(m, cell_id, fillb, slot, st));
+    CK(launch_cell_sort_gather(m, slot, st));
+
+    // neighbours and circles
+    int *nbr_cnt, *circ_cnt;
+    CKS(T.alloc(&nbr_cnt, m.n));
+    CKS(T.alloc(&circ_cnt, m.n));
+    CKS(A.alloc(&m.nbr_off, m.n + 1));
+    CKS(A.alloc(&m.circ_off, m.n + 1));
+    CKS(A.alloc(&m.circ_any, m.n));
+    CKS(A.alloc(&m.aflag, m.n));
+    CK(launch_nbr(m, false, nbr_cnt, circ_cnt, st));
+    CK(scan_i32(nbr_cnt, m.n, m.nbr_off, tmp, st));
+    CK(scan_i32(circ_cnt, m.n, m.circ_off, tmp, st));
+    int tot[2];
+    CKS(d2h(&tot[0], m.nbr_off + m.n, 1, st));
+    CKS(d2h(&tot[1], m.circ_off + m.n, 1, st));
+    m.ncirc = tot[1];
+    CKS(A.alloc(&m.nbr, tot[0]));
+    CKS(A.alloc(&m.circ_i, m.ncirc));
+    CKS(A.alloc(&m.circ_j, m.ncirc));
+    CKS(A.alloc(&m.circ_oR, m.ncirc));
+    CKS(A.alloc(&m.circ_n, m.ncirc));
+    CKS(A.alloc(&m.cflag, m.ncirc));
+    CK(launch_nbr(m, true, nbr_cnt, circ_cnt, st));
+
+    // concave probe positions and exposure flags
+    int *vcnt, *tmp2;
+    CKS(T.alloc(&vcnt, m.ncirc));
+    CKS(T.alloc(&tmp2, scan_tmp_elems(m.ncirc) + 64));
+    CKS(A.alloc(&m.vert_off, m.ncirc + 1));
+    CK(launch_vertex(m, false, vcnt, st));
+    CK(launch_circle_free(m, st));
+    CK(scan_i32(vcnt, m.ncirc, m.vert_off, tmp2, st));
+    CKS(d2h(&m.nvert, m.vert_off + m.ncirc, 1, st));
+    CKS(A.alloc(&m.vert_p, m.nvert));
+    CKS(A.alloc(&m.vert_ijks, m.nvert));
+    CK(launch_vertex(m, true, vcnt, st));
+
+    // exposed faces and circles
+    int *face_cnt, *ec_cnt, *vert_cnt;
+    CKS(T.alloc(&face_cnt, m.n));
+    CKS(T.alloc(&ec_cnt, m.n));
+    CKS(T.alloc(&vert_cnt, m.n));
+    CKS(A.alloc(&m.face_off_atom, m.n + 1));
+    CKS(A.alloc(&m.ec_off_atom, m.n + 1));
+    CKS(A.alloc(&m.vert_off_atom, m.n + 1));
+    CK(launch_atom_features(m, face_cnt, ec_cnt, vert_cnt, st));
+    CK(scan_i32(face_cnt, m.n, m.face_off_atom, tmp, st));
+    CK(scan_i32(ec_cnt, m.n, m.ec_off_atom, tmp, st));
+    CKS(d2h(&m.nface, m.face_off_atom + m.n, 1, st));
+    CKS(d2h(&m.nec, m.ec_off_atom + m.n, 1, st));
+
+    int *fcut_cnt, *eccut_cnt, *tmp3;
+    CKS(A.alloc(&m.face_atom, m.nface));
+    CKS(A.alloc(&m.face_cut_off, m.nface + 1));
+    CKS(T.alloc(&fcut_cnt, m.nface));
+    CKS(T.alloc(&tmp3, scan_tmp_elems(std::max(m.nface, m.nec)) + 64));
+    CK(launch_face_list(m, fcut_cnt, st));
+    CK(scan_i32(fcut_cnt, m.nface, m.face_cut_off, tmp3, st));
+    int nfc = 0;
+    CKS(d2h(&nfc, m.face_cut_off + m.nface, 1, st));
+    CKS(A.alloc(&m.face_cut, nfc));
+    CK(launch_face_cuts(m, st));
+
+    CKS(A.alloc(&m.ec_circ, m.nec));
+    CKS(A.alloc(&m.ec_cut_off, m.nec + 1));
+    CKS(T.alloc(&eccut_cnt, m.nec));
+    CK(launch_ec_list(m, false, eccut_cnt, st));
+    CK(scan_i32(eccut_cnt, m.nec, m.ec_cut_off, tmp3, st));
+    int nec_cut = 0;
+    CKS(d2h(&nec_cut, m.ec_cut_off + m.nec, 1, st));
+    CKS(A.alloc(&m.ec_cut, nec_cut));
+    CK(launch_ec_list(m, true, eccut_cnt, st));
+
+    // per-tile lists
+    int *cA, *cF, *cC, *cV;
+    CKS(T.alloc(&cA, m.ntiles));
+    CKS(T.alloc(&cF, m.ntiles));
+    CKS(T.alloc(&cC, m.ntiles));
+    CKS(T.alloc(&cV, m.ntiles));
+    CKS(A.alloc(&m.tA_off, m.ntiles + 1));
+    CKS(A.alloc(&m.tF_off, m.ntiles + 1));
+    CKS(A.alloc(&m.tC_off, m.ntiles + 1));
+    CKS(A.alloc(&m.tV_off, m.ntiles + 1));
+    CK(launch_tiles(m, false, cA, cF, cC, cV, st));
+    CK(scan_i32(cA, m.ntiles, m.tA_off, tmp, st));
+    CK(scan_i32(cF, m.ntiles, m.tF_off, tmp, st));
+    CK(scan_i32(cC, m.ntiles, m.tC_off, tmp, st));
+    CK(scan_i32(cV, m.ntiles, m.tV_off, tmp, st));
+    int tl[4];
+    CKS(d2h(&tl[0], m.tA_off + m.ntiles, 1, st));
+    CKS(d2h(&tl[1], m.tF_off + m.ntiles, 1, st));
+    CKS(d2h(&tl[2], m.tC_off + m.ntiles, 1, st));
+    CKS(d2h(&tl[3], m.tV_off + m.ntiles, 1, st));
+    CKS(A.alloc(&m.tA, tl[0]));
+    CKS(A.alloc(&m.tF, tl[1]));
+    CKS(A.alloc(&m.tC, tl[2]));
+    CKS(A.alloc(&m.tV, tl[3]));
+    CK(launch_tiles(m, true, cA, cF, cC, cV, st));
+
+    int hdiag[4];
+    CKS(d2h(hdiag, m.diag, 4, st));
+    if (hdiag[0] != 0) {
+        set_err("internal: %d list entries beyond their counted range", hdiag[0]);
+        return ESES_EINTERNAL;
+    }
+
+    eses_candidate_stats &s = S->stats;
+    s.n_atoms = m.n;
+    for (int a = 0; a < 3; ++a) s.dims[a] = dims[a];
+    s.n_points = m.npts;
+    s.n_neighbour_pairs = tot[0];
+    s.n_circles = m.ncirc;
+    s.n_vertices = m.nvert;
+    s.n_exposed_faces = m.nface;
+    s.n_exposed_circles = m.nec;
+    s.n_tiles = m.ntiles;
+    s.tile_list_entries = (int64_t)tl[0] + tl[1] + tl[2] + tl[3];
+    T.release();
+    CK(hipGetLastError());
+    return ESES_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *eses_last_error(void) { return g_err.c_str(); }
+
+const char *eses_version(void) { return "eses-gfx950 0.1"; }
+
+eses_status eses_bbox_from_atoms(const double *c, const double *r, int64_t n, double margin,
+                                 double lo[3], double hi[3]) {
+    g_err.clear();
+    if (!c || !r || !lo || !hi || n < 1 || !std::isfinite(margin) || margin < 0.0) {
+        set_err("eses_bbox_from_atoms: bad argument");
+        return ESES_EINVAL;
+    }
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = INFINITY;
+        hi[a] = -INFINITY;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        if (!std::isfinite(r[i]) || !(r[i] > 0.0) || !finite3(c + 3 * i)) {
+            set_err("eses_bbox_from_atoms: atom %lld is not finite or has radius <= 0", (long long)i);
+            return ESES_EINVAL;
+        }
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::fmin(lo[a], c[3 * i + a] - r[i]);
+            hi[a] = std::fmax(hi[a], c[3 * i + a] + r[i]);
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        lo[a] -= margin;
+        hi[a] += margin;
+    }
+    return ESES_OK;
+}
+
+eses_status eses_grid_dims(const eses_molecule *mol, int32_t dims[3]) {
+    g_err.clear();
+    if (!dims) {
+        set_err("dims is NULL");
+        return ESES_EINVAL;
+    }
+    return dims_of(mol, dims);
+}
+
+eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
+                                  const eses_config *cfg, void *stream, eses_candidates **out) {
+    g_err.clear();
+    if (!out) {
+        set_err("out is NULL");
+        return ESES_EINVAL;
+    }
+    *out = nullptr;
+    if (!mols || n_mols < 1) {
+        set_err("need at least one molecule");
+        return ESES_EINVAL;
+    }
+    int tile = 8;
+    if (cfg) {
+        if (cfg->tile != 0) tile = cfg->tile;
+        for (int q = 0; q < 7; ++q)
+            if (cfg->reserved[q] != 0) {
+                set_err("eses_config.reserved must be zero");
+                return ESES_EINVAL;
+            }
+        if (tile != 4 && tile != 8) {
+            set_err("tile must be 4 or 8");
+            return ESES_EINVAL;
+        }
+    }
+    hipStream_t st = (hipStream_t)stream;
+    eses_candidates *c = new eses_candidates();
+    c->stream = st;
+    for (int32_t q = 0; q < n_mols; ++q) {
+        MolState *S = new MolState();
+        c->mols.push_back(S);
+        eses_status s = build_one(&mols[q], tile, S, st);
+        if (s != ESES_OK) {
+            std::string msg = g_err;
+            eses_free_candidates(c);
+            char pre[64];
+            snprintf(pre, sizeof pre, "molecule %d: ", q);
+            g_err = pre + msg;
+            return s;
+        }
+    }
+    *out = c;
+    return ESES_OK;
+}
+
+eses_status eses_candidates_info(const eses_candidates *c, int32_t mol, eses_candidate_stats *st) {
+    g_err.clear();
+    if (!c || !st || mol < 0 || mol >= (int32_t)c->mols.size()) {
+        set_err("bad handle, molecule index or stats pointer");
+        return ESES_EINVAL;
+    }
+    *st = c->mols[mol]->stats;
+    return ESES_OK;
+}
+
+eses_status eses_copy_vertices(const eses_candidates *c, int32_t mol, double *p, int32_t *atoms,
+                               int8_t *sign, int64_t capacity, int64_t *count, void *stream) {
+    g_err.clear();
+    if (!c || mol < 0 || mol >= (int32_t)c->mols.size() || !count || capacity < 0 ||
+        (capacity > 0 && (!p || !atoms || !sign))) {
+        set_err("bad argument");
+        return ESES_EINVAL;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const Mol &m = c->mols[mol]->m;
+    *count = m.nvert;
+    long long nw = std::min<long long>(m.nvert, capacity);
+    CK(launch_export_vertices(m, p, atoms, sign, nw, st));
+    CK(hipStreamSynchronize(st));
+    if (m.nvert > capacity) {
+        set_err("capacity %lld below %d concave probe positions", (long long)capacity, m.nvert);
+        return ESES_ECAPACITY;
+    }
+    return ESES_OK;
+}
+
+eses_status eses_classify(eses_candidates *c, eses_precision prec, uint8_t *const *labels,
+                          eses_classify_stats *stats, void *stream) {
+    g_err.clear();
+    if (!c || !labels) {
+        set_err("bad handle or labels");
+        return ESES_EINVAL;
+    }
+    if (prec != ESES_FP64 && prec != ESES_FP32_RECHECK) {
+        set_err("unknown precision");
+        return ESES_EINVAL;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    for (size_t q = 0; q < c->mols.size(); ++q) {
+        if (!labels[q]) {
+            set_err("labels[%zu] is NULL", q);
+            return ESES_EINVAL;
+        }
+        const Mol &m = c->mols[q]->m;
+        CK(launch_classify_fp64(m, labels[q], st));
+    }
+    if (stats) {
+        const size_t nm = c->mols.size();
+        const size_t per = 1 + WC_COUNT;
+        unsigned long long *d = nullptr;
+        CK(hipMallocAsync((void **)&d, sizeof(unsigned long long) * nm * per, st));
+        std::vector<unsigned long long> h(nm * per);
+        CK(fill_u32((uint32_t *)d, (long long)(2 * nm * per), 0u, st));
+        for (size_t q = 0; q < nm; ++q) {
+            CK(launch_count_inside(labels[q], c->mols[q]->m.npts, d + q * per, st));
+            CK(launch_classify_work(c->mols[q]->m, d + q * per + 1, st));
+        }
+        CK(hipMemcpyAsync(h.data(), d, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost, st));
+        CK(hipFreeAsync(d, st));
+        CK(hipStreamSynchronize(st));
+        for (size_t q = 0; q < nm; ++q) {
+            const unsigned long long *w = h.data() + q * per;
+            eses_classify_stats &o = stats[q];
+            o.n_points = c->mols[q]->m.npts;
+            o.n_inside = (int64_t)w[0];
+            o.n_rechecked = 0;
+            o.tests_atom = (int64_t)w[1 + WC_ATOM];
+            o.tests_vertex = (int64_t)w[1 + WC_VERTEX];
+            o.tests_face = (int64_t)w[1 + WC_FACE];
+            o.tests_face_cut = (int64_t)w[1 + WC_FACE_CUT];
+            o.tests_circle = (int64_t)w[1 + WC_CIRCLE];
+            o.tests_circle_cut = (int64_t)w[1 + WC_CIRCLE_CUT];
+            o.n_shell = (int64_t)w[1 + WC_CASE_SHELL];
+        }
+    }
+    return ESES_OK;
+}
+
+eses_status eses_edge_intersections(eses_candidates *c, const uint8_t *const *labels,
+                                    const eses_isect_soa *out, int64_t *counts, void *stream) {
+    g_err.clear();
+    if (!c || !labels || !out || !counts) {
+        set_err("bad argument");
+        return ESES_EINVAL;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    bool short_cap = false;
+    for (size_t q = 0; q < c->mols.size(); ++q) {
+        const Mol &m = c->mols[q]->m;
+        const eses_isect_soa &o = out[q];
+        if (!labels[q] || o.capacity < 0 ||
+            (o.capacity > 0 && (!o.key || !o.lambda || !o.normal || !o.patch_type || !o.atoms))) {
+            set_err("molecule %zu: bad labels or output descriptor", q);
+            return ESES_EINVAL;
+        }
+        Arena T;
+        T.st = st;
+        long long nb = (m.npts + 255) / 256;
+        int *bcount;
+        long long *boff, *tmp;
+        int *ovf;
+        eses_status s;
+        if ((s = T.alloc(&bcount, nb + 1)) != ESES_OK || (s = T.alloc(&boff, nb + 2)) != ESES_OK ||
+            (s = T.alloc(&tmp, scan_tmp_elems(nb) + 64)) != ESES_OK ||
+            (s = T.alloc(&ovf, 1)) != ESES_OK) {
+            T.release();
+            return s;
+        }
+        long long nblk = 0;
+        hipError_t e = launch_edge_detect_count(labels[q], m, bcount, &nblk, st);
+        if (e == hipSuccess) e = scan_i64(bcount, nblk, boff, tmp, st);
+        long long total = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&total, boff + nblk, sizeof(long long), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        long long nw = std::min<long long>(total, o.capacity);
+        if (e == hipSuccess && nw > 0) e = launch_edge_detect_write(labels[q], m, boff, o.capacity, (long long *)o.key, st);
+        if (e == hipSuccess) e = fill_i32(ovf, 1, 0, st);
+        if (e == hipSuccess && nw > 0)
+            e = launch_edge_roots(m, labels[q], (const long long *)o.key, nw, o.lambda, o.normal, o.patch_type,
+                                  o.atoms, ovf, st);
+        int hovf = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&hovf, ovf, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        T.release();
+        if (e != hipSuccess) {
+            set_err("edge intersections: %s", hipGetErrorString(e));
+            return ESES_EDEVICE;
+        }
+        if (hovf) {
+            set_err("molecule %zu: more roots on one edge than the per-edge list holds", q);
+            return ESES_EINTERNAL;
+        }
+        counts[q] = total;
+        if (total > o.capacity) short_cap = true;
+    }
+    if (short_cap) {
+        set_err("an output capacity is below the number of crossing edges (see counts)");
+        return ESES_ECAPACITY;
+    }
+    return ESES_OK;
+}
+
+void eses_free_candidates(eses_candidates *c) {
+    if (!c) return;
+    for (MolState *S : c->mols) {
+        S->arena.release();
+        S->scratch.release();
+        delete S;
+    }
+    (void)hipStreamSynchronize(c->stream);
+    delete c;
+}
+
+}  // extern "C"

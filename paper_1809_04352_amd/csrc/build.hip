@@ -1,0 +1,694 @@
+// Stage 1 kernels: cell binning, SAS neighbours and pair circles, concave
+// probe positions, exposure flags, exposed-feature cut lists and per-tile
+// candidate lists.  Every list is built in two passes (count, scan, fill) so
+// its order is deterministic.
+#include "eses_device.h"
+#include "launch.h"
+
+namespace eses {
+
+// ----------------------------------------------------------------- utilities
+
+__global__ void k_fill_i32(int *p, long long n, int v) { fill_i32(p, n, v); }
+
+__global__ void k_fill_u32(uint32_t *p, long long n, uint32_t v) {
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x)
+        p[q] = v;
+}
+
+// Exclusive scan, three passes: per-block sums, one-block scan of the sums,
+// per-block scan plus offset.  out has n + 1 entries (out[n] = total).
+constexpr int SCAN_BLOCK = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
+
+template <typename T>
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_reduce(const int *in, long long n, T *bsum) {
+    __shared__ T lds[SCAN_BLOCK / WAVE + 1];
+    long long base = (long long)blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    T v = 0;
+#pragma unroll
+    for (int q = 0; q < SCAN_ITEMS; ++q)
+        if (base + q < n) v += (T)in[base + q];
+    T tot;
+    block_excl_scan<T, SCAN_BLOCK>(v, lds, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_blocks(T *bsum, long long nb) {
+    __shared__ T lds[SCAN_BLOCK / WAVE + 1];
+    T carry = 0;
+    for (long long b0 = 0; b0 < nb; b0 += SCAN_BLOCK) {
+        long long q = b0 + threadIdx.x;
+        T v = q < nb ? bsum[q] : T(0);
+        T tot;
+        T ex = block_excl_scan<T, SCAN_BLOCK>(v, lds, &tot);
+        if (q < nb) bsum[q] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_apply(const int *in, long long n,
+                                                           const T *bsum, T *out) {
+    __shared__ T lds[SCAN_BLOCK / WAVE + 1];
+    long long base = (long long)blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    T vals[SCAN_ITEMS];
+    T v = 0;
+#pragma unroll
+    for (int q = 0; q < SCAN_ITEMS; ++q) {
+        vals[q] = base + q < n ? (T)in[base + q] : T(0);
+        v += vals[q];
+    }
+    T tot;
+    T ex = block_excl_scan<T, SCAN_BLOCK>(v, lds, &tot) + bsum[blockIdx.x];
+#pragma unroll
+    for (int q = 0; q < SCAN_ITEMS; ++q) {
+        if (base + q < n) out[base + q] = ex;
+        ex += vals[q];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = bsum[gridDim.x];
+}
+
+template <typename T>
+static hipError_t scan_impl(const int *in, long long n, T *out, T *tmp, hipStream_t st) {
+    long long nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, st, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_blocks<T>, dim3(1), dim3(SCAN_BLOCK), 0, st, tmp, nb);
+    hipLaunchKernelGGL(k_scan_apply<T>, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, st, in, n, tmp,
+                       out);
+    return hipGetLastError();
+}
+
+long long scan_tmp_elems(long long n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 2; }
+
+hipError_t scan_i32(const int *in, long long n, int *out, int *tmp, hipStream_t st) {
+    return scan_impl<int>(in, n, out, tmp, st);
+}
+
+hipError_t scan_i64(const int *in, long long n, long long *out, long long *tmp, hipStream_t st) {
+    return scan_impl<long long>(in, n, out, tmp, st);
+}
+
+hipError_t fill_i32(int *p, long long n, int v, hipStream_t st) {
+    long long nb = (n + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)nb), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t fill_u32(uint32_t *p, long long n, uint32_t v, hipStream_t st) {
+    long long nb = (n + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)nb), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------- atom binning
+
+// Bounds of the centres and the largest radius; flags non-finite or
+// non-positive input.  One block.
+__global__ void __launch_bounds__(256) k_bounds(const double *c, const double *r, long long n,
+                                                double *out, int *bad) {
+    __shared__ double sh[7][256];
+    __shared__ int shbad[256];
+    double v[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0};
+    int b = 0;
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+        double x = c[3 * i], y = c[3 * i + 1], z = c[3 * i + 2], rr = r[i];
+        if (!isfinite(x) || !isfinite(y) || !isfinite(z) || !isfinite(rr) || !(rr > 0.0)) b = 1;
+        v[0] = fmin(v[0], x);
+        v[1] = fmin(v[1], y);
+        v[2] = fmin(v[2], z);
+        v[3] = fmax(v[3], x);
+        v[4] = fmax(v[4], y);
+        v[5] = fmax(v[5], z);
+        v[6] = fmax(v[6], rr);
+    }
+    for (int q = 0; q < 7; ++q) sh[q][threadIdx.x] = v[q];
+    shbad[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] = fmin(sh[q][threadIdx.x], sh[q][threadIdx.x + s]);
+            for (int q = 3; q < 7; ++q) sh[q][threadIdx.x] = fmax(sh[q][threadIdx.x], sh[q][threadIdx.x + s]);
+            shbad[threadIdx.x] |= shbad[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 7; ++q) out[q] = sh[q][0];
+        *bad = shbad[0];
+    }
+}
+
+__device__ inline int cell_axis(const Mol &m, double x, int a) {
+    int c = (int)floor((x - m.clo[a]) / m.cell);
+    return c < 0 ? 0 : (c >= m.nc[a] ? m.nc[a] - 1 : c);
+}
+
+__global__ void k_cell_count(Mol m, int *cell_id, int *count) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.n) return;
+    int c = cell_axis(m, m.in_c[3 * i], 0) +
+            m.nc[0] * (cell_axis(m, m.in_c[3 * i + 1], 1) + m.nc[1] * cell_axis(m, m.in_c[3 * i + 2], 2));
+    cell_id[i] = c;
+    atomicAdd(&count[c], 1);
+}
+
+__global__ void k_cell_scatter(Mol m, const int *cell_id, int *fill, int *slot_orig) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.n) return;
+    int pos = atomicAdd(&fill[cell_id[i]], 1);
+    slot_orig[pos] = i;
+}
+
+// Sort each cell's caller ids ascending (cells hold a few dozen atoms), then
+// gather the atoms into internal order.
+__global__ void k_cell_sort(Mol m, int *slot_orig) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= m.ncell) return;
+    int b = m.cell_start[c], e = m.cell_start[c + 1];
+    for (int q = b + 1; q < e; ++q) {
+        int v = slot_orig[q];
+        int p = q - 1;
+        while (p >= b && slot_orig[p] > v) {
+            slot_orig[p + 1] = slot_orig[p];
+            --p;
+        }
+        slot_orig[p + 1] = v;
+    }
+}
+
+__global__ void k_gather_atoms(Mol m, const int *slot_orig) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m.n) return;
+    int i = slot_orig[q];
+    m.orig[q] = i;
+    m.atom[q] = make_double4(m.in_c[3 * i], m.in_c[3 * i + 1], m.in_c[3 * i + 2], m.in_r[i]);
+}
+
+// A fill pass writes slot `at` of a range sized by its count pass.  Both
+// passes take the same decisions, but a write past the range is dropped and
+// counted rather than trusted.
+__device__ inline bool fill_ok(const Mol &m, long long at, long long end) {
+    if (at < end) return true;
+    atomicAdd(&m.diag[0], 1);
+    return false;
+}
+
+// ------------------------------------------------ SAS neighbours and circles
+
+// Thread per internal atom i.  Stencil cells are visited in increasing cell
+// index, and internal ids increase with the cell index, so each neighbour
+// list comes out ascending.
+template <bool FILL>
+__global__ void k_nbr(Mol m, int *nbr_cnt, int *circ_cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.n) return;
+    double4 ai = m.atom[i];
+    double si = ai.w + m.rho;
+    int cx = cell_axis(m, ai.x, 0), cy = cell_axis(m, ai.y, 1), cz = cell_axis(m, ai.z, 2);
+    int nn = 0, nc = 0, nany = 0;
+    bool contained = false;
+    int wn = FILL ? m.nbr_off[i] : 0;
+    int wc = FILL ? m.circ_off[i] : 0;
+    for (int z = max(cz - 1, 0); z <= min(cz + 1, m.nc[2] - 1); ++z)
+        for (int y = max(cy - 1, 0); y <= min(cy + 1, m.nc[1] - 1); ++y)
+            for (int x = max(cx - 1, 0); x <= min(cx + 1, m.nc[0] - 1); ++x) {
+                int c = x + m.nc[0] * (y + m.nc[1] * z);
+                for (int k = m.cell_start[c], ke = m.cell_start[c + 1]; k < ke; ++k) {
+                    if (k == i) continue;
+                    double4 ak = m.atom[k];
+                    double sk = ak.w + m.rho;
+                    double dx = ak.x - ai.x, dy = ak.y - ai.y, dz = ak.z - ai.z;
+                    double d2 = dx * dx + dy * dy + dz * dz;
+                    if (!(d2 < sq(si + sk + LIST_SLACK))) continue;
+                    if (FILL && fill_ok(m, wn + nn, m.nbr_off[i + 1])) m.nbr[wn + nn] = k;
+                    ++nn;
+                    if (sqrt(d2) + si < sk) contained = true;
+                    double4 oR, n;
+                    if (pair_circle(ai, ak, m.rho, oR, n)) {
+                        ++nany;
+                        if (k > i) {
+                            if (FILL && fill_ok(m, wc + nc, m.circ_off[i + 1])) {
+                                m.circ_i[wc + nc] = i;
+                                m.circ_j[wc + nc] = k;
+                                m.circ_oR[wc + nc] = oR;
+                                m.circ_n[wc + nc] = n;
+                                m.cflag[wc + nc] = 0u;
+                            }
+                            ++nc;
+                        }
+                    }
+                }
+            }
+    if (!FILL) {
+        nbr_cnt[i] = nn;
+        circ_cnt[i] = nc;
+        m.circ_any[i] = nany;
+        m.aflag[i] = contained ? AF_CONTAINED : 0u;
+    }
+}
+
+// ------------------------------------------------- concave probe positions
+
+// Circle id of the pair (a, b), a < b, or -1.
+__device__ inline int find_circle(const Mol &m, int a, int b) {
+    int lo = m.circ_off[a], hi = m.circ_off[a + 1] - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) >> 1;
+        int v = m.circ_j[mid];
+        if (v == b) return mid;
+        if (v < b) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+// Thread per circle (i, j).  For every k > j among i's neighbours, the circle
+// meets S_k where the in-plane angle phi to the direction of c_k satisfies
+//   cos(phi) = (|c_k - o|^2 + R^2 - s_k^2) / (2 R b_k),
+// b_k = distance of c_k from the circle's axis.  The two points are
+// o + R (cos(phi) e +- sin(phi) n x e), e = in-plane unit vector towards c_k;
+// the "+" point has (p - c_i) . ((c_j - c_i) x (c_k - c_i)) > 0.  A point is
+// kept iff no neighbour other than j, k holds it strictly inside its SAS ball
+// (points on S_i can only be inside balls of i's neighbours).
+template <bool FILL>
+__global__ void k_vertex(Mol m, int *vcnt) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= m.ncirc) return;
+    int i = m.circ_i[c], j = m.circ_j[c];
+    double4 oR = m.circ_oR[c];
+    double4 n = m.circ_n[c];
+    double R = oR.w;
+    int count = 0;
+    int wv = FILL ? m.vert_off[c] : 0;
+    uint32_t myflag = 0;
+    int nb = m.nbr_off[i], ne = m.nbr_off[i + 1];
+    for (int q = nb; q < ne; ++q) {
+        int k = m.nbr[q];
+        if (k <= j) continue;
+        double4 ak = m.atom[k];
+        double sk = ak.w + m.rho;
+        double wx = ak.x - oR.x, wy = ak.y - oR.y, wz = ak.z - oR.z;
+        double t = wx * n.x + wy * n.y + wz * n.z;
+        double px = wx - t * n.x, py = wy - t * n.y, pz = wz - t * n.z;
+        double b = sqrt(px * px + py * py + pz * pz);
+        double ww = wx * wx + wy * wy + wz * wz;
+        if (!(b > 1e-12 * (sqrt(ww) + R))) continue;  // c_k on the axis: no isolated points
+        double cphi = (ww + R * R - sk * sk) / (2.0 * R * b);
+        if (!(cphi >= -1.0 && cphi <= 1.0)) continue;
+        bool crossed = cphi > -1.0 && cphi < 1.0;
+        double sphi = sqrt(fmax(0.0, 1.0 - cphi * cphi));
+        double ex = px / b, ey = py / b, ez = pz / b;
+        double fx = n.y * ez - n.z * ey, fy = n.z * ex - n.x * ez, fz = n.x * ey - n.y * ex;
+        bool any_exposed = false;
+        for (int sgn = 0; sgn < 2; ++sgn) {
+            double sp = sgn == 0 ? sphi : -sphi;
+            double vx = oR.x + R * (cphi * ex + sp * fx);
+            double vy = oR.y + R * (cphi * ey + sp * fy);
+            double vz = oR.z + R * (cphi * ez + sp * fz);
+            bool ok = true;
+            for (int q2 = nb; q2 < ne && ok; ++q2) {
+                int l = m.nbr[q2];
+                if (l == j || l == k) continue;
+                double4 al = m.atom[l];
+                double sl = al.w + m.rho;
+                double dx = vx - al.x, dy = vy - al.y, dz = vz - al.z;
+                if (dx * dx + dy * dy + dz * dz < sl * sl) ok = false;
+            }
+            if (!ok) continue;
+            any_exposed = true;
+            if (FILL && fill_ok(m, wv + count, m.vert_off[c + 1])) {
+                m.vert_p[wv + count] = make_double4(vx, vy, vz, 0.0);
+                m.vert_ijks[wv + count] = make_int4(i, j, k, sgn == 0 ? 1 : -1);
+            }
+            ++count;
+        }
+        if (!FILL) {
+            uint32_t f = (crossed ? CF_CROSSED : 0u) | (any_exposed ? CF_EXPOSED_VERTEX : 0u);
+            if (f) {
+                myflag |= f;
+                int cik = find_circle(m, i, k);
+                int cjk = find_circle(m, j, k);
+                if (cik >= 0) atomicOr(&m.cflag[cik], f);
+                if (cjk >= 0) atomicOr(&m.cflag[cjk], f);
+            }
+            if (any_exposed) {
+                atomicOr(&m.aflag[i], AF_EXPOSED_VERTEX);
+                atomicOr(&m.aflag[j], AF_EXPOSED_VERTEX);
+                atomicOr(&m.aflag[k], AF_EXPOSED_VERTEX);
+            }
+        }
+    }
+    if (!FILL) {
+        vcnt[c] = count;
+        if (myflag) atomicOr(&m.cflag[c], myflag);
+    }
+}
+
+// A circle that no other sphere cuts is wholly inside or wholly outside each
+// other SAS ball, so one test point decides whether it is admissible.
+__global__ void k_circle_free(Mol m) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= m.ncirc) return;
+    if (m.cflag[c] & CF_CROSSED) return;
+    int i = m.circ_i[c], j = m.circ_j[c];
+    double4 oR = m.circ_oR[c];
+    double4 n = m.circ_n[c];
+    double ux, uy, uz;
+    perp_unit(n.x, n.y, n.z, ux, uy, uz);
+    double qx = oR.x + oR.w * ux, qy = oR.y + oR.w * uy, qz = oR.z + oR.w * uz;
+    for (int q = m.nbr_off[i]; q < m.nbr_off[i + 1]; ++q) {
+        int l = m.nbr[q];
+        if (l == j) continue;
+        double4 al = m.atom[l];
+        double sl = al.w + m.rho;
+        double dx = qx - al.x, dy = qy - al.y, dz = qz - al.z;
+        if (dx * dx + dy * dy + dz * dz < sl * sl) return;
+    }
+    atomicOr(&m.cflag[c], CF_EXPOSED_FREE);
+    atomicOr(&m.aflag[i], AF_EXPOSED_CIRCLE);
+    atomicOr(&m.aflag[j], AF_EXPOSED_CIRCLE);
+}
+
+// Per atom: face flag and the counts that the feature scans need.
+//   A face has an admissible point iff it carries an admissible
+//   three-sphere point or admissible crossing-free circle, or it has no
+//   circle at all and lies in no other ball (an isolated sphere).
+__global__ void k_atom_features(Mol m, int *face_cnt, int *ec_cnt, int *vert_cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.n) return;
+    uint32_t f = m.aflag[i];
+    bool face = (f & (AF_EXPOSED_VERTEX | AF_EXPOSED_CIRCLE)) ||
+                (m.circ_any[i] == 0 && !(f & AF_CONTAINED));
+    if (face) m.aflag[i] = f | AF_FACE;
+    face_cnt[i] = face ? 1 : 0;
+    int e = 0;
+    for (int c = m.circ_off[i]; c < m.circ_off[i + 1]; ++c) e += (m.cflag[c] & CF_EXPOSED) ? 1 : 0;
+    ec_cnt[i] = e;
+    vert_cnt[i] = m.vert_off[m.circ_off[i + 1]] - m.vert_off[m.circ_off[i]];
+}
+
+// ------------------------------------------------------ exposed feature lists
+
+__global__ void k_face_list(Mol m, int *cut_cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.n) return;
+    if (!(m.aflag[i] & AF_FACE)) return;
+    int f = m.face_off_atom[i];
+    m.face_atom[f] = i;
+    cut_cnt[f] = m.nbr_off[i + 1] - m.nbr_off[i];
+}
+
+__global__ void k_face_cuts(Mol m) {
+    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= m.nface) return;
+    int i = m.face_atom[f];
+    double4 ai = m.atom[i];
+    double si = ai.w + m.rho;
+    int w = m.face_cut_off[f];
+    for (int q = m.nbr_off[i]; q < m.nbr_off[i + 1]; ++q) {
+        double4 ak = m.atom[m.nbr[q]];
+        double sk = ak.w + m.rho;
+        double vx = ak.x - ai.x, vy = ak.y - ai.y, vz = ak.z - ai.z;
+        double d2 = vx * vx + vy * vy + vz * vz;
+        m.face_cut[w++] = make_double4(vx, vy, vz, (si * si + d2 - sk * sk) / (2.0 * si));
+    }
+}
+
+// Exposed circles: id list, then per circle the neighbours of the owner that
+// reach the circle (distance from c_k to the circle below s_k).
+template <bool FILL>
+__global__ void k_ec_list(Mol m, int *cut_cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.n) return;
+    int e = m.ec_off_atom[i];
+    for (int c = m.circ_off[i]; c < m.circ_off[i + 1]; ++c) {
+        if (!(m.cflag[c] & CF_EXPOSED)) continue;
+        int j = m.circ_j[c];
+        double4 oR = m.circ_oR[c];
+        double4 n = m.circ_n[c];
+        double R = oR.w;
+        int cnt = 0;
+        int w = FILL ? m.ec_cut_off[e] : 0;
+        for (int q = m.nbr_off[i]; q < m.nbr_off[i + 1]; ++q) {
+            int k = m.nbr[q];
+            if (k == j) continue;
+            double4 ak = m.atom[k];
+            double sk = ak.w + m.rho;
+            double wx = ak.x - oR.x, wy = ak.y - oR.y, wz = ak.z - oR.z;
+            double t = wx * n.x + wy * n.y + wz * n.z;
+            double ux = wx - t * n.x, uy = wy - t * n.y, uz = wz - t * n.z;
+            double b = sqrt(ux * ux + uy * uy + uz * uz);
+            if (!(t * t + sq(b - R) < sq(sk + LIST_SLACK))) continue;
+            if (FILL && fill_ok(m, w + cnt, m.ec_cut_off[e + 1])) {
+                double ww = wx * wx + wy * wy + wz * wz;
+                m.ec_cut[w + cnt] = make_double4(ux, uy, uz, (R * R + ww - sk * sk) / (2.0 * R));
+            }
+            ++cnt;
+        }
+        if (FILL) m.ec_circ[e] = c;
+        else cut_cnt[e] = cnt;
+        ++e;
+    }
+}
+
+__global__ void k_vert_off_atom(Mol m) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > m.n) return;
+    m.vert_off_atom[i] = m.vert_off[m.circ_off[i]];
+}
+
+// ---------------------------------------------------------------- tile lists
+
+// One wavefront per tile.  The tile box spans grid points [T t, T t + T] on
+// each axis (one point past the tile, so the box also holds the far ends of
+// the edges the tile owns).  Candidates are gathered from the cells that
+// overlap the box grown by s_max + rho and compacted with ballots.
+constexpr int TILE_WAVES = 4;
+
+template <bool FILL>
+__global__ void __launch_bounds__(TILE_WAVES *WAVE) k_tiles(Mol m, int *cntA, int *cntF,
+                                                             int *cntC, int *cntV) {
+    int tile = blockIdx.x * TILE_WAVES + threadIdx.x / WAVE;
+    if (tile >= m.ntiles) return;
+    const int lane = lane_id();
+    int t3[3] = {tile % m.tdims[0], (tile / m.tdims[0]) % m.tdims[1],
+                 tile / (m.tdims[0] * m.tdims[1])};
+    double blo[3], bhi[3];
+    int c0[3], c1[3];
+    const double grow = m.smax + m.rho + LIST_SLACK;
+    for (int a = 0; a < 3; ++a) {
+        blo[a] = m.lo[a] + (double)(t3[a] * m.tile) * m.h;
+        bhi[a] = m.lo[a] + (double)(t3[a] * m.tile + m.tile) * m.h;
+        c0[a] = cell_axis(m, blo[a] - grow, a);
+        c1[a] = cell_axis(m, bhi[a] + grow, a);
+    }
+    int nA = 0, nF = 0, nC = 0, nV = 0;
+    int oA = FILL ? m.tA_off[tile] : 0, oF = FILL ? m.tF_off[tile] : 0;
+    int oC = FILL ? m.tC_off[tile] : 0, oV = FILL ? m.tV_off[tile] : 0;
+    const double rho = m.rho;
+    for (int z = c0[2]; z <= c1[2]; ++z)
+        for (int y = c0[1]; y <= c1[1]; ++y)
+            for (int x = c0[0]; x <= c1[0]; ++x) {
+                int c = x + m.nc[0] * (y + m.nc[1] * z);
+                int ab = m.cell_start[c], ae = m.cell_start[c + 1];
+                for (int base = ab; base < ae; base += WAVE) {
+                    int i = base + lane;
+                    bool inA = false, inF = false;
+                    if (i < ae) {
+                        double4 a = m.atom[i];
+                        double s = a.w + rho;
+                        double d2 = box_dist2(blo, bhi, a.x, a.y, a.z);
+                        inA = d2 < sq(s + LIST_SLACK);
+                        inF = (m.aflag[i] & AF_FACE) && d2 < sq(s + rho + LIST_SLACK);
+                    }
+                    unsigned long long bA = __ballot(inA), bF = __ballot(inF);
+                    if (FILL) {
+                        int pa = oA + nA + mask_prefix(bA), pf = oF + nF + mask_prefix(bF);
+                        if (inA && fill_ok(m, pa, m.tA_off[tile + 1])) m.tA[pa] = i;
+                        if (inF && fill_ok(m, pf, m.tF_off[tile + 1])) m.tF[pf] = m.face_off_atom[i];
+                    }
+                    nA += __popcll(bA);
+                    nF += __popcll(bF);
+                }
+                int eb = m.ec_off_atom[ab], ee = m.ec_off_atom[ae];
+                for (int base = eb; base < ee; base += WAVE) {
+                    int e = base + lane;
+                    bool in = false;
+                    if (e < ee) {
+                        int ci = m.ec_circ[e];
+                        double4 oR = m.circ_oR[ci];
+                        double4 n = m.circ_n[ci];
+                        double d2 = box_dist2(blo, bhi, oR.x, oR.y, oR.z);
+                        // signed distance of the box from the circle's plane
+                        double tmin = 0.0, tmax = 0.0;
+                        double nv[3] = {n.x, n.y, n.z}, ov[3] = {oR.x, oR.y, oR.z};
+                        for (int a = 0; a < 3; ++a) {
+                            double u0 = nv[a] * (blo[a] - ov[a]), u1 = nv[a] * (bhi[a] - ov[a]);
+                            tmin += fmin(u0, u1);
+                            tmax += fmax(u0, u1);
+                        }
+                        in = d2 < sq(oR.w + rho + LIST_SLACK) && tmin < rho + LIST_SLACK &&
+                             tmax > -rho - LIST_SLACK;
+                    }
+                    unsigned long long bC = __ballot(in);
+                    int pc = oC + nC + mask_prefix(bC);
+                    if (FILL && in && fill_ok(m, pc, m.tC_off[tile + 1])) m.tC[pc] = e;
+                    nC += __popcll(bC);
+                }
+                int vb = m.vert_off_atom[ab], ve = m.vert_off_atom[ae];
+                for (int base = vb; base < ve; base += WAVE) {
+                    int v = base + lane;
+                    bool in = false;
+                    if (v < ve) {
+                        double4 p = m.vert_p[v];
+                        in = box_dist2(blo, bhi, p.x, p.y, p.z) < sq(rho + LIST_SLACK);
+                    }
+                    unsigned long long bV = __ballot(in);
+                    int pv = oV + nV + mask_prefix(bV);
+                    if (FILL && in && fill_ok(m, pv, m.tV_off[tile + 1])) m.tV[pv] = v;
+                    nV += __popcll(bV);
+                }
+            }
+    if (!FILL && lane == 0) {
+        cntA[tile] = nA;
+        cntF[tile] = nF;
+        cntC[tile] = nC;
+        cntV[tile] = nV;
+    }
+}
+
+// --------------------------------------------------------- vertex export
+
+// Caller ids in ascending order; the side flips with the parity of the sort,
+// since (p - c_a) . ((c_b - c_a) x (c_c - c_a)) is antisymmetric in (a, b, c).
+__global__ void k_export_vertices(Mol m, double *p, int *atoms, int8_t *sign, long long count) {
+    long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (v >= count) return;
+    double4 q = m.vert_p[v];
+    int4 t = m.vert_ijks[v];
+    int a[3] = {m.orig[t.x], m.orig[t.y], m.orig[t.z]};
+    int sg = t.w;
+    for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2 - x; ++y)
+            if (a[y] > a[y + 1]) {
+                int tmp = a[y];
+                a[y] = a[y + 1];
+                a[y + 1] = tmp;
+                sg = -sg;
+            }
+    p[3 * v] = q.x;
+    p[3 * v + 1] = q.y;
+    p[3 * v + 2] = q.z;
+    atoms[3 * v] = a[0];
+    atoms[3 * v + 1] = a[1];
+    atoms[3 * v + 2] = a[2];
+    sign[v] = (int8_t)sg;
+}
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t launch_export_vertices(const Mol &m, double *p, int *atoms, int8_t *sign,
+                                  long long count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_export_vertices, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
+                       m, p, atoms, sign, count);
+    return hipGetLastError();
+}
+
+static inline unsigned blocks_for(long long n, int bs) {
+    long long b = (n + bs - 1) / bs;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+hipError_t launch_bounds(const double *c, const double *r, long long n, double *out, int *bad,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_bounds, dim3(1), dim3(256), 0, st, c, r, n, out, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_count(const Mol &m, int *cell_id, int *count, hipStream_t st) {
+    hipLaunchKernelGGL(k_cell_count, dim3(blocks_for(m.n, 256)), dim3(256), 0, st, m, cell_id, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_scatter(const Mol &m, const int *cell_id, int *fill, int *slot_orig,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_cell_scatter, dim3(blocks_for(m.n, 256)), dim3(256), 0, st, m, cell_id,
+                       fill, slot_orig);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_sort_gather(const Mol &m, int *slot_orig, hipStream_t st) {
+    hipLaunchKernelGGL(k_cell_sort, dim3(blocks_for(m.ncell, 128)), dim3(128), 0, st, m, slot_orig);
+    hipLaunchKernelGGL(k_gather_atoms, dim3(blocks_for(m.n, 256)), dim3(256), 0, st, m, slot_orig);
+    return hipGetLastError();
+}
+
+hipError_t launch_nbr(const Mol &m, bool fill, int *nbr_cnt, int *circ_cnt, hipStream_t st) {
+    if (fill)
+        hipLaunchKernelGGL(k_nbr<true>, dim3(blocks_for(m.n, 128)), dim3(128), 0, st, m, nbr_cnt, circ_cnt);
+    else
+        hipLaunchKernelGGL(k_nbr<false>, dim3(blocks_for(m.n, 128)), dim3(128), 0, st, m, nbr_cnt, circ_cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_vertex(const Mol &m, bool fill, int *vcnt, hipStream_t st) {
+    if (fill)
+        hipLaunchKernelGGL(k_vertex<true>, dim3(blocks_for(m.ncirc, 128)), dim3(128), 0, st, m, vcnt);
+    else
+        hipLaunchKernelGGL(k_vertex<false>, dim3(blocks_for(m.ncirc, 128)), dim3(128), 0, st, m, vcnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_circle_free(const Mol &m, hipStream_t st) {
+    hipLaunchKernelGGL(k_circle_free, dim3(blocks_for(m.ncirc, 128)), dim3(128), 0, st, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_atom_features(const Mol &m, int *face_cnt, int *ec_cnt, int *vert_cnt,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(k_atom_features, dim3(blocks_for(m.n, 256)), dim3(256), 0, st, m, face_cnt,
+                       ec_cnt, vert_cnt);
+    hipLaunchKernelGGL(k_vert_off_atom, dim3(blocks_for(m.n + 1, 256)), dim3(256), 0, st, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_face_list(const Mol &m, int *cut_cnt, hipStream_t st) {
+    hipLaunchKernelGGL(k_face_list, dim3(blocks_for(m.n, 256)), dim3(256), 0, st, m, cut_cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_face_cuts(const Mol &m, hipStream_t st) {
+    hipLaunchKernelGGL(k_face_cuts, dim3(blocks_for(m.nface, 128)), dim3(128), 0, st, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_ec_list(const Mol &m, bool fill, int *cut_cnt, hipStream_t st) {
+    if (fill)
+        hipLaunchKernelGGL(k_ec_list<true>, dim3(blocks_for(m.n, 128)), dim3(128), 0, st, m, cut_cnt);
+    else
+        hipLaunchKernelGGL(k_ec_list<false>, dim3(blocks_for(m.n, 128)), dim3(128), 0, st, m, cut_cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_tiles(const Mol &m, bool fill, int *cA, int *cF, int *cC, int *cV,
+                        hipStream_t st) {
+    unsigned nb = blocks_for(m.ntiles, TILE_WAVES);
+    if (fill)
+        hipLaunchKernelGGL(k_tiles<true>, dim3(nb), dim3(TILE_WAVES * WAVE), 0, st, m, cA, cF, cC, cV);
+    else
+        hipLaunchKernelGGL(k_tiles<false>, dim3(nb), dim3(TILE_WAVES * WAVE), 0, st, m, cA, cF, cC, cV);
+    return hipGetLastError();
+}
+
+}  // namespace eses

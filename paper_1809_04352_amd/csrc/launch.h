@@ -1,0 +1,52 @@
+// Host-side launchers of the ESES kernels (one per kernel family).
+#pragma once
+
+#include "eses_internal.h"
+
+namespace eses {
+
+// utilities
+long long scan_tmp_elems(long long n);
+hipError_t scan_i32(const int *in, long long n, int *out, int *tmp, hipStream_t st);
+hipError_t scan_i64(const int *in, long long n, long long *out, long long *tmp, hipStream_t st);
+hipError_t fill_i32(int *p, long long n, int v, hipStream_t st);
+hipError_t fill_u32(uint32_t *p, long long n, uint32_t v, hipStream_t st);
+
+// stage 1
+hipError_t launch_bounds(const double *c, const double *r, long long n, double *out, int *bad,
+                         hipStream_t st);
+hipError_t launch_cell_count(const Mol &m, int *cell_id, int *count, hipStream_t st);
+hipError_t launch_cell_scatter(const Mol &m, const int *cell_id, int *fill, int *slot_orig,
+                               hipStream_t st);
+hipError_t launch_cell_sort_gather(const Mol &m, int *slot_orig, hipStream_t st);
+hipError_t launch_nbr(const Mol &m, bool fill, int *nbr_cnt, int *circ_cnt, hipStream_t st);
+hipError_t launch_vertex(const Mol &m, bool fill, int *vcnt, hipStream_t st);
+hipError_t launch_circle_free(const Mol &m, hipStream_t st);
+hipError_t launch_atom_features(const Mol &m, int *face_cnt, int *ec_cnt, int *vert_cnt,
+                                hipStream_t st);
+hipError_t launch_face_list(const Mol &m, int *cut_cnt, hipStream_t st);
+hipError_t launch_face_cuts(const Mol &m, hipStream_t st);
+hipError_t launch_ec_list(const Mol &m, bool fill, int *cut_cnt, hipStream_t st);
+hipError_t launch_tiles(const Mol &m, bool fill, int *cA, int *cF, int *cC, int *cV,
+                        hipStream_t st);
+
+// stage 2
+hipError_t launch_classify_fp64(const Mol &m, uint8_t *labels, hipStream_t st);
+hipError_t launch_classify_work(const Mol &m, unsigned long long *work, hipStream_t st);
+hipError_t launch_count_inside(const uint8_t *labels, long long n, unsigned long long *out,
+                               hipStream_t st);
+
+// stage 3
+hipError_t launch_edge_detect_count(const uint8_t *L, const Mol &m, int *bcount, long long *nblk,
+                                    hipStream_t st);
+hipError_t launch_edge_detect_write(const uint8_t *L, const Mol &m, const long long *boff,
+                                    long long cap, long long *keys, hipStream_t st);
+hipError_t launch_edge_roots(const Mol &m, const uint8_t *L, const long long *keys,
+                             long long count, double *lam, double *nrm, uint8_t *ptype,
+                             int *patoms, int *overflow, hipStream_t st);
+
+// vertex export
+hipError_t launch_export_vertices(const Mol &m, double *p, int *atoms, int8_t *sign,
+                                  long long count, hipStream_t st);
+
+}  // namespace eses

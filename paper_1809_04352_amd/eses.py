@@ -1,0 +1,303 @@
+"""Python binding of the gfx950 ESES library (include/eses.h).
+
+Argument marshalling only: device memory and streams come from PyTorch, every
+step of the computation runs in the HIP library.  Loading fails loudly if the
+library has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libeses_gfx950.so")
+
+ESES_OK = 0
+ESES_EINVAL = -1
+ESES_ENOMEM = -2
+ESES_ECAPACITY = -3
+ESES_EDEVICE = -4
+ESES_EINTERNAL = -5
+
+ESES_FP64 = 0
+ESES_FP32_RECHECK = 1
+
+EXPORTED = [
+    "eses_bbox_from_atoms", "eses_grid_dims", "eses_build_candidates", "eses_candidates_info",
+    "eses_copy_vertices", "eses_classify", "eses_edge_intersections", "eses_free_candidates",
+    "eses_last_error", "eses_version",
+]
+
+
+class EsesError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"eses status {status}: {msg}")
+        self.status = status
+
+
+class Molecule(ctypes.Structure):
+    _fields_ = [("centers", ctypes.c_void_p), ("radii", ctypes.c_void_p),
+                ("n_atoms", ctypes.c_int64), ("probe_radius", ctypes.c_double),
+                ("spacing", ctypes.c_double), ("bbox_lo", ctypes.c_double * 3),
+                ("bbox_hi", ctypes.c_double * 3)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+class CandidateStats(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int64), ("dims", ctypes.c_int32 * 3),
+                ("n_points", ctypes.c_int64), ("n_neighbour_pairs", ctypes.c_int64),
+                ("n_circles", ctypes.c_int64), ("n_vertices", ctypes.c_int64),
+                ("n_exposed_faces", ctypes.c_int64), ("n_exposed_circles", ctypes.c_int64),
+                ("n_tiles", ctypes.c_int64), ("tile_list_entries", ctypes.c_int64)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["dims"] = tuple(self.dims)
+        return d
+
+
+class ClassifyStats(ctypes.Structure):
+    _fields_ = [("n_points", ctypes.c_int64), ("n_inside", ctypes.c_int64),
+                ("n_rechecked", ctypes.c_int64), ("n_shell", ctypes.c_int64),
+                ("tests_atom", ctypes.c_int64), ("tests_vertex", ctypes.c_int64),
+                ("tests_face", ctypes.c_int64), ("tests_face_cut", ctypes.c_int64),
+                ("tests_circle", ctypes.c_int64), ("tests_circle_cut", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class IsectSoA(ctypes.Structure):
+    _fields_ = [("key", ctypes.c_void_p), ("lambda_", ctypes.c_void_p),
+                ("normal", ctypes.c_void_p), ("patch_type", ctypes.c_void_p),
+                ("atoms", ctypes.c_void_p), ("capacity", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load():
+    """Load the built library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"ESES HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    st = ctypes.c_int
+    lib.eses_last_error.restype = ctypes.c_char_p
+    lib.eses_version.restype = ctypes.c_char_p
+    lib.eses_bbox_from_atoms.restype = st
+    lib.eses_bbox_from_atoms.argtypes = [P, P, ctypes.c_int64, ctypes.c_double, P, P]
+    lib.eses_grid_dims.restype = st
+    lib.eses_grid_dims.argtypes = [ctypes.POINTER(Molecule), P]
+    lib.eses_build_candidates.restype = st
+    lib.eses_build_candidates.argtypes = [ctypes.POINTER(Molecule), ctypes.c_int32,
+                                          ctypes.POINTER(Config), P, ctypes.POINTER(P)]
+    lib.eses_candidates_info.restype = st
+    lib.eses_candidates_info.argtypes = [P, ctypes.c_int32, ctypes.POINTER(CandidateStats)]
+    lib.eses_copy_vertices.restype = st
+    lib.eses_copy_vertices.argtypes = [P, ctypes.c_int32, P, P, P, ctypes.c_int64,
+                                       ctypes.POINTER(ctypes.c_int64), P]
+    lib.eses_classify.restype = st
+    lib.eses_classify.argtypes = [P, ctypes.c_int, P, ctypes.POINTER(ClassifyStats), P]
+    lib.eses_edge_intersections.restype = st
+    lib.eses_edge_intersections.argtypes = [P, P, ctypes.POINTER(IsectSoA), P, P]
+    lib.eses_free_candidates.restype = None
+    lib.eses_free_candidates.argtypes = [P]
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != ESES_OK:
+        raise EsesError(status, load().eses_last_error().decode())
+
+
+def version() -> str:
+    return load().eses_version().decode()
+
+
+def bbox_from_atoms(centres, radii, margin: float):
+    c = np.ascontiguousarray(centres, dtype=np.float64)
+    r = np.ascontiguousarray(radii, dtype=np.float64)
+    lo = np.zeros(3)
+    hi = np.zeros(3)
+    _check(load().eses_bbox_from_atoms(c.ctypes.data, r.ctypes.data, r.shape[0], float(margin),
+                                       lo.ctypes.data, hi.ctypes.data))
+    return lo, hi
+
+
+def make_molecule(centres_dev, radii_dev, probe: float, spacing: float, lo, hi) -> Molecule:
+    """Descriptor over device tensors centres [n,3] and radii [n] (float64)."""
+    m = Molecule()
+    m.centers = centres_dev.data_ptr()
+    m.radii = radii_dev.data_ptr()
+    m.n_atoms = int(radii_dev.shape[0])
+    m.probe_radius = float(probe)
+    m.spacing = float(spacing)
+    for a in range(3):
+        m.bbox_lo[a] = float(lo[a])
+        m.bbox_hi[a] = float(hi[a])
+    return m
+
+
+def grid_dims(mol: Molecule):
+    d = (ctypes.c_int32 * 3)()
+    _check(load().eses_grid_dims(ctypes.byref(mol), ctypes.addressof(d)))
+    return tuple(int(v) for v in d)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return int(stream)
+
+
+class Candidates:
+    """Owning wrapper of an eses_candidates handle."""
+
+    def __init__(self, mols, tile: int = 0, stream=None):
+        lib = load()
+        self.mols = list(mols)
+        arr = (Molecule * len(self.mols))(*self.mols)
+        cfg = Config()
+        cfg.tile = int(tile)
+        h = ctypes.c_void_p()
+        self.stream = _stream_ptr(stream)
+        _check(lib.eses_build_candidates(arr, len(self.mols), ctypes.byref(cfg), self.stream,
+                                         ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            load().eses_free_candidates(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self, mol: int = 0) -> dict:
+        st = CandidateStats()
+        _check(load().eses_candidates_info(self.h, int(mol), ctypes.byref(st)))
+        return st.as_dict()
+
+
+def build_candidates(mols, tile: int = 0, stream=None) -> Candidates:
+    return Candidates(mols, tile, stream)
+
+
+def copy_vertices(cand: Candidates, mol: int, p_dev, atoms_dev, sign_dev, stream=None) -> int:
+    cnt = ctypes.c_int64()
+    cap = int(sign_dev.shape[0])
+    st = load().eses_copy_vertices(cand.h, int(mol), p_dev.data_ptr() if cap else None,
+                                   atoms_dev.data_ptr() if cap else None,
+                                   sign_dev.data_ptr() if cap else None, cap, ctypes.byref(cnt),
+                                   _stream_ptr(stream))
+    if st not in (ESES_OK, ESES_ECAPACITY):
+        _check(st)
+    return int(cnt.value)
+
+
+def classify(cand: Candidates, prec: int, labels_dev, stream=None, stats: bool = False):
+    n = len(labels_dev)
+    ptrs = (ctypes.c_void_p * n)(*[t.data_ptr() for t in labels_dev])
+    out = (ClassifyStats * n)() if stats else None
+    _check(load().eses_classify(cand.h, int(prec), ptrs, out, _stream_ptr(stream)))
+    if stats:
+        return [s.as_dict() for s in out]
+    return None
+
+
+@dataclass
+class IsectBuffers:
+    key: object
+    lam: object
+    normal: object
+    patch_type: object
+    atoms: object
+
+    @property
+    def capacity(self) -> int:
+        return int(self.key.shape[0])
+
+
+def alloc_isect(capacity: int, device="cuda"):
+    import torch
+    cap = max(int(capacity), 1)
+    return IsectBuffers(torch.empty(cap, dtype=torch.int64, device=device),
+                        torch.empty(cap, dtype=torch.float64, device=device),
+                        torch.empty((cap, 3), dtype=torch.float64, device=device),
+                        torch.empty(cap, dtype=torch.uint8, device=device),
+                        torch.empty((cap, 3), dtype=torch.int32, device=device))
+
+
+def edge_intersections(cand: Candidates, labels_dev, outs, stream=None):
+    """Returns (status, counts).  status is ESES_OK or ESES_ECAPACITY."""
+    n = len(labels_dev)
+    ptrs = (ctypes.c_void_p * n)(*[t.data_ptr() for t in labels_dev])
+    soa = (IsectSoA * n)()
+    for q, o in enumerate(outs):
+        soa[q].key = o.key.data_ptr()
+        soa[q].lambda_ = o.lam.data_ptr()
+        soa[q].normal = o.normal.data_ptr()
+        soa[q].patch_type = o.patch_type.data_ptr()
+        soa[q].atoms = o.atoms.data_ptr()
+        soa[q].capacity = o.capacity
+    counts = (ctypes.c_int64 * n)()
+    st = load().eses_edge_intersections(cand.h, ptrs, soa, counts, _stream_ptr(stream))
+    if st not in (ESES_OK, ESES_ECAPACITY):
+        _check(st)
+    return st, [int(c) for c in counts]
+
+
+def surface(centres, radii, probe: float, spacing: float, lo, hi, prec: int = ESES_FP64,
+            tile: int = 0, isect_capacity: int | None = None, device="cuda"):
+    """Whole hot path for one molecule given host arrays; returns host numpy results."""
+    import torch
+    c = torch.as_tensor(np.ascontiguousarray(centres, dtype=np.float64), device=device)
+    r = torch.as_tensor(np.ascontiguousarray(radii, dtype=np.float64), device=device)
+    mol = make_molecule(c, r, probe, spacing, lo, hi)
+    dims = grid_dims(mol)
+    cand = build_candidates([mol], tile)
+    try:
+        info = cand.info(0)
+        nv = info["n_vertices"]
+        vp = torch.empty((max(nv, 1), 3), dtype=torch.float64, device=device)
+        va = torch.empty((max(nv, 1), 3), dtype=torch.int32, device=device)
+        vs = torch.empty(max(nv, 1), dtype=torch.int8, device=device)
+        copy_vertices(cand, 0, vp, va, vs)
+        labels = torch.empty(dims[0] * dims[1] * dims[2], dtype=torch.uint8, device=device)
+        classify(cand, prec, [labels])
+        cap = isect_capacity if isect_capacity is not None else max(1024, labels.numel() // 8)
+        out = alloc_isect(cap, device)
+        status, counts = edge_intersections(cand, [labels], [out])
+        if status == ESES_ECAPACITY:
+            out = alloc_isect(counts[0], device)
+            status, counts = edge_intersections(cand, [labels], [out])
+        torch.cuda.synchronize()
+        k = counts[0]
+        return dict(
+            dims=dims,
+            info=info,
+            vertices=(vp[:nv].cpu().numpy(), va[:nv].cpu().numpy(), vs[:nv].cpu().numpy()),
+            labels=labels.cpu().numpy().reshape(dims[2], dims[1], dims[0]),
+            key=out.key[:k].cpu().numpy(),
+            lam=out.lam[:k].cpu().numpy(),
+            normal=out.normal[:k].cpu().numpy(),
+            patch_type=out.patch_type[:k].cpu().numpy(),
+            atoms=out.atoms[:k].cpu().numpy(),
+        )
+    finally:
+        cand.close()

@@ -1,0 +1,74 @@
+"""Comparison of the HIP path's outputs with the oracle's (test helper)."""
+import numpy as np
+
+POS_TOL = 1e-6      # angstrom, intersection positions
+NORMAL_TOL = 1e-6   # per component, unit normals
+
+
+def compare_vertices(gpu_vertices, oracle):
+    p, a, s = gpu_vertices
+    po, ao, so = oracle.vertices()
+    kg = {(int(x[0]), int(x[1]), int(x[2]), int(sg)): q for q, x, sg in zip(p, a, s)}
+    ko = {(int(x[0]), int(x[1]), int(x[2]), int(sg)): q for q, x, sg in zip(po, ao, so)}
+    assert len(kg) == len(p), "duplicate concave probe positions from the HIP path"
+    assert set(kg) == set(ko), (len(set(kg) - set(ko)), len(set(ko) - set(kg)))
+    if ko:
+        err = max(np.max(np.abs(kg[k] - ko[k])) for k in ko)
+        assert err < 1e-9, err
+    return len(ko)
+
+
+def compare_labels(gpu_labels, oracle_labels):
+    assert gpu_labels.shape == oracle_labels.shape
+    diff = np.flatnonzero(gpu_labels.reshape(-1) != oracle_labels.reshape(-1))
+    assert diff.size == 0, f"{diff.size} labels differ, first at flat index {diff[:5]}"
+
+
+def cusp_mask(res, centres, lo, h, dims, tol=1e-6):
+    """Saddle crossings on (or within tol of) the axis through their two atoms:
+    there every circle point is equally near, so the normal is not unique."""
+    key = res["key"]
+    nx, ny, _ = dims
+    axis = key % 3
+    idx = key // 3
+    p = np.stack([lo[0] + (idx % nx) * h, lo[1] + ((idx // nx) % ny) * h,
+                  lo[2] + (idx // (nx * ny)) * h], axis=1)
+    p[np.arange(len(key)), axis] += (1 - res["lam"]) * h
+    sad = res["patch_type"] == 2
+    out = np.zeros(len(key), bool)
+    if sad.any():
+        a = centres[res["atoms"][sad, 0]]
+        b = centres[res["atoms"][sad, 1]]
+        n = (b - a) / np.linalg.norm(b - a, axis=1, keepdims=True)
+        w = p[sad] - a
+        perp = w - np.sum(w * n, axis=1, keepdims=True) * n
+        out[sad] = np.linalg.norm(perp, axis=1) < tol
+    return out
+
+
+def compare_edges(res, oracle, lo, h, dims, ref_labels=None):
+    """Edge set identical to the oracle's crossing set; lambda (as a position
+    along the edge) within POS_TOL; normals within NORMAL_TOL; patch tags equal
+    except where two surfaces meet (ties of the owner).  Normals at saddle
+    cusps (crossings on the axis of a spindle torus) are not unique and are
+    not compared."""
+    from oracle.oracle import crossing_keys
+    key = res["key"]
+    assert np.all(np.diff(key) > 0), "keys not strictly ascending"
+    if ref_labels is not None:
+        want = crossing_keys(ref_labels)
+        assert np.array_equal(key, want), (len(key), len(want))
+    rec = oracle.edges(lo, h, dims, key)
+    assert np.all(rec["status"] == 1)
+    dpos = np.abs(rec["lam"] - res["lam"]) * h
+    assert dpos.max(initial=0.0) < POS_TOL, dpos.max()
+    dn = np.abs(rec["normal"] - res["normal"]).max(axis=1) if len(key) else np.zeros(0)
+    tag_same = (rec["type"] == res["patch_type"]) & np.all(rec["atoms"] == res["atoms"], axis=1)
+    # where the owner differs, two surfaces meet at the crossing: both records
+    # must still describe the same point
+    assert tag_same.mean() > 0.999 if len(key) else True
+    unique = tag_same & ~cusp_mask(res, oracle.c, lo, h, dims)
+    assert dn[unique].max(initial=0.0) < NORMAL_TOL, dn[unique].max(initial=0.0)
+    assert np.all(np.abs(np.linalg.norm(res["normal"], axis=1) - 1) < 1e-12)
+    assert set(np.unique(res["patch_type"])) <= {1, 2, 3}
+    return len(key), int((~tag_same).sum())

@@ -1,0 +1,144 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Labels bit-exact, the crossing-edge set identical, intersection positions
+within 1e-6 A and normals within 1e-6, concave probe positions identical as
+a set (triple + side) and within 1e-9 A.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from tests.parity import compare_edges, compare_labels, compare_vertices
+
+pytestmark = pytest.mark.gpu
+
+RHO = 1.4
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1809_04352_amd import eses
+    eses.load()
+    return eses
+
+
+def run_and_compare(E, oracle_mod, c, r, probe, h, lo, hi, prec, tile=0):
+    from eses_inputs import grid_dims
+    dims = grid_dims(lo, hi, h)
+    print(f"case: n={len(r)} h={h} dims={dims} prec={prec} tile={tile}", flush=True)
+    res = E.surface(c, r, probe, h, lo, hi, prec=prec, tile=tile)
+    assert res["dims"] == dims
+    o = oracle_mod.Oracle(c, r, probe)
+    ref = o.labels_grid(lo, h, dims)
+    compare_labels(res["labels"], ref)
+    nv = compare_vertices(res["vertices"], o)
+    ne, ties = compare_edges(res, o, lo, h, dims, ref)
+    return res, nv, ne
+
+
+@pytest.mark.parametrize("prec", [0])
+@pytest.mark.parametrize("n,seed,h,tile", [
+    (1, 1, 0.25, 8), (2, 2, 0.3, 8), (40, 3, 0.35, 8), (120, 4, 0.5, 4), (120, 4, 0.5, 8),
+    (300, 5, 0.45, 8),
+])
+def test_small_molecules(E, oracle_mod, prec, n, seed, h, tile):
+    from eses_inputs import molecule
+    m = molecule(n, seed, h)
+    run_and_compare(E, oracle_mod, m.centres, m.radii, m.probe, h, m.lo, m.hi, prec, tile)
+
+
+@pytest.mark.parametrize("prec", [0])
+def test_globule500(E, oracle_mod, prec):
+    from eses_inputs import workload
+    m = workload("globule500_h0.5")
+    res, nv, ne = run_and_compare(E, oracle_mod, m.centres, m.radii, m.probe, m.spacing, m.lo,
+                                  m.hi, prec)
+    assert nv > 100 and ne > 1000
+
+
+def test_dyadic_single_sphere_ties(E, oracle_mod):
+    """Grid points exactly on the sphere (dyadic inputs) are inside."""
+    c = np.array([[0.25, -0.5, 0.125]])
+    r = np.array([1.5])
+    lo = np.array([-4.0, -4.0, -4.0])
+    hi = np.array([4.0, 4.0, 4.0])
+    res, _, ne = run_and_compare(E, oracle_mod, c, r, RHO, 0.125, lo, hi, 0)
+    assert res["labels"].sum() > 0
+
+
+def test_two_atoms_on_grid_axis(E, oracle_mod):
+    """Atoms on a grid line: points on the circle's axis see every circle point
+    at the same distance (the degenerate nearest point)."""
+    c = np.array([[0.0, 0.0, 0.0], [5.6, 0.0, 0.0]])
+    r = np.array([1.5, 1.5])
+    lo = np.array([-4.0, -4.0, -4.0])
+    hi = np.array([9.6, 4.0, 4.0])
+    run_and_compare(E, oracle_mod, c, r, RHO, 0.2, lo, hi, 0)
+
+
+def test_sparse_atoms_far_apart(E, oracle_mod):
+    """Isolated atoms far apart (empty cells, tiles with no candidates)."""
+    c = np.array([[0.0, 0.0, 0.0], [30.0, 1.0, -2.0], [3.1, 0.2, 0.1]])
+    r = np.array([1.7, 1.2, 1.55])
+    from eses_inputs import bbox_from_atoms
+    lo, hi = bbox_from_atoms(c, r, 2.0)
+    run_and_compare(E, oracle_mod, c, r, RHO, 0.4, lo, hi, 0)
+
+
+def test_capacity_and_counts(E, oracle_mod):
+    import torch
+    from eses_inputs import molecule
+    m = molecule(80, 9, 0.5)
+    ct = torch.as_tensor(m.centres, device="cuda")
+    rt = torch.as_tensor(m.radii, device="cuda")
+    mol = E.make_molecule(ct, rt, m.probe, m.spacing, m.lo, m.hi)
+    cand = E.build_candidates([mol])
+    dims = E.grid_dims(mol)
+    lab = torch.empty(dims[0] * dims[1] * dims[2], dtype=torch.uint8, device="cuda")
+    E.classify(cand, 0, [lab])
+    small = E.alloc_isect(10)
+    st, counts = E.edge_intersections(cand, [lab], [small])
+    assert st == E.ESES_ECAPACITY and counts[0] > 10
+    full = E.alloc_isect(counts[0])
+    st, counts2 = E.edge_intersections(cand, [lab], [full])
+    assert st == E.ESES_OK and counts2 == counts
+    torch.cuda.synchronize()
+    assert np.array_equal(small.key.cpu().numpy(), full.key[:10].cpu().numpy())
+    assert np.array_equal(small.lam.cpu().numpy(), full.lam[:10].cpu().numpy())
+    stats = E.classify(cand, 0, [lab], stats=True)
+    assert stats[0]["n_inside"] == int(lab.sum().item())
+    cand.close()
+
+
+def test_invalid_device_input(E):
+    import torch
+    c = torch.zeros((2, 3), dtype=torch.float64, device="cuda")
+    r = torch.tensor([1.5, -1.0], dtype=torch.float64, device="cuda")
+    mol = E.make_molecule(c, r, 1.4, 0.5, [-5, -5, -5], [5, 5, 5])
+    with pytest.raises(E.EsesError) as ei:
+        E.build_candidates([mol])
+    assert ei.value.status == E.ESES_EINVAL
+
+
+def test_repeat_is_deterministic(E):
+    from eses_inputs import molecule
+    m = molecule(150, 12, 0.4)
+    a = E.surface(m.centres, m.radii, m.probe, m.spacing, m.lo, m.hi)
+    b = E.surface(m.centres, m.radii, m.probe, m.spacing, m.lo, m.hi)
+    for k in ("labels", "key", "lam", "normal", "patch_type", "atoms"):
+        assert np.array_equal(a[k], b[k]), k
+    for x, y in zip(a["vertices"], b["vertices"]):
+        assert np.array_equal(x, y)
+
+
+def test_tile_shape_invariance(E):
+    from eses_inputs import molecule
+    m = molecule(200, 13, 0.3)
+    a = E.surface(m.centres, m.radii, m.probe, m.spacing, m.lo, m.hi, tile=8)
+    b = E.surface(m.centres, m.radii, m.probe, m.spacing, m.lo, m.hi, tile=4)
+    for k in ("labels", "key", "lam", "normal", "patch_type", "atoms"):
+        assert np.array_equal(a[k], b[k]), k

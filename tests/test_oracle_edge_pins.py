@@ -203,3 +203,30 @@ def test_volume_consistent_across_axes(oracle_mod):
     assert max(vols) / min(vols) - 1 < 2e-3
     cnt = L.sum() * m.spacing ** 3
     assert abs(vols[0] / cnt - 1) < 0.05
+
+
+def test_spindle_axis_crossing_closed_form(oracle_mod):
+    """On the axis of a spindle torus (R < rho) every circle point is at the
+    same distance, so the label changes where sqrt((xi - a)^2 + R^2) = rho:
+    xi = a -+ sqrt(rho^2 - R^2).  There the torus quartic is a perfect square
+    and the crossing is a double root."""
+    r, d = 1.5, 5.6
+    s = r + RHO
+    c = np.array([[0.0, 0.0, 0.0], [d, 0.0, 0.0]])
+    o = oracle_mod.Oracle(c, [r, r], RHO)
+    a = d / 2
+    R = math.sqrt(s * s - a * a)
+    assert R < RHO
+    lo = np.array([-4.0, -4.0, -4.0])
+    h = 0.2
+    dims = (69, 41, 41)
+    nx, ny = dims[0], dims[1]
+    L = o.labels_grid(lo, h, dims)
+    keys = oracle_mod.crossing_keys(L)
+    j = k = 20  # y = z = 0
+    row = keys[(keys % 3 == 0) & ((keys // 3) // nx == j + ny * k)]
+    assert len(row) == 4  # van der Waals exits/entries around the open neck
+    rec = o.edges(lo, h, dims, row)
+    x = lo[0] + ((row // 3) % nx + 1 - rec["lam"]) * h
+    want = sorted([-r, a - math.sqrt(RHO ** 2 - R ** 2), a + math.sqrt(RHO ** 2 - R ** 2), d + r])
+    assert np.allclose(np.sort(x), want, atol=1e-9)
