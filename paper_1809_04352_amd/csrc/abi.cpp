@@ -257,18 +257,21 @@ eses_status build_one(const eses_molecule *in, int tile, MolState *S, hipStream_
     CK(launch_vertex(m, true, vcnt, st));
 
     // exposed faces and circles
-    int *face_cnt, *ec_cnt, *vert_cnt;
+    int *face_cnt, *ecf, *ec_pos;
     CKS(T.alloc(&face_cnt, m.n));
-    CKS(T.alloc(&ec_cnt, m.n));
-    CKS(T.alloc(&vert_cnt, m.n));
+    CKS(T.alloc(&ecf, m.ncirc));
+    CKS(T.alloc(&ec_pos, m.ncirc + 1));
     CKS(A.alloc(&m.face_off_atom, m.n + 1));
     CKS(A.alloc(&m.ec_off_atom, m.n + 1));
     CKS(A.alloc(&m.vert_off_atom, m.n + 1));
-    CK(launch_atom_features(m, face_cnt, ec_cnt, vert_cnt, st));
+    CK(launch_atom_features(m, face_cnt, st));
     CK(scan_i32(face_cnt, m.n, m.face_off_atom, tmp, st));
-    CK(scan_i32(ec_cnt, m.n, m.ec_off_atom, tmp, st));
+    CK(launch_ec_flag(m, ecf, st));
+    CK(scan_i32(ecf, m.ncirc, ec_pos, tmp2, st));
     CKS(d2h(&m.nface, m.face_off_atom + m.n, 1, st));
-    CKS(d2h(&m.nec, m.ec_off_atom + m.n, 1, st));
+    CKS(d2h(&m.nec, ec_pos + m.ncirc, 1, st));
+    CKS(A.alloc(&m.ec_circ, m.nec));
+    CK(launch_ec_ids(m, ec_pos, st));
 
     int *fcut_cnt, *eccut_cnt, *tmp3;
     CKS(A.alloc(&m.face_atom, m.nface));
@@ -282,15 +285,14 @@ eses_status build_one(const eses_molecule *in, int tile, MolState *S, hipStream_
     CKS(A.alloc(&m.face_cut, nfc));
     CK(launch_face_cuts(m, st));
 
-    CKS(A.alloc(&m.ec_circ, m.nec));
     CKS(A.alloc(&m.ec_cut_off, m.nec + 1));
     CKS(T.alloc(&eccut_cnt, m.nec));
-    CK(launch_ec_list(m, false, eccut_cnt, st));
+    CK(launch_ec_cuts(m, false, eccut_cnt, st));
     CK(scan_i32(eccut_cnt, m.nec, m.ec_cut_off, tmp3, st));
     int nec_cut = 0;
     CKS(d2h(&nec_cut, m.ec_cut_off + m.nec, 1, st));
     CKS(A.alloc(&m.ec_cut, nec_cut));
-    CK(launch_ec_list(m, true, eccut_cnt, st));
+    CK(launch_ec_cuts(m, true, eccut_cnt, st));
 
     // per-tile lists
     int *cA, *cF, *cC, *cV;

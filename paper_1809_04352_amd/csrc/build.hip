@@ -205,55 +205,71 @@ __device__ inline bool fill_ok(const Mol &m, long long at, long long end) {
 
 // ------------------------------------------------ SAS neighbours and circles
 
-// Thread per internal atom i.  Stencil cells are visited in increasing cell
-// index, and internal ids increase with the cell index, so each neighbour
-// list comes out ascending.
+// One wavefront per internal atom i; lanes take the atoms of each stencil
+// cell in turn and ballots compact the hits.  Stencil cells are visited in
+// increasing cell index and internal ids increase with the cell index, so
+// each neighbour list comes out ascending.
+constexpr int NB_WAVES = 4;
+
 template <bool FILL>
-__global__ void k_nbr(Mol m, int *nbr_cnt, int *circ_cnt) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m.n) return;
+__global__ void __launch_bounds__(NB_WAVES *WAVE) k_nbr(Mol m, int *nbr_cnt, int *circ_cnt) {
+    int i = blockIdx.x * NB_WAVES + threadIdx.x / WAVE;
+    if (i >= m.n) return;  // uniform across the wavefront
+    const int lane = lane_id();
     double4 ai = m.atom[i];
     double si = ai.w + m.rho;
     int cx = cell_axis(m, ai.x, 0), cy = cell_axis(m, ai.y, 1), cz = cell_axis(m, ai.z, 2);
     int nn = 0, nc = 0, nany = 0;
     bool contained = false;
-    int wn = FILL ? m.nbr_off[i] : 0;
-    int wc = FILL ? m.circ_off[i] : 0;
+    int wn = FILL ? m.nbr_off[i] : 0, en = FILL ? m.nbr_off[i + 1] : 0;
+    int wc = FILL ? m.circ_off[i] : 0, ecc = FILL ? m.circ_off[i + 1] : 0;
     for (int z = max(cz - 1, 0); z <= min(cz + 1, m.nc[2] - 1); ++z)
         for (int y = max(cy - 1, 0); y <= min(cy + 1, m.nc[1] - 1); ++y)
             for (int x = max(cx - 1, 0); x <= min(cx + 1, m.nc[0] - 1); ++x) {
                 int c = x + m.nc[0] * (y + m.nc[1] * z);
-                for (int k = m.cell_start[c], ke = m.cell_start[c + 1]; k < ke; ++k) {
-                    if (k == i) continue;
-                    double4 ak = m.atom[k];
-                    double sk = ak.w + m.rho;
-                    double dx = ak.x - ai.x, dy = ak.y - ai.y, dz = ak.z - ai.z;
-                    double d2 = dx * dx + dy * dy + dz * dz;
-                    if (!(d2 < sq(si + sk + LIST_SLACK))) continue;
-                    if (FILL && fill_ok(m, wn + nn, m.nbr_off[i + 1])) m.nbr[wn + nn] = k;
-                    ++nn;
-                    if (sqrt(d2) + si < sk) contained = true;
-                    double4 oR, n;
-                    if (pair_circle(ai, ak, m.rho, oR, n)) {
-                        ++nany;
-                        if (k > i) {
-                            if (FILL && fill_ok(m, wc + nc, m.circ_off[i + 1])) {
-                                m.circ_i[wc + nc] = i;
-                                m.circ_j[wc + nc] = k;
-                                m.circ_oR[wc + nc] = oR;
-                                m.circ_n[wc + nc] = n;
-                                m.cflag[wc + nc] = 0u;
+                int kb = m.cell_start[c], ke = m.cell_start[c + 1];
+                for (int base = kb; base < ke; base += WAVE) {
+                    int k = base + lane;
+                    bool nb = false, circ = false, any = false;
+                    double4 oR = make_double4(0, 0, 0, 0), n = make_double4(0, 0, 0, 0);
+                    if (k < ke && k != i) {
+                        double4 ak = m.atom[k];
+                        double sk = ak.w + m.rho;
+                        double dx = ak.x - ai.x, dy = ak.y - ai.y, dz = ak.z - ai.z;
+                        double d2 = dx * dx + dy * dy + dz * dz;
+                        nb = d2 < sq(si + sk + LIST_SLACK);
+                        if (nb) {
+                            if (sqrt(d2) + si < sk) contained = true;
+                            if (pair_circle(ai, ak, m.rho, oR, n)) {
+                                any = true;
+                                circ = k > i;
                             }
-                            ++nc;
                         }
                     }
+                    unsigned long long bn = __ballot(nb), bc = __ballot(circ), ba = __ballot(any);
+                    if (FILL) {
+                        int pn = wn + nn + mask_prefix(bn);
+                        if (nb && fill_ok(m, pn, en)) m.nbr[pn] = k;
+                        int pc = wc + nc + mask_prefix(bc);
+                        if (circ && fill_ok(m, pc, ecc)) {
+                            m.circ_i[pc] = i;
+                            m.circ_j[pc] = k;
+                            m.circ_oR[pc] = oR;
+                            m.circ_n[pc] = n;
+                            m.cflag[pc] = 0u;
+                        }
+                    }
+                    nn += __popcll(bn);
+                    nc += __popcll(bc);
+                    nany += __popcll(ba);
                 }
             }
-    if (!FILL) {
+    unsigned long long bcont = __ballot(contained);
+    if (!FILL && lane == 0) {
         nbr_cnt[i] = nn;
         circ_cnt[i] = nc;
         m.circ_any[i] = nany;
-        m.aflag[i] = contained ? AF_CONTAINED : 0u;
+        m.aflag[i] = bcont ? AF_CONTAINED : 0u;
     }
 }
 
@@ -272,85 +288,122 @@ __device__ inline int find_circle(const Mol &m, int a, int b) {
     return -1;
 }
 
-// Thread per circle (i, j).  For every k > j among i's neighbours, the circle
-// meets S_k where the in-plane angle phi to the direction of c_k satisfies
+// One wavefront per circle (i, j); lanes take the neighbours k > j of i.
+// The circle meets S_k where the in-plane angle phi to the direction of c_k
+// satisfies
 //   cos(phi) = (|c_k - o|^2 + R^2 - s_k^2) / (2 R b_k),
 // b_k = distance of c_k from the circle's axis.  The two points are
 // o + R (cos(phi) e +- sin(phi) n x e), e = in-plane unit vector towards c_k;
 // the "+" point has (p - c_i) . ((c_j - c_i) x (c_k - c_i)) > 0.  A point is
 // kept iff no neighbour other than j, k holds it strictly inside its SAS ball
-// (points on S_i can only be inside balls of i's neighbours).
+// (points on S_i can only be inside balls of i's neighbours).  Output order:
+// k ascending, "+" before "-".
+constexpr int VX_WAVES = 4;
+
 template <bool FILL>
-__global__ void k_vertex(Mol m, int *vcnt) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= m.ncirc) return;
+__global__ void __launch_bounds__(VX_WAVES *WAVE) k_vertex(Mol m, int *vcnt) {
+    int c = blockIdx.x * VX_WAVES + threadIdx.x / WAVE;
+    if (c >= m.ncirc) return;  // uniform across the wavefront
+    const int lane = lane_id();
     int i = m.circ_i[c], j = m.circ_j[c];
     double4 oR = m.circ_oR[c];
     double4 n = m.circ_n[c];
     double R = oR.w;
     int count = 0;
-    int wv = FILL ? m.vert_off[c] : 0;
-    uint32_t myflag = 0;
+    int wv = FILL ? m.vert_off[c] : 0, ev = FILL ? m.vert_off[c + 1] : 0;
+    uint32_t lflag = 0;
     int nb = m.nbr_off[i], ne = m.nbr_off[i + 1];
-    for (int q = nb; q < ne; ++q) {
-        int k = m.nbr[q];
-        if (k <= j) continue;
-        double4 ak = m.atom[k];
-        double sk = ak.w + m.rho;
-        double wx = ak.x - oR.x, wy = ak.y - oR.y, wz = ak.z - oR.z;
-        double t = wx * n.x + wy * n.y + wz * n.z;
-        double px = wx - t * n.x, py = wy - t * n.y, pz = wz - t * n.z;
-        double b = sqrt(px * px + py * py + pz * pz);
-        double ww = wx * wx + wy * wy + wz * wz;
-        if (!(b > 1e-12 * (sqrt(ww) + R))) continue;  // c_k on the axis: no isolated points
-        double cphi = (ww + R * R - sk * sk) / (2.0 * R * b);
-        if (!(cphi >= -1.0 && cphi <= 1.0)) continue;
-        bool crossed = cphi > -1.0 && cphi < 1.0;
-        double sphi = sqrt(fmax(0.0, 1.0 - cphi * cphi));
-        double ex = px / b, ey = py / b, ez = pz / b;
-        double fx = n.y * ez - n.z * ey, fy = n.z * ex - n.x * ez, fz = n.x * ey - n.y * ex;
-        bool any_exposed = false;
-        for (int sgn = 0; sgn < 2; ++sgn) {
-            double sp = sgn == 0 ? sphi : -sphi;
-            double vx = oR.x + R * (cphi * ex + sp * fx);
-            double vy = oR.y + R * (cphi * ey + sp * fy);
-            double vz = oR.z + R * (cphi * ez + sp * fz);
-            bool ok = true;
-            for (int q2 = nb; q2 < ne && ok; ++q2) {
-                int l = m.nbr[q2];
-                if (l == j || l == k) continue;
-                double4 al = m.atom[l];
-                double sl = al.w + m.rho;
-                double dx = vx - al.x, dy = vy - al.y, dz = vz - al.z;
-                if (dx * dx + dy * dy + dz * dz < sl * sl) ok = false;
+    // first neighbour above j (the list is ascending and holds j)
+    int lo = nb, hi = ne;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (m.nbr[mid] <= j) lo = mid + 1;
+        else hi = mid;
+    }
+    for (int base = lo; base < ne; base += WAVE) {
+        int q = base + lane;
+        bool live = false, crossed = false;
+        double v0x = 0, v0y = 0, v0z = 0, v1x = 0, v1y = 0, v1z = 0;
+        int k = -1;
+        if (q < ne) {
+            k = m.nbr[q];
+            double4 ak = m.atom[k];
+            double sk = ak.w + m.rho;
+            double wx = ak.x - oR.x, wy = ak.y - oR.y, wz = ak.z - oR.z;
+            double t = wx * n.x + wy * n.y + wz * n.z;
+            double px = wx - t * n.x, py = wy - t * n.y, pz = wz - t * n.z;
+            double b = sqrt(px * px + py * py + pz * pz);
+            double ww = wx * wx + wy * wy + wz * wz;
+            if (b > 1e-12 * (sqrt(ww) + R)) {  // c_k off the axis: isolated points
+                double cphi = (ww + R * R - sk * sk) / (2.0 * R * b);
+                if (cphi >= -1.0 && cphi <= 1.0) {
+                    live = true;
+                    crossed = cphi > -1.0 && cphi < 1.0;
+                    double sphi = sqrt(fmax(0.0, 1.0 - cphi * cphi));
+                    double ex = px / b, ey = py / b, ez = pz / b;
+                    double fx = n.y * ez - n.z * ey, fy = n.z * ex - n.x * ez, fz = n.x * ey - n.y * ex;
+                    v0x = oR.x + R * (cphi * ex + sphi * fx);
+                    v0y = oR.y + R * (cphi * ey + sphi * fy);
+                    v0z = oR.z + R * (cphi * ez + sphi * fz);
+                    v1x = oR.x + R * (cphi * ex - sphi * fx);
+                    v1y = oR.y + R * (cphi * ey - sphi * fy);
+                    v1z = oR.z + R * (cphi * ez - sphi * fz);
+                }
             }
-            if (!ok) continue;
-            any_exposed = true;
-            if (FILL && fill_ok(m, wv + count, m.vert_off[c + 1])) {
-                m.vert_p[wv + count] = make_double4(vx, vy, vz, 0.0);
-                m.vert_ijks[wv + count] = make_int4(i, j, k, sgn == 0 ? 1 : -1);
-            }
-            ++count;
         }
-        if (!FILL) {
-            uint32_t f = (crossed ? CF_CROSSED : 0u) | (any_exposed ? CF_EXPOSED_VERTEX : 0u);
+        bool ok0 = live, ok1 = live;
+        for (int q2 = nb; q2 < ne; ++q2) {
+            if (!__any(ok0 || ok1)) break;
+            int l = m.nbr[q2];
+            double4 al = m.atom[l];
+            double sl2 = sq(al.w + m.rho);
+            if (l == j || l == k) continue;
+            double d0 = sq(v0x - al.x) + sq(v0y - al.y) + sq(v0z - al.z);
+            double d1 = sq(v1x - al.x) + sq(v1y - al.y) + sq(v1z - al.z);
+            ok0 = ok0 && !(d0 < sl2);
+            ok1 = ok1 && !(d1 < sl2);
+        }
+        unsigned long long b0 = __ballot(ok0), b1 = __ballot(ok1);
+        if (FILL) {
+            // lane order, "+" before "-" within a lane
+            int before = __popcll(b0 & ((1ull << lane) - 1ull)) + __popcll(b1 & ((1ull << lane) - 1ull));
+            int p0 = wv + count + before;
+            int p1 = p0 + (ok0 ? 1 : 0);
+            if (ok0 && fill_ok(m, p0, ev)) {
+                m.vert_p[p0] = make_double4(v0x, v0y, v0z, 0.0);
+                m.vert_ijks[p0] = make_int4(i, j, k, 1);
+            }
+            if (ok1 && fill_ok(m, p1, ev)) {
+                m.vert_p[p1] = make_double4(v1x, v1y, v1z, 0.0);
+                m.vert_ijks[p1] = make_int4(i, j, k, -1);
+            }
+        } else {
+            bool anyx = ok0 || ok1;
+            uint32_t f = (crossed ? CF_CROSSED : 0u) | (anyx ? CF_EXPOSED_VERTEX : 0u);
             if (f) {
-                myflag |= f;
+                lflag |= f;
                 int cik = find_circle(m, i, k);
                 int cjk = find_circle(m, j, k);
                 if (cik >= 0) atomicOr(&m.cflag[cik], f);
                 if (cjk >= 0) atomicOr(&m.cflag[cjk], f);
             }
-            if (any_exposed) {
-                atomicOr(&m.aflag[i], AF_EXPOSED_VERTEX);
-                atomicOr(&m.aflag[j], AF_EXPOSED_VERTEX);
-                atomicOr(&m.aflag[k], AF_EXPOSED_VERTEX);
-            }
+            if (anyx) atomicOr(&m.aflag[k], AF_EXPOSED_VERTEX);
         }
+        count += __popcll(b0) + __popcll(b1);
     }
     if (!FILL) {
-        vcnt[c] = count;
-        if (myflag) atomicOr(&m.cflag[c], myflag);
+        // reduce the circle's own flags over the wavefront
+        uint32_t f = 0;
+        if (__any(lflag & CF_CROSSED)) f |= CF_CROSSED;
+        if (__any(lflag & CF_EXPOSED_VERTEX)) f |= CF_EXPOSED_VERTEX;
+        if (lane == 0) {
+            vcnt[c] = count;
+            if (f) atomicOr(&m.cflag[c], f);
+            if (f & CF_EXPOSED_VERTEX) {
+                atomicOr(&m.aflag[i], AF_EXPOSED_VERTEX);
+                atomicOr(&m.aflag[j], AF_EXPOSED_VERTEX);
+            }
+        }
     }
 }
 
@@ -379,11 +432,11 @@ __global__ void k_circle_free(Mol m) {
     atomicOr(&m.aflag[j], AF_EXPOSED_CIRCLE);
 }
 
-// Per atom: face flag and the counts that the feature scans need.
+// Per atom: the face flag.
 //   A face has an admissible point iff it carries an admissible
 //   three-sphere point or admissible crossing-free circle, or it has no
 //   circle at all and lies in no other ball (an isolated sphere).
-__global__ void k_atom_features(Mol m, int *face_cnt, int *ec_cnt, int *vert_cnt) {
+__global__ void k_atom_features(Mol m, int *face_cnt) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m.n) return;
     uint32_t f = m.aflag[i];
@@ -391,10 +444,6 @@ __global__ void k_atom_features(Mol m, int *face_cnt, int *ec_cnt, int *vert_cnt
                 (m.circ_any[i] == 0 && !(f & AF_CONTAINED));
     if (face) m.aflag[i] = f | AF_FACE;
     face_cnt[i] = face ? 1 : 0;
-    int e = 0;
-    for (int c = m.circ_off[i]; c < m.circ_off[i + 1]; ++c) e += (m.cflag[c] & CF_EXPOSED) ? 1 : 0;
-    ec_cnt[i] = e;
-    vert_cnt[i] = m.vert_off[m.circ_off[i + 1]] - m.vert_off[m.circ_off[i]];
 }
 
 // ------------------------------------------------------ exposed feature lists
@@ -408,63 +457,88 @@ __global__ void k_face_list(Mol m, int *cut_cnt) {
     cut_cnt[f] = m.nbr_off[i + 1] - m.nbr_off[i];
 }
 
-__global__ void k_face_cuts(Mol m) {
-    int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= m.nface) return;
+constexpr int FC_WAVES = 4;
+
+__global__ void __launch_bounds__(FC_WAVES *WAVE) k_face_cuts(Mol m) {
+    int f = blockIdx.x * FC_WAVES + threadIdx.x / WAVE;
+    if (f >= m.nface) return;  // uniform across the wavefront
     int i = m.face_atom[f];
     double4 ai = m.atom[i];
     double si = ai.w + m.rho;
     int w = m.face_cut_off[f];
-    for (int q = m.nbr_off[i]; q < m.nbr_off[i + 1]; ++q) {
+    int nb = m.nbr_off[i], ne = m.nbr_off[i + 1];
+    for (int q = nb + lane_id(); q < ne; q += WAVE) {
         double4 ak = m.atom[m.nbr[q]];
         double sk = ak.w + m.rho;
         double vx = ak.x - ai.x, vy = ak.y - ai.y, vz = ak.z - ai.z;
         double d2 = vx * vx + vy * vy + vz * vz;
-        m.face_cut[w++] = make_double4(vx, vy, vz, (si * si + d2 - sk * sk) / (2.0 * si));
+        m.face_cut[w + (q - nb)] = make_double4(vx, vy, vz, (si * si + d2 - sk * sk) / (2.0 * si));
     }
 }
 
-// Exposed circles: id list, then per circle the neighbours of the owner that
-// reach the circle (distance from c_k to the circle below s_k).
+// Exposed circles: a 0/1 flag per circle (scanned into positions), the id
+// list, then per exposed circle the neighbours of its owner that reach the
+// circle (distance from c_k to the circle below s_k), one wavefront per circle.
+__global__ void k_ec_flag(Mol m, int *ecf) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= m.ncirc) return;
+    ecf[c] = (m.cflag[c] & CF_EXPOSED) ? 1 : 0;
+}
+
+__global__ void k_ec_ids(Mol m, const int *ec_pos) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= m.ncirc) return;
+    if (m.cflag[c] & CF_EXPOSED) m.ec_circ[ec_pos[c]] = c;
+}
+
+constexpr int EC_WAVES = 4;
+
 template <bool FILL>
-__global__ void k_ec_list(Mol m, int *cut_cnt) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m.n) return;
-    int e = m.ec_off_atom[i];
-    for (int c = m.circ_off[i]; c < m.circ_off[i + 1]; ++c) {
-        if (!(m.cflag[c] & CF_EXPOSED)) continue;
-        int j = m.circ_j[c];
-        double4 oR = m.circ_oR[c];
-        double4 n = m.circ_n[c];
-        double R = oR.w;
-        int cnt = 0;
-        int w = FILL ? m.ec_cut_off[e] : 0;
-        for (int q = m.nbr_off[i]; q < m.nbr_off[i + 1]; ++q) {
+__global__ void __launch_bounds__(EC_WAVES *WAVE) k_ec_cuts(Mol m, int *cut_cnt) {
+    int e = blockIdx.x * EC_WAVES + threadIdx.x / WAVE;
+    if (e >= m.nec) return;  // uniform across the wavefront
+    const int lane = lane_id();
+    int c = m.ec_circ[e];
+    int i = m.circ_i[c], j = m.circ_j[c];
+    double4 oR = m.circ_oR[c];
+    double4 n = m.circ_n[c];
+    double R = oR.w;
+    int cnt = 0;
+    int w = FILL ? m.ec_cut_off[e] : 0, we = FILL ? m.ec_cut_off[e + 1] : 0;
+    for (int base = m.nbr_off[i]; base < m.nbr_off[i + 1]; base += WAVE) {
+        int q = base + lane;
+        bool in = false;
+        double4 cut = make_double4(0, 0, 0, 0);
+        if (q < m.nbr_off[i + 1]) {
             int k = m.nbr[q];
-            if (k == j) continue;
-            double4 ak = m.atom[k];
-            double sk = ak.w + m.rho;
-            double wx = ak.x - oR.x, wy = ak.y - oR.y, wz = ak.z - oR.z;
-            double t = wx * n.x + wy * n.y + wz * n.z;
-            double ux = wx - t * n.x, uy = wy - t * n.y, uz = wz - t * n.z;
-            double b = sqrt(ux * ux + uy * uy + uz * uz);
-            if (!(t * t + sq(b - R) < sq(sk + LIST_SLACK))) continue;
-            if (FILL && fill_ok(m, w + cnt, m.ec_cut_off[e + 1])) {
+            if (k != j) {
+                double4 ak = m.atom[k];
+                double sk = ak.w + m.rho;
+                double wx = ak.x - oR.x, wy = ak.y - oR.y, wz = ak.z - oR.z;
+                double t = wx * n.x + wy * n.y + wz * n.z;
+                double ux = wx - t * n.x, uy = wy - t * n.y, uz = wz - t * n.z;
+                double b = sqrt(ux * ux + uy * uy + uz * uz);
+                in = t * t + sq(b - R) < sq(sk + LIST_SLACK);
                 double ww = wx * wx + wy * wy + wz * wz;
-                m.ec_cut[w + cnt] = make_double4(ux, uy, uz, (R * R + ww - sk * sk) / (2.0 * R));
+                cut = make_double4(ux, uy, uz, (R * R + ww - sk * sk) / (2.0 * R));
             }
-            ++cnt;
         }
-        if (FILL) m.ec_circ[e] = c;
-        else cut_cnt[e] = cnt;
-        ++e;
+        unsigned long long bm = __ballot(in);
+        if (FILL) {
+            int p = w + cnt + mask_prefix(bm);
+            if (in && fill_ok(m, p, we)) m.ec_cut[p] = cut;
+        }
+        cnt += __popcll(bm);
     }
+    if (!FILL && lane == 0) cut_cnt[e] = cnt;
 }
 
-__global__ void k_vert_off_atom(Mol m) {
+// Per-atom offsets of the circle-ordered exposed-circle and vertex lists.
+__global__ void k_feature_off_atom(Mol m, const int *ec_pos) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i > m.n) return;
     m.vert_off_atom[i] = m.vert_off[m.circ_off[i]];
+    m.ec_off_atom[i] = ec_pos[m.circ_off[i]];
 }
 
 // ---------------------------------------------------------------- tile lists
@@ -635,31 +709,43 @@ hipError_t launch_cell_sort_gather(const Mol &m, int *slot_orig, hipStream_t st)
 }
 
 hipError_t launch_nbr(const Mol &m, bool fill, int *nbr_cnt, int *circ_cnt, hipStream_t st) {
+    unsigned nb = blocks_for(m.n, NB_WAVES);
     if (fill)
-        hipLaunchKernelGGL(k_nbr<true>, dim3(blocks_for(m.n, 128)), dim3(128), 0, st, m, nbr_cnt, circ_cnt);
+        hipLaunchKernelGGL(k_nbr<true>, dim3(nb), dim3(NB_WAVES * WAVE), 0, st, m, nbr_cnt, circ_cnt);
     else
-        hipLaunchKernelGGL(k_nbr<false>, dim3(blocks_for(m.n, 128)), dim3(128), 0, st, m, nbr_cnt, circ_cnt);
+        hipLaunchKernelGGL(k_nbr<false>, dim3(nb), dim3(NB_WAVES * WAVE), 0, st, m, nbr_cnt, circ_cnt);
     return hipGetLastError();
 }
 
 hipError_t launch_vertex(const Mol &m, bool fill, int *vcnt, hipStream_t st) {
+    if (m.ncirc <= 0) return hipSuccess;
+    unsigned nb = blocks_for(m.ncirc, VX_WAVES);
     if (fill)
-        hipLaunchKernelGGL(k_vertex<true>, dim3(blocks_for(m.ncirc, 128)), dim3(128), 0, st, m, vcnt);
+        hipLaunchKernelGGL(k_vertex<true>, dim3(nb), dim3(VX_WAVES * WAVE), 0, st, m, vcnt);
     else
-        hipLaunchKernelGGL(k_vertex<false>, dim3(blocks_for(m.ncirc, 128)), dim3(128), 0, st, m, vcnt);
+        hipLaunchKernelGGL(k_vertex<false>, dim3(nb), dim3(VX_WAVES * WAVE), 0, st, m, vcnt);
     return hipGetLastError();
 }
 
 hipError_t launch_circle_free(const Mol &m, hipStream_t st) {
+    if (m.ncirc <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_circle_free, dim3(blocks_for(m.ncirc, 128)), dim3(128), 0, st, m);
     return hipGetLastError();
 }
 
-hipError_t launch_atom_features(const Mol &m, int *face_cnt, int *ec_cnt, int *vert_cnt,
-                                hipStream_t st) {
-    hipLaunchKernelGGL(k_atom_features, dim3(blocks_for(m.n, 256)), dim3(256), 0, st, m, face_cnt,
-                       ec_cnt, vert_cnt);
-    hipLaunchKernelGGL(k_vert_off_atom, dim3(blocks_for(m.n + 1, 256)), dim3(256), 0, st, m);
+hipError_t launch_atom_features(const Mol &m, int *face_cnt, hipStream_t st) {
+    hipLaunchKernelGGL(k_atom_features, dim3(blocks_for(m.n, 256)), dim3(256), 0, st, m, face_cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_ec_flag(const Mol &m, int *ecf, hipStream_t st) {
+    hipLaunchKernelGGL(k_ec_flag, dim3(blocks_for(m.ncirc, 256)), dim3(256), 0, st, m, ecf);
+    return hipGetLastError();
+}
+
+hipError_t launch_ec_ids(const Mol &m, const int *ec_pos, hipStream_t st) {
+    hipLaunchKernelGGL(k_ec_ids, dim3(blocks_for(m.ncirc, 256)), dim3(256), 0, st, m, ec_pos);
+    hipLaunchKernelGGL(k_feature_off_atom, dim3(blocks_for(m.n + 1, 256)), dim3(256), 0, st, m, ec_pos);
     return hipGetLastError();
 }
 
@@ -669,15 +755,18 @@ hipError_t launch_face_list(const Mol &m, int *cut_cnt, hipStream_t st) {
 }
 
 hipError_t launch_face_cuts(const Mol &m, hipStream_t st) {
-    hipLaunchKernelGGL(k_face_cuts, dim3(blocks_for(m.nface, 128)), dim3(128), 0, st, m);
+    if (m.nface <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_face_cuts, dim3(blocks_for(m.nface, FC_WAVES)), dim3(FC_WAVES * WAVE), 0, st, m);
     return hipGetLastError();
 }
 
-hipError_t launch_ec_list(const Mol &m, bool fill, int *cut_cnt, hipStream_t st) {
+hipError_t launch_ec_cuts(const Mol &m, bool fill, int *cut_cnt, hipStream_t st) {
+    if (m.nec <= 0) return hipSuccess;
+    unsigned nb = blocks_for(m.nec, EC_WAVES);
     if (fill)
-        hipLaunchKernelGGL(k_ec_list<true>, dim3(blocks_for(m.n, 128)), dim3(128), 0, st, m, cut_cnt);
+        hipLaunchKernelGGL(k_ec_cuts<true>, dim3(nb), dim3(EC_WAVES * WAVE), 0, st, m, cut_cnt);
     else
-        hipLaunchKernelGGL(k_ec_list<false>, dim3(blocks_for(m.n, 128)), dim3(128), 0, st, m, cut_cnt);
+        hipLaunchKernelGGL(k_ec_cuts<false>, dim3(nb), dim3(EC_WAVES * WAVE), 0, st, m, cut_cnt);
     return hipGetLastError();
 }
 

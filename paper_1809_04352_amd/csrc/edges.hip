@@ -174,17 +174,19 @@ __device__ int quartic01(const double *g, double *out) {
     return nr;
 }
 
-constexpr int MAXR = 32;
+constexpr int MAXR = 12;   // roots per page of the walk
 
-__device__ inline void push_root(double *ru, int *rt, int &nr, int *overflow, double u, int type,
+// Sorted insertion by (u, type, id) keeping the MAXR smallest roots; a root
+// that does not fit marks the list truncated.
+__device__ inline void push_root(double *ru, int *rt, int &nr, bool &truncated, double u, int type,
                                  int id) {
-    if (nr >= MAXR) {
-        *overflow = 1;
-        return;
-    }
-    // insertion by (u, type)
-    int p = nr++;
     int key = (type << 28) | id;
+    if (nr == MAXR) {
+        truncated = true;
+        if (ru[MAXR - 1] < u || (ru[MAXR - 1] == u && rt[MAXR - 1] <= key)) return;
+        --nr;
+    }
+    int p = nr++;
     while (p > 0 && (ru[p - 1] > u || (ru[p - 1] == u && rt[p - 1] > key))) {
         ru[p] = ru[p - 1];
         rt[p] = rt[p - 1];
@@ -194,11 +196,125 @@ __device__ inline void push_root(double *ru, int *rt, int &nr, int *overflow, do
     rt[p] = key;
 }
 
+// A point y of the sphere S_i seen from x along c_i -> x is admissible iff
+// (x - c_i) . v_k <= |x - c_i| tau_k for every cut of the face.
+__device__ inline bool face_admissible(const Mol &m, int f, double dx, double dy, double dz) {
+    double d = sqrt(dx * dx + dy * dy + dz * dz);
+    for (int c = m.face_cut_off[f], ce = m.face_cut_off[f + 1]; c < ce; ++c) {
+        double4 v = m.face_cut[c];
+        if (dx * v.x + dy * v.y + dz * v.z > d * v.w) return false;
+    }
+    return true;
+}
+
+// The circle point nearest to x (w = x - o) is admissible iff
+// w_perp . u_k <= |w_perp| T_k for every cut of the circle.
+__device__ inline bool circle_admissible(const Mol &m, int ec, double4 n, double wx, double wy,
+                                         double wz) {
+    double t = wx * n.x + wy * n.y + wz * n.z;
+    double px = wx - t * n.x, py = wy - t * n.y, pz = wz - t * n.z;
+    double b = sqrt(px * px + py * py + pz * pz);
+    if (!(b > 0.0)) {
+        perp_unit(n.x, n.y, n.z, px, py, pz);
+        b = 1.0;
+    }
+    for (int c = m.ec_cut_off[ec], ce = m.ec_cut_off[ec + 1]; c < ce; ++c) {
+        double4 u = m.ec_cut[c];
+        if (px * u.x + py * u.y + pz * u.z > b * u.w) return false;
+    }
+    return true;
+}
+
 __device__ inline void sort3(int &a, int &b, int &c) {
     int t;
     if (a > b) { t = a; a = b; b = t; }
     if (b > c) { t = b; b = c; c = t; }
     if (a > b) { t = a; a = b; b = t; }
+}
+
+// Roots of surfaces that can carry the boundary of M on the edge.  A root x is
+// kept only if the point of A that would put x on the boundary is admissible:
+// the radial projection onto an exposed face (van der Waals roots) or the
+// nearest point of an exposed circle (torus roots).  Every label change lies
+// on such a point, so dropping the others is exact.  Only roots u > lower
+// are kept (the MAXR smallest of them).
+__device__ void collect_roots(const Mol &m, int tile, int axis, const double *xs,
+                              const double *mid, double lower, double *ru, int *rt, int &nr,
+                              bool &truncated) {
+    const double h = m.h, rho = m.rho;
+    nr = 0;
+    truncated = false;
+    double tmp[4];
+    // A surface can cross the edge only if its distance from the edge's
+    // midpoint is within h/2 of zero (distance to a set is 1-Lipschitz).
+    const double half = 0.5 * h + 1e-9;
+    // van der Waals spheres of atoms with an exposed face
+    for (int p = m.tF_off[tile], e = m.tF_off[tile + 1]; p < e; ++p) {
+        int f = m.tF[p];
+        int i = m.face_atom[f];
+        double4 a = m.atom[i];
+        double dm2 = sq(mid[0] - a.x) + sq(mid[1] - a.y) + sq(mid[2] - a.z);
+        if (dm2 > sq(a.w + half) || (a.w > half && dm2 < sq(a.w - half))) continue;
+        double w0[3] = {xs[0] - a.x, xs[1] - a.y, xs[2] - a.z};
+        int n = quad01(h * h, 2.0 * h * w0[axis],
+                       w0[0] * w0[0] + w0[1] * w0[1] + w0[2] * w0[2] - a.w * a.w, tmp);
+        for (int t = 0; t < n; ++t) {
+            double x[3] = {w0[0], w0[1], w0[2]};
+            x[axis] += tmp[t] * h;
+            if (face_admissible(m, f, x[0], x[1], x[2]))
+                if (tmp[t] > lower) push_root(ru, rt, nr, truncated, tmp[t], 1, i);
+        }
+    }
+    // probe spheres around concave probe positions
+    for (int p = m.tV_off[tile], e = m.tV_off[tile + 1]; p < e; ++p) {
+        int v = m.tV[p];
+        double4 c = m.vert_p[v];
+        double dm2 = sq(mid[0] - c.x) + sq(mid[1] - c.y) + sq(mid[2] - c.z);
+        if (dm2 > sq(rho + half) || (rho > half && dm2 < sq(rho - half))) continue;
+        double w0[3] = {xs[0] - c.x, xs[1] - c.y, xs[2] - c.z};
+        int n = quad01(h * h, 2.0 * h * w0[axis],
+                       w0[0] * w0[0] + w0[1] * w0[1] + w0[2] * w0[2] - rho * rho, tmp);
+        for (int t = 0; t < n; ++t)
+            if (tmp[t] > lower) push_root(ru, rt, nr, truncated, tmp[t], 3, v);
+    }
+    // tori: (|w|^2 + R^2 - rho^2)^2 = 4 R^2 |w_perp|^2, the branch at distance
+    // rho from the near circle point
+    for (int p = m.tC_off[tile], e = m.tC_off[tile + 1]; p < e; ++p) {
+        int ec = m.tC[p];
+        int ci = m.ec_circ[ec];
+        double4 oR = m.circ_oR[ci];
+        double4 nn = m.circ_n[ci];
+        double R = oR.w;
+        double dm[3] = {mid[0] - oR.x, mid[1] - oR.y, mid[2] - oR.z};
+        {
+            double tm = dm[0] * nn.x + dm[1] * nn.y + dm[2] * nn.z;
+            double bm = sqrt(fmax(0.0, dm[0] * dm[0] + dm[1] * dm[1] + dm[2] * dm[2] - tm * tm));
+            double dc2 = tm * tm + sq(bm - R);  // squared distance of the midpoint from the circle
+            if (dc2 > sq(rho + half) || (rho > half && dc2 < sq(rho - half))) continue;
+        }
+        double w0[3] = {xs[0] - oR.x, xs[1] - oR.y, xs[2] - oR.z};
+        double nv[3] = {nn.x, nn.y, nn.z};
+        double ww = w0[0] * w0[0] + w0[1] * w0[1] + w0[2] * w0[2];
+        double t0 = w0[0] * nv[0] + w0[1] * nv[1] + w0[2] * nv[2];
+        double RR = R * R;
+        double a0 = ww + RR - rho * rho, a1 = 2.0 * h * w0[axis], a2 = h * h;
+        double b0 = ww - t0 * t0, b1 = 2.0 * h * (w0[axis] - t0 * nv[axis]),
+               b2 = h * h * (1.0 - nv[axis] * nv[axis]);
+        double g[5] = {a0 * a0 - 4.0 * RR * b0, 2.0 * a0 * a1 - 4.0 * RR * b1,
+                       a1 * a1 + 2.0 * a0 * a2 - 4.0 * RR * b2, 2.0 * a1 * a2, a2 * a2};
+        double r4[10];
+        int n = quartic01(g, r4);
+        for (int t = 0; t < n; ++t) {
+            double x[3] = {w0[0], w0[1], w0[2]};
+            x[axis] += r4[t] * h;
+            double tt = x[0] * nv[0] + x[1] * nv[1] + x[2] * nv[2];
+            double bb = sqrt(fmax(0.0, x[0] * x[0] + x[1] * x[1] + x[2] * x[2] - tt * tt));
+            double near = fabs(sq(bb - R) + tt * tt - rho * rho);
+            double far = fabs(sq(bb + R) + tt * tt - rho * rho);
+            if (r4[t] > lower && near <= far && circle_admissible(m, ec, nn, x[0], x[1], x[2]))
+                push_root(ru, rt, nr, truncated, r4[t], 2, ec);
+        }
+    }
 }
 
 __global__ void __launch_bounds__(256) k_edge_roots(Mol m, const uint8_t *L, const long long *keys,
@@ -223,107 +339,56 @@ __global__ void __launch_bounds__(256) k_edge_roots(Mol m, const uint8_t *L, con
     double ru[MAXR];
     int rt[MAXR];
     int nr = 0;
-    double tmp[4];
-    // van der Waals spheres
-    for (int p = m.tA_off[tile], e = m.tA_off[tile + 1]; p < e; ++p) {
-        int i = m.tA[p];
-        double4 a = m.atom[i];
-        double w0[3] = {xs[0] - a.x, xs[1] - a.y, xs[2] - a.z};
-        int n = quad01(h * h, 2.0 * h * w0[axis],
-                       w0[0] * w0[0] + w0[1] * w0[1] + w0[2] * w0[2] - a.w * a.w, tmp);
-        for (int t = 0; t < n; ++t) push_root(ru, rt, nr, overflow, tmp[t], 1, i);
-    }
-    // probe spheres around concave probe positions
-    for (int p = m.tV_off[tile], e = m.tV_off[tile + 1]; p < e; ++p) {
-        int v = m.tV[p];
-        double4 c = m.vert_p[v];
-        double w0[3] = {xs[0] - c.x, xs[1] - c.y, xs[2] - c.z};
-        int n = quad01(h * h, 2.0 * h * w0[axis],
-                       w0[0] * w0[0] + w0[1] * w0[1] + w0[2] * w0[2] - rho * rho, tmp);
-        for (int t = 0; t < n; ++t) push_root(ru, rt, nr, overflow, tmp[t], 3, v);
-    }
-    // tori: (|w|^2 + R^2 - rho^2)^2 = 4 R^2 |w_perp|^2, the branch at distance
-    // rho from the near circle point
-    for (int p = m.tC_off[tile], e = m.tC_off[tile + 1]; p < e; ++p) {
-        int ec = m.tC[p];
-        int ci = m.ec_circ[ec];
-        double4 oR = m.circ_oR[ci];
-        double4 nn = m.circ_n[ci];
-        double R = oR.w;
-        double dm[3] = {mid[0] - oR.x, mid[1] - oR.y, mid[2] - oR.z};
-        if (dm[0] * dm[0] + dm[1] * dm[1] + dm[2] * dm[2] > sq(R + rho + 0.5 * h)) continue;
-        double w0[3] = {xs[0] - oR.x, xs[1] - oR.y, xs[2] - oR.z};
-        double nv[3] = {nn.x, nn.y, nn.z};
-        double ww = w0[0] * w0[0] + w0[1] * w0[1] + w0[2] * w0[2];
-        double t0 = w0[0] * nv[0] + w0[1] * nv[1] + w0[2] * nv[2];
-        double RR = R * R;
-        double a0 = ww + RR - rho * rho, a1 = 2.0 * h * w0[axis], a2 = h * h;
-        double b0 = ww - t0 * t0, b1 = 2.0 * h * (w0[axis] - t0 * nv[axis]),
-               b2 = h * h * (1.0 - nv[axis] * nv[axis]);
-        double g[5] = {a0 * a0 - 4.0 * RR * b0, 2.0 * a0 * a1 - 4.0 * RR * b1,
-                       a1 * a1 + 2.0 * a0 * a2 - 4.0 * RR * b2, 2.0 * a1 * a2, a2 * a2};
-        double r4[10];
-        int n = quartic01(g, r4);
-        for (int t = 0; t < n; ++t) {
-            double x[3] = {w0[0], w0[1], w0[2]};
-            x[axis] += r4[t] * h;
-            double tt = x[0] * nv[0] + x[1] * nv[1] + x[2] * nv[2];
-            double bb = sqrt(fmax(0.0, x[0] * x[0] + x[1] * x[1] + x[2] * x[2] - tt * tt));
-            double near = fabs(sq(bb - R) + tt * tt - rho * rho);
-            double far = fabs(sq(bb + R) + tt * tt - rho * rho);
-            if (near <= far) push_root(ru, rt, nr, overflow, r4[t], 2, ec);
-        }
-    }
+    bool truncated = false;
 
     // Walk the intervals from s.  The label is constant between consecutive
-    // roots; the first interval has Inside[s] and the last Inside[t] unless
-    // a root sits exactly on that end.
-    bool root0 = nr > 0 && ru[0] == 0.0;
-    bool root1 = nr > 0 && ru[nr - 1] == 1.0;
+    // roots; the first interval has Inside[s] and the last Inside[t] unless a
+    // root sits exactly on that end.  Roots come in pages of the MAXR smallest
+    // above the last one walked; a page that ends before t is followed by the
+    // next one.
     double ustar = 1.0;
-    int owner = -1;
     double prev = 0.0;
-    int prev_idx = -1;
-    for (int r = 0; r <= nr; ++r) {
-        double next = r < nr ? ru[r] : 1.0;
-        if (next > prev) {
-            int lab;
-            if (prev == 0.0 && !root0) lab = Ls;
-            else if (next == 1.0 && !root1) lab = Lt;
-            else {
-                double x[3] = {xs[0], xs[1], xs[2]};
-                x[axis] += 0.5 * (prev + next) * h;
-                lab = label_fp64(m, tile, x[0], x[1], x[2]);
+    int prev_key = -1, owner_key = -1;
+    bool found = false;
+    for (int page = 0; page < 64; ++page) {
+        const bool first = page == 0;
+        collect_roots(m, tile, axis, xs, mid, first ? -1.0 : prev, ru, rt, nr, truncated);
+        bool root0 = first && nr > 0 && ru[0] == 0.0;
+        bool root1 = !truncated && nr > 0 && ru[nr - 1] == 1.0;
+        for (int r = 0; r <= nr; ++r) {
+            if (r == nr && truncated) break;
+            double next = r < nr ? ru[r] : 1.0;
+            if (next > prev) {
+                int lab;
+                if (first && prev == 0.0 && !root0) lab = Ls;
+                else if (r == nr && !root1) lab = Lt;
+                else {
+                    double x[3] = {xs[0], xs[1], xs[2]};
+                    x[axis] += 0.5 * (prev + next) * h;
+                    lab = label_fp64(m, tile, x[0], x[1], x[2]);
+                }
+                if (lab != Ls) {
+                    ustar = prev;
+                    owner_key = prev_key;
+                    found = true;
+                    break;
+                }
             }
-            if (lab != Ls) {
-                ustar = prev;
-                owner = prev_idx;
-                break;
-            }
+            if (r < nr && (prev_key < 0 || next > prev)) prev_key = rt[r];
+            if (next > prev) prev = next;
         }
-        if (r < nr && (prev_idx < 0 || next > prev)) {
-            prev_idx = r;
-        }
-        if (next > prev) prev = next;
+        if (found || !truncated) break;
+        if (page == 63) *overflow = 1;
     }
-    if (owner < 0 && nr > 0) {
-        // change at u* = 0 (a root at s) or at t: the root closest to u*
-        int best = 0;
-        double bd = fabs(ru[0] - ustar);
-        for (int r = 1; r < nr; ++r)
-            if (fabs(ru[r] - ustar) < bd) {
-                bd = fabs(ru[r] - ustar);
-                best = r;
-            }
-        owner = best;
-    }
+    // no change inside the edge: it happens at t itself (the last root)
+    if (!found) owner_key = prev_key;
     double xst[3] = {xs[0], xs[1], xs[2]};
     xst[axis] += ustar * h;
     double n3[3] = {0.0, 0.0, 0.0};
     int type = 0, at[3] = {-1, -1, -1};
-    if (owner >= 0) {
-        type = rt[owner] >> 28;
-        int id = rt[owner] & ((1 << 28) - 1);
+    if (owner_key >= 0) {
+        type = owner_key >> 28;
+        int id = owner_key & ((1 << 28) - 1);
         double y[3];
         if (type == 1) {
             double4 a = m.atom[id];

@@ -22,11 +22,12 @@ hipError_t launch_cell_sort_gather(const Mol &m, int *slot_orig, hipStream_t st)
 hipError_t launch_nbr(const Mol &m, bool fill, int *nbr_cnt, int *circ_cnt, hipStream_t st);
 hipError_t launch_vertex(const Mol &m, bool fill, int *vcnt, hipStream_t st);
 hipError_t launch_circle_free(const Mol &m, hipStream_t st);
-hipError_t launch_atom_features(const Mol &m, int *face_cnt, int *ec_cnt, int *vert_cnt,
-                                hipStream_t st);
+hipError_t launch_atom_features(const Mol &m, int *face_cnt, hipStream_t st);
+hipError_t launch_ec_flag(const Mol &m, int *ecf, hipStream_t st);
+hipError_t launch_ec_ids(const Mol &m, const int *ec_pos, hipStream_t st);
 hipError_t launch_face_list(const Mol &m, int *cut_cnt, hipStream_t st);
 hipError_t launch_face_cuts(const Mol &m, hipStream_t st);
-hipError_t launch_ec_list(const Mol &m, bool fill, int *cut_cnt, hipStream_t st);
+hipError_t launch_ec_cuts(const Mol &m, bool fill, int *cut_cnt, hipStream_t st);
 hipError_t launch_tiles(const Mol &m, bool fill, int *cA, int *cF, int *cC, int *cV,
                         hipStream_t st);
 
