@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run one plain device copy of this many MiB (a known-size "
+                         "reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -219,6 +222,14 @@ def main():
             "flops_per_point": flops_classify / npts,
         },
     }
+    if args.calibrate_copy > 0:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        res["calibrate_copy_bytes"] = nbytes
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(m, n_cross, args.cpu_seconds)
     print(json.dumps(res))

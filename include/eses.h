@@ -92,7 +92,10 @@ typedef struct {
 /* Tuning knobs; pass NULL for defaults.  Results never depend on them. */
 typedef struct {
     int32_t tile;          /* tile edge in grid points: 4 or 8 (default 8) */
-    int32_t reserved[7];   /* must be zero */
+    int32_t force_recheck; /* test aid: with ESES_FP32_RECHECK, treat every FP32
+                              decision as uncertain so each point is re-tested
+                              in FP64 (0 = off) */
+    int32_t reserved[6];   /* must be zero */
 } eses_config;
 
 typedef struct eses_candidates eses_candidates; /* opaque, library-owned */

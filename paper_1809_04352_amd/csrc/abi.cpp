@@ -129,7 +129,8 @@ eses_status d2h(T *host, const T *dev, size_t count, hipStream_t st) {
 }
 
 // Stage 1 for one molecule.
-eses_status build_one(const eses_molecule *in, int tile, MolState *S, hipStream_t st) {
+eses_status build_one(const eses_molecule *in, int tile, int force_recheck, MolState *S,
+                      hipStream_t st) {
     Mol &m = S->m;
     Arena &A = S->arena;
     Arena &T = S->scratch;
@@ -160,6 +161,7 @@ eses_status build_one(const eses_molecule *in, int tile, MolState *S, hipStream_
     m.in_c = in->centers;
     m.in_r = in->radii;
     m.tile = tile;
+    m.force_recheck = force_recheck ? 1 : 0;
     for (int a = 0; a < 3; ++a) m.tdims[a] = (dims[a] + tile - 1) / tile;
     long long ntiles = (long long)m.tdims[0] * m.tdims[1] * m.tdims[2];
     if (ntiles > (1LL << 30)) {
@@ -400,10 +402,11 @@ eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
         set_err("need at least one molecule");
         return ESES_EINVAL;
     }
-    int tile = 8;
+    int tile = 8, force_recheck = 0;
     if (cfg) {
         if (cfg->tile != 0) tile = cfg->tile;
-        for (int q = 0; q < 7; ++q)
+        force_recheck = cfg->force_recheck;
+        for (int q = 0; q < 6; ++q)
             if (cfg->reserved[q] != 0) {
                 set_err("eses_config.reserved must be zero");
                 return ESES_EINVAL;
@@ -419,7 +422,7 @@ eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
     for (int32_t q = 0; q < n_mols; ++q) {
         MolState *S = new MolState();
         c->mols.push_back(S);
-        eses_status s = build_one(&mols[q], tile, S, st);
+        eses_status s = build_one(&mols[q], tile, force_recheck, S, st);
         if (s != ESES_OK) {
             std::string msg = g_err;
             eses_free_candidates(c);
@@ -476,24 +479,28 @@ eses_status eses_classify(eses_candidates *c, eses_precision prec, uint8_t *cons
         return ESES_EINVAL;
     }
     hipStream_t st = (hipStream_t)stream;
-    for (size_t q = 0; q < c->mols.size(); ++q) {
+    for (size_t q = 0; q < c->mols.size(); ++q)
         if (!labels[q]) {
             set_err("labels[%zu] is NULL", q);
             return ESES_EINVAL;
         }
-        const Mol &m = c->mols[q]->m;
-        CK(launch_classify_fp64(m, labels[q], st));
-    }
+    if (stats)
+        for (size_t q = 0; q < c->mols.size(); ++q) CK(fill_i32(c->mols[q]->m.diag + 1, 1, 0, st));
+    for (size_t q = 0; q < c->mols.size(); ++q)
+        CK(launch_classify(c->mols[q]->m, prec == ESES_FP32_RECHECK, labels[q], st));
     if (stats) {
         const size_t nm = c->mols.size();
-        const size_t per = 1 + WC_COUNT;
+        const size_t per = 2 + WC_COUNT;
         unsigned long long *d = nullptr;
         CK(hipMallocAsync((void **)&d, sizeof(unsigned long long) * nm * per, st));
         std::vector<unsigned long long> h(nm * per);
         CK(fill_u32((uint32_t *)d, (long long)(2 * nm * per), 0u, st));
+        std::vector<int> rechecked(nm);
         for (size_t q = 0; q < nm; ++q) {
             CK(launch_count_inside(labels[q], c->mols[q]->m.npts, d + q * per, st));
-            CK(launch_classify_work(c->mols[q]->m, d + q * per + 1, st));
+            CK(launch_classify_work(c->mols[q]->m, d + q * per + 2, st));
+            CK(hipMemcpyAsync(&rechecked[q], c->mols[q]->m.diag + 1, sizeof(int),
+                              hipMemcpyDeviceToHost, st));
         }
         CK(hipMemcpyAsync(h.data(), d, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost, st));
         CK(hipFreeAsync(d, st));
@@ -503,14 +510,14 @@ eses_status eses_classify(eses_candidates *c, eses_precision prec, uint8_t *cons
             eses_classify_stats &o = stats[q];
             o.n_points = c->mols[q]->m.npts;
             o.n_inside = (int64_t)w[0];
-            o.n_rechecked = 0;
-            o.tests_atom = (int64_t)w[1 + WC_ATOM];
-            o.tests_vertex = (int64_t)w[1 + WC_VERTEX];
-            o.tests_face = (int64_t)w[1 + WC_FACE];
-            o.tests_face_cut = (int64_t)w[1 + WC_FACE_CUT];
-            o.tests_circle = (int64_t)w[1 + WC_CIRCLE];
-            o.tests_circle_cut = (int64_t)w[1 + WC_CIRCLE_CUT];
-            o.n_shell = (int64_t)w[1 + WC_CASE_SHELL];
+            o.n_rechecked = rechecked[q];
+            o.tests_atom = (int64_t)w[2 + WC_ATOM];
+            o.tests_vertex = (int64_t)w[2 + WC_VERTEX];
+            o.tests_face = (int64_t)w[2 + WC_FACE];
+            o.tests_face_cut = (int64_t)w[2 + WC_FACE_CUT];
+            o.tests_circle = (int64_t)w[2 + WC_CIRCLE];
+            o.tests_circle_cut = (int64_t)w[2 + WC_CIRCLE_CUT];
+            o.n_shell = (int64_t)w[2 + WC_CASE_SHELL];
         }
     }
     return ESES_OK;

@@ -10,25 +10,400 @@ namespace eses {
 
 constexpr int CLS_BLOCK = 512;
 
-__global__ void __launch_bounds__(CLS_BLOCK) k_classify_fp64(Mol m, uint8_t *labels) {
+// One workgroup per tile.
+//  Phase 1 stages the tile's atom list in LDS (chunks of CLS_ATOMS) and
+//  decides cases 1 and 2 for every point; the undecided points (inside an SAS
+//  ball, in no van der Waals ball) are compacted into an LDS queue.
+//  Staging copies the tile's probe, face and circle lists into LDS together
+//  with the cuts that can matter inside the tile: a cut (v, tau) of a face
+//  can only reject a direction u from c_i with u . v > tau, so a cut whose
+//  half-space holds the whole cone of directions from c_i towards the tile is
+//  dropped (likewise for circle cuts, with in-plane directions from o).
+//  Phase 2 runs the candidate tests over the queue with every lane busy.
+// Lists or cut pools larger than the LDS capacities fall back to global
+// memory (uncut), so results never depend on the capacities.
+constexpr int CLS_THREADS = 256;
+constexpr int CLS_WAVES = CLS_THREADS / WAVE;
+constexpr int CLS_ATOMS = 256;
+constexpr int CLS_MAXPTS = 512;  // points per tile (8^3)
+constexpr int CAP_V = 64, CAP_F = 64, CAP_C = 64, CAP_CUT = 512;
+
+struct ClsPhase1 {
+    double4 a[CLS_ATOMS];  // FP64: x, y, z, r^2
+    double s2[CLS_ATOMS];  // FP64: (r + rho)^2
+};
+
+struct ClsPhase1f {
+    float4 a[CLS_ATOMS];   // FP32: atom offset from the tile origin
+    float4 t[CLS_ATOMS];   // FP32 thresholds: vdW (lo, hi), SAS (lo, hi)
+};
+
+struct ClsPhase2 {
+    double4 v[CAP_V];      // probe positions
+    double4 f[CAP_F];      // face atom x, y, z, (r + 2 rho)^2
+    int2 fr[CAP_F];        // cut range in `cut` (start, count), or (-1, face id): global cuts
+    double4 co[CAP_C];     // circle o, R
+    double4 cn[CAP_C];     // circle n, R^2 - rho^2
+    int2 cr[CAP_C];        // cut range, or (-1, exposed-circle id)
+    double4 cut[CAP_CUT];
+};
+
+struct ClsShared {
+    union {
+        ClsPhase1 p1;
+        ClsPhase1f p1f;
+        ClsPhase2 p2;
+    };
+    int queue[CLS_MAXPTS];   // points for the candidate tests (case 3)
+    int rqueue[CLS_MAXPTS];  // FP32 points whose phase-1 decision was not certified
+    int qn, rqn, pool;
+};
+
+// Certified FP32 phase-1 thresholds.  With offsets X, C of the point and the
+// atom from the tile origin (|components| <= lam), the FP32 difference
+// delta differs from the exact x - c by at most E = 4.01 u lam per component
+// (two conversions and one subtraction, u = 2^-24), so the exact squared
+// distance is within c0 = 3 E (4 lam + E) of sum(delta^2), and the FP32 sum of
+// squares S is within gamma_3 <= 4u (relative) of sum(delta^2), with or
+// without fused multiply-adds.  Hence, for an exact threshold t,
+//   S < lo = (t (1 - 2^-52) - c0) (1 - 4u)  =>  |x - c|^2 < t   (certain),
+//   S > hi = (t (1 + 2^-52) + c0) (1 + 4u)  =>  |x - c|^2 > t   (certain),
+// with lo rounded down and hi rounded up to FP32.
+constexpr double U32 = 5.9604644775390625e-08;  // 2^-24
+
+__device__ inline float thr_lo(double t, double c0) {
+    return __double2float_rd((t * (1.0 - 2.220446049250313e-16) - c0) * (1.0 - 4.0 * U32));
+}
+
+__device__ inline float thr_hi(double t, double c0) {
+    return __double2float_ru((t * (1.0 + 2.220446049250313e-16) + c0) * (1.0 + 4.0 * U32));
+}
+
+// Directional cone of the tile from an apex: axis `a` (unit), sin and cos of
+// the half-angle; `all` when the apex is inside the tile's ball.
+struct Cone {
+    double ax, ay, az, st, ct;
+    bool all;
+};
+
+__device__ inline Cone make_cone(double vx, double vy, double vz, double rb) {
+    Cone c;
+    double L = sqrt(vx * vx + vy * vy + vz * vz);
+    c.all = !(L > rb * (1.0 + 1e-12) + 1e-12);
+    if (c.all) {
+        c.ax = c.ay = c.az = c.st = 0.0;
+        c.ct = 1.0;
+        return c;
+    }
+    c.ax = vx / L;
+    c.ay = vy / L;
+    c.az = vz / L;
+    c.st = rb / L;
+    c.ct = sqrt(fmax(0.0, 1.0 - c.st * c.st));
+    return c;
+}
+
+// True if some direction u of the cone has u . v > tau (the cut can matter).
+__device__ inline bool cut_matters(const Cone &c, double4 cut) {
+    if (c.all) return true;
+    double vn = sqrt(cut.x * cut.x + cut.y * cut.y + cut.z * cut.z);
+    if (!(vn > 0.0)) return 0.0 > cut.w - 1e-9;
+    double cp = (c.ax * cut.x + c.ay * cut.y + c.az * cut.z) / vn;
+    double best;
+    if (cp >= c.ct) {
+        best = vn;
+    } else {
+        double sp = sqrt(fmax(0.0, 1.0 - cp * cp));
+        best = vn * (cp * c.ct + sp * c.st);
+    }
+    return best > cut.w - 1e-9;
+}
+
+// Copy the cuts [b, e) of global `src` that matter for cone `cone` into the
+// LDS pool (one wavefront); returns the LDS range, or (-1, fallback) when
+// the pool is full.
+__device__ inline int2 stage_cuts(ClsShared &sh, const double4 *src, int b, int e,
+                                  const Cone &cone, int fallback) {
+    const int lane = lane_id();
+    int cnt = 0;
+    for (int base = b; base < e; base += WAVE) {
+        int q = base + lane;
+        bool keep = q < e && cut_matters(cone, src[q]);
+        cnt += __popcll(__ballot(keep));
+    }
+    int start = 0;
+    if (lane == 0) start = atomicAdd(&sh.pool, cnt);
+    start = __shfl(start, 0, WAVE);
+    if (start + cnt > CAP_CUT) return make_int2(-1, fallback);
+    int w = start;
+    for (int base = b; base < e; base += WAVE) {
+        int q = base + lane;
+        double4 c = q < e ? src[q] : make_double4(0, 0, 0, 0);
+        bool keep = q < e && cut_matters(cone, c);
+        unsigned long long bm = __ballot(keep);
+        if (keep) sh.p2.cut[w + mask_prefix(bm)] = c;
+        w += __popcll(bm);
+    }
+    return make_int2(start, cnt);
+}
+
+__device__ inline bool cuts_pass(const double4 *cuts, int b, int e, double dx, double dy,
+                                 double dz, double d) {
+    for (int c = b; c < e; ++c) {
+        double4 v = cuts[c];
+        if (dx * v.x + dy * v.y + dz * v.z > d * v.w) return false;
+    }
+    return true;
+}
+
+// Case 3 of one queued point against the staged lists (global beyond them).
+__device__ inline int shell_label_staged(const Mol &m, const ClsShared &sh, int tile, int nV,
+                                         int nF, int nC, double x, double y, double z) {
+    const double rho = m.rho;
+    const double rho2 = rho * rho;
+    for (int q = 0; q < nV; ++q) {
+        double4 p = sh.p2.v[q];
+        double dx = x - p.x, dy = y - p.y, dz = z - p.z;
+        if (dx * dx + dy * dy + dz * dz < rho2) return 0;
+    }
+    for (int q = m.tV_off[tile] + nV, e = m.tV_off[tile + 1]; q < e; ++q) {
+        double4 p = m.vert_p[m.tV[q]];
+        double dx = x - p.x, dy = y - p.y, dz = z - p.z;
+        if (dx * dx + dy * dy + dz * dz < rho2) return 0;
+    }
+    for (int q = 0; q < nF; ++q) {
+        double4 a = sh.p2.f[q];
+        double dx = x - a.x, dy = y - a.y, dz = z - a.z;
+        double d2 = dx * dx + dy * dy + dz * dz;
+        if (!(d2 < a.w)) continue;
+        double d = sqrt(d2);
+        int2 r = sh.p2.fr[q];
+        bool ok = r.x >= 0 ? cuts_pass(sh.p2.cut, r.x, r.x + r.y, dx, dy, dz, d)
+                           : cuts_pass(m.face_cut, m.face_cut_off[r.y], m.face_cut_off[r.y + 1],
+                                       dx, dy, dz, d);
+        if (ok) return 0;
+    }
+    for (int q = m.tF_off[tile] + nF, e = m.tF_off[tile + 1]; q < e; ++q) {
+        int f = m.tF[q];
+        double4 a = m.atom[m.face_atom[f]];
+        double dx = x - a.x, dy = y - a.y, dz = z - a.z;
+        double d2 = dx * dx + dy * dy + dz * dz;
+        if (!(d2 < sq(a.w + 2.0 * rho))) continue;
+        if (cuts_pass(m.face_cut, m.face_cut_off[f], m.face_cut_off[f + 1], dx, dy, dz, sqrt(d2)))
+            return 0;
+    }
+    for (int q = 0; q < nC + (m.tC_off[tile + 1] - m.tC_off[tile] - nC); ++q) {
+        double4 oR, n;
+        int2 r;
+        if (q < nC) {
+            oR = sh.p2.co[q];
+            n = sh.p2.cn[q];
+            r = sh.p2.cr[q];
+        } else {
+            int ec = m.tC[m.tC_off[tile] + q];
+            int ci = m.ec_circ[ec];
+            oR = m.circ_oR[ci];
+            n = m.circ_n[ci];
+            n.w = oR.w * oR.w - rho2;
+            r = make_int2(-1, ec);
+        }
+        double wx = x - oR.x, wy = y - oR.y, wz = z - oR.z;
+        double t = wx * n.x + wy * n.y + wz * n.z;
+        double ww = wx * wx + wy * wy + wz * wz;
+        double b = sqrt(fmax(ww - t * t, 0.0));
+        if (!(ww + n.w < 2.0 * b * oR.w)) continue;
+        double px = wx, py = wy, pz = wz, pb = b;
+        if (!(b > 0.0)) {
+            perp_unit(n.x, n.y, n.z, px, py, pz);
+            pb = 1.0;
+        }
+        bool ok = r.x >= 0 ? cuts_pass(sh.p2.cut, r.x, r.x + r.y, px, py, pz, pb)
+                           : cuts_pass(m.ec_cut, m.ec_cut_off[r.y], m.ec_cut_off[r.y + 1], px,
+                                       py, pz, pb);
+        if (ok) return 0;
+    }
+    return 1;
+}
+
+// F32: phase 1 (cases 1 and 2, every point against the tile's atoms) in FP32
+// with the certified thresholds above; points it cannot certify are
+// re-labelled in FP64 (counted in diag[1]).  Case 3 runs in FP64 either way.
+template <bool F32>
+__global__ void __launch_bounds__(CLS_THREADS) k_classify(Mol m, uint8_t *labels, int nblocks) {
+    __shared__ ClsShared sh;
+    const int tile = xcd_tile(blockIdx.x, nblocks, m.ntiles);
+    if (tile < 0) return;  // uniform across the workgroup
     const int T = m.tile;
-    const int per = T * T * T;
-    const int tiles_per_block = CLS_BLOCK / per;
-    int tile = blockIdx.x * tiles_per_block + threadIdx.x / per;
-    if (tile >= m.ntiles) return;
-    int local = threadIdx.x % per;
-    int t3[3] = {tile % m.tdims[0], (tile / m.tdims[0]) % m.tdims[1],
-                 tile / (m.tdims[0] * m.tdims[1])};
-    int i = t3[0] * T + local % T;
-    int j = t3[1] * T + (local / T) % T;
-    int k = t3[2] * T + local / (T * T);
-    if (i >= m.dims[0] || j >= m.dims[1] || k >= m.dims[2]) return;
-    double x = grid_coord(m.lo[0], m.h, i);
-    double y = grid_coord(m.lo[1], m.h, j);
-    double z = grid_coord(m.lo[2], m.h, k);
-    int lab = label_fp64(m, tile, x, y, z);
-    labels[(long long)i + (long long)m.dims[0] * ((long long)j + (long long)m.dims[1] * k)] =
-        (uint8_t)lab;
+    const int P = T * T * T;
+    const int t3[3] = {tile % m.tdims[0], (tile / m.tdims[0]) % m.tdims[1],
+                       tile / (m.tdims[0] * m.tdims[1])};
+    constexpr int PPT = CLS_MAXPTS / CLS_THREADS;  // points per thread
+    double px[PPT], py[PPT], pz[PPT];
+    float fx[PPT], fy[PPT], fz[PPT];
+    bool valid[PPT], inv[PPT], inu[PPT], vmay[PPT], umay[PPT];
+    double org[3];
+    for (int a = 0; a < 3; ++a) org[a] = grid_coord(m.lo[a], m.h, t3[a] * T);
+    for (int r = 0; r < PPT; ++r) {
+        int p = threadIdx.x + r * CLS_THREADS;
+        int i = t3[0] * T + p % T, j = t3[1] * T + (p / T) % T, k = t3[2] * T + p / (T * T);
+        valid[r] = p < P && i < m.dims[0] && j < m.dims[1] && k < m.dims[2];
+        px[r] = grid_coord(m.lo[0], m.h, i);
+        py[r] = grid_coord(m.lo[1], m.h, j);
+        pz[r] = grid_coord(m.lo[2], m.h, k);
+        fx[r] = (float)(px[r] - org[0]);
+        fy[r] = (float)(py[r] - org[1]);
+        fz[r] = (float)(pz[r] - org[2]);
+        inv[r] = false;
+        inu[r] = false;
+        vmay[r] = false;
+        umay[r] = false;
+    }
+    if (threadIdx.x == 0) {
+        sh.qn = 0;
+        sh.rqn = 0;
+        sh.pool = 0;
+    }
+    const int a0 = m.tA_off[tile], a1 = m.tA_off[tile + 1];
+    const double rho = m.rho;
+    // bound of the offsets' components: tile points and atoms within s_max of it
+    const double lam = (T - 1) * m.h + m.smax + 1e-3;
+    const double E = 4.01 * U32 * lam;
+    const double cb = 3.0 * E * (4.0 * lam + E) + 1e-30;
+    for (int base = a0; base < a1; base += CLS_ATOMS) {
+        int cnt = min(CLS_ATOMS, a1 - base);
+        __syncthreads();
+        for (int q = threadIdx.x; q < cnt; q += CLS_THREADS) {
+            double4 a = m.atom[m.tA[base + q]];
+            if (F32) {
+                sh.p1f.a[q] = make_float4((float)(a.x - org[0]), (float)(a.y - org[1]),
+                                          (float)(a.z - org[2]), 0.0f);
+                double s = a.w + rho;
+                sh.p1f.t[q] = make_float4(thr_lo(a.w * a.w, cb), thr_hi(a.w * a.w, cb),
+                                          thr_lo(s * s, cb), thr_hi(s * s, cb));
+            } else {
+                sh.p1.a[q] = make_double4(a.x, a.y, a.z, a.w * a.w);
+                sh.p1.s2[q] = sq(a.w + rho);
+            }
+        }
+        __syncthreads();
+        for (int r = 0; r < PPT; ++r) {
+            if (!valid[r] || inv[r]) continue;
+            if (F32) {
+                bool v = false, vm = vmay[r], u = inu[r], um = umay[r];
+                for (int q = 0; q < cnt; ++q) {
+                    float4 a = sh.p1f.a[q];
+                    float4 t = sh.p1f.t[q];
+                    float dx = fx[r] - a.x, dy = fy[r] - a.y, dz = fz[r] - a.z;
+                    float d2 = dx * dx + dy * dy + dz * dz;
+                    v |= d2 < t.x;
+                    vm |= d2 <= t.y;
+                    u |= d2 < t.z;
+                    um |= d2 <= t.w;
+                }
+                inv[r] = v;
+                vmay[r] = vm;
+                inu[r] = u;
+                umay[r] = um;
+            } else {
+                bool v = false, u = inu[r];
+                for (int q = 0; q < cnt; ++q) {
+                    double4 a = sh.p1.a[q];
+                    double dx = px[r] - a.x, dy = py[r] - a.y, dz = pz[r] - a.z;
+                    double d2 = dx * dx + dy * dy + dz * dz;
+                    v |= d2 <= a.w;
+                    u |= d2 < sh.p1.s2[q];
+                }
+                inv[r] = v;
+                inu[r] = u;
+            }
+        }
+    }
+    __syncthreads();
+    for (int r = 0; r < PPT; ++r) {
+        if (!valid[r]) continue;
+        int p = threadIdx.x + r * CLS_THREADS;
+        int i = t3[0] * T + p % T, j = t3[1] * T + (p / T) % T, k = t3[2] * T + p / (T * T);
+        long long gi = (long long)i + (long long)m.dims[0] * ((long long)j + (long long)m.dims[1] * k);
+        if (F32) {
+            // certain: in a vdW ball; outside every SAS ball; or shell (in an
+            // SAS ball, certainly in no vdW ball)
+            if (m.force_recheck) sh.rqueue[atomicAdd(&sh.rqn, 1)] = p;
+            else if (inv[r]) labels[gi] = 1;
+            else if (!umay[r]) labels[gi] = 0;
+            else if (inu[r] && !vmay[r]) sh.queue[atomicAdd(&sh.qn, 1)] = p;
+            else sh.rqueue[atomicAdd(&sh.rqn, 1)] = p;
+        } else {
+            if (inv[r] || !inu[r]) labels[gi] = inv[r] ? 1 : 0;
+            else sh.queue[atomicAdd(&sh.qn, 1)] = p;
+        }
+    }
+    __syncthreads();
+    if (F32) {
+        const int nr = sh.rqn;
+        for (int q = threadIdx.x; q < nr; q += CLS_THREADS) {
+            int p = sh.rqueue[q];
+            int i = t3[0] * T + p % T, j = t3[1] * T + (p / T) % T, k = t3[2] * T + p / (T * T);
+            labels[(long long)i + (long long)m.dims[0] * ((long long)j + (long long)m.dims[1] * k)] =
+                (uint8_t)label_fp64(m, tile, grid_coord(m.lo[0], m.h, i),
+                                    grid_coord(m.lo[1], m.h, j), grid_coord(m.lo[2], m.h, k));
+        }
+        if (threadIdx.x == 0 && nr > 0) atomicAdd(&m.diag[1], nr);
+    }
+    const int nq = sh.qn;
+    if (nq == 0) return;  // uniform: no point needs the candidate tests
+
+    // staging of the candidate lists (phase-1 LDS is dead from here on)
+    const int v0 = m.tV_off[tile], f0 = m.tF_off[tile], c0 = m.tC_off[tile];
+    const int nV = min(CAP_V, m.tV_off[tile + 1] - v0);
+    const int nF = min(CAP_F, m.tF_off[tile + 1] - f0);
+    const int nC = min(CAP_C, m.tC_off[tile + 1] - c0);
+    for (int q = threadIdx.x; q < nV; q += CLS_THREADS) sh.p2.v[q] = m.vert_p[m.tV[v0 + q]];
+    for (int q = threadIdx.x; q < nF; q += CLS_THREADS) {
+        double4 a = m.atom[m.face_atom[m.tF[f0 + q]]];
+        sh.p2.f[q] = make_double4(a.x, a.y, a.z, sq(a.w + 2.0 * rho));
+    }
+    for (int q = threadIdx.x; q < nC; q += CLS_THREADS) {
+        int ci = m.ec_circ[m.tC[c0 + q]];
+        double4 oR = m.circ_oR[ci];
+        double4 n = m.circ_n[ci];
+        sh.p2.co[q] = oR;
+        sh.p2.cn[q] = make_double4(n.x, n.y, n.z, oR.w * oR.w - rho * rho);
+    }
+    // the tile's own points span T - 1 spacings per axis
+    double bc[3], rb;
+    {
+        double half = 0.5 * (T - 1) * m.h;
+        for (int a = 0; a < 3; ++a) bc[a] = m.lo[a] + (double)(t3[a] * T) * m.h + half;
+        rb = sqrt(3.0) * half * (1.0 + 1e-12) + 1e-12;
+    }
+    const int wv = threadIdx.x / WAVE;
+    for (int q = wv; q < nF; q += CLS_WAVES) {
+        int f = m.tF[f0 + q];
+        double4 a = m.atom[m.face_atom[f]];
+        Cone cone = make_cone(bc[0] - a.x, bc[1] - a.y, bc[2] - a.z, rb);
+        int2 r = stage_cuts(sh, m.face_cut, m.face_cut_off[f], m.face_cut_off[f + 1], cone, f);
+        if (lane_id() == 0) sh.p2.fr[q] = r;
+    }
+    for (int q = wv; q < nC; q += CLS_WAVES) {
+        int ec = m.tC[c0 + q];
+        int ci = m.ec_circ[ec];
+        double4 oR = m.circ_oR[ci];
+        double4 n = m.circ_n[ci];
+        double wx = bc[0] - oR.x, wy = bc[1] - oR.y, wz = bc[2] - oR.z;
+        double t = wx * n.x + wy * n.y + wz * n.z;
+        Cone cone = make_cone(wx - t * n.x, wy - t * n.y, wz - t * n.z, rb);
+        int2 r = stage_cuts(sh, m.ec_cut, m.ec_cut_off[ec], m.ec_cut_off[ec + 1], cone, ec);
+        if (lane_id() == 0) sh.p2.cr[q] = r;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < nq; q += CLS_THREADS) {
+        int p = sh.queue[q];
+        int i = t3[0] * T + p % T, j = t3[1] * T + (p / T) % T, k = t3[2] * T + p / (T * T);
+        int lab = shell_label_staged(m, sh, tile, nV, nF, nC, grid_coord(m.lo[0], m.h, i),
+                                     grid_coord(m.lo[1], m.h, j), grid_coord(m.lo[2], m.h, k));
+        labels[(long long)i + (long long)m.dims[0] * ((long long)j + (long long)m.dims[1] * k)] =
+            (uint8_t)lab;
+    }
 }
 
 // Statistics pass: the same decision with its tests tallied (not timed).
@@ -82,11 +457,12 @@ hipError_t launch_count_inside(const uint8_t *labels, long long n, unsigned long
     return hipGetLastError();
 }
 
-hipError_t launch_classify_fp64(const Mol &m, uint8_t *labels, hipStream_t st) {
-    const int per = m.tile * m.tile * m.tile;
-    const int tpb = CLS_BLOCK / per;
-    unsigned nb = (unsigned)((m.ntiles + tpb - 1) / tpb);
-    hipLaunchKernelGGL(k_classify_fp64, dim3(nb < 1 ? 1 : nb), dim3(CLS_BLOCK), 0, st, m, labels);
+hipError_t launch_classify(const Mol &m, bool fp32, uint8_t *labels, hipStream_t st) {
+    int nb = (m.ntiles + NXCD - 1) / NXCD * NXCD;
+    if (fp32)
+        hipLaunchKernelGGL(k_classify<true>, dim3(nb), dim3(CLS_THREADS), 0, st, m, labels, nb);
+    else
+        hipLaunchKernelGGL(k_classify<false>, dim3(nb), dim3(CLS_THREADS), 0, st, m, labels, nb);
     return hipGetLastError();
 }
 

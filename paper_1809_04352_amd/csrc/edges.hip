@@ -319,8 +319,12 @@ __device__ void collect_roots(const Mol &m, int tile, int axis, const double *xs
 
 __global__ void __launch_bounds__(256) k_edge_roots(Mol m, const uint8_t *L, const long long *keys,
                                                     long long count, double *lam, double *nrm,
-                                                    uint8_t *ptype, int *patoms, int *overflow) {
-    long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+                                                    uint8_t *ptype, int *patoms, int *overflow,
+                                                    int nblocks) {
+    // consecutive edges (same rows, same tiles) stay on one XCD
+    int blk = xcd_tile(blockIdx.x, nblocks, (int)((count + 255) / 256));
+    if (blk < 0) return;
+    long long q = (long long)blk * 256 + threadIdx.x;
     if (q >= count) return;
     long long key = keys[q];
     int axis = (int)(key % 3);
@@ -469,9 +473,10 @@ hipError_t launch_edge_roots(const Mol &m, const uint8_t *L, const long long *ke
                              long long count, double *lam, double *nrm, uint8_t *ptype,
                              int *patoms, int *overflow, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    unsigned nb = (unsigned)((count + 255) / 256);
+    int nb = (int)((count + 255) / 256);
+    nb = (nb + NXCD - 1) / NXCD * NXCD;
     hipLaunchKernelGGL(k_edge_roots, dim3(nb), dim3(256), 0, st, m, L, keys, count, lam, nrm,
-                       ptype, patoms, overflow);
+                       ptype, patoms, overflow, nb);
     return hipGetLastError();
 }
 

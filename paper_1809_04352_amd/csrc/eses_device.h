@@ -202,6 +202,75 @@ __device__ inline int label_fp64(const Mol &m, int tile, double x, double y, dou
     return label_fp64_t<false>(m, tile, x, y, z, nullptr);
 }
 
+// Case 3 only (x inside some SAS ball and in no van der Waals ball): outside
+// iff an admissible candidate lies closer than rho.
+__device__ inline int shell_label_fp64(const Mol &m, int tile, double x, double y, double z) {
+    const double rho = m.rho;
+    const double rho2 = rho * rho;
+    for (int q = m.tV_off[tile], e = m.tV_off[tile + 1]; q < e; ++q) {
+        double4 p = m.vert_p[m.tV[q]];
+        double dx = x - p.x, dy = y - p.y, dz = z - p.z;
+        if (dx * dx + dy * dy + dz * dz < rho2) return 0;
+    }
+    for (int q = m.tF_off[tile], e = m.tF_off[tile + 1]; q < e; ++q) {
+        int f = m.tF[q];
+        double4 a = m.atom[m.face_atom[f]];
+        double dx = x - a.x, dy = y - a.y, dz = z - a.z;
+        double d2 = dx * dx + dy * dy + dz * dz;
+        double sr = a.w + 2.0 * rho;
+        if (!(d2 < sr * sr)) continue;
+        double d = sqrt(d2);
+        bool ok = true;
+        for (int c = m.face_cut_off[f], ce = m.face_cut_off[f + 1]; c < ce; ++c) {
+            double4 v = m.face_cut[c];
+            if (dx * v.x + dy * v.y + dz * v.z > d * v.w) {
+                ok = false;
+                break;
+            }
+        }
+        if (ok) return 0;
+    }
+    for (int q = m.tC_off[tile], e = m.tC_off[tile + 1]; q < e; ++q) {
+        int ec = m.tC[q];
+        int ci = m.ec_circ[ec];
+        double4 oR = m.circ_oR[ci];
+        double4 n = m.circ_n[ci];
+        double wx = x - oR.x, wy = y - oR.y, wz = z - oR.z;
+        double t = wx * n.x + wy * n.y + wz * n.z;
+        double ww = wx * wx + wy * wy + wz * wz;
+        double b = sqrt(fmax(ww - t * t, 0.0));
+        double R = oR.w;
+        if (!(ww + R * R - rho2 < 2.0 * b * R)) continue;
+        double px = wx, py = wy, pz = wz, pb = b;
+        if (!(b > 0.0)) {
+            perp_unit(n.x, n.y, n.z, px, py, pz);
+            pb = 1.0;
+        }
+        bool ok = true;
+        for (int c = m.ec_cut_off[ec], ce = m.ec_cut_off[ec + 1]; c < ce; ++c) {
+            double4 u = m.ec_cut[c];
+            if (px * u.x + py * u.y + pz * u.z > pb * u.w) {
+                ok = false;
+                break;
+            }
+        }
+        if (ok) return 0;
+    }
+    return 1;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Map block b to tile (b % 8) * per + b / 8 so each XCD walks a
+// contiguous run of tiles and neighbouring tiles share its L2.  `nblocks`
+// is a multiple of 8; blocks past `ntiles` return -1.
+constexpr int NXCD = 8;
+
+__device__ inline int xcd_tile(int b, int nblocks, int ntiles) {
+    int per = nblocks / NXCD;
+    int t = (b % NXCD) * per + b / NXCD;
+    return t < ntiles ? t : -1;
+}
+
 __device__ inline void fill_i32(int *p, long long n, int v) {
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
          q += (long long)gridDim.x * blockDim.x)

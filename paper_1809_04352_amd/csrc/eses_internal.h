@@ -45,6 +45,7 @@ struct Mol {
     int ncell;
     // tiles
     int tile;
+    int force_recheck;   // FP32 path: every phase-1 decision treated as uncertain
     int tdims[3];
     int ntiles;
 

@@ -32,7 +32,7 @@ hipError_t launch_tiles(const Mol &m, bool fill, int *cA, int *cF, int *cC, int 
                         hipStream_t st);
 
 // stage 2
-hipError_t launch_classify_fp64(const Mol &m, uint8_t *labels, hipStream_t st);
+hipError_t launch_classify(const Mol &m, bool fp32, uint8_t *labels, hipStream_t st);
 hipError_t launch_classify_work(const Mol &m, unsigned long long *work, hipStream_t st);
 hipError_t launch_count_inside(const uint8_t *labels, long long n, unsigned long long *out,
                                hipStream_t st);

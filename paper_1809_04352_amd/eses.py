@@ -46,7 +46,8 @@ class Molecule(ctypes.Structure):
 
 
 class Config(ctypes.Structure):
-    _fields_ = [("tile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("tile", ctypes.c_int32), ("force_recheck", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class CandidateStats(ctypes.Structure):
@@ -165,12 +166,13 @@ def _stream_ptr(stream):
 class Candidates:
     """Owning wrapper of an eses_candidates handle."""
 
-    def __init__(self, mols, tile: int = 0, stream=None):
+    def __init__(self, mols, tile: int = 0, stream=None, force_recheck: bool = False):
         lib = load()
         self.mols = list(mols)
         arr = (Molecule * len(self.mols))(*self.mols)
         cfg = Config()
         cfg.tile = int(tile)
+        cfg.force_recheck = 1 if force_recheck else 0
         h = ctypes.c_void_p()
         self.stream = _stream_ptr(stream)
         _check(lib.eses_build_candidates(arr, len(self.mols), ctypes.byref(cfg), self.stream,
@@ -194,8 +196,8 @@ class Candidates:
         return st.as_dict()
 
 
-def build_candidates(mols, tile: int = 0, stream=None) -> Candidates:
-    return Candidates(mols, tile, stream)
+def build_candidates(mols, tile: int = 0, stream=None, force_recheck: bool = False) -> Candidates:
+    return Candidates(mols, tile, stream, force_recheck)
 
 
 def copy_vertices(cand: Candidates, mol: int, p_dev, atoms_dev, sign_dev, stream=None) -> int:
@@ -263,14 +265,15 @@ def edge_intersections(cand: Candidates, labels_dev, outs, stream=None):
 
 
 def surface(centres, radii, probe: float, spacing: float, lo, hi, prec: int = ESES_FP64,
-            tile: int = 0, isect_capacity: int | None = None, device="cuda"):
+            tile: int = 0, isect_capacity: int | None = None, device="cuda",
+            force_recheck: bool = False, stats: bool = False):
     """Whole hot path for one molecule given host arrays; returns host numpy results."""
     import torch
     c = torch.as_tensor(np.ascontiguousarray(centres, dtype=np.float64), device=device)
     r = torch.as_tensor(np.ascontiguousarray(radii, dtype=np.float64), device=device)
     mol = make_molecule(c, r, probe, spacing, lo, hi)
     dims = grid_dims(mol)
-    cand = build_candidates([mol], tile)
+    cand = build_candidates([mol], tile, force_recheck=force_recheck)
     try:
         info = cand.info(0)
         nv = info["n_vertices"]
@@ -279,7 +282,7 @@ def surface(centres, radii, probe: float, spacing: float, lo, hi, prec: int = ES
         vs = torch.empty(max(nv, 1), dtype=torch.int8, device=device)
         copy_vertices(cand, 0, vp, va, vs)
         labels = torch.empty(dims[0] * dims[1] * dims[2], dtype=torch.uint8, device=device)
-        classify(cand, prec, [labels])
+        cstats = classify(cand, prec, [labels], stats=stats)
         cap = isect_capacity if isect_capacity is not None else max(1024, labels.numel() // 8)
         out = alloc_isect(cap, device)
         status, counts = edge_intersections(cand, [labels], [out])
@@ -298,6 +301,7 @@ def surface(centres, radii, probe: float, spacing: float, lo, hi, prec: int = ES
             normal=out.normal[:k].cpu().numpy(),
             patch_type=out.patch_type[:k].cpu().numpy(),
             atoms=out.atoms[:k].cpu().numpy(),
+            classify_stats=cstats[0] if cstats else None,
         )
     finally:
         cand.close()

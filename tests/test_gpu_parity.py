@@ -40,7 +40,7 @@ def run_and_compare(E, oracle_mod, c, r, probe, h, lo, hi, prec, tile=0):
     return res, nv, ne
 
 
-@pytest.mark.parametrize("prec", [0])
+@pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("n,seed,h,tile", [
     (1, 1, 0.25, 8), (2, 2, 0.3, 8), (40, 3, 0.35, 8), (120, 4, 0.5, 4), (120, 4, 0.5, 8),
     (300, 5, 0.45, 8),
@@ -51,7 +51,7 @@ def test_small_molecules(E, oracle_mod, prec, n, seed, h, tile):
     run_and_compare(E, oracle_mod, m.centres, m.radii, m.probe, h, m.lo, m.hi, prec, tile)
 
 
-@pytest.mark.parametrize("prec", [0])
+@pytest.mark.parametrize("prec", [0, 1])
 def test_globule500(E, oracle_mod, prec):
     from eses_inputs import workload
     m = workload("globule500_h0.5")
@@ -142,3 +142,24 @@ def test_tile_shape_invariance(E):
     b = E.surface(m.centres, m.radii, m.probe, m.spacing, m.lo, m.hi, tile=4)
     for k in ("labels", "key", "lam", "normal", "patch_type", "atoms"):
         assert np.array_equal(a[k], b[k]), k
+
+
+def test_fp32_recheck_matches_fp64_and_counts(E):
+    """FP32 certified decisions plus FP64 recheck give the FP64 labels; forcing
+    every point through the recheck path gives them too."""
+    from eses_inputs import molecule
+    m = molecule(400, 21, 0.3)
+    a = E.surface(m.centres, m.radii, m.probe, m.spacing, m.lo, m.hi, prec=E.ESES_FP64,
+                  stats=True)
+    b = E.surface(m.centres, m.radii, m.probe, m.spacing, m.lo, m.hi,
+                  prec=E.ESES_FP32_RECHECK, stats=True)
+    c = E.surface(m.centres, m.radii, m.probe, m.spacing, m.lo, m.hi,
+                  prec=E.ESES_FP32_RECHECK, force_recheck=True, stats=True)
+    for r in (b, c):
+        for k in ("labels", "key", "lam", "normal", "patch_type", "atoms"):
+            assert np.array_equal(a[k], r[k]), k
+    assert a["classify_stats"]["n_rechecked"] == 0
+    n = a["labels"].size
+    assert c["classify_stats"]["n_rechecked"] == n
+    assert b["classify_stats"]["n_rechecked"] < 1e-3 * n
+    print("rechecked", b["classify_stats"]["n_rechecked"], "of", n)
