@@ -14,6 +14,8 @@ from .globule import (
     molecule,
     Molecule,
     batch_sizes,
+    batch,
+    build,
     WORKLOADS,
     PROBE_RADIUS,
     MARGIN,
@@ -31,5 +33,7 @@ __all__ = [
     "PROBE_RADIUS",
     "MARGIN",
     "batch_sizes",
+    "batch",
+    "build",
     "WORKLOADS",
 ]

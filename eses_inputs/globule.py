@@ -7,10 +7,9 @@ bonded random walk at 1.5 A steps, no two non-bonded centres closer than
 2.4 A, packed towards 0.1 atoms per cubic angstrom, with radii drawn from the
 C/N/O/S/H table below.
 
-Recipe (each step consumes the generator in this order, so a seed fixes the
-molecule bit for bit):
+Recipe (globule.c; a seed fixes the molecule bit for bit):
   * confinement ball of radius R = (3N / (4 pi 0.1))^(1/3) around the origin;
-  * the walk starts at the origin; each step tries up to 64 directions drawn
+  * the walk starts at the origin; each step draws up to 64 directions
     uniformly on the sphere, taking the first that stays in the ball and keeps
     2.4 A from every placed atom other than its bonded predecessor;
   * if all 64 fail, the walk restarts from a uniformly drawn placed atom (a
@@ -24,7 +23,10 @@ grid point (i, j, k) at lo + (i, j, k) * h.
 """
 from __future__ import annotations
 
+import ctypes
 import math
+import os
+import subprocess
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -37,79 +39,56 @@ PROBE_RADIUS = 1.4
 MARGIN = 4.0
 
 
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "globule.c")
+_LIB = os.path.join(_HERE, "libglobule.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the generator (plain C, gcc)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"],
+                       check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.globule_generate.restype = ctypes.c_int
+        lib.globule_generate.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_double, dp, dp, ctypes.c_int,
+                                         dp, dp]
+        lib.globule_log_uniform.restype = None
+        lib.globule_log_uniform.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_double,
+                                            ctypes.c_double, ctypes.POINTER(ctypes.c_int)]
+        _lib = lib
+    return _lib
+
+
 def globule(n: int, seed: int, density: float = 0.1, step: float = 1.5,
             min_sep: float = 2.4, tries: int = 64, restarts_before_grow: int = 200,
             grow: float = 1.02):
     """Return (centres [n,3] float64, radii [n] float64) of a seeded globule."""
     if n < 1:
         raise ValueError("n must be >= 1")
-    rng = np.random.default_rng(seed)
-    radius = (3.0 * n / (4.0 * math.pi * density)) ** (1.0 / 3.0)
+    lib = _load()
     pos = np.zeros((n, 3), dtype=np.float64)
-    # Occupancy grid of 2.4 A cells (fixed slots per cell, -1 = empty).  A cell
-    # of side min_sep holds few atoms, since non-bonded centres keep min_sep apart.
-    cell = min_sep
-    reach = int(math.ceil((step + min_sep) / cell))
-    slots = 16
-    state = {}
-
-    def cell_of(p):
-        half = state["half"]
-        return (int(math.floor(p[0] / cell)) + half, int(math.floor(p[1] / cell)) + half,
-                int(math.floor(p[2] / cell)) + half)
-
-    def insert(idx):
-        cx, cy, cz = cell_of(pos[idx])
-        f = state["fill"][cx, cy, cz]
-        if f >= slots:
-            raise RuntimeError("globule: cell slot overflow")
-        state["grid"][cx, cy, cz, f] = idx
-        state["fill"][cx, cy, cz] = f + 1
-
-    def rebuild(count, rad):
-        half = int(math.ceil(1.25 * rad / cell)) + reach + 2
-        side = 2 * half
-        state["half"] = half
-        state["grid"] = np.full((side, side, side, slots), -1, dtype=np.int32)
-        state["fill"] = np.zeros((side, side, side), dtype=np.int32)
-        for q in range(count):
-            insert(q)
-
-    rebuild(0, radius)
-    insert(0)
-    min_sep2 = min_sep * min_sep
-    cur = 0
-    failed_restarts = 0
-    for m in range(1, n):
-        while True:
-            d = rng.normal(size=(tries, 3))
-            d /= np.linalg.norm(d, axis=1, keepdims=True)
-            cand = pos[cur] + step * d
-            ok = np.einsum("ij,ij->i", cand, cand) <= radius * radius
-            cx, cy, cz = cell_of(pos[cur])
-            near = state["grid"][cx - reach:cx + reach + 1, cy - reach:cy + reach + 1,
-                                 cz - reach:cz + reach + 1].reshape(-1)
-            near = near[(near >= 0) & (near != cur)]
-            if near.size:
-                diff = cand[:, None, :] - pos[near][None, :, :]
-                dist2 = np.einsum("ijk,ijk->ij", diff, diff)
-                ok &= np.all(dist2 >= min_sep2, axis=1)
-            hit = np.flatnonzero(ok)
-            if hit.size:
-                pos[m] = cand[hit[0]]
-                insert(m)
-                cur = m
-                failed_restarts = 0
-                break
-            cur = int(rng.integers(m))
-            failed_restarts += 1
-            if failed_restarts >= restarts_before_grow:
-                radius *= grow
-                failed_restarts = 0
-                if radius / cell + reach + 2 > state["half"]:
-                    rebuild(m, radius)
-    kinds = rng.choice(len(RADII_TABLE), size=n, p=RADII_PROB)
-    radii = RADII_TABLE[kinds].copy()
+    radii = np.zeros(n, dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = lib.globule_generate(int(n), int(seed), float(density), float(step), float(min_sep),
+                              int(tries), int(restarts_before_grow), float(grow),
+                              RADII_TABLE.ctypes.data_as(dp), RADII_PROB.ctypes.data_as(dp),
+                              len(RADII_TABLE), pos.ctypes.data_as(dp), radii.ctypes.data_as(dp))
+    if rc != 0:
+        raise RuntimeError("globule generation failed")
     return pos, radii
 
 
@@ -172,6 +151,11 @@ def workload(name: str) -> Molecule:
 
 def batch_sizes(count: int = 256, lo: int = 200, hi: int = 20000, seed: int = 5):
     """Log-uniform molecule sizes for the batched workload; molecule m uses seed 1000 + m."""
-    rng = np.random.default_rng(seed)
-    u = rng.uniform(math.log(lo), math.log(hi), size=count)
-    return [int(round(math.exp(v))) for v in u]
+    out = (ctypes.c_int * count)()
+    _load().globule_log_uniform(int(count), int(seed), float(lo), float(hi), out)
+    return [int(v) for v in out]
+
+
+def batch(count: int = 256, spacing: float = 0.5, seed: int = 5):
+    """The batched workload: `count` globules of log-uniform sizes in [200, 20000]."""
+    return [molecule(n, 1000 + q, spacing) for q, n in enumerate(batch_sizes(count, seed=seed))]

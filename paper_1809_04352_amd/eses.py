@@ -283,10 +283,11 @@ def surface(centres, radii, probe: float, spacing: float, lo, hi, prec: int = ES
         copy_vertices(cand, 0, vp, va, vs)
         labels = torch.empty(dims[0] * dims[1] * dims[2], dtype=torch.uint8, device=device)
         cstats = classify(cand, prec, [labels], stats=stats)
-        cap = isect_capacity if isect_capacity is not None else max(1024, labels.numel() // 8)
+        cap = isect_capacity if isect_capacity is not None else 1
         out = alloc_isect(cap, device)
         status, counts = edge_intersections(cand, [labels], [out])
         if status == ESES_ECAPACITY:
+            del out
             out = alloc_isect(counts[0], device)
             status, counts = edge_intersections(cand, [labels], [out])
         torch.cuda.synchronize()
