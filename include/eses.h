@@ -95,7 +95,10 @@ typedef struct {
     int32_t force_recheck; /* test aid: with ESES_FP32_RECHECK, treat every FP32
                               decision as uncertain so each point is re-tested
                               in FP64 (0 = off) */
-    int32_t reserved[6];   /* must be zero */
+    int32_t blocks_per_cu; /* batches (n_mols > 1): persistent workgroups per
+                              compute unit of the fused classification launch
+                              (0 = as many as fit) */
+    int32_t reserved[5];   /* must be zero */
 } eses_config;
 
 typedef struct eses_candidates eses_candidates; /* opaque, library-owned */
@@ -172,7 +175,10 @@ eses_status eses_copy_vertices(const eses_candidates *c, int32_t mol, double *p,
 
 /* Stage 2 (eq. 2): labels every grid point of every molecule.
  * labels: host array of n_mols DEVICE pointers, each [nx*ny*nz] uint8.
- * stats: host array of n_mols entries or NULL (non-NULL synchronises). */
+ * stats: host array of n_mols entries or NULL (non-NULL synchronises).
+ * A handle of several molecules runs one persistent fused launch over all
+ * their tiles (heaviest tiles first, from an atomic work queue), recorded
+ * once per precision as a HIP graph and replayed on later calls. */
 eses_status eses_classify(eses_candidates *c, eses_precision prec, uint8_t *const *labels,
                           eses_classify_stats *stats, void *stream);
 

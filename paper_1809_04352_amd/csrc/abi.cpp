@@ -2,6 +2,7 @@
 // the count read-backs that size the lists (see include/eses.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -87,6 +88,20 @@ struct MolState {
 struct eses_candidates {
     std::vector<MolState *> mols;
     hipStream_t stream = nullptr;
+    // batch structures (n_mols > 1)
+    Arena batch;
+    Mol *mols_dev = nullptr;
+    int *tile_base_dev = nullptr;
+    int2 *units = nullptr;
+    int *cls = nullptr;        // [0..2] class counts, [3..5] class fill
+    int *head = nullptr;
+    uint8_t **labels_dev = nullptr;
+    long long nunits = 0;
+    int batch_blocks = 0;
+    int blocks_per_cu = 0;
+    // recorded fused classification, per precision
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -345,6 +360,74 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, MolS
     return ESES_OK;
 }
 
+// Device copies of the molecules' views and the heaviest-first list of
+// (molecule, tile) units for the fused classification launch.
+eses_status build_batch(eses_candidates *c, hipStream_t st) {
+    Arena &B = c->batch;
+    B.st = st;
+    const int nm = (int)c->mols.size();
+    std::vector<Mol> hm(nm);
+    std::vector<int> base(nm + 1, 0);
+    for (int q = 0; q < nm; ++q) {
+        hm[q] = c->mols[q]->m;
+        base[q + 1] = base[q] + hm[q].ntiles;
+    }
+    if ((long long)base[nm] > (1LL << 30)) {
+        set_err("batch too large: %d tiles", base[nm]);
+        return ESES_EINVAL;
+    }
+    c->nunits = base[nm];
+    CKS(B.alloc(&c->mols_dev, nm));
+    CKS(B.alloc(&c->tile_base_dev, nm + 1));
+    CKS(B.alloc(&c->units, c->nunits));
+    CKS(B.alloc(&c->cls, 8));
+    CKS(B.alloc(&c->head, 1));
+    CKS(B.alloc(&c->labels_dev, nm));
+    CK(hipMemcpyAsync(c->mols_dev, hm.data(), sizeof(Mol) * nm, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(c->tile_base_dev, base.data(), sizeof(int) * (nm + 1),
+                      hipMemcpyHostToDevice, st));
+    CK(launch_units(c->mols_dev, c->tile_base_dev, nm, c->nunits, c->cls, c->cls + 3, c->units,
+                    st));
+    CK(hipStreamSynchronize(st));  // host arrays above are released on return
+    int dev = 0, ncu = 0;
+    CK(hipGetDevice(&dev));
+    CK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    int per = c->blocks_per_cu > 0 ? c->blocks_per_cu : classify_batch_blocks_per_cu(true);
+    c->batch_blocks = std::max(1, ncu * per);
+    return ESES_OK;
+}
+
+// The fused classification of a batch, recorded once per precision on a
+// private stream and replayed on the caller's.
+eses_status classify_batch(eses_candidates *c, bool fp32, uint8_t *const *labels,
+                           hipStream_t st) {
+    const int nm = (int)c->mols.size();
+    CK(hipMemcpyAsync(c->labels_dev, labels, sizeof(uint8_t *) * nm, hipMemcpyHostToDevice, st));
+    const int k = fp32 ? 1 : 0;
+    if (!c->exec[k]) {
+        hipStream_t cap;
+        CK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess)
+            e = launch_classify_batch(c->mols_dev, c->labels_dev, c->units, (int)c->nunits,
+                                      c->head, c->batch_blocks, fp32, cap);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cap, &g);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&c->exec[k], g, nullptr, nullptr, 0);
+        (void)hipStreamDestroy(cap);
+        if (e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            c->exec[k] = nullptr;
+            set_err("recording the fused classification failed: %s", hipGetErrorString(e));
+            return ESES_EDEVICE;
+        }
+        c->graph[k] = g;
+    }
+    CK(hipGraphLaunch(c->exec[k], st));
+    return ESES_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -406,7 +489,11 @@ eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
     if (cfg) {
         if (cfg->tile != 0) tile = cfg->tile;
         force_recheck = cfg->force_recheck;
-        for (int q = 0; q < 6; ++q)
+        if (cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64) {
+            set_err("blocks_per_cu must be in [0, 64]");
+            return ESES_EINVAL;
+        }
+        for (int q = 0; q < 5; ++q)
             if (cfg->reserved[q] != 0) {
                 set_err("eses_config.reserved must be zero");
                 return ESES_EINVAL;
@@ -429,6 +516,16 @@ eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
             char pre[64];
             snprintf(pre, sizeof pre, "molecule %d: ", q);
             g_err = pre + msg;
+            return s;
+        }
+    }
+    if (n_mols > 1) {
+        c->blocks_per_cu = cfg ? cfg->blocks_per_cu : 0;
+        eses_status s = build_batch(c, st);
+        if (s != ESES_OK) {
+            std::string msg = g_err;
+            eses_free_candidates(c);
+            g_err = msg;
             return s;
         }
     }
@@ -486,8 +583,11 @@ eses_status eses_classify(eses_candidates *c, eses_precision prec, uint8_t *cons
         }
     if (stats)
         for (size_t q = 0; q < c->mols.size(); ++q) CK(fill_i32(c->mols[q]->m.diag + 1, 1, 0, st));
-    for (size_t q = 0; q < c->mols.size(); ++q)
-        CK(launch_classify(c->mols[q]->m, prec == ESES_FP32_RECHECK, labels[q], st));
+    if (c->mols.size() > 1) {
+        CKS(classify_batch(c, prec == ESES_FP32_RECHECK, labels, st));
+    } else {
+        CK(launch_classify(c->mols[0]->m, prec == ESES_FP32_RECHECK, labels[0], st));
+    }
     if (stats) {
         const size_t nm = c->mols.size();
         const size_t per = 2 + WC_COUNT;
@@ -589,6 +689,11 @@ eses_status eses_edge_intersections(eses_candidates *c, const uint8_t *const *la
 
 void eses_free_candidates(eses_candidates *c) {
     if (!c) return;
+    for (int k = 0; k < 2; ++k) {
+        if (c->exec[k]) (void)hipGraphExecDestroy(c->exec[k]);
+        if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+    }
+    c->batch.release();
     for (MolState *S : c->mols) {
         S->arena.release();
         S->scratch.release();

@@ -229,10 +229,7 @@ __device__ inline int shell_label_staged(const Mol &m, const ClsShared &sh, int 
 // with the certified thresholds above; points it cannot certify are
 // re-labelled in FP64 (counted in diag[1]).  Case 3 runs in FP64 either way.
 template <bool F32>
-__global__ void __launch_bounds__(CLS_THREADS) k_classify(Mol m, uint8_t *labels, int nblocks) {
-    __shared__ ClsShared sh;
-    const int tile = xcd_tile(blockIdx.x, nblocks, m.ntiles);
-    if (tile < 0) return;  // uniform across the workgroup
+__device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared &sh) {
     const int T = m.tile;
     const int P = T * T * T;
     const int t3[3] = {tile % m.tdims[0], (tile / m.tdims[0]) % m.tdims[1],
@@ -406,6 +403,84 @@ __global__ void __launch_bounds__(CLS_THREADS) k_classify(Mol m, uint8_t *labels
     }
 }
 
+template <bool F32>
+__global__ void __launch_bounds__(CLS_THREADS) k_classify(Mol m, uint8_t *labels, int nblocks) {
+    __shared__ ClsShared sh;
+    const int tile = xcd_tile(blockIdx.x, nblocks, m.ntiles);
+    if (tile < 0) return;  // uniform across the workgroup
+    classify_tile<F32>(m, tile, labels, sh);
+}
+
+// Persistent form for a batch of molecules: each workgroup pulls (molecule,
+// tile) units from an atomic queue until the queue is empty (every wave
+// reaches that exit).  Units are ordered heaviest first (tiles with
+// candidate features, then tiles with atoms, then empty tiles).
+template <bool F32>
+__global__ void __launch_bounds__(CLS_THREADS) k_classify_batch(const Mol *mols,
+                                                               uint8_t *const *labels,
+                                                               const int2 *units, int nunits,
+                                                               int *head) {
+    __shared__ ClsShared sh;
+    __shared__ int cur;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) cur = atomicAdd(head, 1);
+        __syncthreads();
+        const int u = cur;
+        if (u >= nunits) break;  // uniform across the workgroup
+        const int2 w = units[u];
+        classify_tile<F32>(mols[w.x], w.y, labels[w.x], sh);
+    }
+}
+
+// Work units of a batch: tile cost class 0 (probe, face or circle
+// candidates), 1 (atoms only) or 2 (empty), counted then scattered by class.
+__global__ void k_unit_count(const Mol *mols, const int *tile_base, int nmols, long long total,
+                             int *cls_count) {
+    long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    int lo = 0, hi = nmols - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (tile_base[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    const Mol &m = mols[lo];
+    int t = (int)(g - tile_base[lo]);
+    int heavy = (m.tF_off[t + 1] - m.tF_off[t]) + (m.tC_off[t + 1] - m.tC_off[t]) +
+                (m.tV_off[t + 1] - m.tV_off[t]);
+    int cls = heavy > 0 ? 0 : (m.tA_off[t + 1] > m.tA_off[t] ? 1 : 2);
+    atomicAdd(&cls_count[cls], 1);
+}
+
+__global__ void k_unit_scatter(const Mol *mols, const int *tile_base, int nmols, long long total,
+                               int *cls_fill, int2 *units) {
+    long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    int lo = 0, hi = nmols - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (tile_base[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    const Mol &m = mols[lo];
+    int t = (int)(g - tile_base[lo]);
+    int heavy = (m.tF_off[t + 1] - m.tF_off[t]) + (m.tC_off[t + 1] - m.tC_off[t]) +
+                (m.tV_off[t + 1] - m.tV_off[t]);
+    int cls = heavy > 0 ? 0 : (m.tA_off[t + 1] > m.tA_off[t] ? 1 : 2);
+    int pos = atomicAdd(&cls_fill[cls], 1);
+    units[pos] = make_int2(lo, t);
+}
+
+// cls_fill[c] = first slot of class c (from the counts), head = 0.
+__global__ void k_unit_bases(const int *cls_count, int *cls_fill) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        cls_fill[0] = 0;
+        cls_fill[1] = cls_count[0];
+        cls_fill[2] = cls_count[0] + cls_count[1];
+    }
+}
+
 // Statistics pass: the same decision with its tests tallied (not timed).
 __global__ void __launch_bounds__(CLS_BLOCK) k_classify_work(Mol m, unsigned long long *work) {
     const int T = m.tile;
@@ -454,6 +529,42 @@ hipError_t launch_count_inside(const uint8_t *labels, long long n, unsigned long
     if (nb > 2048) nb = 2048;
     if (nb < 1) nb = 1;
     hipLaunchKernelGGL(k_count_inside, dim3((unsigned)nb), dim3(256), 0, st, labels, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_units(const Mol *mols_dev, const int *tile_base_dev, int nmols, long long total,
+                        int *cls_count, int *cls_fill, int2 *units, hipStream_t st) {
+    unsigned nb = (unsigned)((total + 255) / 256);
+    hipError_t e = fill_i32(cls_count, 3, 0, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_unit_count, dim3(nb), dim3(256), 0, st, mols_dev, tile_base_dev, nmols,
+                       total, cls_count);
+    hipLaunchKernelGGL(k_unit_bases, dim3(1), dim3(64), 0, st, cls_count, cls_fill);
+    hipLaunchKernelGGL(k_unit_scatter, dim3(nb), dim3(256), 0, st, mols_dev, tile_base_dev, nmols,
+                       total, cls_fill, units);
+    return hipGetLastError();
+}
+
+int classify_batch_blocks_per_cu(bool fp32) {
+    int nb = 0;
+    if (fp32)
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_classify_batch<true>, CLS_THREADS, 0);
+    else
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_classify_batch<false>, CLS_THREADS, 0);
+    return nb > 0 ? nb : 1;
+}
+
+hipError_t launch_classify_batch(const Mol *mols_dev, uint8_t *const *labels_dev,
+                                 const int2 *units, int nunits, int *head, int nblocks, bool fp32,
+                                 hipStream_t st) {
+    hipError_t e = fill_i32(head, 1, 0, st);
+    if (e != hipSuccess) return e;
+    if (fp32)
+        hipLaunchKernelGGL(k_classify_batch<true>, dim3(nblocks), dim3(CLS_THREADS), 0, st,
+                           mols_dev, labels_dev, units, nunits, head);
+    else
+        hipLaunchKernelGGL(k_classify_batch<false>, dim3(nblocks), dim3(CLS_THREADS), 0, st,
+                           mols_dev, labels_dev, units, nunits, head);
     return hipGetLastError();
 }
 

@@ -33,6 +33,12 @@ hipError_t launch_tiles(const Mol &m, bool fill, int *cA, int *cF, int *cC, int 
 
 // stage 2
 hipError_t launch_classify(const Mol &m, bool fp32, uint8_t *labels, hipStream_t st);
+hipError_t launch_units(const Mol *mols_dev, const int *tile_base_dev, int nmols, long long total,
+                        int *cls_count, int *cls_fill, int2 *units, hipStream_t st);
+int classify_batch_blocks_per_cu(bool fp32);
+hipError_t launch_classify_batch(const Mol *mols_dev, uint8_t *const *labels_dev,
+                                 const int2 *units, int nunits, int *head, int nblocks, bool fp32,
+                                 hipStream_t st);
 hipError_t launch_classify_work(const Mol &m, unsigned long long *work, hipStream_t st);
 hipError_t launch_count_inside(const uint8_t *labels, long long n, unsigned long long *out,
                                hipStream_t st);

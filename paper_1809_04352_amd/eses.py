@@ -47,7 +47,7 @@ class Molecule(ctypes.Structure):
 
 class Config(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("force_recheck", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class CandidateStats(ctypes.Structure):
@@ -166,13 +166,15 @@ def _stream_ptr(stream):
 class Candidates:
     """Owning wrapper of an eses_candidates handle."""
 
-    def __init__(self, mols, tile: int = 0, stream=None, force_recheck: bool = False):
+    def __init__(self, mols, tile: int = 0, stream=None, force_recheck: bool = False,
+                 blocks_per_cu: int = 0):
         lib = load()
         self.mols = list(mols)
         arr = (Molecule * len(self.mols))(*self.mols)
         cfg = Config()
         cfg.tile = int(tile)
         cfg.force_recheck = 1 if force_recheck else 0
+        cfg.blocks_per_cu = int(blocks_per_cu)
         h = ctypes.c_void_p()
         self.stream = _stream_ptr(stream)
         _check(lib.eses_build_candidates(arr, len(self.mols), ctypes.byref(cfg), self.stream,
@@ -196,8 +198,9 @@ class Candidates:
         return st.as_dict()
 
 
-def build_candidates(mols, tile: int = 0, stream=None, force_recheck: bool = False) -> Candidates:
-    return Candidates(mols, tile, stream, force_recheck)
+def build_candidates(mols, tile: int = 0, stream=None, force_recheck: bool = False,
+                     blocks_per_cu: int = 0) -> Candidates:
+    return Candidates(mols, tile, stream, force_recheck, blocks_per_cu)
 
 
 def copy_vertices(cand: Candidates, mol: int, p_dev, atoms_dev, sign_dev, stream=None) -> int:

@@ -1,0 +1,127 @@
+"""The batched form: one persistent fused classification launch over many
+molecules (recorded as a HIP graph and replayed), against per-molecule
+results and the oracle."""
+import numpy as np
+import pytest
+
+from tests.parity import compare_edges, compare_labels
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def E():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1809_04352_amd import eses
+    eses.load()
+    return eses
+
+
+def run_batch(E, mols_np, prec, reps=2, blocks_per_cu=0, tile=0):
+    import torch
+    tens = [(torch.as_tensor(m.centres, device="cuda"), torch.as_tensor(m.radii, device="cuda"))
+            for m in mols_np]
+    mols = [E.make_molecule(c, r, m.probe, m.spacing, m.lo, m.hi)
+            for (c, r), m in zip(tens, mols_np)]
+    cand = E.build_candidates(mols, tile=tile, blocks_per_cu=blocks_per_cu)
+    dims = [E.grid_dims(m) for m in mols]
+    out = []
+    for rep in range(reps):
+        labels = [torch.full((d[0] * d[1] * d[2],), 7, dtype=torch.uint8, device="cuda")
+                  for d in dims]
+        E.classify(cand, prec, labels)
+        torch.cuda.synchronize()
+        # eager work between replays
+        _ = torch.arange(1000, device="cuda").sum().item()
+        out.append([l.cpu().numpy().reshape(d[2], d[1], d[0]) for l, d in zip(labels, dims)])
+    for rep in range(1, reps):
+        for a, b in zip(out[0], out[rep]):
+            assert np.array_equal(a, b), "replay differs"
+    edges = []
+    isect = [E.alloc_isect(1) for _ in mols]
+    st, counts = E.edge_intersections(cand, labels, isect)
+    isect = [E.alloc_isect(max(k, 1)) for k in counts]
+    st, counts = E.edge_intersections(cand, labels, isect)
+    assert st == E.ESES_OK
+    torch.cuda.synchronize()
+    for o, k in zip(isect, counts):
+        edges.append(dict(key=o.key[:k].cpu().numpy(), lam=o.lam[:k].cpu().numpy(),
+                          normal=o.normal[:k].cpu().numpy(),
+                          patch_type=o.patch_type[:k].cpu().numpy(),
+                          atoms=o.atoms[:k].cpu().numpy()))
+    cand.close()
+    return out[0], edges
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_matches_single(E, oracle_mod, prec):
+    from eses_inputs import molecule
+    spec = [(1, 1, 0.4), (2, 2, 0.5), (40, 3, 0.35), (300, 4, 0.5), (120, 5, 0.25), (60, 6, 0.45),
+            (800, 7, 0.5), (3, 8, 0.3)]
+    mols = [molecule(n, s, h) for n, s, h in spec]
+    print("case: batch of", len(mols), "prec", prec, flush=True)
+    labels, edges = run_batch(E, mols, prec, reps=3)
+    for m, lab, ed in zip(mols, labels, edges):
+        single = E.surface(m.centres, m.radii, m.probe, m.spacing, m.lo, m.hi, prec=prec)
+        assert np.array_equal(single["labels"], lab)
+        for k in ("key", "lam", "normal", "patch_type", "atoms"):
+            assert np.array_equal(single[k], ed[k]), k
+        o = oracle_mod.Oracle(m.centres, m.radii, m.probe)
+        ref = o.labels_grid(m.lo, m.spacing, m.dims)
+        compare_labels(lab, ref)
+        compare_edges(ed, o, m.lo, m.spacing, m.dims, ref)
+
+
+def test_batch256(E, oracle_mod):
+    """The 256-molecule batch (log-uniform sizes 200-20,000 atoms, h = 0.5 A):
+    FP32+recheck equals FP64 over every grid; the oracle checks the smallest
+    molecules whole and slices of the largest."""
+    from eses_inputs import batch
+    mols = batch(256, 0.5)
+    print("case: batch256, atoms", sum(m.n_atoms for m in mols), "points",
+          sum(m.n_points for m in mols), flush=True)
+    lab64, ed64 = run_batch(E, mols, 0, reps=2)
+    lab32, ed32 = run_batch(E, mols, 1, reps=2)
+    for a, b in zip(lab64, lab32):
+        assert np.array_equal(a, b)
+    for a, b in zip(ed64, ed32):
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
+    order = np.argsort([m.n_atoms for m in mols])
+    for q in list(order[:3]) + list(order[-2:]):
+        m = mols[q]
+        o = oracle_mod.Oracle(m.centres, m.radii, m.probe)
+        nx, ny, nz = m.dims
+        if m.n_points < 3e6:
+            ref = o.labels_grid(m.lo, m.spacing, m.dims)
+            compare_labels(lab64[q], ref)
+            compare_edges(ed64[q], o, m.lo, m.spacing, m.dims, ref)
+        else:
+            key = ed64[q]["key"]
+            for k in np.linspace(1, nz - 3, 5).astype(int):
+                ref = o.labels_grid(m.lo, m.spacing, m.dims, int(k), int(k) + 2)
+                compare_labels(lab64[q][k:k + 2], ref)
+                sel = (key // 3) // (nx * ny) == k
+                want = oracle_mod.crossing_keys(ref)
+                want = want[(want // 3) < nx * ny] + 3 * int(k) * nx * ny
+                assert np.array_equal(key[sel], want)
+                compare_edges({f: ed64[q][f][sel] for f in ed64[q]}, o, m.lo, m.spacing, m.dims)
+
+
+def test_autotune(E, tmp_path, monkeypatch):
+    from eses_inputs import molecule
+    from paper_1809_04352_amd import autotune
+    import torch
+    monkeypatch.setenv("ESES_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
+    mols_np = [molecule(n, 30 + n, 0.5) for n in (100, 400, 900)]
+    tens = [(torch.as_tensor(m.centres, device="cuda"), torch.as_tensor(m.radii, device="cuda"))
+            for m in mols_np]
+    mols = [E.make_molecule(c, r, m.probe, m.spacing, m.lo, m.hi)
+            for (c, r), m in zip(tens, mols_np)]
+    best, times = autotune.tune(mols, E.ESES_FP32_RECHECK, reps=2)
+    assert len(times) == len(autotune.CANDIDATES_BATCH)
+    assert best in autotune.CANDIDATES_BATCH
+    best2, times2 = autotune.tune(mols, E.ESES_FP32_RECHECK, reps=2)
+    assert best2 == best and times2 == times  # cached
