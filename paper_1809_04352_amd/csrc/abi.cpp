@@ -7,7 +7,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/eses.h"
@@ -143,6 +145,14 @@ eses_status d2h(T *host, const T *dev, size_t count, hipStream_t st) {
     return ESES_OK;
 }
 
+// Several single ints read back with one synchronisation.
+eses_status d2h_ints(std::initializer_list<std::pair<int *, const int *>> items, hipStream_t st) {
+    for (auto &it : items)
+        CK(hipMemcpyAsync(it.first, it.second, sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    return ESES_OK;
+}
+
 // Stage 1 for one molecule.
 eses_status build_one(const eses_molecule *in, int tile, int force_recheck, MolState *S,
                       hipStream_t st) {
@@ -196,7 +206,7 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, MolS
     CK(launch_bounds(in->centers, in->radii, m.n, dbounds, dbad, st));
     double hb[8];
     int hbad = 0;
-    CKS(d2h(hb, dbounds, 7, st));
+    CK(hipMemcpyAsync(hb, dbounds, sizeof(double) * 7, hipMemcpyDeviceToHost, st));
     CKS(d2h(&hbad, dbad, 1, st));
     if (hbad) {
         set_err("centres must be finite and radii finite and > 0");
@@ -249,18 +259,20 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, MolS
     CK(scan_i32(nbr_cnt, m.n, m.nbr_off, tmp, st));
     CK(scan_i32(circ_cnt, m.n, m.circ_off, tmp, st));
     int tot[2];
-    CKS(d2h(&tot[0], m.nbr_off + m.n, 1, st));
-    CKS(d2h(&tot[1], m.circ_off + m.n, 1, st));
+    CKS(d2h_ints({{&tot[0], m.nbr_off + m.n}, {&tot[1], m.circ_off + m.n}}, st));
     m.ncirc = tot[1];
     CKS(A.alloc(&m.nbr, tot[0]));
+    CKS(A.alloc(&m.nbr_cov, tot[0]));
     CKS(A.alloc(&m.circ_i, m.ncirc));
     CKS(A.alloc(&m.circ_j, m.ncirc));
     CKS(A.alloc(&m.circ_oR, m.ncirc));
     CKS(A.alloc(&m.circ_n, m.ncirc));
     CKS(A.alloc(&m.cflag, m.ncirc));
     CK(launch_nbr(m, true, nbr_cnt, circ_cnt, st));
+    CK(launch_nbr_sort(m, st));
 
-    // concave probe positions and exposure flags
+    // concave probe positions (count pass), exposure flags, exposed faces and
+    // circles; their totals come back with one synchronisation
     int *vcnt, *tmp2;
     CKS(T.alloc(&vcnt, m.ncirc));
     CKS(T.alloc(&tmp2, scan_tmp_elems(m.ncirc) + 64));
@@ -268,12 +280,6 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, MolS
     CK(launch_vertex(m, false, vcnt, st));
     CK(launch_circle_free(m, st));
     CK(scan_i32(vcnt, m.ncirc, m.vert_off, tmp2, st));
-    CKS(d2h(&m.nvert, m.vert_off + m.ncirc, 1, st));
-    CKS(A.alloc(&m.vert_p, m.nvert));
-    CKS(A.alloc(&m.vert_ijks, m.nvert));
-    CK(launch_vertex(m, true, vcnt, st));
-
-    // exposed faces and circles
     int *face_cnt, *ecf, *ec_pos;
     CKS(T.alloc(&face_cnt, m.n));
     CKS(T.alloc(&ecf, m.ncirc));
@@ -285,29 +291,30 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, MolS
     CK(scan_i32(face_cnt, m.n, m.face_off_atom, tmp, st));
     CK(launch_ec_flag(m, ecf, st));
     CK(scan_i32(ecf, m.ncirc, ec_pos, tmp2, st));
-    CKS(d2h(&m.nface, m.face_off_atom + m.n, 1, st));
-    CKS(d2h(&m.nec, ec_pos + m.ncirc, 1, st));
+    CKS(d2h_ints({{&m.nvert, m.vert_off + m.ncirc}, {&m.nface, m.face_off_atom + m.n},
+                   {&m.nec, ec_pos + m.ncirc}}, st));
+    CKS(A.alloc(&m.vert_p, m.nvert));
+    CKS(A.alloc(&m.vert_ijks, m.nvert));
+    CK(launch_vertex(m, true, vcnt, st));
     CKS(A.alloc(&m.ec_circ, m.nec));
     CK(launch_ec_ids(m, ec_pos, st));
 
+    // cut lists of exposed faces and circles (one synchronisation for both)
     int *fcut_cnt, *eccut_cnt, *tmp3;
     CKS(A.alloc(&m.face_atom, m.nface));
     CKS(A.alloc(&m.face_cut_off, m.nface + 1));
+    CKS(A.alloc(&m.ec_cut_off, m.nec + 1));
     CKS(T.alloc(&fcut_cnt, m.nface));
+    CKS(T.alloc(&eccut_cnt, m.nec));
     CKS(T.alloc(&tmp3, scan_tmp_elems(std::max(m.nface, m.nec)) + 64));
     CK(launch_face_list(m, fcut_cnt, st));
     CK(scan_i32(fcut_cnt, m.nface, m.face_cut_off, tmp3, st));
-    int nfc = 0;
-    CKS(d2h(&nfc, m.face_cut_off + m.nface, 1, st));
-    CKS(A.alloc(&m.face_cut, nfc));
-    CK(launch_face_cuts(m, st));
-
-    CKS(A.alloc(&m.ec_cut_off, m.nec + 1));
-    CKS(T.alloc(&eccut_cnt, m.nec));
     CK(launch_ec_cuts(m, false, eccut_cnt, st));
     CK(scan_i32(eccut_cnt, m.nec, m.ec_cut_off, tmp3, st));
-    int nec_cut = 0;
-    CKS(d2h(&nec_cut, m.ec_cut_off + m.nec, 1, st));
+    int nfc = 0, nec_cut = 0;
+    CKS(d2h_ints({{&nfc, m.face_cut_off + m.nface}, {&nec_cut, m.ec_cut_off + m.nec}}, st));
+    CKS(A.alloc(&m.face_cut, nfc));
+    CK(launch_face_cuts(m, st));
     CKS(A.alloc(&m.ec_cut, nec_cut));
     CK(launch_ec_cuts(m, true, eccut_cnt, st));
 
@@ -327,10 +334,8 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, MolS
     CK(scan_i32(cC, m.ntiles, m.tC_off, tmp, st));
     CK(scan_i32(cV, m.ntiles, m.tV_off, tmp, st));
     int tl[4];
-    CKS(d2h(&tl[0], m.tA_off + m.ntiles, 1, st));
-    CKS(d2h(&tl[1], m.tF_off + m.ntiles, 1, st));
-    CKS(d2h(&tl[2], m.tC_off + m.ntiles, 1, st));
-    CKS(d2h(&tl[3], m.tV_off + m.ntiles, 1, st));
+    CKS(d2h_ints({{&tl[0], m.tA_off + m.ntiles}, {&tl[1], m.tF_off + m.ntiles},
+                   {&tl[2], m.tC_off + m.ntiles}, {&tl[3], m.tV_off + m.ntiles}}, st));
     CKS(A.alloc(&m.tA, tl[0]));
     CKS(A.alloc(&m.tF, tl[1]));
     CKS(A.alloc(&m.tC, tl[2]));
@@ -660,11 +665,23 @@ eses_status eses_edge_intersections(eses_candidates *c, const uint8_t *const *la
         if (e == hipSuccess) e = hipMemcpyAsync(&total, boff + nblk, sizeof(long long), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         long long nw = std::min<long long>(total, o.capacity);
+        int *tcount = nullptr, *tfill = nullptr, *order = nullptr, *ttmp = nullptr;
+        if (e == hipSuccess && nw > 0) {
+            if ((s = T.alloc(&tcount, m.ntiles + 1)) != ESES_OK ||
+                (s = T.alloc(&tfill, m.ntiles + 1)) != ESES_OK ||
+                (s = T.alloc(&order, nw)) != ESES_OK ||
+                (s = T.alloc(&ttmp, scan_tmp_elems(m.ntiles) + 64)) != ESES_OK) {
+                T.release();
+                return s;
+            }
+        }
         if (e == hipSuccess && nw > 0) e = launch_edge_detect_write(labels[q], m, boff, o.capacity, (long long *)o.key, st);
         if (e == hipSuccess) e = fill_i32(ovf, 1, 0, st);
         if (e == hipSuccess && nw > 0)
+            e = launch_edge_group(m, (const long long *)o.key, nw, tcount, tfill, order, ttmp, st);
+        if (e == hipSuccess && nw > 0)
             e = launch_edge_roots(m, labels[q], (const long long *)o.key, nw, o.lambda, o.normal, o.patch_type,
-                                  o.atoms, ovf, st);
+                                  o.atoms, ovf, order, st);
         int hovf = 0;
         if (e == hipSuccess) e = hipMemcpyAsync(&hovf, ovf, sizeof(int), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);

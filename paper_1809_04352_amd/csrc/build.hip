@@ -273,6 +273,52 @@ __global__ void __launch_bounds__(NB_WAVES *WAVE) k_nbr(Mol m, int *nbr_cnt, int
     }
 }
 
+// Neighbour lists re-ordered by the cap each neighbour cuts from S_i,
+// largest first (ascending cos of the cap's half-angle, tau_ik / d_ik), so
+// loops that stop at the first covering ball find it early.  One wavefront
+// per atom ranks its list in LDS; a list longer than NS_MAX keeps the
+// ascending order.
+constexpr int NS_WAVES = 4;
+constexpr int NS_MAX = 256;
+
+__global__ void __launch_bounds__(NS_WAVES *WAVE) k_nbr_sort(Mol m) {
+    __shared__ double keys[NS_WAVES][NS_MAX];
+    const int w = threadIdx.x / WAVE;
+    const int lane = lane_id();
+    const int i = blockIdx.x * NS_WAVES + w;
+    // every wavefront reaches the barrier below; `mode` says what it does
+    int b = 0, n = 0, mode = 0;  // 0 idle, 1 copy unsorted, 2 rank
+    if (i < m.n) {
+        b = m.nbr_off[i];
+        n = m.nbr_off[i + 1] - b;
+        mode = n > NS_MAX ? 1 : 2;
+    }
+    if (mode == 1)
+        for (int q = lane; q < n; q += WAVE) m.nbr_cov[b + q] = m.nbr[b + q];
+    if (mode == 2) {
+        double4 ai = m.atom[i];
+        double si = ai.w + m.rho;
+        for (int q = lane; q < n; q += WAVE) {
+            double4 ak = m.atom[m.nbr[b + q]];
+            double sk = ak.w + m.rho;
+            double d2 = sq(ak.x - ai.x) + sq(ak.y - ai.y) + sq(ak.z - ai.z);
+            keys[w][q] = (si * si + d2 - sk * sk) / (2.0 * si * sqrt(d2));
+        }
+    }
+    __syncthreads();
+    if (mode == 2) {
+        for (int q = lane; q < n; q += WAVE) {
+            double kq = keys[w][q];
+            int rank = 0;
+            for (int p = 0; p < n; ++p) {
+                double kp = keys[w][p];
+                rank += (kp < kq || (kp == kq && p < q)) ? 1 : 0;
+            }
+            m.nbr_cov[b + rank] = m.nbr[b + q];
+        }
+    }
+}
+
 // ------------------------------------------------- concave probe positions
 
 // Circle id of the pair (a, b), a < b, or -1.
@@ -354,7 +400,7 @@ __global__ void __launch_bounds__(VX_WAVES *WAVE) k_vertex(Mol m, int *vcnt) {
         bool ok0 = live, ok1 = live;
         for (int q2 = nb; q2 < ne; ++q2) {
             if (!__any(ok0 || ok1)) break;
-            int l = m.nbr[q2];
+            int l = m.nbr_cov[q2];
             double4 al = m.atom[l];
             double sl2 = sq(al.w + m.rho);
             if (l == j || l == k) continue;
@@ -420,7 +466,7 @@ __global__ void k_circle_free(Mol m) {
     perp_unit(n.x, n.y, n.z, ux, uy, uz);
     double qx = oR.x + oR.w * ux, qy = oR.y + oR.w * uy, qz = oR.z + oR.w * uz;
     for (int q = m.nbr_off[i]; q < m.nbr_off[i + 1]; ++q) {
-        int l = m.nbr[q];
+        int l = m.nbr_cov[q];
         if (l == j) continue;
         double4 al = m.atom[l];
         double sl = al.w + m.rho;
@@ -468,7 +514,7 @@ __global__ void __launch_bounds__(FC_WAVES *WAVE) k_face_cuts(Mol m) {
     int w = m.face_cut_off[f];
     int nb = m.nbr_off[i], ne = m.nbr_off[i + 1];
     for (int q = nb + lane_id(); q < ne; q += WAVE) {
-        double4 ak = m.atom[m.nbr[q]];
+        double4 ak = m.atom[m.nbr_cov[q]];
         double sk = ak.w + m.rho;
         double vx = ak.x - ai.x, vy = ak.y - ai.y, vz = ak.z - ai.z;
         double d2 = vx * vx + vy * vy + vz * vz;
@@ -510,7 +556,7 @@ __global__ void __launch_bounds__(EC_WAVES *WAVE) k_ec_cuts(Mol m, int *cut_cnt)
         bool in = false;
         double4 cut = make_double4(0, 0, 0, 0);
         if (q < m.nbr_off[i + 1]) {
-            int k = m.nbr[q];
+            int k = m.nbr_cov[q];
             if (k != j) {
                 double4 ak = m.atom[k];
                 double sk = ak.w + m.rho;
@@ -714,6 +760,11 @@ hipError_t launch_nbr(const Mol &m, bool fill, int *nbr_cnt, int *circ_cnt, hipS
         hipLaunchKernelGGL(k_nbr<true>, dim3(nb), dim3(NB_WAVES * WAVE), 0, st, m, nbr_cnt, circ_cnt);
     else
         hipLaunchKernelGGL(k_nbr<false>, dim3(nb), dim3(NB_WAVES * WAVE), 0, st, m, nbr_cnt, circ_cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_nbr_sort(const Mol &m, hipStream_t st) {
+    hipLaunchKernelGGL(k_nbr_sort, dim3(blocks_for(m.n, NS_WAVES)), dim3(NS_WAVES * WAVE), 0, st, m);
     return hipGetLastError();
 }
 

@@ -232,66 +232,84 @@ __device__ inline void sort3(int &a, int &b, int &c) {
     if (a > b) { t = a; a = b; b = t; }
 }
 
-// Roots of surfaces that can carry the boundary of M on the edge.  A root x is
-// kept only if the point of A that would put x on the boundary is admissible:
-// the radial projection onto an exposed face (van der Waals roots) or the
-// nearest point of an exposed circle (torus roots).  Every label change lies
-// on such a point, so dropping the others is exact.  Only roots u > lower
-// are kept (the MAXR smallest of them).
-__device__ void collect_roots(const Mol &m, int tile, int axis, const double *xs,
-                              const double *mid, double lower, double *ru, int *rt, int &nr,
-                              bool &truncated) {
+// Surfaces whose distance from the edge's midpoint is within h/2 of zero
+// (distance to a set is 1-Lipschitz, so only these can cross the edge) are
+// first gathered per lane, so the solves below run over each lane's own short
+// list instead of every lane waiting on every other lane's solves.
+constexpr int EDGE_THREADS = 256;
+constexpr int MAXS = 32;  // surfaces listed per edge; more are solved in place
+
+struct EdgeSurf {
+    int n;
+    bool more;  // more than MAXS surfaces: the lists are scanned again
+};
+
+__device__ inline int surf_slot(int q) { return q * EDGE_THREADS + (int)threadIdx.x; }
+
+__device__ inline bool face_reaches(const Mol &m, int f, const double *mid, double half) {
+    double4 a = m.atom[m.face_atom[f]];
+    double dm2 = sq(mid[0] - a.x) + sq(mid[1] - a.y) + sq(mid[2] - a.z);
+    return !(dm2 > sq(a.w + half) || (a.w > half && dm2 < sq(a.w - half)));
+}
+
+__device__ inline bool probe_reaches(const Mol &m, int v, const double *mid, double half) {
+    double4 c = m.vert_p[v];
+    double dm2 = sq(mid[0] - c.x) + sq(mid[1] - c.y) + sq(mid[2] - c.z);
+    return !(dm2 > sq(m.rho + half) || (m.rho > half && dm2 < sq(m.rho - half)));
+}
+
+__device__ inline bool torus_reaches(const Mol &m, int ec, const double *mid, double half) {
+    int ci = m.ec_circ[ec];
+    double4 oR = m.circ_oR[ci];
+    double4 nn = m.circ_n[ci];
+    double dm0 = mid[0] - oR.x, dm1 = mid[1] - oR.y, dm2 = mid[2] - oR.z;
+    double tm = dm0 * nn.x + dm1 * nn.y + dm2 * nn.z;
+    double bm = sqrt(fmax(0.0, dm0 * dm0 + dm1 * dm1 + dm2 * dm2 - tm * tm));
+    double dc2 = tm * tm + sq(bm - oR.w);  // squared distance of the midpoint from the circle
+    return !(dc2 > sq(m.rho + half) || (m.rho > half && dc2 < sq(m.rho - half)));
+}
+
+// Roots u > lower (in [0, 1]) of one surface (type 1 face atom f, 3 probe v,
+// 2 exposed circle ec), kept only if the point of A that would put the root
+// on the boundary is admissible: the radial projection onto the exposed face
+// (van der Waals roots) or the nearest point of the exposed circle (torus
+// roots).  Every label change lies on such a point, so dropping the others
+// is exact.
+__device__ void surface_roots(const Mol &m, int type, int id, int axis,
+                                          const double *xs,
+                              double lower, double *ru, int *rt, int &nr, bool &truncated) {
     const double h = m.h, rho = m.rho;
-    nr = 0;
-    truncated = false;
     double tmp[4];
-    // A surface can cross the edge only if its distance from the edge's
-    // midpoint is within h/2 of zero (distance to a set is 1-Lipschitz).
-    const double half = 0.5 * h + 1e-9;
-    // van der Waals spheres of atoms with an exposed face
-    for (int p = m.tF_off[tile], e = m.tF_off[tile + 1]; p < e; ++p) {
-        int f = m.tF[p];
+    if (type == 1) {
+        int f = id;
         int i = m.face_atom[f];
         double4 a = m.atom[i];
-        double dm2 = sq(mid[0] - a.x) + sq(mid[1] - a.y) + sq(mid[2] - a.z);
-        if (dm2 > sq(a.w + half) || (a.w > half && dm2 < sq(a.w - half))) continue;
         double w0[3] = {xs[0] - a.x, xs[1] - a.y, xs[2] - a.z};
         int n = quad01(h * h, 2.0 * h * w0[axis],
                        w0[0] * w0[0] + w0[1] * w0[1] + w0[2] * w0[2] - a.w * a.w, tmp);
         for (int t = 0; t < n; ++t) {
+            if (!(tmp[t] > lower)) continue;
             double x[3] = {w0[0], w0[1], w0[2]};
             x[axis] += tmp[t] * h;
             if (face_admissible(m, f, x[0], x[1], x[2]))
-                if (tmp[t] > lower) push_root(ru, rt, nr, truncated, tmp[t], 1, i);
+                push_root(ru, rt, nr, truncated, tmp[t], 1, i);
         }
-    }
-    // probe spheres around concave probe positions
-    for (int p = m.tV_off[tile], e = m.tV_off[tile + 1]; p < e; ++p) {
-        int v = m.tV[p];
+    } else if (type == 3) {
+        int v = id;
         double4 c = m.vert_p[v];
-        double dm2 = sq(mid[0] - c.x) + sq(mid[1] - c.y) + sq(mid[2] - c.z);
-        if (dm2 > sq(rho + half) || (rho > half && dm2 < sq(rho - half))) continue;
         double w0[3] = {xs[0] - c.x, xs[1] - c.y, xs[2] - c.z};
         int n = quad01(h * h, 2.0 * h * w0[axis],
                        w0[0] * w0[0] + w0[1] * w0[1] + w0[2] * w0[2] - rho * rho, tmp);
         for (int t = 0; t < n; ++t)
             if (tmp[t] > lower) push_root(ru, rt, nr, truncated, tmp[t], 3, v);
-    }
-    // tori: (|w|^2 + R^2 - rho^2)^2 = 4 R^2 |w_perp|^2, the branch at distance
-    // rho from the near circle point
-    for (int p = m.tC_off[tile], e = m.tC_off[tile + 1]; p < e; ++p) {
-        int ec = m.tC[p];
+    } else {
+        // torus (|w|^2 + R^2 - rho^2)^2 = 4 R^2 |w_perp|^2, the branch at
+        // distance rho from the near circle point
+        int ec = id;
         int ci = m.ec_circ[ec];
         double4 oR = m.circ_oR[ci];
         double4 nn = m.circ_n[ci];
         double R = oR.w;
-        double dm[3] = {mid[0] - oR.x, mid[1] - oR.y, mid[2] - oR.z};
-        {
-            double tm = dm[0] * nn.x + dm[1] * nn.y + dm[2] * nn.z;
-            double bm = sqrt(fmax(0.0, dm[0] * dm[0] + dm[1] * dm[1] + dm[2] * dm[2] - tm * tm));
-            double dc2 = tm * tm + sq(bm - R);  // squared distance of the midpoint from the circle
-            if (dc2 > sq(rho + half) || (rho > half && dc2 < sq(rho - half))) continue;
-        }
         double w0[3] = {xs[0] - oR.x, xs[1] - oR.y, xs[2] - oR.z};
         double nv[3] = {nn.x, nn.y, nn.z};
         double ww = w0[0] * w0[0] + w0[1] * w0[1] + w0[2] * w0[2];
@@ -305,27 +323,78 @@ __device__ void collect_roots(const Mol &m, int tile, int axis, const double *xs
         double r4[10];
         int n = quartic01(g, r4);
         for (int t = 0; t < n; ++t) {
+            if (!(r4[t] > lower)) continue;
             double x[3] = {w0[0], w0[1], w0[2]};
             x[axis] += r4[t] * h;
             double tt = x[0] * nv[0] + x[1] * nv[1] + x[2] * nv[2];
             double bb = sqrt(fmax(0.0, x[0] * x[0] + x[1] * x[1] + x[2] * x[2] - tt * tt));
             double near = fabs(sq(bb - R) + tt * tt - rho * rho);
             double far = fabs(sq(bb + R) + tt * tt - rho * rho);
-            if (r4[t] > lower && near <= far && circle_admissible(m, ec, nn, x[0], x[1], x[2]))
+            if (near <= far && circle_admissible(m, ec, nn, x[0], x[1], x[2]))
                 push_root(ru, rt, nr, truncated, r4[t], 2, ec);
         }
     }
 }
 
-__global__ void __launch_bounds__(256) k_edge_roots(Mol m, const uint8_t *L, const long long *keys,
+// The edge's reaching surfaces with index in [skip, skip + MAXS), packed
+// (type << 28 | id) in LDS; `more` if there are further ones.
+__device__ EdgeSurf gather_surfaces(const Mol &m, int tile, const double *mid, int *slots,
+                                    int skip) {
+    const double half = 0.5 * m.h + 1e-9;
+    EdgeSurf es = {0, false};
+    int seen = 0;
+    for (int p = m.tF_off[tile], e = m.tF_off[tile + 1]; p < e; ++p) {
+        int f = m.tF[p];
+        if (!face_reaches(m, f, mid, half) || seen++ < skip) continue;
+        if (es.n < MAXS) slots[surf_slot(es.n++)] = (1 << 28) | f;
+        else es.more = true;
+    }
+    for (int p = m.tV_off[tile], e = m.tV_off[tile + 1]; p < e; ++p) {
+        int v = m.tV[p];
+        if (!probe_reaches(m, v, mid, half) || seen++ < skip) continue;
+        if (es.n < MAXS) slots[surf_slot(es.n++)] = (3 << 28) | v;
+        else es.more = true;
+    }
+    for (int p = m.tC_off[tile], e = m.tC_off[tile + 1]; p < e; ++p) {
+        int ec = m.tC[p];
+        if (!torus_reaches(m, ec, mid, half) || seen++ < skip) continue;
+        if (es.n < MAXS) slots[surf_slot(es.n++)] = (2 << 28) | ec;
+        else es.more = true;
+    }
+    return es;
+}
+
+// All roots u > lower of the edge's reaching surfaces (the MAXR smallest).
+// `es` describes the first window of surfaces in `slots`; further windows
+// (rare) are gathered in turn and the first one is restored at the end.
+__device__ void collect_roots(const Mol &m, int tile, int axis, const double *xs,
+                              const double *mid, int *slots, EdgeSurf es, double lower,
+                              double *ru, int *rt, int &nr, bool &truncated) {
+    nr = 0;
+    truncated = false;
+    int skip = 0;
+    for (;;) {
+        for (int q = 0; q < es.n; ++q) {
+            int s = slots[surf_slot(q)];
+            surface_roots(m, s >> 28, s & ((1 << 28) - 1), axis, xs, lower, ru, rt, nr, truncated);
+        }
+        if (!es.more) break;
+        skip += MAXS;
+        es = gather_surfaces(m, tile, mid, slots, skip);
+    }
+    if (skip > 0) gather_surfaces(m, tile, mid, slots, 0);
+}
+
+__global__ void __launch_bounds__(EDGE_THREADS) k_edge_roots(Mol m, const uint8_t *L, const long long *keys,
                                                     long long count, double *lam, double *nrm,
                                                     uint8_t *ptype, int *patoms, int *overflow,
-                                                    int nblocks) {
-    // consecutive edges (same rows, same tiles) stay on one XCD
-    int blk = xcd_tile(blockIdx.x, nblocks, (int)((count + 255) / 256));
+                                                    const int *order, int nblocks) {
+    // edges grouped by tile (order), consecutive groups on one XCD
+    int blk = xcd_tile(blockIdx.x, nblocks, (int)((count + EDGE_THREADS - 1) / EDGE_THREADS));
     if (blk < 0) return;
-    long long q = (long long)blk * 256 + threadIdx.x;
-    if (q >= count) return;
+    long long g = (long long)blk * EDGE_THREADS + threadIdx.x;
+    if (g >= count) return;
+    const long long q = order[g];
     long long key = keys[q];
     int axis = (int)(key % 3);
     long long idx = key / 3;
@@ -340,6 +409,8 @@ __global__ void __launch_bounds__(256) k_edge_roots(Mol m, const uint8_t *L, con
     double mid[3] = {xs[0], xs[1], xs[2]};
     mid[axis] += 0.5 * h;
 
+    __shared__ int slots[MAXS * EDGE_THREADS];
+    const EdgeSurf es = gather_surfaces(m, tile, mid, slots, 0);
     double ru[MAXR];
     int rt[MAXR];
     int nr = 0;
@@ -356,7 +427,8 @@ __global__ void __launch_bounds__(256) k_edge_roots(Mol m, const uint8_t *L, con
     bool found = false;
     for (int page = 0; page < 64; ++page) {
         const bool first = page == 0;
-        collect_roots(m, tile, axis, xs, mid, first ? -1.0 : prev, ru, rt, nr, truncated);
+        collect_roots(m, tile, axis, xs, mid, slots, es, first ? -1.0 : prev, ru, rt, nr,
+                      truncated);
         bool root0 = first && nr > 0 && ru[0] == 0.0;
         bool root1 = !truncated && nr > 0 && ru[nr - 1] == 1.0;
         for (int r = 0; r <= nr; ++r) {
@@ -450,6 +522,42 @@ __global__ void __launch_bounds__(256) k_edge_roots(Mol m, const uint8_t *L, con
     patoms[3 * q + 2] = at[2];
 }
 
+// Permutation of the crossing edges grouping them by the tile owning s
+// (counting sort; the order inside a tile is not used by any result).
+__device__ inline int edge_tile(const Mol &m, long long key) {
+    long long idx = key / 3;
+    const int nx = m.dims[0], ny = m.dims[1];
+    int i = (int)(idx % nx), j = (int)((idx / nx) % ny), k = (int)(idx / ((long long)nx * ny));
+    return i / m.tile + m.tdims[0] * (j / m.tile + m.tdims[1] * (k / m.tile));
+}
+
+__global__ void k_edge_tile_count(Mol m, const long long *keys, long long count, int *tcount) {
+    long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    atomicAdd(&tcount[edge_tile(m, keys[q])], 1);
+}
+
+__global__ void k_edge_tile_scatter(Mol m, const long long *keys, long long count, int *tfill,
+                                    int *order) {
+    long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    order[atomicAdd(&tfill[edge_tile(m, keys[q])], 1)] = (int)q;
+}
+
+hipError_t launch_edge_group(const Mol &m, const long long *keys, long long count, int *tcount,
+                             int *tfill, int *order, int *tmp, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    unsigned nb = (unsigned)((count + 255) / 256);
+    hipError_t e = fill_i32(tcount, m.ntiles + 1, 0, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_edge_tile_count, dim3(nb), dim3(256), 0, st, m, keys, count, tcount);
+    e = scan_i32(tcount, m.ntiles, tfill, tmp, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_edge_tile_scatter, dim3(nb), dim3(256), 0, st, m, keys, count, tfill,
+                       order);
+    return hipGetLastError();
+}
+
 hipError_t launch_edge_detect_count(const uint8_t *L, const Mol &m, int *bcount, long long *nblk,
                                     hipStream_t st) {
     long long nb = (m.npts + EDGE_BLOCK - 1) / EDGE_BLOCK;
@@ -471,12 +579,12 @@ hipError_t launch_edge_detect_write(const uint8_t *L, const Mol &m, const long l
 
 hipError_t launch_edge_roots(const Mol &m, const uint8_t *L, const long long *keys,
                              long long count, double *lam, double *nrm, uint8_t *ptype,
-                             int *patoms, int *overflow, hipStream_t st) {
+                             int *patoms, int *overflow, const int *order, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    int nb = (int)((count + 255) / 256);
+    int nb = (int)((count + EDGE_THREADS - 1) / EDGE_THREADS);
     nb = (nb + NXCD - 1) / NXCD * NXCD;
-    hipLaunchKernelGGL(k_edge_roots, dim3(nb), dim3(256), 0, st, m, L, keys, count, lam, nrm,
-                       ptype, patoms, overflow, nb);
+    hipLaunchKernelGGL(k_edge_roots, dim3(nb), dim3(EDGE_THREADS), 0, st, m, L, keys, count, lam, nrm,
+                       ptype, patoms, overflow, order, nb);
     return hipGetLastError();
 }
 

@@ -60,6 +60,7 @@ struct Mol {
 
     int *nbr_off;        // [n + 1]
     int *nbr;            // internal ids, ascending per atom
+    int *nbr_cov;        // the same lists, largest cap cut from S_i first
     int *circ_any;       // [n] circles on S_i (either owner)
     uint32_t *aflag;     // [n]
 

@@ -20,6 +20,7 @@ hipError_t launch_cell_scatter(const Mol &m, const int *cell_id, int *fill, int 
                                hipStream_t st);
 hipError_t launch_cell_sort_gather(const Mol &m, int *slot_orig, hipStream_t st);
 hipError_t launch_nbr(const Mol &m, bool fill, int *nbr_cnt, int *circ_cnt, hipStream_t st);
+hipError_t launch_nbr_sort(const Mol &m, hipStream_t st);
 hipError_t launch_vertex(const Mol &m, bool fill, int *vcnt, hipStream_t st);
 hipError_t launch_circle_free(const Mol &m, hipStream_t st);
 hipError_t launch_atom_features(const Mol &m, int *face_cnt, hipStream_t st);
@@ -48,9 +49,11 @@ hipError_t launch_edge_detect_count(const uint8_t *L, const Mol &m, int *bcount,
                                     hipStream_t st);
 hipError_t launch_edge_detect_write(const uint8_t *L, const Mol &m, const long long *boff,
                                     long long cap, long long *keys, hipStream_t st);
+hipError_t launch_edge_group(const Mol &m, const long long *keys, long long count, int *tcount,
+                             int *tfill, int *order, int *tmp, hipStream_t st);
 hipError_t launch_edge_roots(const Mol &m, const uint8_t *L, const long long *keys,
                              long long count, double *lam, double *nrm, uint8_t *ptype,
-                             int *patoms, int *overflow, hipStream_t st);
+                             int *patoms, int *overflow, const int *order, hipStream_t st);
 
 // vertex export
 hipError_t launch_export_vertices(const Mol &m, double *p, int *atoms, int8_t *sign,
