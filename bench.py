@@ -39,6 +39,21 @@ PEAK_FP64_TFLOPS = 78.6
 FLOPS_PER_TEST = {"tests_atom": 11, "tests_vertex": 8, "tests_face": 11, "tests_face_cut": 6,
                   "tests_circle": 21, "tests_circle_cut": 6}
 
+# FP64 flops of the edge-root kernel's work items (from its statistics pass):
+#   sphere reach (van der Waals or probe): mid - c (3), |.|^2 (5), bounds (4)   = 12
+#   torus reach: mid - o (3), t (5), |.|^2 (5), b (3), (b-R)^2 + t^2 (4),
+#                bounds (3)                                                   = 23
+#   quadratic: coefficients (9), discriminant (3), sqrt, two roots (5)        = 18
+#   quartic set-up: |w|^2, t, a/b coefficients, g coefficients                 = 35
+#   half-space test of a root: dot (5), |.| tau (1)                           = 6
+#   per edge: coordinates, normal and its norm                                = 30
+# plus the solver's polynomial evaluations (counted in flops) and the label
+# evaluations between roots (classification constants above).
+FLOPS_EDGE = {"reach_sphere": 12, "reach_torus": 23, "quad_solves": 18, "quartic_solves": 35,
+              "horner_flops": 1, "cut_tests": 6, "n_edges": 30,
+              "label_tests_atom": 11, "label_tests_vertex": 8, "label_tests_face": 11,
+              "label_tests_face_cut": 6, "label_tests_circle": 21, "label_tests_circle_cut": 6}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -110,6 +125,16 @@ def cpu_baseline(m, n_crossings, target_s):
     }
 
 
+def load_workload(name):
+    from eses_inputs import workload, batch
+    if name.startswith("batch"):
+        # batch<count>_h<spacing>
+        count = int(name[5:].split("_")[0])
+        h = float(name.split("_h")[1])
+        return batch(count, h)
+    return [workload(name)]
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -119,60 +144,69 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
-    from eses_inputs import workload
     from paper_1809_04352_amd import eses
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     eses.load()
     prec = eses.ESES_FP64 if args.prec == "fp64" else eses.ESES_FP32_RECHECK
-    m = workload(args.workload)
+    mols_np = load_workload(args.workload)
     dev = torch.device("cuda:0")
-    ct = torch.as_tensor(m.centres, device=dev)
-    rt = torch.as_tensor(m.radii, device=dev)
-    mol = eses.make_molecule(ct, rt, m.probe, m.spacing, m.lo, m.hi)
-    dims = eses.grid_dims(mol)
-    npts = dims[0] * dims[1] * dims[2]
-    labels = torch.empty(npts, dtype=torch.uint8, device=dev)
+    tens = [(torch.as_tensor(m.centres, device=dev), torch.as_tensor(m.radii, device=dev))
+            for m in mols_np]
+    mols = [eses.make_molecule(c, r, m.probe, m.spacing, m.lo, m.hi)
+            for (c, r), m in zip(tens, mols_np)]
+    dims = [eses.grid_dims(m) for m in mols]
+    npts = sum(d[0] * d[1] * d[2] for d in dims)
+    labels = [torch.empty(d[0] * d[1] * d[2], dtype=torch.uint8, device=dev) for d in dims]
 
-    # sizing pass (outside the timed region): output capacity and work counts
-    cand = eses.build_candidates([mol])
-    info = cand.info(0)
-    work = eses.classify(cand, prec, [labels], stats=True)[0]
-    probe_out = eses.alloc_isect(1)
-    _, counts = eses.edge_intersections(cand, [labels], [probe_out])
+    # sizing pass (outside the timed region): output capacities and work counts
+    cand = eses.build_candidates(mols)
+    infos = [cand.info(q) for q in range(len(mols))]
+    work = eses.classify(cand, prec, labels, stats=True)
+    probe_out = [eses.alloc_isect(1) for _ in mols]
+    _, counts = eses.edge_intersections(cand, labels, probe_out)
+    ework = eses.edge_work(cand, labels)
     cand.close()
-    out = eses.alloc_isect(counts[0])
-    n_cross = counts[0]
-    flops_classify = sum(FLOPS_PER_TEST[k] * work[k] for k in FLOPS_PER_TEST)
+    outs = [eses.alloc_isect(max(k, 1)) for k in counts]
+    n_cross = sum(counts)
+
+    def total(dicts, key):
+        return sum(d[key] for d in dicts)
+
+    flops_classify = sum(FLOPS_PER_TEST[k] * total(work, k) for k in FLOPS_PER_TEST)
+    flops_edges = sum(FLOPS_EDGE[k] * total(ework, k) for k in FLOPS_EDGE)
 
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     stage = {"build": [], "classify": [], "edges": []}
+    kern = {"classify_ms": [], "edge_detect_ms": [], "edge_roots_ms": []}
 
     def step(record):
         if record:
             ev[0].record(stream)
-        c = eses.build_candidates([mol])
+        c = eses.build_candidates(mols)
         if record:
             ev[1].record(stream)
-        eses.classify(c, prec, [labels])
+        eses.classify(c, prec, labels)
         if record:
             ev[2].record(stream)
-        st, cnt = eses.edge_intersections(c, [labels], [out])
+        st, cnt = eses.edge_intersections(c, labels, outs)
         if record:
             ev[3].record(stream)
+            kt = eses.kernel_times(c)
         c.close()
-        if st != eses.ESES_OK or cnt[0] != n_cross:
+        if st != eses.ESES_OK or sum(cnt) != n_cross:
             raise RuntimeError("unexpected edge count")
         if record:
             torch.cuda.synchronize()
             stage["build"].append(ev[0].elapsed_time(ev[1]))
             stage["classify"].append(ev[1].elapsed_time(ev[2]))
             stage["edges"].append(ev[2].elapsed_time(ev[3]))
+            for k in kern:
+                kern[k].append(kt[k])
 
     for _ in range(args.warmup):
-        step(True)
-    stage = {k: [] for k in stage}
+        step(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -180,14 +214,34 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = 1e3 * wall / args.steps
-    # per-stage event timing in separate steps (the synchronising reads of
-    # the timed loop are not disturbed)
+    # per-stage and per-kernel HIP-event timing in separate steps, so the
+    # event reads do not disturb the timed loop
+    eses.set_timing(True)
     for _ in range(max(3, min(args.steps, 10))):
         step(True)
+    eses.set_timing(False)
     med = {k: float(np.median(v)) for k, v in stage.items()}
+    kmed = {k: float(np.median(v)) for k, v in kern.items()}
 
-    t_cls = med["classify"] * 1e-3
-    achieved = flops_classify / t_cls / 1e12
+    rl = {}
+    for name, fl, t in (("classify", flops_classify, kmed["classify_ms"]),
+                        ("edge_roots", flops_edges, kmed["edge_roots_ms"])):
+        a = fl / (t * 1e-3) / 1e12
+        rl[name] = {"kernel": "k_classify" if name == "classify" else "k_edge_roots",
+                    "bound": "alu", "achieved": a, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                    "frac": a / PEAK_FP64_TFLOPS, "traffic": None, "algorithmic_flops": fl,
+                    "ms": t}
+    for v in rl.values():
+        v["traffic"] = profiled_traffic(v["kernel"], args.workload, args.prec)
+    dominant = max(rl, key=lambda k: rl[k]["ms"])
+    roof = dict(rl[dominant])
+    single = len(mols_np) == 1
+    m0 = mols_np[0]
+    config = {"workload": args.workload, "molecules": len(mols_np),
+              "atoms": sum(m.n_atoms for m in mols_np), "probe": m0.probe,
+              "spacing": m0.spacing, "points": npts, "precision": args.prec, "tile": 8}
+    if single:
+        config["dims"] = list(dims[0])
     res = {
         "metric": METRIC,
         "value": npts / (ms * 1e-3),
@@ -201,27 +255,20 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.prec == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "atoms": m.n_atoms, "probe": m.probe,
-                   "spacing": m.spacing, "dims": list(dims), "points": npts,
-                   "precision": args.prec, "tile": 8},
-        "classify_pts_per_s": npts / t_cls,
+        "config": config,
+        "classify_pts_per_s": npts / (kmed["classify_ms"] * 1e-3),
         "isect_per_s": n_cross / (med["edges"] * 1e-3),
         "crossings": n_cross,
         "stages_ms": med,
-        "candidates": {k: (list(v) if isinstance(v, tuple) else v) for k, v in info.items()},
-        "classify_work": work,
-        "roofline": {
-            "kernel": "k_classify_fp64",
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": PEAK_FP64_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_TFLOPS,
-            "traffic": None,
-            "algorithmic_flops": flops_classify,
-            "flops_per_point": flops_classify / npts,
-        },
+        "kernels_ms": kmed,
+        "classify_work": {k: total(work, k) for k in work[0]},
+        "edge_work": {k: total(ework, k) for k in ework[0]},
+        "roofline": roof,
+        "roofline_other": {k: v for k, v in rl.items() if k != dominant},
     }
+    if single:
+        res["candidates"] = {k: (list(v) if isinstance(v, tuple) else v)
+                             for k, v in infos[0].items()}
     if args.calibrate_copy > 0:
         nbytes = args.calibrate_copy << 20
         src = torch.ones(nbytes, dtype=torch.uint8, device=dev)
@@ -230,9 +277,42 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         res["calibrate_copy_bytes"] = nbytes
-    if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(m, n_cross, args.cpu_seconds)
+    if not args.no_cpu_baseline and single:
+        res["cpu_baseline"] = cpu_baseline(m0, n_cross, args.cpu_seconds)
     print(json.dumps(res))
+
+
+def kernel_sources_digest(kernel):
+    """Digest of the sources a kernel is built from (to match a profile)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1809_04352_amd", "csrc")
+    files = ["eses_device.h", "eses_internal.h",
+             "classify.hip" if kernel == "k_classify" else "edges.hip"]
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel, workload, prec):
+    """HBM bytes per launch from a committed PMC summary of this exact kernel
+    source (profiles/pmc_<kernel>_<workload>_<prec>.md), else None."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}_{prec}.md")
+    if not os.path.exists(path):
+        return None
+    digest = kernel_sources_digest(kernel)
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("sources digest") != digest:
+        return None
+    try:
+        return float(vals["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 if __name__ == "__main__":

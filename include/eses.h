@@ -190,6 +190,39 @@ eses_status eses_classify(eses_candidates *c, eses_precision prec, uint8_t *cons
 eses_status eses_edge_intersections(eses_candidates *c, const uint8_t *const *labels,
                                     const eses_isect_soa *out, int64_t *counts, void *stream);
 
+/* Work of the edge-root kernel for molecule-by-molecule statistics, counted
+ * by a separate pass (not timed) over the same crossing edges. */
+typedef struct {
+    int64_t n_edges;          /* crossing edges */
+    int64_t reach_sphere;     /* reach tests of van der Waals and probe spheres */
+    int64_t reach_torus;      /* reach tests of tori */
+    int64_t quad_solves;      /* sphere quadratics solved */
+    int64_t quartic_solves;   /* torus quartics set up */
+    int64_t horner_flops;     /* flops of polynomial evaluations in the quartic solver */
+    int64_t cut_tests;        /* admissibility half-space tests of roots */
+    int64_t label_evals;      /* labels evaluated between roots */
+    int64_t label_tests[6];   /* their tests: atom, probe, face, face cut, circle, circle cut */
+} eses_edge_stats;
+
+/* Runs the edge statistics pass for every molecule of `c` with the labels
+ * of eses_classify.  stats: host [n_mols].  Synchronises. */
+eses_status eses_edge_work(eses_candidates *c, const uint8_t *const *labels,
+                           eses_edge_stats *stats, void *stream);
+
+/* Kernel timing for diagnostics.  While enabled (process-wide), the library
+ * records HIP events on the caller's stream around its classification kernel
+ * and its edge kernels; eses_get_kernel_times returns the last durations of a
+ * handle (waiting for the events).  Times of several molecules are summed. */
+typedef struct {
+    double classify_ms;       /* classification launch of the last eses_classify */
+    double edge_detect_ms;    /* crossing-edge pass and grouping of the last
+                                 eses_edge_intersections */
+    double edge_roots_ms;     /* root kernel of the last eses_edge_intersections */
+} eses_kernel_times;
+
+void eses_set_timing(int enable);
+eses_status eses_get_kernel_times(const eses_candidates *c, eses_kernel_times *out);
+
 /* Releases the handle and its device workspace.  Call after the work queued
  * with it has finished.  NULL is ignored. */
 void eses_free_candidates(eses_candidates *c);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -21,6 +22,7 @@ using namespace eses;
 namespace {
 
 thread_local std::string g_err;
+std::atomic<int> g_timing{0};
 
 void set_err(const char *fmt, ...) {
     char buf[512];
@@ -104,6 +106,10 @@ struct eses_candidates {
     // recorded fused classification, per precision
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
+    // kernel timing (eses_set_timing)
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    bool cls_timed = false;
+    double detect_ms = 0.0, roots_ms = 0.0;
 };
 
 namespace {
@@ -365,6 +371,12 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, MolS
     return ESES_OK;
 }
 
+eses_status ensure_events(eses_candidates *c) {
+    for (int q = 0; q < 6; ++q)
+        if (!c->ev[q]) CK(hipEventCreate(&c->ev[q]));
+    return ESES_OK;
+}
+
 // Device copies of the molecules' views and the heaviest-first list of
 // (molecule, tile) units for the fused classification launch.
 eses_status build_batch(eses_candidates *c, hipStream_t st) {
@@ -588,10 +600,19 @@ eses_status eses_classify(eses_candidates *c, eses_precision prec, uint8_t *cons
         }
     if (stats)
         for (size_t q = 0; q < c->mols.size(); ++q) CK(fill_i32(c->mols[q]->m.diag + 1, 1, 0, st));
+    const bool timed = g_timing.load() != 0;
+    if (timed) {
+        CKS(ensure_events(c));
+        CK(hipEventRecord(c->ev[0], st));
+    }
     if (c->mols.size() > 1) {
         CKS(classify_batch(c, prec == ESES_FP32_RECHECK, labels, st));
     } else {
         CK(launch_classify(c->mols[0]->m, prec == ESES_FP32_RECHECK, labels[0], st));
+    }
+    if (timed) {
+        CK(hipEventRecord(c->ev[1], st));
+        c->cls_timed = true;
     }
     if (stats) {
         const size_t nm = c->mols.size();
@@ -637,6 +658,9 @@ eses_status eses_edge_intersections(eses_candidates *c, const uint8_t *const *la
     }
     hipStream_t st = (hipStream_t)stream;
     bool short_cap = false;
+    const bool timed = g_timing.load() != 0;
+    if (timed) CKS(ensure_events(c));
+    c->detect_ms = c->roots_ms = 0.0;
     for (size_t q = 0; q < c->mols.size(); ++q) {
         const Mol &m = c->mols[q]->m;
         const eses_isect_soa &o = out[q];
@@ -659,7 +683,8 @@ eses_status eses_edge_intersections(eses_candidates *c, const uint8_t *const *la
             return s;
         }
         long long nblk = 0;
-        hipError_t e = launch_edge_detect_count(labels[q], m, bcount, &nblk, st);
+        hipError_t e = timed ? hipEventRecord(c->ev[2], st) : hipSuccess;
+        if (e == hipSuccess) e = launch_edge_detect_count(labels[q], m, bcount, &nblk, st);
         if (e == hipSuccess) e = scan_i64(bcount, nblk, boff, tmp, st);
         long long total = 0;
         if (e == hipSuccess) e = hipMemcpyAsync(&total, boff + nblk, sizeof(long long), hipMemcpyDeviceToHost, st);
@@ -679,12 +704,22 @@ eses_status eses_edge_intersections(eses_candidates *c, const uint8_t *const *la
         if (e == hipSuccess) e = fill_i32(ovf, 1, 0, st);
         if (e == hipSuccess && nw > 0)
             e = launch_edge_group(m, (const long long *)o.key, nw, tcount, tfill, order, ttmp, st);
+        if (e == hipSuccess && timed) e = hipEventRecord(c->ev[3], st);
+        if (e == hipSuccess && timed) e = hipEventRecord(c->ev[4], st);
         if (e == hipSuccess && nw > 0)
             e = launch_edge_roots(m, labels[q], (const long long *)o.key, nw, o.lambda, o.normal, o.patch_type,
                                   o.atoms, ovf, order, st);
+        if (e == hipSuccess && timed) e = hipEventRecord(c->ev[5], st);
         int hovf = 0;
         if (e == hipSuccess) e = hipMemcpyAsync(&hovf, ovf, sizeof(int), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e == hipSuccess && timed) {
+            float a = 0.0f, b = 0.0f;
+            e = hipEventElapsedTime(&a, c->ev[2], c->ev[3]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&b, c->ev[4], c->ev[5]);
+            c->detect_ms += a;
+            c->roots_ms += b;
+        }
         T.release();
         if (e != hipSuccess) {
             set_err("edge intersections: %s", hipGetErrorString(e));
@@ -704,6 +739,95 @@ eses_status eses_edge_intersections(eses_candidates *c, const uint8_t *const *la
     return ESES_OK;
 }
 
+void eses_set_timing(int enable) { g_timing.store(enable ? 1 : 0); }
+
+eses_status eses_get_kernel_times(const eses_candidates *c, eses_kernel_times *out) {
+    g_err.clear();
+    if (!c || !out) {
+        set_err("bad argument");
+        return ESES_EINVAL;
+    }
+    out->classify_ms = 0.0;
+    if (c->cls_timed) {
+        float a = 0.0f;
+        CK(hipEventSynchronize(c->ev[1]));
+        CK(hipEventElapsedTime(&a, c->ev[0], c->ev[1]));
+        out->classify_ms = a;
+    }
+    out->edge_detect_ms = c->detect_ms;
+    out->edge_roots_ms = c->roots_ms;
+    return ESES_OK;
+}
+
+eses_status eses_edge_work(eses_candidates *c, const uint8_t *const *labels,
+                           eses_edge_stats *stats, void *stream) {
+    g_err.clear();
+    if (!c || !labels || !stats) {
+        set_err("bad argument");
+        return ESES_EINVAL;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    for (size_t q = 0; q < c->mols.size(); ++q) {
+        const Mol &m = c->mols[q]->m;
+        if (!labels[q]) {
+            set_err("labels[%zu] is NULL", q);
+            return ESES_EINVAL;
+        }
+        Arena T;
+        T.st = st;
+        long long nb = (m.npts + 255) / 256;
+        int *bcount, *ovf;
+        long long *boff, *tmp;
+        unsigned long long *work;
+        eses_status s;
+        if ((s = T.alloc(&bcount, nb + 1)) != ESES_OK || (s = T.alloc(&boff, nb + 2)) != ESES_OK ||
+            (s = T.alloc(&tmp, scan_tmp_elems(nb) + 64)) != ESES_OK ||
+            (s = T.alloc(&ovf, 1)) != ESES_OK || (s = T.alloc(&work, EDGE_WORK_COUNTERS)) != ESES_OK) {
+            T.release();
+            return s;
+        }
+        long long nblk = 0, total = 0;
+        hipError_t e = launch_edge_detect_count(labels[q], m, bcount, &nblk, st);
+        if (e == hipSuccess) e = scan_i64(bcount, nblk, boff, tmp, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&total, boff + nblk, sizeof(long long), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        long long *keys = nullptr;
+        int *tcount = nullptr, *tfill = nullptr, *order = nullptr, *ttmp = nullptr;
+        if (e == hipSuccess && total > 0) {
+            if ((s = T.alloc(&keys, total)) != ESES_OK || (s = T.alloc(&tcount, m.ntiles + 1)) != ESES_OK ||
+                (s = T.alloc(&tfill, m.ntiles + 1)) != ESES_OK || (s = T.alloc(&order, total)) != ESES_OK ||
+                (s = T.alloc(&ttmp, scan_tmp_elems(m.ntiles) + 64)) != ESES_OK) {
+                T.release();
+                return s;
+            }
+        }
+        if (e == hipSuccess) e = fill_u32((uint32_t *)work, 2 * EDGE_WORK_COUNTERS, 0u, st);
+        if (e == hipSuccess) e = fill_i32(ovf, 1, 0, st);
+        if (e == hipSuccess && total > 0) e = launch_edge_detect_write(labels[q], m, boff, total, keys, st);
+        if (e == hipSuccess && total > 0) e = launch_edge_group(m, keys, total, tcount, tfill, order, ttmp, st);
+        if (e == hipSuccess && total > 0) e = launch_edge_work(m, labels[q], keys, total, order, ovf, work, st);
+        unsigned long long h[EDGE_WORK_COUNTERS] = {0};
+        if (e == hipSuccess) e = hipMemcpyAsync(h, work, sizeof(h), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        T.release();
+        if (e != hipSuccess) {
+            set_err("edge statistics: %s", hipGetErrorString(e));
+            return ESES_EDEVICE;
+        }
+        eses_edge_stats &o = stats[q];
+        o.n_edges = (int64_t)h[0];
+        o.reach_sphere = (int64_t)h[1];
+        o.reach_torus = (int64_t)h[2];
+        o.quad_solves = (int64_t)h[3];
+        o.quartic_solves = (int64_t)h[4];
+        o.horner_flops = (int64_t)h[5];
+        o.cut_tests = (int64_t)h[6];
+        o.label_evals = (int64_t)h[7];
+        for (int k = 0; k < 6; ++k) o.label_tests[k] = (int64_t)h[8 + k];
+    }
+    return ESES_OK;
+}
+
 void eses_free_candidates(eses_candidates *c) {
     if (!c) return;
     for (int k = 0; k < 2; ++k) {
@@ -711,6 +835,8 @@ void eses_free_candidates(eses_candidates *c) {
         if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
     }
     c->batch.release();
+    for (int q = 0; q < 6; ++q)
+        if (c->ev[q]) (void)hipEventDestroy(c->ev[q]);
     for (MolState *S : c->mols) {
         S->arena.release();
         S->scratch.release();

@@ -17,6 +17,25 @@ namespace eses {
 
 constexpr int EDGE_BLOCK = 256;
 
+// Work counters of the statistics pass of the root kernel.
+enum EdgeCounter {
+    EC_EDGES = 0,
+    EC_REACH_SPHERE,   // reach tests of van der Waals and probe spheres
+    EC_REACH_TORUS,    // reach tests of tori
+    EC_QUAD,           // sphere quadratics solved
+    EC_QUARTIC,        // torus quartics set up
+    EC_HORNER_FLOPS,   // flops of polynomial evaluations in the quartic solver
+    EC_CUT,            // admissibility half-space tests of roots
+    EC_LABEL,          // interval labels evaluated
+    EC_L_ATOM,         // the label evaluations' tests (as in classification)
+    EC_L_VERTEX,
+    EC_L_FACE,
+    EC_L_FACE_CUT,
+    EC_L_CIRCLE,
+    EC_L_CIRCLE_CUT,
+    EC_COUNT
+};
+
 __device__ inline int edge_flags(const uint8_t *L, long long idx, int i, int j, int k, int nx,
                                  int ny, int nz) {
     uint8_t a = L[idx];
@@ -78,11 +97,14 @@ __device__ inline double horner(const double *c, int deg, double u) {
 // Root of the polynomial c (degree deg) in [lo, hi] where its values at the
 // ends have opposite signs: Newton steps kept inside a shrinking bracket,
 // bisection when a step leaves it.
-__device__ double bracket_root(const double *c, int deg, double lo, double hi, double flo) {
+template <bool CNT>
+__device__ double bracket_root(const double *c, int deg, double lo, double hi, double flo,
+                               unsigned long long *cnt) {
     double d[4];
     for (int q = 1; q <= deg; ++q) d[q - 1] = q * c[q];
     double x = 0.5 * (lo + hi);
     for (int it = 0; it < 128; ++it) {
+        if (CNT) cnt[EC_HORNER_FLOPS] += 4 * deg + 4;  // f, f' and the step
         double f = horner(c, deg, x);
         if (f == 0.0) return x;
         if ((f < 0.0) == (flo < 0.0)) lo = x;
@@ -110,98 +132,101 @@ __device__ inline int quad01(double a, double b, double c, double *r) {
     return n;
 }
 
-// Real roots in [0, 1] of the quartic g (ascending coefficients): the roots
-// of g'' split [0, 1] into intervals where g' is monotone, the roots of g'
-// found there split it into intervals where g is monotone, and each sign
-// change of g on those is refined by bracket_root.
-__device__ int quartic01(const double *g, double *out) {
-    double br[4];
-    int nb = 0;
-    br[nb++] = 0.0;
+// Real roots in [0, 1] of the quartic g (ascending coefficients), passed to
+// emit in increasing order: the roots of g'' split [0, 1] into intervals
+// where g' is monotone, the root of g' found in each splits it further into
+// intervals where g is monotone, and each sign change of g on those is
+// refined by bracket_root.  Both stages run in one loop, without lists, so
+// that each refinement is a single call site.
+template <bool CNT, class Emit>
+__device__ void quartic01(const double *g, Emit emit, unsigned long long *cnt) {
+    // interior roots of g'' (sorted), 1.0 standing in for a missing one
+    double x1 = 1.0, x2 = 1.0;
     {
         double a = 12.0 * g[4], b = 6.0 * g[3], c = 2.0 * g[2];
-        double r[2];
-        int n = 0;
+        double r0 = 2.0, r1 = 2.0;
         if (a != 0.0) {
             double disc = b * b - 4.0 * a * c;
             if (disc > 0.0) {
                 double sd = sqrt(disc);
                 double q = -0.5 * (b + copysign(sd, b));
-                r[n++] = q / a;
-                if (q != 0.0) r[n++] = c / q;
+                r0 = q / a;
+                if (q != 0.0) r1 = c / q;
             }
         } else if (b != 0.0) {
-            r[n++] = -c / b;
+            r0 = -c / b;
         }
-        if (n == 2 && r[1] < r[0]) {
-            double t = r[0];
-            r[0] = r[1];
-            r[1] = t;
+        bool in0 = r0 > 0.0 && r0 < 1.0, in1 = r1 > 0.0 && r1 < 1.0;
+        if (in0 && in1) {
+            x1 = fmin(r0, r1);
+            x2 = fmax(r0, r1);
+        } else if (in0) {
+            x1 = r0;
+        } else if (in1) {
+            x1 = r1;
         }
-        for (int q = 0; q < n; ++q)
-            if (r[q] > 0.0 && r[q] < 1.0) br[nb++] = r[q];
     }
-    br[nb++] = 1.0;
-    double d1[4] = {g[1], 2.0 * g[2], 3.0 * g[3], 4.0 * g[4]};
-    double cp[6];
-    int ncp = 0;
-    cp[ncp++] = 0.0;
-    for (int q = 0; q + 1 < nb; ++q) {
-        double a = br[q], b = br[q + 1];
-        if (!(b > a)) continue;
-        double fa = horner(d1, 3, a), fb = horner(d1, 3, b);
-        if (fa == 0.0 && a > 0.0) cp[ncp++] = a;
-        else if (fa != 0.0 && fb != 0.0 && ((fa < 0.0) != (fb < 0.0)))
-            cp[ncp++] = bracket_root(d1, 3, a, b, fa);
-    }
-    cp[ncp++] = 1.0;
+    const double d1[4] = {g[1], 2.0 * g[2], 3.0 * g[3], 4.0 * g[4]};
     // An interior critical point where g vanishes to within rounding is a
     // root of even multiplicity: a line through the self-intersection of a
     // spindle torus on its axis, where the quartic is a perfect square.
     const double tol =
         1e-12 * (fabs(g[0]) + fabs(g[1]) + fabs(g[2]) + fabs(g[3]) + fabs(g[4]));
-    int nr = 0;
-    double f0 = horner(g, 4, 0.0);
-    if (f0 == 0.0) out[nr++] = 0.0;
-    for (int q = 0; q + 1 < ncp; ++q) {
-        double a = cp[q], b = cp[q + 1];
-        if (!(b > a)) continue;
-        double fa = horner(g, 4, a), fb = horner(g, 4, b);
-        if (fb == 0.0) out[nr++] = b;
-        else if (fa != 0.0 && ((fa < 0.0) != (fb < 0.0))) out[nr++] = bracket_root(g, 4, a, b, fa);
-        if (q + 2 < ncp && fb != 0.0 && fabs(fb) <= tol) out[nr++] = b;
+    double ca = 0.0;                 // last critical point of g (or 0)
+    double fca = horner(g, 4, 0.0);  // g there
+    if (fca == 0.0) emit(0.0);
+#pragma unroll 1
+    for (int q = 0; q < 4; ++q) {
+        // next critical point of g from the g' interval q; q == 3: the end 1
+        double cp = 1.0;
+        bool have = true, interior = q < 3;
+        if (interior) {
+            double a = q == 0 ? 0.0 : q == 1 ? x1 : x2;
+            double b = q == 0 ? x1 : q == 1 ? x2 : 1.0;
+            have = false;
+            if (b > a) {
+                double fa = horner(d1, 3, a), fb = horner(d1, 3, b);
+                if (CNT) cnt[EC_HORNER_FLOPS] += 12;
+                if (fa == 0.0 && a > 0.0) {
+                    cp = a;
+                    have = true;
+                } else if (fa != 0.0 && fb != 0.0 && ((fa < 0.0) != (fb < 0.0))) {
+                    cp = bracket_root<CNT>(d1, 3, a, b, fa, cnt);
+                    have = true;
+                }
+            }
+        }
+        if (!have || !(cp > ca)) continue;
+        double fb = horner(g, 4, cp);
+        if (CNT) cnt[EC_HORNER_FLOPS] += 16;
+        if (fb == 0.0) emit(cp);
+        else if (fca != 0.0 && ((fca < 0.0) != (fb < 0.0)))
+            emit(bracket_root<CNT>(g, 4, ca, cp, fca, cnt));
+        if (interior && fb != 0.0 && fabs(fb) <= tol) emit(cp);
+        ca = cp;
+        fca = fb;
     }
-    return nr;
 }
 
-constexpr int MAXR = 12;   // roots per page of the walk
-
-// Sorted insertion by (u, type, id) keeping the MAXR smallest roots; a root
-// that does not fit marks the list truncated.
-__device__ inline void push_root(double *ru, int *rt, int &nr, bool &truncated, double u, int type,
-                                 int id) {
-    int key = (type << 28) | id;
-    if (nr == MAXR) {
-        truncated = true;
-        if (ru[MAXR - 1] < u || (ru[MAXR - 1] == u && rt[MAXR - 1] <= key)) return;
-        --nr;
-    }
-    int p = nr++;
-    while (p > 0 && (ru[p - 1] > u || (ru[p - 1] == u && rt[p - 1] > key))) {
-        ru[p] = ru[p - 1];
-        rt[p] = rt[p - 1];
-        --p;
-    }
-    ru[p] = u;
-    rt[p] = key;
-}
+// ------------------------------------------------ roots, one wavefront per edge
+//
+// One wavefront per crossing edge.  Lanes gather the surfaces that reach the
+// edge (distance from the edge's midpoint within h/2 of the surface: distance
+// to a set is 1-Lipschitz), each lane solves one surface, the roots are
+// rank-sorted across lanes in LDS, and the labels of the intervals between
+// roots are evaluated cooperatively (lanes split the atoms and candidate
+// features, ballots combine).  The walk from s stops at the first interval
+// whose label differs from Inside[s]; its start is u*, lambda = 1 - u*.
 
 // A point y of the sphere S_i seen from x along c_i -> x is admissible iff
 // (x - c_i) . v_k <= |x - c_i| tau_k for every cut of the face.
-__device__ inline bool face_admissible(const Mol &m, int f, double dx, double dy, double dz) {
+template <bool CNT>
+__device__ inline bool face_admissible(const Mol &m, int f, double dx, double dy, double dz,
+                                       unsigned long long *cnt) {
     double d = sqrt(dx * dx + dy * dy + dz * dz);
     for (int c = m.face_cut_off[f], ce = m.face_cut_off[f + 1]; c < ce; ++c) {
         double4 v = m.face_cut[c];
+        if (CNT) ++cnt[EC_CUT];
         if (dx * v.x + dy * v.y + dz * v.z > d * v.w) return false;
     }
     return true;
@@ -209,8 +234,9 @@ __device__ inline bool face_admissible(const Mol &m, int f, double dx, double dy
 
 // The circle point nearest to x (w = x - o) is admissible iff
 // w_perp . u_k <= |w_perp| T_k for every cut of the circle.
+template <bool CNT>
 __device__ inline bool circle_admissible(const Mol &m, int ec, double4 n, double wx, double wy,
-                                         double wz) {
+                                         double wz, unsigned long long *cnt) {
     double t = wx * n.x + wy * n.y + wz * n.z;
     double px = wx - t * n.x, py = wy - t * n.y, pz = wz - t * n.z;
     double b = sqrt(px * px + py * py + pz * pz);
@@ -220,6 +246,7 @@ __device__ inline bool circle_admissible(const Mol &m, int ec, double4 n, double
     }
     for (int c = m.ec_cut_off[ec], ce = m.ec_cut_off[ec + 1]; c < ce; ++c) {
         double4 u = m.ec_cut[c];
+        if (CNT) ++cnt[EC_CUT];
         if (px * u.x + py * u.y + pz * u.z > b * u.w) return false;
     }
     return true;
@@ -232,19 +259,12 @@ __device__ inline void sort3(int &a, int &b, int &c) {
     if (a > b) { t = a; a = b; b = t; }
 }
 
-// Surfaces whose distance from the edge's midpoint is within h/2 of zero
-// (distance to a set is 1-Lipschitz, so only these can cross the edge) are
-// first gathered per lane, so the solves below run over each lane's own short
-// list instead of every lane waiting on every other lane's solves.
-constexpr int EDGE_THREADS = 256;
-constexpr int MAXS = 32;  // surfaces listed per edge; more are solved in place
-
-struct EdgeSurf {
-    int n;
-    bool more;  // more than MAXS surfaces: the lists are scanned again
-};
-
-__device__ inline int surf_slot(int q) { return q * EDGE_THREADS + (int)threadIdx.x; }
+// Visibility of LDS writes of a wavefront to its other lanes.
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __device__ inline bool face_reaches(const Mol &m, int f, const double *mid, double half) {
     double4 a = m.atom[m.face_atom[f]];
@@ -269,216 +289,392 @@ __device__ inline bool torus_reaches(const Mol &m, int ec, const double *mid, do
     return !(dc2 > sq(m.rho + half) || (m.rho > half && dc2 < sq(m.rho - half)));
 }
 
-// Roots u > lower (in [0, 1]) of one surface (type 1 face atom f, 3 probe v,
-// 2 exposed circle ec), kept only if the point of A that would put the root
-// on the boundary is admissible: the radial projection onto the exposed face
-// (van der Waals roots) or the nearest point of the exposed circle (torus
-// roots).  Every label change lies on such a point, so dropping the others
-// is exact.
-__device__ void surface_roots(const Mol &m, int type, int id, int axis,
-                                          const double *xs,
-                              double lower, double *ru, int *rt, int &nr, bool &truncated) {
+constexpr int EW_WAVES = 4;      // edges (wavefronts) per workgroup
+constexpr int EW_THREADS = EW_WAVES * WAVE;
+constexpr int EW_SURF = 128;     // reaching surfaces kept per edge
+constexpr int EW_ROOTS = 128;    // roots kept per edge
+
+struct EdgeWaveLds {
+    int surf[EW_SURF];
+    double u[EW_ROOTS];
+    int k[EW_ROOTS];
+    double su[EW_ROOTS];
+    int sk[EW_ROOTS];
+    int nroot;
+};
+
+// Appends a root (position u along the edge, owner key) to the wavefront's
+// list; the order of appends is irrelevant (the list is rank-sorted).
+__device__ inline void push_root(EdgeWaveLds &S, double u, int key) {
+    int pos = atomicAdd(&S.nroot, 1);
+    if (pos < EW_ROOTS) {
+        S.u[pos] = u;
+        S.k[pos] = key;
+    }
+}
+
+// Roots in [0, 1] of one surface (type 1 face f, 3 probe v, 2 exposed circle
+// ec) along the edge x(u) = xs + u h e, appended to the wavefront's list with
+// the key (type << 28) | id.
+template <bool CNT>
+__device__ void surface_roots(const Mol &m, int key, const double *e, const double *xs,
+                              EdgeWaveLds &S, unsigned long long *cnt) {
     const double h = m.h, rho = m.rho;
-    double tmp[4];
-    if (type == 1) {
-        int f = id;
-        int i = m.face_atom[f];
-        double4 a = m.atom[i];
-        double w0[3] = {xs[0] - a.x, xs[1] - a.y, xs[2] - a.z};
-        int n = quad01(h * h, 2.0 * h * w0[axis],
-                       w0[0] * w0[0] + w0[1] * w0[1] + w0[2] * w0[2] - a.w * a.w, tmp);
-        for (int t = 0; t < n; ++t) {
-            if (!(tmp[t] > lower)) continue;
-            double x[3] = {w0[0], w0[1], w0[2]};
-            x[axis] += tmp[t] * h;
-            if (face_admissible(m, f, x[0], x[1], x[2]))
-                push_root(ru, rt, nr, truncated, tmp[t], 1, i);
-        }
-    } else if (type == 3) {
-        int v = id;
-        double4 c = m.vert_p[v];
+    const int type = key >> 28, id = key & ((1 << 28) - 1);
+    if (type != 2) {
+        // sphere |x(u) - c|^2 = r^2: a van der Waals face or a probe
+        double4 c = type == 1 ? m.atom[m.face_atom[id]] : m.vert_p[id];
+        double r = type == 1 ? c.w : rho;
+        if (CNT) ++cnt[EC_QUAD];
         double w0[3] = {xs[0] - c.x, xs[1] - c.y, xs[2] - c.z};
-        int n = quad01(h * h, 2.0 * h * w0[axis],
-                       w0[0] * w0[0] + w0[1] * w0[1] + w0[2] * w0[2] - rho * rho, tmp);
-        for (int t = 0; t < n; ++t)
-            if (tmp[t] > lower) push_root(ru, rt, nr, truncated, tmp[t], 3, v);
-    } else {
-        // torus (|w|^2 + R^2 - rho^2)^2 = 4 R^2 |w_perp|^2, the branch at
-        // distance rho from the near circle point
-        int ec = id;
-        int ci = m.ec_circ[ec];
-        double4 oR = m.circ_oR[ci];
-        double4 nn = m.circ_n[ci];
-        double R = oR.w;
-        double w0[3] = {xs[0] - oR.x, xs[1] - oR.y, xs[2] - oR.z};
-        double nv[3] = {nn.x, nn.y, nn.z};
-        double ww = w0[0] * w0[0] + w0[1] * w0[1] + w0[2] * w0[2];
-        double t0 = w0[0] * nv[0] + w0[1] * nv[1] + w0[2] * nv[2];
-        double RR = R * R;
-        double a0 = ww + RR - rho * rho, a1 = 2.0 * h * w0[axis], a2 = h * h;
-        double b0 = ww - t0 * t0, b1 = 2.0 * h * (w0[axis] - t0 * nv[axis]),
-               b2 = h * h * (1.0 - nv[axis] * nv[axis]);
-        double g[5] = {a0 * a0 - 4.0 * RR * b0, 2.0 * a0 * a1 - 4.0 * RR * b1,
-                       a1 * a1 + 2.0 * a0 * a2 - 4.0 * RR * b2, 2.0 * a1 * a2, a2 * a2};
-        double r4[10];
-        int n = quartic01(g, r4);
-        for (int t = 0; t < n; ++t) {
-            if (!(r4[t] > lower)) continue;
-            double x[3] = {w0[0], w0[1], w0[2]};
-            x[axis] += r4[t] * h;
-            double tt = x[0] * nv[0] + x[1] * nv[1] + x[2] * nv[2];
-            double bb = sqrt(fmax(0.0, x[0] * x[0] + x[1] * x[1] + x[2] * x[2] - tt * tt));
-            double near = fabs(sq(bb - R) + tt * tt - rho * rho);
-            double far = fabs(sq(bb + R) + tt * tt - rho * rho);
-            if (near <= far && circle_admissible(m, ec, nn, x[0], x[1], x[2]))
-                push_root(ru, rt, nr, truncated, r4[t], 2, ec);
+        double we = w0[0] * e[0] + w0[1] * e[1] + w0[2] * e[2];
+        double tmp[2];
+        int n = quad01(h * h, 2.0 * h * we,
+                       w0[0] * w0[0] + w0[1] * w0[1] + w0[2] * w0[2] - r * r, tmp);
+        if (n > 0) push_root(S, tmp[0], key);
+        if (n > 1) push_root(S, tmp[1], key);
+        return;
+    }
+    // torus (|w|^2 + R^2 - rho^2)^2 = 4 R^2 |w_perp|^2 of the circle's
+    // points at distance rho; both branches (the far one is dropped later)
+    const int ci = m.ec_circ[id];
+    const double4 oR = m.circ_oR[ci];
+    const double4 nn = m.circ_n[ci];
+    const double R = oR.w;
+    const double w0[3] = {xs[0] - oR.x, xs[1] - oR.y, xs[2] - oR.z};
+    const double ww = w0[0] * w0[0] + w0[1] * w0[1] + w0[2] * w0[2];
+    const double t0 = w0[0] * nn.x + w0[1] * nn.y + w0[2] * nn.z;
+    const double we = w0[0] * e[0] + w0[1] * e[1] + w0[2] * e[2];
+    const double ne = nn.x * e[0] + nn.y * e[1] + nn.z * e[2];
+    const double RR = R * R;
+    const double a0 = ww + RR - rho * rho, a1 = 2.0 * h * we, a2 = h * h;
+    const double b0 = ww - t0 * t0, b1 = 2.0 * h * (we - t0 * ne), b2 = h * h * (1.0 - ne * ne);
+    const double g[5] = {a0 * a0 - 4.0 * RR * b0, 2.0 * a0 * a1 - 4.0 * RR * b1,
+                         a1 * a1 + 2.0 * a0 * a2 - 4.0 * RR * b2, 2.0 * a1 * a2, a2 * a2};
+    if (CNT) ++cnt[EC_QUARTIC];
+    quartic01<CNT>(g, [&](double u) { push_root(S, u, key); }, cnt);
+}
+
+// Whether a root is kept: only if the point of A that would put it on the
+// boundary is admissible, the radial projection onto the exposed face (van
+// der Waals roots) or the nearest point of the exposed circle on the near
+// branch of the torus (torus roots).  Every label change lies on such a
+// point, so dropping the others is exact.  Probe roots are always kept.
+template <bool CNT>
+__device__ bool root_admissible(const Mol &m, int key, double u, const double *e,
+                                const double *xs, unsigned long long *cnt) {
+    const int type = key >> 28, id = key & ((1 << 28) - 1);
+    if (type == 3) return true;
+    const double s = u * m.h;
+    if (type == 1) {
+        double4 a = m.atom[m.face_atom[id]];
+        return face_admissible<CNT>(m, id, xs[0] - a.x + s * e[0], xs[1] - a.y + s * e[1],
+                                    xs[2] - a.z + s * e[2], cnt);
+    }
+    const int ci = m.ec_circ[id];
+    const double4 oR = m.circ_oR[ci];
+    const double4 nn = m.circ_n[ci];
+    const double R = oR.w, rho = m.rho;
+    double x0 = xs[0] - oR.x + s * e[0], x1 = xs[1] - oR.y + s * e[1],
+           x2 = xs[2] - oR.z + s * e[2];
+    double tt = x0 * nn.x + x1 * nn.y + x2 * nn.z;
+    double bb = sqrt(fmax(0.0, x0 * x0 + x1 * x1 + x2 * x2 - tt * tt));
+    double near = fabs(sq(bb - R) + tt * tt - rho * rho);
+    double far = fabs(sq(bb + R) + tt * tt - rho * rho);
+    return near <= far && circle_admissible<CNT>(m, id, nn, x0, x1, x2, cnt);
+}
+
+// Inside/outside of x (eq. 2) evaluated by the whole wavefront: the three
+// cases of the classification with lanes splitting the tile's atoms and
+// candidate features.
+template <bool CNT>
+__device__ int label_wave(const Mol &m, int tile, double x, double y, double z,
+                          unsigned long long *cnt) {
+    const int lane = lane_id();
+    const double rho = m.rho, rho2 = rho * rho;
+    bool inU = false;
+    for (int base = m.tA_off[tile], e = m.tA_off[tile + 1]; base < e; base += WAVE) {
+        int q = base + lane;
+        bool v = false, u = false;
+        if (q < e) {
+            double4 a = m.atom[m.tA[q]];
+            double dx = x - a.x, dy = y - a.y, dz = z - a.z;
+            double d2 = dx * dx + dy * dy + dz * dz;
+            if (CNT) ++cnt[EC_L_ATOM];
+            v = d2 <= a.w * a.w;
+            u = d2 < sq(a.w + rho);
         }
+        if (__any(v)) return 1;
+        inU = inU || __any(u);
     }
-}
-
-// The edge's reaching surfaces with index in [skip, skip + MAXS), packed
-// (type << 28 | id) in LDS; `more` if there are further ones.
-__device__ EdgeSurf gather_surfaces(const Mol &m, int tile, const double *mid, int *slots,
-                                    int skip) {
-    const double half = 0.5 * m.h + 1e-9;
-    EdgeSurf es = {0, false};
-    int seen = 0;
-    for (int p = m.tF_off[tile], e = m.tF_off[tile + 1]; p < e; ++p) {
-        int f = m.tF[p];
-        if (!face_reaches(m, f, mid, half) || seen++ < skip) continue;
-        if (es.n < MAXS) slots[surf_slot(es.n++)] = (1 << 28) | f;
-        else es.more = true;
-    }
-    for (int p = m.tV_off[tile], e = m.tV_off[tile + 1]; p < e; ++p) {
-        int v = m.tV[p];
-        if (!probe_reaches(m, v, mid, half) || seen++ < skip) continue;
-        if (es.n < MAXS) slots[surf_slot(es.n++)] = (3 << 28) | v;
-        else es.more = true;
-    }
-    for (int p = m.tC_off[tile], e = m.tC_off[tile + 1]; p < e; ++p) {
-        int ec = m.tC[p];
-        if (!torus_reaches(m, ec, mid, half) || seen++ < skip) continue;
-        if (es.n < MAXS) slots[surf_slot(es.n++)] = (2 << 28) | ec;
-        else es.more = true;
-    }
-    return es;
-}
-
-// All roots u > lower of the edge's reaching surfaces (the MAXR smallest).
-// `es` describes the first window of surfaces in `slots`; further windows
-// (rare) are gathered in turn and the first one is restored at the end.
-__device__ void collect_roots(const Mol &m, int tile, int axis, const double *xs,
-                              const double *mid, int *slots, EdgeSurf es, double lower,
-                              double *ru, int *rt, int &nr, bool &truncated) {
-    nr = 0;
-    truncated = false;
-    int skip = 0;
-    for (;;) {
-        for (int q = 0; q < es.n; ++q) {
-            int s = slots[surf_slot(q)];
-            surface_roots(m, s >> 28, s & ((1 << 28) - 1), axis, xs, lower, ru, rt, nr, truncated);
+    if (!inU) return 0;
+    for (int base = m.tV_off[tile], e = m.tV_off[tile + 1]; base < e; base += WAVE) {
+        int q = base + lane;
+        bool hit = false;
+        if (q < e) {
+            double4 p = m.vert_p[m.tV[q]];
+            if (CNT) ++cnt[EC_L_VERTEX];
+            hit = sq(x - p.x) + sq(y - p.y) + sq(z - p.z) < rho2;
         }
-        if (!es.more) break;
-        skip += MAXS;
-        es = gather_surfaces(m, tile, mid, slots, skip);
+        if (__any(hit)) return 0;
     }
-    if (skip > 0) gather_surfaces(m, tile, mid, slots, 0);
-}
-
-__global__ void __launch_bounds__(EDGE_THREADS) k_edge_roots(Mol m, const uint8_t *L, const long long *keys,
-                                                    long long count, double *lam, double *nrm,
-                                                    uint8_t *ptype, int *patoms, int *overflow,
-                                                    const int *order, int nblocks) {
-    // edges grouped by tile (order), consecutive groups on one XCD
-    int blk = xcd_tile(blockIdx.x, nblocks, (int)((count + EDGE_THREADS - 1) / EDGE_THREADS));
-    if (blk < 0) return;
-    long long g = (long long)blk * EDGE_THREADS + threadIdx.x;
-    if (g >= count) return;
-    const long long q = order[g];
-    long long key = keys[q];
-    int axis = (int)(key % 3);
-    long long idx = key / 3;
-    const int nx = m.dims[0], ny = m.dims[1];
-    int ii[3] = {(int)(idx % nx), (int)((idx / nx) % ny), (int)(idx / ((long long)nx * ny))};
-    const long long stride[3] = {1, nx, (long long)nx * ny};
-    int Ls = L[idx], Lt = L[idx + stride[axis]];
-    int tile = ii[0] / m.tile + m.tdims[0] * (ii[1] / m.tile + m.tdims[1] * (ii[2] / m.tile));
-    double xs[3];
-    for (int a = 0; a < 3; ++a) xs[a] = grid_coord(m.lo[a], m.h, ii[a]);
-    const double h = m.h, rho = m.rho;
-    double mid[3] = {xs[0], xs[1], xs[2]};
-    mid[axis] += 0.5 * h;
-
-    __shared__ int slots[MAXS * EDGE_THREADS];
-    const EdgeSurf es = gather_surfaces(m, tile, mid, slots, 0);
-    double ru[MAXR];
-    int rt[MAXR];
-    int nr = 0;
-    bool truncated = false;
-
-    // Walk the intervals from s.  The label is constant between consecutive
-    // roots; the first interval has Inside[s] and the last Inside[t] unless a
-    // root sits exactly on that end.  Roots come in pages of the MAXR smallest
-    // above the last one walked; a page that ends before t is followed by the
-    // next one.
-    double ustar = 1.0;
-    double prev = 0.0;
-    int prev_key = -1, owner_key = -1;
-    bool found = false;
-    for (int page = 0; page < 64; ++page) {
-        const bool first = page == 0;
-        collect_roots(m, tile, axis, xs, mid, slots, es, first ? -1.0 : prev, ru, rt, nr,
-                      truncated);
-        bool root0 = first && nr > 0 && ru[0] == 0.0;
-        bool root1 = !truncated && nr > 0 && ru[nr - 1] == 1.0;
-        for (int r = 0; r <= nr; ++r) {
-            if (r == nr && truncated) break;
-            double next = r < nr ? ru[r] : 1.0;
-            if (next > prev) {
-                int lab;
-                if (first && prev == 0.0 && !root0) lab = Ls;
-                else if (r == nr && !root1) lab = Lt;
-                else {
-                    double x[3] = {xs[0], xs[1], xs[2]};
-                    x[axis] += 0.5 * (prev + next) * h;
-                    lab = label_fp64(m, tile, x[0], x[1], x[2]);
-                }
-                if (lab != Ls) {
-                    ustar = prev;
-                    owner_key = prev_key;
-                    found = true;
-                    break;
+    for (int base = m.tF_off[tile], e = m.tF_off[tile + 1]; base < e; base += WAVE) {
+        int q = base + lane;
+        bool hit = false;
+        if (q < e) {
+            int f = m.tF[q];
+            double4 a = m.atom[m.face_atom[f]];
+            double dx = x - a.x, dy = y - a.y, dz = z - a.z;
+            double d2 = dx * dx + dy * dy + dz * dz;
+            if (CNT) ++cnt[EC_L_FACE];
+            if (d2 < sq(a.w + 2.0 * rho)) {
+                double d = sqrt(d2);
+                hit = true;
+                for (int c = m.face_cut_off[f], ce = m.face_cut_off[f + 1]; c < ce; ++c) {
+                    double4 v = m.face_cut[c];
+                    if (CNT) ++cnt[EC_L_FACE_CUT];
+                    if (dx * v.x + dy * v.y + dz * v.z > d * v.w) {
+                        hit = false;
+                        break;
+                    }
                 }
             }
-            if (r < nr && (prev_key < 0 || next > prev)) prev_key = rt[r];
-            if (next > prev) prev = next;
         }
-        if (found || !truncated) break;
-        if (page == 63) *overflow = 1;
+        if (__any(hit)) return 0;
+    }
+    for (int base = m.tC_off[tile], e = m.tC_off[tile + 1]; base < e; base += WAVE) {
+        int q = base + lane;
+        bool hit = false;
+        if (q < e) {
+            int ec = m.tC[q];
+            int ci = m.ec_circ[ec];
+            double4 oR = m.circ_oR[ci];
+            double4 n = m.circ_n[ci];
+            double wx = x - oR.x, wy = y - oR.y, wz = z - oR.z;
+            double t = wx * n.x + wy * n.y + wz * n.z;
+            double ww = wx * wx + wy * wy + wz * wz;
+            double b = sqrt(fmax(ww - t * t, 0.0));
+            double R = oR.w;
+            if (CNT) ++cnt[EC_L_CIRCLE];
+            if (ww + R * R - rho2 < 2.0 * b * R) {
+                double px = wx, py = wy, pz = wz, pb = b;
+                if (!(b > 0.0)) {
+                    perp_unit(n.x, n.y, n.z, px, py, pz);
+                    pb = 1.0;
+                }
+                hit = true;
+                for (int c = m.ec_cut_off[ec], ce = m.ec_cut_off[ec + 1]; c < ce; ++c) {
+                    double4 u = m.ec_cut[c];
+                    if (CNT) ++cnt[EC_L_CIRCLE_CUT];
+                    if (px * u.x + py * u.y + pz * u.z > pb * u.w) {
+                        hit = false;
+                        break;
+                    }
+                }
+            }
+        }
+        if (__any(hit)) return 0;
+    }
+    return 1;
+}
+
+// CNT: the statistics pass (not timed); it tallies the work into
+// `work[EC_COUNT]` and writes no record.
+template <bool CNT>
+__global__ void __launch_bounds__(EW_THREADS)
+    k_edge_roots(Mol m, const uint8_t *L, const long long *keys, long long count, double *lam,
+                 double *nrm, uint8_t *ptype, int *patoms, int *overflow, const int *order,
+                 int nblocks, unsigned long long *work) {
+    __shared__ EdgeWaveLds lds[EW_WAVES];
+    const int w = threadIdx.x / WAVE, lane = lane_id();
+    // edges grouped by tile (order); consecutive groups stay on one XCD
+    const int blk = xcd_tile(blockIdx.x, nblocks, (int)((count + EW_WAVES - 1) / EW_WAVES));
+    if (blk < 0) return;  // uniform across the workgroup
+    const long long g = (long long)blk * EW_WAVES + w;
+    if (g >= count) return;  // uniform across the wavefront; no workgroup barrier below
+    EdgeWaveLds &S = lds[w];
+    unsigned long long cnt[CNT ? EC_COUNT : 1];
+    for (int c = 0; c < (CNT ? (int)EC_COUNT : 1); ++c) cnt[c] = 0;
+
+    const long long q = order[g];
+    const long long key = keys[q];
+    const int axis = (int)(key % 3);
+    const long long idx = key / 3;
+    const int nx = m.dims[0], ny = m.dims[1];
+    const int i0 = (int)(idx % nx), i1 = (int)((idx / nx) % ny),
+              i2 = (int)(idx / ((long long)nx * ny));
+    const long long step = axis == 0 ? 1 : axis == 1 ? (long long)nx : (long long)nx * ny;
+    const int Ls = L[idx], Lt = L[idx + step];
+    const int tile = i0 / m.tile + m.tdims[0] * (i1 / m.tile + m.tdims[1] * (i2 / m.tile));
+    const double h = m.h;
+    // the edge x(u) = xs + u h e, u in [0, 1]
+    const double e[3] = {axis == 0 ? 1.0 : 0.0, axis == 1 ? 1.0 : 0.0, axis == 2 ? 1.0 : 0.0};
+    const double xs[3] = {grid_coord(m.lo[0], h, i0), grid_coord(m.lo[1], h, i1),
+                          grid_coord(m.lo[2], h, i2)};
+    const double hh = 0.5 * h;
+    const double mid[3] = {xs[0] + hh * e[0], xs[1] + hh * e[1], xs[2] + hh * e[2]};
+    const double half = 0.5 * h + 1e-9;
+    bool ovf = false;
+    if (lane == 0) S.nroot = 0;
+
+    // 1. surfaces reaching the edge, compacted with ballots
+    int ns = 0;
+    for (int base = m.tF_off[tile], end = m.tF_off[tile + 1]; base < end; base += WAVE) {
+        int p = base + lane;
+        int f = p < end ? m.tF[p] : 0;
+        bool r = p < end && face_reaches(m, f, mid, half);
+        if (CNT && p < end) ++cnt[EC_REACH_SPHERE];
+        unsigned long long bm = __ballot(r);
+        int pos = ns + mask_prefix(bm);
+        if (r && pos < EW_SURF) S.surf[pos] = (1 << 28) | f;
+        ns += __popcll(bm);
+    }
+    for (int base = m.tV_off[tile], end = m.tV_off[tile + 1]; base < end; base += WAVE) {
+        int p = base + lane;
+        int v = p < end ? m.tV[p] : 0;
+        bool r = p < end && probe_reaches(m, v, mid, half);
+        if (CNT && p < end) ++cnt[EC_REACH_SPHERE];
+        unsigned long long bm = __ballot(r);
+        int pos = ns + mask_prefix(bm);
+        if (r && pos < EW_SURF) S.surf[pos] = (3 << 28) | v;
+        ns += __popcll(bm);
+    }
+    for (int base = m.tC_off[tile], end = m.tC_off[tile + 1]; base < end; base += WAVE) {
+        int p = base + lane;
+        int ec = p < end ? m.tC[p] : 0;
+        bool r = p < end && torus_reaches(m, ec, mid, half);
+        if (CNT && p < end) ++cnt[EC_REACH_TORUS];
+        unsigned long long bm = __ballot(r);
+        int pos = ns + mask_prefix(bm);
+        if (r && pos < EW_SURF) S.surf[pos] = (2 << 28) | ec;
+        ns += __popcll(bm);
+    }
+    if (ns > EW_SURF) {
+        ovf = true;
+        ns = EW_SURF;
+    }
+    wave_sync();
+
+    // 2. one surface per lane, every root in [0, 1] appended
+    for (int sb = 0; sb < ns; sb += WAVE) {
+        int si = sb + lane;
+        if (si < ns) surface_roots<CNT>(m, S.surf[si], e, xs, S, cnt);
+    }
+    wave_sync();
+    int nraw = S.nroot;
+    if (nraw > EW_ROOTS) {
+        ovf = true;
+        nraw = EW_ROOTS;
+    }
+
+    // 3. one root per lane: admissible ones compacted into (su, sk)
+    int nr = 0;
+    for (int b = 0; b < nraw; b += WAVE) {
+        int r = b + lane;
+        bool keep = false;
+        double u = 0.0;
+        int k = 0;
+        if (r < nraw) {
+            u = S.u[r];
+            k = S.k[r];
+            keep = root_admissible<CNT>(m, k, u, e, xs, cnt);
+        }
+        unsigned long long bm = __ballot(keep);
+        if (keep) {
+            int pos = nr + mask_prefix(bm);
+            S.su[pos] = u;
+            S.sk[pos] = k;
+        }
+        nr += __popcll(bm);
+    }
+    wave_sync();
+
+    // 4. rank sort by (u, key) from (su, sk) into (u, k)
+    for (int b = 0; b < nr; b += WAVE) {
+        int r = b + lane;
+        if (r < nr) {
+            double u = S.su[r];
+            int k = S.sk[r];
+            int rank = 0;
+            for (int p = 0; p < nr; ++p) {
+                double up = S.su[p];
+                int kp = S.sk[p];
+                rank += (up < u || (up == u && (kp < k || (kp == k && p < r)))) ? 1 : 0;
+            }
+            S.u[rank] = u;
+            S.k[rank] = k;
+        }
+    }
+    wave_sync();
+
+    // 5. walk the intervals from s (uniform across the wavefront).  The label
+    // is constant between consecutive roots; the first interval has
+    // Inside[s] and the last Inside[t] unless a root sits exactly on that end.
+    const bool root0 = nr > 0 && S.u[0] == 0.0;
+    const bool root1 = nr > 0 && S.u[nr - 1] == 1.0;
+    double ustar = 1.0, prev = 0.0;
+    int prev_key = -1, owner_key = -1;
+    bool found = false;
+    for (int r = 0; r <= nr; ++r) {
+        double next = r < nr ? S.u[r] : 1.0;
+        if (next > prev) {
+            int lab;
+            if (prev == 0.0 && !root0) {
+                lab = Ls;
+            } else if (r == nr && !root1) {
+                lab = Lt;
+            } else {
+                double um = 0.5 * (prev + next) * h;
+                if (CNT && lane == 0) ++cnt[EC_LABEL];
+                lab = label_wave<CNT>(m, tile, xs[0] + um * e[0], xs[1] + um * e[1],
+                                      xs[2] + um * e[2], cnt);
+            }
+            if (lab != Ls) {
+                ustar = prev;
+                owner_key = prev_key;
+                found = true;
+                break;
+            }
+        }
+        // owner of a position: the smallest key among the roots there
+        if (r < nr && (prev_key < 0 || next > prev)) prev_key = S.k[r];
+        if (next > prev) prev = next;
     }
     // no change inside the edge: it happens at t itself (the last root)
     if (!found) owner_key = prev_key;
-    double xst[3] = {xs[0], xs[1], xs[2]};
-    xst[axis] += ustar * h;
+    if (__any(ovf) && lane == 0) *overflow = 1;
+    if (CNT) {
+        if (lane == 0) cnt[EC_EDGES] = 1;
+        // untimed statistics pass: one atomic per lane and counter
+        for (int c = 0; c < EC_COUNT; ++c)
+            if (cnt[c]) atomicAdd(&work[c], cnt[c]);
+        return;
+    }
+    if (lane != 0) return;
+
+    // 6. the record: normal of the owning surface at x(u*), atoms of its patch
+    const double us = ustar * h;
+    const double xst[3] = {xs[0] + us * e[0], xs[1] + us * e[1], xs[2] + us * e[2]};
     double n3[3] = {0.0, 0.0, 0.0};
-    int type = 0, at[3] = {-1, -1, -1};
+    int type = 0, at0 = -1, at1 = -1, at2 = -1;
     if (owner_key >= 0) {
         type = owner_key >> 28;
-        int id = owner_key & ((1 << 28) - 1);
+        const int id = owner_key & ((1 << 28) - 1);
         double y[3];
         if (type == 1) {
-            double4 a = m.atom[id];
+            const int ia = m.face_atom[id];
+            double4 a = m.atom[ia];
             y[0] = xst[0] - a.x;
             y[1] = xst[1] - a.y;
             y[2] = xst[2] - a.z;
-            at[0] = m.orig[id];
+            at0 = m.orig[ia];
         } else if (type == 2) {
             int ci = m.ec_circ[id];
             double4 oR = m.circ_oR[ci];
             double4 nn = m.circ_n[ci];
-            double w[3] = {xst[0] - oR.x, xst[1] - oR.y, xst[2] - oR.z};
-            double t = w[0] * nn.x + w[1] * nn.y + w[2] * nn.z;
-            double wp[3] = {w[0] - t * nn.x, w[1] - t * nn.y, w[2] - t * nn.z};
+            double wv[3] = {xst[0] - oR.x, xst[1] - oR.y, xst[2] - oR.z};
+            double t = wv[0] * nn.x + wv[1] * nn.y + wv[2] * nn.z;
+            double wp[3] = {wv[0] - t * nn.x, wv[1] - t * nn.y, wv[2] - t * nn.z};
             double b = sqrt(wp[0] * wp[0] + wp[1] * wp[1] + wp[2] * wp[2]);
             double u[3];
             if (b > 0.0) {
@@ -488,25 +684,21 @@ __global__ void __launch_bounds__(EDGE_THREADS) k_edge_roots(Mol m, const uint8_
             } else {
                 perp_unit(nn.x, nn.y, nn.z, u[0], u[1], u[2]);
             }
-            for (int a = 0; a < 3; ++a)
-                y[a] = ((a == 0 ? oR.x : a == 1 ? oR.y : oR.z) + oR.w * u[a]) - xst[a];
-            at[0] = m.orig[m.circ_i[ci]];
-            at[1] = m.orig[m.circ_j[ci]];
-            if (at[0] > at[1]) {
-                int t2 = at[0];
-                at[0] = at[1];
-                at[1] = t2;
-            }
+            y[0] = oR.x + oR.w * u[0] - xst[0];
+            y[1] = oR.y + oR.w * u[1] - xst[1];
+            y[2] = oR.z + oR.w * u[2] - xst[2];
+            at0 = min(m.orig[m.circ_i[ci]], m.orig[m.circ_j[ci]]);
+            at1 = max(m.orig[m.circ_i[ci]], m.orig[m.circ_j[ci]]);
         } else {
             double4 p = m.vert_p[id];
             y[0] = p.x - xst[0];
             y[1] = p.y - xst[1];
             y[2] = p.z - xst[2];
             int4 v = m.vert_ijks[id];
-            at[0] = m.orig[v.x];
-            at[1] = m.orig[v.y];
-            at[2] = m.orig[v.z];
-            sort3(at[0], at[1], at[2]);
+            at0 = m.orig[v.x];
+            at1 = m.orig[v.y];
+            at2 = m.orig[v.z];
+            sort3(at0, at1, at2);
         }
         double l = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
         if (l > 0.0)
@@ -517,10 +709,11 @@ __global__ void __launch_bounds__(EDGE_THREADS) k_edge_roots(Mol m, const uint8_
     nrm[3 * q + 1] = n3[1];
     nrm[3 * q + 2] = n3[2];
     ptype[q] = (uint8_t)type;
-    patoms[3 * q] = at[0];
-    patoms[3 * q + 1] = at[1];
-    patoms[3 * q + 2] = at[2];
+    patoms[3 * q] = at0;
+    patoms[3 * q + 1] = at1;
+    patoms[3 * q + 2] = at2;
 }
+
 
 // Permutation of the crossing edges grouping them by the tile owning s
 // (counting sort; the order inside a tile is not used by any result).
@@ -581,10 +774,21 @@ hipError_t launch_edge_roots(const Mol &m, const uint8_t *L, const long long *ke
                              long long count, double *lam, double *nrm, uint8_t *ptype,
                              int *patoms, int *overflow, const int *order, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    int nb = (int)((count + EDGE_THREADS - 1) / EDGE_THREADS);
+    int nb = (int)((count + EW_WAVES - 1) / EW_WAVES);
     nb = (nb + NXCD - 1) / NXCD * NXCD;
-    hipLaunchKernelGGL(k_edge_roots, dim3(nb), dim3(EDGE_THREADS), 0, st, m, L, keys, count, lam, nrm,
-                       ptype, patoms, overflow, order, nb);
+    hipLaunchKernelGGL(k_edge_roots<false>, dim3(nb), dim3(EW_THREADS), 0, st, m, L, keys, count,
+                       lam, nrm, ptype, patoms, overflow, order, nb, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_edge_work(const Mol &m, const uint8_t *L, const long long *keys,
+                            long long count, const int *order, int *overflow,
+                            unsigned long long *work, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    int nb = (int)((count + EW_WAVES - 1) / EW_WAVES);
+    nb = (nb + NXCD - 1) / NXCD * NXCD;
+    hipLaunchKernelGGL(k_edge_roots<true>, dim3(nb), dim3(EW_THREADS), 0, st, m, L, keys, count,
+                       nullptr, nullptr, nullptr, nullptr, overflow, order, nb, work);
     return hipGetLastError();
 }
 

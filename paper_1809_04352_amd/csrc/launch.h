@@ -55,6 +55,11 @@ hipError_t launch_edge_roots(const Mol &m, const uint8_t *L, const long long *ke
                              long long count, double *lam, double *nrm, uint8_t *ptype,
                              int *patoms, int *overflow, const int *order, hipStream_t st);
 
+hipError_t launch_edge_work(const Mol &m, const uint8_t *L, const long long *keys,
+                            long long count, const int *order, int *overflow,
+                            unsigned long long *work, hipStream_t st);
+constexpr int EDGE_WORK_COUNTERS = 14;
+
 // vertex export
 hipError_t launch_export_vertices(const Mol &m, double *p, int *atoms, int8_t *sign,
                                   long long count, hipStream_t st);

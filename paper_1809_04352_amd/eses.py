@@ -28,7 +28,8 @@ ESES_FP32_RECHECK = 1
 EXPORTED = [
     "eses_bbox_from_atoms", "eses_grid_dims", "eses_build_candidates", "eses_candidates_info",
     "eses_copy_vertices", "eses_classify", "eses_edge_intersections", "eses_free_candidates",
-    "eses_last_error", "eses_version",
+    "eses_last_error", "eses_version", "eses_edge_work", "eses_set_timing",
+    "eses_get_kernel_times",
 ]
 
 
@@ -74,6 +75,26 @@ class ClassifyStats(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+class EdgeStats(ctypes.Structure):
+    _fields_ = [("n_edges", ctypes.c_int64), ("reach_sphere", ctypes.c_int64),
+                ("reach_torus", ctypes.c_int64), ("quad_solves", ctypes.c_int64),
+                ("quartic_solves", ctypes.c_int64), ("horner_flops", ctypes.c_int64),
+                ("cut_tests", ctypes.c_int64), ("label_evals", ctypes.c_int64),
+                ("label_tests", ctypes.c_int64 * 6)]
+
+    def as_dict(self):
+        d = {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "label_tests"}
+        names = ["atom", "vertex", "face", "face_cut", "circle", "circle_cut"]
+        for n, v in zip(names, self.label_tests):
+            d["label_tests_" + n] = int(v)
+        return d
+
+
+class KernelTimes(ctypes.Structure):
+    _fields_ = [("classify_ms", ctypes.c_double), ("edge_detect_ms", ctypes.c_double),
+                ("edge_roots_ms", ctypes.c_double)]
+
+
 class IsectSoA(ctypes.Structure):
     _fields_ = [("key", ctypes.c_void_p), ("lambda_", ctypes.c_void_p),
                 ("normal", ctypes.c_void_p), ("patch_type", ctypes.c_void_p),
@@ -113,6 +134,12 @@ def load():
     lib.eses_edge_intersections.argtypes = [P, P, ctypes.POINTER(IsectSoA), P, P]
     lib.eses_free_candidates.restype = None
     lib.eses_free_candidates.argtypes = [P]
+    lib.eses_edge_work.restype = st
+    lib.eses_edge_work.argtypes = [P, P, ctypes.POINTER(EdgeStats), P]
+    lib.eses_set_timing.restype = None
+    lib.eses_set_timing.argtypes = [ctypes.c_int]
+    lib.eses_get_kernel_times.restype = st
+    lib.eses_get_kernel_times.argtypes = [P, ctypes.POINTER(KernelTimes)]
     _lib = lib
     return lib
 
@@ -265,6 +292,25 @@ def edge_intersections(cand: Candidates, labels_dev, outs, stream=None):
     if st not in (ESES_OK, ESES_ECAPACITY):
         _check(st)
     return st, [int(c) for c in counts]
+
+
+def edge_work(cand: Candidates, labels_dev, stream=None):
+    n = len(labels_dev)
+    ptrs = (ctypes.c_void_p * n)(*[t.data_ptr() for t in labels_dev])
+    out = (EdgeStats * n)()
+    _check(load().eses_edge_work(cand.h, ptrs, out, _stream_ptr(stream)))
+    return [o.as_dict() for o in out]
+
+
+def set_timing(enable: bool):
+    load().eses_set_timing(1 if enable else 0)
+
+
+def kernel_times(cand: Candidates) -> dict:
+    t = KernelTimes()
+    _check(load().eses_get_kernel_times(cand.h, ctypes.byref(t)))
+    return {"classify_ms": t.classify_ms, "edge_detect_ms": t.edge_detect_ms,
+            "edge_roots_ms": t.edge_roots_ms}
 
 
 def surface(centres, radii, probe: float, spacing: float, lo, hi, prec: int = ESES_FP64,

@@ -163,3 +163,35 @@ def test_fp32_recheck_matches_fp64_and_counts(E):
     assert c["classify_stats"]["n_rechecked"] == n
     assert b["classify_stats"]["n_rechecked"] < 1e-3 * n
     print("rechecked", b["classify_stats"]["n_rechecked"], "of", n)
+
+
+def test_kernel_timing_and_edge_work(E):
+    """Library-side HIP-event timing and the edge statistics pass."""
+    import torch
+    from eses_inputs import molecule
+    m = molecule(300, 31, 0.4)
+    ct = torch.as_tensor(m.centres, device="cuda")
+    rt = torch.as_tensor(m.radii, device="cuda")
+    mol = E.make_molecule(ct, rt, m.probe, m.spacing, m.lo, m.hi)
+    cand = E.build_candidates([mol])
+    dims = E.grid_dims(mol)
+    lab = torch.empty(dims[0] * dims[1] * dims[2], dtype=torch.uint8, device="cuda")
+    E.set_timing(True)
+    try:
+        E.classify(cand, 0, [lab])
+        out = E.alloc_isect(1)
+        _, counts = E.edge_intersections(cand, [lab], [out])
+        out = E.alloc_isect(counts[0])
+        E.edge_intersections(cand, [lab], [out])
+        t = E.kernel_times(cand)
+    finally:
+        E.set_timing(False)
+    assert t["classify_ms"] > 0 and t["edge_roots_ms"] > 0 and t["edge_detect_ms"] > 0
+    w = E.edge_work(cand, [lab])[0]
+    assert w["n_edges"] == counts[0]
+    assert w["quad_solves"] > 0 and w["reach_sphere"] >= w["quad_solves"]
+    assert w["label_evals"] <= 8 * counts[0]
+    # the statistics pass leaves the records untouched
+    st, c2 = E.edge_intersections(cand, [lab], [out])
+    assert c2 == counts
+    cand.close()
