@@ -13,8 +13,11 @@ LIB = os.path.join(HERE, "libeses_gfx950.so")
 SOURCES = ["build.hip", "classify.hip", "edges.hip", "abi.cpp"]
 
 # Packed FP32 instructions stay disabled; the compiler would otherwise form
-# them from ordinary float code.
-HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+# them from ordinary float code.  Multiply-adds are fused only within one
+# source expression (-ffp-contract=on): a function inlined or duplicated in
+# several places then rounds the same way in every copy, so results do not
+# depend on which copy (or which thread's iteration of a peeled loop) ran.
+HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wno-unused-command-line-argument"]
 

@@ -690,11 +690,15 @@ eses_status eses_edge_intersections(eses_candidates *c, const uint8_t *const *la
         if (e == hipSuccess) e = hipMemcpyAsync(&total, boff + nblk, sizeof(long long), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         long long nw = std::min<long long>(total, o.capacity);
-        int *tcount = nullptr, *tfill = nullptr, *order = nullptr, *ttmp = nullptr;
+        int *tcount = nullptr, *ccount = nullptr, *coff = nullptr, *tfill = nullptr,
+            *order = nullptr, *ttmp = nullptr, *fb = nullptr, *nfb = nullptr;
         if (e == hipSuccess && nw > 0) {
             if ((s = T.alloc(&tcount, m.ntiles + 1)) != ESES_OK ||
+                (s = T.alloc(&ccount, m.ntiles + 1)) != ESES_OK ||
+                (s = T.alloc(&coff, m.ntiles + 1)) != ESES_OK ||
                 (s = T.alloc(&tfill, m.ntiles + 1)) != ESES_OK ||
-                (s = T.alloc(&order, nw)) != ESES_OK ||
+                (s = T.alloc(&order, edge_order_capacity(m, nw))) != ESES_OK ||
+                (s = T.alloc(&fb, nw)) != ESES_OK || (s = T.alloc(&nfb, 1)) != ESES_OK ||
                 (s = T.alloc(&ttmp, scan_tmp_elems(m.ntiles) + 64)) != ESES_OK) {
                 T.release();
                 return s;
@@ -703,12 +707,13 @@ eses_status eses_edge_intersections(eses_candidates *c, const uint8_t *const *la
         if (e == hipSuccess && nw > 0) e = launch_edge_detect_write(labels[q], m, boff, o.capacity, (long long *)o.key, st);
         if (e == hipSuccess) e = fill_i32(ovf, 1, 0, st);
         if (e == hipSuccess && nw > 0)
-            e = launch_edge_group(m, (const long long *)o.key, nw, tcount, tfill, order, ttmp, st);
+            e = launch_edge_group(m, (const long long *)o.key, nw, tcount, ccount, coff, tfill,
+                                  order, ttmp, st);
         if (e == hipSuccess && timed) e = hipEventRecord(c->ev[3], st);
         if (e == hipSuccess && timed) e = hipEventRecord(c->ev[4], st);
         if (e == hipSuccess && nw > 0)
-            e = launch_edge_roots(m, labels[q], (const long long *)o.key, nw, o.lambda, o.normal, o.patch_type,
-                                  o.atoms, ovf, order, st);
+            e = launch_edge_roots(m, labels[q], (const long long *)o.key, nw, order, tcount, coff,
+                                  o.lambda, o.normal, o.patch_type, o.atoms, fb, nfb, ovf, st);
         if (e == hipSuccess && timed) e = hipEventRecord(c->ev[5], st);
         int hovf = 0;
         if (e == hipSuccess) e = hipMemcpyAsync(&hovf, ovf, sizeof(int), hipMemcpyDeviceToHost, st);
@@ -792,10 +797,15 @@ eses_status eses_edge_work(eses_candidates *c, const uint8_t *const *labels,
         if (e == hipSuccess) e = hipMemcpyAsync(&total, boff + nblk, sizeof(long long), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         long long *keys = nullptr;
-        int *tcount = nullptr, *tfill = nullptr, *order = nullptr, *ttmp = nullptr;
+        int *tcount = nullptr, *ccount = nullptr, *coff = nullptr, *tfill = nullptr,
+            *order = nullptr, *ttmp = nullptr, *fb = nullptr, *nfb = nullptr;
         if (e == hipSuccess && total > 0) {
             if ((s = T.alloc(&keys, total)) != ESES_OK || (s = T.alloc(&tcount, m.ntiles + 1)) != ESES_OK ||
-                (s = T.alloc(&tfill, m.ntiles + 1)) != ESES_OK || (s = T.alloc(&order, total)) != ESES_OK ||
+                (s = T.alloc(&ccount, m.ntiles + 1)) != ESES_OK ||
+                (s = T.alloc(&coff, m.ntiles + 1)) != ESES_OK ||
+                (s = T.alloc(&tfill, m.ntiles + 1)) != ESES_OK ||
+                (s = T.alloc(&order, edge_order_capacity(m, total))) != ESES_OK ||
+                (s = T.alloc(&fb, total)) != ESES_OK || (s = T.alloc(&nfb, 1)) != ESES_OK ||
                 (s = T.alloc(&ttmp, scan_tmp_elems(m.ntiles) + 64)) != ESES_OK) {
                 T.release();
                 return s;
@@ -804,8 +814,10 @@ eses_status eses_edge_work(eses_candidates *c, const uint8_t *const *labels,
         if (e == hipSuccess) e = fill_u32((uint32_t *)work, 2 * EDGE_WORK_COUNTERS, 0u, st);
         if (e == hipSuccess) e = fill_i32(ovf, 1, 0, st);
         if (e == hipSuccess && total > 0) e = launch_edge_detect_write(labels[q], m, boff, total, keys, st);
-        if (e == hipSuccess && total > 0) e = launch_edge_group(m, keys, total, tcount, tfill, order, ttmp, st);
-        if (e == hipSuccess && total > 0) e = launch_edge_work(m, labels[q], keys, total, order, ovf, work, st);
+        if (e == hipSuccess && total > 0)
+            e = launch_edge_group(m, keys, total, tcount, ccount, coff, tfill, order, ttmp, st);
+        if (e == hipSuccess && total > 0)
+            e = launch_edge_work(m, labels[q], keys, total, order, tcount, coff, fb, nfb, ovf, work, st);
         unsigned long long h[EDGE_WORK_COUNTERS] = {0};
         if (e == hipSuccess) e = hipMemcpyAsync(h, work, sizeof(h), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -3,13 +3,14 @@
 // (a) Crossing edges: a streaming pass over the label array finds every axis
 //     edge whose end labels differ; a block-level prefix sum plus a scan of
 //     block counts gives each edge its slot, so keys come out ascending.
-// (b) Roots: one lane per crossing edge collects, along s + u h e_axis, the
-//     roots in [0, 1] of every surface that can carry the boundary of M
-//     there -- van der Waals spheres (convex), tori of radius rho around
-//     exposed circles (saddle), probe spheres around exposed concave probe
-//     positions (concave) -- sorts them, and walks the intervals from s.
-//     u* is the start of the first interval whose label differs from
-//     Inside[s]; lambda = 1 - u*.
+// (b) Roots: along s + u h e_axis, the roots in [0, 1] of every surface that
+//     can carry the boundary of M there -- van der Waals spheres (convex),
+//     tori of radius rho around exposed circles (saddle), probe spheres
+//     around exposed concave probe positions (concave) -- are found, sorted,
+//     and the intervals walked from s.  u* is the start of the first
+//     interval whose label differs from Inside[s]; lambda = 1 - u*.  Edges
+//     are processed in chunks of one tile (a workgroup per chunk, the tile's
+//     surfaces staged in LDS).
 #include "eses_device.h"
 #include "launch.h"
 
@@ -208,48 +209,43 @@ __device__ void quartic01(const double *g, Emit emit, unsigned long long *cnt) {
     }
 }
 
-// ------------------------------------------------ roots, one wavefront per edge
-//
-// One wavefront per crossing edge.  Lanes gather the surfaces that reach the
-// edge (distance from the edge's midpoint within h/2 of the surface: distance
-// to a set is 1-Lipschitz), each lane solves one surface, the roots are
-// rank-sorted across lanes in LDS, and the labels of the intervals between
-// roots are evaluated cooperatively (lanes split the atoms and candidate
-// features, ballots combine).  The walk from s stops at the first interval
-// whose label differs from Inside[s]; its start is u*, lambda = 1 - u*.
+// ------------------------------------------------ admissibility of roots
+
+// Every cut of cuts[b, e) passes for the direction p (scaled by s):
+// p . v <= s v.w.  cc: the counter of the tests (statistics pass).
+template <bool CNT>
+__device__ inline bool cuts_pass(const double4 *cuts, int b, int e, double px, double py,
+                                 double pz, double s, unsigned long long *cc) {
+    for (int c = b; c < e; ++c) {
+        double4 v = cuts[c];
+        if (CNT) ++*cc;
+        if (px * v.x + py * v.y + pz * v.z > s * v.w) return false;
+    }
+    return true;
+}
 
 // A point y of the sphere S_i seen from x along c_i -> x is admissible iff
 // (x - c_i) . v_k <= |x - c_i| tau_k for every cut of the face.
 template <bool CNT>
-__device__ inline bool face_admissible(const Mol &m, int f, double dx, double dy, double dz,
-                                       unsigned long long *cnt) {
+__device__ inline bool face_admissible(const double4 *cuts, int b, int e, double dx, double dy,
+                                       double dz, unsigned long long *cc) {
     double d = sqrt(dx * dx + dy * dy + dz * dz);
-    for (int c = m.face_cut_off[f], ce = m.face_cut_off[f + 1]; c < ce; ++c) {
-        double4 v = m.face_cut[c];
-        if (CNT) ++cnt[EC_CUT];
-        if (dx * v.x + dy * v.y + dz * v.z > d * v.w) return false;
-    }
-    return true;
+    return cuts_pass<CNT>(cuts, b, e, dx, dy, dz, d, cc);
 }
 
 // The circle point nearest to x (w = x - o) is admissible iff
 // w_perp . u_k <= |w_perp| T_k for every cut of the circle.
 template <bool CNT>
-__device__ inline bool circle_admissible(const Mol &m, int ec, double4 n, double wx, double wy,
-                                         double wz, unsigned long long *cnt) {
+__device__ inline bool circle_admissible(const double4 *cuts, int b, int e, double4 n, double wx,
+                                         double wy, double wz, unsigned long long *cc) {
     double t = wx * n.x + wy * n.y + wz * n.z;
     double px = wx - t * n.x, py = wy - t * n.y, pz = wz - t * n.z;
-    double b = sqrt(px * px + py * py + pz * pz);
-    if (!(b > 0.0)) {
+    double pb = sqrt(px * px + py * py + pz * pz);
+    if (!(pb > 0.0)) {
         perp_unit(n.x, n.y, n.z, px, py, pz);
-        b = 1.0;
+        pb = 1.0;
     }
-    for (int c = m.ec_cut_off[ec], ce = m.ec_cut_off[ec + 1]; c < ce; ++c) {
-        double4 u = m.ec_cut[c];
-        if (CNT) ++cnt[EC_CUT];
-        if (px * u.x + py * u.y + pz * u.z > b * u.w) return false;
-    }
-    return true;
+    return cuts_pass<CNT>(cuts, b, e, px, py, pz, pb, cc);
 }
 
 __device__ inline void sort3(int &a, int &b, int &c) {
@@ -266,85 +262,70 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ inline bool face_reaches(const Mol &m, int f, const double *mid, double half) {
-    double4 a = m.atom[m.face_atom[f]];
-    double dm2 = sq(mid[0] - a.x) + sq(mid[1] - a.y) + sq(mid[2] - a.z);
-    return !(dm2 > sq(a.w + half) || (a.w > half && dm2 < sq(a.w - half)));
-}
-
-__device__ inline bool probe_reaches(const Mol &m, int v, const double *mid, double half) {
-    double4 c = m.vert_p[v];
-    double dm2 = sq(mid[0] - c.x) + sq(mid[1] - c.y) + sq(mid[2] - c.z);
-    return !(dm2 > sq(m.rho + half) || (m.rho > half && dm2 < sq(m.rho - half)));
-}
-
-__device__ inline bool torus_reaches(const Mol &m, int ec, const double *mid, double half) {
-    int ci = m.ec_circ[ec];
-    double4 oR = m.circ_oR[ci];
-    double4 nn = m.circ_n[ci];
-    double dm0 = mid[0] - oR.x, dm1 = mid[1] - oR.y, dm2 = mid[2] - oR.z;
-    double tm = dm0 * nn.x + dm1 * nn.y + dm2 * nn.z;
-    double bm = sqrt(fmax(0.0, dm0 * dm0 + dm1 * dm1 + dm2 * dm2 - tm * tm));
-    double dc2 = tm * tm + sq(bm - oR.w);  // squared distance of the midpoint from the circle
-    return !(dc2 > sq(m.rho + half) || (m.rho > half && dc2 < sq(m.rho - half)));
-}
-
-constexpr int EW_WAVES = 4;      // edges (wavefronts) per workgroup
-constexpr int EW_THREADS = EW_WAVES * WAVE;
-constexpr int EW_SURF = 128;     // reaching surfaces kept per edge
-constexpr int EW_ROOTS = 128;    // roots kept per edge
-
-struct EdgeWaveLds {
-    int surf[EW_SURF];
-    double u[EW_ROOTS];
-    int k[EW_ROOTS];
-    double su[EW_ROOTS];
-    int sk[EW_ROOTS];
-    int nroot;
+// Surface parameters as staged: spheres (van der Waals face, probe) as
+// centre + radius; tori as circle centre + radius R and circle normal n.
+struct SurfParams {
+    double4 c;
+    double4 n;
 };
 
-// Appends a root (position u along the edge, owner key) to the wavefront's
-// list; the order of appends is irrelevant (the list is rank-sorted).
-__device__ inline void push_root(EdgeWaveLds &S, double u, int key) {
-    int pos = atomicAdd(&S.nroot, 1);
-    if (pos < EW_ROOTS) {
-        S.u[pos] = u;
-        S.k[pos] = key;
+__device__ inline SurfParams surf_params(const Mol &m, int key) {
+    const int type = key >> 28, id = key & ((1 << 28) - 1);
+    SurfParams p;
+    p.n = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (type == 1) {
+        p.c = m.atom[m.face_atom[id]];
+    } else if (type == 3) {
+        double4 v = m.vert_p[id];
+        p.c = make_double4(v.x, v.y, v.z, m.rho);
+    } else {
+        int ci = m.ec_circ[id];
+        p.c = m.circ_oR[ci];
+        p.n = m.circ_n[ci];
     }
+    return p;
 }
 
-// Roots in [0, 1] of one surface (type 1 face f, 3 probe v, 2 exposed circle
-// ec) along the edge x(u) = xs + u h e, appended to the wavefront's list with
-// the key (type << 28) | id.
-template <bool CNT>
-__device__ void surface_roots(const Mol &m, int key, const double *e, const double *xs,
-                              EdgeWaveLds &S, unsigned long long *cnt) {
-    const double h = m.h, rho = m.rho;
-    const int type = key >> 28, id = key & ((1 << 28) - 1);
+// Whether the surface can cross the edge: the distance from the edge's
+// midpoint to the surface is at most `half` (distance to a set is
+// 1-Lipschitz, so a crossing on the edge puts the midpoint within h/2).
+__device__ inline bool surf_reaches(int type, const SurfParams &p, double rho, const double *mid,
+                                    double half) {
     if (type != 2) {
-        // sphere |x(u) - c|^2 = r^2: a van der Waals face or a probe
-        double4 c = type == 1 ? m.atom[m.face_atom[id]] : m.vert_p[id];
-        double r = type == 1 ? c.w : rho;
+        double r = p.c.w;
+        double dm2 = sq(mid[0] - p.c.x) + sq(mid[1] - p.c.y) + sq(mid[2] - p.c.z);
+        return !(dm2 > sq(r + half) || (r > half && dm2 < sq(r - half)));
+    }
+    double dm0 = mid[0] - p.c.x, dm1 = mid[1] - p.c.y, dm2 = mid[2] - p.c.z;
+    double tm = dm0 * p.n.x + dm1 * p.n.y + dm2 * p.n.z;
+    double bm = sqrt(fmax(0.0, dm0 * dm0 + dm1 * dm1 + dm2 * dm2 - tm * tm));
+    double dc2 = tm * tm + sq(bm - p.c.w);  // squared distance of the midpoint from the circle
+    return !(dc2 > sq(rho + half) || (rho > half && dc2 < sq(rho - half)));
+}
+
+// Roots in [0, 1] of one surface along the edge x(u) = xs + u h e, each
+// passed to sink(u): spheres |x(u) - c|^2 = r^2 (a quadratic), tori
+// (|w|^2 + R^2 - rho^2)^2 = 4 R^2 |w_perp|^2 of the circle's points at
+// distance rho (a quartic; both branches, the far one is dropped later).
+template <bool CNT, class Sink>
+__device__ void surface_roots(int type, const SurfParams &p, double h, double rho,
+                              const double *e, const double *xs, Sink sink,
+                              unsigned long long *cnt) {
+    const double w0[3] = {xs[0] - p.c.x, xs[1] - p.c.y, xs[2] - p.c.z};
+    const double ww = w0[0] * w0[0] + w0[1] * w0[1] + w0[2] * w0[2];
+    const double we = w0[0] * e[0] + w0[1] * e[1] + w0[2] * e[2];
+    if (type != 2) {
         if (CNT) ++cnt[EC_QUAD];
-        double w0[3] = {xs[0] - c.x, xs[1] - c.y, xs[2] - c.z};
-        double we = w0[0] * e[0] + w0[1] * e[1] + w0[2] * e[2];
+        double r = p.c.w;
         double tmp[2];
-        int n = quad01(h * h, 2.0 * h * we,
-                       w0[0] * w0[0] + w0[1] * w0[1] + w0[2] * w0[2] - r * r, tmp);
-        if (n > 0) push_root(S, tmp[0], key);
-        if (n > 1) push_root(S, tmp[1], key);
+        int n = quad01(h * h, 2.0 * h * we, ww - r * r, tmp);
+        if (n > 0) sink(tmp[0]);
+        if (n > 1) sink(tmp[1]);
         return;
     }
-    // torus (|w|^2 + R^2 - rho^2)^2 = 4 R^2 |w_perp|^2 of the circle's
-    // points at distance rho; both branches (the far one is dropped later)
-    const int ci = m.ec_circ[id];
-    const double4 oR = m.circ_oR[ci];
-    const double4 nn = m.circ_n[ci];
-    const double R = oR.w;
-    const double w0[3] = {xs[0] - oR.x, xs[1] - oR.y, xs[2] - oR.z};
-    const double ww = w0[0] * w0[0] + w0[1] * w0[1] + w0[2] * w0[2];
+    const double4 nn = p.n;
+    const double R = p.c.w;
     const double t0 = w0[0] * nn.x + w0[1] * nn.y + w0[2] * nn.z;
-    const double we = w0[0] * e[0] + w0[1] * e[1] + w0[2] * e[2];
     const double ne = nn.x * e[0] + nn.y * e[1] + nn.z * e[2];
     const double RR = R * R;
     const double a0 = ww + RR - rho * rho, a1 = 2.0 * h * we, a2 = h * h;
@@ -352,7 +333,7 @@ __device__ void surface_roots(const Mol &m, int key, const double *e, const doub
     const double g[5] = {a0 * a0 - 4.0 * RR * b0, 2.0 * a0 * a1 - 4.0 * RR * b1,
                          a1 * a1 + 2.0 * a0 * a2 - 4.0 * RR * b2, 2.0 * a1 * a2, a2 * a2};
     if (CNT) ++cnt[EC_QUARTIC];
-    quartic01<CNT>(g, [&](double u) { push_root(S, u, key); }, cnt);
+    quartic01<CNT>(g, sink, cnt);
 }
 
 // Whether a root is kept: only if the point of A that would put it on the
@@ -361,300 +342,125 @@ __device__ void surface_roots(const Mol &m, int key, const double *e, const doub
 // branch of the torus (torus roots).  Every label change lies on such a
 // point, so dropping the others is exact.  Probe roots are always kept.
 template <bool CNT>
-__device__ bool root_admissible(const Mol &m, int key, double u, const double *e,
-                                const double *xs, unsigned long long *cnt) {
-    const int type = key >> 28, id = key & ((1 << 28) - 1);
+__device__ bool root_admissible(const Mol &m, int key, const SurfParams &p, const double4 *cuts,
+                                int cb, int ce, double u, const double *e, const double *xs,
+                                unsigned long long *cnt) {
+    const int type = key >> 28;
     if (type == 3) return true;
     const double s = u * m.h;
-    if (type == 1) {
-        double4 a = m.atom[m.face_atom[id]];
-        return face_admissible<CNT>(m, id, xs[0] - a.x + s * e[0], xs[1] - a.y + s * e[1],
-                                    xs[2] - a.z + s * e[2], cnt);
-    }
-    const int ci = m.ec_circ[id];
-    const double4 oR = m.circ_oR[ci];
-    const double4 nn = m.circ_n[ci];
-    const double R = oR.w, rho = m.rho;
-    double x0 = xs[0] - oR.x + s * e[0], x1 = xs[1] - oR.y + s * e[1],
-           x2 = xs[2] - oR.z + s * e[2];
+    const double x0 = xs[0] - p.c.x + s * e[0], x1 = xs[1] - p.c.y + s * e[1],
+                 x2 = xs[2] - p.c.z + s * e[2];
+    unsigned long long *cc = CNT ? cnt + EC_CUT : nullptr;
+    if (type == 1) return face_admissible<CNT>(cuts, cb, ce, x0, x1, x2, cc);
+    const double4 nn = p.n;
+    const double R = p.c.w, rho = m.rho;
     double tt = x0 * nn.x + x1 * nn.y + x2 * nn.z;
     double bb = sqrt(fmax(0.0, x0 * x0 + x1 * x1 + x2 * x2 - tt * tt));
     double near = fabs(sq(bb - R) + tt * tt - rho * rho);
     double far = fabs(sq(bb + R) + tt * tt - rho * rho);
-    return near <= far && circle_admissible<CNT>(m, id, nn, x0, x1, x2, cnt);
+    return near <= far && circle_admissible<CNT>(cuts, cb, ce, nn, x0, x1, x2, cc);
 }
 
-// Inside/outside of x (eq. 2) evaluated by the whole wavefront: the three
-// cases of the classification with lanes splitting the tile's atoms and
-// candidate features.
-template <bool CNT>
-__device__ int label_wave(const Mol &m, int tile, double x, double y, double z,
-                          unsigned long long *cnt) {
-    const int lane = lane_id();
-    const double rho = m.rho, rho2 = rho * rho;
-    bool inU = false;
-    for (int base = m.tA_off[tile], e = m.tA_off[tile + 1]; base < e; base += WAVE) {
-        int q = base + lane;
-        bool v = false, u = false;
-        if (q < e) {
-            double4 a = m.atom[m.tA[q]];
-            double dx = x - a.x, dy = y - a.y, dz = z - a.z;
-            double d2 = dx * dx + dy * dy + dz * dz;
-            if (CNT) ++cnt[EC_L_ATOM];
-            v = d2 <= a.w * a.w;
-            u = d2 < sq(a.w + rho);
-        }
-        if (__any(v)) return 1;
-        inU = inU || __any(u);
+// The cut planes of surface `key` in global memory: [*cb, *ce) of the
+// returned array (none for probes).
+__device__ inline const double4 *global_cuts(const Mol &m, int key, int *cb, int *ce) {
+    const int type = key >> 28, id = key & ((1 << 28) - 1);
+    if (type == 1) {
+        *cb = m.face_cut_off[id];
+        *ce = m.face_cut_off[id + 1];
+        return m.face_cut;
     }
-    if (!inU) return 0;
-    for (int base = m.tV_off[tile], e = m.tV_off[tile + 1]; base < e; base += WAVE) {
-        int q = base + lane;
-        bool hit = false;
-        if (q < e) {
-            double4 p = m.vert_p[m.tV[q]];
-            if (CNT) ++cnt[EC_L_VERTEX];
-            hit = sq(x - p.x) + sq(y - p.y) + sq(z - p.z) < rho2;
-        }
-        if (__any(hit)) return 0;
+    if (type == 2) {
+        *cb = m.ec_cut_off[id];
+        *ce = m.ec_cut_off[id + 1];
+        return m.ec_cut;
     }
-    for (int base = m.tF_off[tile], e = m.tF_off[tile + 1]; base < e; base += WAVE) {
-        int q = base + lane;
-        bool hit = false;
-        if (q < e) {
-            int f = m.tF[q];
-            double4 a = m.atom[m.face_atom[f]];
-            double dx = x - a.x, dy = y - a.y, dz = z - a.z;
-            double d2 = dx * dx + dy * dy + dz * dz;
-            if (CNT) ++cnt[EC_L_FACE];
-            if (d2 < sq(a.w + 2.0 * rho)) {
-                double d = sqrt(d2);
-                hit = true;
-                for (int c = m.face_cut_off[f], ce = m.face_cut_off[f + 1]; c < ce; ++c) {
-                    double4 v = m.face_cut[c];
-                    if (CNT) ++cnt[EC_L_FACE_CUT];
-                    if (dx * v.x + dy * v.y + dz * v.z > d * v.w) {
-                        hit = false;
-                        break;
-                    }
-                }
-            }
-        }
-        if (__any(hit)) return 0;
-    }
-    for (int base = m.tC_off[tile], e = m.tC_off[tile + 1]; base < e; base += WAVE) {
-        int q = base + lane;
-        bool hit = false;
-        if (q < e) {
-            int ec = m.tC[q];
-            int ci = m.ec_circ[ec];
-            double4 oR = m.circ_oR[ci];
-            double4 n = m.circ_n[ci];
-            double wx = x - oR.x, wy = y - oR.y, wz = z - oR.z;
-            double t = wx * n.x + wy * n.y + wz * n.z;
-            double ww = wx * wx + wy * wy + wz * wz;
-            double b = sqrt(fmax(ww - t * t, 0.0));
-            double R = oR.w;
-            if (CNT) ++cnt[EC_L_CIRCLE];
-            if (ww + R * R - rho2 < 2.0 * b * R) {
-                double px = wx, py = wy, pz = wz, pb = b;
-                if (!(b > 0.0)) {
-                    perp_unit(n.x, n.y, n.z, px, py, pz);
-                    pb = 1.0;
-                }
-                hit = true;
-                for (int c = m.ec_cut_off[ec], ce = m.ec_cut_off[ec + 1]; c < ce; ++c) {
-                    double4 u = m.ec_cut[c];
-                    if (CNT) ++cnt[EC_L_CIRCLE_CUT];
-                    if (px * u.x + py * u.y + pz * u.z > pb * u.w) {
-                        hit = false;
-                        break;
-                    }
-                }
-            }
-        }
-        if (__any(hit)) return 0;
-    }
-    return 1;
+    *cb = *ce = 0;
+    return m.face_cut;
 }
 
-// CNT: the statistics pass (not timed); it tallies the work into
-// `work[EC_COUNT]` and writes no record.
-template <bool CNT>
-__global__ void __launch_bounds__(EW_THREADS)
-    k_edge_roots(Mol m, const uint8_t *L, const long long *keys, long long count, double *lam,
-                 double *nrm, uint8_t *ptype, int *patoms, int *overflow, const int *order,
-                 int nblocks, unsigned long long *work) {
-    __shared__ EdgeWaveLds lds[EW_WAVES];
-    const int w = threadIdx.x / WAVE, lane = lane_id();
-    // edges grouped by tile (order); consecutive groups stay on one XCD
-    const int blk = xcd_tile(blockIdx.x, nblocks, (int)((count + EW_WAVES - 1) / EW_WAVES));
-    if (blk < 0) return;  // uniform across the workgroup
-    const long long g = (long long)blk * EW_WAVES + w;
-    if (g >= count) return;  // uniform across the wavefront; no workgroup barrier below
-    EdgeWaveLds &S = lds[w];
-    unsigned long long cnt[CNT ? EC_COUNT : 1];
-    for (int c = 0; c < (CNT ? (int)EC_COUNT : 1); ++c) cnt[c] = 0;
+// Position and end labels of crossing edge `key` (3 * point index + axis).
+struct EdgeGeom {
+    double xs[3];
+    double e[3];
+    int tile, Ls, Lt;
+};
 
-    const long long q = order[g];
-    const long long key = keys[q];
+__device__ inline EdgeGeom edge_geom(const Mol &m, const uint8_t *L, long long key) {
+    EdgeGeom G;
     const int axis = (int)(key % 3);
     const long long idx = key / 3;
     const int nx = m.dims[0], ny = m.dims[1];
     const int i0 = (int)(idx % nx), i1 = (int)((idx / nx) % ny),
               i2 = (int)(idx / ((long long)nx * ny));
     const long long step = axis == 0 ? 1 : axis == 1 ? (long long)nx : (long long)nx * ny;
-    const int Ls = L[idx], Lt = L[idx + step];
-    const int tile = i0 / m.tile + m.tdims[0] * (i1 / m.tile + m.tdims[1] * (i2 / m.tile));
-    const double h = m.h;
-    // the edge x(u) = xs + u h e, u in [0, 1]
-    const double e[3] = {axis == 0 ? 1.0 : 0.0, axis == 1 ? 1.0 : 0.0, axis == 2 ? 1.0 : 0.0};
-    const double xs[3] = {grid_coord(m.lo[0], h, i0), grid_coord(m.lo[1], h, i1),
-                          grid_coord(m.lo[2], h, i2)};
-    const double hh = 0.5 * h;
-    const double mid[3] = {xs[0] + hh * e[0], xs[1] + hh * e[1], xs[2] + hh * e[2]};
-    const double half = 0.5 * h + 1e-9;
-    bool ovf = false;
-    if (lane == 0) S.nroot = 0;
+    G.Ls = L[idx];
+    G.Lt = L[idx + step];
+    G.tile = i0 / m.tile + m.tdims[0] * (i1 / m.tile + m.tdims[1] * (i2 / m.tile));
+    G.e[0] = axis == 0 ? 1.0 : 0.0;
+    G.e[1] = axis == 1 ? 1.0 : 0.0;
+    G.e[2] = axis == 2 ? 1.0 : 0.0;
+    G.xs[0] = grid_coord(m.lo[0], m.h, i0);
+    G.xs[1] = grid_coord(m.lo[1], m.h, i1);
+    G.xs[2] = grid_coord(m.lo[2], m.h, i2);
+    return G;
+}
 
-    // 1. surfaces reaching the edge, compacted with ballots
-    int ns = 0;
-    for (int base = m.tF_off[tile], end = m.tF_off[tile + 1]; base < end; base += WAVE) {
-        int p = base + lane;
-        int f = p < end ? m.tF[p] : 0;
-        bool r = p < end && face_reaches(m, f, mid, half);
-        if (CNT && p < end) ++cnt[EC_REACH_SPHERE];
-        unsigned long long bm = __ballot(r);
-        int pos = ns + mask_prefix(bm);
-        if (r && pos < EW_SURF) S.surf[pos] = (1 << 28) | f;
-        ns += __popcll(bm);
+// The walk over the sorted roots u[0..n) (keys k[]) of one edge: the label
+// is constant between consecutive distinct roots; the first interval has
+// Inside[s] and the last Inside[t] unless a root sits exactly on that end,
+// the others are evaluated at their midpoints.  Returns u*, the start of the
+// first interval whose label differs from Inside[s] (1 if none: the change
+// is at t itself), and the owner key of that position (the smallest key of
+// the roots there).  LabelFn(x, y, z) evaluates eq. (2).
+template <bool CNT, class RootAt, class LabelFn>
+__device__ double walk_roots(int n, RootAt root_at, int Ls, int Lt, const double *xs,
+                             const double *e, double h, LabelFn label, int *owner,
+                             unsigned long long *cnt) {
+    double u0 = 0.0, ulast = 0.0;
+    int k0 = 0;
+    if (n > 0) {
+        root_at(0, u0, k0);
+        root_at(n - 1, ulast, k0);
     }
-    for (int base = m.tV_off[tile], end = m.tV_off[tile + 1]; base < end; base += WAVE) {
-        int p = base + lane;
-        int v = p < end ? m.tV[p] : 0;
-        bool r = p < end && probe_reaches(m, v, mid, half);
-        if (CNT && p < end) ++cnt[EC_REACH_SPHERE];
-        unsigned long long bm = __ballot(r);
-        int pos = ns + mask_prefix(bm);
-        if (r && pos < EW_SURF) S.surf[pos] = (3 << 28) | v;
-        ns += __popcll(bm);
-    }
-    for (int base = m.tC_off[tile], end = m.tC_off[tile + 1]; base < end; base += WAVE) {
-        int p = base + lane;
-        int ec = p < end ? m.tC[p] : 0;
-        bool r = p < end && torus_reaches(m, ec, mid, half);
-        if (CNT && p < end) ++cnt[EC_REACH_TORUS];
-        unsigned long long bm = __ballot(r);
-        int pos = ns + mask_prefix(bm);
-        if (r && pos < EW_SURF) S.surf[pos] = (2 << 28) | ec;
-        ns += __popcll(bm);
-    }
-    if (ns > EW_SURF) {
-        ovf = true;
-        ns = EW_SURF;
-    }
-    wave_sync();
-
-    // 2. one surface per lane, every root in [0, 1] appended
-    for (int sb = 0; sb < ns; sb += WAVE) {
-        int si = sb + lane;
-        if (si < ns) surface_roots<CNT>(m, S.surf[si], e, xs, S, cnt);
-    }
-    wave_sync();
-    int nraw = S.nroot;
-    if (nraw > EW_ROOTS) {
-        ovf = true;
-        nraw = EW_ROOTS;
-    }
-
-    // 3. one root per lane: admissible ones compacted into (su, sk)
-    int nr = 0;
-    for (int b = 0; b < nraw; b += WAVE) {
-        int r = b + lane;
-        bool keep = false;
-        double u = 0.0;
-        int k = 0;
-        if (r < nraw) {
-            u = S.u[r];
-            k = S.k[r];
-            keep = root_admissible<CNT>(m, k, u, e, xs, cnt);
-        }
-        unsigned long long bm = __ballot(keep);
-        if (keep) {
-            int pos = nr + mask_prefix(bm);
-            S.su[pos] = u;
-            S.sk[pos] = k;
-        }
-        nr += __popcll(bm);
-    }
-    wave_sync();
-
-    // 4. rank sort by (u, key) from (su, sk) into (u, k)
-    for (int b = 0; b < nr; b += WAVE) {
-        int r = b + lane;
-        if (r < nr) {
-            double u = S.su[r];
-            int k = S.sk[r];
-            int rank = 0;
-            for (int p = 0; p < nr; ++p) {
-                double up = S.su[p];
-                int kp = S.sk[p];
-                rank += (up < u || (up == u && (kp < k || (kp == k && p < r)))) ? 1 : 0;
-            }
-            S.u[rank] = u;
-            S.k[rank] = k;
-        }
-    }
-    wave_sync();
-
-    // 5. walk the intervals from s (uniform across the wavefront).  The label
-    // is constant between consecutive roots; the first interval has
-    // Inside[s] and the last Inside[t] unless a root sits exactly on that end.
-    const bool root0 = nr > 0 && S.u[0] == 0.0;
-    const bool root1 = nr > 0 && S.u[nr - 1] == 1.0;
-    double ustar = 1.0, prev = 0.0;
-    int prev_key = -1, owner_key = -1;
-    bool found = false;
-    for (int r = 0; r <= nr; ++r) {
-        double next = r < nr ? S.u[r] : 1.0;
+    const bool root0 = n > 0 && u0 == 0.0;
+    const bool root1 = n > 0 && ulast == 1.0;
+    double prev = 0.0;
+    int prev_key = -1;
+    for (int r = 0; r <= n; ++r) {
+        double next = 1.0;
+        int kn = -1;
+        if (r < n) root_at(r, next, kn);
         if (next > prev) {
             int lab;
             if (prev == 0.0 && !root0) {
                 lab = Ls;
-            } else if (r == nr && !root1) {
+            } else if (r == n && !root1) {
                 lab = Lt;
             } else {
                 double um = 0.5 * (prev + next) * h;
-                if (CNT && lane == 0) ++cnt[EC_LABEL];
-                lab = label_wave<CNT>(m, tile, xs[0] + um * e[0], xs[1] + um * e[1],
-                                      xs[2] + um * e[2], cnt);
+                if (CNT) ++cnt[EC_LABEL];
+                lab = label(xs[0] + um * e[0], xs[1] + um * e[1], xs[2] + um * e[2]);
             }
             if (lab != Ls) {
-                ustar = prev;
-                owner_key = prev_key;
-                found = true;
-                break;
+                *owner = prev_key;
+                return prev;
             }
         }
-        // owner of a position: the smallest key among the roots there
-        if (r < nr && (prev_key < 0 || next > prev)) prev_key = S.k[r];
+        if (r < n && (prev_key < 0 || next > prev)) prev_key = kn;
         if (next > prev) prev = next;
     }
-    // no change inside the edge: it happens at t itself (the last root)
-    if (!found) owner_key = prev_key;
-    if (__any(ovf) && lane == 0) *overflow = 1;
-    if (CNT) {
-        if (lane == 0) cnt[EC_EDGES] = 1;
-        // untimed statistics pass: one atomic per lane and counter
-        for (int c = 0; c < EC_COUNT; ++c)
-            if (cnt[c]) atomicAdd(&work[c], cnt[c]);
-        return;
-    }
-    if (lane != 0) return;
+    *owner = prev_key;
+    return 1.0;
+}
 
-    // 6. the record: normal of the owning surface at x(u*), atoms of its patch
-    const double us = ustar * h;
-    const double xst[3] = {xs[0] + us * e[0], xs[1] + us * e[1], xs[2] + us * e[2]};
+// The record of edge q: lambda = 1 - u*, the outward unit normal of the
+// owning surface at x(u*), its patch type and atoms (original indices).
+__device__ inline void write_record(const Mol &m, long long q, const EdgeGeom &G, double ustar,
+                                    int owner_key, double *lam, double *nrm, uint8_t *ptype,
+                                    int *patoms) {
+    const double us = ustar * m.h;
+    const double xst[3] = {G.xs[0] + us * G.e[0], G.xs[1] + us * G.e[1], G.xs[2] + us * G.e[2]};
     double n3[3] = {0.0, 0.0, 0.0};
     int type = 0, at0 = -1, at1 = -1, at2 = -1;
     if (owner_key >= 0) {
@@ -714,9 +520,6 @@ __global__ void __launch_bounds__(EW_THREADS)
     patoms[3 * q + 2] = at2;
 }
 
-
-// Permutation of the crossing edges grouping them by the tile owning s
-// (counting sort; the order inside a tile is not used by any result).
 __device__ inline int edge_tile(const Mol &m, long long key) {
     long long idx = key / 3;
     const int nx = m.dims[0], ny = m.dims[1];
@@ -724,30 +527,579 @@ __device__ inline int edge_tile(const Mol &m, long long key) {
     return i / m.tile + m.tdims[0] * (j / m.tile + m.tdims[1] * (k / m.tile));
 }
 
+// Surface count and the key of entry s of tile t's candidate surfaces:
+// exposed faces, then probes, then exposed circles.
+__device__ inline int tile_surfaces(const Mol &m, int t) {
+    return (m.tF_off[t + 1] - m.tF_off[t]) + (m.tV_off[t + 1] - m.tV_off[t]) +
+           (m.tC_off[t + 1] - m.tC_off[t]);
+}
+
+__device__ inline int tile_surface_key(const Mol &m, int t, int s) {
+    int nf = m.tF_off[t + 1] - m.tF_off[t];
+    if (s < nf) return (1 << 28) | m.tF[m.tF_off[t] + s];
+    s -= nf;
+    int nv = m.tV_off[t + 1] - m.tV_off[t];
+    if (s < nv) return (3 << 28) | m.tV[m.tV_off[t] + s];
+    return (2 << 28) | m.tC[m.tC_off[t] + s - nv];
+}
+
+// ------------------------------------------------ roots, chunks of one tile
+//
+// A workgroup takes up to CH_EDGES crossing edges of one tile (a chunk) and
+// the tile's candidate surfaces, staged in LDS.  Threads run over the
+// (edge, surface) pairs for the reach test; the pairs that pass are queued
+// (tori and spheres apart, so that waves solve one kind), one thread per
+// queued pair solves it and keeps its admissible roots; the roots are then
+// grouped by edge and one thread per edge sorts its roots and walks the
+// intervals, evaluating eq. (2) where an interval's label is not implied by
+// the end labels.
+constexpr int CH_EDGES = 64;
+constexpr int CH_THREADS = 256;
+constexpr int CH_SURF = 128;    // surfaces staged per pass
+constexpr int CH_PAIRS = 1024;  // queued (edge, surface) pairs per solve round
+constexpr int CH_ROOTS = 512;   // admissible roots per chunk
+constexpr int CH_SLOTS = 4;     // roots of one quartic before the admissibility test
+constexpr int CH_ATOMS = 192;   // tile atoms staged for the labels
+constexpr int CH_CUTS = 384;    // cut planes of the staged surfaces
+
+struct ChunkLds {
+    SurfParams sp[CH_SURF];
+    double4 atoms[CH_ATOMS];
+    double4 cut[CH_CUTS];
+    double xs[CH_EDGES][3];
+    double slot[CH_SLOTS][CH_THREADS];
+    double fu[CH_ROOTS];
+    int fk[CH_ROOTS];
+    int skey[CH_SURF];
+    int2 crange[CH_SURF];  // cut range in `cut`, or (-1 - begin, end) in global memory
+    long long eq[CH_EDGES];
+    int einfo[CH_EDGES];  // axis | Ls << 2 | Lt << 3
+    int ecount[CH_EDGES + 1];
+    int eoff[CH_EDGES + 1];
+    int scan[CH_THREADS / WAVE + 1];
+    unsigned short pair[CH_PAIRS];
+    unsigned short perm[CH_ROOTS];
+    unsigned char fe[CH_ROOTS];
+    int npair_s, npair_t, nf, ovf, tile, fb_base;
+};
+
+// Cut planes of staged surface s: LDS or global memory.
+__device__ inline const double4 *staged_cuts(const Mol &m, const ChunkLds &S, int s, int *cb,
+                                             int *ce) {
+    int2 r = S.crange[s];
+    *ce = r.y;
+    if (r.x >= 0) {
+        *cb = r.x;
+        return S.cut;
+    }
+    *cb = -1 - r.x;
+    return (S.skey[s] >> 28) == 1 ? m.face_cut : m.ec_cut;
+}
+
+// Inside/outside of x (eq. 2) from the staged tile data: the first nAst
+// atoms of the tile's atom list in LDS (the rest read from global memory),
+// the surfaces (exposed faces [0, nF), probes [nF, nF + nV), exposed
+// circles [nF + nV, ns)) and their cuts.  The same tests as label_fp64_t.
+template <bool CNT>
+__device__ int label_chunk(const Mol &m, const ChunkLds &S, int tile, int nAst, int nF, int nV,
+                           int ns, double x, double y, double z, unsigned long long *cnt) {
+    const double rho = m.rho;
+    const double rho2 = rho * rho;
+    bool inU = false;
+    for (int q = 0; q < nAst; ++q) {
+        double4 a = S.atoms[q];
+        double dx = x - a.x, dy = y - a.y, dz = z - a.z;
+        double d2 = dx * dx + dy * dy + dz * dz;
+        if (CNT) ++cnt[EC_L_ATOM];
+        if (d2 <= a.w * a.w) return 1;
+        double s = a.w + rho;
+        inU |= d2 < s * s;
+    }
+    for (int q = m.tA_off[tile] + nAst, e = m.tA_off[tile + 1]; q < e; ++q) {
+        double4 a = m.atom[m.tA[q]];
+        double dx = x - a.x, dy = y - a.y, dz = z - a.z;
+        double d2 = dx * dx + dy * dy + dz * dz;
+        if (CNT) ++cnt[EC_L_ATOM];
+        if (d2 <= a.w * a.w) return 1;
+        double s = a.w + rho;
+        inU |= d2 < s * s;
+    }
+    if (!inU) return 0;
+    for (int q = nF; q < nF + nV; ++q) {
+        double4 p = S.sp[q].c;
+        double dx = x - p.x, dy = y - p.y, dz = z - p.z;
+        if (CNT) ++cnt[EC_L_VERTEX];
+        if (dx * dx + dy * dy + dz * dz < rho2) return 0;
+    }
+    for (int q = 0; q < nF; ++q) {
+        double4 a = S.sp[q].c;
+        double dx = x - a.x, dy = y - a.y, dz = z - a.z;
+        double d2 = dx * dx + dy * dy + dz * dz;
+        double sr = a.w + 2.0 * rho;
+        if (CNT) ++cnt[EC_L_FACE];
+        if (!(d2 < sr * sr)) continue;
+        double d = sqrt(d2);
+        int cb, ce;
+        const double4 *cuts = staged_cuts(m, S, q, &cb, &ce);
+        if (cuts_pass<CNT>(cuts, cb, ce, dx, dy, dz, d, CNT ? cnt + EC_L_FACE_CUT : nullptr))
+            return 0;
+    }
+    for (int q = nF + nV; q < ns; ++q) {
+        double4 oR = S.sp[q].c;
+        double4 n = S.sp[q].n;
+        double wx = x - oR.x, wy = y - oR.y, wz = z - oR.z;
+        double t = wx * n.x + wy * n.y + wz * n.z;
+        double ww = wx * wx + wy * wy + wz * wz;
+        double b = sqrt(fmax(ww - t * t, 0.0));
+        double R = oR.w;
+        if (CNT) ++cnt[EC_L_CIRCLE];
+        if (!(ww + R * R - rho2 < 2.0 * b * R)) continue;
+        double px = wx, py = wy, pz = wz, pb = b;
+        if (!(b > 0.0)) {
+            perp_unit(n.x, n.y, n.z, px, py, pz);
+            pb = 1.0;
+        }
+        int cb, ce;
+        const double4 *cuts = staged_cuts(m, S, q, &cb, &ce);
+        if (cuts_pass<CNT>(cuts, cb, ce, px, py, pz, pb, CNT ? cnt + EC_L_CIRCLE_CUT : nullptr))
+            return 0;
+    }
+    return 1;
+}
+
+template <bool CNT>
+__device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys,
+                           const int *order, int g0, int n, double *lam, double *nrm,
+                           uint8_t *ptype, int *patoms, int *fallback, int *nfallback,
+                           ChunkLds &S, unsigned long long *cnt) {
+    const int tid = threadIdx.x;
+    const double h = m.h, rho = m.rho;
+    const double half = 0.5 * h + 1e-9;
+    if (tid < n) {
+        long long q = order[g0 + tid];
+        long long key = keys[q];
+        EdgeGeom G = edge_geom(m, L, key);
+        S.eq[tid] = q;
+        S.xs[tid][0] = G.xs[0];
+        S.xs[tid][1] = G.xs[1];
+        S.xs[tid][2] = G.xs[2];
+        S.einfo[tid] = (int)(key % 3) | (G.Ls << 2) | (G.Lt << 3);
+        S.ecount[tid] = 0;
+        if (tid == 0) S.tile = G.tile;
+    }
+    if (tid == 0) {
+        S.nf = 0;
+        S.ovf = 0;
+    }
+    __syncthreads();
+    const int tile = S.tile;
+    const int a0 = m.tA_off[tile];
+    const int nAst = min(CH_ATOMS, m.tA_off[tile + 1] - a0);
+    for (int q = tid; q < nAst; q += CH_THREADS) S.atoms[q] = m.atom[m.tA[a0 + q]];
+    const int ns_all = tile_surfaces(m, tile);
+    for (int sb = 0; sb < ns_all; sb += CH_SURF) {
+        const int ns = min(CH_SURF, ns_all - sb);
+        // stage the pass's surfaces and as many of their cut planes as fit
+        int key = 0, cb = 0, ce = 0;
+        const double4 *gc = nullptr;
+        if (tid < ns) {
+            key = tile_surface_key(m, tile, sb + tid);
+            S.skey[tid] = key;
+            S.sp[tid] = surf_params(m, key);
+            gc = global_cuts(m, key, &cb, &ce);
+        }
+        int total;
+        const int off = block_excl_scan<int, CH_THREADS>(ce - cb, S.scan, &total);
+        if (tid < ns) {
+            if (off + (ce - cb) <= CH_CUTS) {
+                for (int c = cb; c < ce; ++c) S.cut[off + c - cb] = gc[c];
+                S.crange[tid] = make_int2(off, off + ce - cb);
+            } else {
+                S.crange[tid] = make_int2(-1 - cb, ce);
+            }
+        }
+        __syncthreads();
+        const int npairs = n * ns;
+        int pb = 0;
+        while (pb < npairs) {
+            if (tid == 0) {
+                S.npair_s = 0;
+                S.npair_t = 0;
+            }
+            __syncthreads();
+            // reach tests until the queue could not take another round (a
+            // round adds at most CH_THREADS pairs); the length is read between
+            // two barriers, so every thread takes the same decision
+            for (;;) {
+                int p = pb + tid;
+                if (p < npairs) {
+                    int ei = p % n, si = p / n;
+                    int type = S.skey[si] >> 28;
+                    double mid[3];
+                    int axis = S.einfo[ei] & 3;
+                    for (int a = 0; a < 3; ++a)
+                        mid[a] = S.xs[ei][a] + (a == axis ? 0.5 * h : 0.0);
+                    if (CNT) ++cnt[type == 2 ? EC_REACH_TORUS : EC_REACH_SPHERE];
+                    if (surf_reaches(type, S.sp[si], rho, mid, half)) {
+                        unsigned short v = (unsigned short)(ei | (si << 6));
+                        if (type == 2) S.pair[CH_PAIRS - 1 - atomicAdd(&S.npair_t, 1)] = v;
+                        else S.pair[atomicAdd(&S.npair_s, 1)] = v;
+                    }
+                }
+                pb += CH_THREADS;
+                __syncthreads();
+                const int queued = S.npair_s + S.npair_t;
+                __syncthreads();
+                if (pb >= npairs || queued + CH_THREADS > CH_PAIRS) break;
+            }
+            // one thread per queued pair: tori first, then spheres
+            const int nt = S.npair_t, nq = nt + S.npair_s;
+            for (int j = tid; j < nq; j += CH_THREADS) {
+                unsigned short v = j < nt ? S.pair[CH_PAIRS - 1 - j] : S.pair[j - nt];
+                const int ei = v & 63, si = v >> 6;
+                const int skey = S.skey[si];
+                const SurfParams sp = S.sp[si];
+                const int axis = S.einfo[ei] & 3;
+                const double xs[3] = {S.xs[ei][0], S.xs[ei][1], S.xs[ei][2]};
+                const double e[3] = {axis == 0 ? 1.0 : 0.0, axis == 1 ? 1.0 : 0.0,
+                                     axis == 2 ? 1.0 : 0.0};
+                int nr = 0;
+                surface_roots<CNT>(
+                    skey >> 28, sp, h, rho, e, xs,
+                    [&](double u) {
+                        if (nr < CH_SLOTS) S.slot[nr][tid] = u;
+                        ++nr;
+                    },
+                    cnt);
+                if (nr > CH_SLOTS) {
+                    S.ovf = 1;
+                    nr = CH_SLOTS;
+                }
+                int scb, sce;
+                const double4 *cuts = staged_cuts(m, S, si, &scb, &sce);
+                for (int r = 0; r < nr; ++r) {
+                    double u = S.slot[r][tid];
+                    if (root_admissible<CNT>(m, skey, sp, cuts, scb, sce, u, e, xs, cnt)) {
+                        int pos = atomicAdd(&S.nf, 1);
+                        if (pos < CH_ROOTS) {
+                            S.fu[pos] = u;
+                            S.fk[pos] = skey;
+                            S.fe[pos] = (unsigned char)ei;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // too many roots for the chunk's lists: its edges go to the wavefront kernel
+    if (S.ovf || S.nf > CH_ROOTS) {
+        if (tid == 0) S.fb_base = atomicAdd(nfallback, n);
+        __syncthreads();
+        if (tid < n) fallback[S.fb_base + tid] = (int)S.eq[tid];
+        return;
+    }
+    // group the roots by edge (counting sort)
+    const int nf = S.nf;
+    for (int j = tid; j < nf; j += CH_THREADS) atomicAdd(&S.ecount[S.fe[j]], 1);
+    __syncthreads();
+    if (tid < WAVE) {
+        int c = tid < n ? S.ecount[tid] : 0;
+        int incl = wave_incl_scan(c);
+        if (tid < n) {
+            S.eoff[tid] = incl - c;
+            S.ecount[tid] = incl - c;  // fill cursor
+        }
+    }
+    __syncthreads();
+    for (int j = tid; j < nf; j += CH_THREADS) S.perm[atomicAdd(&S.ecount[S.fe[j]], 1)] = (unsigned short)j;
+    __syncthreads();
+    if (tid >= n) return;
+    // one thread per edge: sort its roots by (u, key), walk, write the record
+    const int o = S.eoff[tid], ne = S.ecount[tid] - o;
+    for (int a = 1; a < ne; ++a) {
+        unsigned short v = S.perm[o + a];
+        double u = S.fu[v];
+        int k = S.fk[v];
+        int b = a - 1;
+        while (b >= 0) {
+            unsigned short w = S.perm[o + b];
+            double uw = S.fu[w];
+            if (uw < u || (uw == u && S.fk[w] <= k)) break;
+            S.perm[o + b + 1] = w;
+            --b;
+        }
+        S.perm[o + b + 1] = v;
+    }
+    EdgeGeom G;
+    const int info = S.einfo[tid];
+    const int axis = info & 3;
+    for (int a = 0; a < 3; ++a) {
+        G.xs[a] = S.xs[tid][a];
+        G.e[a] = a == axis ? 1.0 : 0.0;
+    }
+    G.tile = tile;
+    G.Ls = (info >> 2) & 1;
+    G.Lt = (info >> 3) & 1;
+    // the staged surfaces serve the labels when the tile had a single pass
+    const bool staged = ns_all <= CH_SURF;
+    const int nF = m.tF_off[tile + 1] - m.tF_off[tile];
+    const int nV = m.tV_off[tile + 1] - m.tV_off[tile];
+    int owner = -1;
+    const double ustar = walk_roots<CNT>(
+        ne,
+        [&](int r, double &u, int &k) {
+            unsigned short v = S.perm[o + r];
+            u = S.fu[v];
+            k = S.fk[v];
+        },
+        G.Ls, G.Lt, G.xs, G.e, h,
+        [&](double x, double y, double z) {
+            return staged ? label_chunk<CNT>(m, S, tile, nAst, nF, nV, ns_all, x, y, z, cnt)
+                          : label_fp64_t<CNT>(m, tile, x, y, z, CNT ? cnt + EC_L_ATOM : nullptr);
+        },
+        &owner, cnt);
+    if (CNT) {
+        ++cnt[EC_EDGES];
+        return;
+    }
+    write_record(m, S.eq[tid], G, ustar, owner, lam, nrm, ptype, patoms);
+}
+
+// Chunk c covers positions [CH_EDGES c, CH_EDGES c + n) of `order`, all in
+// one tile (each tile's segment is padded to a multiple of CH_EDGES).  The
+// grid is a multiple of the XCD count; XCD x takes the x-th contiguous range
+// of chunks, so that neighbouring tiles share an L2.
+template <bool CNT>
+__global__ void __launch_bounds__(CH_THREADS)
+    k_edge_chunks(Mol m, const uint8_t *L, const long long *keys, const int *order,
+                  const int *tcount, const int *coff, double *lam, double *nrm, uint8_t *ptype,
+                  int *patoms, int *fallback, int *nfallback, unsigned long long *work) {
+    __shared__ ChunkLds S;
+    unsigned long long cnt[CNT ? EC_COUNT + 1 : 1];
+    for (int c = 0; c < (CNT ? (int)EC_COUNT + 1 : 1); ++c) cnt[c] = 0;
+    const int nch = coff[m.ntiles];
+    const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
+    const int per_xcd = (int)(gridDim.x / NXCD);
+    const int per = (nch + NXCD - 1) / NXCD;
+    const int cend = min(nch, (xcd + 1) * per);
+    for (int c = xcd * per + slot; c < cend; c += per_xcd) {
+        const int g0 = c * CH_EDGES;
+        // the chunk's tile and edge count
+        const int t = edge_tile(m, keys[order[g0]]);
+        const int n = min(CH_EDGES, tcount[t] - (g0 - coff[t] * CH_EDGES));
+        edge_chunk<CNT>(m, L, keys, order, g0, n, lam, nrm, ptype, patoms, fallback, nfallback,
+                        S, cnt);
+        __syncthreads();
+    }
+    if (CNT)
+        for (int c = 0; c < EC_COUNT; ++c)
+            if (cnt[c]) atomicAdd(&work[c], cnt[c]);
+}
+
+// ------------------------------------------------ roots, one wavefront per edge
+//
+// For the edges of chunks whose root lists overflow: one wavefront per edge,
+// with up to EW_SURF reaching surfaces and EW_ROOTS roots.  Lanes gather the
+// reaching surfaces, each lane solves one surface, one lane per root tests
+// admissibility, the roots are rank-sorted in LDS and the walk runs on every
+// lane (uniformly).  The arithmetic is that of the chunk path.
+constexpr int EW_WAVES = 4;
+constexpr int EW_THREADS = EW_WAVES * WAVE;
+constexpr int EW_SURF = 256;
+constexpr int EW_ROOTS = 256;
+
+struct EdgeWaveLds {
+    int surf[EW_SURF];
+    double u[EW_ROOTS];
+    int k[EW_ROOTS];
+    double su[EW_ROOTS];
+    int sk[EW_ROOTS];
+    int nroot;
+};
+
+template <bool CNT>
+__device__ void edge_wave(const Mol &m, const uint8_t *L, const long long *keys, long long q,
+                          double *lam, double *nrm, uint8_t *ptype, int *patoms, int *overflow,
+                          EdgeWaveLds &S, unsigned long long *cnt) {
+    const int lane = lane_id();
+    const long long key = keys[q];
+    const EdgeGeom G = edge_geom(m, L, key);
+    const int tile = G.tile;
+    const double h = m.h, rho = m.rho;
+    const double hh = 0.5 * h;
+    const double mid[3] = {G.xs[0] + hh * G.e[0], G.xs[1] + hh * G.e[1], G.xs[2] + hh * G.e[2]};
+    const double half = 0.5 * h + 1e-9;
+    bool ovf = false;
+    if (lane == 0) S.nroot = 0;
+    // 1. reaching surfaces, compacted with ballots
+    const int ns_all = tile_surfaces(m, tile);
+    int ns = 0;
+    for (int base = 0; base < ns_all; base += WAVE) {
+        int s = base + lane;
+        bool r = false;
+        int key = 0;
+        if (s < ns_all) {
+            key = tile_surface_key(m, tile, s);
+            int type = key >> 28;
+            if (CNT) ++cnt[type == 2 ? EC_REACH_TORUS : EC_REACH_SPHERE];
+            r = surf_reaches(type, surf_params(m, key), rho, mid, half);
+        }
+        unsigned long long bm = __ballot(r);
+        int pos = ns + mask_prefix(bm);
+        if (r && pos < EW_SURF) S.surf[pos] = key;
+        ns += __popcll(bm);
+    }
+    if (ns > EW_SURF) {
+        ovf = true;
+        ns = EW_SURF;
+    }
+    wave_sync();
+    // 2. one surface per lane, every root in [0, 1] appended
+    for (int sb = 0; sb < ns; sb += WAVE) {
+        int si = sb + lane;
+        if (si < ns) {
+            const int key = S.surf[si];
+            surface_roots<CNT>(
+                key >> 28, surf_params(m, key), h, rho, G.e, G.xs,
+                [&](double u) {
+                    int pos = atomicAdd(&S.nroot, 1);
+                    if (pos < EW_ROOTS) {
+                        S.u[pos] = u;
+                        S.k[pos] = key;
+                    }
+                },
+                cnt);
+        }
+    }
+    wave_sync();
+    int nraw = S.nroot;
+    if (nraw > EW_ROOTS) {
+        ovf = true;
+        nraw = EW_ROOTS;
+    }
+    // 3. one root per lane: admissible ones compacted into (su, sk)
+    int nr = 0;
+    for (int b = 0; b < nraw; b += WAVE) {
+        int r = b + lane;
+        bool keep = false;
+        double u = 0.0;
+        int k = 0;
+        if (r < nraw) {
+            u = S.u[r];
+            k = S.k[r];
+            int cb, ce;
+            const double4 *cuts = global_cuts(m, k, &cb, &ce);
+            keep = root_admissible<CNT>(m, k, surf_params(m, k), cuts, cb, ce, u, G.e, G.xs, cnt);
+        }
+        unsigned long long bm = __ballot(keep);
+        if (keep) {
+            int pos = nr + mask_prefix(bm);
+            S.su[pos] = u;
+            S.sk[pos] = k;
+        }
+        nr += __popcll(bm);
+    }
+    wave_sync();
+    // 4. rank sort by (u, key) from (su, sk) into (u, k)
+    for (int b = 0; b < nr; b += WAVE) {
+        int r = b + lane;
+        if (r < nr) {
+            double u = S.su[r];
+            int k = S.sk[r];
+            int rank = 0;
+            for (int p = 0; p < nr; ++p) {
+                double up = S.su[p];
+                int kp = S.sk[p];
+                rank += (up < u || (up == u && (kp < k || (kp == k && p < r)))) ? 1 : 0;
+            }
+            S.u[rank] = u;
+            S.k[rank] = k;
+        }
+    }
+    wave_sync();
+    // 5. the walk, the same on every lane; lane 0 counts and writes
+    unsigned long long dummy[EC_COUNT + 1];
+    unsigned long long *lc = lane == 0 ? cnt : dummy;
+    int owner = -1;
+    const double ustar = walk_roots<CNT>(
+        nr,
+        [&](int r, double &u, int &k) {
+            u = S.u[r];
+            k = S.k[r];
+        },
+        G.Ls, G.Lt, G.xs, G.e, h,
+        [&](double x, double y, double z) {
+            return label_fp64_t<CNT>(m, tile, x, y, z, lc + EC_L_ATOM);
+        },
+        &owner, lc);
+    if (__any(ovf) && lane == 0) *overflow = 1;
+    if (CNT) {
+        if (lane == 0) ++cnt[EC_EDGES];
+        return;
+    }
+    if (lane == 0) write_record(m, q, G, ustar, owner, lam, nrm, ptype, patoms);
+}
+
+template <bool CNT>
+__global__ void __launch_bounds__(EW_THREADS)
+    k_edge_wave(Mol m, const uint8_t *L, const long long *keys, const int *list,
+                const int *nlist, double *lam, double *nrm, uint8_t *ptype, int *patoms,
+                int *overflow, unsigned long long *work) {
+    __shared__ EdgeWaveLds lds[EW_WAVES];
+    const int w = threadIdx.x / WAVE;
+    unsigned long long cnt[CNT ? EC_COUNT + 1 : 1];
+    for (int c = 0; c < (CNT ? (int)EC_COUNT + 1 : 1); ++c) cnt[c] = 0;
+    const int n = *nlist;
+    for (int g = blockIdx.x * EW_WAVES + w; g < n; g += gridDim.x * EW_WAVES) {
+        edge_wave<CNT>(m, L, keys, list[g], lam, nrm, ptype, patoms, overflow, lds[w], cnt);
+        wave_sync();
+    }
+    if (CNT)
+        for (int c = 0; c < EC_COUNT; ++c)
+            if (cnt[c]) atomicAdd(&work[c], cnt[c]);
+}
+
+// ------------------------------------------------ grouping by tile, launches
+
 __global__ void k_edge_tile_count(Mol m, const long long *keys, long long count, int *tcount) {
     long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (q >= count) return;
     atomicAdd(&tcount[edge_tile(m, keys[q])], 1);
 }
 
-__global__ void k_edge_tile_scatter(Mol m, const long long *keys, long long count, int *tfill,
-                                    int *order) {
+__global__ void k_edge_chunk_count(const int *tcount, int ntiles, int *ccount) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < ntiles) ccount[t] = (tcount[t] + CH_EDGES - 1) / CH_EDGES;
+}
+
+__global__ void k_edge_tile_scatter(Mol m, const long long *keys, long long count,
+                                    const int *coff, int *tfill, int *order) {
     long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (q >= count) return;
-    order[atomicAdd(&tfill[edge_tile(m, keys[q])], 1)] = (int)q;
+    int t = edge_tile(m, keys[q]);
+    order[(long long)coff[t] * CH_EDGES + atomicAdd(&tfill[t], 1)] = (int)q;
+}
+
+long long edge_order_capacity(const Mol &m, long long count) {
+    return count + (long long)(CH_EDGES - 1) * std::min<long long>(m.ntiles, count);
 }
 
 hipError_t launch_edge_group(const Mol &m, const long long *keys, long long count, int *tcount,
-                             int *tfill, int *order, int *tmp, hipStream_t st) {
+                             int *ccount, int *coff, int *tfill, int *order, int *tmp,
+                             hipStream_t st) {
     if (count <= 0) return hipSuccess;
     unsigned nb = (unsigned)((count + 255) / 256);
     hipError_t e = fill_i32(tcount, m.ntiles + 1, 0, st);
+    if (e == hipSuccess) e = fill_i32(tfill, m.ntiles + 1, 0, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_edge_tile_count, dim3(nb), dim3(256), 0, st, m, keys, count, tcount);
-    e = scan_i32(tcount, m.ntiles, tfill, tmp, st);
+    hipLaunchKernelGGL(k_edge_chunk_count, dim3((m.ntiles + 255) / 256), dim3(256), 0, st,
+                       tcount, m.ntiles, ccount);
+    e = scan_i32(ccount, m.ntiles, coff, tmp, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_edge_tile_scatter, dim3(nb), dim3(256), 0, st, m, keys, count, tfill,
-                       order);
+    hipLaunchKernelGGL(k_edge_tile_scatter, dim3(nb), dim3(256), 0, st, m, keys, count, coff,
+                       tfill, order);
     return hipGetLastError();
 }
 
@@ -770,26 +1122,52 @@ hipError_t launch_edge_detect_write(const uint8_t *L, const Mol &m, const long l
     return hipGetLastError();
 }
 
-hipError_t launch_edge_roots(const Mol &m, const uint8_t *L, const long long *keys,
-                             long long count, double *lam, double *nrm, uint8_t *ptype,
-                             int *patoms, int *overflow, const int *order, hipStream_t st) {
+// Chunk kernel over every chunk, then the wavefront kernel over the edges of
+// chunks that overflowed (normally none).  With work != nullptr the
+// statistics variants run and no record is written.
+static hipError_t edge_roots_impl(const Mol &m, const uint8_t *L, const long long *keys,
+                                  long long count, const int *order, const int *tcount,
+                                  const int *coff, double *lam, double *nrm, uint8_t *ptype,
+                                  int *patoms, int *fallback, int *nfallback, int *overflow,
+                                  unsigned long long *work, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    int nb = (int)((count + EW_WAVES - 1) / EW_WAVES);
-    nb = (nb + NXCD - 1) / NXCD * NXCD;
-    hipLaunchKernelGGL(k_edge_roots<false>, dim3(nb), dim3(EW_THREADS), 0, st, m, L, keys, count,
-                       lam, nrm, ptype, patoms, overflow, order, nb, nullptr);
+    hipError_t e = fill_i32(nfallback, 1, 0, st);
+    if (e != hipSuccess) return e;
+    long long chunks_max = (count + CH_EDGES - 1) / CH_EDGES + std::min<long long>(m.ntiles, count);
+    long long grid = std::min<long long>(chunks_max, 2048);
+    grid = (grid + NXCD - 1) / NXCD * NXCD;
+    if (work)
+        hipLaunchKernelGGL(k_edge_chunks<true>, dim3((unsigned)grid), dim3(CH_THREADS), 0, st, m,
+                           L, keys, order, tcount, coff, lam, nrm, ptype, patoms, fallback,
+                           nfallback, work);
+    else
+        hipLaunchKernelGGL(k_edge_chunks<false>, dim3((unsigned)grid), dim3(CH_THREADS), 0, st,
+                           m, L, keys, order, tcount, coff, lam, nrm, ptype, patoms, fallback,
+                           nfallback, work);
+    if (work)
+        hipLaunchKernelGGL(k_edge_wave<true>, dim3(256), dim3(EW_THREADS), 0, st, m, L, keys,
+                           fallback, nfallback, lam, nrm, ptype, patoms, overflow, work);
+    else
+        hipLaunchKernelGGL(k_edge_wave<false>, dim3(256), dim3(EW_THREADS), 0, st, m, L, keys,
+                           fallback, nfallback, lam, nrm, ptype, patoms, overflow, work);
     return hipGetLastError();
 }
 
+hipError_t launch_edge_roots(const Mol &m, const uint8_t *L, const long long *keys,
+                             long long count, const int *order, const int *tcount,
+                             const int *coff, double *lam, double *nrm, uint8_t *ptype,
+                             int *patoms, int *fallback, int *nfallback, int *overflow,
+                             hipStream_t st) {
+    return edge_roots_impl(m, L, keys, count, order, tcount, coff, lam, nrm, ptype, patoms,
+                           fallback, nfallback, overflow, nullptr, st);
+}
+
 hipError_t launch_edge_work(const Mol &m, const uint8_t *L, const long long *keys,
-                            long long count, const int *order, int *overflow,
+                            long long count, const int *order, const int *tcount,
+                            const int *coff, int *fallback, int *nfallback, int *overflow,
                             unsigned long long *work, hipStream_t st) {
-    if (count <= 0) return hipSuccess;
-    int nb = (int)((count + EW_WAVES - 1) / EW_WAVES);
-    nb = (nb + NXCD - 1) / NXCD * NXCD;
-    hipLaunchKernelGGL(k_edge_roots<true>, dim3(nb), dim3(EW_THREADS), 0, st, m, L, keys, count,
-                       nullptr, nullptr, nullptr, nullptr, overflow, order, nb, work);
-    return hipGetLastError();
+    return edge_roots_impl(m, L, keys, count, order, tcount, coff, nullptr, nullptr, nullptr,
+                           nullptr, fallback, nfallback, overflow, work, st);
 }
 
 }  // namespace eses

@@ -49,15 +49,26 @@ hipError_t launch_edge_detect_count(const uint8_t *L, const Mol &m, int *bcount,
                                     hipStream_t st);
 hipError_t launch_edge_detect_write(const uint8_t *L, const Mol &m, const long long *boff,
                                     long long cap, long long *keys, hipStream_t st);
+// Crossing edges grouped by tile: order[] holds, per tile, its edges padded
+// to a multiple of the chunk size (edge_order_capacity entries); coff[t] is
+// the tile's first chunk and coff[ntiles] the number of chunks.
+long long edge_order_capacity(const Mol &m, long long count);
 hipError_t launch_edge_group(const Mol &m, const long long *keys, long long count, int *tcount,
-                             int *tfill, int *order, int *tmp, hipStream_t st);
+                             int *ccount, int *coff, int *tfill, int *order, int *tmp,
+                             hipStream_t st);
+// fallback: count ints; nfallback, overflow: one int each (overflow is set,
+// not cleared).
 hipError_t launch_edge_roots(const Mol &m, const uint8_t *L, const long long *keys,
-                             long long count, double *lam, double *nrm, uint8_t *ptype,
-                             int *patoms, int *overflow, const int *order, hipStream_t st);
+                             long long count, const int *order, const int *tcount,
+                             const int *coff, double *lam, double *nrm, uint8_t *ptype,
+                             int *patoms, int *fallback, int *nfallback, int *overflow,
+                             hipStream_t st);
 
 hipError_t launch_edge_work(const Mol &m, const uint8_t *L, const long long *keys,
-                            long long count, const int *order, int *overflow,
+                            long long count, const int *order, const int *tcount,
+                            const int *coff, int *fallback, int *nfallback, int *overflow,
                             unsigned long long *work, hipStream_t st);
+
 constexpr int EDGE_WORK_COUNTERS = 14;
 
 // vertex export
