@@ -346,19 +346,20 @@ __device__ inline int find_circle(const Mol &m, int a, int b) {
 // k ascending, "+" before "-".
 constexpr int VX_WAVES = 4;
 
+// The concave probe positions on circle c = (i, j): for each neighbour k of
+// i above j, the two points of the circle at distance s_k from c_k, kept if
+// no other neighbour's SAS ball holds them (i's neighbours 0..nst-1 from
+// LDS, the rest from global memory).
 template <bool FILL>
-__global__ void __launch_bounds__(VX_WAVES *WAVE) k_vertex(Mol m, int *vcnt) {
-    int c = blockIdx.x * VX_WAVES + threadIdx.x / WAVE;
-    if (c >= m.ncirc) return;  // uniform across the wavefront
-    const int lane = lane_id();
-    int i = m.circ_i[c], j = m.circ_j[c];
+__device__ void vertex_circle(const Mol &m, int c, int i, int nb, int ne, int nst,
+                              const double4 *nat, const int *nid, int lane, int *vcnt) {
+    int j = m.circ_j[c];
     double4 oR = m.circ_oR[c];
     double4 n = m.circ_n[c];
     double R = oR.w;
     int count = 0;
     int wv = FILL ? m.vert_off[c] : 0, ev = FILL ? m.vert_off[c + 1] : 0;
     uint32_t lflag = 0;
-    int nb = m.nbr_off[i], ne = m.nbr_off[i + 1];
     // first neighbour above j (the list is ascending and holds j)
     int lo = nb, hi = ne;
     while (lo < hi) {
@@ -398,16 +399,23 @@ __global__ void __launch_bounds__(VX_WAVES *WAVE) k_vertex(Mol m, int *vcnt) {
             }
         }
         bool ok0 = live, ok1 = live;
-        for (int q2 = nb; q2 < ne; ++q2) {
+        for (int q2 = 0; q2 < ne - nb; ++q2) {
             if (!__any(ok0 || ok1)) break;
-            int l = m.nbr_cov[q2];
-            double4 al = m.atom[l];
-            double sl2 = sq(al.w + m.rho);
+            int l;
+            double4 al;
+            if (q2 < nst) {
+                l = nid[q2];
+                al = nat[q2];
+            } else {
+                l = m.nbr_cov[nb + q2];
+                double4 a = m.atom[l];
+                al = make_double4(a.x, a.y, a.z, sq(a.w + m.rho));
+            }
             if (l == j || l == k) continue;
             double d0 = sq(v0x - al.x) + sq(v0y - al.y) + sq(v0z - al.z);
             double d1 = sq(v1x - al.x) + sq(v1y - al.y) + sq(v1z - al.z);
-            ok0 = ok0 && !(d0 < sl2);
-            ok1 = ok1 && !(d1 < sl2);
+            ok0 = ok0 && !(d0 < al.w);
+            ok1 = ok1 && !(d1 < al.w);
         }
         unsigned long long b0 = __ballot(ok0), b1 = __ballot(ok1);
         if (FILL) {
@@ -450,6 +458,33 @@ __global__ void __launch_bounds__(VX_WAVES *WAVE) k_vertex(Mol m, int *vcnt) {
                 atomicOr(&m.aflag[j], AF_EXPOSED_VERTEX);
             }
         }
+    }
+}
+
+constexpr int VX_NBR = 256;  // neighbours of atom i staged in LDS
+
+// One workgroup per atom i, one wavefront per circle (i, j) of i; i's
+// neighbours (cover order) are staged in LDS for the exposure tests.
+template <bool FILL>
+__global__ void __launch_bounds__(VX_WAVES *WAVE) k_vertex(Mol m, int *vcnt) {
+    __shared__ double4 nat[VX_NBR];  // x, y, z, (r + rho)^2
+    __shared__ int nid[VX_NBR];
+    const int i = blockIdx.x;
+    const int c0 = m.circ_off[i], c1 = m.circ_off[i + 1];
+    if (c0 == c1) return;  // uniform across the workgroup
+    const int nb = m.nbr_off[i], ne = m.nbr_off[i + 1];
+    const int nst = min(VX_NBR, ne - nb);
+    for (int q = threadIdx.x; q < nst; q += VX_WAVES * WAVE) {
+        int l = m.nbr_cov[nb + q];
+        double4 al = m.atom[l];
+        nat[q] = make_double4(al.x, al.y, al.z, sq(al.w + m.rho));
+        nid[q] = l;
+    }
+    __syncthreads();
+    const int lane = lane_id();
+    for (int c = c0 + threadIdx.x / WAVE; c < c1; c += VX_WAVES) {
+        if (FILL && m.vert_off[c + 1] == m.vert_off[c]) continue;  // no probe position here
+        vertex_circle<FILL>(m, c, i, nb, ne, nst, nat, nid, lane, vcnt);
     }
 }
 
@@ -770,11 +805,10 @@ hipError_t launch_nbr_sort(const Mol &m, hipStream_t st) {
 
 hipError_t launch_vertex(const Mol &m, bool fill, int *vcnt, hipStream_t st) {
     if (m.ncirc <= 0) return hipSuccess;
-    unsigned nb = blocks_for(m.ncirc, VX_WAVES);
     if (fill)
-        hipLaunchKernelGGL(k_vertex<true>, dim3(nb), dim3(VX_WAVES * WAVE), 0, st, m, vcnt);
+        hipLaunchKernelGGL(k_vertex<true>, dim3(m.n), dim3(VX_WAVES * WAVE), 0, st, m, vcnt);
     else
-        hipLaunchKernelGGL(k_vertex<false>, dim3(nb), dim3(VX_WAVES * WAVE), 0, st, m, vcnt);
+        hipLaunchKernelGGL(k_vertex<false>, dim3(m.n), dim3(VX_WAVES * WAVE), 0, st, m, vcnt);
     return hipGetLastError();
 }
 

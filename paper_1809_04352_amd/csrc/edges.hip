@@ -212,11 +212,22 @@ __device__ void quartic01(const double *g, Emit emit, unsigned long long *cnt) {
 // ------------------------------------------------ admissibility of roots
 
 // Every cut of cuts[b, e) passes for the direction p (scaled by s):
-// p . v <= s v.w.  cc: the counter of the tests (statistics pass).
-template <bool CNT>
+// p . v <= s v.w.  UNROLL: four cuts are fetched before they are tested, so
+// that their loads overlap.  cc: the counter of the tests (statistics pass).
+template <bool CNT, bool UNROLL = false>
 __device__ inline bool cuts_pass(const double4 *cuts, int b, int e, double px, double py,
                                  double pz, double s, unsigned long long *cc) {
-    for (int c = b; c < e; ++c) {
+    int c = b;
+    for (; UNROLL && c + 4 <= e; c += 4) {
+        double4 v0 = cuts[c], v1 = cuts[c + 1], v2 = cuts[c + 2], v3 = cuts[c + 3];
+        if (CNT) *cc += 4;
+        bool out = (px * v0.x + py * v0.y + pz * v0.z > s * v0.w) |
+                   (px * v1.x + py * v1.y + pz * v1.z > s * v1.w) |
+                   (px * v2.x + py * v2.y + pz * v2.z > s * v2.w) |
+                   (px * v3.x + py * v3.y + pz * v3.z > s * v3.w);
+        if (out) return false;
+    }
+    for (; c < e; ++c) {
         double4 v = cuts[c];
         if (CNT) ++*cc;
         if (px * v.x + py * v.y + pz * v.z > s * v.w) return false;
@@ -225,19 +236,18 @@ __device__ inline bool cuts_pass(const double4 *cuts, int b, int e, double px, d
 }
 
 // A point y of the sphere S_i seen from x along c_i -> x is admissible iff
-// (x - c_i) . v_k <= |x - c_i| tau_k for every cut of the face.
-template <bool CNT>
-__device__ inline bool face_admissible(const double4 *cuts, int b, int e, double dx, double dy,
-                                       double dz, unsigned long long *cc) {
+// (x - c_i) . v_k <= |x - c_i| tau_k for every cut of the face;
+// pass(px, py, pz, s) runs the face's cut tests.
+template <class Pass>
+__device__ inline bool face_admissible(Pass pass, double dx, double dy, double dz) {
     double d = sqrt(dx * dx + dy * dy + dz * dz);
-    return cuts_pass<CNT>(cuts, b, e, dx, dy, dz, d, cc);
+    return pass(dx, dy, dz, d);
 }
 
 // The circle point nearest to x (w = x - o) is admissible iff
 // w_perp . u_k <= |w_perp| T_k for every cut of the circle.
-template <bool CNT>
-__device__ inline bool circle_admissible(const double4 *cuts, int b, int e, double4 n, double wx,
-                                         double wy, double wz, unsigned long long *cc) {
+template <class Pass>
+__device__ inline bool circle_admissible(Pass pass, double4 n, double wx, double wy, double wz) {
     double t = wx * n.x + wy * n.y + wz * n.z;
     double px = wx - t * n.x, py = wy - t * n.y, pz = wz - t * n.z;
     double pb = sqrt(px * px + py * py + pz * pz);
@@ -245,7 +255,7 @@ __device__ inline bool circle_admissible(const double4 *cuts, int b, int e, doub
         perp_unit(n.x, n.y, n.z, px, py, pz);
         pb = 1.0;
     }
-    return cuts_pass<CNT>(cuts, b, e, px, py, pz, pb, cc);
+    return pass(px, py, pz, pb);
 }
 
 __device__ inline void sort3(int &a, int &b, int &c) {
@@ -303,6 +313,25 @@ __device__ inline bool surf_reaches(int type, const SurfParams &p, double rho, c
     return !(dc2 > sq(rho + half) || (rho > half && dc2 < sq(rho - half)));
 }
 
+// As surf_reaches, and in *rel whether the surface's candidate test of
+// eq. (2) can hold at some point of the edge: a probe within rho, a face's
+// projection within rho (|x - c| < r + 2 rho), a circle within rho.
+__device__ inline bool surf_reaches_rel(int type, const SurfParams &p, double rho,
+                                        const double *mid, double half, bool *rel) {
+    if (type != 2) {
+        double r = p.c.w;
+        double dm2 = sq(mid[0] - p.c.x) + sq(mid[1] - p.c.y) + sq(mid[2] - p.c.z);
+        *rel = dm2 < sq((type == 1 ? r + 2.0 * rho : rho) + half);
+        return !(dm2 > sq(r + half) || (r > half && dm2 < sq(r - half)));
+    }
+    double dm0 = mid[0] - p.c.x, dm1 = mid[1] - p.c.y, dm2 = mid[2] - p.c.z;
+    double tm = dm0 * p.n.x + dm1 * p.n.y + dm2 * p.n.z;
+    double bm = sqrt(fmax(0.0, dm0 * dm0 + dm1 * dm1 + dm2 * dm2 - tm * tm));
+    double dc2 = tm * tm + sq(bm - p.c.w);
+    *rel = dc2 < sq(rho + half);
+    return !(dc2 > sq(rho + half) || (rho > half && dc2 < sq(rho - half)));
+}
+
 // Roots in [0, 1] of one surface along the edge x(u) = xs + u h e, each
 // passed to sink(u): spheres |x(u) - c|^2 = r^2 (a quadratic), tori
 // (|w|^2 + R^2 - rho^2)^2 = 4 R^2 |w_perp|^2 of the circle's points at
@@ -341,24 +370,22 @@ __device__ void surface_roots(int type, const SurfParams &p, double h, double rh
 // der Waals roots) or the nearest point of the exposed circle on the near
 // branch of the torus (torus roots).  Every label change lies on such a
 // point, so dropping the others is exact.  Probe roots are always kept.
-template <bool CNT>
-__device__ bool root_admissible(const Mol &m, int key, const SurfParams &p, const double4 *cuts,
-                                int cb, int ce, double u, const double *e, const double *xs,
-                                unsigned long long *cnt) {
+template <class Pass>
+__device__ bool root_admissible(const Mol &m, int key, const SurfParams &p, Pass pass, double u,
+                                const double *e, const double *xs) {
     const int type = key >> 28;
     if (type == 3) return true;
     const double s = u * m.h;
     const double x0 = xs[0] - p.c.x + s * e[0], x1 = xs[1] - p.c.y + s * e[1],
                  x2 = xs[2] - p.c.z + s * e[2];
-    unsigned long long *cc = CNT ? cnt + EC_CUT : nullptr;
-    if (type == 1) return face_admissible<CNT>(cuts, cb, ce, x0, x1, x2, cc);
+    if (type == 1) return face_admissible(pass, x0, x1, x2);
     const double4 nn = p.n;
     const double R = p.c.w, rho = m.rho;
     double tt = x0 * nn.x + x1 * nn.y + x2 * nn.z;
     double bb = sqrt(fmax(0.0, x0 * x0 + x1 * x1 + x2 * x2 - tt * tt));
     double near = fabs(sq(bb - R) + tt * tt - rho * rho);
     double far = fabs(sq(bb + R) + tt * tt - rho * rho);
-    return near <= far && circle_admissible<CNT>(cuts, cb, ce, nn, x0, x1, x2, cc);
+    return near <= far && circle_admissible(pass, nn, x0, x1, x2);
 }
 
 // The cut planes of surface `key` in global memory: [*cb, *ce) of the
@@ -580,20 +607,23 @@ struct ChunkLds {
     unsigned short pair[CH_PAIRS];
     unsigned short perm[CH_ROOTS];
     unsigned char fe[CH_ROOTS];
+    // per edge: the staged atoms and surfaces whose label test can hold
+    // somewhere on the edge (bit masks over the staged arrays)
+    unsigned long long amask[CH_EDGES][CH_ATOMS / 64];
+    unsigned long long smask[CH_EDGES][CH_SURF / 64];
     int npair_s, npair_t, nf, ovf, tile, fb_base;
 };
 
-// Cut planes of staged surface s: LDS or global memory.
-__device__ inline const double4 *staged_cuts(const Mol &m, const ChunkLds &S, int s, int *cb,
-                                             int *ce) {
-    int2 r = S.crange[s];
-    *ce = r.y;
-    if (r.x >= 0) {
-        *cb = r.x;
-        return S.cut;
-    }
-    *cb = -1 - r.x;
-    return (S.skey[s] >> 28) == 1 ? m.face_cut : m.ec_cut;
+// The cut tests of staged surface s, on its planes in LDS or, where they did
+// not fit, in global memory.
+template <bool CNT>
+__device__ inline bool staged_cuts_pass(const Mol &m, const ChunkLds &S, int s, double px,
+                                        double py, double pz, double sc,
+                                        unsigned long long *cc) {
+    const int2 r = S.crange[s];
+    if (r.x >= 0) return cuts_pass<CNT>(S.cut, r.x, r.y, px, py, pz, sc, cc);
+    const double4 *g = (S.skey[s] >> 28) == 1 ? m.face_cut : m.ec_cut;
+    return cuts_pass<CNT>(g, -1 - r.x, r.y, px, py, pz, sc, cc);
 }
 
 // Inside/outside of x (eq. 2) from the staged tile data: the first nAst
@@ -639,9 +669,7 @@ __device__ int label_chunk(const Mol &m, const ChunkLds &S, int tile, int nAst, 
         if (CNT) ++cnt[EC_L_FACE];
         if (!(d2 < sr * sr)) continue;
         double d = sqrt(d2);
-        int cb, ce;
-        const double4 *cuts = staged_cuts(m, S, q, &cb, &ce);
-        if (cuts_pass<CNT>(cuts, cb, ce, dx, dy, dz, d, CNT ? cnt + EC_L_FACE_CUT : nullptr))
+        if (staged_cuts_pass<CNT>(m, S, q, dx, dy, dz, d, CNT ? cnt + EC_L_FACE_CUT : nullptr))
             return 0;
     }
     for (int q = nF + nV; q < ns; ++q) {
@@ -659,13 +687,79 @@ __device__ int label_chunk(const Mol &m, const ChunkLds &S, int tile, int nAst, 
             perp_unit(n.x, n.y, n.z, px, py, pz);
             pb = 1.0;
         }
-        int cb, ce;
-        const double4 *cuts = staged_cuts(m, S, q, &cb, &ce);
-        if (cuts_pass<CNT>(cuts, cb, ce, px, py, pz, pb, CNT ? cnt + EC_L_CIRCLE_CUT : nullptr))
+        if (staged_cuts_pass<CNT>(m, S, q, px, py, pz, pb, CNT ? cnt + EC_L_CIRCLE_CUT : nullptr))
             return 0;
     }
     return 1;
 }
+
+// label_chunk restricted to the atoms and surfaces of edge ei's masks: the
+// others fail their tests everywhere on the edge (distance bounds from the
+// edge's midpoint), so the result is the same.
+template <bool CNT>
+__device__ int label_masked(const Mol &m, const ChunkLds &S, int ei, int nF, int nV, double x,
+                            double y, double z, unsigned long long *cnt) {
+    const double rho = m.rho;
+    const double rho2 = rho * rho;
+    bool inU = false;
+    for (int w = 0; w < CH_ATOMS / 64; ++w) {
+        for (unsigned long long bits = S.amask[ei][w]; bits; bits &= bits - 1) {
+            double4 a = S.atoms[w * 64 + __builtin_ctzll(bits)];
+            double dx = x - a.x, dy = y - a.y, dz = z - a.z;
+            double d2 = dx * dx + dy * dy + dz * dz;
+            if (CNT) ++cnt[EC_L_ATOM];
+            if (d2 <= a.w * a.w) return 1;
+            double s = a.w + rho;
+            inU |= d2 < s * s;
+        }
+    }
+    if (!inU) return 0;
+    for (int w = 0; w < CH_SURF / 64; ++w) {
+        for (unsigned long long bits = S.smask[ei][w]; bits; bits &= bits - 1) {
+            const int q = w * 64 + __builtin_ctzll(bits);
+            if (q < nF) {
+                double4 a = S.sp[q].c;
+                double dx = x - a.x, dy = y - a.y, dz = z - a.z;
+                double d2 = dx * dx + dy * dy + dz * dz;
+                double sr = a.w + 2.0 * rho;
+                if (CNT) ++cnt[EC_L_FACE];
+                if (!(d2 < sr * sr)) continue;
+                double d = sqrt(d2);
+                if (staged_cuts_pass<CNT>(m, S, q, dx, dy, dz, d,
+                                          CNT ? cnt + EC_L_FACE_CUT : nullptr))
+                    return 0;
+            } else if (q < nF + nV) {
+                double4 p = S.sp[q].c;
+                double dx = x - p.x, dy = y - p.y, dz = z - p.z;
+                if (CNT) ++cnt[EC_L_VERTEX];
+                if (dx * dx + dy * dy + dz * dz < rho2) return 0;
+            } else {
+                double4 oR = S.sp[q].c;
+                double4 n = S.sp[q].n;
+                double wx = x - oR.x, wy = y - oR.y, wz = z - oR.z;
+                double t = wx * n.x + wy * n.y + wz * n.z;
+                double ww = wx * wx + wy * wy + wz * wz;
+                double b = sqrt(fmax(ww - t * t, 0.0));
+                double R = oR.w;
+                if (CNT) ++cnt[EC_L_CIRCLE];
+                if (!(ww + R * R - rho2 < 2.0 * b * R)) continue;
+                double px = wx, py = wy, pz = wz, pb = b;
+                if (!(b > 0.0)) {
+                    perp_unit(n.x, n.y, n.z, px, py, pz);
+                    pb = 1.0;
+                }
+                if (staged_cuts_pass<CNT>(m, S, q, px, py, pz, pb,
+                                          CNT ? cnt + EC_L_CIRCLE_CUT : nullptr))
+                    return 0;
+            }
+        }
+    }
+    return 1;
+}
+
+// Thread t's item within a block-wide round: items 4k .. 4k+3 go to lane k
+// of waves 0 .. 3, so that a short round still uses every SIMD.
+__device__ inline int spread(int t) { return (t % WAVE) * (CH_THREADS / WAVE) + t / WAVE; }
 
 template <bool CNT>
 __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys,
@@ -685,6 +779,8 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
         S.xs[tid][2] = G.xs[2];
         S.einfo[tid] = (int)(key % 3) | (G.Ls << 2) | (G.Lt << 3);
         S.ecount[tid] = 0;
+        for (int w = 0; w < CH_ATOMS / 64; ++w) S.amask[tid][w] = 0;
+        for (int w = 0; w < CH_SURF / 64; ++w) S.smask[tid][w] = 0;
         if (tid == 0) S.tile = G.tile;
     }
     if (tid == 0) {
@@ -694,9 +790,12 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
     __syncthreads();
     const int tile = S.tile;
     const int a0 = m.tA_off[tile];
-    const int nAst = min(CH_ATOMS, m.tA_off[tile + 1] - a0);
+    const int nA = m.tA_off[tile + 1] - a0;
+    const int nAst = min(CH_ATOMS, nA);
     for (int q = tid; q < nAst; q += CH_THREADS) S.atoms[q] = m.atom[m.tA[a0 + q]];
     const int ns_all = tile_surfaces(m, tile);
+    // one surface pass with every atom staged: labels from the per-edge masks
+    const bool filt = ns_all > 0 && ns_all <= CH_SURF && nA <= CH_ATOMS;
     for (int sb = 0; sb < ns_all; sb += CH_SURF) {
         const int ns = min(CH_SURF, ns_all - sb);
         // stage the pass's surfaces and as many of their cut planes as fit
@@ -719,9 +818,11 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
             }
         }
         __syncthreads();
+        // (edge, surface) pairs, then (edge, atom) pairs for the label masks
         const int npairs = n * ns;
+        const int ntests = npairs + (filt ? n * nAst : 0);
         int pb = 0;
-        while (pb < npairs) {
+        while (pb < ntests) {
             if (tid == 0) {
                 S.npair_s = 0;
                 S.npair_t = 0;
@@ -740,21 +841,39 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
                     for (int a = 0; a < 3; ++a)
                         mid[a] = S.xs[ei][a] + (a == axis ? 0.5 * h : 0.0);
                     if (CNT) ++cnt[type == 2 ? EC_REACH_TORUS : EC_REACH_SPHERE];
-                    if (surf_reaches(type, S.sp[si], rho, mid, half)) {
+                    bool rel;
+                    if (surf_reaches_rel(type, S.sp[si], rho, mid, half, &rel)) {
                         unsigned short v = (unsigned short)(ei | (si << 6));
                         if (type == 2) S.pair[CH_PAIRS - 1 - atomicAdd(&S.npair_t, 1)] = v;
                         else S.pair[atomicAdd(&S.npair_s, 1)] = v;
                     }
+                    if (rel) atomicOr(&S.smask[ei][si >> 6], 1ull << (si & 63));
+                } else if (p < ntests) {
+                    // atom whose SAS ball can hold a point of the edge
+                    int ei = (p - npairs) % n, ai = (p - npairs) / n;
+                    double4 a = S.atoms[ai];
+                    int axis = S.einfo[ei] & 3;
+                    double dm2 = 0.0;
+                    for (int c = 0; c < 3; ++c) {
+                        double mc = S.xs[ei][c] + (c == axis ? 0.5 * h : 0.0);
+                        double ac = c == 0 ? a.x : c == 1 ? a.y : a.z;
+                        dm2 += sq(mc - ac);
+                    }
+                    if (dm2 < sq(a.w + rho + half))
+                        atomicOr(&S.amask[ei][ai >> 6], 1ull << (ai & 63));
                 }
                 pb += CH_THREADS;
                 __syncthreads();
                 const int queued = S.npair_s + S.npair_t;
                 __syncthreads();
-                if (pb >= npairs || queued + CH_THREADS > CH_PAIRS) break;
+                if (pb >= ntests || queued + CH_THREADS > CH_PAIRS) break;
             }
-            // one thread per queued pair: tori first, then spheres
+            // one thread per queued pair: tori first, then spheres; pair j
+            // goes to wave j % 4, so that the costly tori spread over the SIMDs
             const int nt = S.npair_t, nq = nt + S.npair_s;
-            for (int j = tid; j < nq; j += CH_THREADS) {
+            for (int j0 = 0; j0 < nq; j0 += CH_THREADS) {
+                const int j = j0 + spread(tid);
+                if (j >= nq) continue;
                 unsigned short v = j < nt ? S.pair[CH_PAIRS - 1 - j] : S.pair[j - nt];
                 const int ei = v & 63, si = v >> 6;
                 const int skey = S.skey[si];
@@ -775,11 +894,13 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
                     S.ovf = 1;
                     nr = CH_SLOTS;
                 }
-                int scb, sce;
-                const double4 *cuts = staged_cuts(m, S, si, &scb, &sce);
+                auto pass = [&](double px, double py, double pz, double sc) {
+                    return staged_cuts_pass<CNT>(m, S, si, px, py, pz, sc,
+                                                 CNT ? cnt + EC_CUT : nullptr);
+                };
                 for (int r = 0; r < nr; ++r) {
                     double u = S.slot[r][tid];
-                    if (root_admissible<CNT>(m, skey, sp, cuts, scb, sce, u, e, xs, cnt)) {
+                    if (root_admissible(m, skey, sp, pass, u, e, xs)) {
                         int pos = atomicAdd(&S.nf, 1);
                         if (pos < CH_ROOTS) {
                             S.fu[pos] = u;
@@ -814,9 +935,11 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
     __syncthreads();
     for (int j = tid; j < nf; j += CH_THREADS) S.perm[atomicAdd(&S.ecount[S.fe[j]], 1)] = (unsigned short)j;
     __syncthreads();
-    if (tid >= n) return;
-    // one thread per edge: sort its roots by (u, key), walk, write the record
-    const int o = S.eoff[tid], ne = S.ecount[tid] - o;
+    // one thread per edge (edge e on wave e % 4): sort its roots by (u, key),
+    // walk, write the record
+    const int ei = spread(tid);
+    if (ei >= n) return;
+    const int o = S.eoff[ei], ne = S.ecount[ei] - o;
     for (int a = 1; a < ne; ++a) {
         unsigned short v = S.perm[o + a];
         double u = S.fu[v];
@@ -832,10 +955,10 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
         S.perm[o + b + 1] = v;
     }
     EdgeGeom G;
-    const int info = S.einfo[tid];
+    const int info = S.einfo[ei];
     const int axis = info & 3;
     for (int a = 0; a < 3; ++a) {
-        G.xs[a] = S.xs[tid][a];
+        G.xs[a] = S.xs[ei][a];
         G.e[a] = a == axis ? 1.0 : 0.0;
     }
     G.tile = tile;
@@ -855,15 +978,16 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
         },
         G.Ls, G.Lt, G.xs, G.e, h,
         [&](double x, double y, double z) {
-            return staged ? label_chunk<CNT>(m, S, tile, nAst, nF, nV, ns_all, x, y, z, cnt)
-                          : label_fp64_t<CNT>(m, tile, x, y, z, CNT ? cnt + EC_L_ATOM : nullptr);
+            return filt     ? label_masked<CNT>(m, S, ei, nF, nV, x, y, z, cnt)
+                   : staged ? label_chunk<CNT>(m, S, tile, nAst, nF, nV, ns_all, x, y, z, cnt)
+                            : label_fp64_t<CNT>(m, tile, x, y, z, CNT ? cnt + EC_L_ATOM : nullptr);
         },
         &owner, cnt);
     if (CNT) {
         ++cnt[EC_EDGES];
         return;
     }
-    write_record(m, S.eq[tid], G, ustar, owner, lam, nrm, ptype, patoms);
+    write_record(m, S.eq[ei], G, ustar, owner, lam, nrm, ptype, patoms);
 }
 
 // Chunk c covers positions [CH_EDGES c, CH_EDGES c + n) of `order`, all in
@@ -990,7 +1114,10 @@ __device__ void edge_wave(const Mol &m, const uint8_t *L, const long long *keys,
             k = S.k[r];
             int cb, ce;
             const double4 *cuts = global_cuts(m, k, &cb, &ce);
-            keep = root_admissible<CNT>(m, k, surf_params(m, k), cuts, cb, ce, u, G.e, G.xs, cnt);
+            auto pass = [&](double px, double py, double pz, double sc) {
+                return cuts_pass<CNT>(cuts, cb, ce, px, py, pz, sc, CNT ? cnt + EC_CUT : nullptr);
+            };
+            keep = root_admissible(m, k, surf_params(m, k), pass, u, G.e, G.xs);
         }
         unsigned long long bm = __ballot(keep);
         if (keep) {
