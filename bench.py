@@ -52,7 +52,8 @@ FLOPS_PER_TEST = {"tests_atom": 11, "tests_vertex": 8, "tests_face": 11, "tests_
 FLOPS_EDGE = {"reach_sphere": 12, "reach_torus": 23, "quad_solves": 18, "quartic_solves": 35,
               "horner_flops": 1, "cut_tests": 6, "n_edges": 30,
               "label_tests_atom": 11, "label_tests_vertex": 8, "label_tests_face": 11,
-              "label_tests_face_cut": 6, "label_tests_circle": 21, "label_tests_circle_cut": 6}
+              "label_tests_face_cut": 6, "label_tests_circle": 21, "label_tests_circle_cut": 6,
+              "cone_tests": 20}
 
 
 def parse():

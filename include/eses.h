@@ -202,6 +202,7 @@ typedef struct {
     int64_t cut_tests;        /* admissibility half-space tests of roots */
     int64_t label_evals;      /* labels evaluated between roots */
     int64_t label_tests[6];   /* their tests: atom, probe, face, face cut, circle, circle cut */
+    int64_t cone_tests;       /* cut planes tested against an edge's direction cone */
 } eses_edge_stats;
 
 /* Runs the edge statistics pass for every molecule of `c` with the labels

@@ -836,6 +836,7 @@ eses_status eses_edge_work(eses_candidates *c, const uint8_t *const *labels,
         o.cut_tests = (int64_t)h[6];
         o.label_evals = (int64_t)h[7];
         for (int k = 0; k < 6; ++k) o.label_tests[k] = (int64_t)h[8 + k];
+        o.cone_tests = (int64_t)h[15];
     }
     return ESES_OK;
 }

@@ -34,8 +34,15 @@ enum EdgeCounter {
     EC_L_FACE_CUT,
     EC_L_CIRCLE,
     EC_L_CIRCLE_CUT,
+    EC_L_SHELL,        // (label_fp64_t's case-3 tally; not reported)
+    EC_CONE,           // cut planes tested against an edge's direction cone
     EC_COUNT
 };
+// label_fp64_t tallies into cnt + EC_L_ATOM with the classification's layout
+static_assert(EC_L_CIRCLE_CUT - EC_L_ATOM == WC_CIRCLE_CUT - WC_ATOM &&
+                  EC_L_SHELL - EC_L_ATOM == WC_CASE_SHELL - WC_ATOM &&
+                  EC_L_FACE_CUT - EC_L_ATOM == WC_FACE_CUT - WC_ATOM,
+              "edge label counters must mirror the classification counters");
 
 __device__ inline int edge_flags(const uint8_t *L, long long idx, int i, int j, int k, int nx,
                                  int ny, int nz) {
@@ -584,20 +591,35 @@ constexpr int CH_EDGES = 64;
 constexpr int CH_THREADS = 256;
 constexpr int CH_SURF = 128;    // surfaces staged per pass
 constexpr int CH_PAIRS = 1024;  // queued (edge, surface) pairs per solve round
+constexpr int CH_ROUND = 512;   // reach tests between two reads of the queue length
 constexpr int CH_ROOTS = 512;   // admissible roots per chunk
 constexpr int CH_SLOTS = 4;     // roots of one quartic before the admissibility test
 constexpr int CH_ATOMS = 192;   // tile atoms staged for the labels
 constexpr int CH_CUTS = 384;    // cut planes of the staged surfaces
+constexpr int CH_Q = 256;       // label queries of a chunk evaluated together
 
 struct ChunkLds {
     SurfParams sp[CH_SURF];
     double4 atoms[CH_ATOMS];
     double4 cut[CH_CUTS];
     double xs[CH_EDGES][3];
-    double slot[CH_SLOTS][CH_THREADS];
+    union {
+        // solve phase: roots of one quartic per thread
+        double slot[CH_SLOTS][CH_THREADS];
+        // walk phase: label queries (edge, midpoint parameter), their test
+        // results (1 van der Waals ball, 2 SAS ball, 4 candidate within rho)
+        // and the offsets of their (query, candidate) tests
+        struct {
+            double qu[CH_Q];
+            int qflag[CH_Q];
+            int qoff[CH_Q + 1];
+            unsigned char qe[CH_Q];
+        } q;
+    };
     double fu[CH_ROOTS];
     int fk[CH_ROOTS];
     int skey[CH_SURF];
+    unsigned char sdead[CH_SURF];  // surface inadmissible throughout the tile
     int2 crange[CH_SURF];  // cut range in `cut`, or (-1 - begin, end) in global memory
     long long eq[CH_EDGES];
     int einfo[CH_EDGES];  // axis | Ls << 2 | Lt << 3
@@ -611,7 +633,7 @@ struct ChunkLds {
     // somewhere on the edge (bit masks over the staged arrays)
     unsigned long long amask[CH_EDGES][CH_ATOMS / 64];
     unsigned long long smask[CH_EDGES][CH_SURF / 64];
-    int npair_s, npair_t, nf, ovf, tile, fb_base;
+    int npair_s, npair_t, nf, ovf, tile, fb_base, nq, pool;
 };
 
 // The cut tests of staged surface s, on its planes in LDS or, where they did
@@ -757,6 +779,208 @@ __device__ int label_masked(const Mol &m, const ChunkLds &S, int ei, int nF, int
     return 1;
 }
 
+// The intervals of one edge's sorted roots whose label walk_roots may
+// evaluate, in its order: emit(u) with u the midpoint parameter.
+template <class RootAt, class Emit>
+__device__ inline void label_intervals(int n, RootAt root_at, Emit emit) {
+    double u0 = 0.0, ulast = 0.0;
+    int k0 = 0;
+    if (n > 0) {
+        root_at(0, u0, k0);
+        root_at(n - 1, ulast, k0);
+    }
+    const bool root0 = n > 0 && u0 == 0.0;
+    const bool root1 = n > 0 && ulast == 1.0;
+    double prev = 0.0;
+    for (int r = 0; r <= n; ++r) {
+        double next = 1.0;
+        int kn;
+        if (r < n) root_at(r, next, kn);
+        if (next > prev) {
+            if (!(prev == 0.0 && !root0) && !(r == n && !root1)) emit(0.5 * (prev + next));
+            prev = next;
+        }
+    }
+}
+
+// Test j of the label query at parameter um on edge e: the j-th atom or
+// surface of the edge's masks (atoms first).  Returns 1 if x lies in the
+// atom's van der Waals ball, 2 if in its SAS ball only, 4 if the surface's
+// candidate lies within rho; label_masked's tests, one at a time.
+template <bool CNT>
+__device__ int label_test(const Mol &m, const ChunkLds &S, int e, int j, double um, int nF,
+                          int nV, unsigned long long *cnt) {
+    const double rho = m.rho, rho2 = rho * rho, h = m.h;
+    const int axis = S.einfo[e] & 3;
+    const double us = um * h;
+    const double x = S.xs[e][0] + us * (axis == 0 ? 1.0 : 0.0);
+    const double y = S.xs[e][1] + us * (axis == 1 ? 1.0 : 0.0);
+    const double z = S.xs[e][2] + us * (axis == 2 ? 1.0 : 0.0);
+    int w = 0;
+    unsigned long long bits = 0;
+    for (; w < CH_ATOMS / 64 + CH_SURF / 64; ++w) {
+        bits = w < CH_ATOMS / 64 ? S.amask[e][w] : S.smask[e][w - CH_ATOMS / 64];
+        const int c = __popcll(bits);
+        if (j < c) break;
+        j -= c;
+    }
+    for (; j > 0; --j) bits &= bits - 1;
+    const int b = __builtin_ctzll(bits);
+    if (w < CH_ATOMS / 64) {
+        double4 a = S.atoms[w * 64 + b];
+        double dx = x - a.x, dy = y - a.y, dz = z - a.z;
+        double d2 = dx * dx + dy * dy + dz * dz;
+        if (CNT) ++cnt[EC_L_ATOM];
+        if (d2 <= a.w * a.w) return 1;
+        double sr = a.w + rho;
+        return d2 < sr * sr ? 2 : 0;
+    }
+    const int q = (w - CH_ATOMS / 64) * 64 + b;
+    if (q < nF) {
+        double4 a = S.sp[q].c;
+        double dx = x - a.x, dy = y - a.y, dz = z - a.z;
+        double d2 = dx * dx + dy * dy + dz * dz;
+        double sr = a.w + 2.0 * rho;
+        if (CNT) ++cnt[EC_L_FACE];
+        if (!(d2 < sr * sr)) return 0;
+        double d = sqrt(d2);
+        return staged_cuts_pass<CNT>(m, S, q, dx, dy, dz, d, CNT ? cnt + EC_L_FACE_CUT : nullptr)
+                   ? 4
+                   : 0;
+    }
+    if (q < nF + nV) {
+        double4 p = S.sp[q].c;
+        double dx = x - p.x, dy = y - p.y, dz = z - p.z;
+        if (CNT) ++cnt[EC_L_VERTEX];
+        return dx * dx + dy * dy + dz * dz < rho2 ? 4 : 0;
+    }
+    double4 oR = S.sp[q].c;
+    double4 nn = S.sp[q].n;
+    double wx = x - oR.x, wy = y - oR.y, wz = z - oR.z;
+    double t = wx * nn.x + wy * nn.y + wz * nn.z;
+    double ww = wx * wx + wy * wy + wz * wz;
+    double bb = sqrt(fmax(ww - t * t, 0.0));
+    double R = oR.w;
+    if (CNT) ++cnt[EC_L_CIRCLE];
+    if (!(ww + R * R - rho2 < 2.0 * bb * R)) return 0;
+    double px = wx, py = wy, pz = wz, pb = bb;
+    if (!(bb > 0.0)) {
+        perp_unit(nn.x, nn.y, nn.z, px, py, pz);
+        pb = 1.0;
+    }
+    return staged_cuts_pass<CNT>(m, S, q, px, py, pz, pb, CNT ? cnt + EC_L_CIRCLE_CUT : nullptr)
+               ? 4
+               : 0;
+}
+
+// Directions of a face's or circle's candidate over a ball: the cone of
+// half-angle theta (sin st, cos ct) around the unit axis; `all` when the
+// ball holds the apex (every direction possible).
+struct DirCone {
+    double ax, ay, az, st, ct;
+    bool all;
+};
+
+// The cone over ball (bc, rb): from the atom centre for a face, in the
+// circle's plane from its centre for a circle (the in-plane part of a
+// displacement is no longer than the displacement).
+__device__ inline DirCone surface_cone(int type, const SurfParams &p, const double *bc, double rb) {
+    double ax = bc[0] - p.c.x, ay = bc[1] - p.c.y, az = bc[2] - p.c.z;
+    if (type == 2) {
+        double t = ax * p.n.x + ay * p.n.y + az * p.n.z;
+        ax -= t * p.n.x;
+        ay -= t * p.n.y;
+        az -= t * p.n.z;
+    }
+    DirCone c;
+    const double L = sqrt(ax * ax + ay * ay + az * az);
+    c.all = !(L > rb * (1.0 + 1e-9));
+    if (c.all) {
+        c.ax = c.ay = c.az = c.st = 0.0;
+        c.ct = 1.0;
+        return c;
+    }
+    c.ax = ax / L;
+    c.ay = ay / L;
+    c.az = az / L;
+    c.st = rb / L;
+    c.ct = sqrt(fmax(0.0, 1.0 - c.st * c.st));
+    return c;
+}
+
+// A cut (v, tau) rejects the unit direction u iff u . v > tau.  Over the
+// cone, u . v ranges between |v| cos(phi + theta) and |v| cos(phi - theta)
+// (phi the angle between v and the axis, clamped to [0, pi]); both tests
+// keep a small slack on the conservative side.
+__device__ inline bool cone_rejects(const DirCone &c, double4 v) {
+    if (c.all) return false;
+    const double vn = sqrt(v.x * v.x + v.y * v.y + v.z * v.z);
+    if (!(vn > 0.0)) return false;
+    const double cp = (c.ax * v.x + c.ay * v.y + c.az * v.z) / vn;
+    if (cp <= -c.ct) return false;  // the cone holds the direction opposite to v
+    const double sp = sqrt(fmax(0.0, 1.0 - cp * cp));
+    return vn * (cp * c.ct - sp * c.st) > v.w + 1e-9 * (vn + fabs(v.w));
+}
+
+__device__ inline bool cone_may_reject(const DirCone &c, double4 v) {
+    if (c.all) return true;
+    const double vn = sqrt(v.x * v.x + v.y * v.y + v.z * v.z);
+    if (!(vn > 0.0)) return 0.0 > v.w - 1e-9;
+    const double cp = (c.ax * v.x + c.ay * v.y + c.az * v.z) / vn;
+    double best = vn;  // the cone holds v's direction
+    if (cp < c.ct) {
+        const double sp = sqrt(fmax(0.0, 1.0 - cp * cp));
+        best = vn * (cp * c.ct + sp * c.st);
+    }
+    return best > v.w - 1e-9 * (vn + fabs(v.w));
+}
+
+// Whether some cut of staged face or circle si rejects its candidate at
+// every point of the edge (the ball of radius `half` around mid).  The
+// candidate's direction -- from the atom centre for a face, in the circle's
+// plane from its centre for a circle -- stays within angle theta of its value
+// at mid, sin theta = half / distance; a cut (v, tau) rejects the direction u
+// iff u . v > tau, so it rejects the whole cone iff |v| cos(phi + theta) > tau
+// with phi the angle between v and the axis (a small slack keeps the test
+// conservative under rounding).
+template <bool CNT>
+__device__ bool edge_cone_dead(const Mol &m, const ChunkLds &S, int si, int type,
+                               const double *mid, double half, unsigned long long *cnt) {
+    const SurfParams &p = S.sp[si];
+    double ax = mid[0] - p.c.x, ay = mid[1] - p.c.y, az = mid[2] - p.c.z;
+    if (type == 2) {
+        double t = ax * p.n.x + ay * p.n.y + az * p.n.z;
+        ax -= t * p.n.x;
+        ay -= t * p.n.y;
+        az -= t * p.n.z;
+    }
+    const double L = sqrt(ax * ax + ay * ay + az * az);
+    if (!(L > 2.0 * half)) return false;  // the cone is too wide to decide
+    ax /= L;
+    ay /= L;
+    az /= L;
+    const double st = half / L, ct = sqrt(1.0 - st * st);
+    const int2 r = S.crange[si];
+    const double4 *cuts = S.cut;
+    int b = r.x, e = r.y;
+    if (r.x < 0) {
+        cuts = type == 1 ? m.face_cut : m.ec_cut;
+        b = -1 - r.x;
+    }
+    for (int c = b; c < e; ++c) {
+        const double4 v = cuts[c];
+        if (CNT) ++cnt[EC_CONE];
+        const double vn = sqrt(v.x * v.x + v.y * v.y + v.z * v.z);
+        if (!(vn > 0.0)) continue;
+        const double cp = (ax * v.x + ay * v.y + az * v.z) / vn;
+        if (cp <= -ct) continue;  // the cone holds the direction opposite to v
+        const double sp = sqrt(fmax(0.0, 1.0 - cp * cp));
+        const double mn = vn * (cp * ct - sp * st);  // min of u . v over the cone
+        if (mn > v.w + 1e-9 * (vn + fabs(v.w))) return true;
+    }
+    return false;
+}
+
 // Thread t's item within a block-wide round: items 4k .. 4k+3 go to lane k
 // of waves 0 .. 3, so that a short round still uses every SIMD.
 __device__ inline int spread(int t) { return (t % WAVE) * (CH_THREADS / WAVE) + t / WAVE; }
@@ -796,77 +1020,131 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
     const int ns_all = tile_surfaces(m, tile);
     // one surface pass with every atom staged: labels from the per-edge masks
     const bool filt = ns_all > 0 && ns_all <= CH_SURF && nA <= CH_ATOMS;
+    // ball holding every point of the tile's edges: points T t .. T t + T per axis
+    double bc[3];
+    const int T = m.tile;
+    {
+        const int t3[3] = {tile % m.tdims[0], (tile / m.tdims[0]) % m.tdims[1],
+                           tile / (m.tdims[0] * m.tdims[1])};
+        for (int a = 0; a < 3; ++a) bc[a] = m.lo[a] + (t3[a] * T + 0.5 * T) * h;
+    }
+    const double rb = sqrt(3.0) * 0.5 * T * h * (1.0 + 1e-12) + 1e-9;
     for (int sb = 0; sb < ns_all; sb += CH_SURF) {
         const int ns = min(CH_SURF, ns_all - sb);
-        // stage the pass's surfaces and as many of their cut planes as fit
-        int key = 0, cb = 0, ce = 0;
-        const double4 *gc = nullptr;
+        // stage the pass's surfaces and, culled to the tile's direction cone,
+        // as many of their cut planes as fit (one wavefront per surface); a
+        // surface that one cut rejects over the whole cone is dead in this tile
         if (tid < ns) {
-            key = tile_surface_key(m, tile, sb + tid);
+            const int key = tile_surface_key(m, tile, sb + tid);
             S.skey[tid] = key;
             S.sp[tid] = surf_params(m, key);
-            gc = global_cuts(m, key, &cb, &ce);
         }
-        int total;
-        const int off = block_excl_scan<int, CH_THREADS>(ce - cb, S.scan, &total);
-        if (tid < ns) {
-            if (off + (ce - cb) <= CH_CUTS) {
-                for (int c = cb; c < ce; ++c) S.cut[off + c - cb] = gc[c];
-                S.crange[tid] = make_int2(off, off + ce - cb);
-            } else {
-                S.crange[tid] = make_int2(-1 - cb, ce);
+        if (tid == 0) S.pool = 0;
+        __syncthreads();
+        for (int q = tid / WAVE; q < ns; q += CH_THREADS / WAVE) {
+            const int lane = lane_id();
+            const int key = S.skey[q], type = key >> 28;
+            int cb, ce;
+            const double4 *gc = global_cuts(m, key, &cb, &ce);
+            const DirCone cone = surface_cone(type, S.sp[q], bc, rb);
+            bool dead = false;
+            int nkeep = 0;
+            for (int base = cb; base < ce; base += WAVE) {
+                const int c = base + lane;
+                bool rej = false, keep = false;
+                if (c < ce) {
+                    const double4 v = gc[c];
+                    rej = cone_rejects(cone, v);
+                    keep = cone_may_reject(cone, v);
+                }
+                dead = dead || __any(rej);
+                nkeep += __popcll(__ballot(keep));
+            }
+            int start = 0;
+            if (lane == 0 && !dead) start = atomicAdd(&S.pool, nkeep);
+            start = __shfl(start, 0, WAVE);
+            const bool fits = !dead && start + nkeep <= CH_CUTS;
+            if (fits) {
+                int w = start;
+                for (int base = cb; base < ce; base += WAVE) {
+                    const int c = base + lane;
+                    double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
+                    bool keep = false;
+                    if (c < ce) {
+                        v = gc[c];
+                        keep = cone_may_reject(cone, v);
+                    }
+                    const unsigned long long bm = __ballot(keep);
+                    if (keep) S.cut[w + mask_prefix(bm)] = v;
+                    w += __popcll(bm);
+                }
+            }
+            if (lane == 0) {
+                S.sdead[q] = dead ? 1 : 0;
+                // every cut, in global memory, when the pool is full (or dead)
+                S.crange[q] = fits ? make_int2(start, start + nkeep) : make_int2(-1 - cb, ce);
             }
         }
         __syncthreads();
-        // (edge, surface) pairs, then (edge, atom) pairs for the label masks
+        // atoms whose SAS ball can hold a point of an edge (label masks)
+        if (filt && sb == 0) {
+            for (int p = tid; p < n * nAst; p += CH_THREADS) {
+                const int ei = p % n, ai = p / n;
+                const double4 a = S.atoms[ai];
+                const int axis = S.einfo[ei] & 3;
+                double dm2 = 0.0;
+                for (int c = 0; c < 3; ++c) {
+                    const double mc = S.xs[ei][c] + (c == axis ? 0.5 * h : 0.0);
+                    const double ac = c == 0 ? a.x : c == 1 ? a.y : a.z;
+                    dm2 += sq(mc - ac);
+                }
+                if (dm2 < sq(a.w + rho + half)) atomicOr(&S.amask[ei][ai >> 6], 1ull << (ai & 63));
+            }
+        }
+        // (edge, surface) pairs: reach tests, label masks, the solve queue
         const int npairs = n * ns;
-        const int ntests = npairs + (filt ? n * nAst : 0);
         int pb = 0;
-        while (pb < ntests) {
+        while (pb < npairs) {
             if (tid == 0) {
                 S.npair_s = 0;
                 S.npair_t = 0;
             }
             __syncthreads();
             // reach tests until the queue could not take another round (a
-            // round adds at most CH_THREADS pairs); the length is read between
+            // round adds at most CH_ROUND pairs); the length is read between
             // two barriers, so every thread takes the same decision
             for (;;) {
-                int p = pb + tid;
-                if (p < npairs) {
-                    int ei = p % n, si = p / n;
-                    int type = S.skey[si] >> 28;
+                for (int r = 0; r < CH_ROUND; r += CH_THREADS) {
+                    const int p = pb + r + tid;
+                    if (p >= npairs) break;
+                    const int ei = p % n, si = p / n;
+                    const int type = S.skey[si] >> 28;
                     double mid[3];
-                    int axis = S.einfo[ei] & 3;
+                    const int axis = S.einfo[ei] & 3;
                     for (int a = 0; a < 3; ++a)
                         mid[a] = S.xs[ei][a] + (a == axis ? 0.5 * h : 0.0);
                     if (CNT) ++cnt[type == 2 ? EC_REACH_TORUS : EC_REACH_SPHERE];
-                    bool rel;
-                    if (surf_reaches_rel(type, S.sp[si], rho, mid, half, &rel)) {
+                    bool rel = false, hit = false;
+                    if (!S.sdead[si]) hit = surf_reaches_rel(type, S.sp[si], rho, mid, half, &rel);
+                    // a circle whose candidate is inadmissible on the whole edge
+                    // has no kept root there and fails every label test
+                    if ((hit || rel) && type == 2 &&
+                        edge_cone_dead<CNT>(m, S, si, type, mid, half, cnt)) {
+                        hit = false;
+                        rel = false;
+                    }
+                    if (hit) {
                         unsigned short v = (unsigned short)(ei | (si << 6));
                         if (type == 2) S.pair[CH_PAIRS - 1 - atomicAdd(&S.npair_t, 1)] = v;
                         else S.pair[atomicAdd(&S.npair_s, 1)] = v;
                     }
                     if (rel) atomicOr(&S.smask[ei][si >> 6], 1ull << (si & 63));
-                } else if (p < ntests) {
-                    // atom whose SAS ball can hold a point of the edge
-                    int ei = (p - npairs) % n, ai = (p - npairs) / n;
-                    double4 a = S.atoms[ai];
-                    int axis = S.einfo[ei] & 3;
-                    double dm2 = 0.0;
-                    for (int c = 0; c < 3; ++c) {
-                        double mc = S.xs[ei][c] + (c == axis ? 0.5 * h : 0.0);
-                        double ac = c == 0 ? a.x : c == 1 ? a.y : a.z;
-                        dm2 += sq(mc - ac);
-                    }
-                    if (dm2 < sq(a.w + rho + half))
-                        atomicOr(&S.amask[ei][ai >> 6], 1ull << (ai & 63));
                 }
-                pb += CH_THREADS;
+                pb += CH_ROUND;
                 __syncthreads();
                 const int queued = S.npair_s + S.npair_t;
                 __syncthreads();
-                if (pb >= ntests || queued + CH_THREADS > CH_PAIRS) break;
+                if (pb >= npairs || queued + CH_ROUND > CH_PAIRS) break;
             }
             // one thread per queued pair: tori first, then spheres; pair j
             // goes to wave j % 4, so that the costly tori spread over the SIMDs
@@ -935,54 +1213,121 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
     __syncthreads();
     for (int j = tid; j < nf; j += CH_THREADS) S.perm[atomicAdd(&S.ecount[S.fe[j]], 1)] = (unsigned short)j;
     __syncthreads();
-    // one thread per edge (edge e on wave e % 4): sort its roots by (u, key),
-    // walk, write the record
+    // one thread per edge (edge e on wave e % 4): sort its roots by (u, key)
     const int ei = spread(tid);
-    if (ei >= n) return;
-    const int o = S.eoff[ei], ne = S.ecount[ei] - o;
-    for (int a = 1; a < ne; ++a) {
-        unsigned short v = S.perm[o + a];
-        double u = S.fu[v];
-        int k = S.fk[v];
-        int b = a - 1;
-        while (b >= 0) {
-            unsigned short w = S.perm[o + b];
-            double uw = S.fu[w];
-            if (uw < u || (uw == u && S.fk[w] <= k)) break;
-            S.perm[o + b + 1] = w;
-            --b;
+    const bool act = ei < n;
+    int o = 0, ne = 0;
+    if (act) {
+        o = S.eoff[ei];
+        ne = S.ecount[ei] - o;
+        for (int a = 1; a < ne; ++a) {
+            unsigned short v = S.perm[o + a];
+            double u = S.fu[v];
+            int k = S.fk[v];
+            int b = a - 1;
+            while (b >= 0) {
+                unsigned short w = S.perm[o + b];
+                double uw = S.fu[w];
+                if (uw < u || (uw == u && S.fk[w] <= k)) break;
+                S.perm[o + b + 1] = w;
+                --b;
+            }
+            S.perm[o + b + 1] = v;
         }
-        S.perm[o + b + 1] = v;
     }
     EdgeGeom G;
-    const int info = S.einfo[ei];
+    const int info = act ? S.einfo[ei] : 0;
     const int axis = info & 3;
     for (int a = 0; a < 3; ++a) {
-        G.xs[a] = S.xs[ei][a];
+        G.xs[a] = act ? S.xs[ei][a] : 0.0;
         G.e[a] = a == axis ? 1.0 : 0.0;
     }
     G.tile = tile;
     G.Ls = (info >> 2) & 1;
     G.Lt = (info >> 3) & 1;
+    auto root_at = [&](int r, double &u, int &k) {
+        unsigned short v = S.perm[o + r];
+        u = S.fu[v];
+        k = S.fk[v];
+    };
     // the staged surfaces serve the labels when the tile had a single pass
     const bool staged = ns_all <= CH_SURF;
     const int nF = m.tF_off[tile + 1] - m.tF_off[tile];
     const int nV = m.tV_off[tile + 1] - m.tV_off[tile];
     int owner = -1;
-    const double ustar = walk_roots<CNT>(
-        ne,
-        [&](int r, double &u, int &k) {
-            unsigned short v = S.perm[o + r];
-            u = S.fu[v];
-            k = S.fk[v];
-        },
-        G.Ls, G.Lt, G.xs, G.e, h,
-        [&](double x, double y, double z) {
-            return filt     ? label_masked<CNT>(m, S, ei, nF, nV, x, y, z, cnt)
-                   : staged ? label_chunk<CNT>(m, S, tile, nAst, nF, nV, ns_all, x, y, z, cnt)
-                            : label_fp64_t<CNT>(m, tile, x, y, z, CNT ? cnt + EC_L_ATOM : nullptr);
-        },
-        &owner, cnt);
+    double ustar = 1.0;
+    bool done = false;
+    if (filt) {
+        // every interval whose label the walk may read becomes a query; the
+        // block evaluates all (query, candidate) tests of the per-edge masks
+        // at once, and the walk reads the combined results
+        if (tid == 0) S.nq = 0;
+        __syncthreads();
+        int nqe = 0, q0 = 0;
+        if (act) {
+            label_intervals(ne, root_at, [&](double) { ++nqe; });
+            q0 = atomicAdd(&S.nq, nqe);
+        }
+        __syncthreads();
+        const int nq = S.nq;
+        if (nq <= CH_Q) {
+            if (act && nqe > 0) {
+                int k = q0;
+                label_intervals(ne, root_at, [&](double um) {
+                    S.q.qu[k] = um;
+                    S.q.qe[k] = (unsigned char)ei;
+                    ++k;
+                });
+                if (CNT) cnt[EC_LABEL] += nqe;
+            }
+            __syncthreads();
+            int kq = 0;
+            if (tid < nq) {
+                const int e = S.q.qe[tid];
+                for (int w = 0; w < CH_ATOMS / 64; ++w) kq += __popcll(S.amask[e][w]);
+                for (int w = 0; w < CH_SURF / 64; ++w) kq += __popcll(S.smask[e][w]);
+                S.q.qflag[tid] = 0;
+            }
+            int tot;
+            const int off = block_excl_scan<int, CH_THREADS>(kq, S.scan, &tot);
+            if (tid < nq) S.q.qoff[tid] = off;
+            if (tid == 0) S.q.qoff[nq] = tot;
+            __syncthreads();
+            for (int p = tid; p < tot; p += CH_THREADS) {
+                int lo = 0, hi = nq;
+                while (lo < hi) {
+                    int mid = (lo + hi) >> 1;
+                    if (S.q.qoff[mid + 1] <= p) lo = mid + 1;
+                    else hi = mid;
+                }
+                const int f = label_test<CNT>(m, S, S.q.qe[lo], p - S.q.qoff[lo], S.q.qu[lo], nF,
+                                              nV, cnt);
+                if (f) atomicOr(&S.q.qflag[lo], f);
+            }
+            __syncthreads();
+            if (act) {
+                int k = q0;
+                ustar = walk_roots<false>(
+                    ne, root_at, G.Ls, G.Lt, G.xs, G.e, h,
+                    [&](double, double, double) {
+                        const int f = S.q.qflag[k++];
+                        return (f & 1) ? 1 : (!(f & 2) ? 0 : ((f & 4) ? 0 : 1));
+                    },
+                    &owner, cnt);
+            }
+            done = true;
+        }
+    }
+    if (!act) return;
+    if (!done)
+        ustar = walk_roots<CNT>(
+            ne, root_at, G.Ls, G.Lt, G.xs, G.e, h,
+            [&](double x, double y, double z) {
+                return filt     ? label_masked<CNT>(m, S, ei, nF, nV, x, y, z, cnt)
+                       : staged ? label_chunk<CNT>(m, S, tile, nAst, nF, nV, ns_all, x, y, z, cnt)
+                                : label_fp64_t<CNT>(m, tile, x, y, z, CNT ? cnt + EC_L_ATOM : nullptr);
+            },
+            &owner, cnt);
     if (CNT) {
         ++cnt[EC_EDGES];
         return;
@@ -995,7 +1340,7 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
 // grid is a multiple of the XCD count; XCD x takes the x-th contiguous range
 // of chunks, so that neighbouring tiles share an L2.
 template <bool CNT>
-__global__ void __launch_bounds__(CH_THREADS)
+__global__ void __launch_bounds__(CH_THREADS) __attribute__((amdgpu_waves_per_eu(3)))
     k_edge_chunks(Mol m, const uint8_t *L, const long long *keys, const int *order,
                   const int *tcount, const int *coff, double *lam, double *nrm, uint8_t *ptype,
                   int *patoms, int *fallback, int *nfallback, unsigned long long *work) {

@@ -69,7 +69,7 @@ hipError_t launch_edge_work(const Mol &m, const uint8_t *L, const long long *key
                             const int *coff, int *fallback, int *nfallback, int *overflow,
                             unsigned long long *work, hipStream_t st);
 
-constexpr int EDGE_WORK_COUNTERS = 14;
+constexpr int EDGE_WORK_COUNTERS = 16;
 
 // vertex export
 hipError_t launch_export_vertices(const Mol &m, double *p, int *atoms, int8_t *sign,

@@ -80,7 +80,7 @@ class EdgeStats(ctypes.Structure):
                 ("reach_torus", ctypes.c_int64), ("quad_solves", ctypes.c_int64),
                 ("quartic_solves", ctypes.c_int64), ("horner_flops", ctypes.c_int64),
                 ("cut_tests", ctypes.c_int64), ("label_evals", ctypes.c_int64),
-                ("label_tests", ctypes.c_int64 * 6)]
+                ("label_tests", ctypes.c_int64 * 6), ("cone_tests", ctypes.c_int64)]
 
     def as_dict(self):
         d = {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "label_tests"}
