@@ -98,7 +98,11 @@ typedef struct {
     int32_t blocks_per_cu; /* batches (n_mols > 1): persistent workgroups per
                               compute unit of the fused classification launch
                               (0 = as many as fit) */
-    int32_t reserved[5];   /* must be zero */
+    int32_t edge_fallback; /* test aid: send every crossing edge to the
+                              one-wavefront-per-edge root kernel, the path
+                              otherwise taken only by edges of a tile whose
+                              root lists overflow (0 = off) */
+    int32_t reserved[4];   /* must be zero */
 } eses_config;
 
 typedef struct eses_candidates eses_candidates; /* opaque, library-owned */
@@ -224,8 +228,16 @@ typedef struct {
 void eses_set_timing(int enable);
 eses_status eses_get_kernel_times(const eses_candidates *c, eses_kernel_times *out);
 
-/* Releases the handle and its device workspace.  Call after the work queued
- * with it has finished.  NULL is ignored. */
+/* Device workspace is taken on the caller's stream and, when released, kept
+ * in a cache (per device, stream and power-of-two size class) for the next
+ * call on that stream.  eses_trim_cache synchronises every device that holds
+ * cached blocks and frees them; call it when no library work is in flight
+ * (e.g. before handing the memory to other code).  Returns ESES_EDEVICE if a
+ * HIP call failed. */
+eses_status eses_trim_cache(void);
+
+/* Releases the handle; its device workspace returns to the cache of the
+ * stream it was built on (eses_trim_cache frees it).  NULL is ignored. */
 void eses_free_candidates(eses_candidates *c);
 
 /* Message of the last failed call on this thread ("" if none). */

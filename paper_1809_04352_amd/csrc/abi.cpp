@@ -9,7 +9,10 @@
 #include <cstdio>
 #include <cstring>
 #include <initializer_list>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -52,31 +55,73 @@ struct Status {
         if (s_ != ESES_OK) return s_;    \
     } while (0)
 
-// Device workspace of one molecule: every buffer allocated on the stream and
-// released together.
+// Device memory cache.  Released workspace blocks are kept per (device,
+// stream, power-of-two size class) and handed to the next request of that
+// class on the same stream: the stream orders the reuse after the work that
+// used the block, so no synchronisation is needed.  Blocks stay cached until
+// eses_trim_cache.
+struct BlockCache {
+    std::mutex mu;
+    std::map<std::tuple<int, hipStream_t, int>, std::vector<void *>> free;
+};
+
+BlockCache &block_cache() {
+    static BlockCache *c = new BlockCache();  // outlives static destruction
+    return *c;
+}
+
+int size_class(size_t bytes) {
+    int c = 8;  // 256 B
+    while (((size_t)1 << c) < bytes) ++c;
+    return c;
+}
+
+// Device workspace of one molecule: every buffer taken on the stream and
+// returned to the cache together.
 struct Arena {
-    std::vector<void *> ptrs;
+    struct Block {
+        void *p;
+        int dev, cls;
+    };
+    std::vector<Block> blocks;
     hipStream_t st = nullptr;
 
     template <typename T>
     eses_status alloc(T **p, long long count) {
-        size_t bytes = sizeof(T) * (size_t)(count > 0 ? count : 1);
-        bytes = (bytes + 255) & ~(size_t)255;
+        const size_t bytes = sizeof(T) * (size_t)(count > 0 ? count : 1);
+        const int cls = size_class(bytes);
+        int dev = 0;
+        (void)hipGetDevice(&dev);
         void *q = nullptr;
-        hipError_t e = hipMallocAsync(&q, bytes, st);
-        if (e != hipSuccess || !q) {
-            (void)hipGetLastError();
-            set_err("device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
-            return ESES_ENOMEM;
+        {
+            BlockCache &bc = block_cache();
+            std::lock_guard<std::mutex> lock(bc.mu);
+            auto it = bc.free.find(std::make_tuple(dev, st, cls));
+            if (it != bc.free.end() && !it->second.empty()) {
+                q = it->second.back();
+                it->second.pop_back();
+            }
         }
-        ptrs.push_back(q);
+        if (!q) {
+            hipError_t e = hipMallocAsync(&q, (size_t)1 << cls, st);
+            if (e != hipSuccess || !q) {
+                (void)hipGetLastError();
+                set_err("device allocation of %zu bytes failed: %s", (size_t)1 << cls,
+                        hipGetErrorString(e));
+                return ESES_ENOMEM;
+            }
+        }
+        blocks.push_back({q, dev, cls});
         *p = (T *)q;
         return ESES_OK;
     }
 
     void release() {
-        for (void *p : ptrs) (void)hipFreeAsync(p, st);
-        ptrs.clear();
+        if (blocks.empty()) return;
+        BlockCache &bc = block_cache();
+        std::lock_guard<std::mutex> lock(bc.mu);
+        for (const Block &b : blocks) bc.free[std::make_tuple(b.dev, st, b.cls)].push_back(b.p);
+        blocks.clear();
     }
 };
 
@@ -160,8 +205,8 @@ eses_status d2h_ints(std::initializer_list<std::pair<int *, const int *>> items,
 }
 
 // Stage 1 for one molecule.
-eses_status build_one(const eses_molecule *in, int tile, int force_recheck, MolState *S,
-                      hipStream_t st) {
+eses_status build_one(const eses_molecule *in, int tile, int force_recheck, int edge_fallback,
+                      MolState *S, hipStream_t st) {
     Mol &m = S->m;
     Arena &A = S->arena;
     Arena &T = S->scratch;
@@ -193,6 +238,7 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, MolS
     m.in_r = in->radii;
     m.tile = tile;
     m.force_recheck = force_recheck ? 1 : 0;
+    m.edge_fallback = edge_fallback ? 1 : 0;
     for (int a = 0; a < 3; ++a) m.tdims[a] = (dims[a] + tile - 1) / tile;
     long long ntiles = (long long)m.tdims[0] * m.tdims[1] * m.tdims[2];
     if (ntiles > (1LL << 30)) {
@@ -502,15 +548,16 @@ eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
         set_err("need at least one molecule");
         return ESES_EINVAL;
     }
-    int tile = 8, force_recheck = 0;
+    int tile = 8, force_recheck = 0, edge_fallback = 0;
     if (cfg) {
         if (cfg->tile != 0) tile = cfg->tile;
         force_recheck = cfg->force_recheck;
+        edge_fallback = cfg->edge_fallback;
         if (cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64) {
             set_err("blocks_per_cu must be in [0, 64]");
             return ESES_EINVAL;
         }
-        for (int q = 0; q < 5; ++q)
+        for (int q = 0; q < 4; ++q)
             if (cfg->reserved[q] != 0) {
                 set_err("eses_config.reserved must be zero");
                 return ESES_EINVAL;
@@ -526,7 +573,7 @@ eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
     for (int32_t q = 0; q < n_mols; ++q) {
         MolState *S = new MolState();
         c->mols.push_back(S);
-        eses_status s = build_one(&mols[q], tile, force_recheck, S, st);
+        eses_status s = build_one(&mols[q], tile, force_recheck, edge_fallback, S, st);
         if (s != ESES_OK) {
             std::string msg = g_err;
             eses_free_candidates(c);
@@ -837,6 +884,34 @@ eses_status eses_edge_work(eses_candidates *c, const uint8_t *const *labels,
         o.label_evals = (int64_t)h[7];
         for (int k = 0; k < 6; ++k) o.label_tests[k] = (int64_t)h[8 + k];
         o.cone_tests = (int64_t)h[15];
+    }
+    return ESES_OK;
+}
+
+eses_status eses_trim_cache(void) {
+    g_err.clear();
+    BlockCache &bc = block_cache();
+    std::lock_guard<std::mutex> lock(bc.mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    hipError_t err = hipSuccess;
+    for (auto &kv : bc.free) {
+        const int dev = std::get<0>(kv.first);
+        if (hipSetDevice(dev) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+            err = hipGetLastError();
+            continue;
+        }
+        for (void *p : kv.second) {
+            hipError_t e = hipFree(p);
+            if (e != hipSuccess) err = e;
+        }
+        kv.second.clear();
+    }
+    bc.free.clear();
+    (void)hipSetDevice(cur);
+    if (err != hipSuccess) {
+        set_err("eses_trim_cache: %s", hipGetErrorString(err));
+        return ESES_EDEVICE;
     }
     return ESES_OK;
 }

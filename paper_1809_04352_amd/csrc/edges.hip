@@ -1192,7 +1192,7 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
         }
     }
     // too many roots for the chunk's lists: its edges go to the wavefront kernel
-    if (S.ovf || S.nf > CH_ROOTS) {
+    if (S.ovf || S.nf > CH_ROOTS || m.edge_fallback) {
         if (tid == 0) S.fb_base = atomicAdd(nfallback, n);
         __syncthreads();
         if (tid < n) fallback[S.fb_base + tid] = (int)S.eq[tid];

@@ -46,6 +46,7 @@ struct Mol {
     // tiles
     int tile;
     int force_recheck;   // FP32 path: every phase-1 decision treated as uncertain
+    int edge_fallback;   // every crossing edge through the wavefront root kernel
     int tdims[3];
     int ntiles;
 

@@ -29,7 +29,7 @@ EXPORTED = [
     "eses_bbox_from_atoms", "eses_grid_dims", "eses_build_candidates", "eses_candidates_info",
     "eses_copy_vertices", "eses_classify", "eses_edge_intersections", "eses_free_candidates",
     "eses_last_error", "eses_version", "eses_edge_work", "eses_set_timing",
-    "eses_get_kernel_times",
+    "eses_get_kernel_times", "eses_trim_cache",
 ]
 
 
@@ -48,7 +48,8 @@ class Molecule(ctypes.Structure):
 
 class Config(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("force_recheck", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("blocks_per_cu", ctypes.c_int32), ("edge_fallback", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class CandidateStats(ctypes.Structure):
@@ -136,6 +137,8 @@ def load():
     lib.eses_free_candidates.argtypes = [P]
     lib.eses_edge_work.restype = st
     lib.eses_edge_work.argtypes = [P, P, ctypes.POINTER(EdgeStats), P]
+    lib.eses_trim_cache.restype = st
+    lib.eses_trim_cache.argtypes = []
     lib.eses_set_timing.restype = None
     lib.eses_set_timing.argtypes = [ctypes.c_int]
     lib.eses_get_kernel_times.restype = st
@@ -194,7 +197,7 @@ class Candidates:
     """Owning wrapper of an eses_candidates handle."""
 
     def __init__(self, mols, tile: int = 0, stream=None, force_recheck: bool = False,
-                 blocks_per_cu: int = 0):
+                 blocks_per_cu: int = 0, edge_fallback: bool = False):
         lib = load()
         self.mols = list(mols)
         arr = (Molecule * len(self.mols))(*self.mols)
@@ -202,6 +205,7 @@ class Candidates:
         cfg.tile = int(tile)
         cfg.force_recheck = 1 if force_recheck else 0
         cfg.blocks_per_cu = int(blocks_per_cu)
+        cfg.edge_fallback = 1 if edge_fallback else 0
         h = ctypes.c_void_p()
         self.stream = _stream_ptr(stream)
         _check(lib.eses_build_candidates(arr, len(self.mols), ctypes.byref(cfg), self.stream,
@@ -226,8 +230,8 @@ class Candidates:
 
 
 def build_candidates(mols, tile: int = 0, stream=None, force_recheck: bool = False,
-                     blocks_per_cu: int = 0) -> Candidates:
-    return Candidates(mols, tile, stream, force_recheck, blocks_per_cu)
+                     blocks_per_cu: int = 0, edge_fallback: bool = False) -> Candidates:
+    return Candidates(mols, tile, stream, force_recheck, blocks_per_cu, edge_fallback)
 
 
 def copy_vertices(cand: Candidates, mol: int, p_dev, atoms_dev, sign_dev, stream=None) -> int:
@@ -306,6 +310,11 @@ def set_timing(enable: bool):
     load().eses_set_timing(1 if enable else 0)
 
 
+def trim_cache():
+    """Free the library's cached device workspace (synchronises)."""
+    _check(load().eses_trim_cache())
+
+
 def kernel_times(cand: Candidates) -> dict:
     t = KernelTimes()
     _check(load().eses_get_kernel_times(cand.h, ctypes.byref(t)))
@@ -315,14 +324,14 @@ def kernel_times(cand: Candidates) -> dict:
 
 def surface(centres, radii, probe: float, spacing: float, lo, hi, prec: int = ESES_FP64,
             tile: int = 0, isect_capacity: int | None = None, device="cuda",
-            force_recheck: bool = False, stats: bool = False):
+            force_recheck: bool = False, stats: bool = False, edge_fallback: bool = False):
     """Whole hot path for one molecule given host arrays; returns host numpy results."""
     import torch
     c = torch.as_tensor(np.ascontiguousarray(centres, dtype=np.float64), device=device)
     r = torch.as_tensor(np.ascontiguousarray(radii, dtype=np.float64), device=device)
     mol = make_molecule(c, r, probe, spacing, lo, hi)
     dims = grid_dims(mol)
-    cand = build_candidates([mol], tile, force_recheck=force_recheck)
+    cand = build_candidates([mol], tile, force_recheck=force_recheck, edge_fallback=edge_fallback)
     try:
         info = cand.info(0)
         nv = info["n_vertices"]

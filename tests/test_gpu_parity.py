@@ -195,3 +195,32 @@ def test_kernel_timing_and_edge_work(E):
     st, c2 = E.edge_intersections(cand, [lab], [out])
     assert c2 == counts
     cand.close()
+
+
+@pytest.mark.parametrize("n,seed,h", [(120, 4, 0.5), (300, 5, 0.45), (500, 1, 0.5)])
+def test_edge_fallback_path(E, oracle_mod, n, seed, h):
+    """The one-wavefront-per-edge root kernel (taken by edges of tiles whose
+    root lists overflow) gives the chunk path's records bit for bit, and the
+    oracle's."""
+    from eses_inputs import molecule
+    m = molecule(n, seed, h)
+    a = E.surface(m.centres, m.radii, m.probe, m.spacing, m.lo, m.hi)
+    b = E.surface(m.centres, m.radii, m.probe, m.spacing, m.lo, m.hi, edge_fallback=True)
+    for k in ("labels", "key", "lam", "normal", "patch_type", "atoms"):
+        assert np.array_equal(a[k], b[k]), k
+    o = oracle_mod.Oracle(m.centres, m.radii, m.probe)
+    ref = o.labels_grid(m.lo, m.spacing, m.dims)
+    compare_edges(b, o, m.lo, m.spacing, m.dims, ref)
+
+
+def test_workspace_cache_reuse_and_trim(E):
+    """Workspace blocks reused from the cache, and freed by eses_trim_cache,
+    leave the results unchanged."""
+    from eses_inputs import molecule
+    m = molecule(150, 12, 0.4)
+    a = E.surface(m.centres, m.radii, m.probe, m.spacing, m.lo, m.hi)
+    b = E.surface(m.centres, m.radii, m.probe, m.spacing, m.lo, m.hi)
+    E.trim_cache()
+    c = E.surface(m.centres, m.radii, m.probe, m.spacing, m.lo, m.hi)
+    for k in ("labels", "key", "lam", "normal", "patch_type", "atoms"):
+        assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k]), k
