@@ -73,8 +73,34 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_apply(const int *in, long l
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = bsum[gridDim.x];
 }
 
+// Small inputs: one workgroup, each thread summing a contiguous run, so the
+// scan is a single launch.
+constexpr int SCAN1_BLOCK = 1024;
+constexpr long long SCAN1_MAX = 8 * SCAN1_BLOCK;
+
+template <typename T>
+__global__ void __launch_bounds__(SCAN1_BLOCK) k_scan_small(const int *in, long long n, T *out) {
+    __shared__ T lds[SCAN1_BLOCK / WAVE + 1];
+    const long long per = (n + SCAN1_BLOCK - 1) / SCAN1_BLOCK;
+    const long long b = threadIdx.x * per, e = b + per < n ? b + per : n;
+    T v = 0;
+    for (long long q = b; q < e; ++q) v += (T)in[q];
+    T tot;
+    T ex = block_excl_scan<T, SCAN1_BLOCK>(v, lds, &tot);
+    for (long long q = b; q < e; ++q) {
+        T x = (T)in[q];
+        out[q] = ex;
+        ex += x;
+    }
+    if (threadIdx.x == 0) out[n] = tot;
+}
+
 template <typename T>
 static hipError_t scan_impl(const int *in, long long n, T *out, T *tmp, hipStream_t st) {
+    if (n <= SCAN1_MAX) {
+        hipLaunchKernelGGL(k_scan_small<T>, dim3(1), dim3(SCAN1_BLOCK), 0, st, in, n, out);
+        return hipGetLastError();
+    }
     long long nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb < 1) nb = 1;
     hipLaunchKernelGGL(k_scan_reduce<T>, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, st, in, n, tmp);
@@ -345,6 +371,7 @@ __device__ inline int find_circle(const Mol &m, int a, int b) {
 // (points on S_i can only be inside balls of i's neighbours).  Output order:
 // k ascending, "+" before "-".
 constexpr int VX_WAVES = 4;
+constexpr int VX_NBR = 256;  // neighbours of atom i staged in LDS
 
 // The concave probe positions on circle c = (i, j): for each neighbour k of
 // i above j, the two points of the circle at distance s_k from c_k, kept if
@@ -352,7 +379,11 @@ constexpr int VX_WAVES = 4;
 // LDS, the rest from global memory).
 template <bool FILL>
 __device__ void vertex_circle(const Mol &m, int c, int i, int nb, int ne, int nst,
-                              const double4 *nat, const int *nid, int lane, int *vcnt) {
+                              const double4 *nat, const int *nid, const int *nasc,
+                              const int *cjl, int ncl, int lane, int *vcnt) {
+    // i's ascending neighbour list and the partners of i's circles, from LDS
+    // when they fit (nasc: all ne - nb entries; cjl: ncl circles)
+    const bool asc_lds = ne - nb <= VX_NBR;
     int j = m.circ_j[c];
     double4 oR = m.circ_oR[c];
     double4 n = m.circ_n[c];
@@ -364,7 +395,7 @@ __device__ void vertex_circle(const Mol &m, int c, int i, int nb, int ne, int ns
     int lo = nb, hi = ne;
     while (lo < hi) {
         int mid = (lo + hi) >> 1;
-        if (m.nbr[mid] <= j) lo = mid + 1;
+        if ((asc_lds ? nasc[mid - nb] : m.nbr[mid]) <= j) lo = mid + 1;
         else hi = mid;
     }
     for (int base = lo; base < ne; base += WAVE) {
@@ -373,7 +404,7 @@ __device__ void vertex_circle(const Mol &m, int c, int i, int nb, int ne, int ns
         double v0x = 0, v0y = 0, v0z = 0, v1x = 0, v1y = 0, v1z = 0;
         int k = -1;
         if (q < ne) {
-            k = m.nbr[q];
+            k = asc_lds ? nasc[q - nb] : m.nbr[q];
             double4 ak = m.atom[k];
             double sk = ak.w + m.rho;
             double wx = ak.x - oR.x, wy = ak.y - oR.y, wz = ak.z - oR.z;
@@ -436,7 +467,22 @@ __device__ void vertex_circle(const Mol &m, int c, int i, int nb, int ne, int ns
             uint32_t f = (crossed ? CF_CROSSED : 0u) | (anyx ? CF_EXPOSED_VERTEX : 0u);
             if (f) {
                 lflag |= f;
-                int cik = find_circle(m, i, k);
+                int cik = -1;
+                if (ncl >= 0) {
+                    int a = 0, b = ncl - 1;
+                    while (a <= b) {
+                        int mid = (a + b) >> 1;
+                        int v = cjl[mid];
+                        if (v == k) {
+                            cik = m.circ_off[i] + mid;
+                            break;
+                        }
+                        if (v < k) a = mid + 1;
+                        else b = mid - 1;
+                    }
+                } else {
+                    cik = find_circle(m, i, k);
+                }
                 int cjk = find_circle(m, j, k);
                 if (cik >= 0) atomicOr(&m.cflag[cik], f);
                 if (cjk >= 0) atomicOr(&m.cflag[cjk], f);
@@ -461,14 +507,14 @@ __device__ void vertex_circle(const Mol &m, int c, int i, int nb, int ne, int ns
     }
 }
 
-constexpr int VX_NBR = 256;  // neighbours of atom i staged in LDS
-
 // One workgroup per atom i, one wavefront per circle (i, j) of i; i's
 // neighbours (cover order) are staged in LDS for the exposure tests.
 template <bool FILL>
 __global__ void __launch_bounds__(VX_WAVES *WAVE) k_vertex(Mol m, int *vcnt) {
-    __shared__ double4 nat[VX_NBR];  // x, y, z, (r + rho)^2
+    __shared__ double4 nat[VX_NBR];  // x, y, z, (r + rho)^2 in cover order
     __shared__ int nid[VX_NBR];
+    __shared__ int nasc[VX_NBR];     // ascending neighbour ids
+    __shared__ int cjl[VX_NBR];      // partner j of each circle (i, j) of i, ascending
     const int i = blockIdx.x;
     const int c0 = m.circ_off[i], c1 = m.circ_off[i + 1];
     if (c0 == c1) return;  // uniform across the workgroup
@@ -479,12 +525,15 @@ __global__ void __launch_bounds__(VX_WAVES *WAVE) k_vertex(Mol m, int *vcnt) {
         double4 al = m.atom[l];
         nat[q] = make_double4(al.x, al.y, al.z, sq(al.w + m.rho));
         nid[q] = l;
+        nasc[q] = m.nbr[nb + q];
     }
+    const int ncl = c1 - c0 <= VX_NBR ? c1 - c0 : -1;
+    for (int q = threadIdx.x; q < ncl; q += VX_WAVES * WAVE) cjl[q] = m.circ_j[c0 + q];
     __syncthreads();
     const int lane = lane_id();
     for (int c = c0 + threadIdx.x / WAVE; c < c1; c += VX_WAVES) {
         if (FILL && m.vert_off[c + 1] == m.vert_off[c]) continue;  // no probe position here
-        vertex_circle<FILL>(m, c, i, nb, ne, nst, nat, nid, lane, vcnt);
+        vertex_circle<FILL>(m, c, i, nb, ne, nst, nat, nid, nasc, cjl, ncl, lane, vcnt);
     }
 }
 
@@ -651,11 +700,12 @@ __global__ void __launch_bounds__(TILE_WAVES *WAVE) k_tiles(Mol m, int *cntA, in
     int oA = FILL ? m.tA_off[tile] : 0, oF = FILL ? m.tF_off[tile] : 0;
     int oC = FILL ? m.tC_off[tile] : 0, oV = FILL ? m.tV_off[tile] : 0;
     const double rho = m.rho;
+    // cells of one (y, z) row are consecutive, and so are their atoms and
+    // features: one range per row
     for (int z = c0[2]; z <= c1[2]; ++z)
-        for (int y = c0[1]; y <= c1[1]; ++y)
-            for (int x = c0[0]; x <= c1[0]; ++x) {
-                int c = x + m.nc[0] * (y + m.nc[1] * z);
-                int ab = m.cell_start[c], ae = m.cell_start[c + 1];
+        for (int y = c0[1]; y <= c1[1]; ++y) {
+                int crow = m.nc[0] * (y + m.nc[1] * z);
+                int ab = m.cell_start[crow + c0[0]], ae = m.cell_start[crow + c1[0] + 1];
                 for (int base = ab; base < ae; base += WAVE) {
                     int i = base + lane;
                     bool inA = false, inF = false;
