@@ -228,7 +228,7 @@ def main():
     for name, fl, t in (("classify", flops_classify, kmed["classify_ms"]),
                         ("edge_roots", flops_edges, kmed["edge_roots_ms"])):
         a = fl / (t * 1e-3) / 1e12
-        rl[name] = {"kernel": "k_classify" if name == "classify" else "k_edge_roots",
+        rl[name] = {"kernel": "k_classify" if name == "classify" else "k_edge_chunks",
                     "bound": "alu", "achieved": a, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                     "frac": a / PEAK_FP64_TFLOPS, "traffic": None, "algorithmic_flops": fl,
                     "ms": t}
