@@ -39,13 +39,15 @@ PEAK_FP64_TFLOPS = 78.6
 FLOPS_PER_TEST = {"tests_atom": 11, "tests_vertex": 8, "tests_face": 11, "tests_face_cut": 6,
                   "tests_circle": 21, "tests_circle_cut": 6}
 
-# FP64 flops of the edge-root kernel's work items (from its statistics pass):
+# FP64 flops of the edge-root kernels' work items (from their statistics pass):
 #   sphere reach (van der Waals or probe): mid - c (3), |.|^2 (5), bounds (4)   = 12
 #   torus reach: mid - o (3), t (5), |.|^2 (5), b (3), (b-R)^2 + t^2 (4),
 #                bounds (3)                                                   = 23
 #   quadratic: coefficients (9), discriminant (3), sqrt, two roots (5)        = 18
 #   quartic set-up: |w|^2, t, a/b coefficients, g coefficients                 = 35
 #   half-space test of a root: dot (5), |.| tau (1)                           = 6
+#   cone test of a cut against an edge's direction cone: |v| (6), cos phi (6),
+#     sin phi (3), |v| cos(phi + theta) (4), threshold (1)                    = 20
 #   per edge: coordinates, normal and its norm                                = 30
 # plus the solver's polynomial evaluations (counted in flops) and the label
 # evaluations between roots (classification constants above).
