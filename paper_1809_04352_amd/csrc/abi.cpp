@@ -196,11 +196,68 @@ eses_status d2h(T *host, const T *dev, size_t count, hipStream_t st) {
     return ESES_OK;
 }
 
+// Pinned host memory (per thread) that the read-back kernel writes into.
+long long *readback_host() {
+    thread_local long long *p = nullptr;
+    if (!p && hipHostMalloc((void **)&p, 16 * sizeof(long long), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+    }
+    return p;
+}
+
+// Device scalars read back with one kernel and one synchronisation: each
+// item's value (an int, or a long long where is64) lands in *out.
+struct Scalar {
+    const void *dev;
+    bool is64;
+    long long *out;
+};
+
+eses_status read_scalars(std::initializer_list<Scalar> items, hipStream_t st) {
+    long long *h = readback_host();
+    if (!h) {
+        set_err("pinned host allocation for read-backs failed");
+        return ESES_ENOMEM;
+    }
+    ReadBack rb{};
+    for (const Scalar &it : items) {
+        if (rb.n == 16) {
+            set_err("internal: more than 16 read-backs");
+            return ESES_EINTERNAL;
+        }
+        rb.p[rb.n] = it.dev;
+        rb.is64[rb.n] = it.is64 ? 1 : 0;
+        ++rb.n;
+    }
+    CK(launch_collect(rb, h, st));
+    CK(hipStreamSynchronize(st));
+    int q = 0;
+    for (const Scalar &it : items) *it.out = h[q++];
+    return ESES_OK;
+}
+
 // Several single ints read back with one synchronisation.
 eses_status d2h_ints(std::initializer_list<std::pair<int *, const int *>> items, hipStream_t st) {
-    for (auto &it : items)
-        CK(hipMemcpyAsync(it.first, it.second, sizeof(int), hipMemcpyDeviceToHost, st));
+    long long *h = readback_host();
+    if (!h) {
+        set_err("pinned host allocation for read-backs failed");
+        return ESES_ENOMEM;
+    }
+    ReadBack rb{};
+    for (auto &it : items) {
+        if (rb.n == 16) {
+            set_err("internal: more than 16 read-backs");
+            return ESES_EINTERNAL;
+        }
+        rb.p[rb.n] = it.second;
+        rb.is64[rb.n] = 0;
+        ++rb.n;
+    }
+    CK(launch_collect(rb, h, st));
     CK(hipStreamSynchronize(st));
+    int q = 0;
+    for (auto &it : items) *it.first = (int)h[q++];
     return ESES_OK;
 }
 
@@ -257,9 +314,13 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, int 
     CKS(T.alloc(&dbad, 1));
     CK(launch_bounds(in->centers, in->radii, m.n, dbounds, dbad, st));
     double hb[8];
-    int hbad = 0;
-    CK(hipMemcpyAsync(hb, dbounds, sizeof(double) * 7, hipMemcpyDeviceToHost, st));
-    CKS(d2h(&hbad, dbad, 1, st));
+    long long hbits[7], hbad = 0;
+    CKS(read_scalars({{dbounds, true, &hbits[0]}, {dbounds + 1, true, &hbits[1]},
+                      {dbounds + 2, true, &hbits[2]}, {dbounds + 3, true, &hbits[3]},
+                      {dbounds + 4, true, &hbits[4]}, {dbounds + 5, true, &hbits[5]},
+                      {dbounds + 6, true, &hbits[6]}, {dbad, false, &hbad}},
+                     st));
+    memcpy(hb, hbits, sizeof(double) * 7);  // the doubles' bit patterns
     if (hbad) {
         set_err("centres must be finite and radii finite and > 0");
         return ESES_EINVAL;
@@ -308,8 +369,11 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, int 
     CKS(A.alloc(&m.circ_any, m.n));
     CKS(A.alloc(&m.aflag, m.n));
     CK(launch_nbr(m, false, nbr_cnt, circ_cnt, st));
-    CK(scan_i32(nbr_cnt, m.n, m.nbr_off, tmp, st));
-    CK(scan_i32(circ_cnt, m.n, m.circ_off, tmp, st));
+    {
+        const int *ins[2] = {nbr_cnt, circ_cnt};
+        int *outs[2] = {m.nbr_off, m.circ_off};
+        CK(scan_i32_multi(ins, m.n, outs, 2, tmp, st));
+    }
     int tot[2];
     CKS(d2h_ints({{&tot[0], m.nbr_off + m.n}, {&tot[1], m.circ_off + m.n}}, st));
     m.ncirc = tot[1];
@@ -381,10 +445,11 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, int 
     CKS(A.alloc(&m.tC_off, m.ntiles + 1));
     CKS(A.alloc(&m.tV_off, m.ntiles + 1));
     CK(launch_tiles(m, false, cA, cF, cC, cV, st));
-    CK(scan_i32(cA, m.ntiles, m.tA_off, tmp, st));
-    CK(scan_i32(cF, m.ntiles, m.tF_off, tmp, st));
-    CK(scan_i32(cC, m.ntiles, m.tC_off, tmp, st));
-    CK(scan_i32(cV, m.ntiles, m.tV_off, tmp, st));
+    {
+        const int *ins[4] = {cA, cF, cC, cV};
+        int *outs[4] = {m.tA_off, m.tF_off, m.tC_off, m.tV_off};
+        CK(scan_i32_multi(ins, m.ntiles, outs, 4, tmp, st));
+    }
     int tl[4];
     CKS(d2h_ints({{&tl[0], m.tA_off + m.ntiles}, {&tl[1], m.tF_off + m.ntiles},
                    {&tl[2], m.tC_off + m.ntiles}, {&tl[3], m.tV_off + m.ntiles}}, st));
@@ -394,8 +459,8 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, int 
     CKS(A.alloc(&m.tV, tl[3]));
     CK(launch_tiles(m, true, cA, cF, cC, cV, st));
 
-    int hdiag[4];
-    CKS(d2h(hdiag, m.diag, 4, st));
+    int hdiag[1];
+    CKS(d2h_ints({{&hdiag[0], m.diag}}, st));
     if (hdiag[0] != 0) {
         set_err("internal: %d list entries beyond their counted range", hdiag[0]);
         return ESES_EINTERNAL;
@@ -734,8 +799,13 @@ eses_status eses_edge_intersections(eses_candidates *c, const uint8_t *const *la
         if (e == hipSuccess) e = launch_edge_detect_count(labels[q], m, bcount, &nblk, st);
         if (e == hipSuccess) e = scan_i64(bcount, nblk, boff, tmp, st);
         long long total = 0;
-        if (e == hipSuccess) e = hipMemcpyAsync(&total, boff + nblk, sizeof(long long), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e == hipSuccess) {
+            eses_status rs = read_scalars({{boff + nblk, true, &total}}, st);
+            if (rs != ESES_OK) {
+                T.release();
+                return rs;
+            }
+        }
         long long nw = std::min<long long>(total, o.capacity);
         int *tcount = nullptr, *ccount = nullptr, *coff = nullptr, *tfill = nullptr,
             *order = nullptr, *ttmp = nullptr, *fb = nullptr, *nfb = nullptr;
@@ -762,9 +832,14 @@ eses_status eses_edge_intersections(eses_candidates *c, const uint8_t *const *la
             e = launch_edge_roots(m, labels[q], (const long long *)o.key, nw, order, tcount, coff,
                                   o.lambda, o.normal, o.patch_type, o.atoms, fb, nfb, ovf, st);
         if (e == hipSuccess && timed) e = hipEventRecord(c->ev[5], st);
-        int hovf = 0;
-        if (e == hipSuccess) e = hipMemcpyAsync(&hovf, ovf, sizeof(int), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        long long hovf = 0;
+        if (e == hipSuccess) {
+            eses_status rs = read_scalars({{ovf, false, &hovf}}, st);
+            if (rs != ESES_OK) {
+                T.release();
+                return rs;
+            }
+        }
         if (e == hipSuccess && timed) {
             float a = 0.0f, b = 0.0f;
             e = hipEventElapsedTime(&a, c->ev[2], c->ev[3]);

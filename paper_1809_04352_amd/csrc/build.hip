@@ -11,6 +11,17 @@ namespace eses {
 
 __global__ void k_fill_i32(int *p, long long n, int v) { fill_i32(p, n, v); }
 
+// Scalars the host reads back, gathered into host memory by one thread.
+__global__ void k_collect(ReadBack rb, long long *host) {
+    for (int q = 0; q < rb.n; ++q)
+        host[q] = rb.is64[q] ? *(const long long *)rb.p[q] : (long long)*(const int *)rb.p[q];
+}
+
+hipError_t launch_collect(const ReadBack &rb, long long *host, hipStream_t st) {
+    hipLaunchKernelGGL(k_collect, dim3(1), dim3(1), 0, st, rb, host);
+    return hipGetLastError();
+}
+
 __global__ void k_fill_u32(uint32_t *p, long long n, uint32_t v) {
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
          q += (long long)gridDim.x * blockDim.x)
@@ -73,32 +84,51 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_apply(const int *in, long l
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = bsum[gridDim.x];
 }
 
-// Small inputs: one workgroup, each thread summing a contiguous run, so the
-// scan is a single launch.
+// Inputs up to SCAN1_MAX: one workgroup walks the input in coalesced tiles
+// of SCAN1_BLOCK x 4 elements, carrying the running total, so the scan is a
+// single launch; blockIdx.x selects one of several arrays of equal length.
 constexpr int SCAN1_BLOCK = 1024;
-constexpr long long SCAN1_MAX = 8 * SCAN1_BLOCK;
+constexpr long long SCAN1_MAX = 1 << 15;
+
+struct ScanArrays {
+    const int *in[4];
+    void *out[4];
+};
 
 template <typename T>
-__global__ void __launch_bounds__(SCAN1_BLOCK) k_scan_small(const int *in, long long n, T *out) {
+__global__ void __launch_bounds__(SCAN1_BLOCK) k_scan_small(ScanArrays a, long long n) {
     __shared__ T lds[SCAN1_BLOCK / WAVE + 1];
-    const long long per = (n + SCAN1_BLOCK - 1) / SCAN1_BLOCK;
-    const long long b = threadIdx.x * per, e = b + per < n ? b + per : n;
-    T v = 0;
-    for (long long q = b; q < e; ++q) v += (T)in[q];
-    T tot;
-    T ex = block_excl_scan<T, SCAN1_BLOCK>(v, lds, &tot);
-    for (long long q = b; q < e; ++q) {
-        T x = (T)in[q];
-        out[q] = ex;
-        ex += x;
+    const int *in = a.in[blockIdx.x];
+    T *out = (T *)a.out[blockIdx.x];
+    T carry = 0;
+    for (long long b0 = 0; b0 < n; b0 += 4 * SCAN1_BLOCK) {
+        const long long b = b0 + 4 * threadIdx.x;
+        T v[4];
+        T sum = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v[q] = b + q < n ? (T)in[b + q] : T(0);
+            sum += v[q];
+        }
+        T tot;
+        T ex = block_excl_scan<T, SCAN1_BLOCK>(sum, lds, &tot) + carry;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (b + q < n) out[b + q] = ex;
+            ex += v[q];
+        }
+        carry += tot;
     }
-    if (threadIdx.x == 0) out[n] = tot;
+    if (threadIdx.x == 0) out[n] = carry;
 }
 
 template <typename T>
 static hipError_t scan_impl(const int *in, long long n, T *out, T *tmp, hipStream_t st) {
     if (n <= SCAN1_MAX) {
-        hipLaunchKernelGGL(k_scan_small<T>, dim3(1), dim3(SCAN1_BLOCK), 0, st, in, n, out);
+        ScanArrays a{};
+        a.in[0] = in;
+        a.out[0] = out;
+        hipLaunchKernelGGL(k_scan_small<T>, dim3(1), dim3(SCAN1_BLOCK), 0, st, a, n);
         return hipGetLastError();
     }
     long long nb = (n + SCAN_TILE - 1) / SCAN_TILE;
@@ -118,6 +148,25 @@ hipError_t scan_i32(const int *in, long long n, int *out, int *tmp, hipStream_t 
 
 hipError_t scan_i64(const int *in, long long n, long long *out, long long *tmp, hipStream_t st) {
     return scan_impl<long long>(in, n, out, tmp, st);
+}
+
+hipError_t scan_i32_multi(const int *const *in, long long n, int *const *out, int k, int *tmp,
+                          hipStream_t st) {
+    if (k < 1 || k > 4) return hipErrorInvalidValue;
+    if (n <= SCAN1_MAX) {
+        ScanArrays a{};
+        for (int q = 0; q < k; ++q) {
+            a.in[q] = in[q];
+            a.out[q] = out[q];
+        }
+        hipLaunchKernelGGL(k_scan_small<int>, dim3(k), dim3(SCAN1_BLOCK), 0, st, a, n);
+        return hipGetLastError();
+    }
+    for (int q = 0; q < k; ++q) {
+        hipError_t e = scan_impl<int>(in[q], n, out[q], tmp, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t fill_i32(int *p, long long n, int v, hipStream_t st) {

@@ -9,6 +9,18 @@ namespace eses {
 long long scan_tmp_elems(long long n);
 hipError_t scan_i32(const int *in, long long n, int *out, int *tmp, hipStream_t st);
 hipError_t scan_i64(const int *in, long long n, long long *out, long long *tmp, hipStream_t st);
+// k (<= 4) arrays of length n scanned together (one launch when n is small).
+hipError_t scan_i32_multi(const int *const *in, long long n, int *const *out, int k, int *tmp,
+                          hipStream_t st);
+// Up to 16 device scalars (int, or long long where is64) copied by one kernel
+// into host-visible memory `host` (long long each).
+struct ReadBack {
+    const void *p[16];
+    int is64[16];
+    int n;
+};
+hipError_t launch_collect(const ReadBack &rb, long long *host, hipStream_t st);
+
 hipError_t fill_i32(int *p, long long n, int v, hipStream_t st);
 hipError_t fill_u32(uint32_t *p, long long n, uint32_t v, hipStream_t st);
 
