@@ -12,6 +12,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <utility>
 #include <vector>
@@ -204,6 +205,84 @@ long long *readback_host() {
         p = nullptr;
     }
     return p;
+}
+
+// Worker streams for per-molecule work of a batch: created once per device
+// (default priority, not blocking on the null stream) and kept for the
+// process lifetime, so that workspace cached under them stays reusable.
+constexpr int N_WORKERS = 4;
+
+eses_status worker_streams(hipStream_t *ws) {
+    static std::mutex mu;
+    static std::map<int, std::vector<hipStream_t>> pool;
+    int dev = 0;
+    CK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    std::vector<hipStream_t> &v = pool[dev];
+    while ((int)v.size() < N_WORKERS) {
+        hipStream_t s = nullptr;
+        CK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        v.push_back(s);
+    }
+    for (int q = 0; q < N_WORKERS; ++q) ws[q] = v[q];
+    return ESES_OK;
+}
+
+// Runs job(q, stream) for q in [0, n) on the worker streams from as many
+// host threads, after the work already queued on `st`; `st` then waits for
+// all of it.  Returns the status of the lowest failing q (its message in
+// g_err, prefixed with the molecule index).
+template <class Job>
+eses_status run_on_workers(int n, hipStream_t st, Job job) {
+    hipStream_t ws[N_WORKERS];
+    CKS(worker_streams(ws));
+    const int P = std::min(N_WORKERS, n);
+    hipEvent_t ready = nullptr, done[N_WORKERS] = {};
+    CK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    CK(hipEventRecord(ready, st));
+    for (int p = 0; p < P; ++p) {
+        CK(hipEventCreateWithFlags(&done[p], hipEventDisableTiming));
+        CK(hipStreamWaitEvent(ws[p], ready, 0));
+    }
+    int dev = 0;
+    CK(hipGetDevice(&dev));
+    std::atomic<int> next{0};
+    std::vector<eses_status> res(n, ESES_OK);
+    std::vector<std::string> msg(n);
+    std::vector<std::thread> th;
+    for (int p = 0; p < P; ++p)
+        th.emplace_back([&, p]() {
+            if (hipSetDevice(dev) != hipSuccess) {
+                for (int q = next++; q < n; q = next++) {
+                    res[q] = ESES_EDEVICE;
+                    msg[q] = "hipSetDevice failed in a worker thread";
+                }
+                return;
+            }
+            for (int q = next++; q < n; q = next++) {
+                g_err.clear();
+                res[q] = job(q, ws[p]);
+                if (res[q] != ESES_OK) msg[q] = g_err;
+            }
+        });
+    for (auto &t : th) t.join();
+    eses_status out = ESES_OK;
+    for (int p = 0; p < P; ++p) {
+        if (hipEventRecord(done[p], ws[p]) != hipSuccess ||
+            hipStreamWaitEvent(st, done[p], 0) != hipSuccess)
+            out = ESES_EDEVICE;
+    }
+    (void)hipEventDestroy(ready);
+    for (int p = 0; p < P; ++p) (void)hipEventDestroy(done[p]);
+    for (int q = 0; q < n; ++q)
+        if (res[q] != ESES_OK) {
+            char pre[64];
+            snprintf(pre, sizeof pre, "molecule %d: ", q);
+            g_err = pre + msg[q];
+            return res[q];
+        }
+    if (out != ESES_OK) set_err("ordering the worker streams failed");
+    return out;
 }
 
 // Device scalars read back with one kernel and one synchronisation: each
@@ -459,12 +538,8 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, int 
     CKS(A.alloc(&m.tV, tl[3]));
     CK(launch_tiles(m, true, cA, cF, cC, cV, st));
 
-    int hdiag[1];
-    CKS(d2h_ints({{&hdiag[0], m.diag}}, st));
-    if (hdiag[0] != 0) {
-        set_err("internal: %d list entries beyond their counted range", hdiag[0]);
-        return ESES_EINTERNAL;
-    }
+    // (m.diag[0], set by a fill pass that met more entries than it counted,
+    // is checked at the next read-back: eses_edge_intersections)
 
     eses_candidate_stats &s = S->stats;
     s.n_atoms = m.n;
@@ -556,6 +631,98 @@ eses_status classify_batch(eses_candidates *c, bool fp32, uint8_t *const *labels
     return ESES_OK;
 }
 
+// Stage 3 for molecule q on stream st: crossing edges, grouping, roots.
+// counts[q] receives the number of crossing edges.  With `timed` the
+// handle's events bracket the kernels and their times are added up.
+eses_status edges_one(eses_candidates *c, size_t q, const uint8_t *lab, const eses_isect_soa &o,
+                      int64_t *counts, hipStream_t st, bool timed) {
+    const Mol &m = c->mols[q]->m;
+    Arena T;
+    T.st = st;
+    long long nb = (m.npts + 255) / 256;
+    int *bcount;
+    long long *boff, *tmp;
+    int *ovf;
+    eses_status s;
+    if ((s = T.alloc(&bcount, nb + 1)) != ESES_OK || (s = T.alloc(&boff, nb + 2)) != ESES_OK ||
+        (s = T.alloc(&tmp, scan_tmp_elems(nb) + 64)) != ESES_OK ||
+        (s = T.alloc(&ovf, 1)) != ESES_OK) {
+        T.release();
+        return s;
+    }
+    long long nblk = 0;
+    hipError_t e = timed ? hipEventRecord(c->ev[2], st) : hipSuccess;
+    if (e == hipSuccess) e = launch_edge_detect_count(lab, m, bcount, &nblk, st);
+    if (e == hipSuccess) e = scan_i64(bcount, nblk, boff, tmp, st);
+    long long total = 0;
+    long long fill_overflow = 0;
+    if (e == hipSuccess) {
+        eses_status rs =
+            read_scalars({{boff + nblk, true, &total}, {m.diag, false, &fill_overflow}}, st);
+        if (rs == ESES_OK && fill_overflow != 0) {
+            set_err("internal: %lld candidate list entries beyond their counted range",
+                    fill_overflow);
+            rs = ESES_EINTERNAL;
+        }
+        if (rs != ESES_OK) {
+            T.release();
+            return rs;
+        }
+    }
+    long long nw = std::min<long long>(total, o.capacity);
+    int *tcount = nullptr, *ccount = nullptr, *coff = nullptr, *tfill = nullptr,
+        *order = nullptr, *ttmp = nullptr, *fb = nullptr, *nfb = nullptr;
+    if (e == hipSuccess && nw > 0) {
+        if ((s = T.alloc(&tcount, m.ntiles + 1)) != ESES_OK ||
+            (s = T.alloc(&ccount, m.ntiles + 1)) != ESES_OK ||
+            (s = T.alloc(&coff, m.ntiles + 1)) != ESES_OK ||
+            (s = T.alloc(&tfill, m.ntiles + 1)) != ESES_OK ||
+            (s = T.alloc(&order, edge_order_capacity(m, nw))) != ESES_OK ||
+            (s = T.alloc(&fb, nw)) != ESES_OK || (s = T.alloc(&nfb, 1)) != ESES_OK ||
+            (s = T.alloc(&ttmp, scan_tmp_elems(m.ntiles) + 64)) != ESES_OK) {
+            T.release();
+            return s;
+        }
+    }
+    if (e == hipSuccess && nw > 0) e = launch_edge_detect_write(lab, m, boff, o.capacity, (long long *)o.key, st);
+    if (e == hipSuccess) e = fill_i32(ovf, 1, 0, st);
+    if (e == hipSuccess && nw > 0)
+        e = launch_edge_group(m, (const long long *)o.key, nw, tcount, ccount, coff, tfill,
+                              order, ttmp, st);
+    if (e == hipSuccess && timed) e = hipEventRecord(c->ev[3], st);
+    if (e == hipSuccess && timed) e = hipEventRecord(c->ev[4], st);
+    if (e == hipSuccess && nw > 0)
+        e = launch_edge_roots(m, lab, (const long long *)o.key, nw, order, tcount, coff,
+                              o.lambda, o.normal, o.patch_type, o.atoms, fb, nfb, ovf, st);
+    if (e == hipSuccess && timed) e = hipEventRecord(c->ev[5], st);
+    long long hovf = 0;
+    if (e == hipSuccess) {
+        eses_status rs = read_scalars({{ovf, false, &hovf}}, st);
+        if (rs != ESES_OK) {
+            T.release();
+            return rs;
+        }
+    }
+    if (e == hipSuccess && timed) {
+        float a = 0.0f, b = 0.0f;
+        e = hipEventElapsedTime(&a, c->ev[2], c->ev[3]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&b, c->ev[4], c->ev[5]);
+        c->detect_ms += a;
+        c->roots_ms += b;
+    }
+    T.release();
+    if (e != hipSuccess) {
+        set_err("edge intersections: %s", hipGetErrorString(e));
+        return ESES_EDEVICE;
+    }
+    if (hovf) {
+        set_err("more roots on one edge than the per-edge list holds");
+        return ESES_EINTERNAL;
+    }
+    counts[q] = total;
+    return ESES_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -635,16 +802,26 @@ eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
     hipStream_t st = (hipStream_t)stream;
     eses_candidates *c = new eses_candidates();
     c->stream = st;
-    for (int32_t q = 0; q < n_mols; ++q) {
-        MolState *S = new MolState();
-        c->mols.push_back(S);
-        eses_status s = build_one(&mols[q], tile, force_recheck, edge_fallback, S, st);
+    for (int32_t q = 0; q < n_mols; ++q) c->mols.push_back(new MolState());
+    if (n_mols == 1) {
+        eses_status s = build_one(&mols[0], tile, force_recheck, edge_fallback, c->mols[0], st);
         if (s != ESES_OK) {
             std::string msg = g_err;
             eses_free_candidates(c);
-            char pre[64];
-            snprintf(pre, sizeof pre, "molecule %d: ", q);
-            g_err = pre + msg;
+            g_err = "molecule 0: " + msg;
+            return s;
+        }
+    } else {
+        // molecules built concurrently on the worker streams; their workspace
+        // then belongs to the caller's stream, which waits for the builds
+        eses_status s = run_on_workers(n_mols, st, [&](int q, hipStream_t ws) {
+            return build_one(&mols[q], tile, force_recheck, edge_fallback, c->mols[q], ws);
+        });
+        for (MolState *S : c->mols) S->arena.st = st;
+        if (s != ESES_OK) {
+            std::string msg = g_err;
+            eses_free_candidates(c);
+            g_err = msg;
             return s;
         }
     }
@@ -769,100 +946,38 @@ eses_status eses_edge_intersections(eses_candidates *c, const uint8_t *const *la
         return ESES_EINVAL;
     }
     hipStream_t st = (hipStream_t)stream;
-    bool short_cap = false;
     const bool timed = g_timing.load() != 0;
     if (timed) CKS(ensure_events(c));
     c->detect_ms = c->roots_ms = 0.0;
-    for (size_t q = 0; q < c->mols.size(); ++q) {
-        const Mol &m = c->mols[q]->m;
+    const int nm = (int)c->mols.size();
+    for (int q = 0; q < nm; ++q) {
         const eses_isect_soa &o = out[q];
         if (!labels[q] || o.capacity < 0 ||
             (o.capacity > 0 && (!o.key || !o.lambda || !o.normal || !o.patch_type || !o.atoms))) {
-            set_err("molecule %zu: bad labels or output descriptor", q);
+            set_err("molecule %d: bad labels or output descriptor", q);
             return ESES_EINVAL;
         }
-        Arena T;
-        T.st = st;
-        long long nb = (m.npts + 255) / 256;
-        int *bcount;
-        long long *boff, *tmp;
-        int *ovf;
-        eses_status s;
-        if ((s = T.alloc(&bcount, nb + 1)) != ESES_OK || (s = T.alloc(&boff, nb + 2)) != ESES_OK ||
-            (s = T.alloc(&tmp, scan_tmp_elems(nb) + 64)) != ESES_OK ||
-            (s = T.alloc(&ovf, 1)) != ESES_OK) {
-            T.release();
-            return s;
-        }
-        long long nblk = 0;
-        hipError_t e = timed ? hipEventRecord(c->ev[2], st) : hipSuccess;
-        if (e == hipSuccess) e = launch_edge_detect_count(labels[q], m, bcount, &nblk, st);
-        if (e == hipSuccess) e = scan_i64(bcount, nblk, boff, tmp, st);
-        long long total = 0;
-        if (e == hipSuccess) {
-            eses_status rs = read_scalars({{boff + nblk, true, &total}}, st);
-            if (rs != ESES_OK) {
-                T.release();
-                return rs;
-            }
-        }
-        long long nw = std::min<long long>(total, o.capacity);
-        int *tcount = nullptr, *ccount = nullptr, *coff = nullptr, *tfill = nullptr,
-            *order = nullptr, *ttmp = nullptr, *fb = nullptr, *nfb = nullptr;
-        if (e == hipSuccess && nw > 0) {
-            if ((s = T.alloc(&tcount, m.ntiles + 1)) != ESES_OK ||
-                (s = T.alloc(&ccount, m.ntiles + 1)) != ESES_OK ||
-                (s = T.alloc(&coff, m.ntiles + 1)) != ESES_OK ||
-                (s = T.alloc(&tfill, m.ntiles + 1)) != ESES_OK ||
-                (s = T.alloc(&order, edge_order_capacity(m, nw))) != ESES_OK ||
-                (s = T.alloc(&fb, nw)) != ESES_OK || (s = T.alloc(&nfb, 1)) != ESES_OK ||
-                (s = T.alloc(&ttmp, scan_tmp_elems(m.ntiles) + 64)) != ESES_OK) {
-                T.release();
+    }
+    if (nm == 1 || timed) {
+        // one molecule, or kernel timing (events of one stream): in order on `st`
+        for (int q = 0; q < nm; ++q) {
+            eses_status s = edges_one(c, q, labels[q], out[q], counts, st, timed);
+            if (s != ESES_OK) {
+                g_err = "molecule " + std::to_string(q) + ": " + g_err;
                 return s;
             }
         }
-        if (e == hipSuccess && nw > 0) e = launch_edge_detect_write(labels[q], m, boff, o.capacity, (long long *)o.key, st);
-        if (e == hipSuccess) e = fill_i32(ovf, 1, 0, st);
-        if (e == hipSuccess && nw > 0)
-            e = launch_edge_group(m, (const long long *)o.key, nw, tcount, ccount, coff, tfill,
-                                  order, ttmp, st);
-        if (e == hipSuccess && timed) e = hipEventRecord(c->ev[3], st);
-        if (e == hipSuccess && timed) e = hipEventRecord(c->ev[4], st);
-        if (e == hipSuccess && nw > 0)
-            e = launch_edge_roots(m, labels[q], (const long long *)o.key, nw, order, tcount, coff,
-                                  o.lambda, o.normal, o.patch_type, o.atoms, fb, nfb, ovf, st);
-        if (e == hipSuccess && timed) e = hipEventRecord(c->ev[5], st);
-        long long hovf = 0;
-        if (e == hipSuccess) {
-            eses_status rs = read_scalars({{ovf, false, &hovf}}, st);
-            if (rs != ESES_OK) {
-                T.release();
-                return rs;
-            }
-        }
-        if (e == hipSuccess && timed) {
-            float a = 0.0f, b = 0.0f;
-            e = hipEventElapsedTime(&a, c->ev[2], c->ev[3]);
-            if (e == hipSuccess) e = hipEventElapsedTime(&b, c->ev[4], c->ev[5]);
-            c->detect_ms += a;
-            c->roots_ms += b;
-        }
-        T.release();
-        if (e != hipSuccess) {
-            set_err("edge intersections: %s", hipGetErrorString(e));
-            return ESES_EDEVICE;
-        }
-        if (hovf) {
-            set_err("molecule %zu: more roots on one edge than the per-edge list holds", q);
-            return ESES_EINTERNAL;
-        }
-        counts[q] = total;
-        if (total > o.capacity) short_cap = true;
+    } else {
+        // molecules concurrently on the worker streams
+        CKS(run_on_workers(nm, st, [&](int q, hipStream_t ws) {
+            return edges_one(c, q, labels[q], out[q], counts, ws, false);
+        }));
     }
-    if (short_cap) {
-        set_err("an output capacity is below the number of crossing edges (see counts)");
-        return ESES_ECAPACITY;
-    }
+    for (int q = 0; q < nm; ++q)
+        if (counts[q] > out[q].capacity) {
+            set_err("an output capacity is below the number of crossing edges (see counts)");
+            return ESES_ECAPACITY;
+        }
     return ESES_OK;
 }
 

@@ -420,22 +420,36 @@ __device__ inline int find_circle(const Mol &m, int a, int b) {
 // (points on S_i can only be inside balls of i's neighbours).  Output order:
 // k ascending, "+" before "-".
 constexpr int VX_WAVES = 4;
-constexpr int VX_NBR = 256;  // neighbours of atom i staged in LDS
+constexpr int VX_NBR = 128;  // neighbours (and circles) of atom i staged in LDS
+
+// Atom i's neighbours (cover order with (r + rho)^2, ascending order with the
+// atom records) and i's circles, staged for the wavefronts of its workgroup.
+struct VxLds {
+    double4 nat[VX_NBR];
+    double4 natasc[VX_NBR];
+    double4 coR[VX_NBR];
+    double4 cn[VX_NBR];
+    int nid[VX_NBR];
+    int nasc[VX_NBR];
+    int cj[VX_NBR];
+};
 
 // The concave probe positions on circle c = (i, j): for each neighbour k of
 // i above j, the two points of the circle at distance s_k from c_k, kept if
 // no other neighbour's SAS ball holds them (i's neighbours 0..nst-1 from
 // LDS, the rest from global memory).
 template <bool FILL>
-__device__ void vertex_circle(const Mol &m, int c, int i, int nb, int ne, int nst,
-                              const double4 *nat, const int *nid, const int *nasc,
-                              const int *cjl, int ncl, int lane, int *vcnt) {
-    // i's ascending neighbour list and the partners of i's circles, from LDS
-    // when they fit (nasc: all ne - nb entries; cjl: ncl circles)
+__device__ void vertex_circle(const Mol &m, int c, int c0, int i, int nb, int ne, int nst,
+                              const VxLds &L, int ncl, int lane, int *vcnt) {
+    // i's neighbour lists and circles come from LDS when they fit (all
+    // ne - nb neighbours; ncl >= 0 circles), else from global memory
+    const double4 *nat = L.nat;
+    const int *nid = L.nid;
     const bool asc_lds = ne - nb <= VX_NBR;
-    int j = m.circ_j[c];
-    double4 oR = m.circ_oR[c];
-    double4 n = m.circ_n[c];
+    const bool circ_lds = ncl >= 0;
+    const int j = circ_lds ? L.cj[c - c0] : m.circ_j[c];
+    const double4 oR = circ_lds ? L.coR[c - c0] : m.circ_oR[c];
+    const double4 n = circ_lds ? L.cn[c - c0] : m.circ_n[c];
     double R = oR.w;
     int count = 0;
     int wv = FILL ? m.vert_off[c] : 0, ev = FILL ? m.vert_off[c + 1] : 0;
@@ -444,7 +458,7 @@ __device__ void vertex_circle(const Mol &m, int c, int i, int nb, int ne, int ns
     int lo = nb, hi = ne;
     while (lo < hi) {
         int mid = (lo + hi) >> 1;
-        if ((asc_lds ? nasc[mid - nb] : m.nbr[mid]) <= j) lo = mid + 1;
+        if ((asc_lds ? L.nasc[mid - nb] : m.nbr[mid]) <= j) lo = mid + 1;
         else hi = mid;
     }
     for (int base = lo; base < ne; base += WAVE) {
@@ -453,8 +467,8 @@ __device__ void vertex_circle(const Mol &m, int c, int i, int nb, int ne, int ns
         double v0x = 0, v0y = 0, v0z = 0, v1x = 0, v1y = 0, v1z = 0;
         int k = -1;
         if (q < ne) {
-            k = asc_lds ? nasc[q - nb] : m.nbr[q];
-            double4 ak = m.atom[k];
+            k = asc_lds ? L.nasc[q - nb] : m.nbr[q];
+            const double4 ak = asc_lds ? L.natasc[q - nb] : m.atom[k];
             double sk = ak.w + m.rho;
             double wx = ak.x - oR.x, wy = ak.y - oR.y, wz = ak.z - oR.z;
             double t = wx * n.x + wy * n.y + wz * n.z;
@@ -517,11 +531,11 @@ __device__ void vertex_circle(const Mol &m, int c, int i, int nb, int ne, int ns
             if (f) {
                 lflag |= f;
                 int cik = -1;
-                if (ncl >= 0) {
+                if (circ_lds) {
                     int a = 0, b = ncl - 1;
                     while (a <= b) {
                         int mid = (a + b) >> 1;
-                        int v = cjl[mid];
+                        int v = L.cj[mid];
                         if (v == k) {
                             cik = m.circ_off[i] + mid;
                             break;
@@ -560,29 +574,32 @@ __device__ void vertex_circle(const Mol &m, int c, int i, int nb, int ne, int ns
 // neighbours (cover order) are staged in LDS for the exposure tests.
 template <bool FILL>
 __global__ void __launch_bounds__(VX_WAVES *WAVE) k_vertex(Mol m, int *vcnt) {
-    __shared__ double4 nat[VX_NBR];  // x, y, z, (r + rho)^2 in cover order
-    __shared__ int nid[VX_NBR];
-    __shared__ int nasc[VX_NBR];     // ascending neighbour ids
-    __shared__ int cjl[VX_NBR];      // partner j of each circle (i, j) of i, ascending
+    __shared__ VxLds L;
     const int i = blockIdx.x;
     const int c0 = m.circ_off[i], c1 = m.circ_off[i + 1];
     if (c0 == c1) return;  // uniform across the workgroup
     const int nb = m.nbr_off[i], ne = m.nbr_off[i + 1];
     const int nst = min(VX_NBR, ne - nb);
     for (int q = threadIdx.x; q < nst; q += VX_WAVES * WAVE) {
-        int l = m.nbr_cov[nb + q];
-        double4 al = m.atom[l];
-        nat[q] = make_double4(al.x, al.y, al.z, sq(al.w + m.rho));
-        nid[q] = l;
-        nasc[q] = m.nbr[nb + q];
+        const int l = m.nbr_cov[nb + q];
+        const double4 al = m.atom[l];
+        L.nat[q] = make_double4(al.x, al.y, al.z, sq(al.w + m.rho));
+        L.nid[q] = l;
+        const int k = m.nbr[nb + q];
+        L.nasc[q] = k;
+        L.natasc[q] = m.atom[k];
     }
     const int ncl = c1 - c0 <= VX_NBR ? c1 - c0 : -1;
-    for (int q = threadIdx.x; q < ncl; q += VX_WAVES * WAVE) cjl[q] = m.circ_j[c0 + q];
+    for (int q = threadIdx.x; q < ncl; q += VX_WAVES * WAVE) {
+        L.cj[q] = m.circ_j[c0 + q];
+        L.coR[q] = m.circ_oR[c0 + q];
+        L.cn[q] = m.circ_n[c0 + q];
+    }
     __syncthreads();
     const int lane = lane_id();
     for (int c = c0 + threadIdx.x / WAVE; c < c1; c += VX_WAVES) {
         if (FILL && m.vert_off[c + 1] == m.vert_off[c]) continue;  // no probe position here
-        vertex_circle<FILL>(m, c, i, nb, ne, nst, nat, nid, nasc, cjl, ncl, lane, vcnt);
+        vertex_circle<FILL>(m, c, c0, i, nb, ne, nst, L, ncl, lane, vcnt);
     }
 }
 
