@@ -639,7 +639,7 @@ eses_status edges_one(eses_candidates *c, size_t q, const uint8_t *lab, const es
     const Mol &m = c->mols[q]->m;
     Arena T;
     T.st = st;
-    long long nb = (m.npts + 255) / 256;
+    long long nb = edge_detect_blocks(m);
     int *bcount;
     long long *boff, *tmp;
     int *ovf;
@@ -684,7 +684,8 @@ eses_status edges_one(eses_candidates *c, size_t q, const uint8_t *lab, const es
             return s;
         }
     }
-    if (e == hipSuccess && nw > 0) e = launch_edge_detect_write(lab, m, boff, o.capacity, (long long *)o.key, st);
+    if (e == hipSuccess && nw > 0)
+        e = launch_edge_detect_write(lab, m, boff, o.capacity, (long long *)o.key, tcount, st);
     if (e == hipSuccess) e = fill_i32(ovf, 1, 0, st);
     if (e == hipSuccess && nw > 0)
         e = launch_edge_group(m, (const long long *)o.key, nw, tcount, ccount, coff, tfill,
@@ -1017,7 +1018,7 @@ eses_status eses_edge_work(eses_candidates *c, const uint8_t *const *labels,
         }
         Arena T;
         T.st = st;
-        long long nb = (m.npts + 255) / 256;
+        long long nb = edge_detect_blocks(m);
         int *bcount, *ovf;
         long long *boff, *tmp;
         unsigned long long *work;
@@ -1050,7 +1051,8 @@ eses_status eses_edge_work(eses_candidates *c, const uint8_t *const *labels,
         }
         if (e == hipSuccess) e = fill_u32((uint32_t *)work, 2 * EDGE_WORK_COUNTERS, 0u, st);
         if (e == hipSuccess) e = fill_i32(ovf, 1, 0, st);
-        if (e == hipSuccess && total > 0) e = launch_edge_detect_write(labels[q], m, boff, total, keys, st);
+        if (e == hipSuccess && total > 0)
+            e = launch_edge_detect_write(labels[q], m, boff, total, keys, tcount, st);
         if (e == hipSuccess && total > 0)
             e = launch_edge_group(m, keys, total, tcount, ccount, coff, tfill, order, ttmp, st);
         if (e == hipSuccess && total > 0)

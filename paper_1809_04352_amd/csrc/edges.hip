@@ -54,44 +54,85 @@ __device__ inline int edge_flags(const uint8_t *L, long long idx, int i, int j, 
     return f;
 }
 
+// Each thread takes EDGE_PPT consecutive points (in index order), each block
+// EDGE_BLOCK x EDGE_PPT of them, so that the per-block scan is amortised;
+// counts and keys come out in point order.
+constexpr int EDGE_PPT = 8;
+
+__device__ inline void point_ijk(long long idx, int nx, int ny, int &i, int &j, int &k) {
+    i = (int)(idx % nx);
+    const long long r = idx / nx;
+    j = (int)(r % ny);
+    k = (int)(r / ny);
+}
+
+// Next point after (i, j, k) in index order.
+__device__ inline void point_next(int nx, int ny, int &i, int &j, int &k) {
+    if (++i == nx) {
+        i = 0;
+        if (++j == ny) {
+            j = 0;
+            ++k;
+        }
+    }
+}
+
 __global__ void __launch_bounds__(EDGE_BLOCK) k_edge_count(const uint8_t *L, int nx, int ny,
                                                            int nz, long long npts, int *bcount) {
     __shared__ int lds[EDGE_BLOCK / WAVE + 1];
-    long long idx = (long long)blockIdx.x * EDGE_BLOCK + threadIdx.x;
+    const long long idx0 = ((long long)blockIdx.x * EDGE_BLOCK + threadIdx.x) * EDGE_PPT;
     int c = 0;
-    if (idx < npts) {
-        int i = (int)(idx % nx);
-        long long r = idx / nx;
-        int j = (int)(r % ny);
-        int k = (int)(r / ny);
-        c = __popc(edge_flags(L, idx, i, j, k, nx, ny, nz));
+    if (idx0 < npts) {
+        int i, j, k;
+        point_ijk(idx0, nx, ny, i, j, k);
+        for (int q = 0; q < EDGE_PPT && idx0 + q < npts; ++q) {
+            c += __popc(edge_flags(L, idx0 + q, i, j, k, nx, ny, nz));
+            point_next(nx, ny, i, j, k);
+        }
     }
     int tot;
     block_excl_scan<int, EDGE_BLOCK>(c, lds, &tot);
     if (threadIdx.x == 0) bcount[blockIdx.x] = tot;
 }
 
+// Also tallies the written edges per owning tile (tcount, zeroed before).
 __global__ void __launch_bounds__(EDGE_BLOCK) k_edge_write(const uint8_t *L, int nx, int ny,
                                                            int nz, long long npts,
                                                            const long long *boff, long long cap,
-                                                           long long *keys) {
+                                                           long long *keys, int *tcount, int T,
+                                                           int tdx, int tdy) {
     __shared__ int lds[EDGE_BLOCK / WAVE + 1];
-    long long idx = (long long)blockIdx.x * EDGE_BLOCK + threadIdx.x;
-    int f = 0;
-    if (idx < npts) {
-        int i = (int)(idx % nx);
-        long long r = idx / nx;
-        int j = (int)(r % ny);
-        int k = (int)(r / ny);
-        f = edge_flags(L, idx, i, j, k, nx, ny, nz);
+    const long long idx0 = ((long long)blockIdx.x * EDGE_BLOCK + threadIdx.x) * EDGE_PPT;
+    int fl[EDGE_PPT], tl[EDGE_PPT];
+    int c = 0;
+    int i = 0, j = 0, k = 0;
+    if (idx0 < npts) point_ijk(idx0, nx, ny, i, j, k);
+#pragma unroll
+    for (int q = 0; q < EDGE_PPT; ++q) {
+        fl[q] = 0;
+        tl[q] = 0;
+        if (idx0 + q < npts) {
+            fl[q] = edge_flags(L, idx0 + q, i, j, k, nx, ny, nz);
+            if (fl[q]) tl[q] = i / T + tdx * (j / T + tdy * (k / T));
+            point_next(nx, ny, i, j, k);
+        }
+        c += __popc(fl[q]);
     }
     int tot;
-    long long w = boff[blockIdx.x] + block_excl_scan<int, EDGE_BLOCK>(__popc(f), lds, &tot);
-    for (int a = 0; a < 3; ++a)
-        if (f & (1 << a)) {
-            if (w < cap) keys[w] = 3 * idx + a;
-            ++w;
-        }
+    long long w = boff[blockIdx.x] + block_excl_scan<int, EDGE_BLOCK>(c, lds, &tot);
+#pragma unroll
+    for (int q = 0; q < EDGE_PPT; ++q) {
+        int nwr = 0;
+        for (int a = 0; a < 3; ++a)
+            if (fl[q] & (1 << a)) {
+                if (w < cap) {
+                    keys[w] = 3 * (idx0 + q) + a;
+                    ++nwr;
+                }
+                ++w;
+            }
+        if (nwr) atomicAdd(&tcount[tl[q]], nwr);
+    }
 }
 
 // ------------------------------------------------------------ root finding
@@ -1534,12 +1575,6 @@ __global__ void __launch_bounds__(EW_THREADS)
 
 // ------------------------------------------------ grouping by tile, launches
 
-__global__ void k_edge_tile_count(Mol m, const long long *keys, long long count, int *tcount) {
-    long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (q >= count) return;
-    atomicAdd(&tcount[edge_tile(m, keys[q])], 1);
-}
-
 __global__ void k_edge_chunk_count(const int *tcount, int ntiles, int *ccount) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < ntiles) ccount[t] = (tcount[t] + CH_EDGES - 1) / CH_EDGES;
@@ -1562,10 +1597,8 @@ hipError_t launch_edge_group(const Mol &m, const long long *keys, long long coun
                              hipStream_t st) {
     if (count <= 0) return hipSuccess;
     unsigned nb = (unsigned)((count + 255) / 256);
-    hipError_t e = fill_i32(tcount, m.ntiles + 1, 0, st);
-    if (e == hipSuccess) e = fill_i32(tfill, m.ntiles + 1, 0, st);
+    hipError_t e = fill_i32(tfill, m.ntiles + 1, 0, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_edge_tile_count, dim3(nb), dim3(256), 0, st, m, keys, count, tcount);
     hipLaunchKernelGGL(k_edge_chunk_count, dim3((m.ntiles + 255) / 256), dim3(256), 0, st,
                        tcount, m.ntiles, ccount);
     e = scan_i32(ccount, m.ntiles, coff, tmp, st);
@@ -1575,22 +1608,27 @@ hipError_t launch_edge_group(const Mol &m, const long long *keys, long long coun
     return hipGetLastError();
 }
 
+long long edge_detect_blocks(const Mol &m) {
+    const long long per = (long long)EDGE_BLOCK * EDGE_PPT;
+    const long long nb = (m.npts + per - 1) / per;
+    return nb < 1 ? 1 : nb;
+}
+
 hipError_t launch_edge_detect_count(const uint8_t *L, const Mol &m, int *bcount, long long *nblk,
                                     hipStream_t st) {
-    long long nb = (m.npts + EDGE_BLOCK - 1) / EDGE_BLOCK;
-    if (nb < 1) nb = 1;
-    *nblk = nb;
-    hipLaunchKernelGGL(k_edge_count, dim3((unsigned)nb), dim3(EDGE_BLOCK), 0, st, L, m.dims[0],
+    *nblk = edge_detect_blocks(m);
+    hipLaunchKernelGGL(k_edge_count, dim3((unsigned)*nblk), dim3(EDGE_BLOCK), 0, st, L, m.dims[0],
                        m.dims[1], m.dims[2], m.npts, bcount);
     return hipGetLastError();
 }
 
 hipError_t launch_edge_detect_write(const uint8_t *L, const Mol &m, const long long *boff,
-                                    long long cap, long long *keys, hipStream_t st) {
-    long long nb = (m.npts + EDGE_BLOCK - 1) / EDGE_BLOCK;
-    if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(k_edge_write, dim3((unsigned)nb), dim3(EDGE_BLOCK), 0, st, L, m.dims[0],
-                       m.dims[1], m.dims[2], m.npts, boff, cap, keys);
+                                    long long cap, long long *keys, int *tcount, hipStream_t st) {
+    hipError_t e = fill_i32(tcount, m.ntiles + 1, 0, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_edge_write, dim3((unsigned)edge_detect_blocks(m)), dim3(EDGE_BLOCK), 0, st,
+                       L, m.dims[0], m.dims[1], m.dims[2], m.npts, boff, cap, keys, tcount, m.tile,
+                       m.tdims[0], m.tdims[1]);
     return hipGetLastError();
 }
 

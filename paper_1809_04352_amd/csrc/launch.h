@@ -57,11 +57,14 @@ hipError_t launch_count_inside(const uint8_t *labels, long long n, unsigned long
                                hipStream_t st);
 
 // stage 3
+// Blocks of the crossing-edge passes (one per EDGE_BLOCK points of a row).
+long long edge_detect_blocks(const Mol &m);
 hipError_t launch_edge_detect_count(const uint8_t *L, const Mol &m, int *bcount, long long *nblk,
                                     hipStream_t st);
 hipError_t launch_edge_detect_write(const uint8_t *L, const Mol &m, const long long *boff,
-                                    long long cap, long long *keys, hipStream_t st);
-// Crossing edges grouped by tile: order[] holds, per tile, its edges padded
+                                    long long cap, long long *keys, int *tcount, hipStream_t st);
+// Crossing edges grouped by tile (tcount: per-tile counts from the key pass):
+// order[] holds, per tile, its edges padded
 // to a multiple of the chunk size (edge_order_capacity entries); coff[t] is
 // the tile's first chunk and coff[ntiles] the number of chunks.
 long long edge_order_capacity(const Mol &m, long long count);
