@@ -244,20 +244,40 @@ __global__ void k_cell_scatter(Mol m, const int *cell_id, int *fill, int *slot_o
     slot_orig[pos] = i;
 }
 
-// Sort each cell's caller ids ascending (cells hold a few dozen atoms), then
-// gather the atoms into internal order.
-__global__ void k_cell_sort(Mol m, int *slot_orig) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= m.ncell) return;
-    int b = m.cell_start[c], e = m.cell_start[c + 1];
-    for (int q = b + 1; q < e; ++q) {
-        int v = slot_orig[q];
-        int p = q - 1;
-        while (p >= b && slot_orig[p] > v) {
-            slot_orig[p + 1] = slot_orig[p];
-            --p;
-        }
-        slot_orig[p + 1] = v;
+// Sort each cell's caller ids ascending, then gather the atoms into internal
+// order.  One wavefront per cell ranks its ids in LDS (the ids are distinct);
+// a cell larger than the LDS slice is sorted by one lane.
+constexpr int CS_WAVES = 4, CS_MAX = 256;
+
+__global__ void __launch_bounds__(CS_WAVES *WAVE) k_cell_sort(Mol m, int *slot_orig) {
+    __shared__ int ids[CS_WAVES][CS_MAX];
+    const int w = threadIdx.x / WAVE, lane = lane_id();
+    const int c = blockIdx.x * CS_WAVES + w;
+    if (c >= m.ncell) return;  // uniform across the wavefront; no workgroup barrier below
+    const int b = m.cell_start[c], n = m.cell_start[c + 1] - b;
+    if (n <= 1) return;
+    if (n > CS_MAX) {
+        if (lane == 0)
+            for (int q = b + 1; q < b + n; ++q) {
+                int v = slot_orig[q];
+                int p = q - 1;
+                while (p >= b && slot_orig[p] > v) {
+                    slot_orig[p + 1] = slot_orig[p];
+                    --p;
+                }
+                slot_orig[p + 1] = v;
+            }
+        return;
+    }
+    for (int q = lane; q < n; q += WAVE) ids[w][q] = slot_orig[b + q];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int q = lane; q < n; q += WAVE) {
+        const int v = ids[w][q];
+        int rank = 0;
+        for (int p = 0; p < n; ++p) rank += ids[w][p] < v ? 1 : 0;
+        slot_orig[b + rank] = v;
     }
 }
 
@@ -438,19 +458,76 @@ struct VxLds {
 // i above j, the two points of the circle at distance s_k from c_k, kept if
 // no other neighbour's SAS ball holds them (i's neighbours 0..nst-1 from
 // LDS, the rest from global memory).
+// The two points of circle (o, R, n) at distance s_k from c_k (isolated
+// points when c_k is off the axis) and whether each is exposed: in no other
+// neighbour's open SAS ball (i's neighbours 0..nst-1 from LDS in cover order,
+// the rest from global memory; j and k themselves skipped).  The loop over
+// neighbours is uniform across the wavefront and ends when no lane has an
+// exposed candidate left.
+__device__ inline void vertex_pair(const Mol &m, bool act, double4 oR, double4 n, int j, int k,
+                                   double4 ak, const VxLds &L, int nb, int ne, int nst,
+                                   bool &crossed, double *v0, double *v1, bool &ok0,
+                                   bool &ok1) {
+    const double R = oR.w;
+    bool live = false;
+    crossed = false;
+    for (int a = 0; a < 3; ++a) v0[a] = v1[a] = 0.0;
+    if (act) {
+        double sk = ak.w + m.rho;
+        double wx = ak.x - oR.x, wy = ak.y - oR.y, wz = ak.z - oR.z;
+        double t = wx * n.x + wy * n.y + wz * n.z;
+        double px = wx - t * n.x, py = wy - t * n.y, pz = wz - t * n.z;
+        double b = sqrt(px * px + py * py + pz * pz);
+        double ww = wx * wx + wy * wy + wz * wz;
+        if (b > 1e-12 * (sqrt(ww) + R)) {  // c_k off the axis: isolated points
+            double cphi = (ww + R * R - sk * sk) / (2.0 * R * b);
+            if (cphi >= -1.0 && cphi <= 1.0) {
+                live = true;
+                crossed = cphi > -1.0 && cphi < 1.0;
+                double sphi = sqrt(fmax(0.0, 1.0 - cphi * cphi));
+                double ex = px / b, ey = py / b, ez = pz / b;
+                double fx = n.y * ez - n.z * ey, fy = n.z * ex - n.x * ez, fz = n.x * ey - n.y * ex;
+                v0[0] = oR.x + R * (cphi * ex + sphi * fx);
+                v0[1] = oR.y + R * (cphi * ey + sphi * fy);
+                v0[2] = oR.z + R * (cphi * ez + sphi * fz);
+                v1[0] = oR.x + R * (cphi * ex - sphi * fx);
+                v1[1] = oR.y + R * (cphi * ey - sphi * fy);
+                v1[2] = oR.z + R * (cphi * ez - sphi * fz);
+            }
+        }
+    }
+    ok0 = live;
+    ok1 = live;
+    for (int q2 = 0; q2 < ne - nb; ++q2) {
+        if (!__any(ok0 || ok1)) break;
+        int l;
+        double4 al;
+        if (q2 < nst) {
+            l = L.nid[q2];
+            al = L.nat[q2];
+        } else {
+            l = m.nbr_cov[nb + q2];
+            double4 a = m.atom[l];
+            al = make_double4(a.x, a.y, a.z, sq(a.w + m.rho));
+        }
+        if (l == j || l == k) continue;
+        double d0 = sq(v0[0] - al.x) + sq(v0[1] - al.y) + sq(v0[2] - al.z);
+        double d1 = sq(v1[0] - al.x) + sq(v1[1] - al.y) + sq(v1[2] - al.z);
+        ok0 = ok0 && !(d0 < al.w);
+        ok1 = ok1 && !(d1 < al.w);
+    }
+}
+
 template <bool FILL>
 __device__ void vertex_circle(const Mol &m, int c, int c0, int i, int nb, int ne, int nst,
                               const VxLds &L, int ncl, int lane, int *vcnt) {
     // i's neighbour lists and circles come from LDS when they fit (all
     // ne - nb neighbours; ncl >= 0 circles), else from global memory
-    const double4 *nat = L.nat;
-    const int *nid = L.nid;
     const bool asc_lds = ne - nb <= VX_NBR;
     const bool circ_lds = ncl >= 0;
     const int j = circ_lds ? L.cj[c - c0] : m.circ_j[c];
     const double4 oR = circ_lds ? L.coR[c - c0] : m.circ_oR[c];
     const double4 n = circ_lds ? L.cn[c - c0] : m.circ_n[c];
-    double R = oR.w;
     int count = 0;
     int wv = FILL ? m.vert_off[c] : 0, ev = FILL ? m.vert_off[c + 1] : 0;
     uint32_t lflag = 0;
@@ -463,54 +540,14 @@ __device__ void vertex_circle(const Mol &m, int c, int c0, int i, int nb, int ne
     }
     for (int base = lo; base < ne; base += WAVE) {
         int q = base + lane;
-        bool live = false, crossed = false;
-        double v0x = 0, v0y = 0, v0z = 0, v1x = 0, v1y = 0, v1z = 0;
-        int k = -1;
-        if (q < ne) {
-            k = asc_lds ? L.nasc[q - nb] : m.nbr[q];
-            const double4 ak = asc_lds ? L.natasc[q - nb] : m.atom[k];
-            double sk = ak.w + m.rho;
-            double wx = ak.x - oR.x, wy = ak.y - oR.y, wz = ak.z - oR.z;
-            double t = wx * n.x + wy * n.y + wz * n.z;
-            double px = wx - t * n.x, py = wy - t * n.y, pz = wz - t * n.z;
-            double b = sqrt(px * px + py * py + pz * pz);
-            double ww = wx * wx + wy * wy + wz * wz;
-            if (b > 1e-12 * (sqrt(ww) + R)) {  // c_k off the axis: isolated points
-                double cphi = (ww + R * R - sk * sk) / (2.0 * R * b);
-                if (cphi >= -1.0 && cphi <= 1.0) {
-                    live = true;
-                    crossed = cphi > -1.0 && cphi < 1.0;
-                    double sphi = sqrt(fmax(0.0, 1.0 - cphi * cphi));
-                    double ex = px / b, ey = py / b, ez = pz / b;
-                    double fx = n.y * ez - n.z * ey, fy = n.z * ex - n.x * ez, fz = n.x * ey - n.y * ex;
-                    v0x = oR.x + R * (cphi * ex + sphi * fx);
-                    v0y = oR.y + R * (cphi * ey + sphi * fy);
-                    v0z = oR.z + R * (cphi * ez + sphi * fz);
-                    v1x = oR.x + R * (cphi * ex - sphi * fx);
-                    v1y = oR.y + R * (cphi * ey - sphi * fy);
-                    v1z = oR.z + R * (cphi * ez - sphi * fz);
-                }
-            }
-        }
-        bool ok0 = live, ok1 = live;
-        for (int q2 = 0; q2 < ne - nb; ++q2) {
-            if (!__any(ok0 || ok1)) break;
-            int l;
-            double4 al;
-            if (q2 < nst) {
-                l = nid[q2];
-                al = nat[q2];
-            } else {
-                l = m.nbr_cov[nb + q2];
-                double4 a = m.atom[l];
-                al = make_double4(a.x, a.y, a.z, sq(a.w + m.rho));
-            }
-            if (l == j || l == k) continue;
-            double d0 = sq(v0x - al.x) + sq(v0y - al.y) + sq(v0z - al.z);
-            double d1 = sq(v1x - al.x) + sq(v1y - al.y) + sq(v1z - al.z);
-            ok0 = ok0 && !(d0 < al.w);
-            ok1 = ok1 && !(d1 < al.w);
-        }
+        const bool act = q < ne;
+        const int k = act ? (asc_lds ? L.nasc[q - nb] : m.nbr[q]) : -1;
+        const double4 ak = act ? (asc_lds ? L.natasc[q - nb] : m.atom[k])
+                               : make_double4(0.0, 0.0, 0.0, 0.0);
+        bool crossed, ok0, ok1;
+        double v0[3], v1[3];
+        vertex_pair(m, act, oR, n, j, k, ak, L, nb, ne, nst, crossed, v0, v1, ok0, ok1);
+        const double v0x = v0[0], v0y = v0[1], v0z = v0[2], v1x = v1[0], v1y = v1[1], v1z = v1[2];
         unsigned long long b0 = __ballot(ok0), b1 = __ballot(ok1);
         if (FILL) {
             // lane order, "+" before "-" within a lane
@@ -575,9 +612,12 @@ __device__ void vertex_circle(const Mol &m, int c, int c0, int i, int nb, int ne
 template <bool FILL>
 __global__ void __launch_bounds__(VX_WAVES *WAVE) k_vertex(Mol m, int *vcnt) {
     __shared__ VxLds L;
+    __shared__ int pj[VX_NBR], poff[VX_NBR + 1], vc[VX_NBR], scan_lds[VX_WAVES + 1];
+    __shared__ uint32_t fl[VX_NBR];
     const int i = blockIdx.x;
     const int c0 = m.circ_off[i], c1 = m.circ_off[i + 1];
     if (c0 == c1) return;  // uniform across the workgroup
+    if (FILL && m.vert_off[c0] == m.vert_off[c1]) return;  // no probe position on i's circles
     const int nb = m.nbr_off[i], ne = m.nbr_off[i + 1];
     const int nst = min(VX_NBR, ne - nb);
     for (int q = threadIdx.x; q < nst; q += VX_WAVES * WAVE) {
@@ -597,6 +637,85 @@ __global__ void __launch_bounds__(VX_WAVES *WAVE) k_vertex(Mol m, int *vcnt) {
     }
     __syncthreads();
     const int lane = lane_id();
+    const int d = ne - nb;
+    if (!FILL && ncl >= 0 && d <= VX_NBR) {
+        // count pass over the flattened (circle, k) pairs of atom i: circle cc
+        // with partner j at ascending position pj[cc] takes the neighbours
+        // above it, pairs poff[cc] .. poff[cc + 1]
+        int np = 0;
+        if ((int)threadIdx.x < ncl) {
+            const int j = L.cj[threadIdx.x];
+            int lo = 0, hi = d;
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if (L.nasc[mid] <= j) lo = mid + 1;
+                else hi = mid;
+            }
+            pj[threadIdx.x] = lo - 1;  // the list holds j
+            np = d - lo;
+            vc[threadIdx.x] = 0;
+            fl[threadIdx.x] = 0;
+        }
+        int total;
+        const int off = block_excl_scan<int, VX_WAVES * WAVE>(np, scan_lds, &total);
+        if ((int)threadIdx.x < ncl) poff[threadIdx.x] = off;
+        if (threadIdx.x == 0) poff[ncl] = total;
+        __syncthreads();
+        for (int t0 = 0; t0 < total; t0 += VX_WAVES * WAVE) {
+            const int t = t0 + (int)threadIdx.x;
+            const bool act = t < total;
+            int cc = 0, p = 0;
+            if (act) {
+                int lo = 0, hi = ncl;
+                while (lo < hi) {
+                    int mid = (lo + hi) >> 1;
+                    if (poff[mid + 1] <= t) lo = mid + 1;
+                    else hi = mid;
+                }
+                cc = lo;
+                p = pj[cc] + 1 + (t - poff[cc]);
+            }
+            const int j = L.cj[cc], k = act ? L.nasc[p] : -1;
+            bool crossed, ok0, ok1;
+            double v0[3], v1[3];
+            vertex_pair(m, act, L.coR[cc], L.cn[cc], j, k, L.natasc[p], L, nb, ne, nst, crossed,
+                        v0, v1, ok0, ok1);
+            if (!act) continue;
+            const int nx = (ok0 ? 1 : 0) + (ok1 ? 1 : 0);
+            if (nx) atomicAdd(&vc[cc], nx);
+            const uint32_t f = (crossed ? CF_CROSSED : 0u) | (nx ? CF_EXPOSED_VERTEX : 0u);
+            if (f) {
+                atomicOr(&fl[cc], f);
+                // circle (i, k): one of i's circles, in LDS
+                int a = 0, b = ncl - 1;
+                while (a <= b) {
+                    int mid = (a + b) >> 1;
+                    int v = L.cj[mid];
+                    if (v == k) {
+                        atomicOr(&fl[mid], f);
+                        break;
+                    }
+                    if (v < k) a = mid + 1;
+                    else b = mid - 1;
+                }
+                const int cjk = find_circle(m, j, k);
+                if (cjk >= 0) atomicOr(&m.cflag[cjk], f);
+            }
+            if (nx) atomicOr(&m.aflag[k], AF_EXPOSED_VERTEX);
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < ncl) {
+            const int c = c0 + threadIdx.x;
+            const uint32_t f = fl[threadIdx.x];
+            vcnt[c] = vc[threadIdx.x];
+            if (f) atomicOr(&m.cflag[c], f);
+            if (f & CF_EXPOSED_VERTEX) {
+                atomicOr(&m.aflag[i], AF_EXPOSED_VERTEX);
+                atomicOr(&m.aflag[L.cj[threadIdx.x]], AF_EXPOSED_VERTEX);
+            }
+        }
+        return;
+    }
     for (int c = c0 + threadIdx.x / WAVE; c < c1; c += VX_WAVES) {
         if (FILL && m.vert_off[c + 1] == m.vert_off[c]) continue;  // no probe position here
         vertex_circle<FILL>(m, c, c0, i, nb, ne, nst, L, ncl, lane, vcnt);
@@ -900,7 +1019,8 @@ hipError_t launch_cell_scatter(const Mol &m, const int *cell_id, int *fill, int 
 }
 
 hipError_t launch_cell_sort_gather(const Mol &m, int *slot_orig, hipStream_t st) {
-    hipLaunchKernelGGL(k_cell_sort, dim3(blocks_for(m.ncell, 128)), dim3(128), 0, st, m, slot_orig);
+    hipLaunchKernelGGL(k_cell_sort, dim3(blocks_for(m.ncell, CS_WAVES)), dim3(CS_WAVES * WAVE), 0, st,
+                       m, slot_orig);
     hipLaunchKernelGGL(k_gather_atoms, dim3(blocks_for(m.n, 256)), dim3(256), 0, st, m, slot_orig);
     return hipGetLastError();
 }
