@@ -46,6 +46,14 @@ struct ClsPhase2 {
     double4 cn[CAP_C];     // circle n, R^2 - rho^2
     int2 cr[CAP_C];        // cut range, or (-1, exposed-circle id)
     double4 cut[CAP_CUT];
+    // staging of the cuts: per surface (faces, then circles) the first
+    // global cut, the prefix of the uncut counts (pair -> surface), the
+    // number of cuts kept and their region in `cut`
+    int ccb[CAP_F + CAP_C];
+    int coff[CAP_F + CAP_C + 1];
+    int ccur[CAP_F + CAP_C];
+    int koff[CAP_F + CAP_C];
+    int scan[CLS_WAVES + 1];
 };
 
 struct ClsShared {
@@ -117,34 +125,6 @@ __device__ inline bool cut_matters(const Cone &c, double4 cut) {
         best = vn * (cp * c.ct + sp * c.st);
     }
     return best > cut.w - 1e-9;
-}
-
-// Copy the cuts [b, e) of global `src` that matter for cone `cone` into the
-// LDS pool (one wavefront); returns the LDS range, or (-1, fallback) when
-// the pool is full.
-__device__ inline int2 stage_cuts(ClsShared &sh, const double4 *src, int b, int e,
-                                  const Cone &cone, int fallback) {
-    const int lane = lane_id();
-    int cnt = 0;
-    for (int base = b; base < e; base += WAVE) {
-        int q = base + lane;
-        bool keep = q < e && cut_matters(cone, src[q]);
-        cnt += __popcll(__ballot(keep));
-    }
-    int start = 0;
-    if (lane == 0) start = atomicAdd(&sh.pool, cnt);
-    start = __shfl(start, 0, WAVE);
-    if (start + cnt > CAP_CUT) return make_int2(-1, fallback);
-    int w = start;
-    for (int base = b; base < e; base += WAVE) {
-        int q = base + lane;
-        double4 c = q < e ? src[q] : make_double4(0, 0, 0, 0);
-        bool keep = q < e && cut_matters(cone, c);
-        unsigned long long bm = __ballot(keep);
-        if (keep) sh.p2.cut[w + mask_prefix(bm)] = c;
-        w += __popcll(bm);
-    }
-    return make_int2(start, cnt);
 }
 
 __device__ inline bool cuts_pass(const double4 *cuts, int b, int e, double dx, double dy,
@@ -373,24 +353,80 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
         for (int a = 0; a < 3; ++a) bc[a] = m.lo[a] + (double)(t3[a] * T) * m.h + half;
         rb = sqrt(3.0) * half * (1.0 + 1e-12) + 1e-12;
     }
-    const int wv = threadIdx.x / WAVE;
-    for (int q = wv; q < nF; q += CLS_WAVES) {
-        int f = m.tF[f0 + q];
-        double4 a = m.atom[m.face_atom[f]];
-        Cone cone = make_cone(bc[0] - a.x, bc[1] - a.y, bc[2] - a.z, rb);
-        int2 r = stage_cuts(sh, m.face_cut, m.face_cut_off[f], m.face_cut_off[f + 1], cone, f);
-        if (lane_id() == 0) sh.p2.fr[q] = r;
+    // cuts of the staged faces and circles that can matter inside the tile,
+    // tested with every thread on a (surface, cut) pair: one pass counts the
+    // kept cuts per surface, the next copies them into the surface's region
+    // of the pool; a surface whose kept cuts overflow the pool keeps all of
+    // its cuts in global memory
+    const int nS = nF + nC;
+    int ncut = 0;
+    if ((int)threadIdx.x < nS) {
+        const int q = threadIdx.x;
+        int id, cb, ce;
+        if (q < nF) {
+            id = m.tF[f0 + q];
+            cb = m.face_cut_off[id];
+            ce = m.face_cut_off[id + 1];
+        } else {
+            id = m.tC[c0 + q - nF];
+            cb = m.ec_cut_off[id];
+            ce = m.ec_cut_off[id + 1];
+        }
+        sh.p2.ccb[q] = cb;
+        sh.p2.ccur[q] = 0;
+        ncut = ce - cb;
     }
-    for (int q = wv; q < nC; q += CLS_WAVES) {
-        int ec = m.tC[c0 + q];
-        int ci = m.ec_circ[ec];
-        double4 oR = m.circ_oR[ci];
-        double4 n = m.circ_n[ci];
-        double wx = bc[0] - oR.x, wy = bc[1] - oR.y, wz = bc[2] - oR.z;
-        double t = wx * n.x + wy * n.y + wz * n.z;
-        Cone cone = make_cone(wx - t * n.x, wy - t * n.y, wz - t * n.z, rb);
-        int2 r = stage_cuts(sh, m.ec_cut, m.ec_cut_off[ec], m.ec_cut_off[ec + 1], cone, ec);
-        if (lane_id() == 0) sh.p2.cr[q] = r;
+    int total;
+    const int coff = block_excl_scan<int, CLS_THREADS>(ncut, sh.p2.scan, &total);
+    if ((int)threadIdx.x < nS) sh.p2.coff[threadIdx.x] = coff;
+    if (threadIdx.x == 0) sh.p2.coff[nS] = total;
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int p = threadIdx.x; p < total; p += CLS_THREADS) {
+            int lo = 0, hi = nS;
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if (sh.p2.coff[mid + 1] <= p) lo = mid + 1;
+                else hi = mid;
+            }
+            const int q = lo;
+            if (pass == 1 && sh.p2.koff[q] < 0) continue;  // not staged
+            const int c = sh.p2.ccb[q] + (p - sh.p2.coff[q]);
+            Cone cone;
+            double4 v;
+            if (q < nF) {
+                const double4 a = sh.p2.f[q];
+                cone = make_cone(bc[0] - a.x, bc[1] - a.y, bc[2] - a.z, rb);
+                v = m.face_cut[c];
+            } else {
+                const double4 oR = sh.p2.co[q - nF], n = sh.p2.cn[q - nF];
+                const double wx = bc[0] - oR.x, wy = bc[1] - oR.y, wz = bc[2] - oR.z;
+                const double t = wx * n.x + wy * n.y + wz * n.z;
+                cone = make_cone(wx - t * n.x, wy - t * n.y, wz - t * n.z, rb);
+                v = m.ec_cut[c];
+            }
+            if (!cut_matters(cone, v)) continue;
+            const int k = atomicAdd(&sh.p2.ccur[q], 1);
+            if (pass == 1) sh.p2.cut[sh.p2.koff[q] + k] = v;
+        }
+        if (pass == 1) break;
+        // kept counts -> regions of the pool
+        __syncthreads();
+        int kept = 0;
+        if ((int)threadIdx.x < nS) kept = sh.p2.ccur[threadIdx.x];
+        int ktot;
+        const int koff = block_excl_scan<int, CLS_THREADS>(kept, sh.p2.scan, &ktot);
+        if ((int)threadIdx.x < nS) {
+            const int q = threadIdx.x;
+            const bool fits = koff + kept <= CAP_CUT;
+            sh.p2.koff[q] = fits ? koff : -1;
+            sh.p2.ccur[q] = 0;
+            const int2 r = fits ? make_int2(koff, kept)
+                                : make_int2(-1, q < nF ? m.tF[f0 + q] : m.tC[c0 + q - nF]);
+            if (q < nF) sh.p2.fr[q] = r;
+            else sh.p2.cr[q - nF] = r;
+        }
+        __syncthreads();
     }
     __syncthreads();
     for (int q = threadIdx.x; q < nq; q += CLS_THREADS) {
