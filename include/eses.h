@@ -190,7 +190,9 @@ eses_status eses_classify(eses_candidates *c, eses_precision prec, uint8_t *cons
  * labels: host array of n_mols DEVICE pointers (as written by eses_classify).
  * out: host array of n_mols SoA descriptors.  counts: host [n_mols], receives
  * the number of crossing edges per molecule; records beyond a molecule's
- * capacity are dropped and ESES_ECAPACITY is returned.  Synchronises. */
+ * capacity are dropped and ESES_ECAPACITY is returned.  ESES_EINTERNAL if a
+ * candidate list of the build met more entries than it had counted, or an
+ * edge has more roots than the per-edge lists hold.  Synchronises. */
 eses_status eses_edge_intersections(eses_candidates *c, const uint8_t *const *labels,
                                     const eses_isect_soa *out, int64_t *counts, void *stream);
 

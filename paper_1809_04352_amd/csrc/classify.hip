@@ -26,7 +26,7 @@ constexpr int CLS_THREADS = 256;
 constexpr int CLS_WAVES = CLS_THREADS / WAVE;
 constexpr int CLS_ATOMS = 256;
 constexpr int CLS_MAXPTS = 512;  // points per tile (8^3)
-constexpr int CAP_V = 64, CAP_F = 64, CAP_C = 64, CAP_CUT = 512;
+constexpr int CAP_V = 48, CAP_F = 48, CAP_C = 48, CAP_CUT = 256;
 
 struct ClsPhase1 {
     double4 a[CLS_ATOMS];  // FP64: x, y, z, r^2
