@@ -671,13 +671,14 @@ eses_status edges_one(eses_candidates *c, size_t q, const uint8_t *lab, const es
     }
     long long nw = std::min<long long>(total, o.capacity);
     int *tcount = nullptr, *ccount = nullptr, *coff = nullptr, *tfill = nullptr,
-        *order = nullptr, *ttmp = nullptr, *fb = nullptr, *nfb = nullptr;
+        *order = nullptr, *units = nullptr, *ttmp = nullptr, *fb = nullptr, *nfb = nullptr;
     if (e == hipSuccess && nw > 0) {
         if ((s = T.alloc(&tcount, m.ntiles + 1)) != ESES_OK ||
             (s = T.alloc(&ccount, m.ntiles + 1)) != ESES_OK ||
             (s = T.alloc(&coff, m.ntiles + 1)) != ESES_OK ||
             (s = T.alloc(&tfill, m.ntiles + 1)) != ESES_OK ||
             (s = T.alloc(&order, edge_order_capacity(m, nw))) != ESES_OK ||
+            (s = T.alloc(&units, edge_units_capacity(m))) != ESES_OK ||
             (s = T.alloc(&fb, nw)) != ESES_OK || (s = T.alloc(&nfb, 1)) != ESES_OK ||
             (s = T.alloc(&ttmp, scan_tmp_elems(m.ntiles) + 64)) != ESES_OK) {
             T.release();
@@ -689,11 +690,11 @@ eses_status edges_one(eses_candidates *c, size_t q, const uint8_t *lab, const es
     if (e == hipSuccess) e = fill_i32(ovf, 1, 0, st);
     if (e == hipSuccess && nw > 0)
         e = launch_edge_group(m, (const long long *)o.key, nw, tcount, ccount, coff, tfill,
-                              order, ttmp, st);
+                              order, units, ttmp, st);
     if (e == hipSuccess && timed) e = hipEventRecord(c->ev[3], st);
     if (e == hipSuccess && timed) e = hipEventRecord(c->ev[4], st);
     if (e == hipSuccess && nw > 0)
-        e = launch_edge_roots(m, lab, (const long long *)o.key, nw, order, tcount, coff,
+        e = launch_edge_roots(m, lab, (const long long *)o.key, nw, order, tcount, coff, units,
                               o.lambda, o.normal, o.patch_type, o.atoms, fb, nfb, ovf, st);
     if (e == hipSuccess && timed) e = hipEventRecord(c->ev[5], st);
     long long hovf = 0;
@@ -1036,13 +1037,14 @@ eses_status eses_edge_work(eses_candidates *c, const uint8_t *const *labels,
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         long long *keys = nullptr;
         int *tcount = nullptr, *ccount = nullptr, *coff = nullptr, *tfill = nullptr,
-            *order = nullptr, *ttmp = nullptr, *fb = nullptr, *nfb = nullptr;
+            *order = nullptr, *units = nullptr, *ttmp = nullptr, *fb = nullptr, *nfb = nullptr;
         if (e == hipSuccess && total > 0) {
             if ((s = T.alloc(&keys, total)) != ESES_OK || (s = T.alloc(&tcount, m.ntiles + 1)) != ESES_OK ||
                 (s = T.alloc(&ccount, m.ntiles + 1)) != ESES_OK ||
                 (s = T.alloc(&coff, m.ntiles + 1)) != ESES_OK ||
                 (s = T.alloc(&tfill, m.ntiles + 1)) != ESES_OK ||
                 (s = T.alloc(&order, edge_order_capacity(m, total))) != ESES_OK ||
+                (s = T.alloc(&units, edge_units_capacity(m))) != ESES_OK ||
                 (s = T.alloc(&fb, total)) != ESES_OK || (s = T.alloc(&nfb, 1)) != ESES_OK ||
                 (s = T.alloc(&ttmp, scan_tmp_elems(m.ntiles) + 64)) != ESES_OK) {
                 T.release();
@@ -1054,9 +1056,11 @@ eses_status eses_edge_work(eses_candidates *c, const uint8_t *const *labels,
         if (e == hipSuccess && total > 0)
             e = launch_edge_detect_write(labels[q], m, boff, total, keys, tcount, st);
         if (e == hipSuccess && total > 0)
-            e = launch_edge_group(m, keys, total, tcount, ccount, coff, tfill, order, ttmp, st);
+            e = launch_edge_group(m, keys, total, tcount, ccount, coff, tfill, order, units, ttmp,
+                                  st);
         if (e == hipSuccess && total > 0)
-            e = launch_edge_work(m, labels[q], keys, total, order, tcount, coff, fb, nfb, ovf, work, st);
+            e = launch_edge_work(m, labels[q], keys, total, order, tcount, coff, units, fb, nfb, ovf,
+                                 work, st);
         unsigned long long h[EDGE_WORK_COUNTERS] = {0};
         if (e == hipSuccess) e = hipMemcpyAsync(h, work, sizeof(h), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -11,6 +11,9 @@
 //     interval whose label differs from Inside[s]; lambda = 1 - u*.  Edges
 //     are processed in chunks of one tile (a workgroup per chunk, the tile's
 //     surfaces staged in LDS).
+#include <algorithm>
+#include <atomic>
+
 #include "eses_device.h"
 #include "launch.h"
 
@@ -645,6 +648,13 @@ struct ChunkLds {
     double4 cut[CH_CUTS];
     double xs[CH_EDGES][3];
     union {
+        // staging: the surfaces' first global cut, the offsets of their
+        // (surface, cut) pairs and the cursors of their kept cuts
+        struct {
+            int ccb[CH_SURF];
+            int coff[CH_SURF + 1];
+            int ccur[CH_SURF];
+        } st;
         // solve phase: roots of one quartic per thread
         double slot[CH_SLOTS][CH_THREADS];
         // walk phase: label queries (edge, midpoint parameter), their test
@@ -674,7 +684,7 @@ struct ChunkLds {
     // somewhere on the edge (bit masks over the staged arrays)
     unsigned long long amask[CH_EDGES][CH_ATOMS / 64];
     unsigned long long smask[CH_EDGES][CH_SURF / 64];
-    int npair_s, npair_t, nf, ovf, tile, fb_base, nq, pool;
+    int npair_s, npair_t, nf, ovf, tile, fb_base, nq;
 };
 
 // The cut tests of staged surface s, on its planes in LDS or, where they did
@@ -1030,7 +1040,7 @@ template <bool CNT>
 __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys,
                            const int *order, int g0, int n, double *lam, double *nrm,
                            uint8_t *ptype, int *patoms, int *fallback, int *nfallback,
-                           ChunkLds &S, unsigned long long *cnt) {
+                           bool same_tile, ChunkLds &S, unsigned long long *cnt) {
     const int tid = threadIdx.x;
     const double h = m.h, rho = m.rho;
     const double half = 0.5 * h + 1e-9;
@@ -1057,8 +1067,12 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
     const int a0 = m.tA_off[tile];
     const int nA = m.tA_off[tile + 1] - a0;
     const int nAst = min(CH_ATOMS, nA);
-    for (int q = tid; q < nAst; q += CH_THREADS) S.atoms[q] = m.atom[m.tA[a0 + q]];
+    // the previous chunk of this block covered the same tile: its staged
+    // atoms, and its staged surfaces if the tile took one pass, still hold
+    if (!same_tile)
+        for (int q = tid; q < nAst; q += CH_THREADS) S.atoms[q] = m.atom[m.tA[a0 + q]];
     const int ns_all = tile_surfaces(m, tile);
+    const bool restage = !same_tile || ns_all > CH_SURF;
     // one surface pass with every atom staged: labels from the per-edge masks
     const bool filt = ns_all > 0 && ns_all <= CH_SURF && nA <= CH_ATOMS;
     // ball holding every point of the tile's edges: points T t .. T t + T per axis
@@ -1073,60 +1087,65 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
     for (int sb = 0; sb < ns_all; sb += CH_SURF) {
         const int ns = min(CH_SURF, ns_all - sb);
         // stage the pass's surfaces and, culled to the tile's direction cone,
-        // as many of their cut planes as fit (one wavefront per surface); a
-        // surface that one cut rejects over the whole cone is dead in this tile
-        if (tid < ns) {
-            const int key = tile_surface_key(m, tile, sb + tid);
-            S.skey[tid] = key;
-            S.sp[tid] = surf_params(m, key);
-        }
-        if (tid == 0) S.pool = 0;
-        __syncthreads();
-        for (int q = tid / WAVE; q < ns; q += CH_THREADS / WAVE) {
-            const int lane = lane_id();
-            const int key = S.skey[q], type = key >> 28;
-            int cb, ce;
-            const double4 *gc = global_cuts(m, key, &cb, &ce);
-            const DirCone cone = surface_cone(type, S.sp[q], bc, rb);
-            bool dead = false;
-            int nkeep = 0;
-            for (int base = cb; base < ce; base += WAVE) {
-                const int c = base + lane;
-                bool rej = false, keep = false;
-                if (c < ce) {
-                    const double4 v = gc[c];
-                    rej = cone_rejects(cone, v);
-                    keep = cone_may_reject(cone, v);
-                }
-                dead = dead || __any(rej);
-                nkeep += __popcll(__ballot(keep));
+        // their cut planes, every thread on a (surface, cut) pair: one sweep
+        // marks the surfaces that one cut rejects over the whole cone (dead
+        // in this tile) and counts the cuts kept, the next copies the kept
+        // cuts of the surfaces that fit the pool; the others keep every cut
+        // in global memory
+        if (restage) {
+            int ncut = 0;
+            if (tid < ns) {
+                const int key = tile_surface_key(m, tile, sb + tid);
+                S.skey[tid] = key;
+                S.sp[tid] = surf_params(m, key);
+                int cb, ce;
+                global_cuts(m, key, &cb, &ce);
+                S.st.ccb[tid] = cb;
+                S.st.ccur[tid] = 0;
+                S.sdead[tid] = 0;
+                ncut = ce - cb;
             }
-            int start = 0;
-            if (lane == 0 && !dead) start = atomicAdd(&S.pool, nkeep);
-            start = __shfl(start, 0, WAVE);
-            const bool fits = !dead && start + nkeep <= CH_CUTS;
-            if (fits) {
-                int w = start;
-                for (int base = cb; base < ce; base += WAVE) {
-                    const int c = base + lane;
-                    double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
-                    bool keep = false;
-                    if (c < ce) {
-                        v = gc[c];
-                        keep = cone_may_reject(cone, v);
+            int total;
+            const int off = block_excl_scan<int, CH_THREADS>(ncut, S.scan, &total);
+            if (tid < ns) S.st.coff[tid] = off;
+            if (tid == 0) S.st.coff[ns] = total;
+            __syncthreads();
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int p = tid; p < total; p += CH_THREADS) {
+                    int lo = 0, hi = ns;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (S.st.coff[mid + 1] <= p) lo = mid + 1;
+                        else hi = mid;
                     }
-                    const unsigned long long bm = __ballot(keep);
-                    if (keep) S.cut[w + mask_prefix(bm)] = v;
-                    w += __popcll(bm);
+                    const int q = lo;
+                    if (pass == 1 && S.crange[q].x < 0) continue;  // not pooled
+                    const int type = S.skey[q] >> 28;
+                    const double4 *gc = type == 1 ? m.face_cut : m.ec_cut;
+                    const double4 v = gc[S.st.ccb[q] + (p - S.st.coff[q])];
+                    const DirCone cone = surface_cone(type, S.sp[q], bc, rb);
+                    if (pass == 0 && cone_rejects(cone, v)) S.sdead[q] = 1;
+                    if (!cone_may_reject(cone, v)) continue;
+                    const int k = atomicAdd(&S.st.ccur[q], 1);
+                    if (pass == 1) S.cut[S.crange[q].x + k] = v;
                 }
+                if (pass == 1) break;
+                __syncthreads();
+                const bool dead = tid < ns && S.sdead[tid];
+                const int kept = tid < ns && !dead ? S.st.ccur[tid] : 0;
+                int ktot;
+                const int koff = block_excl_scan<int, CH_THREADS>(kept, S.scan, &ktot);
+                if (tid < ns) {
+                    const int cb = S.st.ccb[tid];
+                    const int ce = cb + S.st.coff[tid + 1] - S.st.coff[tid];
+                    const bool fits = !dead && koff + kept <= CH_CUTS;
+                    S.crange[tid] = fits ? make_int2(koff, koff + kept) : make_int2(-1 - cb, ce);
+                    S.st.ccur[tid] = 0;
+                }
+                __syncthreads();
             }
-            if (lane == 0) {
-                S.sdead[q] = dead ? 1 : 0;
-                // every cut, in global memory, when the pool is full (or dead)
-                S.crange[q] = fits ? make_int2(start, start + nkeep) : make_int2(-1 - cb, ce);
-            }
+            __syncthreads();
         }
-        __syncthreads();
         // atoms whose SAS ball can hold a point of an edge (label masks)
         if (filt && sb == 0) {
             for (int p = tid; p < n * nAst; p += CH_THREADS) {
@@ -1378,29 +1397,34 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
 
 // Chunk c covers positions [CH_EDGES c, CH_EDGES c + n) of `order`, all in
 // one tile (each tile's segment is padded to a multiple of CH_EDGES).  The
-// grid is a multiple of the XCD count; XCD x takes the x-th contiguous range
-// of chunks, so that neighbouring tiles share an L2.
+// grid is persistent: blocks take the units (tiles with edges, the ones with
+// most chunks first) from one counter, and a block runs every chunk of its
+// tile in a row, staging the tile once.
 template <bool CNT>
 __global__ void __launch_bounds__(CH_THREADS) __attribute__((amdgpu_waves_per_eu(3)))
     k_edge_chunks(Mol m, const uint8_t *L, const long long *keys, const int *order,
-                  const int *tcount, const int *coff, double *lam, double *nrm, uint8_t *ptype,
-                  int *patoms, int *fallback, int *nfallback, unsigned long long *work) {
+                  const int *tcount, const int *coff, int *units, double *lam, double *nrm,
+                  uint8_t *ptype, int *patoms, int *fallback, int *nfallback,
+                  unsigned long long *work) {
     __shared__ ChunkLds S;
+    __shared__ int next;
     unsigned long long cnt[CNT ? EC_COUNT + 1 : 1];
     for (int c = 0; c < (CNT ? (int)EC_COUNT + 1 : 1); ++c) cnt[c] = 0;
-    const int nch = coff[m.ntiles];
-    const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
-    const int per_xcd = (int)(gridDim.x / NXCD);
-    const int per = (nch + NXCD - 1) / NXCD;
-    const int cend = min(nch, (xcd + 1) * per);
-    for (int c = xcd * per + slot; c < cend; c += per_xcd) {
-        const int g0 = c * CH_EDGES;
-        // the chunk's tile and edge count
-        const int t = edge_tile(m, keys[order[g0]]);
-        const int n = min(CH_EDGES, tcount[t] - (g0 - coff[t] * CH_EDGES));
-        edge_chunk<CNT>(m, L, keys, order, g0, n, lam, nrm, ptype, patoms, fallback, nfallback,
-                        S, cnt);
+    const int nunits = units[EU_COUNT];
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(&units[EU_QUEUE], 1);
         __syncthreads();
+        const int u = next;
+        __syncthreads();
+        if (u >= nunits) break;
+        const int t = units[EU_LIST + u];
+        for (int c = coff[t]; c < coff[t + 1]; ++c) {
+            const int g0 = c * CH_EDGES;
+            const int n = min(CH_EDGES, tcount[t] - (c - coff[t]) * CH_EDGES);
+            edge_chunk<CNT>(m, L, keys, order, g0, n, lam, nrm, ptype, patoms, fallback,
+                            nfallback, c != coff[t], S, cnt);
+            __syncthreads();
+        }
     }
     if (CNT)
         for (int c = 0; c < EC_COUNT; ++c)
@@ -1575,9 +1599,54 @@ __global__ void __launch_bounds__(EW_THREADS)
 
 // ------------------------------------------------ grouping by tile, launches
 
-__global__ void k_edge_chunk_count(const int *tcount, int ntiles, int *ccount) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < ntiles) ccount[t] = (tcount[t] + CH_EDGES - 1) / CH_EDGES;
+// Chunks per tile, and the tiles with edges counted by class min(chunks,
+// EU_CLASSES) (in LDS, then one global add per class and block).
+__global__ void __launch_bounds__(256) k_edge_chunk_count(const int *tcount, int ntiles,
+                                                          int *ccount, int *units) {
+    __shared__ int cls[EU_CLASSES];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (threadIdx.x < EU_CLASSES) cls[threadIdx.x] = 0;
+    __syncthreads();
+    if (t < ntiles) {
+        const int c = (tcount[t] + CH_EDGES - 1) / CH_EDGES;
+        ccount[t] = c;
+        if (c > 0) atomicAdd(&cls[min(c, EU_CLASSES) - 1], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < EU_CLASSES && cls[threadIdx.x] > 0)
+        atomicAdd(&units[EU_CLASS + threadIdx.x], cls[threadIdx.x]);
+}
+
+// The unit list: tiles with edges, classes of more chunks first.  A block
+// ranks its tiles per class in LDS and reserves each class's run with one
+// global add.
+__global__ void __launch_bounds__(256) k_edge_unit_order(const int *ccount, int ntiles,
+                                                         int *units) {
+    __shared__ int cls[EU_CLASSES], base[EU_CLASSES];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) {
+        int tot = 0;
+        for (int b = 0; b < EU_CLASSES; ++b) tot += units[EU_CLASS + b];
+        units[EU_COUNT] = tot;
+    }
+    if (threadIdx.x < EU_CLASSES) cls[threadIdx.x] = 0;
+    __syncthreads();
+    int b = -1, r = 0;
+    if (t < ntiles) {
+        const int c = ccount[t];
+        if (c > 0) {
+            b = min(c, EU_CLASSES) - 1;
+            r = atomicAdd(&cls[b], 1);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < EU_CLASSES && cls[threadIdx.x] > 0) {
+        int off = 0;
+        for (int k = threadIdx.x + 1; k < EU_CLASSES; ++k) off += units[EU_CLASS + k];
+        base[threadIdx.x] = off + atomicAdd(&units[EU_FILL + threadIdx.x], cls[threadIdx.x]);
+    }
+    __syncthreads();
+    if (b >= 0) units[EU_LIST + base[b] + r] = t;
 }
 
 __global__ void k_edge_tile_scatter(Mol m, const long long *keys, long long count,
@@ -1592,19 +1661,24 @@ long long edge_order_capacity(const Mol &m, long long count) {
     return count + (long long)(CH_EDGES - 1) * std::min<long long>(m.ntiles, count);
 }
 
+long long edge_units_capacity(const Mol &m) { return EU_LIST + (long long)m.ntiles; }
+
 hipError_t launch_edge_group(const Mol &m, const long long *keys, long long count, int *tcount,
-                             int *ccount, int *coff, int *tfill, int *order, int *tmp,
-                             hipStream_t st) {
+                             int *ccount, int *coff, int *tfill, int *order, int *units,
+                             int *tmp, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     unsigned nb = (unsigned)((count + 255) / 256);
+    const unsigned tb = (unsigned)((m.ntiles + 255) / 256);
     hipError_t e = fill_i32(tfill, m.ntiles + 1, 0, st);
+    if (e == hipSuccess) e = fill_i32(units, EU_LIST, 0, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_edge_chunk_count, dim3((m.ntiles + 255) / 256), dim3(256), 0, st,
-                       tcount, m.ntiles, ccount);
+    hipLaunchKernelGGL(k_edge_chunk_count, dim3(tb), dim3(256), 0, st, tcount, m.ntiles, ccount,
+                       units);
     e = scan_i32(ccount, m.ntiles, coff, tmp, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_edge_tile_scatter, dim3(nb), dim3(256), 0, st, m, keys, count, coff,
                        tfill, order);
+    hipLaunchKernelGGL(k_edge_unit_order, dim3(tb), dim3(256), 0, st, ccount, m.ntiles, units);
     return hipGetLastError();
 }
 
@@ -1635,25 +1709,41 @@ hipError_t launch_edge_detect_write(const uint8_t *L, const Mol &m, const long l
 // Chunk kernel over every chunk, then the wavefront kernel over the edges of
 // chunks that overflowed (normally none).  With work != nullptr the
 // statistics variants run and no record is written.
+// Resident blocks of the chunk kernel on the current device (its persistent grid).
+static int edge_chunk_slots() {
+    static std::atomic<int> slots[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    int v = slots[dev].load(std::memory_order_relaxed);
+    if (v > 0) return v;
+    int ncu = 0, per = 0;
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_edge_chunks<false>, CH_THREADS, 0);
+    v = std::max(1, ncu) * std::max(1, per);
+    slots[dev].store(v, std::memory_order_relaxed);
+    return v;
+}
+
 static hipError_t edge_roots_impl(const Mol &m, const uint8_t *L, const long long *keys,
                                   long long count, const int *order, const int *tcount,
-                                  const int *coff, double *lam, double *nrm, uint8_t *ptype,
-                                  int *patoms, int *fallback, int *nfallback, int *overflow,
-                                  unsigned long long *work, hipStream_t st) {
+                                  const int *coff, int *units, double *lam, double *nrm,
+                                  uint8_t *ptype, int *patoms, int *fallback, int *nfallback,
+                                  int *overflow, unsigned long long *work, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     hipError_t e = fill_i32(nfallback, 1, 0, st);
+    if (e == hipSuccess) e = fill_i32(units + EU_QUEUE, 1, 0, st);
     if (e != hipSuccess) return e;
-    long long chunks_max = (count + CH_EDGES - 1) / CH_EDGES + std::min<long long>(m.ntiles, count);
-    long long grid = std::min<long long>(chunks_max, 2048);
-    grid = (grid + NXCD - 1) / NXCD * NXCD;
+    // no more blocks than units (tiles with edges) or than fit on the device
+    const long long grid =
+        std::min<long long>(std::min<long long>(m.ntiles, count), edge_chunk_slots());
     if (work)
         hipLaunchKernelGGL(k_edge_chunks<true>, dim3((unsigned)grid), dim3(CH_THREADS), 0, st, m,
-                           L, keys, order, tcount, coff, lam, nrm, ptype, patoms, fallback,
-                           nfallback, work);
+                           L, keys, order, tcount, coff, units, lam, nrm, ptype, patoms,
+                           fallback, nfallback, work);
     else
         hipLaunchKernelGGL(k_edge_chunks<false>, dim3((unsigned)grid), dim3(CH_THREADS), 0, st,
-                           m, L, keys, order, tcount, coff, lam, nrm, ptype, patoms, fallback,
-                           nfallback, work);
+                           m, L, keys, order, tcount, coff, units, lam, nrm, ptype, patoms,
+                           fallback, nfallback, work);
     if (work)
         hipLaunchKernelGGL(k_edge_wave<true>, dim3(256), dim3(EW_THREADS), 0, st, m, L, keys,
                            fallback, nfallback, lam, nrm, ptype, patoms, overflow, work);
@@ -1665,19 +1755,19 @@ static hipError_t edge_roots_impl(const Mol &m, const uint8_t *L, const long lon
 
 hipError_t launch_edge_roots(const Mol &m, const uint8_t *L, const long long *keys,
                              long long count, const int *order, const int *tcount,
-                             const int *coff, double *lam, double *nrm, uint8_t *ptype,
-                             int *patoms, int *fallback, int *nfallback, int *overflow,
-                             hipStream_t st) {
-    return edge_roots_impl(m, L, keys, count, order, tcount, coff, lam, nrm, ptype, patoms,
-                           fallback, nfallback, overflow, nullptr, st);
+                             const int *coff, int *units, double *lam, double *nrm,
+                             uint8_t *ptype, int *patoms, int *fallback, int *nfallback,
+                             int *overflow, hipStream_t st) {
+    return edge_roots_impl(m, L, keys, count, order, tcount, coff, units, lam, nrm, ptype,
+                           patoms, fallback, nfallback, overflow, nullptr, st);
 }
 
 hipError_t launch_edge_work(const Mol &m, const uint8_t *L, const long long *keys,
                             long long count, const int *order, const int *tcount,
-                            const int *coff, int *fallback, int *nfallback, int *overflow,
-                            unsigned long long *work, hipStream_t st) {
-    return edge_roots_impl(m, L, keys, count, order, tcount, coff, nullptr, nullptr, nullptr,
-                           nullptr, fallback, nfallback, overflow, work, st);
+                            const int *coff, int *units, int *fallback, int *nfallback,
+                            int *overflow, unsigned long long *work, hipStream_t st) {
+    return edge_roots_impl(m, L, keys, count, order, tcount, coff, units, nullptr, nullptr,
+                           nullptr, nullptr, fallback, nfallback, overflow, work, st);
 }
 
 }  // namespace eses

@@ -66,23 +66,30 @@ hipError_t launch_edge_detect_write(const uint8_t *L, const Mol &m, const long l
 // Crossing edges grouped by tile (tcount: per-tile counts from the key pass):
 // order[] holds, per tile, its edges padded
 // to a multiple of the chunk size (edge_order_capacity entries); coff[t] is
-// the tile's first chunk and coff[ntiles] the number of chunks.
+// the tile's first chunk and coff[ntiles] the number of chunks.  units
+// (edge_units_capacity ints) receives the work list of the root kernel: the
+// tile counts per chunk-count class and their fill cursors, the queue
+// counter, the number of units and, from EU_LIST on, the tiles with edges,
+// the ones with most chunks first.
+constexpr int EU_CLASSES = 8;
+constexpr int EU_CLASS = 0, EU_FILL = 8, EU_QUEUE = 16, EU_COUNT = 24, EU_LIST = 32;
 long long edge_order_capacity(const Mol &m, long long count);
+long long edge_units_capacity(const Mol &m);
 hipError_t launch_edge_group(const Mol &m, const long long *keys, long long count, int *tcount,
-                             int *ccount, int *coff, int *tfill, int *order, int *tmp,
-                             hipStream_t st);
+                             int *ccount, int *coff, int *tfill, int *order, int *units,
+                             int *tmp, hipStream_t st);
 // fallback: count ints; nfallback, overflow: one int each (overflow is set,
 // not cleared).
 hipError_t launch_edge_roots(const Mol &m, const uint8_t *L, const long long *keys,
                              long long count, const int *order, const int *tcount,
-                             const int *coff, double *lam, double *nrm, uint8_t *ptype,
-                             int *patoms, int *fallback, int *nfallback, int *overflow,
-                             hipStream_t st);
+                             const int *coff, int *units, double *lam, double *nrm,
+                             uint8_t *ptype, int *patoms, int *fallback, int *nfallback,
+                             int *overflow, hipStream_t st);
 
 hipError_t launch_edge_work(const Mol &m, const uint8_t *L, const long long *keys,
                             long long count, const int *order, const int *tcount,
-                            const int *coff, int *fallback, int *nfallback, int *overflow,
-                            unsigned long long *work, hipStream_t st);
+                            const int *coff, int *units, int *fallback, int *nfallback,
+                            int *overflow, unsigned long long *work, hipStream_t st);
 
 constexpr int EDGE_WORK_COUNTERS = 16;
 
