@@ -664,6 +664,7 @@ struct ChunkLds {
             double qu[CH_Q];
             int qflag[CH_Q];
             int qoff[CH_Q + 1];
+            int qskip[CH_Q];  // mask bits before the query's tests of a phase
             unsigned char qe[CH_Q];
         } q;
     };
@@ -1084,6 +1085,13 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
         for (int a = 0; a < 3; ++a) bc[a] = m.lo[a] + (t3[a] * T + 0.5 * T) * h;
     }
     const double rb = sqrt(3.0) * 0.5 * T * h * (1.0 + 1e-12) + 1e-9;
+    // pair p -> (p / n, p % n) by a multiply: with n in [2, 64] and
+    // p < 2^16, floor(p * ceil(2^32 / n) / 2^32) is p / n exactly
+    const unsigned ninv = n > 1 ? 0xFFFFFFFFu / (unsigned)n + 1u : 0u;
+    auto split = [&](int p, int &hi, int &lo) {
+        hi = n > 1 ? (int)__umulhi((unsigned)p, ninv) : p;
+        lo = p - hi * n;
+    };
     for (int sb = 0; sb < ns_all; sb += CH_SURF) {
         const int ns = min(CH_SURF, ns_all - sb);
         // stage the pass's surfaces and, culled to the tile's direction cone,
@@ -1149,7 +1157,8 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
         // atoms whose SAS ball can hold a point of an edge (label masks)
         if (filt && sb == 0) {
             for (int p = tid; p < n * nAst; p += CH_THREADS) {
-                const int ei = p % n, ai = p / n;
+                int ei, ai;
+                split(p, ai, ei);
                 const double4 a = S.atoms[ai];
                 const int axis = S.einfo[ei] & 3;
                 double dm2 = 0.0;
@@ -1177,7 +1186,8 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
                 for (int r = 0; r < CH_ROUND; r += CH_THREADS) {
                     const int p = pb + r + tid;
                     if (p >= npairs) break;
-                    const int ei = p % n, si = p / n;
+                    int ei, si;
+                    split(p, si, ei);
                     const int type = S.skey[si] >> 28;
                     double mid[3];
                     const int axis = S.einfo[ei] & 3;
@@ -1341,30 +1351,42 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
                 if (CNT) cnt[EC_LABEL] += nqe;
             }
             __syncthreads();
-            int kq = 0;
-            if (tid < nq) {
-                const int e = S.q.qe[tid];
-                for (int w = 0; w < CH_ATOMS / 64; ++w) kq += __popcll(S.amask[e][w]);
-                for (int w = 0; w < CH_SURF / 64; ++w) kq += __popcll(S.smask[e][w]);
-                S.q.qflag[tid] = 0;
-            }
-            int tot;
-            const int off = block_excl_scan<int, CH_THREADS>(kq, S.scan, &tot);
-            if (tid < nq) S.q.qoff[tid] = off;
-            if (tid == 0) S.q.qoff[nq] = tot;
-            __syncthreads();
-            for (int p = tid; p < tot; p += CH_THREADS) {
-                int lo = 0, hi = nq;
-                while (lo < hi) {
-                    int mid = (lo + hi) >> 1;
-                    if (S.q.qoff[mid + 1] <= p) lo = mid + 1;
-                    else hi = mid;
+            // the atoms' tests first: a query in a van der Waals ball (flag
+            // 1) or in no SAS ball (no flag 2) is decided by them, and the
+            // surfaces' tests run only for the others
+            for (int phase = 0; phase < 2; ++phase) {
+                int kq = 0;
+                if (tid < nq) {
+                    const int e = S.q.qe[tid];
+                    int ka = 0;
+                    for (int w = 0; w < CH_ATOMS / 64; ++w) ka += __popcll(S.amask[e][w]);
+                    if (phase == 0) {
+                        kq = ka;
+                        S.q.qflag[tid] = 0;
+                    } else if (S.q.qflag[tid] == 2) {
+                        for (int w = 0; w < CH_SURF / 64; ++w) kq += __popcll(S.smask[e][w]);
+                    }
+                    S.q.qskip[tid] = phase == 0 ? 0 : ka;
                 }
-                const int f = label_test<CNT>(m, S, S.q.qe[lo], p - S.q.qoff[lo], S.q.qu[lo], nF,
-                                              nV, cnt);
-                if (f) atomicOr(&S.q.qflag[lo], f);
+                int tot;
+                const int off = block_excl_scan<int, CH_THREADS>(kq, S.scan, &tot);
+                if (tid < nq) S.q.qoff[tid] = off;
+                if (tid == 0) S.q.qoff[nq] = tot;
+                __syncthreads();
+                for (int p = tid; p < tot; p += CH_THREADS) {
+                    int lo = 0, hi = nq;
+                    while (lo < hi) {
+                        int mid = (lo + hi) >> 1;
+                        if (S.q.qoff[mid + 1] <= p) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    const int f = label_test<CNT>(m, S, S.q.qe[lo],
+                                                  S.q.qskip[lo] + p - S.q.qoff[lo], S.q.qu[lo],
+                                                  nF, nV, cnt);
+                    if (f) atomicOr(&S.q.qflag[lo], f);
+                }
+                __syncthreads();
             }
-            __syncthreads();
             if (act) {
                 int k = q0;
                 ustar = walk_roots<false>(
