@@ -147,14 +147,16 @@ __device__ inline double horner(const double *c, int deg, double u) {
 }
 
 // Root of the polynomial c (degree deg) in [lo, hi] where its values at the
-// ends have opposite signs: Newton steps kept inside a shrinking bracket,
-// bisection when a step leaves it.
+// ends (flo, fhi) have opposite signs: from the secant point of the ends,
+// Newton steps kept inside a shrinking bracket, bisection when a step leaves
+// it.
 template <bool CNT>
 __device__ double bracket_root(const double *c, int deg, double lo, double hi, double flo,
-                               unsigned long long *cnt) {
+                               double fhi, unsigned long long *cnt) {
     double d[4];
     for (int q = 1; q <= deg; ++q) d[q - 1] = q * c[q];
-    double x = 0.5 * (lo + hi);
+    double x = lo + (hi - lo) * (flo / (flo - fhi));
+    if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
     for (int it = 0; it < 128; ++it) {
         if (CNT) cnt[EC_HORNER_FLOPS] += 4 * deg + 4;  // f, f' and the step
         double f = horner(c, deg, x);
@@ -243,7 +245,7 @@ __device__ void quartic01(const double *g, Emit emit, unsigned long long *cnt) {
                     cp = a;
                     have = true;
                 } else if (fa != 0.0 && fb != 0.0 && ((fa < 0.0) != (fb < 0.0))) {
-                    cp = bracket_root<CNT>(d1, 3, a, b, fa, cnt);
+                    cp = bracket_root<CNT>(d1, 3, a, b, fa, fb, cnt);
                     have = true;
                 }
             }
@@ -253,7 +255,7 @@ __device__ void quartic01(const double *g, Emit emit, unsigned long long *cnt) {
         if (CNT) cnt[EC_HORNER_FLOPS] += 16;
         if (fb == 0.0) emit(cp);
         else if (fca != 0.0 && ((fca < 0.0) != (fb < 0.0)))
-            emit(bracket_root<CNT>(g, 4, ca, cp, fca, cnt));
+            emit(bracket_root<CNT>(g, 4, ca, cp, fca, fb, cnt));
         if (interior && fb != 0.0 && fabs(fb) <= tol) emit(cp);
         ca = cp;
         fca = fb;
@@ -381,6 +383,27 @@ __device__ inline bool surf_reaches_rel(int type, const SurfParams &p, double rh
     double dc2 = tm * tm + sq(bm - p.c.w);
     *rel = dc2 < sq(rho + half);
     return !(dc2 > sq(rho + half) || (rho > half && dc2 < sq(rho - half)));
+}
+
+// A staged sphere (van der Waals face or probe) keeps in n the squared
+// bounds of surf_reaches_rel for edges of half-length `half`: the outer
+// radius, the inner one (-1 when there is none) and the candidate's reach.
+__device__ inline SurfParams sphere_reach_bounds(SurfParams p, int type, double rho,
+                                                 double half) {
+    if (type == 2) return p;
+    const double r = p.c.w;
+    p.n = make_double4(sq(r + half), r > half ? sq(r - half) : -1.0,
+                       sq((type == 1 ? r + 2.0 * rho : rho) + half), 0.0);
+    return p;
+}
+
+// surf_reaches_rel on a staged surface (spheres with their bounds in n).
+__device__ inline bool staged_reaches_rel(int type, const SurfParams &p, double rho,
+                                          const double *mid, double half, bool *rel) {
+    if (type == 2) return surf_reaches_rel(type, p, rho, mid, half, rel);
+    const double dm2 = sq(mid[0] - p.c.x) + sq(mid[1] - p.c.y) + sq(mid[2] - p.c.z);
+    *rel = dm2 < p.n.z;
+    return !(dm2 > p.n.x || dm2 < p.n.y);
 }
 
 // Roots in [0, 1] of one surface along the edge x(u) = xs + u h e, each
@@ -647,6 +670,7 @@ struct ChunkLds {
     double4 atoms[CH_ATOMS];
     double4 cut[CH_CUTS];
     double xs[CH_EDGES][3];
+    double mid[CH_EDGES][3];  // edge midpoints
     union {
         // staging: the surfaces' first global cut, the offsets of their
         // (surface, cut) pairs and the cursors of their kept cuts
@@ -1022,9 +1046,13 @@ __device__ bool edge_cone_dead(const Mol &m, const ChunkLds &S, int si, int type
     for (int c = b; c < e; ++c) {
         const double4 v = cuts[c];
         if (CNT) ++cnt[EC_CONE];
+        // u . v over the cone is at most its value on the axis: a cut that
+        // passes the axis direction rejects no direction of the cone
+        const double av = ax * v.x + ay * v.y + az * v.z;
+        if (!(av > v.w)) continue;
         const double vn = sqrt(v.x * v.x + v.y * v.y + v.z * v.z);
         if (!(vn > 0.0)) continue;
-        const double cp = (ax * v.x + ay * v.y + az * v.z) / vn;
+        const double cp = av / vn;
         if (cp <= -ct) continue;  // the cone holds the direction opposite to v
         const double sp = sqrt(fmax(0.0, 1.0 - cp * cp));
         const double mn = vn * (cp * ct - sp * st);  // min of u . v over the cone
@@ -1050,10 +1078,12 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
         long long key = keys[q];
         EdgeGeom G = edge_geom(m, L, key);
         S.eq[tid] = q;
-        S.xs[tid][0] = G.xs[0];
-        S.xs[tid][1] = G.xs[1];
-        S.xs[tid][2] = G.xs[2];
-        S.einfo[tid] = (int)(key % 3) | (G.Ls << 2) | (G.Lt << 3);
+        const int axis = (int)(key % 3);
+        for (int a = 0; a < 3; ++a) {
+            S.xs[tid][a] = G.xs[a];
+            S.mid[tid][a] = G.xs[a] + (a == axis ? 0.5 * h : 0.0);
+        }
+        S.einfo[tid] = axis | (G.Ls << 2) | (G.Lt << 3);
         S.ecount[tid] = 0;
         for (int w = 0; w < CH_ATOMS / 64; ++w) S.amask[tid][w] = 0;
         for (int w = 0; w < CH_SURF / 64; ++w) S.smask[tid][w] = 0;
@@ -1105,7 +1135,7 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
             if (tid < ns) {
                 const int key = tile_surface_key(m, tile, sb + tid);
                 S.skey[tid] = key;
-                S.sp[tid] = surf_params(m, key);
+                S.sp[tid] = sphere_reach_bounds(surf_params(m, key), key >> 28, rho, half);
                 int cb, ce;
                 global_cuts(m, key, &cb, &ce);
                 S.st.ccb[tid] = cb;
@@ -1160,12 +1190,10 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
                 int ei, ai;
                 split(p, ai, ei);
                 const double4 a = S.atoms[ai];
-                const int axis = S.einfo[ei] & 3;
                 double dm2 = 0.0;
                 for (int c = 0; c < 3; ++c) {
-                    const double mc = S.xs[ei][c] + (c == axis ? 0.5 * h : 0.0);
                     const double ac = c == 0 ? a.x : c == 1 ? a.y : a.z;
-                    dm2 += sq(mc - ac);
+                    dm2 += sq(S.mid[ei][c] - ac);
                 }
                 if (dm2 < sq(a.w + rho + half)) atomicOr(&S.amask[ei][ai >> 6], 1ull << (ai & 63));
             }
@@ -1189,13 +1217,11 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
                     int ei, si;
                     split(p, si, ei);
                     const int type = S.skey[si] >> 28;
-                    double mid[3];
-                    const int axis = S.einfo[ei] & 3;
-                    for (int a = 0; a < 3; ++a)
-                        mid[a] = S.xs[ei][a] + (a == axis ? 0.5 * h : 0.0);
+                    const double mid[3] = {S.mid[ei][0], S.mid[ei][1], S.mid[ei][2]};
                     if (CNT) ++cnt[type == 2 ? EC_REACH_TORUS : EC_REACH_SPHERE];
                     bool rel = false, hit = false;
-                    if (!S.sdead[si]) hit = surf_reaches_rel(type, S.sp[si], rho, mid, half, &rel);
+                    if (!S.sdead[si])
+                        hit = staged_reaches_rel(type, S.sp[si], rho, mid, half, &rel);
                     // a circle whose candidate is inadmissible on the whole edge
                     // has no kept root there and fails every label test
                     if ((hit || rel) && type == 2 &&
