@@ -861,14 +861,33 @@ __global__ void k_feature_off_atom(Mol m, const int *ec_pos) {
 // One wavefront per tile.  The tile box spans grid points [T t, T t + T] on
 // each axis (one point past the tile, so the box also holds the far ends of
 // the edges the tile owns).  Candidates are gathered from the cells that
-// overlap the box grown by s_max + rho and compacted with ballots.
+// overlap the box grown by s_max + rho: the cells of one (y, z) row are
+// consecutive, and so are their atoms and features, so each row is one range
+// per kind.  Lane r reads row r's ranges; the rows' candidates are then
+// taken 64 at a time across the lanes (row-major, ascending within a row)
+// and compacted with ballots.
 constexpr int TILE_WAVES = 4;
+
+// Row of candidate t: the first row whose inclusive end exceeds t.
+__device__ inline int tile_row(const int *incl, int nrow, int t) {
+    int lo = 0, hi = nrow - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (incl[mid] <= t) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
 
 template <bool FILL>
 __global__ void __launch_bounds__(TILE_WAVES *WAVE) k_tiles(Mol m, int *cntA, int *cntF,
                                                              int *cntC, int *cntV) {
-    int tile = blockIdx.x * TILE_WAVES + threadIdx.x / WAVE;
-    if (tile >= m.ntiles) return;
+    // per wavefront and kind (atoms, exposed circles, vertices): each row's
+    // first candidate and inclusive end offset
+    __shared__ int rbeg[TILE_WAVES][3][WAVE], rend[TILE_WAVES][3][WAVE];
+    const int wv = threadIdx.x / WAVE;
+    int tile = blockIdx.x * TILE_WAVES + wv;
+    if (tile >= m.ntiles) return;  // uniform across the wavefront (no block barriers)
     const int lane = lane_id();
     int t3[3] = {tile % m.tdims[0], (tile / m.tdims[0]) % m.tdims[1],
                  tile / (m.tdims[0] * m.tdims[1])};
@@ -885,70 +904,99 @@ __global__ void __launch_bounds__(TILE_WAVES *WAVE) k_tiles(Mol m, int *cntA, in
     int oA = FILL ? m.tA_off[tile] : 0, oF = FILL ? m.tF_off[tile] : 0;
     int oC = FILL ? m.tC_off[tile] : 0, oV = FILL ? m.tV_off[tile] : 0;
     const double rho = m.rho;
-    // cells of one (y, z) row are consecutive, and so are their atoms and
-    // features: one range per row
-    for (int z = c0[2]; z <= c1[2]; ++z)
-        for (int y = c0[1]; y <= c1[1]; ++y) {
-                int crow = m.nc[0] * (y + m.nc[1] * z);
-                int ab = m.cell_start[crow + c0[0]], ae = m.cell_start[crow + c1[0] + 1];
-                for (int base = ab; base < ae; base += WAVE) {
-                    int i = base + lane;
-                    bool inA = false, inF = false;
-                    if (i < ae) {
-                        double4 a = m.atom[i];
-                        double s = a.w + rho;
-                        double d2 = box_dist2(blo, bhi, a.x, a.y, a.z);
-                        inA = d2 < sq(s + LIST_SLACK);
-                        inF = (m.aflag[i] & AF_FACE) && d2 < sq(s + rho + LIST_SLACK);
-                    }
-                    unsigned long long bA = __ballot(inA), bF = __ballot(inF);
-                    if (FILL) {
-                        int pa = oA + nA + mask_prefix(bA), pf = oF + nF + mask_prefix(bF);
-                        if (inA && fill_ok(m, pa, m.tA_off[tile + 1])) m.tA[pa] = i;
-                        if (inF && fill_ok(m, pf, m.tF_off[tile + 1])) m.tF[pf] = m.face_off_atom[i];
-                    }
-                    nA += __popcll(bA);
-                    nF += __popcll(bF);
-                }
-                int eb = m.ec_off_atom[ab], ee = m.ec_off_atom[ae];
-                for (int base = eb; base < ee; base += WAVE) {
-                    int e = base + lane;
-                    bool in = false;
-                    if (e < ee) {
-                        int ci = m.ec_circ[e];
-                        double4 oR = m.circ_oR[ci];
-                        double4 n = m.circ_n[ci];
-                        double d2 = box_dist2(blo, bhi, oR.x, oR.y, oR.z);
-                        // signed distance of the box from the circle's plane
-                        double tmin = 0.0, tmax = 0.0;
-                        double nv[3] = {n.x, n.y, n.z}, ov[3] = {oR.x, oR.y, oR.z};
-                        for (int a = 0; a < 3; ++a) {
-                            double u0 = nv[a] * (blo[a] - ov[a]), u1 = nv[a] * (bhi[a] - ov[a]);
-                            tmin += fmin(u0, u1);
-                            tmax += fmax(u0, u1);
-                        }
-                        in = d2 < sq(oR.w + rho + LIST_SLACK) && tmin < rho + LIST_SLACK &&
-                             tmax > -rho - LIST_SLACK;
-                    }
-                    unsigned long long bC = __ballot(in);
-                    int pc = oC + nC + mask_prefix(bC);
-                    if (FILL && in && fill_ok(m, pc, m.tC_off[tile + 1])) m.tC[pc] = e;
-                    nC += __popcll(bC);
-                }
-                int vb = m.vert_off_atom[ab], ve = m.vert_off_atom[ae];
-                for (int base = vb; base < ve; base += WAVE) {
-                    int v = base + lane;
-                    bool in = false;
-                    if (v < ve) {
-                        double4 p = m.vert_p[v];
-                        in = box_dist2(blo, bhi, p.x, p.y, p.z) < sq(rho + LIST_SLACK);
-                    }
-                    unsigned long long bV = __ballot(in);
-                    int pv = oV + nV + mask_prefix(bV);
-                    if (FILL && in && fill_ok(m, pv, m.tV_off[tile + 1])) m.tV[pv] = v;
-                    nV += __popcll(bV);
-                }
+    const int ny = c1[1] - c0[1] + 1, nrows = ny * (c1[2] - c0[2] + 1);
+    int *ab = rbeg[wv][0], *eb = rbeg[wv][1], *vb = rbeg[wv][2];
+    int *ai = rend[wv][0], *ei = rend[wv][1], *vi = rend[wv][2];
+    for (int r0 = 0; r0 < nrows; r0 += WAVE) {
+        const int nr = min(WAVE, nrows - r0);
+        int a0 = 0, a1 = 0, e0 = 0, e1 = 0, v0 = 0, v1 = 0;
+        if (lane < nr) {
+            const int r = r0 + lane;
+            const int crow = m.nc[0] * (c0[1] + r % ny + m.nc[1] * (c0[2] + r / ny));
+            a0 = m.cell_start[crow + c0[0]];
+            a1 = m.cell_start[crow + c1[0] + 1];
+            e0 = m.ec_off_atom[a0];
+            e1 = m.ec_off_atom[a1];
+            v0 = m.vert_off_atom[a0];
+            v1 = m.vert_off_atom[a1];
+        }
+        const int ia = wave_incl_scan(a1 - a0), ie = wave_incl_scan(e1 - e0),
+                  iv = wave_incl_scan(v1 - v0);
+        ab[lane] = a0;
+        eb[lane] = e0;
+        vb[lane] = v0;
+        ai[lane] = ia;
+        ei[lane] = ie;
+        vi[lane] = iv;
+        wave_sync();
+        const int tA = __shfl(ia, WAVE - 1, WAVE), tE = __shfl(ie, WAVE - 1, WAVE),
+                  tV = __shfl(iv, WAVE - 1, WAVE);
+        for (int base = 0; base < tA; base += WAVE) {
+            const int t = base + lane;
+            bool inA = false, inF = false;
+            int i = 0;
+            if (t < tA) {
+                const int r = tile_row(ai, nr, t);
+                i = ab[r] + t - (r > 0 ? ai[r - 1] : 0);
+                double4 a = m.atom[i];
+                double s = a.w + rho;
+                double d2 = box_dist2(blo, bhi, a.x, a.y, a.z);
+                inA = d2 < sq(s + LIST_SLACK);
+                inF = (m.aflag[i] & AF_FACE) && d2 < sq(s + rho + LIST_SLACK);
             }
+            unsigned long long bA = __ballot(inA), bF = __ballot(inF);
+            if (FILL) {
+                int pa = oA + nA + mask_prefix(bA), pf = oF + nF + mask_prefix(bF);
+                if (inA && fill_ok(m, pa, m.tA_off[tile + 1])) m.tA[pa] = i;
+                if (inF && fill_ok(m, pf, m.tF_off[tile + 1])) m.tF[pf] = m.face_off_atom[i];
+            }
+            nA += __popcll(bA);
+            nF += __popcll(bF);
+        }
+        for (int base = 0; base < tE; base += WAVE) {
+            const int t = base + lane;
+            bool in = false;
+            int e = 0;
+            if (t < tE) {
+                const int r = tile_row(ei, nr, t);
+                e = eb[r] + t - (r > 0 ? ei[r - 1] : 0);
+                int ci = m.ec_circ[e];
+                double4 oR = m.circ_oR[ci];
+                double4 n = m.circ_n[ci];
+                double d2 = box_dist2(blo, bhi, oR.x, oR.y, oR.z);
+                // signed distance of the box from the circle's plane
+                double tmin = 0.0, tmax = 0.0;
+                double nv[3] = {n.x, n.y, n.z}, ov[3] = {oR.x, oR.y, oR.z};
+                for (int a = 0; a < 3; ++a) {
+                    double u0 = nv[a] * (blo[a] - ov[a]), u1 = nv[a] * (bhi[a] - ov[a]);
+                    tmin += fmin(u0, u1);
+                    tmax += fmax(u0, u1);
+                }
+                in = d2 < sq(oR.w + rho + LIST_SLACK) && tmin < rho + LIST_SLACK &&
+                     tmax > -rho - LIST_SLACK;
+            }
+            unsigned long long bC = __ballot(in);
+            int pc = oC + nC + mask_prefix(bC);
+            if (FILL && in && fill_ok(m, pc, m.tC_off[tile + 1])) m.tC[pc] = e;
+            nC += __popcll(bC);
+        }
+        for (int base = 0; base < tV; base += WAVE) {
+            const int t = base + lane;
+            bool in = false;
+            int v = 0;
+            if (t < tV) {
+                const int r = tile_row(vi, nr, t);
+                v = vb[r] + t - (r > 0 ? vi[r - 1] : 0);
+                double4 p = m.vert_p[v];
+                in = box_dist2(blo, bhi, p.x, p.y, p.z) < sq(rho + LIST_SLACK);
+            }
+            unsigned long long bV = __ballot(in);
+            int pv = oV + nV + mask_prefix(bV);
+            if (FILL && in && fill_ok(m, pv, m.tV_off[tile + 1])) m.tV[pv] = v;
+            nV += __popcll(bV);
+        }
+        wave_sync();  // the next batch of rows overwrites the offsets
+    }
     if (!FILL && lane == 0) {
         cntA[tile] = nA;
         cntF[tile] = nF;

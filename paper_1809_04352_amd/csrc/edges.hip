@@ -80,18 +80,61 @@ __device__ inline void point_next(int nx, int ny, int &i, int &j, int &k) {
     }
 }
 
+// The eight labels L[a .. a + 8) as the bytes of a word (a any index; reads
+// the two aligned words around it, so L must be 8-byte aligned and
+// a - a % 8 + 16 <= the grid size).
+__device__ inline unsigned long long label_word(const uint8_t *L, long long a) {
+    const long long b = a & ~7LL;
+    const int s = (int)(a - b) * 8;
+    const unsigned long long lo = *(const unsigned long long *)(L + b);
+    if (s == 0) return lo;
+    const unsigned long long hi = *(const unsigned long long *)(L + b + 8);
+    return (lo >> s) | (hi << (64 - s));
+}
+
+// Crossing-edge flags (bit a: the edge along axis a) of the EDGE_PPT points
+// from idx0 (a multiple of EDGE_PPT) at (i, j, k), into fl[].  Away from the
+// end of the grid and with L 8-byte aligned, the points' labels and those of
+// their +x, +y and +z neighbours are read as words and compared bytewise.
+__device__ inline void edge_flags8(const uint8_t *L, long long idx0, int i, int j, int k, int nx,
+                                   int ny, int nz, long long npts, bool words, int *fl) {
+    const long long nxy = (long long)nx * ny;
+    if (words && idx0 + nxy + 16 <= npts) {
+        // here every point has k + 1 < nz
+        const unsigned long long a = label_word(L, idx0);
+        const unsigned long long X = a ^ ((a >> 8) | ((unsigned long long)L[idx0 + 8] << 56));
+        const unsigned long long Y = a ^ label_word(L, idx0 + nx);
+        const unsigned long long Z = a ^ label_word(L, idx0 + nxy);
+#pragma unroll
+        for (int q = 0; q < EDGE_PPT; ++q) {
+            const int sh = 8 * q;
+            int f = ((Z >> sh) & 0xFF) ? 4 : 0;
+            if (i + 1 < nx && ((X >> sh) & 0xFF)) f |= 1;
+            if (j + 1 < ny && ((Y >> sh) & 0xFF)) f |= 2;
+            fl[q] = f;
+            point_next(nx, ny, i, j, k);
+        }
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < EDGE_PPT; ++q) {
+        fl[q] = idx0 + q < npts ? edge_flags(L, idx0 + q, i, j, k, nx, ny, nz) : 0;
+        point_next(nx, ny, i, j, k);
+    }
+}
+
 __global__ void __launch_bounds__(EDGE_BLOCK) k_edge_count(const uint8_t *L, int nx, int ny,
                                                            int nz, long long npts, int *bcount) {
     __shared__ int lds[EDGE_BLOCK / WAVE + 1];
     const long long idx0 = ((long long)blockIdx.x * EDGE_BLOCK + threadIdx.x) * EDGE_PPT;
+    const bool words = ((uintptr_t)L & 7) == 0;
     int c = 0;
     if (idx0 < npts) {
-        int i, j, k;
+        int i, j, k, fl[EDGE_PPT];
         point_ijk(idx0, nx, ny, i, j, k);
-        for (int q = 0; q < EDGE_PPT && idx0 + q < npts; ++q) {
-            c += __popc(edge_flags(L, idx0 + q, i, j, k, nx, ny, nz));
-            point_next(nx, ny, i, j, k);
-        }
+        edge_flags8(L, idx0, i, j, k, nx, ny, nz, npts, words, fl);
+#pragma unroll
+        for (int q = 0; q < EDGE_PPT; ++q) c += __popc(fl[q]);
     }
     int tot;
     block_excl_scan<int, EDGE_BLOCK>(c, lds, &tot);
@@ -106,20 +149,20 @@ __global__ void __launch_bounds__(EDGE_BLOCK) k_edge_write(const uint8_t *L, int
                                                            int tdx, int tdy) {
     __shared__ int lds[EDGE_BLOCK / WAVE + 1];
     const long long idx0 = ((long long)blockIdx.x * EDGE_BLOCK + threadIdx.x) * EDGE_PPT;
+    const bool words = ((uintptr_t)L & 7) == 0;
     int fl[EDGE_PPT], tl[EDGE_PPT];
     int c = 0;
-    int i = 0, j = 0, k = 0;
-    if (idx0 < npts) point_ijk(idx0, nx, ny, i, j, k);
+    for (int q = 0; q < EDGE_PPT; ++q) fl[q] = tl[q] = 0;
+    if (idx0 < npts) {
+        int i, j, k;
+        point_ijk(idx0, nx, ny, i, j, k);
+        edge_flags8(L, idx0, i, j, k, nx, ny, nz, npts, words, fl);
 #pragma unroll
-    for (int q = 0; q < EDGE_PPT; ++q) {
-        fl[q] = 0;
-        tl[q] = 0;
-        if (idx0 + q < npts) {
-            fl[q] = edge_flags(L, idx0 + q, i, j, k, nx, ny, nz);
+        for (int q = 0; q < EDGE_PPT; ++q) {
             if (fl[q]) tl[q] = i / T + tdx * (j / T + tdy * (k / T));
+            c += __popc(fl[q]);
             point_next(nx, ny, i, j, k);
         }
-        c += __popc(fl[q]);
     }
     int tot;
     long long w = boff[blockIdx.x] + block_excl_scan<int, EDGE_BLOCK>(c, lds, &tot);
@@ -318,12 +361,6 @@ __device__ inline void sort3(int &a, int &b, int &c) {
     if (a > b) { t = a; a = b; b = t; }
 }
 
-// Visibility of LDS writes of a wavefront to its other lanes.
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Surface parameters as staged: spheres (van der Waals face, probe) as
 // centre + radius; tori as circle centre + radius R and circle normal n.
@@ -879,6 +916,29 @@ __device__ inline void label_intervals(int n, RootAt root_at, Emit emit) {
     }
 }
 
+// Position of the j-th (from 0) set bit of x, j < popcount(x): halves
+// chosen by their popcounts.
+__device__ inline int nth_bit(unsigned long long x, int j) {
+    int pos = 0;
+    unsigned v = (unsigned)x;
+    const int c = __popc(v);
+    if (j >= c) {
+        j -= c;
+        v = (unsigned)(x >> 32);
+        pos = 32;
+    }
+#pragma unroll
+    for (int w = 16; w >= 1; w >>= 1) {
+        const int cw = __popc(v & ((1u << w) - 1u));
+        if (j >= cw) {
+            j -= cw;
+            v >>= w;
+            pos += w;
+        }
+    }
+    return pos;
+}
+
 // Test j of the label query at parameter um on edge e: the j-th atom or
 // surface of the edge's masks (atoms first).  Returns 1 if x lies in the
 // atom's van der Waals ball, 2 if in its SAS ball only, 4 if the surface's
@@ -900,8 +960,7 @@ __device__ int label_test(const Mol &m, const ChunkLds &S, int e, int j, double 
         if (j < c) break;
         j -= c;
     }
-    for (; j > 0; --j) bits &= bits - 1;
-    const int b = __builtin_ctzll(bits);
+    const int b = nth_bit(bits, j);
     if (w < CH_ATOMS / 64) {
         double4 a = S.atoms[w * 64 + b];
         double dx = x - a.x, dy = y - a.y, dz = z - a.z;

@@ -16,6 +16,13 @@ __device__ inline int mask_prefix(unsigned long long m) {
     return __popcll(m & ((1ull << lane_id()) - 1ull));
 }
 
+// Visibility of LDS writes of a wavefront to its other lanes.
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Inclusive prefix sum across a wavefront.
 template <typename T>
 __device__ inline T wave_incl_scan(T v) {
