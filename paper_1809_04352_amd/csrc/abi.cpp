@@ -472,7 +472,14 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, int 
     CKS(T.alloc(&vcnt, m.ncirc));
     CKS(T.alloc(&tmp2, scan_tmp_elems(m.ncirc) + 64));
     CKS(A.alloc(&m.vert_off, m.ncirc + 1));
-    CK(launch_vertex(m, false, vcnt, st));
+    // positions pooled by the count pass (placed after the scan when they fit)
+    VertexPool pool{};
+    pool.cap = std::max(4096, m.ncirc / 4);
+    CKS(T.alloc(&pool.p, pool.cap));
+    CKS(T.alloc(&pool.id, pool.cap));
+    CKS(T.alloc(&pool.count, 1));
+    CK(fill_i32(pool.count, 1, 0, st));
+    CK(launch_vertex(m, false, vcnt, pool, st));
     CK(launch_circle_free(m, st));
     CK(scan_i32(vcnt, m.ncirc, m.vert_off, tmp2, st));
     int *face_cnt, *ecf, *ec_pos;
@@ -486,11 +493,15 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, int 
     CK(scan_i32(face_cnt, m.n, m.face_off_atom, tmp, st));
     CK(launch_ec_flag(m, ecf, st));
     CK(scan_i32(ecf, m.ncirc, ec_pos, tmp2, st));
+    int npool = 0;
     CKS(d2h_ints({{&m.nvert, m.vert_off + m.ncirc}, {&m.nface, m.face_off_atom + m.n},
-                   {&m.nec, ec_pos + m.ncirc}}, st));
+                   {&m.nec, ec_pos + m.ncirc}, {&npool, pool.count}}, st));
     CKS(A.alloc(&m.vert_p, m.nvert));
     CKS(A.alloc(&m.vert_ijks, m.nvert));
-    CK(launch_vertex(m, true, vcnt, st));
+    pool.use = npool <= pool.cap ? 1 : 0;
+    if (pool.use) CK(launch_vertex_place(m, pool, npool, vcnt, st));
+    CK(launch_vertex(m, true, vcnt, pool, st));
+    if (pool.use) CK(launch_vertex_order(m, st));
     CKS(A.alloc(&m.ec_circ, m.nec));
     CK(launch_ec_ids(m, ec_pos, st));
 

@@ -610,7 +610,7 @@ __device__ void vertex_circle(const Mol &m, int c, int c0, int i, int nb, int ne
 // One workgroup per atom i, one wavefront per circle (i, j) of i; i's
 // neighbours (cover order) are staged in LDS for the exposure tests.
 template <bool FILL>
-__global__ void __launch_bounds__(VX_WAVES *WAVE) k_vertex(Mol m, int *vcnt) {
+__global__ void __launch_bounds__(VX_WAVES *WAVE) k_vertex(Mol m, int *vcnt, VertexPool pool) {
     __shared__ VxLds L;
     __shared__ int pj[VX_NBR], poff[VX_NBR + 1], vc[VX_NBR], scan_lds[VX_WAVES + 1];
     __shared__ uint32_t fl[VX_NBR];
@@ -620,6 +620,8 @@ __global__ void __launch_bounds__(VX_WAVES *WAVE) k_vertex(Mol m, int *vcnt) {
     if (FILL && m.vert_off[c0] == m.vert_off[c1]) return;  // no probe position on i's circles
     const int nb = m.nbr_off[i], ne = m.nbr_off[i + 1];
     const int nst = min(VX_NBR, ne - nb);
+    // the count pass pooled the positions of an atom whose lists fit in LDS
+    if (FILL && pool.use && c1 - c0 <= VX_NBR && ne - nb <= VX_NBR) return;
     for (int q = threadIdx.x; q < nst; q += VX_WAVES * WAVE) {
         const int l = m.nbr_cov[nb + q];
         const double4 al = m.atom[l];
@@ -680,8 +682,21 @@ __global__ void __launch_bounds__(VX_WAVES *WAVE) k_vertex(Mol m, int *vcnt) {
             double v0[3], v1[3];
             vertex_pair(m, act, L.coR[cc], L.cn[cc], j, k, L.natasc[p], L, nb, ne, nst, crossed,
                         v0, v1, ok0, ok1);
+            const int nx = act ? (ok0 ? 1 : 0) + (ok1 ? 1 : 0) : 0;
+            // the positions go to the pool (placed and ordered on their
+            // circle after the scan)
+            if (nx) {
+                const int w = atomicAdd(pool.count, nx), w1 = w + (ok0 ? 1 : 0);
+                if (ok0 && w < pool.cap) {
+                    pool.p[w] = make_double4(v0[0], v0[1], v0[2], 0.0);
+                    pool.id[w] = make_int4(c0 + cc, 0, k, 1);
+                }
+                if (ok1 && w1 < pool.cap) {
+                    pool.p[w1] = make_double4(v1[0], v1[1], v1[2], 0.0);
+                    pool.id[w1] = make_int4(c0 + cc, 0, k, -1);
+                }
+            }
             if (!act) continue;
-            const int nx = (ok0 ? 1 : 0) + (ok1 ? 1 : 0);
             if (nx) atomicAdd(&vc[cc], nx);
             const uint32_t f = (crossed ? CF_CROSSED : 0u) | (nx ? CF_EXPOSED_VERTEX : 0u);
             if (f) {
@@ -1087,12 +1102,61 @@ hipError_t launch_nbr_sort(const Mol &m, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_vertex(const Mol &m, bool fill, int *vcnt, hipStream_t st) {
+hipError_t launch_vertex(const Mol &m, bool fill, int *vcnt, const VertexPool &pool,
+                         hipStream_t st) {
     if (m.ncirc <= 0) return hipSuccess;
     if (fill)
-        hipLaunchKernelGGL(k_vertex<true>, dim3(m.n), dim3(VX_WAVES * WAVE), 0, st, m, vcnt);
+        hipLaunchKernelGGL(k_vertex<true>, dim3(m.n), dim3(VX_WAVES * WAVE), 0, st, m, vcnt, pool);
     else
-        hipLaunchKernelGGL(k_vertex<false>, dim3(m.n), dim3(VX_WAVES * WAVE), 0, st, m, vcnt);
+        hipLaunchKernelGGL(k_vertex<false>, dim3(m.n), dim3(VX_WAVES * WAVE), 0, st, m, vcnt,
+                           pool);
+    return hipGetLastError();
+}
+
+// Pooled probe positions into their circles' ranges (vcnt[c], the circle's
+// count, is consumed as a cursor), then every circle's range ordered as the
+// fill pass writes it: ascending k, "+" before "-".
+__global__ void k_vertex_place(Mol m, VertexPool pool, int n, int *vcnt) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int4 id = pool.id[q];
+    const int w = m.vert_off[id.x] + atomicSub(&vcnt[id.x], 1) - 1;
+    if (!fill_ok(m, w, m.vert_off[id.x + 1]) || w < m.vert_off[id.x]) return;
+    m.vert_p[w] = pool.p[q];
+    m.vert_ijks[w] = make_int4(m.circ_i[id.x], m.circ_j[id.x], id.z, id.w);
+}
+
+__global__ void k_vertex_order(Mol m) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= m.ncirc) return;
+    const int b = m.vert_off[c], e = m.vert_off[c + 1];
+    for (int a = b + 1; a < e; ++a) {
+        const double4 p = m.vert_p[a];
+        const int4 v = m.vert_ijks[a];
+        int q = a - 1;
+        while (q >= b) {
+            const int4 u = m.vert_ijks[q];
+            if (u.z < v.z || (u.z == v.z && u.w > v.w)) break;
+            m.vert_p[q + 1] = m.vert_p[q];
+            m.vert_ijks[q + 1] = u;
+            --q;
+        }
+        m.vert_p[q + 1] = p;
+        m.vert_ijks[q + 1] = v;
+    }
+}
+
+hipError_t launch_vertex_place(const Mol &m, const VertexPool &pool, int n, int *vcnt,
+                               hipStream_t st) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_vertex_place, dim3(blocks_for(n, 256)), dim3(256), 0, st, m, pool, n,
+                           vcnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_vertex_order(const Mol &m, hipStream_t st) {
+    if (m.ncirc <= 0 || m.nvert <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_vertex_order, dim3(blocks_for(m.ncirc, 256)), dim3(256), 0, st, m);
     return hipGetLastError();
 }
 

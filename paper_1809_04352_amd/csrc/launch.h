@@ -33,7 +33,24 @@ hipError_t launch_cell_scatter(const Mol &m, const int *cell_id, int *fill, int 
 hipError_t launch_cell_sort_gather(const Mol &m, int *slot_orig, hipStream_t st);
 hipError_t launch_nbr(const Mol &m, bool fill, int *nbr_cnt, int *circ_cnt, hipStream_t st);
 hipError_t launch_nbr_sort(const Mol &m, hipStream_t st);
-hipError_t launch_vertex(const Mol &m, bool fill, int *vcnt, hipStream_t st);
+// Probe positions found by the count pass of the atoms whose neighbours and
+// circles fit in LDS (p: x, y, z, -; id: circle, -, k, sign); count: one
+// int, zeroed before the count pass.  When count <= cap after it,
+// launch_vertex_place writes them (consuming the per-circle counts vcnt) and
+// the fill pass (use = 1) skips those atoms; launch_vertex_order then puts
+// every circle's positions in the fill pass's order.
+struct VertexPool {
+    double4 *p;
+    int4 *id;
+    int *count;
+    int cap;
+    int use;
+};
+hipError_t launch_vertex(const Mol &m, bool fill, int *vcnt, const VertexPool &pool,
+                         hipStream_t st);
+hipError_t launch_vertex_place(const Mol &m, const VertexPool &pool, int n, int *vcnt,
+                               hipStream_t st);
+hipError_t launch_vertex_order(const Mol &m, hipStream_t st);
 hipError_t launch_circle_free(const Mol &m, hipStream_t st);
 hipError_t launch_atom_features(const Mol &m, int *face_cnt, hipStream_t st);
 hipError_t launch_ec_flag(const Mol &m, int *ecf, hipStream_t st);
