@@ -701,6 +701,7 @@ constexpr int CH_SLOTS = 4;     // roots of one quartic before the admissibility
 constexpr int CH_ATOMS = 192;   // tile atoms staged for the labels
 constexpr int CH_CUTS = 384;    // cut planes of the staged surfaces
 constexpr int CH_Q = 256;       // label queries of a chunk evaluated together
+constexpr int CH_TILE_UNITS = 3;  // tiles per block for whole-tile units
 
 struct ChunkLds {
     SurfParams sp[CH_SURF];
@@ -1506,7 +1507,8 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
 // one tile (each tile's segment is padded to a multiple of CH_EDGES).  The
 // grid is persistent: blocks take the units (tiles with edges, the ones with
 // most chunks first) from one counter, and a block runs every chunk of its
-// tile in a row, staging the tile once.
+// tile in a row, staging the tile once; when the tiles are fewer than the
+// blocks, each chunk is a unit of its own.
 template <bool CNT>
 __global__ void __launch_bounds__(CH_THREADS) __attribute__((amdgpu_waves_per_eu(3)))
     k_edge_chunks(Mol m, const uint8_t *L, const long long *keys, const int *order,
@@ -1517,19 +1519,33 @@ __global__ void __launch_bounds__(CH_THREADS) __attribute__((amdgpu_waves_per_eu
     __shared__ int next;
     unsigned long long cnt[CNT ? EC_COUNT + 1 : 1];
     for (int c = 0; c < (CNT ? (int)EC_COUNT + 1 : 1); ++c) cnt[c] = 0;
+    // with too few tiles to balance the blocks (fewer than CH_TILE_UNITS per
+    // block), the units are the chunks themselves, so that a tile's chunks
+    // run side by side
     const int nunits = units[EU_COUNT];
+    const bool per_chunk = nunits < CH_TILE_UNITS * (int)gridDim.x;
+    const int nq = per_chunk ? coff[m.ntiles] : nunits;
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(&units[EU_QUEUE], 1);
         __syncthreads();
         const int u = next;
         __syncthreads();
-        if (u >= nunits) break;
-        const int t = units[EU_LIST + u];
-        for (int c = coff[t]; c < coff[t + 1]; ++c) {
+        if (u >= nq) break;
+        int t, cb, ce;
+        if (per_chunk) {
+            cb = u;
+            ce = u + 1;
+            t = edge_tile(m, keys[order[u * CH_EDGES]]);
+        } else {
+            t = units[EU_LIST + u];
+            cb = coff[t];
+            ce = coff[t + 1];
+        }
+        for (int c = cb; c < ce; ++c) {
             const int g0 = c * CH_EDGES;
             const int n = min(CH_EDGES, tcount[t] - (c - coff[t]) * CH_EDGES);
             edge_chunk<CNT>(m, L, keys, order, g0, n, lam, nrm, ptype, patoms, fallback,
-                            nfallback, c != coff[t], S, cnt);
+                            nfallback, c != cb, S, cnt);
             __syncthreads();
         }
     }
@@ -1840,9 +1856,10 @@ static hipError_t edge_roots_impl(const Mol &m, const uint8_t *L, const long lon
     hipError_t e = fill_i32(nfallback, 1, 0, st);
     if (e == hipSuccess) e = fill_i32(units + EU_QUEUE, 1, 0, st);
     if (e != hipSuccess) return e;
-    // no more blocks than units (tiles with edges) or than fit on the device
-    const long long grid =
-        std::min<long long>(std::min<long long>(m.ntiles, count), edge_chunk_slots());
+    // no more blocks than chunks or than fit on the device
+    const long long chunks_max =
+        (count + CH_EDGES - 1) / CH_EDGES + std::min<long long>(m.ntiles, count);
+    const long long grid = std::min<long long>(chunks_max, edge_chunk_slots());
     if (work)
         hipLaunchKernelGGL(k_edge_chunks<true>, dim3((unsigned)grid), dim3(CH_THREADS), 0, st, m,
                            L, keys, order, tcount, coff, units, lam, nrm, ptype, patoms,
