@@ -1302,11 +1302,12 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
                 __syncthreads();
                 if (pb >= npairs || queued + CH_ROUND > CH_PAIRS) break;
             }
-            // one thread per queued pair: tori first, then spheres; pair j
-            // goes to wave j % 4, so that the costly tori spread over the SIMDs
+            // one thread per queued pair: tori first, then spheres, so that
+            // the costly quartics fill the first waves and few waves mix the
+            // two kinds
             const int nt = S.npair_t, nq = nt + S.npair_s;
             for (int j0 = 0; j0 < nq; j0 += CH_THREADS) {
-                const int j = j0 + spread(tid);
+                const int j = j0 + tid;
                 if (j >= nq) continue;
                 unsigned short v = j < nt ? S.pair[CH_PAIRS - 1 - j] : S.pair[j - nt];
                 const int ei = v & 63, si = v >> 6;
