@@ -505,7 +505,7 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, int 
     CKS(A.alloc(&m.ec_circ, m.nec));
     CK(launch_ec_ids(m, ec_pos, st));
 
-    // cut lists of exposed faces and circles (one synchronisation for both)
+    // cut lists of exposed faces and circles
     int *fcut_cnt, *eccut_cnt, *tmp3;
     CKS(A.alloc(&m.face_atom, m.nface));
     CKS(A.alloc(&m.face_cut_off, m.nface + 1));
@@ -517,14 +517,9 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, int 
     CK(scan_i32(fcut_cnt, m.nface, m.face_cut_off, tmp3, st));
     CK(launch_ec_cuts(m, false, eccut_cnt, st));
     CK(scan_i32(eccut_cnt, m.nec, m.ec_cut_off, tmp3, st));
-    int nfc = 0, nec_cut = 0;
-    CKS(d2h_ints({{&nfc, m.face_cut_off + m.nface}, {&nec_cut, m.ec_cut_off + m.nec}}, st));
-    CKS(A.alloc(&m.face_cut, nfc));
-    CK(launch_face_cuts(m, st));
-    CKS(A.alloc(&m.ec_cut, nec_cut));
-    CK(launch_ec_cuts(m, true, eccut_cnt, st));
 
-    // per-tile lists
+    // per-tile lists: the count pass needs no cut planes, so its totals come
+    // back with the cut totals in one synchronisation
     int *cA, *cF, *cC, *cV;
     CKS(T.alloc(&cA, m.ntiles));
     CKS(T.alloc(&cF, m.ntiles));
@@ -540,9 +535,14 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, int 
         int *outs[4] = {m.tA_off, m.tF_off, m.tC_off, m.tV_off};
         CK(scan_i32_multi(ins, m.ntiles, outs, 4, tmp, st));
     }
-    int tl[4];
-    CKS(d2h_ints({{&tl[0], m.tA_off + m.ntiles}, {&tl[1], m.tF_off + m.ntiles},
+    int nfc = 0, nec_cut = 0, tl[4];
+    CKS(d2h_ints({{&nfc, m.face_cut_off + m.nface}, {&nec_cut, m.ec_cut_off + m.nec},
+                   {&tl[0], m.tA_off + m.ntiles}, {&tl[1], m.tF_off + m.ntiles},
                    {&tl[2], m.tC_off + m.ntiles}, {&tl[3], m.tV_off + m.ntiles}}, st));
+    CKS(A.alloc(&m.face_cut, nfc));
+    CK(launch_face_cuts(m, st));
+    CKS(A.alloc(&m.ec_cut, nec_cut));
+    CK(launch_ec_cuts(m, true, eccut_cnt, st));
     CKS(A.alloc(&m.tA, tl[0]));
     CKS(A.alloc(&m.tF, tl[1]));
     CKS(A.alloc(&m.tC, tl[2]));

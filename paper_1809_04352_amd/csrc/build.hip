@@ -300,65 +300,89 @@ __device__ inline bool fill_ok(const Mol &m, long long at, long long end) {
 
 // ------------------------------------------------ SAS neighbours and circles
 
-// One wavefront per internal atom i; lanes take the atoms of each stencil
-// cell in turn and ballots compact the hits.  Stencil cells are visited in
-// increasing cell index and internal ids increase with the cell index, so
-// each neighbour list comes out ascending.
+// One wavefront per internal atom i; the atoms of the 3x3x3 stencil, row by
+// row, are spread over the lanes and ballots compact the hits.  Stencil
+// cells are visited in increasing cell index and internal ids increase with
+// the cell index, so each neighbour list comes out ascending.
 constexpr int NB_WAVES = 4;
 
 template <bool FILL>
 __global__ void __launch_bounds__(NB_WAVES *WAVE) k_nbr(Mol m, int *nbr_cnt, int *circ_cnt) {
-    int i = blockIdx.x * NB_WAVES + threadIdx.x / WAVE;
-    if (i >= m.n) return;  // uniform across the wavefront
+    // per wavefront: the first atom and inclusive end offset of each of the
+    // stencil's (y, z) cell rows (at most 9)
+    __shared__ int rbeg[NB_WAVES][9], rend[NB_WAVES][9];
+    const int wv = threadIdx.x / WAVE;
+    int i = blockIdx.x * NB_WAVES + wv;
+    if (i >= m.n) return;  // uniform across the wavefront (no block barriers)
     const int lane = lane_id();
     double4 ai = m.atom[i];
     double si = ai.w + m.rho;
     int cx = cell_axis(m, ai.x, 0), cy = cell_axis(m, ai.y, 1), cz = cell_axis(m, ai.z, 2);
+    const int x0 = max(cx - 1, 0), x1 = min(cx + 1, m.nc[0] - 1);
+    const int y0 = max(cy - 1, 0), y1 = min(cy + 1, m.nc[1] - 1);
+    const int z0 = max(cz - 1, 0), z1 = min(cz + 1, m.nc[2] - 1);
+    const int ny = y1 - y0 + 1, nr = ny * (z1 - z0 + 1);
+    // the cells of one row are consecutive, and so are their atoms: lane r
+    // reads row r's range, then the rows' atoms are taken 64 at a time
+    // across the lanes (row-major, ascending within a row: ascending ids)
+    int kb = 0, ke = 0;
+    if (lane < nr) {
+        const int c = m.nc[0] * (y0 + lane % ny + m.nc[1] * (z0 + lane / ny));
+        kb = m.cell_start[c + x0];
+        ke = m.cell_start[c + x1 + 1];
+    }
+    const int incl = wave_incl_scan(ke - kb);
+    if (lane < nr) {
+        rbeg[wv][lane] = kb;
+        rend[wv][lane] = incl;
+    }
+    wave_sync();
+    const int total = __shfl(incl, WAVE - 1, WAVE);
     int nn = 0, nc = 0, nany = 0;
     bool contained = false;
     int wn = FILL ? m.nbr_off[i] : 0, en = FILL ? m.nbr_off[i + 1] : 0;
     int wc = FILL ? m.circ_off[i] : 0, ecc = FILL ? m.circ_off[i + 1] : 0;
-    for (int z = max(cz - 1, 0); z <= min(cz + 1, m.nc[2] - 1); ++z)
-        for (int y = max(cy - 1, 0); y <= min(cy + 1, m.nc[1] - 1); ++y)
-            for (int x = max(cx - 1, 0); x <= min(cx + 1, m.nc[0] - 1); ++x) {
-                int c = x + m.nc[0] * (y + m.nc[1] * z);
-                int kb = m.cell_start[c], ke = m.cell_start[c + 1];
-                for (int base = kb; base < ke; base += WAVE) {
-                    int k = base + lane;
-                    bool nb = false, circ = false, any = false;
-                    double4 oR = make_double4(0, 0, 0, 0), n = make_double4(0, 0, 0, 0);
-                    if (k < ke && k != i) {
-                        double4 ak = m.atom[k];
-                        double sk = ak.w + m.rho;
-                        double dx = ak.x - ai.x, dy = ak.y - ai.y, dz = ak.z - ai.z;
-                        double d2 = dx * dx + dy * dy + dz * dz;
-                        nb = d2 < sq(si + sk + LIST_SLACK);
-                        if (nb) {
-                            if (sqrt(d2) + si < sk) contained = true;
-                            if (pair_circle(ai, ak, m.rho, oR, n)) {
-                                any = true;
-                                circ = k > i;
-                            }
-                        }
-                    }
-                    unsigned long long bn = __ballot(nb), bc = __ballot(circ), ba = __ballot(any);
-                    if (FILL) {
-                        int pn = wn + nn + mask_prefix(bn);
-                        if (nb && fill_ok(m, pn, en)) m.nbr[pn] = k;
-                        int pc = wc + nc + mask_prefix(bc);
-                        if (circ && fill_ok(m, pc, ecc)) {
-                            m.circ_i[pc] = i;
-                            m.circ_j[pc] = k;
-                            m.circ_oR[pc] = oR;
-                            m.circ_n[pc] = n;
-                            m.cflag[pc] = 0u;
-                        }
-                    }
-                    nn += __popcll(bn);
-                    nc += __popcll(bc);
-                    nany += __popcll(ba);
+    for (int base = 0; base < total; base += WAVE) {
+        const int t = base + lane;
+        int k = -1;
+        if (t < total) {
+            int r = 0;
+            while (rend[wv][r] <= t) ++r;
+            k = rbeg[wv][r] + t - (r > 0 ? rend[wv][r - 1] : 0);
+        }
+        bool nb = false, circ = false, any = false;
+        double4 oR = make_double4(0, 0, 0, 0), n = make_double4(0, 0, 0, 0);
+        if (k >= 0 && k != i) {
+            double4 ak = m.atom[k];
+            double sk = ak.w + m.rho;
+            double dx = ak.x - ai.x, dy = ak.y - ai.y, dz = ak.z - ai.z;
+            double d2 = dx * dx + dy * dy + dz * dz;
+            nb = d2 < sq(si + sk + LIST_SLACK);
+            if (nb) {
+                if (sqrt(d2) + si < sk) contained = true;
+                if (pair_circle(ai, ak, m.rho, oR, n)) {
+                    any = true;
+                    circ = k > i;
                 }
             }
+        }
+        unsigned long long bn = __ballot(nb), bc = __ballot(circ), ba = __ballot(any);
+        if (FILL) {
+            int pn = wn + nn + mask_prefix(bn);
+            if (nb && fill_ok(m, pn, en)) m.nbr[pn] = k;
+            int pc = wc + nc + mask_prefix(bc);
+            if (circ && fill_ok(m, pc, ecc)) {
+                m.circ_i[pc] = i;
+                m.circ_j[pc] = k;
+                m.circ_oR[pc] = oR;
+                m.circ_n[pc] = n;
+                m.cflag[pc] = 0u;
+            }
+        }
+        nn += __popcll(bn);
+        nc += __popcll(bc);
+        nany += __popcll(ba);
+    }
     unsigned long long bcont = __ballot(contained);
     if (!FILL && lane == 0) {
         nbr_cnt[i] = nn;
