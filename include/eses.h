@@ -102,7 +102,11 @@ typedef struct {
                               one-wavefront-per-edge root kernel, the path
                               otherwise taken only by edges of a tile whose
                               root lists overflow (0 = off) */
-    int32_t reserved[4];   /* must be zero */
+    int32_t vertex_pool;   /* test aid: entries of the pool in which the
+                              probe-position count pass keeps what it finds
+                              (0 = default); when the pool overflows, the
+                              positions are recomputed by a fill pass */
+    int32_t reserved[3];   /* must be zero */
 } eses_config;
 
 typedef struct eses_candidates eses_candidates; /* opaque, library-owned */

@@ -342,7 +342,7 @@ eses_status d2h_ints(std::initializer_list<std::pair<int *, const int *>> items,
 
 // Stage 1 for one molecule.
 eses_status build_one(const eses_molecule *in, int tile, int force_recheck, int edge_fallback,
-                      MolState *S, hipStream_t st) {
+                      int vertex_pool, MolState *S, hipStream_t st) {
     Mol &m = S->m;
     Arena &A = S->arena;
     Arena &T = S->scratch;
@@ -474,7 +474,7 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, int 
     CKS(A.alloc(&m.vert_off, m.ncirc + 1));
     // positions pooled by the count pass (placed after the scan when they fit)
     VertexPool pool{};
-    pool.cap = std::max(4096, m.ncirc / 4);
+    pool.cap = vertex_pool > 0 ? vertex_pool : std::max(4096, m.ncirc / 4);
     CKS(T.alloc(&pool.p, pool.cap));
     CKS(T.alloc(&pool.id, pool.cap));
     CKS(T.alloc(&pool.count, 1));
@@ -793,16 +793,21 @@ eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
         set_err("need at least one molecule");
         return ESES_EINVAL;
     }
-    int tile = 8, force_recheck = 0, edge_fallback = 0;
+    int tile = 8, force_recheck = 0, edge_fallback = 0, vertex_pool = 0;
     if (cfg) {
         if (cfg->tile != 0) tile = cfg->tile;
         force_recheck = cfg->force_recheck;
         edge_fallback = cfg->edge_fallback;
+        vertex_pool = cfg->vertex_pool;
         if (cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64) {
             set_err("blocks_per_cu must be in [0, 64]");
             return ESES_EINVAL;
         }
-        for (int q = 0; q < 4; ++q)
+        if (vertex_pool < 0) {
+            set_err("vertex_pool must be >= 0");
+            return ESES_EINVAL;
+        }
+        for (int q = 0; q < 3; ++q)
             if (cfg->reserved[q] != 0) {
                 set_err("eses_config.reserved must be zero");
                 return ESES_EINVAL;
@@ -817,7 +822,8 @@ eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
     c->stream = st;
     for (int32_t q = 0; q < n_mols; ++q) c->mols.push_back(new MolState());
     if (n_mols == 1) {
-        eses_status s = build_one(&mols[0], tile, force_recheck, edge_fallback, c->mols[0], st);
+        eses_status s = build_one(&mols[0], tile, force_recheck, edge_fallback, vertex_pool, c->mols[0],
+                                  st);
         if (s != ESES_OK) {
             std::string msg = g_err;
             eses_free_candidates(c);
@@ -828,7 +834,8 @@ eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
         // molecules built concurrently on the worker streams; their workspace
         // then belongs to the caller's stream, which waits for the builds
         eses_status s = run_on_workers(n_mols, st, [&](int q, hipStream_t ws) {
-            return build_one(&mols[q], tile, force_recheck, edge_fallback, c->mols[q], ws);
+            return build_one(&mols[q], tile, force_recheck, edge_fallback, vertex_pool, c->mols[q],
+                             ws);
         });
         for (MolState *S : c->mols) S->arena.st = st;
         if (s != ESES_OK) {

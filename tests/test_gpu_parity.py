@@ -224,3 +224,22 @@ def test_workspace_cache_reuse_and_trim(E):
     c = E.surface(m.centres, m.radii, m.probe, m.spacing, m.lo, m.hi)
     for k in ("labels", "key", "lam", "normal", "patch_type", "atoms"):
         assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k]), k
+
+
+@pytest.mark.parametrize("pool", [1, 16])
+def test_vertex_pool_overflow(E, oracle_mod, pool):
+    """Probe positions recomputed by the fill pass when the count pass's pool
+    overflows (a pool of one or 16 entries) come out in the same order as
+    the pooled ones, with identical labels and records, and match the
+    oracle's positions."""
+    from eses_inputs import molecule
+    m = molecule(500, 1, 0.5)
+    a = E.surface(m.centres, m.radii, m.probe, m.spacing, m.lo, m.hi)
+    b = E.surface(m.centres, m.radii, m.probe, m.spacing, m.lo, m.hi, vertex_pool=pool)
+    assert a["info"]["n_vertices"] > pool
+    for q in range(3):
+        assert np.array_equal(a["vertices"][q], b["vertices"][q])
+    for k in ("labels", "key", "lam", "normal", "patch_type", "atoms"):
+        assert np.array_equal(a[k], b[k]), k
+    o = oracle_mod.Oracle(m.centres, m.radii, m.probe)
+    assert compare_vertices(b["vertices"], o) > 10
