@@ -196,7 +196,10 @@ eses_status eses_classify(eses_candidates *c, eses_precision prec, uint8_t *cons
  * the number of crossing edges per molecule; records beyond a molecule's
  * capacity are dropped and ESES_ECAPACITY is returned.  ESES_EINTERNAL if a
  * candidate list of the build met more entries than it had counted, or an
- * edge has more roots than the per-edge lists hold.  Synchronises. */
+ * edge has more roots than the per-edge lists hold.  For a handle of several
+ * molecules, each molecule's crossing edges are found and grouped on worker
+ * streams and the roots of all molecules run in one persistent fused launch
+ * (molecules with most crossing edges first).  Synchronises. */
 eses_status eses_edge_intersections(eses_candidates *c, const uint8_t *const *labels,
                                     const eses_isect_soa *out, int64_t *counts, void *stream);
 
@@ -223,12 +226,15 @@ eses_status eses_edge_work(eses_candidates *c, const uint8_t *const *labels,
 /* Kernel timing for diagnostics.  While enabled (process-wide), the library
  * records HIP events on the caller's stream around its classification kernel
  * and its edge kernels; eses_get_kernel_times returns the last durations of a
- * handle (waiting for the events).  Times of several molecules are summed. */
+ * handle (waiting for the events).  For a handle of several molecules the
+ * spans are those of the batched forms: the fused classification launch, the
+ * molecules' crossing-edge passes and grouping (worker streams, from the
+ * first start to the last end) and the fused root launch. */
 typedef struct {
     double classify_ms;       /* classification launch of the last eses_classify */
     double edge_detect_ms;    /* crossing-edge pass and grouping of the last
                                  eses_edge_intersections */
-    double edge_roots_ms;     /* root kernel of the last eses_edge_intersections */
+    double edge_roots_ms;     /* root kernels of the last eses_edge_intersections */
 } eses_kernel_times;
 
 void eses_set_timing(int enable);

@@ -78,14 +78,21 @@ int size_class(size_t bytes) {
 }
 
 // Device workspace of one molecule: every buffer taken on the stream and
-// returned to the cache together.
+// returned to the cache together.  `key` names the stream whose cache the
+// blocks come from and return to (st unless `keyed`): a batch builds on worker
+// streams that wait for the caller's stream, so they may take blocks from its
+// cache, and the blocks go back there when the handle is freed.
 struct Arena {
     struct Block {
         void *p;
         int dev, cls;
     };
     std::vector<Block> blocks;
-    hipStream_t st = nullptr;
+    hipStream_t st = nullptr;   // stream the blocks are used on (new blocks allocated on it)
+    hipStream_t key = nullptr;  // cache of the blocks when `keyed` (the null stream is a
+    bool keyed = false;         // stream like any other), else st's
+
+    hipStream_t cache() const { return keyed ? key : st; }
 
     template <typename T>
     eses_status alloc(T **p, long long count) {
@@ -97,7 +104,7 @@ struct Arena {
         {
             BlockCache &bc = block_cache();
             std::lock_guard<std::mutex> lock(bc.mu);
-            auto it = bc.free.find(std::make_tuple(dev, st, cls));
+            auto it = bc.free.find(std::make_tuple(dev, cache(), cls));
             if (it != bc.free.end() && !it->second.empty()) {
                 q = it->second.back();
                 it->second.pop_back();
@@ -121,7 +128,8 @@ struct Arena {
         if (blocks.empty()) return;
         BlockCache &bc = block_cache();
         std::lock_guard<std::mutex> lock(bc.mu);
-        for (const Block &b : blocks) bc.free[std::make_tuple(b.dev, st, b.cls)].push_back(b.p);
+        for (const Block &b : blocks)
+            bc.free[std::make_tuple(b.dev, cache(), b.cls)].push_back(b.p);
         blocks.clear();
     }
 };
@@ -341,12 +349,16 @@ eses_status d2h_ints(std::initializer_list<std::pair<int *, const int *>> items,
 }
 
 // Stage 1 for one molecule.
+// The handle's buffers come from (and return to) the cache of `home`, the
+// caller's stream, which `st` follows; build-time temporaries stay with `st`.
 eses_status build_one(const eses_molecule *in, int tile, int force_recheck, int edge_fallback,
-                      int vertex_pool, MolState *S, hipStream_t st) {
+                      int vertex_pool, MolState *S, hipStream_t st, hipStream_t home) {
     Mol &m = S->m;
     Arena &A = S->arena;
     Arena &T = S->scratch;
     A.st = st;
+    A.key = home;
+    A.keyed = true;
     T.st = st;
     if (!in->centers || !in->radii) {
         set_err("centers and radii must be device pointers");
@@ -435,7 +447,7 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, int 
     CK(fill_i32(cnt, m.ncell + 1, 0, st));
     CK(launch_cell_count(m, cell_id, cnt, st));
     CK(scan_i32(cnt, m.ncell, m.cell_start, tmp, st));
-    CK(hipMemcpyAsync(fillb, m.cell_start, sizeof(int) * (m.ncell + 1), hipMemcpyDeviceToDevice, st));
+    CK(copy_i32(fillb, m.cell_start, m.ncell + 1, st));
     CK(launch_cell_scatter(m, cell_id, fillb, slot, st));
     CK(launch_cell_sort_gather(m, slot, st));
 
@@ -645,42 +657,47 @@ eses_status classify_batch(eses_candidates *c, bool fp32, uint8_t *const *labels
 // Stage 3 for molecule q on stream st: crossing edges, grouping, roots.
 // counts[q] receives the number of crossing edges.  With `timed` the
 // handle's events bracket the kernels and their times are added up.
-eses_status edges_one(eses_candidates *c, size_t q, const uint8_t *lab, const eses_isect_soa &o,
-                      int64_t *counts, hipStream_t st, bool timed) {
-    const Mol &m = c->mols[q]->m;
+// Molecule q's crossing edges found, keyed into the output and grouped by
+// tile (the root kernels' input, in P.job; its workspace stays in P.T until
+// released).  With `timed`, HIP events bracket the detection and grouping.
+struct EdgePrep {
     Arena T;
+    EdgeJob job{};
+    long long total = 0, nw = 0;
+    int *ovf = nullptr;
+};
+
+eses_status edges_prepare(eses_candidates *c, size_t q, const uint8_t *lab,
+                          const eses_isect_soa &o, EdgePrep &P, hipStream_t st, bool timed,
+                          bool batch) {
+    const Mol &m = c->mols[q]->m;
+    Arena &T = P.T;
     T.st = st;
     long long nb = edge_detect_blocks(m);
     int *bcount;
     long long *boff, *tmp;
-    int *ovf;
     eses_status s;
     if ((s = T.alloc(&bcount, nb + 1)) != ESES_OK || (s = T.alloc(&boff, nb + 2)) != ESES_OK ||
         (s = T.alloc(&tmp, scan_tmp_elems(nb) + 64)) != ESES_OK ||
-        (s = T.alloc(&ovf, 1)) != ESES_OK) {
-        T.release();
+        (s = T.alloc(&P.ovf, 1)) != ESES_OK)
         return s;
-    }
     long long nblk = 0;
     hipError_t e = timed ? hipEventRecord(c->ev[2], st) : hipSuccess;
     if (e == hipSuccess) e = launch_edge_detect_count(lab, m, bcount, &nblk, st);
     if (e == hipSuccess) e = scan_i64(bcount, nblk, boff, tmp, st);
-    long long total = 0;
     long long fill_overflow = 0;
     if (e == hipSuccess) {
         eses_status rs =
-            read_scalars({{boff + nblk, true, &total}, {m.diag, false, &fill_overflow}}, st);
+            read_scalars({{boff + nblk, true, &P.total}, {m.diag, false, &fill_overflow}}, st);
         if (rs == ESES_OK && fill_overflow != 0) {
             set_err("internal: %lld candidate list entries beyond their counted range",
                     fill_overflow);
             rs = ESES_EINTERNAL;
         }
-        if (rs != ESES_OK) {
-            T.release();
-            return rs;
-        }
+        if (rs != ESES_OK) return rs;
     }
-    long long nw = std::min<long long>(total, o.capacity);
+    const long long nw = P.nw = std::min<long long>(P.total, o.capacity);
+    EdgeJob &J = P.job;
     int *tcount = nullptr, *ccount = nullptr, *coff = nullptr, *tfill = nullptr,
         *order = nullptr, *units = nullptr, *ttmp = nullptr, *fb = nullptr, *nfb = nullptr;
     if (e == hipSuccess && nw > 0) {
@@ -691,28 +708,58 @@ eses_status edges_one(eses_candidates *c, size_t q, const uint8_t *lab, const es
             (s = T.alloc(&order, edge_order_capacity(m, nw))) != ESES_OK ||
             (s = T.alloc(&units, edge_units_capacity(m))) != ESES_OK ||
             (s = T.alloc(&fb, nw)) != ESES_OK || (s = T.alloc(&nfb, 1)) != ESES_OK ||
-            (s = T.alloc(&ttmp, scan_tmp_elems(m.ntiles) + 64)) != ESES_OK) {
-            T.release();
+            (s = T.alloc(&ttmp, scan_tmp_elems(m.ntiles) + 64)) != ESES_OK)
             return s;
-        }
     }
     if (e == hipSuccess && nw > 0)
         e = launch_edge_detect_write(lab, m, boff, o.capacity, (long long *)o.key, tcount, st);
-    if (e == hipSuccess) e = fill_i32(ovf, 1, 0, st);
+    if (e == hipSuccess) e = fill_i32(P.ovf, 1, 0, st);
+    if (e == hipSuccess && nw > 0 && batch) e = fill_i32(nfb, 1, 0, st);  // fused launch
     if (e == hipSuccess && nw > 0)
         e = launch_edge_group(m, (const long long *)o.key, nw, tcount, ccount, coff, tfill,
                               order, units, ttmp, st);
     if (e == hipSuccess && timed) e = hipEventRecord(c->ev[3], st);
-    if (e == hipSuccess && timed) e = hipEventRecord(c->ev[4], st);
-    if (e == hipSuccess && nw > 0)
-        e = launch_edge_roots(m, lab, (const long long *)o.key, nw, order, tcount, coff, units,
-                              o.lambda, o.normal, o.patch_type, o.atoms, fb, nfb, ovf, st);
+    if (e != hipSuccess) {
+        set_err("edge intersections: %s", hipGetErrorString(e));
+        return ESES_EDEVICE;
+    }
+    J.L = lab;
+    J.keys = (const long long *)o.key;
+    J.order = order;
+    J.tcount = tcount;
+    J.coff = coff;
+    J.units = units;
+    J.lam = o.lambda;
+    J.nrm = o.normal;
+    J.ptype = o.patch_type;
+    J.patoms = o.atoms;
+    J.fallback = fb;
+    J.nfallback = nfb;
+    J.mol = (int)q;
+    return ESES_OK;
+}
+
+eses_status edges_one(eses_candidates *c, size_t q, const uint8_t *lab, const eses_isect_soa &o,
+                      int64_t *counts, hipStream_t st, bool timed) {
+    const Mol &m = c->mols[q]->m;
+    EdgePrep P;
+    eses_status s = edges_prepare(c, q, lab, o, P, st, timed, false);
+    if (s != ESES_OK) {
+        P.T.release();
+        return s;
+    }
+    const EdgeJob &J = P.job;
+    hipError_t e = timed ? hipEventRecord(c->ev[4], st) : hipSuccess;
+    if (e == hipSuccess && P.nw > 0)
+        e = launch_edge_roots(m, lab, J.keys, P.nw, J.order, J.tcount, J.coff, (int *)J.units,
+                              J.lam, J.nrm, J.ptype, J.patoms, J.fallback, J.nfallback, P.ovf,
+                              st);
     if (e == hipSuccess && timed) e = hipEventRecord(c->ev[5], st);
     long long hovf = 0;
     if (e == hipSuccess) {
-        eses_status rs = read_scalars({{ovf, false, &hovf}}, st);
+        eses_status rs = read_scalars({{P.ovf, false, &hovf}}, st);
         if (rs != ESES_OK) {
-            T.release();
+            P.T.release();
             return rs;
         }
     }
@@ -723,7 +770,7 @@ eses_status edges_one(eses_candidates *c, size_t q, const uint8_t *lab, const es
         c->detect_ms += a;
         c->roots_ms += b;
     }
-    T.release();
+    P.T.release();
     if (e != hipSuccess) {
         set_err("edge intersections: %s", hipGetErrorString(e));
         return ESES_EDEVICE;
@@ -732,7 +779,84 @@ eses_status edges_one(eses_candidates *c, size_t q, const uint8_t *lab, const es
         set_err("more roots on one edge than the per-edge list holds");
         return ESES_EINTERNAL;
     }
-    counts[q] = total;
+    counts[q] = P.total;
+    return ESES_OK;
+}
+
+// A batch: every molecule's crossing edges found and grouped on the worker
+// streams, then all their tiles in one fused root launch on `st` (molecules
+// with most crossing edges first) and one read-back.
+eses_status edges_batch(eses_candidates *c, const uint8_t *const *labels,
+                        const eses_isect_soa *out, int64_t *counts, hipStream_t st,
+                        bool timed) {
+    const int nm = (int)c->mols.size();
+    std::vector<EdgePrep> prep(nm);
+    auto release_all = [&]() {
+        for (EdgePrep &P : prep) P.T.release();
+    };
+    // with `timed`, events on `st` bracket the per-molecule detection and
+    // grouping (worker streams) and the fused root launch
+    if (timed) CK(hipEventRecord(c->ev[2], st));
+    eses_status s = run_on_workers(nm, st, [&](int q, hipStream_t ws) {
+        return edges_prepare(c, q, labels[q], out[q], prep[q], ws, false, true);
+    });
+    if (s == ESES_OK && timed && hipEventRecord(c->ev[3], st) != hipSuccess) s = ESES_EDEVICE;
+    if (s != ESES_OK) {
+        // the prepared workspace may still be in use on the worker streams
+        (void)hipStreamSynchronize(st);
+        release_all();
+        return s;
+    }
+    std::vector<int> ord;
+    for (int q = 0; q < nm; ++q)
+        if (prep[q].nw > 0) ord.push_back(q);
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int a, int b) { return prep[a].nw > prep[b].nw; });
+    std::vector<EdgeJob> jobs;
+    for (int q : ord) jobs.push_back(prep[q].job);
+    const int nj = (int)jobs.size();
+    Arena B;
+    B.st = st;
+    EdgeJob *jobs_dev = nullptr;
+    int *prefix = nullptr, *ctl = nullptr;
+    long long hovf = 0;
+    if ((s = B.alloc(&jobs_dev, nj)) != ESES_OK || (s = B.alloc(&prefix, nj + 1)) != ESES_OK ||
+        (s = B.alloc(&ctl, 2)) != ESES_OK) {
+        (void)hipStreamSynchronize(st);
+        B.release();
+        release_all();
+        return s;
+    }
+    hipError_t e = hipSuccess;
+    if (nj > 0)
+        e = hipMemcpyAsync(jobs_dev, jobs.data(), sizeof(EdgeJob) * nj, hipMemcpyHostToDevice,
+                           st);
+    if (e == hipSuccess) e = fill_i32(ctl, 2, 0, st);
+    if (e == hipSuccess && timed) e = hipEventRecord(c->ev[4], st);
+    if (e == hipSuccess)
+        e = launch_edge_roots_batch(c->mols_dev, jobs_dev, nj, prefix, ctl, ctl + 1, st);
+    if (e == hipSuccess && timed) e = hipEventRecord(c->ev[5], st);
+    if (e == hipSuccess) s = read_scalars({{ctl + 1, false, &hovf}}, st);
+    else (void)hipStreamSynchronize(st);
+    if (e == hipSuccess && s == ESES_OK && timed) {
+        float a = 0.0f, b = 0.0f;
+        e = hipEventElapsedTime(&a, c->ev[2], c->ev[3]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&b, c->ev[4], c->ev[5]);
+        c->detect_ms += a;
+        c->roots_ms += b;
+    }
+    B.release();
+    release_all();
+    if (e != hipSuccess) {
+        set_err("edge intersections: %s", hipGetErrorString(e));
+        return ESES_EDEVICE;
+    }
+    if (s != ESES_OK) return s;
+    if (hovf) {
+        set_err("more roots on one edge than the per-edge list holds");
+        return ESES_EINTERNAL;
+    }
+    for (int q = 0; q < nm; ++q) counts[q] = prep[q].total;
     return ESES_OK;
 }
 
@@ -823,7 +947,7 @@ eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
     for (int32_t q = 0; q < n_mols; ++q) c->mols.push_back(new MolState());
     if (n_mols == 1) {
         eses_status s = build_one(&mols[0], tile, force_recheck, edge_fallback, vertex_pool, c->mols[0],
-                                  st);
+                                  st, st);
         if (s != ESES_OK) {
             std::string msg = g_err;
             eses_free_candidates(c);
@@ -835,9 +959,9 @@ eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
         // then belongs to the caller's stream, which waits for the builds
         eses_status s = run_on_workers(n_mols, st, [&](int q, hipStream_t ws) {
             return build_one(&mols[q], tile, force_recheck, edge_fallback, vertex_pool, c->mols[q],
-                             ws);
+                             ws, st);
         });
-        for (MolState *S : c->mols) S->arena.st = st;
+        for (MolState *S : c->mols) S->arena.st = st;  // later uses follow the caller's stream
         if (s != ESES_OK) {
             std::string msg = g_err;
             eses_free_candidates(c);
@@ -978,20 +1102,14 @@ eses_status eses_edge_intersections(eses_candidates *c, const uint8_t *const *la
             return ESES_EINVAL;
         }
     }
-    if (nm == 1 || timed) {
-        // one molecule, or kernel timing (events of one stream): in order on `st`
-        for (int q = 0; q < nm; ++q) {
-            eses_status s = edges_one(c, q, labels[q], out[q], counts, st, timed);
-            if (s != ESES_OK) {
-                g_err = "molecule " + std::to_string(q) + ": " + g_err;
-                return s;
-            }
+    if (nm == 1) {
+        eses_status s = edges_one(c, 0, labels[0], out[0], counts, st, timed);
+        if (s != ESES_OK) {
+            g_err = "molecule 0: " + g_err;
+            return s;
         }
     } else {
-        // molecules concurrently on the worker streams
-        CKS(run_on_workers(nm, st, [&](int q, hipStream_t ws) {
-            return edges_one(c, q, labels[q], out[q], counts, ws, false);
-        }));
+        CKS(edges_batch(c, labels, out, counts, st, timed));
     }
     for (int q = 0; q < nm; ++q)
         if (counts[q] > out[q].capacity) {

@@ -11,6 +11,12 @@ namespace eses {
 
 __global__ void k_fill_i32(int *p, long long n, int v) { fill_i32(p, n, v); }
 
+__global__ void k_copy_i32(int *dst, const int *src, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 // Scalars the host reads back, gathered into host memory by one thread.
 __global__ void k_collect(ReadBack rb, long long *host) {
     for (int q = 0; q < rb.n; ++q)
@@ -174,6 +180,14 @@ hipError_t fill_i32(int *p, long long n, int v, hipStream_t st) {
     if (nb > 4096) nb = 4096;
     if (nb < 1) nb = 1;
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)nb), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t copy_i32(int *dst, const int *src, long long n, hipStream_t st) {
+    long long nb = (n + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_copy_i32, dim3((unsigned)nb), dim3(256), 0, st, dst, src, n);
     return hipGetLastError();
 }
 

@@ -1555,6 +1555,58 @@ __global__ void __launch_bounds__(CH_THREADS) __attribute__((amdgpu_waves_per_eu
             if (cnt[c]) atomicAdd(&work[c], cnt[c]);
 }
 
+// ------------------------------------------------ roots of a batch, one launch
+
+// Global unit offsets of the jobs' unit lists (one block).
+__global__ void __launch_bounds__(256) k_edge_batch_prefix(const EdgeJob *jobs, int nj,
+                                                           int *prefix) {
+    __shared__ int lds[256 / WAVE + 1];
+    int carry = 0;
+    for (int b = 0; b < nj; b += 256) {
+        const int j = b + (int)threadIdx.x;
+        const int v = j < nj ? jobs[j].units[EU_COUNT] : 0;
+        int tot;
+        const int off = block_excl_scan<int, 256>(v, lds, &tot);
+        if (j < nj) prefix[j] = carry + off;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) prefix[nj] = carry;
+}
+
+// The chunk kernel over the tiles of every job: global unit u belongs to
+// the last job whose offset is at most u.
+__global__ void __launch_bounds__(CH_THREADS) __attribute__((amdgpu_waves_per_eu(3)))
+    k_edge_chunks_batch(const Mol *mols, const EdgeJob *jobs, int nj, const int *prefix,
+                        int *queue) {
+    __shared__ ChunkLds S;
+    __shared__ int next;
+    unsigned long long cnt[1] = {0};
+    const int total = prefix[nj];
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(queue, 1);
+        __syncthreads();
+        const int u = next;
+        __syncthreads();
+        if (u >= total) break;
+        int lo = 0, hi = nj - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (prefix[mid] <= u) lo = mid;
+            else hi = mid - 1;
+        }
+        const int j = __builtin_amdgcn_readfirstlane(lo);
+        const EdgeJob &J = jobs[j];
+        const int t = J.units[EU_LIST + (u - prefix[j])];
+        const int c0 = J.coff[t], c1 = J.coff[t + 1];
+        for (int c = c0; c < c1; ++c) {
+            const int n = min(CH_EDGES, J.tcount[t] - (c - c0) * CH_EDGES);
+            edge_chunk<false>(mols[J.mol], J.L, J.keys, J.order, c * CH_EDGES, n, J.lam, J.nrm,
+                              J.ptype, J.patoms, J.fallback, J.nfallback, c != c0, S, cnt);
+            __syncthreads();
+        }
+    }
+}
+
 // ------------------------------------------------ roots, one wavefront per edge
 //
 // For the edges of chunks whose root lists overflow: one wavefront per edge,
@@ -1875,6 +1927,34 @@ static hipError_t edge_roots_impl(const Mol &m, const uint8_t *L, const long lon
     else
         hipLaunchKernelGGL(k_edge_wave<false>, dim3(256), dim3(EW_THREADS), 0, st, m, L, keys,
                            fallback, nfallback, lam, nrm, ptype, patoms, overflow, work);
+    return hipGetLastError();
+}
+
+// The fallback edges of every job of a batch.
+__global__ void __launch_bounds__(EW_THREADS)
+    k_edge_wave_batch(const Mol *mols, const EdgeJob *jobs, int nj, int *overflow) {
+    __shared__ EdgeWaveLds lds[EW_WAVES];
+    const int w = threadIdx.x / WAVE;
+    unsigned long long cnt[1] = {0};
+    for (int j = 0; j < nj; ++j) {
+        const EdgeJob &J = jobs[j];
+        const int n = *J.nfallback;
+        for (int g = blockIdx.x * EW_WAVES + w; g < n; g += gridDim.x * EW_WAVES) {
+            edge_wave<false>(mols[J.mol], J.L, J.keys, J.fallback[g], J.lam, J.nrm, J.ptype,
+                             J.patoms, overflow, lds[w], cnt);
+            wave_sync();
+        }
+    }
+}
+
+hipError_t launch_edge_roots_batch(const Mol *mols, const EdgeJob *jobs, int nj, int *prefix,
+                                   int *queue, int *overflow, hipStream_t st) {
+    if (nj <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_edge_batch_prefix, dim3(1), dim3(256), 0, st, jobs, nj, prefix);
+    hipLaunchKernelGGL(k_edge_chunks_batch, dim3((unsigned)edge_chunk_slots()), dim3(CH_THREADS),
+                       0, st, mols, jobs, nj, prefix, queue);
+    hipLaunchKernelGGL(k_edge_wave_batch, dim3(256), dim3(EW_THREADS), 0, st, mols, jobs, nj,
+                       overflow);
     return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ struct ReadBack {
 hipError_t launch_collect(const ReadBack &rb, long long *host, hipStream_t st);
 
 hipError_t fill_i32(int *p, long long n, int v, hipStream_t st);
+hipError_t copy_i32(int *dst, const int *src, long long n, hipStream_t st);
 hipError_t fill_u32(uint32_t *p, long long n, uint32_t v, hipStream_t st);
 
 // stage 1
@@ -107,6 +108,26 @@ hipError_t launch_edge_work(const Mol &m, const uint8_t *L, const long long *key
                             long long count, const int *order, const int *tcount,
                             const int *coff, int *units, int *fallback, int *nfallback,
                             int *overflow, unsigned long long *work, hipStream_t st);
+
+// One molecule's buffers for the fused root launch of a batch (after its
+// crossing edges are grouped): mol indexes the device Mol array; units as
+// written by launch_edge_group; nfallback zeroed.
+struct EdgeJob {
+    const uint8_t *L;
+    const long long *keys;
+    const int *order, *tcount, *coff, *units;
+    double *lam, *nrm;
+    uint8_t *ptype;
+    int *patoms, *fallback, *nfallback;
+    int mol, pad;
+};
+// Every job's tiles in one persistent launch (jobs in the given order, each
+// one's tiles with most chunks first), then the jobs' fallback edges in one
+// launch.  prefix: nj + 1 ints of workspace; queue: one int, zeroed;
+// overflow: one int, set (not cleared) when an edge has more roots than the
+// per-edge lists hold.
+hipError_t launch_edge_roots_batch(const Mol *mols, const EdgeJob *jobs, int nj, int *prefix,
+                                   int *queue, int *overflow, hipStream_t st);
 
 constexpr int EDGE_WORK_COUNTERS = 16;
 
