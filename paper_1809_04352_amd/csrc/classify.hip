@@ -462,10 +462,13 @@ __global__ void __launch_bounds__(CLS_THREADS) k_classify_batch(const Mol *mols,
         __syncthreads();
         if (threadIdx.x == 0) cur = atomicAdd(head, 1);
         __syncthreads();
-        const int u = cur;
+        // the unit and the molecule's view are uniform: keep them in SGPRs
+        const int u = __builtin_amdgcn_readfirstlane(cur);
         if (u >= nunits) break;  // uniform across the workgroup
         const int2 w = units[u];
-        classify_tile<F32>(mols[w.x], w.y, labels[w.x], sh);
+        const int mol = __builtin_amdgcn_readfirstlane(w.x);
+        const int tile = __builtin_amdgcn_readfirstlane(w.y);
+        classify_tile<F32>(uniform_mol(mols, mol), tile, labels[mol], sh);
     }
 }
 

@@ -278,6 +278,19 @@ __device__ inline int xcd_tile(int b, int nblocks, int ntiles) {
     return t < ntiles ? t : -1;
 }
 
+// A molecule's view from a device array at a workgroup-uniform index, copied
+// word by word into uniform registers: read through the pointer, every field
+// would be a vector load (the kernels' stores might alias it) and hold VGPRs.
+__device__ inline Mol uniform_mol(const Mol *mols, int q) {
+    static_assert(sizeof(Mol) % 4 == 0, "Mol is copied in 32-bit words");
+    Mol r;
+    const int *src = (const int *)(mols + q);
+    int *dst = (int *)&r;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(Mol) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+    return r;
+}
+
 __device__ inline void fill_i32(int *p, long long n, int v) {
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
          q += (long long)gridDim.x * blockDim.x)
