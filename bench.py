@@ -230,7 +230,10 @@ def main():
     for name, fl, t in (("classify", flops_classify, kmed["classify_ms"]),
                         ("edge_roots", flops_edges, kmed["edge_roots_ms"])):
         a = fl / (t * 1e-3) / 1e12
-        rl[name] = {"kernel": "k_classify" if name == "classify" else "k_edge_chunks",
+        kname = "k_classify" if name == "classify" else "k_edge_chunks"
+        if len(mols) > 1:
+            kname += "_batch"  # the fused launches of a batch
+        rl[name] = {"kernel": kname,
                     "bound": "alu", "achieved": a, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                     "frac": a / PEAK_FP64_TFLOPS, "traffic": None, "algorithmic_flops": fl,
                     "ms": t}
@@ -290,7 +293,7 @@ def kernel_sources_digest(kernel):
     import hashlib
     csrc = os.path.join(ROOT, "paper_1809_04352_amd", "csrc")
     files = ["eses_device.h", "eses_internal.h",
-             "classify.hip" if kernel == "k_classify" else "edges.hip"]
+             "classify.hip" if kernel.startswith("k_classify") else "edges.hip"]
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(csrc, f), "rb") as fh:
