@@ -218,7 +218,7 @@ long long *readback_host() {
 // Worker streams for per-molecule work of a batch: created once per device
 // (default priority, not blocking on the null stream) and kept for the
 // process lifetime, so that workspace cached under them stays reusable.
-constexpr int N_WORKERS = 4;
+constexpr int N_WORKERS = 8;
 
 eses_status worker_streams(hipStream_t *ws) {
     static std::mutex mu;
