@@ -106,7 +106,11 @@ typedef struct {
                               probe-position count pass keeps what it finds
                               (0 = default); when the pool overflows, the
                               positions are recomputed by a fill pass */
-    int32_t reserved[3];   /* must be zero */
+    int32_t tile_pool;     /* test aid: entries of a tile's candidate lists the
+                              count pass keeps (0 = default; at most the
+                              default); tiles with more are rebuilt by a fill
+                              pass */
+    int32_t reserved[2];   /* must be zero */
 } eses_config;
 
 typedef struct eses_candidates eses_candidates; /* opaque, library-owned */

@@ -352,7 +352,8 @@ eses_status d2h_ints(std::initializer_list<std::pair<int *, const int *>> items,
 // The handle's buffers come from (and return to) the cache of `home`, the
 // caller's stream, which `st` follows; build-time temporaries stay with `st`.
 eses_status build_one(const eses_molecule *in, int tile, int force_recheck, int edge_fallback,
-                      int vertex_pool, MolState *S, hipStream_t st, hipStream_t home) {
+                      int vertex_pool, int tile_pool, MolState *S, hipStream_t st,
+                      hipStream_t home) {
     Mol &m = S->m;
     Arena &A = S->arena;
     Arena &T = S->scratch;
@@ -541,16 +542,24 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, int 
     CKS(A.alloc(&m.tF_off, m.ntiles + 1));
     CKS(A.alloc(&m.tC_off, m.ntiles + 1));
     CKS(A.alloc(&m.tV_off, m.ntiles + 1));
-    CK(launch_tiles(m, false, cA, cF, cC, cV, st));
+    // the count pass keeps the lists in a pool, placed after the read-back
+    TilePool tp{};
+    tp.cap = tile_pool > 0 ? std::min(tile_pool, tile_keep_max()) : tile_keep_max();
+    CKS(T.alloc(&tp.pool, (long long)tp.cap * m.ntiles));
+    CKS(T.alloc(&tp.off, m.ntiles));
+    CKS(T.alloc(&tp.unpooled, 1));
+    CK(fill_i32(tp.unpooled, 1, 0, st));
+    CK(launch_tiles(m, false, cA, cF, cC, cV, tp, st));
     {
         const int *ins[4] = {cA, cF, cC, cV};
         int *outs[4] = {m.tA_off, m.tF_off, m.tC_off, m.tV_off};
         CK(scan_i32_multi(ins, m.ntiles, outs, 4, tmp, st));
     }
-    int nfc = 0, nec_cut = 0, tl[4];
+    int nfc = 0, nec_cut = 0, tl[4], unpooled = 0;
     CKS(d2h_ints({{&nfc, m.face_cut_off + m.nface}, {&nec_cut, m.ec_cut_off + m.nec},
                    {&tl[0], m.tA_off + m.ntiles}, {&tl[1], m.tF_off + m.ntiles},
-                   {&tl[2], m.tC_off + m.ntiles}, {&tl[3], m.tV_off + m.ntiles}}, st));
+                   {&tl[2], m.tC_off + m.ntiles}, {&tl[3], m.tV_off + m.ntiles},
+                   {&unpooled, tp.unpooled}}, st));
     CKS(A.alloc(&m.face_cut, nfc));
     CK(launch_face_cuts(m, st));
     CKS(A.alloc(&m.ec_cut, nec_cut));
@@ -559,7 +568,8 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, int 
     CKS(A.alloc(&m.tF, tl[1]));
     CKS(A.alloc(&m.tC, tl[2]));
     CKS(A.alloc(&m.tV, tl[3]));
-    CK(launch_tiles(m, true, cA, cF, cC, cV, st));
+    CK(launch_tiles_place(m, tp, cA, cF, cC, cV, st));
+    if (unpooled) CK(launch_tiles(m, true, cA, cF, cC, cV, tp, st));
 
     // (m.diag[0], set by a fill pass that met more entries than it counted,
     // is checked at the next read-back: eses_edge_intersections)
@@ -917,21 +927,22 @@ eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
         set_err("need at least one molecule");
         return ESES_EINVAL;
     }
-    int tile = 8, force_recheck = 0, edge_fallback = 0, vertex_pool = 0;
+    int tile = 8, force_recheck = 0, edge_fallback = 0, vertex_pool = 0, tile_pool = 0;
     if (cfg) {
         if (cfg->tile != 0) tile = cfg->tile;
         force_recheck = cfg->force_recheck;
         edge_fallback = cfg->edge_fallback;
         vertex_pool = cfg->vertex_pool;
+        tile_pool = cfg->tile_pool;
         if (cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64) {
             set_err("blocks_per_cu must be in [0, 64]");
             return ESES_EINVAL;
         }
-        if (vertex_pool < 0) {
-            set_err("vertex_pool must be >= 0");
+        if (vertex_pool < 0 || tile_pool < 0) {
+            set_err("vertex_pool and tile_pool must be >= 0");
             return ESES_EINVAL;
         }
-        for (int q = 0; q < 3; ++q)
+        for (int q = 0; q < 2; ++q)
             if (cfg->reserved[q] != 0) {
                 set_err("eses_config.reserved must be zero");
                 return ESES_EINVAL;
@@ -946,8 +957,8 @@ eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
     c->stream = st;
     for (int32_t q = 0; q < n_mols; ++q) c->mols.push_back(new MolState());
     if (n_mols == 1) {
-        eses_status s = build_one(&mols[0], tile, force_recheck, edge_fallback, vertex_pool, c->mols[0],
-                                  st, st);
+        eses_status s = build_one(&mols[0], tile, force_recheck, edge_fallback, vertex_pool,
+                                  tile_pool, c->mols[0], st, st);
         if (s != ESES_OK) {
             std::string msg = g_err;
             eses_free_candidates(c);
@@ -958,8 +969,8 @@ eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
         // molecules built concurrently on the worker streams; their workspace
         // then belongs to the caller's stream, which waits for the builds
         eses_status s = run_on_workers(n_mols, st, [&](int q, hipStream_t ws) {
-            return build_one(&mols[q], tile, force_recheck, edge_fallback, vertex_pool, c->mols[q],
-                             ws, st);
+            return build_one(&mols[q], tile, force_recheck, edge_fallback, vertex_pool,
+                             tile_pool, c->mols[q], ws, st);
         });
         for (MolState *S : c->mols) S->arena.st = st;  // later uses follow the caller's stream
         if (s != ESES_OK) {

@@ -932,15 +932,26 @@ __device__ inline int tile_row(const int *incl, int nrow, int t) {
     return lo;
 }
 
+constexpr int TILE_KEEP = 96;  // entries of a tile's lists the count pass keeps (LDS, pool slot)
+
 template <bool FILL>
 __global__ void __launch_bounds__(TILE_WAVES *WAVE) k_tiles(Mol m, int *cntA, int *cntF,
-                                                             int *cntC, int *cntV) {
+                                                             int *cntC, int *cntV, TilePool tp) {
     // per wavefront and kind (atoms, exposed circles, vertices): each row's
     // first candidate and inclusive end offset
     __shared__ int rbeg[TILE_WAVES][3][WAVE], rend[TILE_WAVES][3][WAVE];
+    // count pass: the first TILE_KEEP entries of the tile's four lists
+    __shared__ int keep[FILL ? 1 : TILE_WAVES][4][FILL ? 1 : TILE_KEEP];
     const int wv = threadIdx.x / WAVE;
     int tile = blockIdx.x * TILE_WAVES + wv;
     if (tile >= m.ntiles) return;  // uniform across the wavefront (no block barriers)
+    // the fill pass skips tiles whose lists the count pass pooled and those
+    // whose four lists are empty (most of a grid's tiles lie away from the
+    // molecule)
+    if (FILL && (tp.off[tile] >= 0 ||
+                 (m.tA_off[tile] == m.tA_off[tile + 1] && m.tF_off[tile] == m.tF_off[tile + 1] &&
+                  m.tC_off[tile] == m.tC_off[tile + 1] && m.tV_off[tile] == m.tV_off[tile + 1])))
+        return;
     const int lane = lane_id();
     int t3[3] = {tile % m.tdims[0], (tile / m.tdims[0]) % m.tdims[1],
                  tile / (m.tdims[0] * m.tdims[1])};
@@ -1002,6 +1013,10 @@ __global__ void __launch_bounds__(TILE_WAVES *WAVE) k_tiles(Mol m, int *cntA, in
                 int pa = oA + nA + mask_prefix(bA), pf = oF + nF + mask_prefix(bF);
                 if (inA && fill_ok(m, pa, m.tA_off[tile + 1])) m.tA[pa] = i;
                 if (inF && fill_ok(m, pf, m.tF_off[tile + 1])) m.tF[pf] = m.face_off_atom[i];
+            } else {
+                const int pa = nA + mask_prefix(bA), pf = nF + mask_prefix(bF);
+                if (inA && pa < TILE_KEEP) keep[wv][0][pa] = i;
+                if (inF && pf < TILE_KEEP) keep[wv][1][pf] = m.face_off_atom[i];
             }
             nA += __popcll(bA);
             nF += __popcll(bF);
@@ -1031,6 +1046,7 @@ __global__ void __launch_bounds__(TILE_WAVES *WAVE) k_tiles(Mol m, int *cntA, in
             unsigned long long bC = __ballot(in);
             int pc = oC + nC + mask_prefix(bC);
             if (FILL && in && fill_ok(m, pc, m.tC_off[tile + 1])) m.tC[pc] = e;
+            if (!FILL && in && pc < TILE_KEEP) keep[wv][2][pc] = e;
             nC += __popcll(bC);
         }
         for (int base = 0; base < tV; base += WAVE) {
@@ -1046,15 +1062,54 @@ __global__ void __launch_bounds__(TILE_WAVES *WAVE) k_tiles(Mol m, int *cntA, in
             unsigned long long bV = __ballot(in);
             int pv = oV + nV + mask_prefix(bV);
             if (FILL && in && fill_ok(m, pv, m.tV_off[tile + 1])) m.tV[pv] = v;
+            if (!FILL && in && pv < TILE_KEEP) keep[wv][3][pv] = v;
             nV += __popcll(bV);
         }
         wave_sync();  // the next batch of rows overwrites the offsets
     }
-    if (!FILL && lane == 0) {
-        cntA[tile] = nA;
-        cntF[tile] = nF;
-        cntC[tile] = nC;
-        cntV[tile] = nV;
+    if (!FILL) {
+        if (lane == 0) {
+            cntA[tile] = nA;
+            cntF[tile] = nF;
+            cntC[tile] = nC;
+            cntV[tile] = nV;
+        }
+        // the kept lists go to the tile's slot of the pool (tp.cap entries
+        // per tile), or the fill pass rebuilds them
+        const int tot = nA + nF + nC + nV;
+        const int base = tot <= tp.cap ? tile * tp.cap : -1;
+        if (lane == 0) {
+            tp.off[tile] = base;
+            if (base < 0) atomicOr(tp.unpooled, 1);
+        }
+        if (base >= 0) {
+            wave_sync();
+            const int n4[4] = {nA, nF, nC, nV};
+            int w = base;
+            for (int k = 0; k < 4; ++k) {
+                for (int q = lane; q < n4[k]; q += WAVE) tp.pool[w + q] = keep[wv][k][q];
+                w += n4[k];
+            }
+        }
+    }
+}
+
+// Pooled tile lists to their places: one wavefront per tile.
+__global__ void __launch_bounds__(TILE_WAVES *WAVE) k_tiles_place(Mol m, TilePool tp,
+                                                                   const int *cA, const int *cF,
+                                                                   const int *cC, const int *cV) {
+    const int tile = blockIdx.x * TILE_WAVES + threadIdx.x / WAVE;
+    if (tile >= m.ntiles) return;
+    const int b = tp.off[tile];
+    if (b < 0) return;
+    const int lane = lane_id();
+    const int n4[4] = {cA[tile], cF[tile], cC[tile], cV[tile]};
+    int *dst[4] = {m.tA + m.tA_off[tile], m.tF + m.tF_off[tile], m.tC + m.tC_off[tile],
+                   m.tV + m.tV_off[tile]};
+    int w = b;
+    for (int k = 0; k < 4; ++k) {
+        for (int q = lane; q < n4[k]; q += WAVE) dst[k][q] = tp.pool[w + q];
+        w += n4[k];
     }
 }
 
@@ -1242,12 +1297,23 @@ hipError_t launch_ec_cuts(const Mol &m, bool fill, int *cut_cnt, hipStream_t st)
 }
 
 hipError_t launch_tiles(const Mol &m, bool fill, int *cA, int *cF, int *cC, int *cV,
-                        hipStream_t st) {
+                        const TilePool &tp, hipStream_t st) {
     unsigned nb = blocks_for(m.ntiles, TILE_WAVES);
     if (fill)
-        hipLaunchKernelGGL(k_tiles<true>, dim3(nb), dim3(TILE_WAVES * WAVE), 0, st, m, cA, cF, cC, cV);
+        hipLaunchKernelGGL(k_tiles<true>, dim3(nb), dim3(TILE_WAVES * WAVE), 0, st, m, cA, cF, cC,
+                           cV, tp);
     else
-        hipLaunchKernelGGL(k_tiles<false>, dim3(nb), dim3(TILE_WAVES * WAVE), 0, st, m, cA, cF, cC, cV);
+        hipLaunchKernelGGL(k_tiles<false>, dim3(nb), dim3(TILE_WAVES * WAVE), 0, st, m, cA, cF,
+                           cC, cV, tp);
+    return hipGetLastError();
+}
+
+int tile_keep_max() { return TILE_KEEP; }
+
+hipError_t launch_tiles_place(const Mol &m, const TilePool &tp, const int *cA, const int *cF,
+                              const int *cC, const int *cV, hipStream_t st) {
+    hipLaunchKernelGGL(k_tiles_place, dim3(blocks_for(m.ntiles, TILE_WAVES)),
+                       dim3(TILE_WAVES * WAVE), 0, st, m, tp, cA, cF, cC, cV);
     return hipGetLastError();
 }
 

@@ -59,8 +59,20 @@ hipError_t launch_ec_ids(const Mol &m, const int *ec_pos, hipStream_t st);
 hipError_t launch_face_list(const Mol &m, int *cut_cnt, hipStream_t st);
 hipError_t launch_face_cuts(const Mol &m, hipStream_t st);
 hipError_t launch_ec_cuts(const Mol &m, bool fill, int *cut_cnt, hipStream_t st);
+// Tile lists kept by the count pass: each tile's four lists (atoms, faces,
+// circles, probes, in that order) copied into its slot of `pool` (cap ints
+// per tile, cap <= tile_keep_max()) at off[t] = t * cap, or off[t] = -1 when
+// they do not fit (then *unpooled, zeroed before, is set and the fill pass
+// rebuilds that tile).
+struct TilePool {
+    int *pool, *off, *unpooled;
+    int cap;
+};
+int tile_keep_max();
+hipError_t launch_tiles_place(const Mol &m, const TilePool &tp, const int *cA, const int *cF,
+                              const int *cC, const int *cV, hipStream_t st);
 hipError_t launch_tiles(const Mol &m, bool fill, int *cA, int *cF, int *cC, int *cV,
-                        hipStream_t st);
+                        const TilePool &tp, hipStream_t st);
 
 // stage 2
 hipError_t launch_classify(const Mol &m, bool fp32, uint8_t *labels, hipStream_t st);

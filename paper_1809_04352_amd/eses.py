@@ -49,7 +49,8 @@ class Molecule(ctypes.Structure):
 class Config(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("force_recheck", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("edge_fallback", ctypes.c_int32),
-                ("vertex_pool", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("vertex_pool", ctypes.c_int32), ("tile_pool", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class CandidateStats(ctypes.Structure):
@@ -197,7 +198,8 @@ class Candidates:
     """Owning wrapper of an eses_candidates handle."""
 
     def __init__(self, mols, tile: int = 0, stream=None, force_recheck: bool = False,
-                 blocks_per_cu: int = 0, edge_fallback: bool = False, vertex_pool: int = 0):
+                 blocks_per_cu: int = 0, edge_fallback: bool = False, vertex_pool: int = 0,
+                 tile_pool: int = 0):
         lib = load()
         self.mols = list(mols)
         arr = (Molecule * len(self.mols))(*self.mols)
@@ -207,6 +209,7 @@ class Candidates:
         cfg.blocks_per_cu = int(blocks_per_cu)
         cfg.edge_fallback = 1 if edge_fallback else 0
         cfg.vertex_pool = int(vertex_pool)
+        cfg.tile_pool = int(tile_pool)
         h = ctypes.c_void_p()
         self.stream = _stream_ptr(stream)
         _check(lib.eses_build_candidates(arr, len(self.mols), ctypes.byref(cfg), self.stream,
@@ -232,9 +235,9 @@ class Candidates:
 
 def build_candidates(mols, tile: int = 0, stream=None, force_recheck: bool = False,
                      blocks_per_cu: int = 0, edge_fallback: bool = False,
-                     vertex_pool: int = 0) -> Candidates:
+                     vertex_pool: int = 0, tile_pool: int = 0) -> Candidates:
     return Candidates(mols, tile, stream, force_recheck, blocks_per_cu, edge_fallback,
-                      vertex_pool)
+                      vertex_pool, tile_pool)
 
 
 def copy_vertices(cand: Candidates, mol: int, p_dev, atoms_dev, sign_dev, stream=None) -> int:
@@ -328,7 +331,7 @@ def kernel_times(cand: Candidates) -> dict:
 def surface(centres, radii, probe: float, spacing: float, lo, hi, prec: int = ESES_FP64,
             tile: int = 0, isect_capacity: int | None = None, device="cuda",
             force_recheck: bool = False, stats: bool = False, edge_fallback: bool = False,
-            vertex_pool: int = 0):
+            vertex_pool: int = 0, tile_pool: int = 0):
     """Whole hot path for one molecule given host arrays; returns host numpy results."""
     import torch
     c = torch.as_tensor(np.ascontiguousarray(centres, dtype=np.float64), device=device)
@@ -336,7 +339,7 @@ def surface(centres, radii, probe: float, spacing: float, lo, hi, prec: int = ES
     mol = make_molecule(c, r, probe, spacing, lo, hi)
     dims = grid_dims(mol)
     cand = build_candidates([mol], tile, force_recheck=force_recheck, edge_fallback=edge_fallback,
-                            vertex_pool=vertex_pool)
+                            vertex_pool=vertex_pool, tile_pool=tile_pool)
     try:
         info = cand.info(0)
         nv = info["n_vertices"]

@@ -243,3 +243,20 @@ def test_vertex_pool_overflow(E, oracle_mod, pool):
         assert np.array_equal(a[k], b[k]), k
     o = oracle_mod.Oracle(m.centres, m.radii, m.probe)
     assert compare_vertices(b["vertices"], o) > 10
+
+
+@pytest.mark.parametrize("pool", [1, 16])
+def test_tile_pool_overflow(E, oracle_mod, pool):
+    """Tile candidate lists rebuilt by the fill pass for the tiles with more
+    entries than the count pass keeps (one: every non-trivial tile; 16: a mix)
+    give the same labels and records as the kept lists, and the oracle's
+    labels."""
+    from eses_inputs import molecule
+    m = molecule(400, 6, 0.45)
+    a = E.surface(m.centres, m.radii, m.probe, m.spacing, m.lo, m.hi)
+    b = E.surface(m.centres, m.radii, m.probe, m.spacing, m.lo, m.hi, tile_pool=pool)
+    assert a["info"]["tile_list_entries"] == b["info"]["tile_list_entries"] > 0
+    for k in ("labels", "key", "lam", "normal", "patch_type", "atoms"):
+        assert np.array_equal(a[k], b[k]), k
+    o = oracle_mod.Oracle(m.centres, m.radii, m.probe)
+    compare_labels(b["labels"], o.labels_grid(m.lo, m.spacing, m.dims))
