@@ -155,7 +155,7 @@ struct eses_candidates {
     int *head = nullptr;
     uint8_t **labels_dev = nullptr;
     long long nunits = 0;
-    int batch_blocks = 0;
+    int batch_blocks[2] = {0, 0};  // persistent classification grid: FP64, FP32
     int blocks_per_cu = 0;
     // recorded fused classification, per precision
     hipGraph_t graph[2] = {nullptr, nullptr};
@@ -628,8 +628,11 @@ eses_status build_batch(eses_candidates *c, hipStream_t st) {
     int dev = 0, ncu = 0;
     CK(hipGetDevice(&dev));
     CK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    int per = c->blocks_per_cu > 0 ? c->blocks_per_cu : classify_batch_blocks_per_cu(true);
-    c->batch_blocks = std::max(1, ncu * per);
+    for (int k = 0; k < 2; ++k) {
+        const int per =
+            c->blocks_per_cu > 0 ? c->blocks_per_cu : classify_batch_blocks_per_cu(k == 1);
+        c->batch_blocks[k] = std::max(1, ncu * per);
+    }
     return ESES_OK;
 }
 
@@ -646,7 +649,7 @@ eses_status classify_batch(eses_candidates *c, bool fp32, uint8_t *const *labels
         hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess)
             e = launch_classify_batch(c->mols_dev, c->labels_dev, c->units, (int)c->nunits,
-                                      c->head, c->batch_blocks, fp32, cap);
+                                      c->head, c->batch_blocks[fp32 ? 1 : 0], fp32, cap);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(cap, &g);
         if (e == hipSuccess) e = e2;

@@ -49,6 +49,10 @@ struct ClsPhase2 {
     // staging of the cuts: per surface (faces, then circles) the first
     // global cut, the prefix of the uncut counts (pair -> surface), the
     // number of cuts kept and their region in `cut`
+    // each surface's cone over the tile, rounded to FP32 (axis, sin; cos, or
+    // -1 for a cone of every direction); the cut test allows for the rounding
+    float4 cna[CAP_F + CAP_C];
+    float cnc[CAP_F + CAP_C];
     int ccb[CAP_F + CAP_C];
     int coff[CAP_F + CAP_C + 1];
     int ccur[CAP_F + CAP_C];
@@ -111,20 +115,25 @@ __device__ inline Cone make_cone(double vx, double vy, double vz, double rb) {
     return c;
 }
 
-// True if some direction u of the cone has u . v > tau (the cut can matter).
-__device__ inline bool cut_matters(const Cone &c, double4 cut) {
-    if (c.all) return true;
-    double vn = sqrt(cut.x * cut.x + cut.y * cut.y + cut.z * cut.z);
+// Whether cut (v, tau) can reject some direction u of the cone (u . v >
+// tau): the maximum of u . v over the cone, |v| cos(max(0, phi - theta)),
+// against tau with a small slack.  The cone's parameters are rounded to FP32
+// (each within 2^-23 relative of its FP64 value), which moves that maximum by
+// less than 1e-6 |v|; the slack covers it, so no cut that matters is dropped
+// (an extra kept cut only costs a test).
+__device__ inline bool cut_matters_f(float4 a, float ct, double4 cut) {
+    if (ct < 0.0f) return true;
+    const double vn = sqrt(cut.x * cut.x + cut.y * cut.y + cut.z * cut.z);
     if (!(vn > 0.0)) return 0.0 > cut.w - 1e-9;
-    double cp = (c.ax * cut.x + c.ay * cut.y + c.az * cut.z) / vn;
+    const double cp = ((double)a.x * cut.x + (double)a.y * cut.y + (double)a.z * cut.z) / vn;
     double best;
-    if (cp >= c.ct) {
+    if (cp >= (double)ct) {
         best = vn;
     } else {
-        double sp = sqrt(fmax(0.0, 1.0 - cp * cp));
-        best = vn * (cp * c.ct + sp * c.st);
+        const double sp = sqrt(fmax(0.0, 1.0 - cp * cp));
+        best = vn * (cp * (double)ct + sp * (double)a.w);
     }
-    return best > cut.w - 1e-9;
+    return best > cut.w - 1e-9 - 1e-6 * vn;
 }
 
 __device__ inline bool cuts_pass(const double4 *cuts, int b, int e, double dx, double dy,
@@ -376,6 +385,26 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
         sh.p2.ccur[q] = 0;
         ncut = ce - cb;
     }
+    // each surface's cone over the tile, once
+    for (int q = threadIdx.x; q < nS; q += CLS_THREADS) {
+        double vx, vy, vz;
+        if (q < nF) {
+            const double4 a = sh.p2.f[q];
+            vx = bc[0] - a.x;
+            vy = bc[1] - a.y;
+            vz = bc[2] - a.z;
+        } else {
+            const double4 oR = sh.p2.co[q - nF], n = sh.p2.cn[q - nF];
+            const double wx = bc[0] - oR.x, wy = bc[1] - oR.y, wz = bc[2] - oR.z;
+            const double t = wx * n.x + wy * n.y + wz * n.z;
+            vx = wx - t * n.x;
+            vy = wy - t * n.y;
+            vz = wz - t * n.z;
+        }
+        const Cone cone = make_cone(vx, vy, vz, rb);
+        sh.p2.cna[q] = make_float4((float)cone.ax, (float)cone.ay, (float)cone.az, (float)cone.st);
+        sh.p2.cnc[q] = cone.all ? -1.0f : (float)cone.ct;
+    }
     int total;
     const int coff = block_excl_scan<int, CLS_THREADS>(ncut, sh.p2.scan, &total);
     if ((int)threadIdx.x < nS) sh.p2.coff[threadIdx.x] = coff;
@@ -392,20 +421,8 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
             const int q = lo;
             if (pass == 1 && sh.p2.koff[q] < 0) continue;  // not staged
             const int c = sh.p2.ccb[q] + (p - sh.p2.coff[q]);
-            Cone cone;
-            double4 v;
-            if (q < nF) {
-                const double4 a = sh.p2.f[q];
-                cone = make_cone(bc[0] - a.x, bc[1] - a.y, bc[2] - a.z, rb);
-                v = m.face_cut[c];
-            } else {
-                const double4 oR = sh.p2.co[q - nF], n = sh.p2.cn[q - nF];
-                const double wx = bc[0] - oR.x, wy = bc[1] - oR.y, wz = bc[2] - oR.z;
-                const double t = wx * n.x + wy * n.y + wz * n.z;
-                cone = make_cone(wx - t * n.x, wy - t * n.y, wz - t * n.z, rb);
-                v = m.ec_cut[c];
-            }
-            if (!cut_matters(cone, v)) continue;
+            const double4 v = q < nF ? m.face_cut[c] : m.ec_cut[c];
+            if (!cut_matters_f(sh.p2.cna[q], sh.p2.cnc[q], v)) continue;
             const int k = atomicAdd(&sh.p2.ccur[q], 1);
             if (pass == 1) sh.p2.cut[sh.p2.koff[q] + k] = v;
         }
