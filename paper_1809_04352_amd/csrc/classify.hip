@@ -118,14 +118,23 @@ __device__ inline Cone make_cone(double vx, double vy, double vz, double rb) {
 // Whether cut (v, tau) can reject some direction u of the cone (u . v >
 // tau): the maximum of u . v over the cone, |v| cos(max(0, phi - theta)),
 // against tau with a small slack.  The cone's parameters are rounded to FP32
-// (each within 2^-23 relative of its FP64 value), which moves that maximum by
-// less than 1e-6 |v|; the slack covers it, so no cut that matters is dropped
-// (an extra kept cut only costs a test).
+// (each within 2^-23 relative of its FP64 value).  The axis a' is rescaled
+// by one Newton step for 1 / |a'| (|a'|^2 is within 4e-7 of 1, so the step
+// is exact to 1e-13): cp is then the cosine of the angle phi' between v and
+// a direction within 2e-7 rad of the exact axis, to 1e-13, so that
+// phi' is within 4e-7 rad of phi even where cp is near +-1, and the maximum
+// moves by less than 1e-6 |v|; the slack covers it, so no cut that matters is
+// dropped (an extra kept cut only costs a test).
+__device__ inline double cone_cos(float4 a, double4 v, double vn) {
+    const double ax = a.x, ay = a.y, az = a.z;
+    return (ax * v.x + ay * v.y + az * v.z) / vn * (1.5 - 0.5 * (ax * ax + ay * ay + az * az));
+}
+
 __device__ inline bool cut_matters_f(float4 a, float ct, double4 cut) {
     if (ct < 0.0f) return true;
     const double vn = sqrt(cut.x * cut.x + cut.y * cut.y + cut.z * cut.z);
     if (!(vn > 0.0)) return 0.0 > cut.w - 1e-9;
-    const double cp = ((double)a.x * cut.x + (double)a.y * cut.y + (double)a.z * cut.z) / vn;
+    const double cp = cone_cos(a, cut, vn);
     double best;
     if (cp >= (double)ct) {
         best = vn;
