@@ -529,8 +529,8 @@ __device__ inline EdgeGeom edge_geom(const Mol &m, const uint8_t *L, long long k
     const int axis = (int)(key % 3);
     const long long idx = key / 3;
     const int nx = m.dims[0], ny = m.dims[1];
-    const int i0 = (int)(idx % nx), i1 = (int)((idx / nx) % ny),
-              i2 = (int)(idx / ((long long)nx * ny));
+    int i0, i1, i2;
+    grid_ijk(idx, nx, ny, i0, i1, i2);
     const long long step = axis == 0 ? 1 : axis == 1 ? (long long)nx : (long long)nx * ny;
     G.Ls = L[idx];
     G.Lt = L[idx + step];
@@ -659,9 +659,8 @@ __device__ inline void write_record(const Mol &m, long long q, const EdgeGeom &G
 }
 
 __device__ inline int edge_tile(const Mol &m, long long key) {
-    long long idx = key / 3;
-    const int nx = m.dims[0], ny = m.dims[1];
-    int i = (int)(idx % nx), j = (int)((idx / nx) % ny), k = (int)(idx / ((long long)nx * ny));
+    int i, j, k;
+    grid_ijk(key / 3, m.dims[0], m.dims[1], i, j, k);
     return i / m.tile + m.tdims[0] * (j / m.tile + m.tdims[1] * (k / m.tile));
 }
 
@@ -716,6 +715,10 @@ struct ChunkLds {
             int ccb[CH_SURF];
             int coff[CH_SURF + 1];
             int ccur[CH_SURF];
+            // each surface's cone over the tile in FP32 (axis, sin; cos, or
+            // -1 for every direction)
+            float4 cna[CH_SURF];
+            float cnc[CH_SURF];
         } st;
         // solve phase: roots of one quartic per thread
         double slot[CH_SLOTS][CH_THREADS];
@@ -1046,29 +1049,44 @@ __device__ inline DirCone surface_cone(int type, const SurfParams &p, const doub
 
 // A cut (v, tau) rejects the unit direction u iff u . v > tau.  Over the
 // cone, u . v ranges between |v| cos(phi + theta) and |v| cos(phi - theta)
-// (phi the angle between v and the axis, clamped to [0, pi]); both tests
-// keep a small slack on the conservative side.
-__device__ inline bool cone_rejects(const DirCone &c, double4 v) {
-    if (c.all) return false;
-    const double vn = sqrt(v.x * v.x + v.y * v.y + v.z * v.z);
-    if (!(vn > 0.0)) return false;
-    const double cp = (c.ax * v.x + c.ay * v.y + c.az * v.z) / vn;
-    if (cp <= -c.ct) return false;  // the cone holds the direction opposite to v
-    const double sp = sqrt(fmax(0.0, 1.0 - cp * cp));
-    return vn * (cp * c.ct - sp * c.st) > v.w + 1e-9 * (vn + fabs(v.w));
+// (phi the angle between v and the axis, clamped to [0, pi]): cone_rejects_f
+// tells whether the cut rejects every direction of the cone, cone_may_reject_f
+// whether it rejects some.  The cone's parameters are rounded to FP32 (each
+// within 2^-23 relative); the axis a' is rescaled by one Newton step for
+// 1 / |a'| (exact to 1e-13, |a'|^2 being within 4e-7 of 1), so cp is the
+// cosine, to 1e-13, of the angle between v and a direction within 2e-7 rad
+// of the exact axis, and that angle is within 4e-7 rad of the exact one even
+// where cp is near +-1.  Those extremes then move by less than 1e-6 |v|; a
+// margin of that size, beside a small slack, keeps both decisions
+// conservative (a surface is declared dead, or a cut dropped, only when the
+// exact cone would do so too).
+__device__ inline double cone_cos(float4 a, double4 v, double vn) {
+    const double ax = a.x, ay = a.y, az = a.z;
+    return (ax * v.x + ay * v.y + az * v.z) / vn * (1.5 - 0.5 * (ax * ax + ay * ay + az * az));
 }
 
-__device__ inline bool cone_may_reject(const DirCone &c, double4 v) {
-    if (c.all) return true;
+__device__ inline bool cone_rejects_f(float4 a, float ct, double4 v) {
+    if (ct < 0.0f) return false;
+    const double vn = sqrt(v.x * v.x + v.y * v.y + v.z * v.z);
+    if (!(vn > 0.0)) return false;
+    const double cp = cone_cos(a, v, vn);
+    if (cp <= -(double)ct) return false;
+    const double sp = sqrt(fmax(0.0, 1.0 - cp * cp));
+    return vn * (cp * (double)ct - sp * (double)a.w) >
+           v.w + 1e-9 * (vn + fabs(v.w)) + 1e-6 * vn;
+}
+
+__device__ inline bool cone_may_reject_f(float4 a, float ct, double4 v) {
+    if (ct < 0.0f) return true;
     const double vn = sqrt(v.x * v.x + v.y * v.y + v.z * v.z);
     if (!(vn > 0.0)) return 0.0 > v.w - 1e-9;
-    const double cp = (c.ax * v.x + c.ay * v.y + c.az * v.z) / vn;
-    double best = vn;  // the cone holds v's direction
-    if (cp < c.ct) {
+    const double cp = cone_cos(a, v, vn);
+    double best = vn;
+    if (cp < (double)ct) {
         const double sp = sqrt(fmax(0.0, 1.0 - cp * cp));
-        best = vn * (cp * c.ct + sp * c.st);
+        best = vn * (cp * (double)ct + sp * (double)a.w);
     }
-    return best > v.w - 1e-9 * (vn + fabs(v.w));
+    return best > v.w - 1e-9 * (vn + fabs(v.w)) - 1e-6 * vn;
 }
 
 // Whether some cut of staged face or circle si rejects its candidate at
@@ -1203,6 +1221,12 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
                 S.sdead[tid] = 0;
                 ncut = ce - cb;
             }
+            if (tid < ns) {
+                const DirCone cone = surface_cone(S.skey[tid] >> 28, S.sp[tid], bc, rb);
+                S.st.cna[tid] =
+                    make_float4((float)cone.ax, (float)cone.ay, (float)cone.az, (float)cone.st);
+                S.st.cnc[tid] = cone.all ? -1.0f : (float)cone.ct;
+            }
             int total;
             const int off = block_excl_scan<int, CH_THREADS>(ncut, S.scan, &total);
             if (tid < ns) S.st.coff[tid] = off;
@@ -1221,9 +1245,10 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
                     const int type = S.skey[q] >> 28;
                     const double4 *gc = type == 1 ? m.face_cut : m.ec_cut;
                     const double4 v = gc[S.st.ccb[q] + (p - S.st.coff[q])];
-                    const DirCone cone = surface_cone(type, S.sp[q], bc, rb);
-                    if (pass == 0 && cone_rejects(cone, v)) S.sdead[q] = 1;
-                    if (!cone_may_reject(cone, v)) continue;
+                    const float4 ca = S.st.cna[q];
+                    const float cc = S.st.cnc[q];
+                    if (pass == 0 && cone_rejects_f(ca, cc, v)) S.sdead[q] = 1;
+                    if (!cone_may_reject_f(ca, cc, v)) continue;
                     const int k = atomicAdd(&S.st.ccur[q], 1);
                     if (pass == 1) S.cut[S.crange[q].x + k] = v;
                 }

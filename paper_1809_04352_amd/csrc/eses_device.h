@@ -278,6 +278,22 @@ __device__ inline int xcd_tile(int b, int nblocks, int ntiles) {
     return t < ntiles ? t : -1;
 }
 
+// Grid indices (i, j, k) of point index idx (x fastest): 32-bit divisions
+// while idx fits, which is every grid below 2^31 points.
+__device__ inline void grid_ijk(long long idx, int nx, int ny, int &i, int &j, int &k) {
+    if (idx < (1LL << 31)) {
+        const unsigned u = (unsigned)idx, q = u / (unsigned)nx;
+        i = (int)(u - q * (unsigned)nx);
+        j = (int)(q % (unsigned)ny);
+        k = (int)(q / (unsigned)ny);
+    } else {
+        const long long q = idx / nx;
+        i = (int)(idx - q * nx);
+        j = (int)(q % ny);
+        k = (int)(q / ny);
+    }
+}
+
 // A molecule's view from a device array at a workgroup-uniform index, copied
 // word by word into uniform registers: read through the pointer, every field
 // would be a vector load (the kernels' stores might alias it) and hold VGPRs.
