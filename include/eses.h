@@ -252,6 +252,23 @@ eses_status eses_get_kernel_times(const eses_candidates *c, eses_kernel_times *o
  * HIP call failed. */
 eses_status eses_trim_cache(void);
 
+/* Device workspace from the caller (e.g. a framework's caching allocator).
+ * With both functions set (process-wide), the library takes every workspace
+ * block from alloc(bytes, stream, ctx) -- NULL means no memory
+ * (ESES_ENOMEM) -- and hands it back with release(ptr, stream, ctx), instead
+ * of using its own cache.  `stream` is the stream the block is used on (the
+ * caller's stream; for a batch's per-molecule temporaries, one of the
+ * library's worker streams, which follow the caller's stream); release is
+ * stream-ordered: work already queued on `stream` may still use the block,
+ * as with hipFreeAsync, so the allocator must not hand it to other work
+ * before that stream's queued work completes.  Both may be called from the
+ * library's worker threads.  NULL functions restore the cache; blocks taken
+ * before a change go back where they came from.  Call it while no library
+ * work is being set up on another thread. */
+typedef void *(*eses_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*eses_release_fn)(void *ptr, void *stream, void *ctx);
+void eses_set_allocator(eses_alloc_fn alloc, eses_release_fn release, void *ctx);
+
 /* Releases the handle; its device workspace returns to the cache of the
  * stream it was built on (eses_trim_cache frees it).  NULL is ignored. */
 void eses_free_candidates(eses_candidates *c);

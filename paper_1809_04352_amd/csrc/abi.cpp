@@ -71,6 +71,20 @@ BlockCache &block_cache() {
     return *c;
 }
 
+// The caller's allocator (eses_set_allocator), when set: workspace blocks come
+// from it and go back to it instead of the cache.
+struct ExtAlloc {
+    std::mutex mu;
+    eses_alloc_fn alloc = nullptr;
+    eses_release_fn release = nullptr;
+    void *ctx = nullptr;
+};
+
+ExtAlloc &ext_alloc() {
+    static ExtAlloc *a = new ExtAlloc();
+    return *a;
+}
+
 int size_class(size_t bytes) {
     int c = 8;  // 256 B
     while (((size_t)1 << c) < bytes) ++c;
@@ -85,7 +99,9 @@ int size_class(size_t bytes) {
 struct Arena {
     struct Block {
         void *p;
-        int dev, cls;
+        int dev, cls;                 // cls < 0: from the caller's allocator
+        eses_release_fn release;      // (with its context)
+        void *ctx;
     };
     std::vector<Block> blocks;
     hipStream_t st = nullptr;   // stream the blocks are used on (new blocks allocated on it)
@@ -97,9 +113,31 @@ struct Arena {
     template <typename T>
     eses_status alloc(T **p, long long count) {
         const size_t bytes = sizeof(T) * (size_t)(count > 0 ? count : 1);
-        const int cls = size_class(bytes);
         int dev = 0;
         (void)hipGetDevice(&dev);
+        {
+            eses_alloc_fn fa;
+            eses_release_fn fr;
+            void *ctx;
+            {
+                ExtAlloc &ea = ext_alloc();
+                std::lock_guard<std::mutex> lock(ea.mu);
+                fa = ea.alloc;
+                fr = ea.release;
+                ctx = ea.ctx;
+            }
+            if (fa) {
+                void *q = fa(bytes, (void *)cache(), ctx);
+                if (!q) {
+                    set_err("the caller's allocator returned no memory for %zu bytes", bytes);
+                    return ESES_ENOMEM;
+                }
+                blocks.push_back({q, dev, -1, fr, ctx});
+                *p = (T *)q;
+                return ESES_OK;
+            }
+        }
+        const int cls = size_class(bytes);
         void *q = nullptr;
         {
             BlockCache &bc = block_cache();
@@ -119,17 +157,19 @@ struct Arena {
                 return ESES_ENOMEM;
             }
         }
-        blocks.push_back({q, dev, cls});
+        blocks.push_back({q, dev, cls, nullptr, nullptr});
         *p = (T *)q;
         return ESES_OK;
     }
 
     void release() {
         if (blocks.empty()) return;
+        for (const Block &b : blocks)
+            if (b.cls < 0 && b.release) b.release(b.p, (void *)cache(), b.ctx);
         BlockCache &bc = block_cache();
         std::lock_guard<std::mutex> lock(bc.mu);
         for (const Block &b : blocks)
-            bc.free[std::make_tuple(b.dev, cache(), b.cls)].push_back(b.p);
+            if (b.cls >= 0) bc.free[std::make_tuple(b.dev, cache(), b.cls)].push_back(b.p);
         blocks.clear();
     }
 };
@@ -1232,6 +1272,15 @@ eses_status eses_edge_work(eses_candidates *c, const uint8_t *const *labels,
         o.cone_tests = (int64_t)h[15];
     }
     return ESES_OK;
+}
+
+void eses_set_allocator(eses_alloc_fn alloc, eses_release_fn release, void *ctx) {
+    ExtAlloc &ea = ext_alloc();
+    std::lock_guard<std::mutex> lock(ea.mu);
+    const bool on = alloc && release;
+    ea.alloc = on ? alloc : nullptr;
+    ea.release = on ? release : nullptr;
+    ea.ctx = on ? ctx : nullptr;
 }
 
 eses_status eses_trim_cache(void) {

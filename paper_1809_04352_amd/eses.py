@@ -29,8 +29,12 @@ EXPORTED = [
     "eses_bbox_from_atoms", "eses_grid_dims", "eses_build_candidates", "eses_candidates_info",
     "eses_copy_vertices", "eses_classify", "eses_edge_intersections", "eses_free_candidates",
     "eses_last_error", "eses_version", "eses_edge_work", "eses_set_timing",
-    "eses_get_kernel_times", "eses_trim_cache",
+    "eses_get_kernel_times", "eses_trim_cache", "eses_set_allocator",
 ]
+
+# C types of the caller-allocator hook (eses_set_allocator).
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class EsesError(RuntimeError):
@@ -138,6 +142,8 @@ def load():
     lib.eses_free_candidates.argtypes = [P]
     lib.eses_edge_work.restype = st
     lib.eses_edge_work.argtypes = [P, P, ctypes.POINTER(EdgeStats), P]
+    lib.eses_set_allocator.restype = None
+    lib.eses_set_allocator.argtypes = [ALLOC_FN, RELEASE_FN, P]
     lib.eses_trim_cache.restype = st
     lib.eses_trim_cache.argtypes = []
     lib.eses_set_timing.restype = None
@@ -319,6 +325,26 @@ def set_timing(enable: bool):
 def trim_cache():
     """Free the library's cached device workspace (synchronises)."""
     _check(load().eses_trim_cache())
+
+
+_allocator = None  # the callbacks given to the library (kept alive while set)
+
+
+def set_allocator(alloc=None, release=None):
+    """Route the library's device workspace through alloc(bytes, stream) ->
+    int pointer (0 for none) and release(ptr, stream); no arguments restore
+    the library's own cache.  The callbacks may run on the library's worker
+    threads."""
+    global _allocator
+    lib = load()
+    if alloc is None or release is None:
+        lib.eses_set_allocator(ALLOC_FN(), RELEASE_FN(), None)
+        _allocator = None
+        return
+    fa = ALLOC_FN(lambda n, st, ctx: alloc(int(n), st or 0) or None)
+    fr = RELEASE_FN(lambda p, st, ctx: release(p or 0, st or 0))
+    lib.eses_set_allocator(fa, fr, None)
+    _allocator = (fa, fr)
 
 
 def kernel_times(cand: Candidates) -> dict:

@@ -260,3 +260,58 @@ def test_tile_pool_overflow(E, oracle_mod, pool):
         assert np.array_equal(a[k], b[k]), k
     o = oracle_mod.Oracle(m.centres, m.radii, m.probe)
     compare_labels(b["labels"], o.labels_grid(m.lo, m.spacing, m.dims))
+
+
+def test_caller_allocator(E):
+    """Workspace taken from the caller's allocator (torch's caching allocator
+    through eses_set_allocator) gives the same records as the library's own
+    cache, for one molecule and for a batch, and every block is handed back."""
+    import torch
+    from eses_inputs import molecule
+    live = {}
+
+    def alloc(n, stream):
+        p = torch.cuda.caching_allocator_alloc(n, stream=stream)
+        live[p] = n
+        return p
+
+    def release(p, stream):
+        assert p in live
+        del live[p]
+        torch.cuda.caching_allocator_delete(p)
+
+    ms = [molecule(n, s, 0.45) for n, s in ((150, 21), (260, 22), (90, 23))]
+
+    def run_batch():
+        mols, labs = [], []
+        for m in ms:
+            c = torch.as_tensor(m.centres, device="cuda")
+            r = torch.as_tensor(m.radii, device="cuda")
+            mols.append((E.make_molecule(c, r, m.probe, m.spacing, m.lo, m.hi), c, r))
+        cand = E.build_candidates([x[0] for x in mols])
+        dims = [E.grid_dims(x[0]) for x in mols]
+        labs = [torch.empty(d[0] * d[1] * d[2], dtype=torch.uint8, device="cuda") for d in dims]
+        E.classify(cand, 0, labs)
+        outs = [E.alloc_isect(1) for _ in ms]
+        _, counts = E.edge_intersections(cand, labs, outs)
+        outs = [E.alloc_isect(k) for k in counts]
+        E.edge_intersections(cand, labs, outs)
+        torch.cuda.synchronize()
+        cand.close()
+        return [l.cpu().numpy() for l in labs], [o.lam[:k].cpu().numpy() for o, k in zip(outs, counts)]
+
+    m = ms[0]
+    a = E.surface(m.centres, m.radii, m.probe, m.spacing, m.lo, m.hi)
+    la, ra = run_batch()
+    E.set_allocator(alloc, release)
+    try:
+        b = E.surface(m.centres, m.radii, m.probe, m.spacing, m.lo, m.hi)
+        lb, rb = run_batch()
+    finally:
+        E.set_allocator()
+    torch.cuda.synchronize()
+    for k in ("labels", "key", "lam", "normal", "patch_type", "atoms"):
+        assert np.array_equal(a[k], b[k]), k
+    for x, y in zip(la + ra, lb + rb):
+        assert np.array_equal(x, y)
+    assert not live, f"{len(live)} blocks not handed back"
