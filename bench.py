@@ -275,6 +275,7 @@ def main():
     if single:
         res["candidates"] = {k: (list(v) if isinstance(v, tuple) else v)
                              for k, v in infos[0].items()}
+    res["ses"] = ses_per_atom(mols_np, work, outs, counts)
     if args.calibrate_copy > 0:
         nbytes = args.calibrate_copy << 20
         src = torch.ones(nbytes, dtype=torch.uint8, device=dev)
@@ -286,6 +287,25 @@ def main():
     if not args.no_cpu_baseline and single:
         res["cpu_baseline"] = cpu_baseline(m0, n_cross, args.cpu_seconds)
     print(json.dumps(res))
+
+
+def ses_per_atom(mols_np, work, outs, counts):
+    """SES volume and area per atom from the timed path's own outputs (outside
+    the timed region), beside the paper's per-atom ranges (appendix table):
+    volume = inside points x h^3; area = h^2 x sum over crossings of |n_a|, the
+    normal's component along the crossing's axis a (a crossing of an axis-a
+    grid line stands for h^2 / |n_a| of surface; weighted by n_a^2, whose sum
+    over the three axes is 1, that is h^2 |n_a|)."""
+    vol = area = 0.0
+    for m, w, o, k in zip(mols_np, work, outs, counts):
+        h = m.spacing
+        vol += w["n_inside"] * h ** 3
+        if k:
+            axis = (o.key[:k] % 3).view(-1, 1)
+            area += float(o.normal[:k].gather(1, axis).abs().sum()) * h * h
+    n = sum(m.n_atoms for m in mols_np)
+    return {"volume_per_atom_A3": vol / n, "area_per_atom_A2": area / n,
+            "paper_range_volume_A3": [8.8, 9.3], "paper_range_area_A2": [2.0, 3.2]}
 
 
 def kernel_sources_digest(kernel):
