@@ -34,7 +34,9 @@
  *     slots are -1.  Atom ids are the caller's indices, ascending.
  *   - Concave probe positions are reported once per atom triple (a<b<c) and
  *     side: sign = +1 iff (p - c_a) . ((c_b - c_a) x (c_c - c_a)) > 0.  A
- *     probe touching a fourth atom is admissible (|p - c| >= s non-strict).
+ *     probe touching a fourth atom is admissible (|p - c| >= s non-strict,
+ *     tested as |p - c|^2 >= s^2 (1 - 1e-9)), so a probe touching four or
+ *     more atoms is reported by every triple of them.
  *
  * Memory and streams: every pointer inside eses_molecule, and every output
  * buffer, is DEVICE memory owned by the caller; it must stay valid until the

@@ -319,6 +319,14 @@ static int label_at(const oracle_t *o, const double x[3], ibuf_t *buf) {
 
 /* ---------------------------------------------------------------- setup */
 
+/* Relative tolerance of the admissibility test of a three-sphere point
+ * (section 1: a probe touching three or more atoms).  A probe that touches a
+ * fourth atom exactly sits at distance s_l from it in exact arithmetic, but the
+ * rounded point may land a few ulps inside that SAS ball; the test keeps points
+ * with |p - c_l|^2 >= s_l^2 (1 - VERTEX_TOL), so that every triple of a
+ * cospherical set reports the probe. */
+#define VERTEX_TOL 1e-9
+
 /* Points on three SAS spheres by trilateration in the frame e_x || c_j - c_i,
  * e_y towards c_k, e_z = e_x x e_y.  Returns 0 if the centres are collinear or
  * the spheres share no point (z^2 < 0). */
@@ -420,12 +428,14 @@ void *orc_create(int n, const double *centres, const double *radii, double rho) 
                 if (!trilaterate(o, i, j, k, pp, pm)) continue;
                 for (int sgn = 0; sgn < 2; sgn++) {
                     double *p = sgn == 0 ? pp : pm;
-                    /* in A: every atom other than i, j, k at least its SAS radius away */
+                    /* in A: every atom other than i, j, k at least its SAS radius away,
+                     * up to VERTEX_TOL (a probe touching four or more atoms stays
+                     * admissible whatever the rounding of p) */
                     int ok = 1;
                     for (int q3 = o->nstart[i]; q3 < o->nstart[i + 1] && ok; q3++) {
                         int l = o->nbr[q3];
                         if (l == j || l == k) continue;
-                        if (dist2_pt(o, l, p) < sq(o->s[l])) ok = 0;
+                        if (dist2_pt(o, l, p) < sq(o->s[l]) * (1.0 - VERTEX_TOL)) ok = 0;
                     }
                     if (!ok) continue;
                     if (nv == vcap) {

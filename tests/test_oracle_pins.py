@@ -173,6 +173,35 @@ def test_equilateral_vertex_closed_form(oracle_mod):
     assert np.all(o.labels_points(pts) == 1)
 
 
+def test_cospherical_square_every_triple(oracle_mod):
+    """Four equal atoms on a square of half-side a: the probe above (and below)
+    the centre touches all four at height sqrt(s^2 - 2 a^2), so each of the four
+    triples reports it on both sides, at that closed-form position, under any
+    rigid motion (the rounding of the point must not drop a triple)."""
+    r, a = 1.7, 1.5
+    s = r + RHO
+    base = np.array([[a, a, 0.0], [-a, a, 0.0], [-a, -a, 0.0], [a, -a, 0.0]])
+    hgt = math.sqrt(s * s - 2 * a * a)
+    triples = {t for t in itertools.combinations(range(4), 3)}
+    for seed in range(60):
+        Rm = rot(100 + seed)
+        shift = np.random.default_rng(seed).uniform(-20.0, 20.0, 3)
+        c = base @ Rm.T + shift
+        o = oracle_mod.Oracle(c, [r] * 4, RHO)
+        p, atoms, sign = o.vertices()
+        assert p.shape == (8, 3)
+        got = {(tuple(int(v) for v in t), int(sg)) for t, sg in zip(atoms, sign)}
+        assert got == {(t, sg) for t in triples for sg in (1, -1)}
+        nrm = Rm @ np.array([0.0, 0.0, 1.0])
+        tops = (shift + hgt * nrm, shift - hgt * nrm)
+        for q in range(8):
+            assert min(np.linalg.norm(p[q] - t) for t in tops) < 1e-12 * (1 + np.abs(shift).max())
+        # the concave region under each probe is outside, the atoms inside
+        for top in (shift + hgt * nrm, shift - hgt * nrm):
+            pts = top + rng_ball(100, RHO * 0.999, seed)
+            assert np.all(o.labels_points(pts) == 0)
+
+
 def rng_ball(n, radius, seed):
     rng = np.random.default_rng(seed)
     v = rng.normal(size=(n, 3))
@@ -203,7 +232,10 @@ def brute_vertices(c, r, rho):
         for t in ((-qb + math.sqrt(disc)) / (2 * qa), (-qb - math.sqrt(disc)) / (2 * qa)):
             p = p0 + t * m
             others = [l for l in range(n) if l not in (i, j, k)]
-            if others and np.any(np.sum((c[others] - p) ** 2, axis=1) < s[others] ** 2):
+            # admissible up to a relative 1e-9 of s_l^2 (a probe touching a
+            # fourth atom exactly stays admissible under rounding)
+            if others and np.any(np.sum((c[others] - p) ** 2, axis=1)
+                                 < s[others] ** 2 * (1 - 1e-9)):
                 continue
             sg = 1 if (p - c[i]) @ m > 0 else -1
             out[(i, j, k, sg)] = p
@@ -253,14 +285,31 @@ def exposed_samples(c, r, rho, per_sphere):
     return np.concatenate(pts)
 
 
-@pytest.mark.parametrize("seed", [7, 8])
+def lattice(nx, ny, nz, step, seed):
+    """Equal-radius atoms on a simple cubic lattice, rigidly moved by seed
+    (seed 0: axis-aligned, unmoved).  Every lattice square is a cospherical
+    quadruple: the probe above its centre touches four atoms."""
+    g = np.array([[i, j, k] for k in range(nz) for j in range(ny) for i in range(nx)], float)
+    c = g * step
+    if seed:
+        c = c @ rot(200 + seed).T + np.random.default_rng(seed).uniform(-5.0, 5.0, 3)
+    return c, np.full(len(c), 1.7)
+
+
+@pytest.mark.parametrize("seed", [7, 8, "lattice"])
 def test_distance_brute_force(oracle_mod, seed):
     """dist(x, A) from the oracle against the nearest of ~1e6 admissible
     points sampled on the exposed parts of the SAS spheres (the boundary of
     A): the sample set lies in A, so the oracle may never exceed it, and it
-    is dense, so the oracle may not fall below it by more than its spacing."""
+    is dense, so the oracle may not fall below it by more than its spacing.
+    The lattice case is a 3x3 slab of equal atoms at 3.0 A, whose concave
+    probes each touch four atoms."""
     from eses_inputs import globule
-    c, r = globule(10, seed)
+    if seed == "lattice":
+        c, r = lattice(3, 3, 1, 3.0, 3)
+        seed = 9
+    else:
+        c, r = globule(10, seed)
     s = r + RHO
     samp = exposed_samples(c, r, RHO, 120000)
     tree = cKDTree(samp)
