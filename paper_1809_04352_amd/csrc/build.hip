@@ -482,6 +482,12 @@ constexpr int VX_NBR = 128;  // neighbours (and circles) of atom i staged in LDS
 
 // Atom i's neighbours (cover order with (r + rho)^2, ascending order with the
 // atom records) and i's circles, staged for the wavefronts of its workgroup.
+// Admissibility of a three-sphere point p (section 1): kept when every other
+// atom has |p - c_l|^2 >= s_l^2 (1 - VERTEX_TOL).  A probe that touches four
+// or more atoms exactly is then reported by every triple of them, whatever the
+// rounding of p.
+constexpr double VERTEX_TOL = 1e-9;
+
 struct VxLds {
     double4 nat[VX_NBR];
     double4 natasc[VX_NBR];
@@ -546,7 +552,7 @@ __device__ inline void vertex_pair(const Mol &m, bool act, double4 oR, double4 n
         } else {
             l = m.nbr_cov[nb + q2];
             double4 a = m.atom[l];
-            al = make_double4(a.x, a.y, a.z, sq(a.w + m.rho));
+            al = make_double4(a.x, a.y, a.z, sq(a.w + m.rho) * (1.0 - VERTEX_TOL));
         }
         if (l == j || l == k) continue;
         double d0 = sq(v0[0] - al.x) + sq(v0[1] - al.y) + sq(v0[2] - al.z);
@@ -663,7 +669,7 @@ __global__ void __launch_bounds__(VX_WAVES *WAVE) k_vertex(Mol m, int *vcnt, Ver
     for (int q = threadIdx.x; q < nst; q += VX_WAVES * WAVE) {
         const int l = m.nbr_cov[nb + q];
         const double4 al = m.atom[l];
-        L.nat[q] = make_double4(al.x, al.y, al.z, sq(al.w + m.rho));
+        L.nat[q] = make_double4(al.x, al.y, al.z, sq(al.w + m.rho) * (1.0 - VERTEX_TOL));
         L.nid[q] = l;
         const int k = m.nbr[nb + q];
         L.nasc[q] = k;

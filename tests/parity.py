@@ -24,6 +24,58 @@ def compare_labels(gpu_labels, oracle_labels):
     assert diff.size == 0, f"{diff.size} labels differ, first at flat index {diff[:5]}"
 
 
+def crossing_points(res, lo, h, dims):
+    """The crossing position of every record (key = 3 * point + axis; the
+    crossing is at lambda * s + (1 - lambda) * (s + h e_axis))."""
+    key = res["key"]
+    nx, ny, _ = dims
+    axis = key % 3
+    idx = key // 3
+    p = np.stack([lo[0] + (idx % nx) * h, lo[1] + ((idx // nx) % ny) * h,
+                  lo[2] + (idx // (nx * ny)) * h], axis=1)
+    p[np.arange(len(key)), axis] += (1 - res["lam"]) * h
+    return p
+
+
+def surface_residual(oracle, ptype, atoms, x):
+    """| distance from x to the claimed patch's whole surface - its radius |:
+    the atom's sphere (type 1), the torus swept by the probe around the pair's
+    circle (type 2), the nearer probe sphere of the triple (type 3).  Also
+    returns the probe centre used for type 3 (nan elsewhere)."""
+    c, r, rho = oracle.c, oracle.r, oracle.probe
+    s = r + rho
+    out = np.full(len(x), np.inf)
+    probe = np.full((len(x), 3), np.nan)
+    t1 = ptype == 1
+    out[t1] = np.abs(np.linalg.norm(x[t1] - c[atoms[t1, 0]], axis=1) - r[atoms[t1, 0]])
+    t2 = np.flatnonzero(ptype == 2)
+    if t2.size:
+        a, b = atoms[t2, 0], atoms[t2, 1]
+        v = c[b] - c[a]
+        d = np.linalg.norm(v, axis=1)
+        n = v / d[:, None]
+        t = (s[a] ** 2 - s[b] ** 2 + d ** 2) / (2 * d)
+        R = np.sqrt(np.maximum(s[a] ** 2 - t ** 2, 0.0))
+        w = x[t2] - (c[a] + t[:, None] * n)
+        along = np.sum(w * n, axis=1)
+        perp = np.linalg.norm(w - along[:, None] * n, axis=1)
+        out[t2] = np.abs(np.hypot(perp - R, along) - rho)
+    t3 = np.flatnonzero(ptype == 3)
+    if t3.size:
+        pv, av, _ = oracle.vertices()
+        by = {}
+        for q, tr in enumerate(av):
+            by.setdefault(tuple(int(v) for v in tr), []).append(pv[q])
+        for m in t3:
+            best = np.inf
+            for pp in by.get(tuple(int(v) for v in atoms[m]), []):
+                e = abs(np.linalg.norm(x[m] - pp) - rho)
+                if e < best:
+                    best, probe[m] = e, pp
+            out[m] = best
+    return out, probe
+
+
 def cusp_mask(res, centres, lo, h, dims, tol=1e-6):
     """Saddle crossings on (or within tol of) the axis through their two atoms:
     there every circle point is equally near, so the normal is not unique."""
@@ -64,9 +116,24 @@ def compare_edges(res, oracle, lo, h, dims, ref_labels=None):
     assert dpos.max(initial=0.0) < POS_TOL, dpos.max()
     dn = np.abs(rec["normal"] - res["normal"]).max(axis=1) if len(key) else np.zeros(0)
     tag_same = (rec["type"] == res["patch_type"]) & np.all(rec["atoms"] == res["atoms"], axis=1)
-    # where the owner differs, two surfaces meet at the crossing: both records
-    # must still describe the same point
-    assert tag_same.mean() > 0.999 if len(key) else True
+    # where the owner differs, two surfaces meet at the crossing or coincide:
+    # the point is compared above, and the HIP path's owner must pass through it
+    diff = np.flatnonzero(~tag_same)
+    if diff.size:
+        x = crossing_points(res, lo, h, dims)[diff]
+        resid, probe = surface_residual(oracle, res["patch_type"][diff], res["atoms"][diff], x)
+        assert resid.max() < POS_TOL, resid.max()
+        # a probe touching four or more atoms is one sphere reported by several
+        # triples, so which triple owns its patch is not unique, and neither is
+        # the owner on a seam where two patches meet tangentially (the normals
+        # agree there); a disagreement with differing normals (a crease or a
+        # cusp) has measure zero
+        _, probe_o = surface_residual(oracle, rec["type"][diff], rec["atoms"][diff], x)
+        same_sphere = ((res["patch_type"][diff] == 3) & (rec["type"][diff] == 3)
+                       & (np.abs(probe - probe_o).max(axis=1) < 1e-9))
+        assert dn[diff[same_sphere]].max(initial=0.0) < NORMAL_TOL
+        odd = ~same_sphere & (dn[diff] >= NORMAL_TOL)
+        assert odd.sum() <= 1e-3 * len(key), (odd.sum(), (~same_sphere).sum(), len(key))
     unique = tag_same & ~cusp_mask(res, oracle.c, lo, h, dims)
     assert dn[unique].max(initial=0.0) < NORMAL_TOL, dn[unique].max(initial=0.0)
     assert np.all(np.abs(np.linalg.norm(res["normal"], axis=1) - 1) < 1e-12)

@@ -89,6 +89,30 @@ def test_sparse_atoms_far_apart(E, oracle_mod):
     run_and_compare(E, oracle_mod, c, r, RHO, 0.4, lo, hi, 0)
 
 
+@pytest.mark.parametrize("motion,prec", [(0, 0), (1, 0), (1, 1), (2, 0)])
+def test_cospherical_lattice(E, oracle_mod, motion, prec):
+    """Equal atoms (r 1.7 A) on a 4x4x3 simple cubic lattice at 3.0 A: every
+    lattice square is a cospherical quadruple whose probe touches four atoms
+    and is reported by all four triples on both sides.  Motion 0 keeps the
+    lattice on the grid's axes (circle axes along grid lines), the others
+    move it rigidly."""
+    from eses_inputs import bbox_from_atoms
+    g = np.array([[i, j, k] for k in range(3) for j in range(4) for i in range(4)], float)
+    c = g * 3.0
+    if motion:
+        rng = np.random.default_rng(motion)
+        q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+        c = c @ q.T + rng.uniform(-5.0, 5.0, 3)
+    r = np.full(len(c), 1.7)
+    lo, hi = bbox_from_atoms(c, r, 3.0)
+    if motion == 0:
+        lo = np.floor(lo)  # whole angstroms: grid points on the lattice planes
+    res, nv, ne = run_and_compare(E, oracle_mod, c, r, RHO, 0.25, lo, hi, prec)
+    # 42 lattice squares on the outer faces, four triples each, outer side only
+    assert nv == 168
+    assert ne > 1000
+
+
 def test_capacity_and_counts(E, oracle_mod):
     import torch
     from eses_inputs import molecule
