@@ -61,7 +61,7 @@ extern "C" {
 
 typedef enum {
     ESES_OK = 0,
-    ESES_EINVAL = -1,     /* bad argument: null, non-finite, n <= 0, dims < 2 ... */
+    ESES_EINVAL = -1,     /* bad argument: null, non-finite, n <= 0, dims < 2, shared centres ... */
     ESES_ENOMEM = -2,     /* device allocation failed; message holds the bytes */
     ESES_ECAPACITY = -3,  /* output capacity too small; required count returned */
     ESES_EDEVICE = -4,    /* a HIP runtime call failed */
@@ -77,7 +77,9 @@ typedef enum {
 } eses_precision;
 
 /* One molecule: the paper's problem statement (eq. 1, probe radius, grid
- * spacing, box).  centres: device, [n_atoms][3] float64, angstrom.
+ * spacing, box).  centres: device, [n_atoms][3] float64, angstrom, pairwise
+ * distinct (atoms are distinct balls: two atoms with the same centre make
+ * eses_build_candidates return ESES_EINVAL).
  * radii: device, [n_atoms] float64, finite and > 0.  probe_radius and spacing
  * finite and > 0.  bbox_lo/bbox_hi: host values; grid point (0,0,0) = bbox_lo
  * and dims = ceil((hi - lo) / h) + 1 >= 2 per axis. */

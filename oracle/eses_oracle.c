@@ -405,6 +405,13 @@ void *orc_create(int n, const double *centres, const double *radii, double rho) 
         query_cells(o, o->cstart, o->catom, x, 2.0 * o->smax, &buf);
         for (int q = 0; q < buf.n; q++) {
             int j = buf.idx[q];
+            if (j != i && dist2_pt(o, j, x) == 0.0) {
+                /* two atoms share a centre: rejected (atoms are distinct balls) */
+                free(buf.idx);
+                free(all.idx);
+                orc_destroy(o);
+                return NULL;
+            }
             if (j != i && dist2_pt(o, j, x) < sq(o->s[i] + o->s[j])) ibuf_push(&all, j);
         }
         o->nstart[i + 1] = all.n;

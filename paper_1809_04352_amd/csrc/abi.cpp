@@ -506,8 +506,13 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, int 
         int *outs[2] = {m.nbr_off, m.circ_off};
         CK(scan_i32_multi(ins, m.n, outs, 2, tmp, st));
     }
-    int tot[2];
-    CKS(d2h_ints({{&tot[0], m.nbr_off + m.n}, {&tot[1], m.circ_off + m.n}}, st));
+    int tot[3];
+    CKS(d2h_ints({{&tot[0], m.nbr_off + m.n}, {&tot[1], m.circ_off + m.n}, {&tot[2], m.diag + 2}},
+                 st));
+    if (tot[2]) {
+        set_err("atom centres must be pairwise distinct (two atoms share a centre)");
+        return ESES_EINVAL;
+    }
     m.ncirc = tot[1];
     CKS(A.alloc(&m.nbr, tot[0]));
     CKS(A.alloc(&m.nbr_cov, tot[0]));

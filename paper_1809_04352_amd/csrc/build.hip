@@ -372,6 +372,7 @@ __global__ void __launch_bounds__(NB_WAVES *WAVE) k_nbr(Mol m, int *nbr_cnt, int
             double dx = ak.x - ai.x, dy = ak.y - ai.y, dz = ak.z - ai.z;
             double d2 = dx * dx + dy * dy + dz * dz;
             nb = d2 < sq(si + sk + LIST_SLACK);
+            if (!FILL && d2 == 0.0) atomicAdd(&m.diag[2], 1);  // coincident centres: rejected
             if (nb) {
                 if (sqrt(d2) + si < sk) contained = true;
                 if (pair_circle(ai, ak, m.rho, oR, n)) {

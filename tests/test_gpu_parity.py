@@ -148,6 +148,26 @@ def test_invalid_device_input(E):
     assert ei.value.status == E.ESES_EINVAL
 
 
+@pytest.mark.parametrize("radii", [(1.5, 1.5), (1.7, 1.2)])
+def test_coincident_centres_rejected(E, oracle_mod, radii):
+    """Two atoms sharing a centre (a duplicate or a concentric pair) are
+    rejected by both the library and the oracle; a valid molecule built right
+    after still matches the oracle."""
+    import torch
+    c = np.array([[0.0, 0.0, 0.0], [3.0, 0.5, 0.2], [0.0, 0.0, 0.0]])
+    r = np.array([radii[0], 1.5, radii[1]])
+    mol = E.make_molecule(torch.as_tensor(c, device="cuda"), torch.as_tensor(r, device="cuda"),
+                          RHO, 0.5, [-5, -5, -5], [7, 5, 5])
+    with pytest.raises(E.EsesError) as ei:
+        E.build_candidates([mol])
+    assert ei.value.status == E.ESES_EINVAL
+    assert "distinct" in str(ei.value)
+    with pytest.raises(ValueError):
+        oracle_mod.Oracle(c, r, RHO)
+    lo, hi = np.array([-5.0, -5.0, -5.0]), np.array([7.0, 5.0, 5.0])
+    run_and_compare(E, oracle_mod, c[:2], r[:2], RHO, 0.25, lo, hi, 0)
+
+
 def test_repeat_is_deterministic(E):
     from eses_inputs import molecule
     m = molecule(150, 12, 0.4)

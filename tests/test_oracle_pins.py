@@ -285,6 +285,16 @@ def exposed_samples(c, r, rho, per_sphere):
     return np.concatenate(pts)
 
 
+def test_coincident_centres_rejected(oracle_mod):
+    """Atoms are distinct balls: two atoms sharing a centre (duplicate or
+    concentric) are rejected rather than given a rounding-dependent surface."""
+    c = np.array([[0.0, 0.0, 0.0], [3.0, 0.5, 0.2], [0.0, 0.0, 0.0]])
+    for r in ([1.7, 1.5, 1.7], [1.7, 1.5, 1.2]):
+        with pytest.raises(ValueError):
+            oracle_mod.Oracle(c, r, RHO)
+    oracle_mod.Oracle(c[:2], [1.7, 1.5], RHO)
+
+
 def lattice(nx, ny, nz, step, seed):
     """Equal-radius atoms on a simple cubic lattice, rigidly moved by seed
     (seed 0: axis-aligned, unmoved).  Every lattice square is a cospherical
