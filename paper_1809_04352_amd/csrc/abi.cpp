@@ -756,13 +756,13 @@ eses_status edges_prepare(eses_candidates *c, size_t q, const uint8_t *lab,
     }
     const long long nw = P.nw = std::min<long long>(P.total, o.capacity);
     EdgeJob &J = P.job;
-    int *tcount = nullptr, *ccount = nullptr, *coff = nullptr, *tfill = nullptr,
+    int *tcount = nullptr, *ccount = nullptr, *coff = nullptr, *rank = nullptr,
         *order = nullptr, *units = nullptr, *ttmp = nullptr, *fb = nullptr, *nfb = nullptr;
     if (e == hipSuccess && nw > 0) {
         if ((s = T.alloc(&tcount, m.ntiles + 1)) != ESES_OK ||
             (s = T.alloc(&ccount, m.ntiles + 1)) != ESES_OK ||
             (s = T.alloc(&coff, m.ntiles + 1)) != ESES_OK ||
-            (s = T.alloc(&tfill, m.ntiles + 1)) != ESES_OK ||
+            (s = T.alloc(&rank, nw)) != ESES_OK ||
             (s = T.alloc(&order, edge_order_capacity(m, nw))) != ESES_OK ||
             (s = T.alloc(&units, edge_units_capacity(m))) != ESES_OK ||
             (s = T.alloc(&fb, nw)) != ESES_OK || (s = T.alloc(&nfb, 1)) != ESES_OK ||
@@ -770,11 +770,12 @@ eses_status edges_prepare(eses_candidates *c, size_t q, const uint8_t *lab,
             return s;
     }
     if (e == hipSuccess && nw > 0)
-        e = launch_edge_detect_write(lab, m, boff, o.capacity, (long long *)o.key, tcount, st);
+        e = launch_edge_detect_write(lab, m, boff, o.capacity, (long long *)o.key, tcount, rank,
+                                     st);
     if (e == hipSuccess) e = fill_i32(P.ovf, 1, 0, st);
     if (e == hipSuccess && nw > 0 && batch) e = fill_i32(nfb, 1, 0, st);  // fused launch
     if (e == hipSuccess && nw > 0)
-        e = launch_edge_group(m, (const long long *)o.key, nw, tcount, ccount, coff, tfill,
+        e = launch_edge_group(m, (const long long *)o.key, nw, tcount, ccount, coff, rank,
                               order, units, ttmp, st);
     if (e == hipSuccess && timed) e = hipEventRecord(c->ev[3], st);
     if (e != hipSuccess) {
@@ -1231,13 +1232,13 @@ eses_status eses_edge_work(eses_candidates *c, const uint8_t *const *labels,
         if (e == hipSuccess) e = hipMemcpyAsync(&total, boff + nblk, sizeof(long long), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         long long *keys = nullptr;
-        int *tcount = nullptr, *ccount = nullptr, *coff = nullptr, *tfill = nullptr,
+        int *tcount = nullptr, *ccount = nullptr, *coff = nullptr, *rank = nullptr,
             *order = nullptr, *units = nullptr, *ttmp = nullptr, *fb = nullptr, *nfb = nullptr;
         if (e == hipSuccess && total > 0) {
             if ((s = T.alloc(&keys, total)) != ESES_OK || (s = T.alloc(&tcount, m.ntiles + 1)) != ESES_OK ||
                 (s = T.alloc(&ccount, m.ntiles + 1)) != ESES_OK ||
                 (s = T.alloc(&coff, m.ntiles + 1)) != ESES_OK ||
-                (s = T.alloc(&tfill, m.ntiles + 1)) != ESES_OK ||
+                (s = T.alloc(&rank, total)) != ESES_OK ||
                 (s = T.alloc(&order, edge_order_capacity(m, total))) != ESES_OK ||
                 (s = T.alloc(&units, edge_units_capacity(m))) != ESES_OK ||
                 (s = T.alloc(&fb, total)) != ESES_OK || (s = T.alloc(&nfb, 1)) != ESES_OK ||
@@ -1249,9 +1250,9 @@ eses_status eses_edge_work(eses_candidates *c, const uint8_t *const *labels,
         if (e == hipSuccess) e = fill_u32((uint32_t *)work, 2 * EDGE_WORK_COUNTERS, 0u, st);
         if (e == hipSuccess) e = fill_i32(ovf, 1, 0, st);
         if (e == hipSuccess && total > 0)
-            e = launch_edge_detect_write(labels[q], m, boff, total, keys, tcount, st);
+            e = launch_edge_detect_write(labels[q], m, boff, total, keys, tcount, rank, st);
         if (e == hipSuccess && total > 0)
-            e = launch_edge_group(m, keys, total, tcount, ccount, coff, tfill, order, units, ttmp,
+            e = launch_edge_group(m, keys, total, tcount, ccount, coff, rank, order, units, ttmp,
                                   st);
         if (e == hipSuccess && total > 0)
             e = launch_edge_work(m, labels[q], keys, total, order, tcount, coff, units, fb, nfb, ovf,

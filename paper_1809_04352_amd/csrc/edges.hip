@@ -141,12 +141,16 @@ __global__ void __launch_bounds__(EDGE_BLOCK) k_edge_count(const uint8_t *L, int
     if (threadIdx.x == 0) bcount[blockIdx.x] = tot;
 }
 
-// Also tallies the written edges per owning tile (tcount, zeroed before).
+// Also tallies the written edges per owning tile (tcount, zeroed before) and
+// keeps each edge's rank among its tile's edges (rank[w]), so that grouping by
+// tile needs no further atomics.  A thread takes one tally per run of its
+// points in one tile; the runs of a tile's rows then meet its counter in lane
+// order, which keeps the ranks close to key order (chunks of nearby edges).
 __global__ void __launch_bounds__(EDGE_BLOCK) k_edge_write(const uint8_t *L, int nx, int ny,
                                                            int nz, long long npts,
                                                            const long long *boff, long long cap,
-                                                           long long *keys, int *tcount, int T,
-                                                           int tdx, int tdy) {
+                                                           long long *keys, int *tcount,
+                                                           int *rank, int T, int tdx, int tdy) {
     __shared__ int lds[EDGE_BLOCK / WAVE + 1];
     const long long idx0 = ((long long)blockIdx.x * EDGE_BLOCK + threadIdx.x) * EDGE_PPT;
     const bool words = ((uintptr_t)L & 7) == 0;
@@ -166,9 +170,13 @@ __global__ void __launch_bounds__(EDGE_BLOCK) k_edge_write(const uint8_t *L, int
     }
     int tot;
     long long w = boff[blockIdx.x] + block_excl_scan<int, EDGE_BLOCK>(c, lds, &tot);
+    // the written edges of a run of points in one tile are consecutive in w
+    int trun = -1, nrun = 0;
+    long long wrun = 0;
 #pragma unroll
     for (int q = 0; q < EDGE_PPT; ++q) {
         int nwr = 0;
+        const long long w0 = w;
         for (int a = 0; a < 3; ++a)
             if (fl[q] & (1 << a)) {
                 if (w < cap) {
@@ -177,7 +185,22 @@ __global__ void __launch_bounds__(EDGE_BLOCK) k_edge_write(const uint8_t *L, int
                 }
                 ++w;
             }
-        if (nwr) atomicAdd(&tcount[tl[q]], nwr);
+        if (nwr) {
+            if (tl[q] != trun) {
+                if (nrun) {
+                    const int r0 = atomicAdd(&tcount[trun], nrun);
+                    for (int e = 0; e < nrun; ++e) rank[wrun + e] = r0 + e;
+                }
+                trun = tl[q];
+                wrun = w0;
+                nrun = 0;
+            }
+            nrun += nwr;
+        }
+    }
+    if (nrun) {
+        const int r0 = atomicAdd(&tcount[trun], nrun);
+        for (int e = 0; e < nrun; ++e) rank[wrun + e] = r0 + e;
     }
 }
 
@@ -1851,11 +1874,11 @@ __global__ void __launch_bounds__(256) k_edge_unit_order(const int *ccount, int 
 }
 
 __global__ void k_edge_tile_scatter(Mol m, const long long *keys, long long count,
-                                    const int *coff, int *tfill, int *order) {
+                                    const int *coff, const int *rank, int *order) {
     long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (q >= count) return;
     int t = edge_tile(m, keys[q]);
-    order[(long long)coff[t] * CH_EDGES + atomicAdd(&tfill[t], 1)] = (int)q;
+    order[(long long)coff[t] * CH_EDGES + rank[q]] = (int)q;
 }
 
 long long edge_order_capacity(const Mol &m, long long count) {
@@ -1865,20 +1888,19 @@ long long edge_order_capacity(const Mol &m, long long count) {
 long long edge_units_capacity(const Mol &m) { return EU_LIST + (long long)m.ntiles; }
 
 hipError_t launch_edge_group(const Mol &m, const long long *keys, long long count, int *tcount,
-                             int *ccount, int *coff, int *tfill, int *order, int *units,
+                             int *ccount, int *coff, const int *rank, int *order, int *units,
                              int *tmp, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     unsigned nb = (unsigned)((count + 255) / 256);
     const unsigned tb = (unsigned)((m.ntiles + 255) / 256);
-    hipError_t e = fill_i32(tfill, m.ntiles + 1, 0, st);
-    if (e == hipSuccess) e = fill_i32(units, EU_LIST, 0, st);
+    hipError_t e = fill_i32(units, EU_LIST, 0, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_edge_chunk_count, dim3(tb), dim3(256), 0, st, tcount, m.ntiles, ccount,
                        units);
     e = scan_i32(ccount, m.ntiles, coff, tmp, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_edge_tile_scatter, dim3(nb), dim3(256), 0, st, m, keys, count, coff,
-                       tfill, order);
+                       rank, order);
     hipLaunchKernelGGL(k_edge_unit_order, dim3(tb), dim3(256), 0, st, ccount, m.ntiles, units);
     return hipGetLastError();
 }
@@ -1898,12 +1920,13 @@ hipError_t launch_edge_detect_count(const uint8_t *L, const Mol &m, int *bcount,
 }
 
 hipError_t launch_edge_detect_write(const uint8_t *L, const Mol &m, const long long *boff,
-                                    long long cap, long long *keys, int *tcount, hipStream_t st) {
+                                    long long cap, long long *keys, int *tcount, int *rank,
+                                    hipStream_t st) {
     hipError_t e = fill_i32(tcount, m.ntiles + 1, 0, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_edge_write, dim3((unsigned)edge_detect_blocks(m)), dim3(EDGE_BLOCK), 0, st,
-                       L, m.dims[0], m.dims[1], m.dims[2], m.npts, boff, cap, keys, tcount, m.tile,
-                       m.tdims[0], m.tdims[1]);
+                       L, m.dims[0], m.dims[1], m.dims[2], m.npts, boff, cap, keys, tcount, rank,
+                       m.tile, m.tdims[0], m.tdims[1]);
     return hipGetLastError();
 }
 

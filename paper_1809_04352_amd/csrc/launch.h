@@ -91,9 +91,12 @@ hipError_t launch_count_inside(const uint8_t *labels, long long n, unsigned long
 long long edge_detect_blocks(const Mol &m);
 hipError_t launch_edge_detect_count(const uint8_t *L, const Mol &m, int *bcount, long long *nblk,
                                     hipStream_t st);
+// keys: the first cap crossing edges; tcount: per-tile counts of them; rank:
+// each edge's rank within its tile (cap ints).
 hipError_t launch_edge_detect_write(const uint8_t *L, const Mol &m, const long long *boff,
-                                    long long cap, long long *keys, int *tcount, hipStream_t st);
-// Crossing edges grouped by tile (tcount: per-tile counts from the key pass):
+                                    long long cap, long long *keys, int *tcount, int *rank,
+                                    hipStream_t st);
+// Crossing edges grouped by tile (tcount, rank: from the key pass):
 // order[] holds, per tile, its edges padded
 // to a multiple of the chunk size (edge_order_capacity entries); coff[t] is
 // the tile's first chunk and coff[ntiles] the number of chunks.  units
@@ -106,7 +109,7 @@ constexpr int EU_CLASS = 0, EU_FILL = 8, EU_QUEUE = 16, EU_COUNT = 24, EU_LIST =
 long long edge_order_capacity(const Mol &m, long long count);
 long long edge_units_capacity(const Mol &m);
 hipError_t launch_edge_group(const Mol &m, const long long *keys, long long count, int *tcount,
-                             int *ccount, int *coff, int *tfill, int *order, int *units,
+                             int *ccount, int *coff, const int *rank, int *order, int *units,
                              int *tmp, hipStream_t st);
 // fallback: count ints; nfallback, overflow: one int each (overflow is set,
 // not cleared).
