@@ -500,10 +500,10 @@ __global__ void __launch_bounds__(CLS_THREADS) k_classify_batch(const Mol *mols,
 
 // Work units of a batch: tile cost class 0 (probe, face or circle
 // candidates), 1 (atoms only) or 2 (empty), counted then scattered by class.
-__global__ void k_unit_count(const Mol *mols, const int *tile_base, int nmols, long long total,
-                             int *cls_count) {
-    long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (g >= total) return;
+// The class of unit g (molecule, tile): 0 with faces, circles or probes in
+// its lists, 1 with atoms only, 2 empty.
+__device__ inline int unit_class(const Mol *mols, const int *tile_base, int nmols, long long g,
+                                 int &mol, int &t) {
     int lo = 0, hi = nmols - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
@@ -511,30 +511,47 @@ __global__ void k_unit_count(const Mol *mols, const int *tile_base, int nmols, l
         else hi = mid - 1;
     }
     const Mol &m = mols[lo];
-    int t = (int)(g - tile_base[lo]);
+    mol = lo;
+    t = (int)(g - tile_base[lo]);
     int heavy = (m.tF_off[t + 1] - m.tF_off[t]) + (m.tC_off[t + 1] - m.tC_off[t]) +
                 (m.tV_off[t + 1] - m.tV_off[t]);
-    int cls = heavy > 0 ? 0 : (m.tA_off[t + 1] > m.tA_off[t] ? 1 : 2);
-    atomicAdd(&cls_count[cls], 1);
+    return heavy > 0 ? 0 : (m.tA_off[t + 1] > m.tA_off[t] ? 1 : 2);
 }
 
-__global__ void k_unit_scatter(const Mol *mols, const int *tile_base, int nmols, long long total,
-                               int *cls_fill, int2 *units) {
+// Units per class: counted in LDS, one global add per class and block.
+__global__ void __launch_bounds__(256) k_unit_count(const Mol *mols, const int *tile_base,
+                                                    int nmols, long long total, int *cls_count) {
+    __shared__ int cls[3];
+    if (threadIdx.x < 3) cls[threadIdx.x] = 0;
+    __syncthreads();
     long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (g >= total) return;
-    int lo = 0, hi = nmols - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (tile_base[mid] <= g) lo = mid;
-        else hi = mid - 1;
+    if (g < total) {
+        int mol, t;
+        atomicAdd(&cls[unit_class(mols, tile_base, nmols, g, mol, t)], 1);
     }
-    const Mol &m = mols[lo];
-    int t = (int)(g - tile_base[lo]);
-    int heavy = (m.tF_off[t + 1] - m.tF_off[t]) + (m.tC_off[t + 1] - m.tC_off[t]) +
-                (m.tV_off[t + 1] - m.tV_off[t]);
-    int cls = heavy > 0 ? 0 : (m.tA_off[t + 1] > m.tA_off[t] ? 1 : 2);
-    int pos = atomicAdd(&cls_fill[cls], 1);
-    units[pos] = make_int2(lo, t);
+    __syncthreads();
+    if (threadIdx.x < 3 && cls[threadIdx.x] > 0) atomicAdd(&cls_count[threadIdx.x], cls[threadIdx.x]);
+}
+
+// The unit list, class by class: a block ranks its units per class in LDS
+// and reserves each class's run with one global add.
+__global__ void __launch_bounds__(256) k_unit_scatter(const Mol *mols, const int *tile_base,
+                                                      int nmols, long long total, int *cls_fill,
+                                                      int2 *units) {
+    __shared__ int cls[3], base[3];
+    if (threadIdx.x < 3) cls[threadIdx.x] = 0;
+    __syncthreads();
+    long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    int c = -1, r = 0, mol = 0, t = 0;
+    if (g < total) {
+        c = unit_class(mols, tile_base, nmols, g, mol, t);
+        r = atomicAdd(&cls[c], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < 3 && cls[threadIdx.x] > 0)
+        base[threadIdx.x] = atomicAdd(&cls_fill[threadIdx.x], cls[threadIdx.x]);
+    __syncthreads();
+    if (c >= 0) units[base[c] + r] = make_int2(mol, t);
 }
 
 // cls_fill[c] = first slot of class c (from the counts), head = 0.
