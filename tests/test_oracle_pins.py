@@ -173,6 +173,36 @@ def test_equilateral_vertex_closed_form(oracle_mod):
     assert np.all(o.labels_points(pts) == 1)
 
 
+def test_concave_cap_flips_at_probe_radius(oracle_mod):
+    """Three atoms and one of their probes p: inside the cone spanned from p
+    by the directions to the three centres, p is the nearest admissible point,
+    so dist(x, A) = |x - p| and the label flips exactly at |x - p| = rho along
+    every ray of the cone (the concave patch is the probe sphere there)."""
+    r, L = np.array([1.7, 1.55, 1.52]), 3.4
+    s = r + RHO
+    ang = np.array([0.0, 2.1, 4.3])
+    base = np.stack([L / math.sqrt(3) * np.cos(ang), L / math.sqrt(3) * np.sin(ang),
+                     np.array([0.0, 0.3, -0.2])], axis=1)
+    Rm = rot(11)
+    c = base @ Rm.T + np.array([-0.7, 1.3, 2.1])
+    o = oracle_mod.Oracle(c, r, RHO)
+    p, atoms, sign = o.vertices()
+    assert p.shape == (2, 3)
+    rng = np.random.default_rng(3)
+    for q in range(2):
+        pq = p[q]
+        assert np.allclose(np.linalg.norm(c - pq, axis=1), s, atol=1e-12)
+        dirs = (c - pq) / np.linalg.norm(c - pq, axis=1, keepdims=True)
+        wts = rng.dirichlet(np.ones(3), size=200)
+        u = wts @ dirs
+        u /= np.linalg.norm(u, axis=1, keepdims=True)
+        for f, want in ((1 - 1e-9, 0), (1 + 1e-9, 1)):
+            assert np.all(o.labels_points(pq + f * RHO * u) == want)
+        d, typ = o.dist_points(pq + 0.5 * RHO * u, 50.0)
+        assert np.allclose(d, 0.5 * RHO, atol=1e-12)
+        assert np.all(typ == 3)
+
+
 def test_cospherical_square_every_triple(oracle_mod):
     """Four equal atoms on a square of half-side a: the probe above (and below)
     the centre touches all four at height sqrt(s^2 - 2 a^2), so each of the four
