@@ -1,9 +1,10 @@
-"""The certified FP32 distance test of the classification (section 4 reading
-R12/R16): emulated here in float32 exactly as the kernel evaluates it (FP64
-offsets from the tile origin rounded to FP32, an FP32 difference, an FP32 sum
-of squares with or without fused multiply-adds), every decision the FP32
-interval certifies must agree with the exact comparison of |x - c|^2 with the
-threshold, also for distances placed within the bound of the threshold.  The
+"""The certified FP32 distance test of the classification (the FP32 path whose
+uncertain decisions are re-taken in FP64): emulated here in float32 exactly as
+the kernel evaluates it (FP64 offsets from the tile origin rounded to FP32, an
+FP32 difference, an FP32 sum of squares with or without fused multiply-adds),
+every decision the FP32 interval certifies must agree with the exact comparison
+of |x - c|^2 with the threshold, also for distances placed within the bound of
+the threshold.  The
 bound: E = 4.01 u lam per component, c0 = 3 E (4 lam + E), thresholds
 (t (1 -+ 2^-52) -+ c0)(1 -+ 4u) rounded outward to FP32."""
 from fractions import Fraction
