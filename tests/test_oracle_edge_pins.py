@@ -230,3 +230,77 @@ def test_spindle_axis_crossing_closed_form(oracle_mod):
     x = lo[0] + ((row // 3) % nx + 1 - rec["lam"]) * h
     want = sorted([-r, a - math.sqrt(RHO ** 2 - R ** 2), a + math.sqrt(RHO ** 2 - R ** 2), d + r])
     assert np.allclose(np.sort(x), want, atol=1e-9)
+
+
+def _grid_around(oracle_mod, o, lo, hi, h):
+    """Labels, crossing keys and edge records of the box [lo, hi] at spacing h."""
+    dims = tuple(int(math.ceil((hi[a] - lo[a]) / h)) + 1 for a in range(3))
+    L = o.labels_grid(lo, h, dims)
+    keys = oracle_mod.crossing_keys(L)
+    return L, keys, o.edges(lo, h, dims, keys), dims
+
+
+def test_two_atom_pappus_volume_and_area(oracle_mod):
+    """Two atoms with an ordinary saddle (R > rho): the SES is a solid of
+    revolution whose profile is the two van der Waals arcs joined by the lower
+    arc of the probe circle, so Pappus' theorems give its volume and its
+    convex (two spherical zones) and saddle areas by 1-D quadrature.  The
+    oracle's crossings reproduce them along every axis (lambda, normals and
+    patch tags all enter)."""
+    from scipy.integrate import quad
+    r1, r2, d = 1.7, 1.5, 3.6
+    s1, s2 = r1 + RHO, r2 + RHO
+    a = (s1 * s1 - s2 * s2 + d * d) / (2 * d)
+    R = math.sqrt(s1 * s1 - a * a)
+    assert R > RHO
+    t1, t2 = a * r1 / s1, d + (a - d) * r2 / s2  # contact points along the axis
+    root = lambda x: math.sqrt(RHO * RHO - (x - a) ** 2)
+    V = math.pi * (r1 * r1 * (t1 + r1) - (t1 ** 3 + r1 ** 3) / 3
+                   + r2 * r2 * (d + r2 - t2) - (r2 ** 3 - (t2 - d) ** 3) / 3)
+    V += quad(lambda x: math.pi * (R - root(x)) ** 2, t1, t2, epsabs=1e-13, epsrel=1e-13)[0]
+    A_convex = 2 * math.pi * (r1 * (t1 + r1) + r2 * (d + r2 - t2))
+    A_saddle = quad(lambda x: 2 * math.pi * (R - root(x)) * RHO / root(x), t1, t2,
+                    epsabs=1e-13, epsrel=1e-13)[0]
+    q, _ = np.linalg.qr(np.random.default_rng(4).normal(size=(3, 3)))
+    c = np.array([[0.0, 0.0, 0.0], [d, 0.0, 0.0]]) @ q.T + np.array([0.0123, -0.0271, 0.0191])
+    o = oracle_mod.Oracle(c, [r1, r2], RHO)
+    h = 0.1
+    lo, hi = c.min(axis=0) - 2.2, c.max(axis=0) + 2.2
+    L, keys, rec, dims = _grid_around(oracle_mod, o, lo, hi, h)
+    for axis in range(3):
+        assert abs(line_volume(L, keys, rec["lam"], h, axis) / V - 1) < 3e-3
+    w = h * h * np.abs(rec["normal"][np.arange(len(keys)), keys % 3])
+    assert abs(w[rec["type"] == 1].sum() / A_convex - 1) < 4e-3
+    assert abs(w[rec["type"] == 2].sum() / A_saddle - 1) < 4e-3
+    assert not np.any(rec["type"] == 3)
+
+
+def test_concave_cap_area_girard(oracle_mod):
+    """Three atoms whose two probes do not overlap: each concave patch is the
+    spherical triangle on its probe sphere with corners toward the three
+    centres, of area rho^2 (alpha + beta + gamma - pi) (Girard); the
+    concave-tagged crossings within rho of the probe reproduce it."""
+    from tests.parity import crossing_points
+    r = np.array([1.7, 1.55, 1.52])
+    s = r + RHO
+    q, _ = np.linalg.qr(np.random.default_rng(5).normal(size=(3, 3)))
+    c = np.array([[0.0, 0.0, 0.0], [3.5, 0.0, 0.0], [1.6, 3.1, 0.0]]) @ q.T + np.array(
+        [0.31, -0.17, 0.05])
+    o = oracle_mod.Oracle(c, r, RHO)
+    P, atoms, sign = o.vertices()
+    assert len(sign) == 2 and np.linalg.norm(P[0] - P[1]) > 2 * RHO
+    h = 0.04
+    for p in P:
+        u = (c - p) / s[:, None]
+        ang = 0.0
+        for i in range(3):
+            a, b, e = u[i], u[(i + 1) % 3], u[(i + 2) % 3]
+            t1, t2 = b - (a @ b) * a, e - (a @ e) * a
+            ang += math.acos(t1 @ t2 / (np.linalg.norm(t1) * np.linalg.norm(t2)))
+        A_cap = RHO * RHO * (ang - math.pi)
+        lo, hi = p - (RHO + 0.1), p + (RHO + 0.1)
+        L, keys, rec, dims = _grid_around(oracle_mod, o, lo, hi, h)
+        x = crossing_points({"key": keys, "lam": rec["lam"]}, lo, h, dims)
+        sel = (rec["type"] == 3) & (np.linalg.norm(x - p, axis=1) < RHO + 1e-9)
+        area = h * h * np.abs(rec["normal"][np.arange(len(keys)), keys % 3])[sel].sum()
+        assert abs(area / A_cap - 1) < 1e-2
