@@ -158,6 +158,10 @@ def test_normals_are_distance_gradients(oracle_mod):
     assert smooth.mean() > 0.95
     assert np.allclose(rec["normal"][smooth], -grad[smooth], atol=2e-4)
     assert np.allclose(np.linalg.norm(rec["normal"], axis=1), 1.0, atol=1e-12)
+    # leaving M along the edge (s inside) the outward normal points forward
+    comp = rec["normal"][np.arange(len(keys)), keys % 3]
+    inside_s = L.reshape(-1)[keys // 3] == 1
+    assert np.all(np.where(inside_s, comp > -1e-12, comp < 1e-12))
 
 
 def line_volume(L, keys, lam, h, axis):
