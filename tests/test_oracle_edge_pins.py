@@ -308,3 +308,19 @@ def test_concave_cap_area_girard(oracle_mod):
         sel = (rec["type"] == 3) & (np.linalg.norm(x - p, axis=1) < RHO + 1e-9)
         area = h * h * np.abs(rec["normal"][np.arange(len(keys)), keys % 3])[sel].sum()
         assert abs(area / A_cap - 1) < 1e-2
+
+
+def test_crossings_lie_on_their_tagged_patch(oracle_mod):
+    """Every crossing lies on the surface its tag names (the atom's sphere, the
+    pair's torus, the triple's probe sphere) to rounding, and the tags cover
+    all three patch types on a molecule."""
+    from tests.parity import crossing_points, surface_residual
+    m = _molecule(120, 4, 0.5)
+    o = oracle_mod.Oracle(m.centres, m.radii, m.probe)
+    L = o.labels_grid(m.lo, m.spacing, m.dims)
+    keys = oracle_mod.crossing_keys(L)
+    rec = o.edges(m.lo, m.spacing, m.dims, keys)
+    x = crossing_points({"key": keys, "lam": rec["lam"]}, m.lo, m.spacing, m.dims)
+    resid, _ = surface_residual(o, rec["type"], rec["atoms"], x)
+    assert resid.max() < 1e-9, resid.max()
+    assert set(np.unique(rec["type"])) == {1, 2, 3}
