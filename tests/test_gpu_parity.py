@@ -51,6 +51,15 @@ def test_small_molecules(E, oracle_mod, prec, n, seed, h, tile):
     run_and_compare(E, oracle_mod, m.centres, m.radii, m.probe, h, m.lo, m.hi, prec, tile)
 
 
+@pytest.mark.parametrize("probe,prec", [(0.6, 0), (2.2, 0), (2.2, 1)])
+def test_probe_radii(E, oracle_mod, probe, prec):
+    """A small and a large probe (more and fewer concave patches, spindle
+    tori with the large one) on a 120-atom globule."""
+    from eses_inputs import molecule
+    m = molecule(120, 4, 0.4)
+    run_and_compare(E, oracle_mod, m.centres, m.radii, probe, 0.4, m.lo, m.hi, prec)
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_globule500(E, oracle_mod, prec):
     from eses_inputs import workload

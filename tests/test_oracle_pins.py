@@ -336,24 +336,25 @@ def lattice(nx, ny, nz, step, seed):
     return c, np.full(len(c), 1.7)
 
 
-@pytest.mark.parametrize("seed", [7, 8, "lattice"])
-def test_distance_brute_force(oracle_mod, seed):
+@pytest.mark.parametrize("seed,rho", [(7, RHO), (8, RHO), ("lattice", RHO), (11, 0.6), (12, 2.2)])
+def test_distance_brute_force(oracle_mod, seed, rho):
     """dist(x, A) from the oracle against the nearest of ~1e6 admissible
     points sampled on the exposed parts of the SAS spheres (the boundary of
     A): the sample set lies in A, so the oracle may never exceed it, and it
     is dense, so the oracle may not fall below it by more than its spacing.
     The lattice case is a 3x3 slab of equal atoms at 3.0 A, whose concave
-    probes each touch four atoms."""
+    probes each touch four atoms; two cases use a small and a large probe."""
     from eses_inputs import globule
     if seed == "lattice":
         c, r = lattice(3, 3, 1, 3.0, 3)
         seed = 9
     else:
         c, r = globule(10, seed)
-    s = r + RHO
-    samp = exposed_samples(c, r, RHO, 120000)
+    s = r + rho
+    per = 120000
+    samp = exposed_samples(c, r, rho, per)
     tree = cKDTree(samp)
-    o = oracle_mod.Oracle(c, r, RHO)
+    o = oracle_mod.Oracle(c, r, rho)
     rng = np.random.default_rng(seed)
     lo = c.min(axis=0) - 3.5
     hi = c.max(axis=0) + 3.5
@@ -363,14 +364,15 @@ def test_distance_brute_force(oracle_mod, seed):
     x = x[inU]
     dist_bf = tree.query(x)[0]
     dist, typ = o.dist_points(x, 50.0)
-    spacing = 0.035
+    # nearest-sample gap on the largest sphere of the Fibonacci sampling
+    spacing = 1.1 * math.sqrt(4 * math.pi * s.max() ** 2 / per)
     assert np.all(dist <= dist_bf + 1e-9)
     assert np.all(dist >= dist_bf - spacing)
     assert set(np.unique(typ)) >= {1, 2}
     # labels from the definition where the brute force is decisive
     vdw = np.any(d2[inU] <= r ** 2, axis=1)
-    lab_bf = np.where(vdw, 1, dist_bf >= RHO).astype(np.uint8)
-    keep = vdw | (np.abs(dist_bf - RHO) > spacing)
+    lab_bf = np.where(vdw, 1, dist_bf >= rho).astype(np.uint8)
+    keep = vdw | (np.abs(dist_bf - rho) > spacing)
     got = o.labels_points(x)
     assert np.array_equal(got[keep], lab_bf[keep])
     assert keep.mean() > 0.95
