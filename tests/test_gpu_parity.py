@@ -60,6 +60,19 @@ def test_probe_radii(E, oracle_mod, probe, prec):
     run_and_compare(E, oracle_mod, m.centres, m.radii, probe, 0.4, m.lo, m.hi, prec)
 
 
+@pytest.mark.parametrize("h,lo,hi", [
+    (2.0, (-1.0, -1.0, -1.0), (1.0, 1.0, 1.0)),      # 2 x 2 x 2 points
+    (0.9, (-1.3, -0.4, -2.2), (1.1, 0.5, 2.0)),      # 4 x 2 x 6
+    (0.35, (-2.0, -0.1, -0.1), (2.1, 0.2, 0.2)),     # one line of points along x
+])
+def test_tiny_grids(E, oracle_mod, h, lo, hi):
+    """Grids of a few points (smaller than one tile and than a label word)
+    cutting through two atoms."""
+    c = np.array([[0.05, 0.02, -0.03], [1.9, 0.1, 0.4]])
+    r = np.array([1.6, 1.2])
+    run_and_compare(E, oracle_mod, c, r, RHO, h, np.array(lo), np.array(hi), 0)
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_globule500(E, oracle_mod, prec):
     from eses_inputs import workload
