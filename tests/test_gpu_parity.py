@@ -74,6 +74,62 @@ def test_tiny_grids(E, oracle_mod, h, lo, hi):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_far_from_origin(E, oracle_mod, prec):
+    """A molecule thousands of angstroms from the origin (tile-local FP32
+    offsets, large FP64 coordinates)."""
+    from eses_inputs import bbox_from_atoms, molecule
+    m = molecule(80, 6, 0.4)
+    c = m.centres + np.array([5321.37, -2987.11, 1234.56])
+    lo, hi = bbox_from_atoms(c, m.radii, 4.0)
+    run_and_compare(E, oracle_mod, c, m.radii, RHO, 0.4, lo, hi, prec)
+
+
+def test_scaled_molecule(E, oracle_mod):
+    """Every length doubled (radii 2.4-3.6 A, probe 2.8 A, spacing 0.8 A): a
+    power-of-two scaling leaves every label unchanged."""
+    from eses_inputs import molecule
+    m = molecule(60, 8, 0.4)
+    base = E.surface(m.centres, m.radii, RHO, 0.4, m.lo, m.hi)
+    res, _, _ = run_and_compare(E, oracle_mod, 2 * m.centres, 2 * m.radii, 2 * RHO, 0.8,
+                                2 * m.lo, 2 * m.hi, 0)
+    assert np.array_equal(res["labels"], base["labels"])
+
+
+@pytest.mark.parametrize("rotate", [False, True])
+def test_collinear_chain(E, oracle_mod, rotate):
+    """Atoms on one line: every triple is collinear (no three-sphere point)
+    and all tori share one axis, parallel to x with rotate=False.  Lengths
+    are chosen so that no grid point lies within rounding of a sphere, where
+    two FP64 evaluations in different operation orders may disagree (decimal
+    lattices make such exact ties: a chain at 2.6 A spacing on this grid puts
+    three points exactly on van der Waals spheres)."""
+    from eses_inputs import bbox_from_atoms
+    c = np.stack([np.arange(6) * 2.6137, np.zeros(6), np.zeros(6)], axis=1) + np.array(
+        [0.0, 0.0313, -0.0271])
+    if rotate:
+        q, _ = np.linalg.qr(np.random.default_rng(3).normal(size=(3, 3)))
+        c = c @ q.T + np.array([0.3, -0.2, 0.1])
+    r = np.array([1.7, 1.5, 1.8, 1.55, 1.7, 1.2])
+    lo, hi = bbox_from_atoms(c, r, 2.0)
+    res, nv, ne = run_and_compare(E, oracle_mod, c, r, RHO, 0.25, lo, hi, 0)
+    assert nv == 0 and ne > 1000
+
+
+def test_contained_atoms(E, oracle_mod):
+    """Atoms whose balls lie inside another's, beside ordinary neighbours:
+    they add nothing to the surface (lengths chosen away from exact ties)."""
+    from eses_inputs import bbox_from_atoms
+    c = np.array([[0.0137, -0.0219, 0.0071], [0.3121, 0.2093, -0.1187], [-0.2113, 0.1171, 0.2534],
+                  [3.2173, 0.4129, 0.1063], [1.5191, 2.7137, -0.3119]])
+    r = np.array([1.8113, 1.2071, 1.1937, 1.6129, 1.5083])
+    lo, hi = bbox_from_atoms(c, r, 2.0)
+    res, _, _ = run_and_compare(E, oracle_mod, c, r, RHO, 0.2, lo, hi, 0)
+    keep = [0, 3, 4]
+    ref = E.surface(c[keep], r[keep], RHO, 0.2, lo, hi)
+    assert np.array_equal(res["labels"], ref["labels"])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_globule500(E, oracle_mod, prec):
     from eses_inputs import workload
     m = workload("globule500_h0.5")
