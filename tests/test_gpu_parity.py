@@ -73,6 +73,16 @@ def test_tiny_grids(E, oracle_mod, h, lo, hi):
     run_and_compare(E, oracle_mod, c, r, RHO, h, np.array(lo), np.array(hi), 0)
 
 
+@pytest.mark.parametrize("probe", [0.1, 5.0])
+def test_extreme_probe_radii(E, oracle_mod, probe):
+    """A probe far smaller than an atom (the surface close to the van der
+    Waals surface, thin saddles) and far larger (wide tori and probe spheres,
+    long reaches in the tile lists)."""
+    from eses_inputs import molecule
+    m = molecule(50, 5, 0.4)
+    run_and_compare(E, oracle_mod, m.centres, m.radii, probe, 0.4, m.lo, m.hi, 0)
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_far_from_origin(E, oracle_mod, prec):
     """A molecule thousands of angstroms from the origin (tile-local FP32
