@@ -74,6 +74,30 @@ def test_batch_matches_single(E, oracle_mod, prec):
         compare_edges(ed, o, m.lo, m.spacing, m.dims, ref)
 
 
+def test_batch_with_empty_surfaces(E, oracle_mod):
+    """Molecules whose grids hold no crossing edge (a box away from the atoms:
+    every point outside; a box inside one atom: every point inside) batched
+    with ordinary ones."""
+    from eses_inputs import Molecule, grid_dims, molecule
+    c1 = np.array([[0.0, 0.0, 0.0], [2.9, 0.3, 0.1]])
+    r1 = np.array([1.7, 1.5])
+    far_lo, far_hi = np.array([10.0, 10.0, 10.0]), np.array([14.1, 12.3, 13.2])
+    in_lo, in_hi = np.array([-0.6, -0.5, -0.55]), np.array([0.6, 0.45, 0.5])
+    mols = [Molecule(c1, r1, 1.4, 0.3, far_lo, far_hi, grid_dims(far_lo, far_hi, 0.3)),
+            molecule(90, 41, 0.4),
+            Molecule(c1, r1, 1.4, 0.1, in_lo, in_hi, grid_dims(in_lo, in_hi, 0.1)),
+            molecule(30, 42, 0.3)]
+    print("case: batch with empty surfaces", flush=True)
+    labels, edges = run_batch(E, mols, 0, reps=2)
+    assert labels[0].sum() == 0 and len(edges[0]["key"]) == 0
+    assert labels[2].all() and len(edges[2]["key"]) == 0
+    for m, lab, ed in zip(mols, labels, edges):
+        o = oracle_mod.Oracle(m.centres, m.radii, m.probe)
+        ref = o.labels_grid(m.lo, m.spacing, m.dims)
+        compare_labels(lab, ref)
+        compare_edges(ed, o, m.lo, m.spacing, m.dims, ref)
+
+
 def test_batch256(E, oracle_mod):
     """The 256-molecule batch (log-uniform sizes 200-20,000 atoms, h = 0.5 A):
     FP32+recheck equals FP64 over every grid; the oracle checks the smallest
