@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <condition_variable>
+#include <functional>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -20,6 +22,7 @@
 #include "../../include/eses.h"
 #include "eses_device.h"
 #include "launch.h"
+#include "worker_pool.h"
 
 using namespace eses;
 
@@ -245,7 +248,10 @@ eses_status d2h(T *host, const T *dev, size_t count, hipStream_t st) {
     return ESES_OK;
 }
 
-// Pinned host memory (per thread) that the read-back kernel writes into.
+// Pinned host memory (per thread) that the read-back kernel writes into: one
+// slot per host thread that ever reads back, allocated once.  The batch
+// workers below are persistent threads, so the slots stay bounded by the
+// number of threads (each worker keeps one for the process lifetime).
 long long *readback_host() {
     thread_local long long *p = nullptr;
     if (!p && hipHostMalloc((void **)&p, 16 * sizeof(long long), hipHostMallocDefault) != hipSuccess) {
@@ -276,7 +282,7 @@ eses_status worker_streams(hipStream_t *ws) {
     return ESES_OK;
 }
 
-// Runs job(q, stream) for q in [0, n) on the worker streams from as many
+// Runs job(q, stream) for q in [0, n) on the worker streams from the pool's
 // host threads, after the work already queued on `st`; `st` then waits for
 // all of it.  Returns the status of the lowest failing q (its message in
 // g_err, prefixed with the molecule index).
@@ -297,23 +303,25 @@ eses_status run_on_workers(int n, hipStream_t st, Job job) {
     std::atomic<int> next{0};
     std::vector<eses_status> res(n, ESES_OK);
     std::vector<std::string> msg(n);
-    std::vector<std::thread> th;
-    for (int p = 0; p < P; ++p)
-        th.emplace_back([&, p]() {
-            if (hipSetDevice(dev) != hipSuccess) {
-                for (int q = next++; q < n; q = next++) {
-                    res[q] = ESES_EDEVICE;
-                    msg[q] = "hipSetDevice failed in a worker thread";
-                }
-                return;
-            }
+    const std::function<void(int)> work = [&](int p) {
+        if (hipSetDevice(dev) != hipSuccess) {
             for (int q = next++; q < n; q = next++) {
-                g_err.clear();
-                res[q] = job(q, ws[p]);
-                if (res[q] != ESES_OK) msg[q] = g_err;
+                res[q] = ESES_EDEVICE;
+                msg[q] = "hipSetDevice failed in a worker thread";
             }
-        });
-    for (auto &t : th) t.join();
+            return;
+        }
+        for (int q = next++; q < n; q = next++) {
+            g_err.clear();
+            res[q] = job(q, ws[p]);
+            if (res[q] != ESES_OK) msg[q] = g_err;
+        }
+    };
+    {
+        eses::WorkerPool &pool = eses::WorkerPool::get();
+        std::lock_guard<std::mutex> one_call(pool.call);
+        pool.run(P, work);
+    }
     eses_status out = ESES_OK;
     for (int p = 0; p < P; ++p) {
         if (hipEventRecord(done[p], ws[p]) != hipSuccess ||
