@@ -50,6 +50,17 @@
  * long double.  Atoms near a point are found with a uniform cell list that
  * only narrows the search to a superset; every decision is an exact-distance
  * comparison.
+ *
+ * Certification of labels: the grid labels of orc_labels_*_cert carry every
+ * comparison's FP64 margin together with a bound on its rounding error (the
+ * bounds are stated beside each test below).  A comparison whose margin lies
+ * within its bound is undecided; a label that depends on an undecided
+ * comparison is returned as 2, and the Python side (oracle/exact.py)
+ * re-decides it in exact rational arithmetic on the input doubles.  The
+ * labels the oracle reports are therefore those of exact real arithmetic on
+ * the given doubles, including points that lie exactly on a sphere, at
+ * exactly rho from a probe, or exactly on the boundary of an admissible
+ * patch.
  */
 #include <math.h>
 #include <stdint.h>
@@ -77,6 +88,8 @@ typedef struct {
     double *vp;   /* [nv][3] */
     int *vatom;   /* [nv][3], ascending atom ids */
     int *vsign;   /* +1 / -1 */
+    double *veps; /* [nv] bound on the rounding error of each position (angstrom) */
+    double cmag;  /* max |coordinate| of any centre */
     int *vcstart; /* vertex cell list */
     int *vcidx;
 } oracle_t;
@@ -317,6 +330,202 @@ static int label_at(const oracle_t *o, const double x[3], ibuf_t *buf) {
     return dist_to_A(o, x, o->rho, NULL, buf) >= o->rho;
 }
 
+/* ------------------------------------------------- certified labels */
+
+/* Width of the undecided band of a comparison, relative to the squared length
+ * scale of its terms: 2^-40, at least 2^12 times the few-ulp rounding error of
+ * the sums of squares and products below (u = 2^-53). */
+#define CERT_BAND 9.094947017729282e-13
+#define U_RND 1.1102230246251565e-16
+
+enum { T_NO = 0, T_YES = 1, T_UNSURE = 2 };
+
+/* Three-valued "m < 0" (or "m <= 0": the two differ only at m = 0, which is
+ * undecided either way) for a margin m computed with |error| <= err. */
+static int tri_neg(double m, double err) {
+    if (m < -err) return T_YES;
+    if (m > err) return T_NO;
+    return T_UNSURE;
+}
+
+static double absmax3(const double v[3]) {
+    return fmax(fabs(v[0]), fmax(fabs(v[1]), fabs(v[2])));
+}
+
+/* Circle S_i ^ S_j as circle_of, with a bound eps on the rounding error of
+ * each component of its centre and of its radius (first order, safety 4):
+ * d within 4u d; a = (s_i^2 - s_j^2 + d^2) / 2d within
+ * da = 2u (s_i^2 + s_j^2 + 3 d^2) / d + 5u |a|; R^2 = s_i^2 - a^2 within
+ * 3u s_i^2 + 2 |a| da + u a^2, hence R within that over 2R plus u R; the unit
+ * axis within 6u per component, so o = c_i + a n within
+ * 2u (|c_i| + |a| + s_i) + da + 6u |a|. */
+static int circle_cert(const oracle_t *o, int i, int j, double oc[3], double n[3], double *R,
+                       double *eps) {
+    if (!circle_of(o, i, j, oc, n, R)) return 0;
+    const double u = U_RND;
+    double v[3] = {o->cx[j] - o->cx[i], o->cy[j] - o->cy[i], o->cz[j] - o->cz[i]};
+    double d = norm3(v);
+    double si = o->s[i], sj = o->s[j];
+    double a = (sq(si) - sq(sj) + d * d) / (2.0 * d);
+    double ci[3] = {o->cx[i], o->cy[i], o->cz[i]};
+    double da = 2.0 * u * (sq(si) + sq(sj) + 3.0 * d * d) / d + 5.0 * u * fabs(a);
+    double dR = (3.0 * u * sq(si) + 2.0 * fabs(a) * da + u * a * a) / (2.0 * *R) + u * *R;
+    *eps = 4.0 * (2.0 * u * (absmax3(ci) + fabs(a) + si) + da + 6.0 * u * fabs(a) + dR);
+    return 1;
+}
+
+/* Certified case 3 for x in U and in no van der Waals ball (both certain):
+ * 0 if some admissible candidate certainly lies closer than rho, 1 if
+ * certainly none does, 2 if that depends on an undecided comparison. */
+static int shell_cert(const oracle_t *o, const double x[3], ibuf_t *buf) {
+    const double rho = o->rho, rho2 = rho * rho, u = U_RND;
+    int unsure = 0;
+    /* (V) concave probe positions: |x - p|^2 < rho^2.  p is within veps of
+     * its exact value, so |x - p|^2 within 2 |x - p| veps (+ rounding);
+     * 2 |x - p| <= |x - p|^2 / rho + rho. */
+    {
+        ibuf_t vb = {0, 0, 0};
+        query_cells(o, o->vcstart, o->vcidx, x, rho + 1e-6, &vb);
+        for (int q = 0; q < vb.n; q++) {
+            int v = vb.idx[q];
+            const double *p = o->vp + 3 * v;
+            double d2 = sq(x[0] - p[0]) + sq(x[1] - p[1]) + sq(x[2] - p[2]);
+            double err = 2.0 * o->veps[v] * (d2 / rho + rho) + CERT_BAND * (d2 + rho2);
+            int t = tri_neg(d2 - rho2, err);
+            if (t == T_YES) {
+                free(vb.idx);
+                return 0;
+            }
+            if (t == T_UNSURE) unsure = 1;
+        }
+        free(vb.idx);
+    }
+    query_cells(o, o->cstart, o->catom, x, o->smax + rho + 1e-6, buf);
+    {
+        int m = 0;
+        for (int q = 0; q < buf->n; q++) {
+            int i = buf->idx[q];
+            if (dist2_pt(o, i, x) < sq(o->s[i] + rho + 1e-6)) buf->idx[m++] = i;
+        }
+        buf->n = m;
+    }
+    /* (F) radial projections y_i = c_i + s_i (x - c_i) / |x - c_i|, within rho
+     * iff |x - c_i| < s_i + rho (x is outside the van der Waals ball); y_i is
+     * within eps_y = 4u (2 |c_i| + 3 s_i) of its exact value, so |y - c_k|^2 is
+     * within 2 |y - c_k| eps_y (+ rounding). */
+    for (int q = 0; q < buf->n; q++) {
+        int i = buf->idx[q];
+        double ci[3] = {o->cx[i], o->cy[i], o->cz[i]};
+        double d2 = dist2_pt(o, i, x);
+        double sr = o->s[i] + rho;
+        int w = tri_neg(d2 - sq(sr), CERT_BAND * (d2 + sq(sr)));
+        if (w == T_NO) continue;
+        double dv[3] = {x[0] - ci[0], x[1] - ci[1], x[2] - ci[2]};
+        double d = sqrt(d2);
+        double y[3];
+        for (int t = 0; t < 3; t++) y[t] = ci[t] + o->s[i] * dv[t] / d;
+        double eps_y = 4.0 * u * (2.0 * absmax3(ci) + 3.0 * o->s[i]);
+        int adm = T_YES;
+        for (int qq = o->nstart[i]; qq < o->nstart[i + 1] && adm != T_NO; qq++) {
+            int k = o->nbr[qq];
+            double dk2 = dist2_pt(o, k, y);
+            double err = 4.0 * sqrt(dk2) * eps_y + CERT_BAND * (dk2 + sq(o->s[k]));
+            int in = tri_neg(dk2 - sq(o->s[k]), err); /* y strictly inside ball k */
+            if (in == T_YES) adm = T_NO;
+            else if (in == T_UNSURE) adm = T_UNSURE;
+        }
+        if (adm == T_NO) continue;
+        if (w == T_YES && adm == T_YES) return 0;
+        unsure = 1;
+    }
+    /* (E) nearest circle points.  With w = x - o, t = w.n, b = |w - t n|:
+     * |x - q|^2 = |w|^2 + R^2 - 2 b R, whose error is below
+     * 8 (|w| + R)(eps + 8u |w|) (+ rounding); q = o + R (w - t n) / b is within
+     * eps_q = 2 eps + 4 R (eps + 13u |w|) / b (the direction is undetermined on
+     * the axis, b = 0).  A neighbour k whose ball certainly misses the whole
+     * circle (distance from c_k to the circle above s_k) cannot make q
+     * inadmissible; one that certainly holds the whole circle always does. */
+    for (int q1 = 0; q1 < buf->n; q1++) {
+        int i = buf->idx[q1];
+        for (int qq = o->nstart[i]; qq < o->nstart[i + 1]; qq++) {
+            int j = o->nbr[qq];
+            if (j <= i) continue;
+            if (!(dist2_pt(o, j, x) < sq(o->s[j] + rho + 1e-6))) continue;
+            double oc[3], n[3], R, eps;
+            if (!circle_cert(o, i, j, oc, n, &R, &eps)) continue;
+            double w[3] = {x[0] - oc[0], x[1] - oc[1], x[2] - oc[2]};
+            double ww = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+            double t = w[0] * n[0] + w[1] * n[1] + w[2] * n[2];
+            double wp[3] = {w[0] - t * n[0], w[1] - t * n[1], w[2] - t * n[2]};
+            double b = norm3(wp);
+            double wl = sqrt(ww);
+            double m = ww + R * R - rho2 - 2.0 * b * R;
+            double err = 8.0 * (wl + R) * (eps + 8.0 * u * wl) +
+                         CERT_BAND * (ww + R * R + rho2 + 2.0 * b * R);
+            int within = tri_neg(m, err);
+            if (within == T_NO) continue;
+            double eps_q = b > 0.0 ? 2.0 * eps + 4.0 * R * (eps + 13.0 * u * wl) / b : INFINITY;
+            double qp[3];
+            circle_nearest(x, oc, n, R, qp);
+            int adm = T_YES;
+            for (int q3 = o->nstart[i]; q3 < o->nstart[i + 1] && adm != T_NO; q3++) {
+                int k = o->nbr[q3];
+                if (k == j) continue;
+                double ck[3] = {o->cx[k], o->cy[k], o->cz[k]};
+                double wk[3] = {ck[0] - oc[0], ck[1] - oc[1], ck[2] - oc[2]};
+                double wkk = wk[0] * wk[0] + wk[1] * wk[1] + wk[2] * wk[2];
+                double tk = wk[0] * n[0] + wk[1] * n[1] + wk[2] * n[2];
+                double bk = sqrt(fmax(0.0, wkk - tk * tk));
+                double sk2 = sq(o->s[k]);
+                double wkl = sqrt(wkk);
+                double errk = 8.0 * (wkl + R) * (eps + 8.0 * u * wkl) +
+                              CERT_BAND * (wkk + R * R + sk2 + 2.0 * bk * R);
+                /* nearest and farthest circle points from c_k */
+                int miss = tri_neg(sk2 - (tk * tk + sq(bk - R)), errk);
+                if (miss == T_YES) continue;
+                int hold = tri_neg(tk * tk + sq(bk + R) - sk2, errk);
+                if (hold == T_YES) {
+                    adm = T_NO;
+                    break;
+                }
+                double dk2 = sq(qp[0] - ck[0]) + sq(qp[1] - ck[1]) + sq(qp[2] - ck[2]);
+                double e2 = isinf(eps_q) ? INFINITY
+                                         : 4.0 * sqrt(dk2) * eps_q + CERT_BAND * (dk2 + sk2);
+                int in = tri_neg(dk2 - sk2, e2);
+                if (in == T_YES) adm = T_NO;
+                else if (in == T_UNSURE) adm = T_UNSURE;
+            }
+            if (adm == T_NO) continue;
+            if (within == T_YES && adm == T_YES) return 0;
+            unsure = 1;
+        }
+    }
+    return unsure ? 2 : 1;
+}
+
+/* Certified label: 1 inside, 0 outside, 2 undecided in FP64 (the cases of
+ * label_at, each comparison three-valued; |x - c|^2, r^2 and s^2 are each
+ * within 4u of their exact values, relative). */
+static int label_cert(const oracle_t *o, const double x[3], ibuf_t *buf) {
+    query_cells(o, o->cstart, o->catom, x, o->smax + 1e-6, buf);
+    int vdw_unsure = 0, inU = 0, inU_unsure = 0;
+    for (int q = 0; q < buf->n; q++) {
+        int i = buf->idx[q];
+        double d2 = dist2_pt(o, i, x);
+        double s2 = sq(o->s[i]);
+        double err = CERT_BAND * (d2 + s2);
+        int v = tri_neg(d2 - sq(o->r[i]), err);
+        if (v == T_YES) return 1;
+        if (v == T_UNSURE) vdw_unsure = 1;
+        int us = tri_neg(d2 - s2, err);
+        if (us == T_YES) inU = 1;
+        else if (us == T_UNSURE) inU_unsure = 1;
+    }
+    if (vdw_unsure) return 2;
+    if (!inU) return inU_unsure ? 2 : 0;
+    return shell_cert(o, x, buf);
+}
+
 /* ---------------------------------------------------------------- setup */
 
 /* Relative tolerance of the admissibility test of a three-sphere point
@@ -330,7 +539,8 @@ static int label_at(const oracle_t *o, const double x[3], ibuf_t *buf) {
 /* Points on three SAS spheres by trilateration in the frame e_x || c_j - c_i,
  * e_y towards c_k, e_z = e_x x e_y.  Returns 0 if the centres are collinear or
  * the spheres share no point (z^2 < 0). */
-static int trilaterate(const oracle_t *o, int i, int j, int k, double pp[3], double pm[3]) {
+static int trilaterate(const oracle_t *o, int i, int j, int k, double pp[3], double pm[3],
+                       double *eps) {
     double ci[3] = {o->cx[i], o->cy[i], o->cz[i]};
     double dj[3] = {o->cx[j] - ci[0], o->cy[j] - ci[1], o->cz[j] - ci[2]};
     double dk[3] = {o->cx[k] - ci[0], o->cy[k] - ci[1], o->cz[k] - ci[2]};
@@ -353,6 +563,23 @@ static int trilaterate(const oracle_t *o, int i, int j, int k, double pp[3], dou
         pp[t] = ci[t] + X * ex[t] + Y * ey[t] + Z * ez[t];
         pm[t] = ci[t] + X * ex[t] + Y * ey[t] - Z * ez[t];
     }
+    /* Rounding-error bound of the positions (first order, with a safety factor
+     * of at least 4).  With L the sum of the lengths that enter (radii, d, |dk|)
+     * and q = 1 + L / jj the amplification by a nearly collinear triple: the
+     * frame vectors are off by <= 8u q, X by <= 4u L^2 / d, Y by <= 8u L^2 q^2 / jj
+     * -- hence |X ex + Y ey| by <= 16u L q^2 (L / jj + L / d) -- and Z by the
+     * error of Z^2 (<= 8u L^2 q^2 (1 + L / d)) over 2 Z, or by its square root
+     * where that is smaller; the centre adds u |c_i|. */
+    {
+        const double u = 1.1102230246251565e-16;
+        const double L = o->s[i] + o->s[j] + o->s[k] + d + norm3(dk);
+        const double q = 1.0 + L / jj;
+        const double cm = fmax(fabs(ci[0]), fmax(fabs(ci[1]), fabs(ci[2])));
+        const double ez2 = 8.0 * u * L * L * q * q * (1.0 + L / d);
+        /* |sqrt(a) - sqrt(b)| <= min(sqrt(|a - b|), |a - b| / (2 sqrt(b))) */
+        *eps = 16.0 * (u * cm + 16.0 * u * L * q * q * (1.0 + L / jj + L / d) +
+                       (Z > 0.0 ? fmin(sqrt(ez2), ez2 / (2.0 * Z)) : sqrt(ez2)));
+    }
     return 1;
 }
 
@@ -361,7 +588,7 @@ void orc_destroy(void *h) {
     if (!o) return;
     free(o->cx); free(o->cy); free(o->cz); free(o->r); free(o->s);
     free(o->cstart); free(o->catom); free(o->nstart); free(o->nbr);
-    free(o->vp); free(o->vatom); free(o->vsign); free(o->vcstart); free(o->vcidx);
+    free(o->vp); free(o->vatom); free(o->vsign); free(o->veps); free(o->vcstart); free(o->vcidx);
     free(o);
 }
 
@@ -384,6 +611,7 @@ void *orc_create(int n, const double *centres, const double *radii, double rho) 
         o->r[i] = radii[i];
         o->s[i] = radii[i] + rho;
         if (o->s[i] > o->smax) o->smax = o->s[i];
+        for (int a = 0; a < 3; a++) o->cmag = fmax(o->cmag, fabs(centres[3 * i + a]));
         for (int a = 0; a < 3; a++) {
             if (centres[3 * i + a] < lo[a]) lo[a] = centres[3 * i + a];
             if (centres[3 * i + a] > hi[a]) hi[a] = centres[3 * i + a];
@@ -420,7 +648,7 @@ void *orc_create(int n, const double *centres, const double *radii, double rho) 
 
     /* exposed three-sphere points, triples i < j < k with pairwise overlap */
     ibuf_t vat = {0, 0, 0}, vsg = {0, 0, 0};
-    double *vp = NULL;
+    double *vp = NULL, *ve = NULL;
     int nv = 0, vcap = 0;
     for (int i = 0; i < n; i++) {
         for (int q1 = o->nstart[i]; q1 < o->nstart[i + 1]; q1++) {
@@ -431,8 +659,8 @@ void *orc_create(int n, const double *centres, const double *radii, double rho) 
                 if (k <= j) continue;
                 double cj[3] = {o->cx[j], o->cy[j], o->cz[j]};
                 if (!(dist2_pt(o, k, cj) < sq(o->s[j] + o->s[k]))) continue;
-                double pp[3], pm[3];
-                if (!trilaterate(o, i, j, k, pp, pm)) continue;
+                double pp[3], pm[3], peps;
+                if (!trilaterate(o, i, j, k, pp, pm, &peps)) continue;
                 for (int sgn = 0; sgn < 2; sgn++) {
                     double *p = sgn == 0 ? pp : pm;
                     /* in A: every atom other than i, j, k at least its SAS radius away,
@@ -448,8 +676,10 @@ void *orc_create(int n, const double *centres, const double *radii, double rho) 
                     if (nv == vcap) {
                         vcap = vcap ? 2 * vcap : 1024;
                         vp = (double *)realloc(vp, sizeof(double) * 3 * (size_t)vcap);
+                        ve = (double *)realloc(ve, sizeof(double) * (size_t)vcap);
                     }
                     memcpy(vp + 3 * nv, p, 3 * sizeof(double));
+                    ve[nv] = peps;
                     ibuf_push(&vat, i);
                     ibuf_push(&vat, j);
                     ibuf_push(&vat, k);
@@ -461,6 +691,7 @@ void *orc_create(int n, const double *centres, const double *radii, double rho) 
     }
     o->nv = nv;
     o->vp = vp ? vp : (double *)malloc(sizeof(double) * 3);
+    o->veps = ve ? ve : (double *)malloc(sizeof(double));
     o->vatom = vat.idx ? vat.idx : (int *)malloc(sizeof(int) * 3);
     o->vsign = vsg.idx ? vsg.idx : (int *)malloc(sizeof(int));
     {
@@ -532,6 +763,42 @@ void orc_labels_grid(void *h, const double lo[3], double hs, const int dims[3], 
             for (long i = 0; i < nx; i++) {
                 x[0] = grid_coord(lo[0], hs, i);
                 out[row * nx + i] = (uint8_t)label_at(o, x, &buf);
+            }
+        }
+        free(buf.idx);
+    }
+}
+
+/* Certified labels (1, 0, or 2 = undecided in FP64) of points, and of the grid
+ * points with k in [k0, k1) as orc_labels_grid. */
+void orc_labels_points_cert(void *h, long count, const double *x, uint8_t *out) {
+    oracle_t *o = (oracle_t *)h;
+#pragma omp parallel
+    {
+        ibuf_t buf = {0, 0, 0};
+#pragma omp for schedule(dynamic, 64)
+        for (long q = 0; q < count; q++) out[q] = (uint8_t)label_cert(o, x + 3 * q, &buf);
+        free(buf.idx);
+    }
+}
+
+void orc_labels_grid_cert(void *h, const double lo[3], double hs, const int dims[3], int k0,
+                          int k1, uint8_t *out) {
+    oracle_t *o = (oracle_t *)h;
+    long nx = dims[0], ny = dims[1];
+    long rows = (long)(k1 - k0) * ny;
+#pragma omp parallel
+    {
+        ibuf_t buf = {0, 0, 0};
+#pragma omp for schedule(dynamic, 1)
+        for (long row = 0; row < rows; row++) {
+            long k = k0 + row / ny, j = row % ny;
+            double x[3];
+            x[1] = grid_coord(lo[1], hs, j);
+            x[2] = grid_coord(lo[2], hs, k);
+            for (long i = 0; i < nx; i++) {
+                x[0] = grid_coord(lo[0], hs, i);
+                out[row * nx + i] = (uint8_t)label_cert(o, x, &buf);
             }
         }
         free(buf.idx);

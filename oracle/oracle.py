@@ -2,6 +2,12 @@
 
 TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU-baseline
 leg of the benchmark may import this module; the product path never does.
+
+Labels are certified: the C oracle decides each comparison in FP64 against a
+bound on its rounding error, and the points it leaves undecided are re-labelled
+in exact rational arithmetic (exact.py), so the labels returned are those of
+exact real arithmetic on the input doubles.  `last_undecided` holds the number
+of points of the last labelling call that needed the exact re-decision.
 """
 from __future__ import annotations
 
@@ -50,6 +56,9 @@ def _load():
     lib.orc_threads.restype = ctypes.c_int
     lib.orc_labels_points.argtypes = [P, ctypes.c_long, dp, u8p]
     lib.orc_labels_grid.argtypes = [P, dp, ctypes.c_double, ip, ctypes.c_int, ctypes.c_int, u8p]
+    lib.orc_labels_points_cert.argtypes = [P, ctypes.c_long, dp, u8p]
+    lib.orc_labels_grid_cert.argtypes = [P, dp, ctypes.c_double, ip, ctypes.c_int, ctypes.c_int,
+                                         u8p]
     lib.orc_dist_points.argtypes = [P, ctypes.c_long, dp, ctypes.c_double, dp, ip]
     lib.orc_edges.argtypes = [P, dp, ctypes.c_double, ip, ctypes.c_long, lp, ip, dp, dp, ip, ip]
     _lib = lib
@@ -96,22 +105,60 @@ class Oracle:
                                       _p(s, ctypes.c_int))
         return p, a, s
 
+    last_undecided = 0
+
+    def _exact(self):
+        ex = getattr(self, "_exact_labeller", None)
+        if ex is None:
+            from .exact import ExactLabeller
+            p, a, sg = self.vertices()
+            ex = ExactLabeller(self.c, self.r, self.probe, a, sg, p)
+            self._exact_labeller = ex
+        return ex
+
     def labels_points(self, x):
+        """Exact labels of points [m,3]."""
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+        out = np.zeros(x.shape[0], dtype=np.uint8)
+        self.lib.orc_labels_points_cert(self.h, x.shape[0], _p(x, ctypes.c_double),
+                                        _p(out, ctypes.c_uint8))
+        und = np.flatnonzero(out == 2)
+        self.last_undecided = int(und.size)
+        if und.size:
+            ex = self._exact()
+            for q in und:
+                out[q] = ex.label(x[q])
+        return out
+
+    def labels_points_fp64(self, x):
+        """Uncertified FP64 labels of points [m,3] (each comparison taken at
+        its FP64 value)."""
         x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
         out = np.zeros(x.shape[0], dtype=np.uint8)
         self.lib.orc_labels_points(self.h, x.shape[0], _p(x, ctypes.c_double),
                                    _p(out, ctypes.c_uint8))
         return out
 
-    def labels_grid(self, lo, h, dims, k0: int = 0, k1: int | None = None):
-        """Labels [k1-k0, ny, nx] (x fastest) of grid points lo + (i,j,k) h."""
+    def labels_grid(self, lo, h, dims, k0: int = 0, k1: int | None = None, certify: bool = True):
+        """Exact labels [k1-k0, ny, nx] (x fastest) of grid points lo + (i,j,k) h
+        (certify=False: uncertified FP64 labels)."""
         dims = tuple(int(d) for d in dims)
         k1 = dims[2] if k1 is None else int(k1)
         lo = np.ascontiguousarray(lo, dtype=np.float64)
         d = np.asarray(dims, dtype=np.int32)
         out = np.zeros((k1 - k0, dims[1], dims[0]), dtype=np.uint8)
-        self.lib.orc_labels_grid(self.h, _p(lo, ctypes.c_double), float(h), _p(d, ctypes.c_int),
-                                 int(k0), int(k1), _p(out, ctypes.c_uint8))
+        fn = self.lib.orc_labels_grid_cert if certify else self.lib.orc_labels_grid
+        fn(self.h, _p(lo, ctypes.c_double), float(h), _p(d, ctypes.c_int), int(k0), int(k1),
+           _p(out, ctypes.c_uint8))
+        if not certify:
+            return out
+        und = np.argwhere(out == 2)
+        self.last_undecided = int(len(und))
+        if len(und):
+            ex = self._exact()
+            for kk, j, i in und:
+                x = grid_point(lo, h, (int(i), int(j), int(kk) + k0))
+                out[kk, j, i] = ex.label(x)
         return out
 
     def dist_points(self, x, cap: float):
@@ -143,6 +190,11 @@ class Oracle:
                            _p(nrm, ctypes.c_double), _p(typ, ctypes.c_int),
                            _p(atoms, ctypes.c_int))
         return dict(status=st, lam=lam, normal=nrm, type=typ, atoms=atoms)
+
+
+def grid_point(lo, h, ijk):
+    """Grid point (i, j, k): each coordinate fl(lo_a + fl(i_a h)) in FP64."""
+    return np.array([float(lo[a]) + float(ijk[a]) * float(h) for a in range(3)])
 
 
 def crossing_keys(labels):
