@@ -112,7 +112,9 @@ def test_edges_against_label_bisection(oracle_mod, n, seed, h):
     K = 256
     us = np.linspace(0.0, 1.0, K + 1)
     pts = s[:, None, :] + (us[None, :, None] * m.spacing) * e[:, None, :]
-    lab = o.labels_points(pts.reshape(-1, 3)).reshape(len(keys), K + 1)
+    # the bisection closes in on the surface to within rounding, so it runs on
+    # the FP64 label function as computed (the crossing records are FP64 too)
+    lab = o.labels_points_fp64(pts.reshape(-1, 3)).reshape(len(keys), K + 1)
     first = np.argmax(lab != lab[:, :1], axis=1)
     assert np.all(lab[np.arange(len(keys)), first] != lab[:, 0])
     lo_u = us[first - 1]
@@ -120,7 +122,7 @@ def test_edges_against_label_bisection(oracle_mod, n, seed, h):
     L0 = lab[:, 0]
     for _ in range(48):
         mid = 0.5 * (lo_u + hi_u)
-        lm = o.labels_points(s + (mid * m.spacing)[:, None] * e)
+        lm = o.labels_points_fp64(s + (mid * m.spacing)[:, None] * e)
         same = lm == L0
         lo_u = np.where(same, mid, lo_u)
         hi_u = np.where(same, hi_u, mid)
