@@ -21,6 +21,7 @@
 
 #include "../../include/eses.h"
 #include "eses_device.h"
+#include "exact.h"
 #include "launch.h"
 #include "worker_pool.h"
 
@@ -960,6 +961,39 @@ eses_status eses_bbox_from_atoms(const double *c, const double *r, int64_t n, do
         lo[a] -= margin;
         hi[a] += margin;
     }
+    return ESES_OK;
+}
+
+eses_status eses_exact_labels(const double *centers, const double *radii, int64_t n_atoms,
+                              double probe_radius, const int32_t *probe_atoms,
+                              const int8_t *probe_sign, int64_t n_probes, const double *points,
+                              int64_t n_points, uint8_t *labels) {
+    g_err.clear();
+    if (!centers || !radii || n_atoms < 1 || !(std::isfinite(probe_radius) && probe_radius > 0.0) ||
+        n_probes < 0 || (n_probes > 0 && (!probe_atoms || !probe_sign)) || n_points < 0 ||
+        (n_points > 0 && (!points || !labels))) {
+        set_err("eses_exact_labels: bad argument");
+        return ESES_EINVAL;
+    }
+    for (int64_t i = 0; i < n_atoms; ++i)
+        if (!finite3(centers + 3 * i) || !std::isfinite(radii[i]) || !(radii[i] > 0.0)) {
+            set_err("eses_exact_labels: atom %lld is not finite or has radius <= 0", (long long)i);
+            return ESES_EINVAL;
+        }
+    for (int64_t v = 0; v < n_probes; ++v)
+        for (int t = 0; t < 3; ++t)
+            if (probe_atoms[3 * v + t] < 0 || probe_atoms[3 * v + t] >= n_atoms) {
+                set_err("eses_exact_labels: probe %lld names no atom", (long long)v);
+                return ESES_EINVAL;
+            }
+    for (int64_t q = 0; q < n_points; ++q)
+        if (!finite3(points + 3 * q)) {
+            set_err("eses_exact_labels: point %lld is not finite", (long long)q);
+            return ESES_EINVAL;
+        }
+    eses::ExactMolecule em(centers, radii, n_atoms, probe_radius, probe_atoms, probe_sign,
+                           n_probes);
+    for (int64_t q = 0; q < n_points; ++q) labels[q] = (uint8_t)em.label(points + 3 * q);
     return ESES_OK;
 }
 

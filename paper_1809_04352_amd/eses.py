@@ -29,7 +29,7 @@ EXPORTED = [
     "eses_bbox_from_atoms", "eses_grid_dims", "eses_build_candidates", "eses_candidates_info",
     "eses_copy_vertices", "eses_classify", "eses_edge_intersections", "eses_free_candidates",
     "eses_last_error", "eses_version", "eses_edge_work", "eses_set_timing",
-    "eses_get_kernel_times", "eses_trim_cache", "eses_set_allocator",
+    "eses_get_kernel_times", "eses_trim_cache", "eses_set_allocator", "eses_exact_labels",
 ]
 
 # C types of the caller-allocator hook (eses_set_allocator).
@@ -148,6 +148,9 @@ def load():
     lib.eses_trim_cache.argtypes = []
     lib.eses_set_timing.restype = None
     lib.eses_set_timing.argtypes = [ctypes.c_int]
+    lib.eses_exact_labels.restype = st
+    lib.eses_exact_labels.argtypes = [P, P, ctypes.c_int64, ctypes.c_double, P, P,
+                                      ctypes.c_int64, P, ctypes.c_int64, P]
     lib.eses_get_kernel_times.restype = st
     lib.eses_get_kernel_times.argtypes = [P, ctypes.POINTER(KernelTimes)]
     _lib = lib
@@ -316,6 +319,23 @@ def edge_work(cand: Candidates, labels_dev, stream=None):
     out = (EdgeStats * n)()
     _check(load().eses_edge_work(cand.h, ptrs, out, _stream_ptr(stream)))
     return [o.as_dict() for o in out]
+
+
+def exact_labels(centres, radii, probe: float, probe_atoms, probe_sign, points):
+    """Exact labels (host arithmetic, no GPU) of points [m,3] for atoms and a
+    concave probe list (ascending atom triples [nv,3], sides [nv])."""
+    c = np.ascontiguousarray(centres, dtype=np.float64).reshape(-1, 3)
+    r = np.ascontiguousarray(radii, dtype=np.float64).reshape(-1)
+    pa = np.ascontiguousarray(probe_atoms, dtype=np.int32).reshape(-1, 3)
+    ps = np.ascontiguousarray(probe_sign, dtype=np.int8).reshape(-1)
+    x = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros(x.shape[0], dtype=np.uint8)
+    _check(load().eses_exact_labels(c.ctypes.data, r.ctypes.data, r.shape[0], float(probe),
+                                    pa.ctypes.data if len(pa) else None,
+                                    ps.ctypes.data if len(ps) else None, pa.shape[0],
+                                    x.ctypes.data if len(x) else None, x.shape[0],
+                                    out.ctypes.data if len(x) else None))
+    return out
 
 
 def set_timing(enable: bool):
