@@ -165,6 +165,25 @@ typedef struct {
 eses_status eses_bbox_from_atoms(const double *centers_host, const double *radii_host, int64_t n,
                                  double margin, double lo[3], double hi[3]);
 
+/* Host helper: exact labels (eq. 2) of points, in exact arithmetic on the
+ * given doubles -- the arbiter that eses_classify applies to the grid points
+ * whose FP64 decision it cannot certify, exported for callers who need the
+ * label of arbitrary points.  All arrays are HOST memory owned by the caller:
+ * centers [n_atoms][3], radii [n_atoms] (finite, > 0), probe_atoms
+ * [n_probes][3] (ascending atom indices of each concave probe position, as
+ * eses_copy_vertices reports them) and probe_sign [n_probes] (its side),
+ * points [n_points][3]; labels [n_points] receives 1 (inside) or 0.  Each
+ * comparison of the label (ball membership, a candidate's distance against
+ * rho, the admissibility of a radial projection or a circle point) is a
+ * polynomial in the inputs up to square roots removed by squaring; its sign is
+ * taken in FP64 when a running error bound decides it, else exactly in
+ * dyadic big-integer arithmetic.  ESES_EINVAL for a null or non-finite
+ * argument or a probe that names no atom. */
+eses_status eses_exact_labels(const double *centers, const double *radii, int64_t n_atoms,
+                              double probe_radius, const int32_t *probe_atoms,
+                              const int8_t *probe_sign, int64_t n_probes, const double *points,
+                              int64_t n_points, uint8_t *labels);
+
 /* Host helper: dims[a] = ceil((hi_a - lo_a) / spacing) + 1 of a molecule. */
 eses_status eses_grid_dims(const eses_molecule *mol, int32_t dims[3]);
 
