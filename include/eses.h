@@ -114,7 +114,11 @@ typedef struct {
                               count pass keeps (0 = default; at most the
                               default); tiles with more are rebuilt by a fill
                               pass */
-    int32_t reserved[2];   /* must be zero */
+    int32_t unc_queue;     /* test aid: initial capacity of the queue of points
+                              whose FP64 decision cannot be certified (0 =
+                              default); a queue that overflows is grown and the
+                              molecule classified again */
+    int32_t reserved;      /* must be zero */
 } eses_config;
 
 typedef struct eses_candidates eses_candidates; /* opaque, library-owned */
@@ -146,6 +150,8 @@ typedef struct {
     int64_t tests_face_cut;      /* face admissibility half-space tests */
     int64_t tests_circle;        /* circle reach tests */
     int64_t tests_circle_cut;    /* circle admissibility half-space tests */
+    int64_t n_exact;             /* points whose FP64 decision could not be
+                                    certified, re-decided exactly on the host */
 } eses_classify_stats;
 
 /* Structure-of-arrays output of eses_edge_intersections for one molecule.

@@ -929,8 +929,18 @@ static int quartic_roots01(const ld c[5], double *roots, int cap) {
     ld scale = fabsl(c[0]) + fabsl(c[1]) + fabsl(c[2]) + fabsl(c[3]) + fabsl(c[4]);
     for (int q = 0; q < nc; q++)
         if (fabsl(horner(c, 4, (ld)cp[q])) <= 1e-15L * scale) add_root(roots, &nr, cap, cp[q]);
+    /* an end where g vanishes to within rounding: the segment starts or ends on
+     * the torus */
+    ld g0 = c[0], g1 = horner(c, 4, 1.0L);
+    if (g0 != 0 && fabsl(g0) <= 1e-15L * scale) add_root(roots, &nr, cap, 0.0L);
+    if (g1 != 0 && fabsl(g1) <= 1e-15L * scale) add_root(roots, &nr, cap, 1.0L);
     return nr;
 }
+
+/* A root within END_SLACK (of the edge's length) outside an end is taken as
+ * a root at that end: a surface through an end point then owns a crossing
+ * there even where rounding puts its computed root just outside the edge. */
+#define END_SLACK 1e-9
 
 /* Real roots in [0,1] of a u^2 + b u + c (stable quadratic formula). */
 static int quad_roots01(double a, double b, double c, double *roots) {
@@ -941,8 +951,12 @@ static int quad_roots01(double a, double b, double c, double *roots) {
     int nr = 0;
     double r1 = qv / a;
     double r2 = qv != 0.0 ? c / qv : r1;
-    if (r1 >= 0.0 && r1 <= 1.0) roots[nr++] = r1;
-    if (r2 >= 0.0 && r2 <= 1.0 && r2 != r1) roots[nr++] = r2;
+    int in1 = r1 >= -END_SLACK && r1 <= 1.0 + END_SLACK;
+    int in2 = r2 >= -END_SLACK && r2 <= 1.0 + END_SLACK;
+    r1 = fmin(1.0, fmax(0.0, r1));
+    r2 = fmin(1.0, fmax(0.0, r2));
+    if (in1) roots[nr++] = r1;
+    if (in2 && !(in1 && r2 == r1)) roots[nr++] = r2;
     return nr;
 }
 

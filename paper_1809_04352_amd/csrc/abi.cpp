@@ -12,6 +12,7 @@
 #include <cstring>
 #include <initializer_list>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -183,6 +184,10 @@ struct MolState {
     Arena arena;
     Arena scratch;  // build-time temporaries
     eses_candidate_stats stats{};
+    // host arbiter of uncertain labels (built on first need) and the number of
+    // points it re-decided in the last classification
+    std::unique_ptr<eses::ExactMolecule> exact;
+    int64_t n_exact = 0;
 };
 
 }  // namespace
@@ -198,6 +203,7 @@ struct eses_candidates {
     int *cls = nullptr;        // [0..2] class counts, [3..5] class fill
     int *head = nullptr;
     uint8_t **labels_dev = nullptr;
+    int *unc_counts = nullptr;  // [n_mols] gathered uncertain-point counts
     long long nunits = 0;
     int batch_blocks[2] = {0, 0};  // persistent classification grid: FP64, FP32
     int blocks_per_cu = 0;
@@ -401,7 +407,7 @@ eses_status d2h_ints(std::initializer_list<std::pair<int *, const int *>> items,
 // The handle's buffers come from (and return to) the cache of `home`, the
 // caller's stream, which `st` follows; build-time temporaries stay with `st`.
 eses_status build_one(const eses_molecule *in, int tile, int force_recheck, int edge_fallback,
-                      int vertex_pool, int tile_pool, MolState *S, hipStream_t st,
+                      int vertex_pool, int tile_pool, int unc_queue, MolState *S, hipStream_t st,
                       hipStream_t home) {
     Mol &m = S->m;
     Arena &A = S->arena;
@@ -468,6 +474,16 @@ eses_status build_one(const eses_molecule *in, int tile, int force_recheck, int 
     }
     m.smax = hb[6] + m.rho;
     m.cell = 2.0 * m.smax;
+    m.cmag = m.smax;
+    for (int a = 0; a < 6; ++a) m.cmag = std::max(m.cmag, std::fabs(hb[a]) + m.smax);
+    // queue of the points whose FP64 decision cannot be certified (grown and
+    // the classification repeated on overflow)
+    m.unc_cap = unc_queue > 0 ? unc_queue
+                              : (int)std::min<long long>(std::max<long long>(4096, m.npts / 512),
+                                                         1LL << 22);
+    CKS(A.alloc(&m.unc_idx, m.unc_cap));
+    CKS(A.alloc(&m.unc_n, 1));
+    CK(fill_i32(m.unc_n, 1, 0, st));
     for (;;) {
         long long nc = 1;
         for (int a = 0; a < 3; ++a) {
@@ -702,7 +718,7 @@ eses_status classify_batch(eses_candidates *c, bool fp32, uint8_t *const *labels
         CK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
         hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess)
-            e = launch_classify_batch(c->mols_dev, c->labels_dev, c->units, (int)c->nunits,
+            e = launch_classify_batch(c->mols_dev, nm, c->labels_dev, c->units, (int)c->nunits,
                                       c->head, c->batch_blocks[fp32 ? 1 : 0], fp32, cap);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(cap, &g);
@@ -718,6 +734,130 @@ eses_status classify_batch(eses_candidates *c, bool fp32, uint8_t *const *labels
         c->graph[k] = g;
     }
     CK(hipGraphLaunch(c->exec[k], st));
+    return ESES_OK;
+}
+
+// Host copies of one molecule's atoms (the caller's device inputs, in caller
+// order) and concave probe list, and the exact arbiter built on them.
+eses_status exact_arbiter(MolState *S, hipStream_t st) {
+    if (S->exact) return ESES_OK;
+    const Mol &m = S->m;
+    std::vector<double> c((size_t)3 * m.n), r((size_t)m.n);
+    CK(hipMemcpyAsync(c.data(), m.in_c, sizeof(double) * c.size(), hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(r.data(), m.in_r, sizeof(double) * r.size(), hipMemcpyDeviceToHost, st));
+    std::vector<int32_t> pa((size_t)3 * std::max(m.nvert, 1));
+    std::vector<int8_t> ps((size_t)std::max(m.nvert, 1));
+    if (m.nvert > 0) {
+        Arena T;
+        T.st = st;
+        double *dp;
+        int *da;
+        int8_t *dsg;
+        eses_status s;
+        if ((s = T.alloc(&dp, 3LL * m.nvert)) != ESES_OK || (s = T.alloc(&da, 3LL * m.nvert)) != ESES_OK ||
+            (s = T.alloc(&dsg, m.nvert)) != ESES_OK) {
+            T.release();
+            return s;
+        }
+        hipError_t e = launch_export_vertices(m, dp, da, dsg, m.nvert, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(pa.data(), da, sizeof(int32_t) * 3 * m.nvert, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ps.data(), dsg, sizeof(int8_t) * m.nvert, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        T.release();
+        if (e != hipSuccess) {
+            set_err("exact arbiter: %s", hipGetErrorString(e));
+            return ESES_EDEVICE;
+        }
+    } else {
+        CK(hipStreamSynchronize(st));
+    }
+    S->exact.reset(new eses::ExactMolecule(c.data(), r.data(), m.n, m.rho, pa.data(), ps.data(),
+                                           m.nvert));
+    return ESES_OK;
+}
+
+// Grid point coordinate fl(lo + fl(i h)) on the host: two rounded operations,
+// kept apart so that they are not contracted into a fused multiply-add.
+double host_grid_coord(double lo, double h, long long i) {
+    volatile double ih = (double)i * h;
+    return lo + ih;
+}
+
+// The exact re-decision of the points the classification left uncertain
+// (their FP64 margins within the rounding bound): counts read back (one
+// synchronisation), each molecule with uncertain points re-decided on the
+// host and the labels written back.  A queue that overflowed is grown and the
+// molecule classified again.
+eses_status arbitrate(eses_candidates *c, bool fp32, uint8_t *const *labels, hipStream_t st) {
+    const int nm = (int)c->mols.size();
+    std::vector<int> cnt((size_t)nm, 0);
+    if (nm == 1) {
+        long long v = 0;
+        CKS(read_scalars({{c->mols[0]->m.unc_n, false, &v}}, st));
+        cnt[0] = (int)v;
+    } else {
+        if (!c->unc_counts) CKS(c->batch.alloc(&c->unc_counts, nm));
+        CK(launch_unc_gather(c->mols_dev, nm, c->unc_counts, st));
+        CK(hipMemcpyAsync(cnt.data(), c->unc_counts, sizeof(int) * nm, hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+    }
+    for (int q = 0; q < nm; ++q) {
+        MolState *S = c->mols[q];
+        Mol &m = S->m;
+        S->n_exact = cnt[q];
+        if (cnt[q] == 0) continue;
+        if (cnt[q] > m.unc_cap) {
+            // grow the queue and classify this molecule again
+            m.unc_cap = cnt[q];
+            CKS(S->arena.alloc(&m.unc_idx, m.unc_cap));
+            if (nm > 1)
+                CK(hipMemcpyAsync(c->mols_dev + q, &m, sizeof(Mol), hipMemcpyHostToDevice, st));
+            CK(fill_i32(m.unc_n, 1, 0, st));
+            CK(launch_classify(m, fp32, labels[q], st));
+            long long v = 0;
+            CKS(read_scalars({{m.unc_n, false, &v}}, st));
+            if (v != cnt[q]) {
+                set_err("internal: uncertain points changed between identical classifications");
+                return ESES_EINTERNAL;
+            }
+        }
+        const int n = cnt[q];
+        std::vector<long long> idx((size_t)n);
+        CK(hipMemcpyAsync(idx.data(), m.unc_idx, sizeof(long long) * n, hipMemcpyDeviceToHost, st));
+        CKS(exact_arbiter(S, st));  // synchronises
+        std::vector<uint8_t> val((size_t)n);
+        const long long nx = m.dims[0], ny = m.dims[1];
+        for (int k = 0; k < n; ++k) {
+            const long long g = idx[(size_t)k];
+            const double x[3] = {host_grid_coord(m.lo[0], m.h, g % nx),
+                                 host_grid_coord(m.lo[1], m.h, (g / nx) % ny),
+                                 host_grid_coord(m.lo[2], m.h, g / (nx * ny))};
+            val[(size_t)k] = (uint8_t)S->exact->label(x);
+        }
+        Arena T;
+        T.st = st;
+        long long *didx;
+        uint8_t *dval;
+        eses_status s;
+        if ((s = T.alloc(&didx, n)) != ESES_OK || (s = T.alloc(&dval, n)) != ESES_OK) {
+            T.release();
+            return s;
+        }
+        hipError_t e = hipMemcpyAsync(didx, idx.data(), sizeof(long long) * n,
+                                      hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dval, val.data(), (size_t)n, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = launch_scatter_labels(didx, dval, n, labels[q], st);
+        // the host arrays are released on return
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        T.release();
+        if (e != hipSuccess) {
+            set_err("exact arbitration: %s", hipGetErrorString(e));
+            return ESES_EDEVICE;
+        }
+    }
     return ESES_OK;
 }
 
@@ -782,6 +922,7 @@ eses_status edges_prepare(eses_candidates *c, size_t q, const uint8_t *lab,
         e = launch_edge_detect_write(lab, m, boff, o.capacity, (long long *)o.key, tcount, rank,
                                      st);
     if (e == hipSuccess) e = fill_i32(P.ovf, 1, 0, st);
+    if (e == hipSuccess) e = fill_i32(m.diag + 3, 1, 0, st);  // ownerless records
     if (e == hipSuccess && nw > 0 && batch) e = fill_i32(nfb, 1, 0, st);  // fused launch
     if (e == hipSuccess && nw > 0)
         e = launch_edge_group(m, (const long long *)o.key, nw, tcount, ccount, coff, rank,
@@ -823,9 +964,9 @@ eses_status edges_one(eses_candidates *c, size_t q, const uint8_t *lab, const es
                               J.lam, J.nrm, J.ptype, J.patoms, J.fallback, J.nfallback, P.ovf,
                               st);
     if (e == hipSuccess && timed) e = hipEventRecord(c->ev[5], st);
-    long long hovf = 0;
+    long long hovf = 0, hown = 0;
     if (e == hipSuccess) {
-        eses_status rs = read_scalars({{P.ovf, false, &hovf}}, st);
+        eses_status rs = read_scalars({{P.ovf, false, &hovf}, {m.diag + 3, false, &hown}}, st);
         if (rs != ESES_OK) {
             P.T.release();
             return rs;
@@ -845,6 +986,11 @@ eses_status edges_one(eses_candidates *c, size_t q, const uint8_t *lab, const es
     }
     if (hovf) {
         set_err("more roots on one edge than the per-edge list holds");
+        return ESES_EINTERNAL;
+    }
+    if (hown) {
+        set_err("internal: %lld crossing edges whose label change no surface root explains",
+                hown);
         return ESES_EINTERNAL;
     }
     counts[q] = P.total;
@@ -904,6 +1050,14 @@ eses_status edges_batch(eses_candidates *c, const uint8_t *const *labels,
     if (e == hipSuccess)
         e = launch_edge_roots_batch(c->mols_dev, jobs_dev, nj, prefix, ctl, ctl + 1, st);
     if (e == hipSuccess && timed) e = hipEventRecord(c->ev[5], st);
+    std::vector<int> own((size_t)nm, 0);
+    if (e == hipSuccess && !c->unc_counts) {
+        s = c->batch.alloc(&c->unc_counts, nm);
+        if (s != ESES_OK) e = hipErrorOutOfMemory;
+    }
+    if (e == hipSuccess) e = launch_diag_gather(c->mols_dev, nm, 3, c->unc_counts, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(own.data(), c->unc_counts, sizeof(int) * nm, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) s = read_scalars({{ctl + 1, false, &hovf}}, st);
     else (void)hipStreamSynchronize(st);
     if (e == hipSuccess && s == ESES_OK && timed) {
@@ -924,6 +1078,12 @@ eses_status edges_batch(eses_candidates *c, const uint8_t *const *labels,
         set_err("more roots on one edge than the per-edge list holds");
         return ESES_EINTERNAL;
     }
+    for (int q = 0; q < nm; ++q)
+        if (own[(size_t)q]) {
+            set_err("internal: molecule %d: %d crossing edges whose label change no surface "
+                    "root explains", q, own[(size_t)q]);
+            return ESES_EINTERNAL;
+        }
     for (int q = 0; q < nm; ++q) counts[q] = prep[q].total;
     return ESES_OK;
 }
@@ -1018,7 +1178,8 @@ eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
         set_err("need at least one molecule");
         return ESES_EINVAL;
     }
-    int tile = 8, force_recheck = 0, edge_fallback = 0, vertex_pool = 0, tile_pool = 0;
+    int tile = 8, force_recheck = 0, edge_fallback = 0, vertex_pool = 0, tile_pool = 0,
+        unc_queue = 0;
     if (cfg) {
         if (cfg->tile != 0) tile = cfg->tile;
         force_recheck = cfg->force_recheck;
@@ -1033,11 +1194,15 @@ eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
             set_err("vertex_pool and tile_pool must be >= 0");
             return ESES_EINVAL;
         }
-        for (int q = 0; q < 2; ++q)
-            if (cfg->reserved[q] != 0) {
-                set_err("eses_config.reserved must be zero");
-                return ESES_EINVAL;
-            }
+        if (cfg->reserved != 0) {
+            set_err("eses_config.reserved must be zero");
+            return ESES_EINVAL;
+        }
+        if (cfg->unc_queue < 0) {
+            set_err("unc_queue must be >= 0");
+            return ESES_EINVAL;
+        }
+        unc_queue = cfg->unc_queue;
         if (tile != 4 && tile != 8) {
             set_err("tile must be 4 or 8");
             return ESES_EINVAL;
@@ -1049,7 +1214,7 @@ eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
     for (int32_t q = 0; q < n_mols; ++q) c->mols.push_back(new MolState());
     if (n_mols == 1) {
         eses_status s = build_one(&mols[0], tile, force_recheck, edge_fallback, vertex_pool,
-                                  tile_pool, c->mols[0], st, st);
+                                  tile_pool, unc_queue, c->mols[0], st, st);
         if (s != ESES_OK) {
             std::string msg = g_err;
             eses_free_candidates(c);
@@ -1061,7 +1226,7 @@ eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
         // then belongs to the caller's stream, which waits for the builds
         eses_status s = run_on_workers(n_mols, st, [&](int q, hipStream_t ws) {
             return build_one(&mols[q], tile, force_recheck, edge_fallback, vertex_pool,
-                             tile_pool, c->mols[q], ws, st);
+                             tile_pool, unc_queue, c->mols[q], ws, st);
         });
         for (MolState *S : c->mols) S->arena.st = st;  // later uses follow the caller's stream
         if (s != ESES_OK) {
@@ -1143,12 +1308,14 @@ eses_status eses_classify(eses_candidates *c, eses_precision prec, uint8_t *cons
     if (c->mols.size() > 1) {
         CKS(classify_batch(c, prec == ESES_FP32_RECHECK, labels, st));
     } else {
+        CK(fill_i32(c->mols[0]->m.unc_n, 1, 0, st));
         CK(launch_classify(c->mols[0]->m, prec == ESES_FP32_RECHECK, labels[0], st));
     }
     if (timed) {
         CK(hipEventRecord(c->ev[1], st));
         c->cls_timed = true;
     }
+    CKS(arbitrate(c, prec == ESES_FP32_RECHECK, labels, st));
     if (stats) {
         const size_t nm = c->mols.size();
         const size_t per = 2 + WC_COUNT;
@@ -1179,6 +1346,7 @@ eses_status eses_classify(eses_candidates *c, eses_precision prec, uint8_t *cons
             o.tests_circle = (int64_t)w[2 + WC_CIRCLE];
             o.tests_circle_cut = (int64_t)w[2 + WC_CIRCLE_CUT];
             o.n_shell = (int64_t)w[2 + WC_CASE_SHELL];
+            o.n_exact = c->mols[q]->n_exact;
         }
     }
     return ESES_OK;

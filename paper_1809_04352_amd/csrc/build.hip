@@ -509,13 +509,23 @@ struct VxLds {
 // the rest from global memory; j and k themselves skipped).  The loop over
 // neighbours is uniform across the wavefront and ends when no lane has an
 // exposed candidate left.
+// `eps` receives a bound on the rounding error of the two positions (first
+// order, safety 4), propagated from the circle's bound n.w = e: w = c_k - o
+// within e + u|w|, its axial part t within 3 (e + 7u|w|), the in-plane part
+// within those plus 6u|t|, so its length b and direction e' = w_perp / b
+// within that over b; cos(phi) = (|w|^2 + R^2 - s_k^2) / (2 R b) within the
+// numerator's error (2|w| e + 2R e + 4u (|w|^2 + R^2 + s_k^2)) over 2 R b plus
+// |cos(phi)| (e / R + db / b + 2u), sin(phi) within min(sqrt(2 dc), |cos| dc /
+// sin); the position o + R (cos e' + sin f) adds R times the errors of the
+// unit vectors and of the two factors.
 __device__ inline void vertex_pair(const Mol &m, bool act, double4 oR, double4 n, int j, int k,
                                    double4 ak, const VxLds &L, int nb, int ne, int nst,
                                    bool &crossed, double *v0, double *v1, bool &ok0,
-                                   bool &ok1) {
+                                   bool &ok1, double &eps) {
     const double R = oR.w;
     bool live = false;
     crossed = false;
+    eps = 0.0;
     for (int a = 0; a < 3; ++a) v0[a] = v1[a] = 0.0;
     if (act) {
         double sk = ak.w + m.rho;
@@ -538,6 +548,20 @@ __device__ inline void vertex_pair(const Mol &m, bool act, double4 oR, double4 n
                 v1[0] = oR.x + R * (cphi * ex - sphi * fx);
                 v1[1] = oR.y + R * (cphi * ey - sphi * fy);
                 v1[2] = oR.z + R * (cphi * ez - sphi * fz);
+                const double ec = n.w, wl = sqrt(ww), at = fabs(t);
+                const double dw = ec + U64 * wl;
+                const double dp = dw + 3.0 * (dw + 7.0 * U64 * wl) + 6.0 * U64 * at;
+                const double de = 2.0 * dp / b + 4.0 * U64;
+                const double df = 2.0 * (de + 6.0 * U64);
+                const double dc =
+                    (2.0 * wl * dw + 2.0 * R * ec + 4.0 * U64 * (ww + R * R + sk * sk)) /
+                        (2.0 * R * b) +
+                    fabs(cphi) * (ec / R + dp / b + 2.0 * U64);
+                const double ds =
+                    (sphi > 0.0 ? fmin(sqrt(2.0 * dc), fabs(cphi) * dc / sphi) : sqrt(2.0 * dc)) +
+                    U64;
+                const double cm = fmax(fabs(oR.x), fmax(fabs(oR.y), fabs(oR.z)));
+                eps = 4.0 * (ec + ec + R * (dc + ds + de + df) + 4.0 * U64 * (cm + R));
             }
         }
     }
@@ -590,8 +614,8 @@ __device__ void vertex_circle(const Mol &m, int c, int c0, int i, int nb, int ne
         const double4 ak = act ? (asc_lds ? L.natasc[q - nb] : m.atom[k])
                                : make_double4(0.0, 0.0, 0.0, 0.0);
         bool crossed, ok0, ok1;
-        double v0[3], v1[3];
-        vertex_pair(m, act, oR, n, j, k, ak, L, nb, ne, nst, crossed, v0, v1, ok0, ok1);
+        double v0[3], v1[3], veps;
+        vertex_pair(m, act, oR, n, j, k, ak, L, nb, ne, nst, crossed, v0, v1, ok0, ok1, veps);
         const double v0x = v0[0], v0y = v0[1], v0z = v0[2], v1x = v1[0], v1y = v1[1], v1z = v1[2];
         unsigned long long b0 = __ballot(ok0), b1 = __ballot(ok1);
         if (FILL) {
@@ -600,11 +624,11 @@ __device__ void vertex_circle(const Mol &m, int c, int c0, int i, int nb, int ne
             int p0 = wv + count + before;
             int p1 = p0 + (ok0 ? 1 : 0);
             if (ok0 && fill_ok(m, p0, ev)) {
-                m.vert_p[p0] = make_double4(v0x, v0y, v0z, 0.0);
+                m.vert_p[p0] = make_double4(v0x, v0y, v0z, veps);
                 m.vert_ijks[p0] = make_int4(i, j, k, 1);
             }
             if (ok1 && fill_ok(m, p1, ev)) {
-                m.vert_p[p1] = make_double4(v1x, v1y, v1z, 0.0);
+                m.vert_p[p1] = make_double4(v1x, v1y, v1z, veps);
                 m.vert_ijks[p1] = make_int4(i, j, k, -1);
             }
         } else {
@@ -724,20 +748,20 @@ __global__ void __launch_bounds__(VX_WAVES *WAVE) k_vertex(Mol m, int *vcnt, Ver
             }
             const int j = L.cj[cc], k = act ? L.nasc[p] : -1;
             bool crossed, ok0, ok1;
-            double v0[3], v1[3];
+            double v0[3], v1[3], veps;
             vertex_pair(m, act, L.coR[cc], L.cn[cc], j, k, L.natasc[p], L, nb, ne, nst, crossed,
-                        v0, v1, ok0, ok1);
+                        v0, v1, ok0, ok1, veps);
             const int nx = act ? (ok0 ? 1 : 0) + (ok1 ? 1 : 0) : 0;
             // the positions go to the pool (placed and ordered on their
             // circle after the scan)
             if (nx) {
                 const int w = atomicAdd(pool.count, nx), w1 = w + (ok0 ? 1 : 0);
                 if (ok0 && w < pool.cap) {
-                    pool.p[w] = make_double4(v0[0], v0[1], v0[2], 0.0);
+                    pool.p[w] = make_double4(v0[0], v0[1], v0[2], veps);
                     pool.id[w] = make_int4(c0 + cc, 0, k, 1);
                 }
                 if (ok1 && w1 < pool.cap) {
-                    pool.p[w1] = make_double4(v1[0], v1[1], v1[2], 0.0);
+                    pool.p[w1] = make_double4(v1[0], v1[1], v1[2], veps);
                     pool.id[w1] = make_int4(c0 + cc, 0, k, -1);
                 }
             }

@@ -31,6 +31,7 @@ constexpr int CAP_V = 48, CAP_F = 48, CAP_C = 48, CAP_CUT = 256;
 struct ClsPhase1 {
     double4 a[CLS_ATOMS];  // FP64: x, y, z, r^2
     double s2[CLS_ATOMS];  // FP64: (r + rho)^2
+    double bd[CLS_ATOMS];  // FP64: error bound of both comparisons
 };
 
 struct ClsPhase1f {
@@ -43,7 +44,8 @@ struct ClsPhase2 {
     double4 f[CAP_F];      // face atom x, y, z, (r + 2 rho)^2
     int2 fr[CAP_F];        // cut range in `cut` (start, count), or (-1, face id): global cuts
     double4 co[CAP_C];     // circle o, R
-    double4 cn[CAP_C];     // circle n, R^2 - rho^2
+    double4 cn[CAP_C];     // circle n, rounding-error bound of o and R
+    double4 cq[CAP_C];     // constants of the certified cut test (circle_cut_consts)
     int2 cr[CAP_C];        // cut range, or (-1, exposed-circle id)
     double4 cut[CAP_CUT];
     // staging of the cuts: per surface (faces, then circles) the first
@@ -154,73 +156,82 @@ __device__ inline bool cuts_pass(const double4 *cuts, int b, int e, double dx, d
     return true;
 }
 
-// Case 3 of one queued point against the staged lists (global beyond them).
-__device__ inline int shell_label_staged(const Mol &m, const ClsShared &sh, int tile, int nV,
-                                         int nF, int nC, double x, double y, double z) {
+// Case 3 of one queued point against the staged lists (global beyond them),
+// every comparison certified: 0 (an admissible candidate certainly within
+// rho), 1 (certainly none), 2 (undecided in FP64).
+__device__ inline int shell_cert_staged(const Mol &m, const ClsShared &sh, const CertK &K,
+                                        int tile, int nV, int nF, int nC, double x, double y,
+                                        double z) {
     const double rho = m.rho;
     const double rho2 = rho * rho;
+    bool unsure = false;
     for (int q = 0; q < nV; ++q) {
-        double4 p = sh.p2.v[q];
-        double dx = x - p.x, dy = y - p.y, dz = z - p.z;
-        if (dx * dx + dy * dy + dz * dz < rho2) return 0;
+        const int t = tv_probe(x, y, z, sh.p2.v[q], rho2, rho, K.inv_rho);
+        if (t == TV_YES) return 0;
+        unsure |= t == TV_UNSURE;
     }
     for (int q = m.tV_off[tile] + nV, e = m.tV_off[tile + 1]; q < e; ++q) {
-        double4 p = m.vert_p[m.tV[q]];
-        double dx = x - p.x, dy = y - p.y, dz = z - p.z;
-        if (dx * dx + dy * dy + dz * dz < rho2) return 0;
+        const int t = tv_probe(x, y, z, m.vert_p[m.tV[q]], rho2, rho, K.inv_rho);
+        if (t == TV_YES) return 0;
+        unsure |= t == TV_UNSURE;
     }
     for (int q = 0; q < nF; ++q) {
         double4 a = sh.p2.f[q];
         double dx = x - a.x, dy = y - a.y, dz = z - a.z;
         double d2 = dx * dx + dy * dy + dz * dz;
-        if (!(d2 < a.w)) continue;
+        const int w = tv_neg(d2 - a.w, K.fw_band);
+        if (w == TV_NO) continue;
         double d = sqrt(d2);
         int2 r = sh.p2.fr[q];
-        bool ok = r.x >= 0 ? cuts_pass(sh.p2.cut, r.x, r.x + r.y, dx, dy, dz, d)
-                           : cuts_pass(m.face_cut, m.face_cut_off[r.y], m.face_cut_off[r.y + 1],
-                                       dx, dy, dz, d);
-        if (ok) return 0;
+        const int c = r.x >= 0 ? tv_face_cuts(sh.p2.cut, r.x, r.x + r.y, dx, dy, dz, d, K.gf)
+                               : tv_face_cuts(m.face_cut, m.face_cut_off[r.y],
+                                              m.face_cut_off[r.y + 1], dx, dy, dz, d, K.gf);
+        if (c == TV_NO) continue;
+        if (w == TV_YES && c == TV_YES) return 0;
+        unsure = true;
     }
     for (int q = m.tF_off[tile] + nF, e = m.tF_off[tile + 1]; q < e; ++q) {
         int f = m.tF[q];
         double4 a = m.atom[m.face_atom[f]];
         double dx = x - a.x, dy = y - a.y, dz = z - a.z;
         double d2 = dx * dx + dy * dy + dz * dz;
-        if (!(d2 < sq(a.w + 2.0 * rho))) continue;
-        if (cuts_pass(m.face_cut, m.face_cut_off[f], m.face_cut_off[f + 1], dx, dy, dz, sqrt(d2)))
-            return 0;
+        const int w = tv_neg(d2 - sq(a.w + 2.0 * rho), K.fw_band);
+        if (w == TV_NO) continue;
+        const int c = tv_face_cuts(m.face_cut, m.face_cut_off[f], m.face_cut_off[f + 1], dx, dy,
+                                   dz, sqrt(d2), K.gf);
+        if (c == TV_NO) continue;
+        if (w == TV_YES && c == TV_YES) return 0;
+        unsure = true;
     }
     for (int q = 0; q < nC + (m.tC_off[tile + 1] - m.tC_off[tile] - nC); ++q) {
-        double4 oR, n;
+        double4 oR, n, cq;
         int2 r;
         if (q < nC) {
             oR = sh.p2.co[q];
             n = sh.p2.cn[q];
+            cq = sh.p2.cq[q];
             r = sh.p2.cr[q];
         } else {
             int ec = m.tC[m.tC_off[tile] + q];
             int ci = m.ec_circ[ec];
             oR = m.circ_oR[ci];
             n = m.circ_n[ci];
-            n.w = oR.w * oR.w - rho2;
+            cq = circle_cut_consts(oR.w, n.w, K.smax);
             r = make_int2(-1, ec);
         }
-        double wx = x - oR.x, wy = y - oR.y, wz = z - oR.z;
-        double t = wx * n.x + wy * n.y + wz * n.z;
-        double ww = wx * wx + wy * wy + wz * wz;
-        double b = sqrt(fmax(ww - t * t, 0.0));
-        if (!(ww + n.w < 2.0 * b * oR.w)) continue;
-        double px = wx, py = wy, pz = wz, pb = b;
-        if (!(b > 0.0)) {
-            perp_unit(n.x, n.y, n.z, px, py, pz);
-            pb = 1.0;
+        int t;
+        if (r.x >= 0) {
+            t = tv_circle(x, y, z, oR, n, cq, rho2, r.y,
+                          [&](int c) { return sh.p2.cut[r.x + c]; });
+        } else {
+            const int cb = m.ec_cut_off[r.y];
+            t = tv_circle(x, y, z, oR, n, cq, rho2, m.ec_cut_off[r.y + 1] - cb,
+                          [&](int c) { return m.ec_cut[cb + c]; });
         }
-        bool ok = r.x >= 0 ? cuts_pass(sh.p2.cut, r.x, r.x + r.y, px, py, pz, pb)
-                           : cuts_pass(m.ec_cut, m.ec_cut_off[r.y], m.ec_cut_off[r.y + 1], px,
-                                       py, pz, pb);
-        if (ok) return 0;
+        if (t == TV_YES) return 0;
+        unsure |= t == TV_UNSURE;
     }
-    return 1;
+    return unsure ? 2 : 1;
 }
 
 // F32: phase 1 (cases 1 and 2, every point against the tile's atoms) in FP32
@@ -262,6 +273,10 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
     const double rho = m.rho;
     // bound of the offsets' components: tile points and atoms within s_max of it
     const double lam = (T - 1) * m.h + m.smax + 1e-3;
+    // FP64 phase 1: |x - c|^2, r^2 and s^2 within a few ulps; a listed atom's
+    // centre lies within s + span of every point of the tile
+    const double span = 2.0 * T * m.h;
+    const double bandA = CERT_BAND;
     const double E = 4.01 * U32 * lam;
     const double cb = 3.0 * E * (4.0 * lam + E) + 1e-30;
     for (int base = a0; base < a1; base += CLS_ATOMS) {
@@ -278,6 +293,7 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
             } else {
                 sh.p1.a[q] = make_double4(a.x, a.y, a.z, a.w * a.w);
                 sh.p1.s2[q] = sq(a.w + rho);
+                sh.p1.bd[q] = bandA * sq(a.w + rho + span);
             }
         }
         __syncthreads();
@@ -300,16 +316,24 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
                 inu[r] = u;
                 umay[r] = um;
             } else {
-                bool v = false, u = inu[r];
+                // certified: certainly in (margin below -bound), maybe in
+                // (margin at most +bound)
+                bool v = false, vm = vmay[r], u = inu[r], um = umay[r];
                 for (int q = 0; q < cnt; ++q) {
                     double4 a = sh.p1.a[q];
                     double dx = px[r] - a.x, dy = py[r] - a.y, dz = pz[r] - a.z;
                     double d2 = dx * dx + dy * dy + dz * dz;
-                    v |= d2 <= a.w;
-                    u |= d2 < sh.p1.s2[q];
+                    const double bd = sh.p1.bd[q];
+                    const double mv = d2 - a.w, ms = d2 - sh.p1.s2[q];
+                    v |= mv < -bd;
+                    vm |= mv <= bd;
+                    u |= ms < -bd;
+                    um |= ms <= bd;
                 }
                 inv[r] = v;
+                vmay[r] = vm;
                 inu[r] = u;
+                umay[r] = um;
             }
         }
     }
@@ -319,17 +343,22 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
         int p = threadIdx.x + r * CLS_THREADS;
         int i = t3[0] * T + p % T, j = t3[1] * T + (p / T) % T, k = t3[2] * T + p / (T * T);
         long long gi = (long long)i + (long long)m.dims[0] * ((long long)j + (long long)m.dims[1] * k);
-        if (F32) {
-            // certain: in a vdW ball; outside every SAS ball; or shell (in an
-            // SAS ball, certainly in no vdW ball)
-            if (m.force_recheck) sh.rqueue[atomicAdd(&sh.rqn, 1)] = p;
-            else if (inv[r]) labels[gi] = 1;
-            else if (!umay[r]) labels[gi] = 0;
-            else if (inu[r] && !vmay[r]) sh.queue[atomicAdd(&sh.qn, 1)] = p;
-            else sh.rqueue[atomicAdd(&sh.rqn, 1)] = p;
+        // certain: in a vdW ball; outside every SAS ball; or shell (in an SAS
+        // ball, certainly in no vdW ball).  Otherwise FP32 decisions are
+        // re-tested in FP64 and FP64 ones re-decided exactly on the host.
+        if (F32 && m.force_recheck) {
+            sh.rqueue[atomicAdd(&sh.rqn, 1)] = p;
+        } else if (inv[r]) {
+            labels[gi] = 1;
+        } else if (!umay[r]) {
+            labels[gi] = 0;
+        } else if (inu[r] && !vmay[r]) {
+            sh.queue[atomicAdd(&sh.qn, 1)] = p;
+        } else if (F32) {
+            sh.rqueue[atomicAdd(&sh.rqn, 1)] = p;
         } else {
-            if (inv[r] || !inu[r]) labels[gi] = inv[r] ? 1 : 0;
-            else sh.queue[atomicAdd(&sh.qn, 1)] = p;
+            labels[gi] = 0;
+            push_uncertain(m, gi);
         }
     }
     __syncthreads();
@@ -338,14 +367,18 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
         for (int q = threadIdx.x; q < nr; q += CLS_THREADS) {
             int p = sh.rqueue[q];
             int i = t3[0] * T + p % T, j = t3[1] * T + (p / T) % T, k = t3[2] * T + p / (T * T);
-            labels[(long long)i + (long long)m.dims[0] * ((long long)j + (long long)m.dims[1] * k)] =
-                (uint8_t)label_fp64(m, tile, grid_coord(m.lo[0], m.h, i),
-                                    grid_coord(m.lo[1], m.h, j), grid_coord(m.lo[2], m.h, k));
+            const long long gi =
+                (long long)i + (long long)m.dims[0] * ((long long)j + (long long)m.dims[1] * k);
+            const int lab = label_cert(m, tile, grid_coord(m.lo[0], m.h, i),
+                                       grid_coord(m.lo[1], m.h, j), grid_coord(m.lo[2], m.h, k));
+            labels[gi] = (uint8_t)(lab == 1);
+            if (lab == 2) push_uncertain(m, gi);
         }
         if (threadIdx.x == 0 && nr > 0) atomicAdd(&m.diag[1], nr);
     }
     const int nq = sh.qn;
     if (nq == 0) return;  // uniform: no point needs the candidate tests
+    const CertK K = cert_consts(m);
 
     // staging of the candidate lists (phase-1 LDS is dead from here on)
     const int v0 = m.tV_off[tile], f0 = m.tF_off[tile], c0 = m.tC_off[tile];
@@ -362,7 +395,8 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
         double4 oR = m.circ_oR[ci];
         double4 n = m.circ_n[ci];
         sh.p2.co[q] = oR;
-        sh.p2.cn[q] = make_double4(n.x, n.y, n.z, oR.w * oR.w - rho * rho);
+        sh.p2.cn[q] = n;
+        sh.p2.cq[q] = circle_cut_consts(oR.w, n.w, m.smax);
     }
     // the tile's own points span T - 1 spacings per axis
     double bc[3], rb;
@@ -458,10 +492,12 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
     for (int q = threadIdx.x; q < nq; q += CLS_THREADS) {
         int p = sh.queue[q];
         int i = t3[0] * T + p % T, j = t3[1] * T + (p / T) % T, k = t3[2] * T + p / (T * T);
-        int lab = shell_label_staged(m, sh, tile, nV, nF, nC, grid_coord(m.lo[0], m.h, i),
-                                     grid_coord(m.lo[1], m.h, j), grid_coord(m.lo[2], m.h, k));
-        labels[(long long)i + (long long)m.dims[0] * ((long long)j + (long long)m.dims[1] * k)] =
-            (uint8_t)lab;
+        const int lab = shell_cert_staged(m, sh, K, tile, nV, nF, nC, grid_coord(m.lo[0], m.h, i),
+                                          grid_coord(m.lo[1], m.h, j), grid_coord(m.lo[2], m.h, k));
+        const long long gi =
+            (long long)i + (long long)m.dims[0] * ((long long)j + (long long)m.dims[1] * k);
+        labels[gi] = (uint8_t)(lab == 1);
+        if (lab == 2) push_uncertain(m, gi);
     }
 }
 
@@ -627,6 +663,56 @@ hipError_t launch_units(const Mol *mols_dev, const int *tile_base_dev, int nmols
     return hipGetLastError();
 }
 
+// Uncertain-point queues of a batch: counters zeroed (a kernel, so that the
+// recorded graph holds no memset) and gathered for one read-back.
+__global__ void k_unc_zero(const Mol *mols, int nmols) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nmols) *mols[q].unc_n = 0;
+}
+
+__global__ void k_unc_gather(const Mol *mols, int nmols, int *out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nmols) out[q] = *mols[q].unc_n;
+}
+
+// Diagnostic word k of every molecule of a batch, gathered for one read-back.
+__global__ void k_diag_gather(const Mol *mols, int nmols, int k, int *out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nmols) out[q] = mols[q].diag[k];
+}
+
+hipError_t launch_diag_gather(const Mol *mols_dev, int nmols, int k, int *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_diag_gather, dim3((nmols + 255) / 256), dim3(256), 0, st, mols_dev, nmols,
+                       k, out);
+    return hipGetLastError();
+}
+
+// Exactly re-decided labels written back: labels[idx[q]] = val[q].
+__global__ void k_scatter_labels(const long long *idx, const uint8_t *val, int n,
+                                 uint8_t *labels) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) labels[idx[q]] = val[q];
+}
+
+hipError_t launch_unc_zero(const Mol *mols_dev, int nmols, hipStream_t st) {
+    hipLaunchKernelGGL(k_unc_zero, dim3((nmols + 255) / 256), dim3(256), 0, st, mols_dev, nmols);
+    return hipGetLastError();
+}
+
+hipError_t launch_unc_gather(const Mol *mols_dev, int nmols, int *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_unc_gather, dim3((nmols + 255) / 256), dim3(256), 0, st, mols_dev, nmols,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_labels(const long long *idx, const uint8_t *val, int n, uint8_t *labels,
+                                 hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_labels, dim3((n + 255) / 256), dim3(256), 0, st, idx, val, n,
+                       labels);
+    return hipGetLastError();
+}
+
 int classify_batch_blocks_per_cu(bool fp32) {
     int nb = 0;
     if (fp32)
@@ -636,10 +722,11 @@ int classify_batch_blocks_per_cu(bool fp32) {
     return nb > 0 ? nb : 1;
 }
 
-hipError_t launch_classify_batch(const Mol *mols_dev, uint8_t *const *labels_dev,
+hipError_t launch_classify_batch(const Mol *mols_dev, int nmols, uint8_t *const *labels_dev,
                                  const int2 *units, int nunits, int *head, int nblocks, bool fp32,
                                  hipStream_t st) {
     hipError_t e = fill_i32(head, 1, 0, st);
+    if (e == hipSuccess) e = launch_unc_zero(mols_dev, nmols, st);
     if (e != hipSuccess) return e;
     if (fp32)
         hipLaunchKernelGGL(k_classify_batch<true>, dim3(nblocks), dim3(CLS_THREADS), 0, st,

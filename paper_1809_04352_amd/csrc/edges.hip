@@ -239,6 +239,14 @@ __device__ double bracket_root(const double *c, int deg, double lo, double hi, d
 }
 
 // Real roots in [0, 1] of a u^2 + b u + c (a > 0), numerically stable form.
+// A root within END_SLACK outside an end counts as a root at that end: a
+// surface through an end point (exactly, where its label is a tie decided
+// exactly) then still owns the crossing there; a breakpoint at an end that
+// the surface misses only splits off an empty interval.
+constexpr double END_SLACK = 1e-9;
+
+__device__ inline double clamp01(double u) { return fmin(1.0, fmax(0.0, u)); }
+
 __device__ inline int quad01(double a, double b, double c, double *r) {
     double disc = b * b - 4.0 * a * c;
     if (disc < 0.0) return 0;
@@ -247,8 +255,12 @@ __device__ inline int quad01(double a, double b, double c, double *r) {
     double r1 = q / a;
     double r2 = q != 0.0 ? c / q : r1;
     int n = 0;
-    if (r1 >= 0.0 && r1 <= 1.0) r[n++] = r1;
-    if (r2 >= 0.0 && r2 <= 1.0 && r2 != r1) r[n++] = r2;
+    const bool in1 = r1 >= -END_SLACK && r1 <= 1.0 + END_SLACK;
+    const bool in2 = r2 >= -END_SLACK && r2 <= 1.0 + END_SLACK;
+    r1 = clamp01(r1);
+    r2 = clamp01(r2);
+    if (in1) r[n++] = r1;
+    if (in2 && !(in1 && r2 == r1)) r[n++] = r2;
     return n;
 }
 
@@ -294,7 +306,9 @@ __device__ void quartic01(const double *g, Emit emit, unsigned long long *cnt) {
         1e-12 * (fabs(g[0]) + fabs(g[1]) + fabs(g[2]) + fabs(g[3]) + fabs(g[4]));
     double ca = 0.0;                 // last critical point of g (or 0)
     double fca = horner(g, 4, 0.0);  // g there
-    if (fca == 0.0) emit(0.0);
+    // g vanishing at an end to within rounding: a root at that end (the
+    // segment starts or ends on the torus)
+    if (fabs(fca) <= tol) emit(0.0);
 #pragma unroll 1
     for (int q = 0; q < 4; ++q) {
         // next critical point of g from the g' interval q; q == 3: the end 1
@@ -322,7 +336,7 @@ __device__ void quartic01(const double *g, Emit emit, unsigned long long *cnt) {
         if (fb == 0.0) emit(cp);
         else if (fca != 0.0 && ((fca < 0.0) != (fb < 0.0)))
             emit(bracket_root<CNT>(g, 4, ca, cp, fca, fb, cnt));
-        if (interior && fb != 0.0 && fabs(fb) <= tol) emit(cp);
+        if (fb != 0.0 && fabs(fb) <= tol) emit(cp);
         ca = cp;
         fca = fb;
     }
@@ -671,6 +685,7 @@ __device__ inline void write_record(const Mol &m, long long q, const EdgeGeom &G
         if (l > 0.0)
             for (int a = 0; a < 3; ++a) n3[a] = y[a] / l;
     }
+    if (owner_key < 0) atomicAdd(&m.diag[3], 1);  // no surface owns the change: reported
     lam[q] = 1.0 - ustar;
     nrm[3 * q] = n3[0];
     nrm[3 * q + 1] = n3[1];

@@ -50,7 +50,16 @@ struct Mol {
     int tdims[3];
     int ntiles;
 
-    int *diag;           // [4] diagnostics: [0] fill-pass overflows
+    int *diag;           // [4] diagnostics: [0] fill-pass overflows, [1] FP32 points
+                         // re-tested in FP64, [2] shared centres, [3] crossing
+                         // edges whose walk found no owning surface
+    double cmag;         // max |coordinate| of any centre, plus s_max: the scale of
+                         // the rounding error of positions derived from centres
+    // points whose FP64 decision could not be certified (re-decided exactly
+    // on the host): grid indices, their count (may exceed the capacity)
+    long long *unc_idx;
+    int *unc_n;
+    int unc_cap;
 
     const double *in_c;  // caller centres [n][3]
     const double *in_r;  // caller radii [n]
@@ -70,12 +79,13 @@ struct Mol {
     int *circ_i;         // [ncirc] owner
     int *circ_j;         // [ncirc] partner, ascending per owner
     double4 *circ_oR;    // [ncirc] centre o, radius R
-    double4 *circ_n;     // [ncirc] unit axis n (owner -> partner)
+    double4 *circ_n;     // [ncirc] unit axis n (owner -> partner); w: a bound on the
+                         // rounding error of o's components and of R
     uint32_t *cflag;     // [ncirc]
 
     int nvert;
     int *vert_off;       // [ncirc + 1]
-    double4 *vert_p;     // [nvert] position
+    double4 *vert_p;     // [nvert] position; w: a bound on its rounding error
     int4 *vert_ijks;     // [nvert] internal i < j < k, sign (+1/-1, internal order)
     int *vert_off_atom;  // [n + 1]
 

@@ -79,8 +79,17 @@ hipError_t launch_classify(const Mol &m, bool fp32, uint8_t *labels, hipStream_t
 hipError_t launch_units(const Mol *mols_dev, const int *tile_base_dev, int nmols, long long total,
                         int *cls_count, int *cls_fill, int2 *units, hipStream_t st);
 int classify_batch_blocks_per_cu(bool fp32);
-hipError_t launch_classify_batch(const Mol *mols_dev, uint8_t *const *labels_dev,
+// (also zeroes every molecule's uncertain-point counter first)
+hipError_t launch_classify_batch(const Mol *mols_dev, int nmols, uint8_t *const *labels_dev,
                                  const int2 *units, int nunits, int *head, int nblocks, bool fp32,
+                                 hipStream_t st);
+// Uncertain-point counters of a batch: zeroed, or gathered into out[nmols].
+hipError_t launch_unc_zero(const Mol *mols_dev, int nmols, hipStream_t st);
+hipError_t launch_unc_gather(const Mol *mols_dev, int nmols, int *out, hipStream_t st);
+// Diagnostic word k (Mol::diag) of every molecule of a batch into out[nmols].
+hipError_t launch_diag_gather(const Mol *mols_dev, int nmols, int k, int *out, hipStream_t st);
+// labels[idx[q]] = val[q] for q < n.
+hipError_t launch_scatter_labels(const long long *idx, const uint8_t *val, int n, uint8_t *labels,
                                  hipStream_t st);
 hipError_t launch_classify_work(const Mol &m, unsigned long long *work, hipStream_t st);
 hipError_t launch_count_inside(const uint8_t *labels, long long n, unsigned long long *out,

@@ -54,7 +54,7 @@ class Config(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("force_recheck", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("edge_fallback", ctypes.c_int32),
                 ("vertex_pool", ctypes.c_int32), ("tile_pool", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("unc_queue", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class CandidateStats(ctypes.Structure):
@@ -75,7 +75,8 @@ class ClassifyStats(ctypes.Structure):
                 ("n_rechecked", ctypes.c_int64), ("n_shell", ctypes.c_int64),
                 ("tests_atom", ctypes.c_int64), ("tests_vertex", ctypes.c_int64),
                 ("tests_face", ctypes.c_int64), ("tests_face_cut", ctypes.c_int64),
-                ("tests_circle", ctypes.c_int64), ("tests_circle_cut", ctypes.c_int64)]
+                ("tests_circle", ctypes.c_int64), ("tests_circle_cut", ctypes.c_int64),
+                ("n_exact", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -208,7 +209,7 @@ class Candidates:
 
     def __init__(self, mols, tile: int = 0, stream=None, force_recheck: bool = False,
                  blocks_per_cu: int = 0, edge_fallback: bool = False, vertex_pool: int = 0,
-                 tile_pool: int = 0):
+                 tile_pool: int = 0, unc_queue: int = 0):
         lib = load()
         self.mols = list(mols)
         arr = (Molecule * len(self.mols))(*self.mols)
@@ -219,6 +220,7 @@ class Candidates:
         cfg.edge_fallback = 1 if edge_fallback else 0
         cfg.vertex_pool = int(vertex_pool)
         cfg.tile_pool = int(tile_pool)
+        cfg.unc_queue = int(unc_queue)
         h = ctypes.c_void_p()
         self.stream = _stream_ptr(stream)
         _check(lib.eses_build_candidates(arr, len(self.mols), ctypes.byref(cfg), self.stream,
@@ -244,9 +246,10 @@ class Candidates:
 
 def build_candidates(mols, tile: int = 0, stream=None, force_recheck: bool = False,
                      blocks_per_cu: int = 0, edge_fallback: bool = False,
-                     vertex_pool: int = 0, tile_pool: int = 0) -> Candidates:
+                     vertex_pool: int = 0, tile_pool: int = 0,
+                     unc_queue: int = 0) -> Candidates:
     return Candidates(mols, tile, stream, force_recheck, blocks_per_cu, edge_fallback,
-                      vertex_pool, tile_pool)
+                      vertex_pool, tile_pool, unc_queue)
 
 
 def copy_vertices(cand: Candidates, mol: int, p_dev, atoms_dev, sign_dev, stream=None) -> int:
@@ -377,7 +380,7 @@ def kernel_times(cand: Candidates) -> dict:
 def surface(centres, radii, probe: float, spacing: float, lo, hi, prec: int = ESES_FP64,
             tile: int = 0, isect_capacity: int | None = None, device="cuda",
             force_recheck: bool = False, stats: bool = False, edge_fallback: bool = False,
-            vertex_pool: int = 0, tile_pool: int = 0):
+            vertex_pool: int = 0, tile_pool: int = 0, unc_queue: int = 0):
     """Whole hot path for one molecule given host arrays; returns host numpy results."""
     import torch
     c = torch.as_tensor(np.ascontiguousarray(centres, dtype=np.float64), device=device)
@@ -385,7 +388,7 @@ def surface(centres, radii, probe: float, spacing: float, lo, hi, prec: int = ES
     mol = make_molecule(c, r, probe, spacing, lo, hi)
     dims = grid_dims(mol)
     cand = build_candidates([mol], tile, force_recheck=force_recheck, edge_fallback=edge_fallback,
-                            vertex_pool=vertex_pool, tile_pool=tile_pool)
+                            vertex_pool=vertex_pool, tile_pool=tile_pool, unc_queue=unc_queue)
     try:
         info = cand.info(0)
         nv = info["n_vertices"]

@@ -98,12 +98,21 @@ def cusp_mask(res, centres, lo, h, dims, tol=1e-6):
     return out
 
 
-def compare_edges(res, oracle, lo, h, dims, ref_labels=None):
+TIE_RESID = 1e-10   # angstrom: a crossing on two surfaces at once (owner tie)
+
+
+def compare_edges(res, oracle, lo, h, dims, ref_labels=None, log=True):
     """Edge set identical to the oracle's crossing set; lambda (as a position
-    along the edge) within POS_TOL; normals within NORMAL_TOL; patch tags equal
-    except where two surfaces meet (ties of the owner).  Normals at saddle
-    cusps (crossings on the axis of a spindle torus) are not unique and are
-    not compared."""
+    along the edge) within POS_TOL; normals within NORMAL_TOL; patch tags equal.
+
+    The owner of a crossing may differ only where both claimed surfaces pass
+    through the crossing point (to TIE_RESID): two patches meeting there, an
+    owner tie.  Where both are the same probe sphere (a probe touching four or
+    more atoms, reported by several triples) the normals must still agree;
+    elsewhere they may differ only by the crease between the two patches.
+    Normals at saddle cusps (crossings on the axis of a spindle torus) are not
+    unique and are not compared.  Returns (records, owner ties); the tie count
+    is printed."""
     from oracle.oracle import crossing_keys
     key = res["key"]
     assert np.all(np.diff(key) > 0), "keys not strictly ascending"
@@ -112,30 +121,27 @@ def compare_edges(res, oracle, lo, h, dims, ref_labels=None):
         assert np.array_equal(key, want), (len(key), len(want))
     rec = oracle.edges(lo, h, dims, key)
     assert np.all(rec["status"] == 1)
+    assert set(np.unique(res["patch_type"])) <= {1, 2, 3}
+    assert np.all(np.abs(np.linalg.norm(res["normal"], axis=1) - 1) < 1e-12)
     dpos = np.abs(rec["lam"] - res["lam"]) * h
     assert dpos.max(initial=0.0) < POS_TOL, dpos.max()
     dn = np.abs(rec["normal"] - res["normal"]).max(axis=1) if len(key) else np.zeros(0)
     tag_same = (rec["type"] == res["patch_type"]) & np.all(rec["atoms"] == res["atoms"], axis=1)
-    # where the owner differs, two surfaces meet at the crossing or coincide:
-    # the point is compared above, and the HIP path's owner must pass through it
     diff = np.flatnonzero(~tag_same)
+    creases = 0
     if diff.size:
         x = crossing_points(res, lo, h, dims)[diff]
         resid, probe = surface_residual(oracle, res["patch_type"][diff], res["atoms"][diff], x)
-        assert resid.max() < POS_TOL, resid.max()
-        # a probe touching four or more atoms is one sphere reported by several
-        # triples, so which triple owns its patch is not unique, and neither is
-        # the owner on a seam where two patches meet tangentially (the normals
-        # agree there); a disagreement with differing normals (a crease or a
-        # cusp) has measure zero
-        _, probe_o = surface_residual(oracle, rec["type"][diff], rec["atoms"][diff], x)
+        resid_o, probe_o = surface_residual(oracle, rec["type"][diff], rec["atoms"][diff], x)
+        assert resid.max() < TIE_RESID, ("HIP owner off the crossing", resid.max())
+        assert resid_o.max() < TIE_RESID, ("owners differ away from a tie", resid_o.max())
         same_sphere = ((res["patch_type"][diff] == 3) & (rec["type"][diff] == 3)
                        & (np.abs(probe - probe_o).max(axis=1) < 1e-9))
         assert dn[diff[same_sphere]].max(initial=0.0) < NORMAL_TOL
-        odd = ~same_sphere & (dn[diff] >= NORMAL_TOL)
-        assert odd.sum() <= 1e-3 * len(key), (odd.sum(), (~same_sphere).sum(), len(key))
+        creases = int((~same_sphere & (dn[diff] >= NORMAL_TOL)).sum())
     unique = tag_same & ~cusp_mask(res, oracle.c, lo, h, dims)
     assert dn[unique].max(initial=0.0) < NORMAL_TOL, dn[unique].max(initial=0.0)
-    assert np.all(np.abs(np.linalg.norm(res["normal"], axis=1) - 1) < 1e-12)
-    assert set(np.unique(res["patch_type"])) <= {1, 2, 3}
-    return len(key), int((~tag_same).sum())
+    if log:
+        print(f"edges: {len(key)} records, {diff.size} owner ties ({creases} at creases)",
+              flush=True)
+    return len(key), int(diff.size)
