@@ -995,8 +995,8 @@ static void push_root(root_t **rs, int *nr, int *cap, double u, int type, int a0
  * Returns 1 with the record if the endpoint labels differ, 0 otherwise,
  * -1 if the key is not an edge of the grid. */
 static int edge_record(const oracle_t *o, const double lo[3], double hs, const int dims[3],
-                       long key, double *lambda, double nrm[3], int *type, int atoms[3],
-                       ibuf_t *buf) {
+                       long key, const int *ends, double *lambda, double nrm[3], int *type,
+                       int atoms[3], ibuf_t *buf) {
     long axis = key % 3, idx = key / 3;
     long nx = dims[0], ny = dims[1], nz = dims[2];
     if (key < 0 || idx >= nx * ny * nz) return -1;
@@ -1008,7 +1008,8 @@ static int edge_record(const oracle_t *o, const double lo[3], double hs, const i
         xs[a] = grid_coord(lo[a], hs, ii[a]);
         xt[a] = grid_coord(lo[a], hs, ii[a] + (a == axis ? 1 : 0));
     }
-    int Ls = label_at(o, xs, buf), Lt = label_at(o, xt, buf);
+    /* end labels: the caller's (exact) ones when given, else FP64 */
+    int Ls = ends ? ends[0] : label_at(o, xs, buf), Lt = ends ? ends[1] : label_at(o, xt, buf);
     if (Ls == Lt) return 0;
 
     /* surfaces that can carry the boundary of M on the segment:
@@ -1151,18 +1152,21 @@ static int edge_record(const oracle_t *o, const double lo[3], double hs, const i
 }
 
 /* Records for a list of edge keys.  status[q]: 1 crossing, 0 same labels,
- * -1 not an edge.  Atom ids are the caller's atom indices. */
+ * -1 not an edge.  Atom ids are the caller's atom indices.  ends (NULL or
+ * [count][2]): the labels of each edge's two end points, as certified and
+ * exactly re-decided by the caller; without them the ends are labelled in
+ * FP64. */
 void orc_edges(void *h, const double lo[3], double hs, const int dims[3], long count,
-               const long *keys, int *status, double *lambda, double *normal, int *type,
-               int *atoms) {
+               const long *keys, const int *ends, int *status, double *lambda, double *normal,
+               int *type, int *atoms) {
     oracle_t *o = (oracle_t *)h;
 #pragma omp parallel
     {
         ibuf_t buf = {0, 0, 0};
 #pragma omp for schedule(dynamic, 16)
         for (long q = 0; q < count; q++) {
-            status[q] = edge_record(o, lo, hs, dims, keys[q], lambda + q, normal + 3 * q,
-                                    type + q, atoms + 3 * q, &buf);
+            status[q] = edge_record(o, lo, hs, dims, keys[q], ends ? ends + 2 * q : NULL,
+                                    lambda + q, normal + 3 * q, type + q, atoms + 3 * q, &buf);
         }
         free(buf.idx);
     }

@@ -60,7 +60,8 @@ def _load():
     lib.orc_labels_grid_cert.argtypes = [P, dp, ctypes.c_double, ip, ctypes.c_int, ctypes.c_int,
                                          u8p]
     lib.orc_dist_points.argtypes = [P, ctypes.c_long, dp, ctypes.c_double, dp, ip]
-    lib.orc_edges.argtypes = [P, dp, ctypes.c_double, ip, ctypes.c_long, lp, ip, dp, dp, ip, ip]
+    lib.orc_edges.argtypes = [P, dp, ctypes.c_double, ip, ctypes.c_long, lp, ip, ip, dp, dp, ip,
+                              ip]
     _lib = lib
     return lib
 
@@ -174,19 +175,38 @@ class Oracle:
         """Records for edge keys 3*(i + nx*(j + ny*k)) + axis.
 
         Returns dict(status, lam, normal, type, atoms); status 1 = crossing,
-        0 = equal labels, -1 = not an edge of the grid.
+        0 = equal labels, -1 = not an edge of the grid.  The two end labels of
+        every edge are the exact ones (certified, undecided ones re-decided).
         """
         keys = np.ascontiguousarray(keys, dtype=np.int64).reshape(-1)
         n = keys.shape[0]
         lo = np.ascontiguousarray(lo, dtype=np.float64)
         d = np.asarray([int(v) for v in dims], dtype=np.int32)
+        nx, ny, nz = (int(v) for v in dims)
+        axis = keys % 3
+        idx = keys // 3
+        ijk = np.stack([idx % nx, (idx // nx) % ny, idx // (nx * ny)], axis=1)
+        ok = (keys >= 0) & (idx < nx * ny * nz)
+        ok &= np.where(ok, ijk[np.arange(n), axis] + 1 < d[axis], False)
+        ijk_t = ijk.copy()
+        ijk_t[np.arange(n), axis] += 1
+        ends = np.zeros((n, 2), dtype=np.int32)
+        if ok.any():
+            hs = float(h)
+            xs = lo[None, :] + ijk[ok].astype(np.float64) * hs  # fl(lo + fl(i h))
+            xt = lo[None, :] + ijk_t[ok].astype(np.float64) * hs
+            lab = self.labels_points(np.concatenate([xs, xt]))
+            m = int(ok.sum())
+            ends[ok, 0] = lab[:m]
+            ends[ok, 1] = lab[m:]
         st = np.zeros(n, dtype=np.int32)
         lam = np.zeros(n, dtype=np.float64)
         nrm = np.zeros((n, 3), dtype=np.float64)
         typ = np.zeros(n, dtype=np.int32)
         atoms = np.full((n, 3), -1, dtype=np.int32)
         self.lib.orc_edges(self.h, _p(lo, ctypes.c_double), float(h), _p(d, ctypes.c_int), n,
-                           _p(keys, ctypes.c_long), _p(st, ctypes.c_int), _p(lam, ctypes.c_double),
+                           _p(keys, ctypes.c_long), _p(ends, ctypes.c_int), _p(st, ctypes.c_int),
+                           _p(lam, ctypes.c_double),
                            _p(nrm, ctypes.c_double), _p(typ, ctypes.c_int),
                            _p(atoms, ctypes.c_int))
         return dict(status=st, lam=lam, normal=nrm, type=typ, atoms=atoms)
