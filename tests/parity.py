@@ -99,20 +99,55 @@ def cusp_mask(res, centres, lo, h, dims, tol=1e-6):
 
 
 TIE_RESID = 1e-10   # angstrom: a crossing on two surfaces at once (owner tie)
+GEN_RESID = 1e-9    # angstrom: a normal consistent with the surface it names
+
+
+def generator_residual(oracle, ptype, atoms, x, n):
+    """How far the normal n at x is from the normal of the claimed surface: the
+    point x - r n must be the atom's centre (convex), x + rho n a point of the
+    pair's circle (saddle) or one of the triple's probe positions (concave)."""
+    c, r, rho = oracle.c, oracle.r, oracle.probe
+    s = r + rho
+    out = np.full(len(x), np.inf)
+    t1 = ptype == 1
+    out[t1] = np.linalg.norm(x[t1] - r[atoms[t1, 0], None] * n[t1] - c[atoms[t1, 0]], axis=1)
+    t2 = np.flatnonzero(ptype == 2)
+    if t2.size:
+        a, b = atoms[t2, 0], atoms[t2, 1]
+        v = c[b] - c[a]
+        d = np.linalg.norm(v, axis=1)
+        ax = v / d[:, None]
+        t = (s[a] ** 2 - s[b] ** 2 + d ** 2) / (2 * d)
+        R = np.sqrt(np.maximum(s[a] ** 2 - t ** 2, 0.0))
+        q = x[t2] + rho * n[t2] - (c[a] + t[:, None] * ax)
+        along = np.sum(q * ax, axis=1)
+        out[t2] = np.hypot(np.linalg.norm(q - along[:, None] * ax, axis=1) - R, along)
+    t3 = np.flatnonzero(ptype == 3)
+    if t3.size:
+        pv, av, _ = oracle.vertices()
+        by = {}
+        for q, tr in enumerate(av):
+            by.setdefault(tuple(int(v) for v in tr), []).append(pv[q])
+        for m in t3:
+            p = x[m] + rho * n[m]
+            out[m] = min((np.linalg.norm(p - pp) for pp in by.get(tuple(int(v) for v in atoms[m]),
+                                                                    [])), default=np.inf)
+    return out
 
 
 def compare_edges(res, oracle, lo, h, dims, ref_labels=None, log=True):
     """Edge set identical to the oracle's crossing set; lambda (as a position
-    along the edge) within POS_TOL; normals within NORMAL_TOL; patch tags equal.
+    along the edge) within POS_TOL; patch tags equal and normals within
+    NORMAL_TOL -- except at owner ties.
 
-    The owner of a crossing may differ only where both claimed surfaces pass
-    through the crossing point (to TIE_RESID): two patches meeting there, an
-    owner tie.  Where both are the same probe sphere (a probe touching four or
-    more atoms, reported by several triples) the normals must still agree;
-    elsewhere they may differ only by the crease between the two patches.
-    Normals at saddle cusps (crossings on the axis of a spindle torus) are not
-    unique and are not compared.  Returns (records, owner ties); the tie count
-    is printed."""
+    A record whose owner or normal differs from the oracle's is an owner tie,
+    accepted only where both claimed surfaces pass through the crossing point
+    (to TIE_RESID: two patches meet there, or one probe sphere is reported by
+    several triples) and each side's normal is the normal of the surface it
+    names (to GEN_RESID); their normals may then differ by the crease between
+    the patches.  Normals at saddle cusps (crossings on the axis of a spindle
+    torus) are not unique and are not compared.  Returns (records, owner
+    ties); the tie count is printed."""
     from oracle.oracle import crossing_keys
     key = res["key"]
     assert np.all(np.diff(key) > 0), "keys not strictly ascending"
@@ -127,20 +162,23 @@ def compare_edges(res, oracle, lo, h, dims, ref_labels=None, log=True):
     assert dpos.max(initial=0.0) < POS_TOL, dpos.max()
     dn = np.abs(rec["normal"] - res["normal"]).max(axis=1) if len(key) else np.zeros(0)
     tag_same = (rec["type"] == res["patch_type"]) & np.all(rec["atoms"] == res["atoms"], axis=1)
-    diff = np.flatnonzero(~tag_same)
+    cusp = cusp_mask(res, oracle.c, lo, h, dims)
+    tie = (~tag_same | (dn >= NORMAL_TOL)) & ~cusp
+    diff = np.flatnonzero(tie)
     creases = 0
     if diff.size:
         x = crossing_points(res, lo, h, dims)[diff]
-        resid, probe = surface_residual(oracle, res["patch_type"][diff], res["atoms"][diff], x)
-        resid_o, probe_o = surface_residual(oracle, rec["type"][diff], rec["atoms"][diff], x)
+        resid, _ = surface_residual(oracle, res["patch_type"][diff], res["atoms"][diff], x)
+        resid_o, _ = surface_residual(oracle, rec["type"][diff], rec["atoms"][diff], x)
         assert resid.max() < TIE_RESID, ("HIP owner off the crossing", resid.max())
         assert resid_o.max() < TIE_RESID, ("owners differ away from a tie", resid_o.max())
-        same_sphere = ((res["patch_type"][diff] == 3) & (rec["type"][diff] == 3)
-                       & (np.abs(probe - probe_o).max(axis=1) < 1e-9))
-        assert dn[diff[same_sphere]].max(initial=0.0) < NORMAL_TOL
-        creases = int((~same_sphere & (dn[diff] >= NORMAL_TOL)).sum())
-    unique = tag_same & ~cusp_mask(res, oracle.c, lo, h, dims)
-    assert dn[unique].max(initial=0.0) < NORMAL_TOL, dn[unique].max(initial=0.0)
+        g = generator_residual(oracle, res["patch_type"][diff], res["atoms"][diff], x,
+                               res["normal"][diff])
+        g_o = generator_residual(oracle, rec["type"][diff], rec["atoms"][diff], x,
+                                 rec["normal"][diff])
+        assert g.max() < GEN_RESID, ("HIP normal is not its surface's", g.max())
+        assert g_o.max() < GEN_RESID, ("oracle normal is not its surface's", g_o.max())
+        creases = int((dn[diff] >= NORMAL_TOL).sum())
     if log:
         print(f"edges: {len(key)} records, {diff.size} owner ties ({creases} at creases)",
               flush=True)
