@@ -98,42 +98,6 @@ def test_batch_with_empty_surfaces(E, oracle_mod):
         compare_edges(ed, o, m.lo, m.spacing, m.dims, ref)
 
 
-def test_batch256(E, oracle_mod):
-    """The 256-molecule batch (log-uniform sizes 200-20,000 atoms, h = 0.5 A):
-    FP32+recheck equals FP64 over every grid; the oracle checks the smallest
-    molecules whole and slices of the largest."""
-    from eses_inputs import batch
-    mols = batch(256, 0.5)
-    print("case: batch256, atoms", sum(m.n_atoms for m in mols), "points",
-          sum(m.n_points for m in mols), flush=True)
-    lab64, ed64 = run_batch(E, mols, 0, reps=2)
-    lab32, ed32 = run_batch(E, mols, 1, reps=2)
-    for a, b in zip(lab64, lab32):
-        assert np.array_equal(a, b)
-    for a, b in zip(ed64, ed32):
-        for k in a:
-            assert np.array_equal(a[k], b[k]), k
-    order = np.argsort([m.n_atoms for m in mols])
-    for q in list(order[:3]) + list(order[-2:]):
-        m = mols[q]
-        o = oracle_mod.Oracle(m.centres, m.radii, m.probe)
-        nx, ny, nz = m.dims
-        if m.n_points < 3e6:
-            ref = o.labels_grid(m.lo, m.spacing, m.dims)
-            compare_labels(lab64[q], ref)
-            compare_edges(ed64[q], o, m.lo, m.spacing, m.dims, ref)
-        else:
-            key = ed64[q]["key"]
-            for k in np.linspace(1, nz - 3, 5).astype(int):
-                ref = o.labels_grid(m.lo, m.spacing, m.dims, int(k), int(k) + 2)
-                compare_labels(lab64[q][k:k + 2], ref)
-                sel = (key // 3) // (nx * ny) == k
-                want = oracle_mod.crossing_keys(ref)
-                want = want[(want // 3) < nx * ny] + 3 * int(k) * nx * ny
-                assert np.array_equal(key[sel], want)
-                compare_edges({f: ed64[q][f][sel] for f in ed64[q]}, o, m.lo, m.spacing, m.dims)
-
-
 def test_autotune(E, tmp_path, monkeypatch):
     from eses_inputs import molecule
     from paper_1809_04352_amd import autotune

@@ -447,3 +447,28 @@ def test_caller_allocator(E):
     for x, y in zip(la + ra, lb + rb):
         assert np.array_equal(x, y)
     assert not live, f"{len(live)} blocks not handed back"
+
+
+@pytest.mark.parametrize("batch", [False, True])
+def test_caller_allocator_out_of_memory(E, batch):
+    """A caller allocator that has no memory: eses_build_candidates returns
+    ESES_ENOMEM (with the bytes asked for in the message), for one molecule
+    and for a batch (the failure comes from a worker thread), and the library
+    works again once its own cache is restored."""
+    import torch
+    from eses_inputs import molecule
+    ms = [molecule(60, 31 + q, 0.5) for q in range(3 if batch else 1)]
+    tens = [(torch.as_tensor(m.centres, device="cuda"), torch.as_tensor(m.radii, device="cuda"))
+            for m in ms]
+    mols = [E.make_molecule(c, r, m.probe, m.spacing, m.lo, m.hi) for (c, r), m in zip(tens, ms)]
+    asked = []
+    E.set_allocator(lambda n, stream: asked.append(n) or 0, lambda p, stream: None)
+    try:
+        with pytest.raises(E.EsesError) as ei:
+            E.build_candidates(mols)
+    finally:
+        E.set_allocator()
+    assert ei.value.status == E.ESES_ENOMEM
+    assert "no memory" in str(ei.value) and asked
+    cand = E.build_candidates(mols)
+    cand.close()
