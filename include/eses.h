@@ -236,6 +236,28 @@ eses_status eses_classify(eses_candidates *c, eses_precision prec, uint8_t *cons
 eses_status eses_edge_intersections(eses_candidates *c, const uint8_t *const *labels,
                                     const eses_isect_soa *out, int64_t *counts, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc): stage 3 of a
+ * handle of ONE molecule, as eses_edge_intersections, with every temporary of
+ * its kernels (crossing-edge counts and offsets, the grouping by tile, the
+ * work queue, fallback lists, counters) cut from a static device array of
+ * 64 MiB that the library holds on each GPU it runs on until the process
+ * ends; the call allocates nothing (no hipMalloc, hipHostMalloc, hipFree or
+ * allocating library routine), and `labels` and `out` are the caller's as
+ * before.  The scratch bounds the molecule: about 2 million crossing edges
+ * at the batch's tile sizes; larger work returns ESES_ECAPACITY naming the
+ * bytes it needs, before any record is written.  Every call on a GPU shares
+ * that GPU's array and leaves its contents behind (what must start at zero is
+ * cleared by the call): calls that overlap on one GPU -- from two threads, or
+ * on two streams without ordering between them -- race and must not be made.
+ * labels: DEVICE [nx*ny*nz] as written by eses_classify; out: host
+ * descriptor of device arrays; *count (host) receives the number of crossing
+ * edges (records beyond out->capacity are dropped with ESES_ECAPACITY).
+ * ESES_EINVAL for a handle of several molecules.  Synchronises `stream`. */
+eses_status eses_edge_intersections_noalloc(eses_candidates *c, const uint8_t *labels,
+                                            const eses_isect_soa *out, int64_t *count,
+                                            void *stream);
+
 /* Work of the edge-root kernel for molecule-by-molecule statistics, counted
  * by a separate pass (not timed) over the same crossing edges. */
 typedef struct {

@@ -112,12 +112,27 @@ struct Arena {
     hipStream_t st = nullptr;   // stream the blocks are used on (new blocks allocated on it)
     hipStream_t key = nullptr;  // cache of the blocks when `keyed` (the null stream is a
     bool keyed = false;         // stream like any other), else st's
+    // carve mode: blocks are cut in order from [carve, carve + carve_cap) (a
+    // caller-provided region) and nothing is allocated or released
+    char *carve = nullptr;
+    size_t carve_cap = 0, carve_used = 0;
 
     hipStream_t cache() const { return keyed ? key : st; }
 
     template <typename T>
     eses_status alloc(T **p, long long count) {
         const size_t bytes = sizeof(T) * (size_t)(count > 0 ? count : 1);
+        if (carve) {
+            const size_t at = (carve_used + 255) & ~(size_t)255;
+            if (at + bytes > carve_cap) {
+                set_err("the work needs more than the %zu bytes of static scratch (at least %zu)",
+                        carve_cap, at + bytes);
+                return ESES_ECAPACITY;
+            }
+            carve_used = at + bytes;
+            *p = (T *)(carve + at);
+            return ESES_OK;
+        }
         int dev = 0;
         (void)hipGetDevice(&dev);
         {
@@ -168,6 +183,7 @@ struct Arena {
     }
 
     void release() {
+        carve_used = 0;
         if (blocks.empty()) return;
         for (const Block &b : blocks)
             if (b.cls < 0 && b.release) b.release(b.p, (void *)cache(), b.ctx);
@@ -356,7 +372,33 @@ struct Scalar {
     long long *out;
 };
 
+// Set while an allocation-free entry point runs on this thread: read-backs
+// then copy each scalar into host stack memory instead of the pinned slot
+// (whose first use on a thread allocates it).
+thread_local bool g_noalloc = false;
+
 eses_status read_scalars(std::initializer_list<Scalar> items, hipStream_t st) {
+    if (g_noalloc) {
+        long long v[16];
+        int q = 0;
+        for (const Scalar &it : items) {
+            if (q == 16) {
+                set_err("internal: more than 16 read-backs");
+                return ESES_EINTERNAL;
+            }
+            v[q] = 0;
+            if (it.is64) CK(hipMemcpyAsync(&v[q], it.dev, sizeof(long long), hipMemcpyDeviceToHost, st));
+            else CK(hipMemcpyAsync(&v[q], it.dev, sizeof(int), hipMemcpyDeviceToHost, st));
+            ++q;
+        }
+        CK(hipStreamSynchronize(st));
+        q = 0;
+        for (const Scalar &it : items) {
+            *it.out = it.is64 ? v[q] : (long long)(int)(v[q] & 0xffffffffLL);
+            ++q;
+        }
+        return ESES_OK;
+    }
     long long *h = readback_host();
     if (!h) {
         set_err("pinned host allocation for read-backs failed");
@@ -949,9 +991,12 @@ eses_status edges_prepare(eses_candidates *c, size_t q, const uint8_t *lab,
 }
 
 eses_status edges_one(eses_candidates *c, size_t q, const uint8_t *lab, const eses_isect_soa &o,
-                      int64_t *counts, hipStream_t st, bool timed) {
+                      int64_t *counts, hipStream_t st, bool timed, char *carve = nullptr,
+                      size_t carve_cap = 0) {
     const Mol &m = c->mols[q]->m;
     EdgePrep P;
+    P.T.carve = carve;  // temporaries cut from a static region instead of allocated
+    P.T.carve_cap = carve_cap;
     eses_status s = edges_prepare(c, q, lab, o, P, st, timed, false);
     if (s != ESES_OK) {
         P.T.release();
@@ -1087,6 +1132,45 @@ eses_status edges_batch(eses_candidates *c, const uint8_t *const *labels,
     for (int q = 0; q < nm; ++q) counts[q] = prep[q].total;
     return ESES_OK;
 }
+
+// Static device scratch of the allocation-free edge entry point: one copy per
+// GPU, held until the process ends.  Host code never passes `scratch` itself
+// (on the host it only names the symbol); the device address of each GPU's
+// copy is looked up once, with that GPU current, and used instead.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+eses_status scratch_address(char **out) {
+    static std::mutex mu;
+    static std::map<int, char *> addr;
+    int dev = 0;
+    CK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            set_err("hipGetSymbolAddress of the static scratch failed: %s", hipGetErrorString(e));
+            return ESES_EDEVICE;
+        }
+        it = addr.emplace(dev, (char *)p).first;
+    }
+    *out = it->second;
+    return ESES_OK;
+}
+
+// Marks the calling thread as inside an allocation-free entry point.
+struct NoAllocScope {
+    NoAllocScope() { g_noalloc = true; }
+    ~NoAllocScope() { g_noalloc = false; }
+};
 
 }  // namespace
 
@@ -1386,6 +1470,40 @@ eses_status eses_edge_intersections(eses_candidates *c, const uint8_t *const *la
             set_err("an output capacity is below the number of crossing edges (see counts)");
             return ESES_ECAPACITY;
         }
+    return ESES_OK;
+}
+
+eses_status eses_edge_intersections_noalloc(eses_candidates *c, const uint8_t *labels,
+                                            const eses_isect_soa *out, int64_t *count,
+                                            void *stream) {
+    g_err.clear();
+    if (!c || !labels || !out || !count) {
+        set_err("bad argument");
+        return ESES_EINVAL;
+    }
+    if (c->mols.size() != 1) {
+        set_err("the allocation-free form takes a handle of one molecule");
+        return ESES_EINVAL;
+    }
+    if (out->capacity < 0 || (out->capacity > 0 && (!out->key || !out->lambda || !out->normal ||
+                                                    !out->patch_type || !out->atoms))) {
+        set_err("bad output descriptor");
+        return ESES_EINVAL;
+    }
+    char *base = nullptr;
+    CKS(scratch_address(&base));
+    hipStream_t st = (hipStream_t)stream;
+    NoAllocScope scope;
+    eses_status s = edges_one(c, 0, labels, *out, count, st, false, base, NOALLOC_SCRATCH_BYTES);
+    if (s != ESES_OK) {
+        // work queued before the failure may still use the scratch
+        (void)hipStreamSynchronize(st);
+        return s;
+    }
+    if (*count > out->capacity) {
+        set_err("the output capacity is below the number of crossing edges (see count)");
+        return ESES_ECAPACITY;
+    }
     return ESES_OK;
 }
 

@@ -30,6 +30,7 @@ EXPORTED = [
     "eses_copy_vertices", "eses_classify", "eses_edge_intersections", "eses_free_candidates",
     "eses_last_error", "eses_version", "eses_edge_work", "eses_set_timing",
     "eses_get_kernel_times", "eses_trim_cache", "eses_set_allocator", "eses_exact_labels",
+    "eses_edge_intersections_noalloc",
 ]
 
 # C types of the caller-allocator hook (eses_set_allocator).
@@ -139,6 +140,9 @@ def load():
     lib.eses_classify.argtypes = [P, ctypes.c_int, P, ctypes.POINTER(ClassifyStats), P]
     lib.eses_edge_intersections.restype = st
     lib.eses_edge_intersections.argtypes = [P, P, ctypes.POINTER(IsectSoA), P, P]
+    lib.eses_edge_intersections_noalloc.restype = st
+    lib.eses_edge_intersections_noalloc.argtypes = [P, P, ctypes.POINTER(IsectSoA),
+                                                    ctypes.POINTER(ctypes.c_int64), P]
     lib.eses_free_candidates.restype = None
     lib.eses_free_candidates.argtypes = [P]
     lib.eses_edge_work.restype = st
@@ -314,6 +318,24 @@ def edge_intersections(cand: Candidates, labels_dev, outs, stream=None):
     if st not in (ESES_OK, ESES_ECAPACITY):
         _check(st)
     return st, [int(c) for c in counts]
+
+
+def edge_intersections_noalloc(cand: Candidates, labels_dev, out, stream=None):
+    """The allocation-free form of edge_intersections for a one-molecule handle:
+    (status, count); status is ESES_OK or ESES_ECAPACITY."""
+    soa = IsectSoA()
+    soa.key = out.key.data_ptr()
+    soa.lambda_ = out.lam.data_ptr()
+    soa.normal = out.normal.data_ptr()
+    soa.patch_type = out.patch_type.data_ptr()
+    soa.atoms = out.atoms.data_ptr()
+    soa.capacity = out.capacity
+    cnt = ctypes.c_int64()
+    st = load().eses_edge_intersections_noalloc(cand.h, labels_dev.data_ptr(), ctypes.byref(soa),
+                                                ctypes.byref(cnt), _stream_ptr(stream))
+    if st not in (ESES_OK, ESES_ECAPACITY):
+        _check(st)
+    return st, int(cnt.value)
 
 
 def edge_work(cand: Candidates, labels_dev, stream=None):
