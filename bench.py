@@ -1,15 +1,19 @@
 #!/usr/bin/env python
 """Benchmark of the ESES hot path on one MI355X.
 
-A step is one pass of the whole path over one molecule whose inputs are
+A step is one pass of the whole path over one batch of molecules (by default
+256 seeded globules of 200-20,000 atoms at 0.5 A spacing) whose inputs are
 already in HBM: eses_build_candidates (cell binning, SAS pairs and circles,
 concave probe positions, exposure flags, tile lists), eses_classify (every grid
 point) and eses_edge_intersections (every crossing edge, roots and normals).
 
-Prints one JSON line.  `value` is grid points through the whole path per
-second; the classification and intersection rates of the metric are reported
-beside it, with a roofline entry for the dominant kernel and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+Prints one JSON line.  The timed steps run the certified FP32 classification
+with FP64 recheck (and exact arbitration of the FP64-uncertain points); `value`
+is grid points through the whole path per second in that form.  The same steps
+in plain FP64 are timed after it and reported beside (`fp64`), with the ratio of
+the two; the classification and intersection rates of the metric, a roofline
+entry for the dominant kernel and the FP64 CPU oracle timed on a bounded sample
+of the same workload complete the line.
 """
 from __future__ import annotations
 
@@ -24,7 +28,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "grid points classified/s + edge intersections/s; batched FP32+FP64-recheck vs FP64"
-DEFAULT_WORKLOAD = "globule5000_h0.25"
+DEFAULT_WORKLOAD = "batch256_h0.5"
 
 # MI355X FP64 vector peak: 256 CUs x 128 FP64 flop/clock (64 FMA lanes) x 2.4 GHz.
 PEAK_FP64_TFLOPS = 78.6
@@ -64,7 +68,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
-    ap.add_argument("--prec", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--prec", choices=["both", "fp64", "fp32"], default="both",
+                    help="both: timed FP32+recheck steps (value), then FP64 steps beside")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
@@ -74,18 +79,13 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(m, n_crossings, target_s):
-    """The FP64 oracle on a bounded, evenly strided sample of z-slices."""
+def cpu_sample(o, m, budget_s, orc):
+    """Labels and crossing-edge records of the oracle `o` on evenly spaced
+    z-slice pairs of molecule m, about budget_s seconds of CPU work.  Returns
+    (points, label seconds, edges, edge seconds, slice pairs)."""
     import numpy as np
-    from oracle import oracle as orc
-
-    orc.build(force=False)
     nx, ny, nz = m.dims
-    t0 = time.perf_counter()
-    o = orc.Oracle(m.centres, m.radii, m.probe)
-    t_create = time.perf_counter() - t0
-    # time one pair of middle slices to pick the stride
-    mid = nz // 2
+    mid = max(0, nz // 2 - 1)
     t0 = time.perf_counter()
     L = o.labels_grid(m.lo, m.spacing, m.dims, mid, mid + 2)
     t_pair_lab = time.perf_counter() - t0
@@ -94,8 +94,8 @@ def cpu_baseline(m, n_crossings, target_s):
     t0 = time.perf_counter()
     o.edges(m.lo, m.spacing, m.dims, keys)
     t_pair_edge = time.perf_counter() - t0
-    per_pair = max(t_pair_lab + t_pair_edge, 1e-3)
-    n_pairs = int(max(1, min(nz // 2, target_s / per_pair)))
+    per_pair = max(t_pair_lab + t_pair_edge, 1e-4)
+    n_pairs = int(max(1, min(nz // 2, budget_s / per_pair)))
     ks = np.linspace(0, nz - 2, n_pairs).astype(int)
     t_lab = t_edge = 0.0
     pts = edges = 0
@@ -112,17 +112,70 @@ def cpu_baseline(m, n_crossings, target_s):
         o.edges(m.lo, m.spacing, m.dims, kk_full)
         t_edge += time.perf_counter() - t0
         edges += len(kk)
-    t_full = t_create + t_lab / pts * m.n_points + (t_edge / max(edges, 1)) * n_crossings
+    return pts, t_lab, edges, t_edge, len(ks)
+
+
+def cpu_baseline(mols_np, counts, target_s):
+    """The FP64 oracle on a bounded sample of the same workload, extrapolated
+    to all of it: for a batch, twelve molecules at evenly spaced ranks of size
+    (smallest to largest), each built whole (probe enumeration) and labelled,
+    with its crossing edges solved, on evenly spaced z-slice pairs; the time
+    per atom of the builds, per point of the labels and per crossing of the
+    edges, pooled over the sample, times the workload's atoms, points and
+    crossings."""
+    import platform
+
+    import numpy as np
+    from oracle import oracle as orc
+
+    orc.build(force=False)
+    order = np.argsort([m.n_atoms for m in mols_np], kind="stable")
+    pick = sorted(set(int(order[int(round(f * (len(order) - 1)))])
+                      for f in np.linspace(0.0, 1.0, 12)))
+    t_create = t_lab = t_edge = 0.0
+    atoms = pts = edges = pairs = 0
+    per_mol = target_s / len(pick)
+    for q in pick:
+        m = mols_np[q]
+        t0 = time.perf_counter()
+        o = orc.Oracle(m.centres, m.radii, m.probe)
+        tc = time.perf_counter() - t0
+        p, tl, e, te, npair = cpu_sample(o, m, max(per_mol - tc, 0.05), orc)
+        del o
+        t_create += tc
+        atoms += m.n_atoms
+        t_lab += tl
+        pts += p
+        t_edge += te
+        edges += e
+        pairs += npair
+    n_atoms = sum(m.n_atoms for m in mols_np)
+    n_points = sum(m.n_points for m in mols_np)
+    n_cross = sum(counts)
+    t_full = (t_create / atoms * n_atoms + t_lab / pts * n_points
+              + (t_edge / max(edges, 1)) * n_cross)
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        cpu = platform.processor() or cpu
+    what = (f"molecules {pick} of {len(mols_np)}" if len(mols_np) > 1 else "the molecule")
     return {
-        "value": m.n_points / t_full,
+        "value": n_points / t_full,
         "unit": "grid points/s",
         "cores": orc.threads(),
+        "cpu_model": cpu,
         "kind": "oracle",
-        "sample": (f"whole-molecule probe enumeration ({t_create:.2f} s) + labels of {pts} points "
-                   f"in {len(ks)} evenly spaced slice pairs ({t_lab:.2f} s) + {edges} crossing "
-                   f"edges there ({t_edge:.2f} s), extrapolated to {m.n_points} points and "
-                   f"{n_crossings} crossings"),
+        "sample": (f"{what} ({atoms} atoms): whole-molecule probe enumeration "
+                   f"({t_create:.2f} s) + labels of {pts} points in {pairs} evenly spaced slice "
+                   f"pairs ({t_lab:.2f} s) + {edges} crossing edges there ({t_edge:.2f} s); "
+                   f"per-atom, per-point and per-crossing times extrapolated to {n_atoms} atoms, "
+                   f"{n_points} points and {n_cross} crossings"),
         "seconds": t_create + t_lab + t_edge,
+        "extrapolated_seconds": t_full,
         "classify_pts_per_s": pts / t_lab,
         "isect_per_s": edges / max(t_edge, 1e-9),
     }
@@ -138,6 +191,10 @@ def load_workload(name):
     return [workload(name)]
 
 
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (packed instructions)
+PEAK_HBM_GBS = 8000.0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -151,7 +208,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     eses.load()
-    prec = eses.ESES_FP64 if args.prec == "fp64" else eses.ESES_FP32_RECHECK
+    precs = {"both": [eses.ESES_FP32_RECHECK, eses.ESES_FP64],
+             "fp32": [eses.ESES_FP32_RECHECK], "fp64": [eses.ESES_FP64]}[args.prec]
+    pname = {eses.ESES_FP32_RECHECK: "fp32", eses.ESES_FP64: "fp64"}
     mols_np = load_workload(args.workload)
     dev = torch.device("cuda:0")
     tens = [(torch.as_tensor(m.centres, device=dev), torch.as_tensor(m.radii, device=dev))
@@ -165,7 +224,8 @@ def main():
     # sizing pass (outside the timed region): output capacities and work counts
     cand = eses.build_candidates(mols)
     infos = [cand.info(q) for q in range(len(mols))]
-    work = eses.classify(cand, prec, labels, stats=True)
+    work = eses.classify(cand, eses.ESES_FP64, labels, stats=True)
+    work32 = eses.classify(cand, eses.ESES_FP32_RECHECK, labels, stats=True)
     probe_out = [eses.alloc_isect(1) for _ in mols]
     _, counts = eses.edge_intersections(cand, labels, probe_out)
     ework = eses.edge_work(cand, labels)
@@ -177,102 +237,145 @@ def main():
         return sum(d[key] for d in dicts)
 
     flops_classify = sum(FLOPS_PER_TEST[k] * total(work, k) for k in FLOPS_PER_TEST)
+    flops_atom = FLOPS_PER_TEST["tests_atom"] * total(work, "tests_atom")
     flops_edges = sum(FLOPS_EDGE[k] * total(ework, k) for k in FLOPS_EDGE)
 
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    stage = {"build": [], "classify": [], "edges": []}
-    kern = {"classify_ms": [], "edge_detect_ms": [], "edge_roots_ms": []}
 
-    def step(record):
-        if record:
-            ev[0].record(stream)
-        c = eses.build_candidates(mols)
-        if record:
-            ev[1].record(stream)
-        eses.classify(c, prec, labels)
-        if record:
-            ev[2].record(stream)
-        st, cnt = eses.edge_intersections(c, labels, outs)
-        if record:
-            ev[3].record(stream)
-            kt = eses.kernel_times(c)
-        c.close()
-        if st != eses.ESES_OK or sum(cnt) != n_cross:
-            raise RuntimeError("unexpected edge count")
-        if record:
-            torch.cuda.synchronize()
-            stage["build"].append(ev[0].elapsed_time(ev[1]))
-            stage["classify"].append(ev[1].elapsed_time(ev[2]))
-            stage["edges"].append(ev[2].elapsed_time(ev[3]))
-            for k in kern:
-                kern[k].append(kt[k])
+    def measure(prec):
+        stage = {"build": [], "classify": [], "edges": []}
+        kern = {"classify_ms": [], "edge_detect_ms": [], "edge_roots_ms": []}
 
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(False)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = 1e3 * wall / args.steps
-    # per-stage and per-kernel HIP-event timing in separate steps, so the
-    # event reads do not disturb the timed loop
-    eses.set_timing(True)
-    for _ in range(max(3, min(args.steps, 10))):
-        step(True)
-    eses.set_timing(False)
-    med = {k: float(np.median(v)) for k, v in stage.items()}
-    kmed = {k: float(np.median(v)) for k, v in kern.items()}
+        def step(record):
+            if record:
+                ev[0].record(stream)
+            c = eses.build_candidates(mols)
+            if record:
+                ev[1].record(stream)
+            eses.classify(c, prec, labels)
+            if record:
+                ev[2].record(stream)
+            st, cnt = eses.edge_intersections(c, labels, outs)
+            if record:
+                ev[3].record(stream)
+                kt = eses.kernel_times(c)
+            c.close()
+            if st != eses.ESES_OK or sum(cnt) != n_cross:
+                raise RuntimeError("unexpected edge count")
+            if record:
+                torch.cuda.synchronize()
+                stage["build"].append(ev[0].elapsed_time(ev[1]))
+                stage["classify"].append(ev[1].elapsed_time(ev[2]))
+                stage["edges"].append(ev[2].elapsed_time(ev[3]))
+                for k in kern:
+                    kern[k].append(kt[k])
 
+        for _ in range(args.warmup):
+            step(False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = 1e3 * wall / args.steps
+        # per-stage and per-kernel HIP-event timing in separate steps, so the
+        # event reads do not disturb the timed loop
+        eses.set_timing(True)
+        for _ in range(max(3, min(args.steps, 10))):
+            step(True)
+        eses.set_timing(False)
+        med = {k: float(np.median(v)) for k, v in stage.items()}
+        kmed = {k: float(np.median(v)) for k, v in kern.items()}
+        return {"ms_per_step": ms, "value": npts / (ms * 1e-3),
+                "classify_pts_per_s": npts / (kmed["classify_ms"] * 1e-3),
+                "isect_per_s": n_cross / (med["edges"] * 1e-3),
+                "stages_ms": med, "kernels_ms": kmed}
+
+    runs = {}
+    for p in precs:
+        runs[pname[p]] = measure(p)
+    main_p = pname[precs[0]]
+    R = runs[main_p]
+    kmed = R["kernels_ms"]
+    batch = len(mols) > 1
     rl = {}
     for name, fl, t in (("classify", flops_classify, kmed["classify_ms"]),
                         ("edge_roots", flops_edges, kmed["edge_roots_ms"])):
         a = fl / (t * 1e-3) / 1e12
         kname = "k_classify" if name == "classify" else "k_edge_chunks"
-        if len(mols) > 1:
+        if batch:
             kname += "_batch"  # the fused launches of a batch
-        rl[name] = {"kernel": kname,
-                    "bound": "alu", "achieved": a, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                    "frac": a / PEAK_FP64_TFLOPS, "traffic": None, "algorithmic_flops": fl,
-                    "ms": t}
+        peak = PEAK_FP64_TFLOPS
+        if name == "classify" and main_p == "fp32":
+            # phase-1 ball tests in FP32, the rest in FP64: the peak of this
+            # mix is the rate at which the vector units could retire it
+            f32, f64 = flops_atom, fl - flops_atom
+            peak = fl / (f32 / PEAK_FP32_TFLOPS + f64 / PEAK_FP64_TFLOPS)
+        rl[name] = {"kernel": kname, "bound": "alu", "achieved": a, "peak": peak,
+                    "unit": "TFLOP/s", "frac": a / peak, "traffic": None,
+                    "algorithmic_flops": fl, "ms": t}
     for v in rl.values():
-        v["traffic"] = profiled_traffic(v["kernel"], args.workload, args.prec)
+        prof = profiled_counters(v["kernel"], args.workload, main_p)
+        if prof:
+            v["traffic"] = prof.get("HBM bytes per launch")
+            if v["traffic"]:
+                gbs = v["traffic"] / (v["ms"] * 1e-3) / 1e9
+                v["hbm_gbs"] = gbs
+                v["hbm_frac"] = gbs / PEAK_HBM_GBS
+            for k in ("measured FP32 flops per launch", "measured FP64 flops per launch"):
+                if prof.get(k) is not None:
+                    v[k.replace(" ", "_")] = prof[k]
+            f32 = prof.get("measured FP32 flops per launch")
+            f64 = prof.get("measured FP64 flops per launch")
+            if f32 is not None and f64 is not None:
+                t = v["ms"] * 1e-3
+                v["mixed_precision_frac"] = (f32 / (PEAK_FP32_TFLOPS * 1e12)
+                                             + f64 / (PEAK_FP64_TFLOPS * 1e12)) / t
+                v["wasted_work_ratio"] = (f32 + f64) / v["algorithmic_flops"]
     dominant = max(rl, key=lambda k: rl[k]["ms"])
     roof = dict(rl[dominant])
-    single = len(mols_np) == 1
     m0 = mols_np[0]
     config = {"workload": args.workload, "molecules": len(mols_np),
               "atoms": sum(m.n_atoms for m in mols_np), "probe": m0.probe,
-              "spacing": m0.spacing, "points": npts, "precision": args.prec, "tile": 8}
-    if single:
+              "spacing": m0.spacing, "points": npts, "precision": main_p, "tile": 8,
+              "blocks_per_cu": 0}
+    if not batch:
         config["dims"] = list(dims[0])
     res = {
         "metric": METRIC,
-        "value": npts / (ms * 1e-3),
+        "value": R["value"],
         "unit": "grid points/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": R["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.prec == "fp64" else "f32+f64",
+        "dtype": "f64" if main_p == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": config,
-        "classify_pts_per_s": npts / (kmed["classify_ms"] * 1e-3),
-        "isect_per_s": n_cross / (med["edges"] * 1e-3),
+        "classify_pts_per_s": R["classify_pts_per_s"],
+        "isect_per_s": R["isect_per_s"],
         "crossings": n_cross,
-        "stages_ms": med,
+        "stages_ms": R["stages_ms"],
         "kernels_ms": kmed,
+        "rechecked_points": total(work32, "n_rechecked"),
+        "exact_points": {"fp32": total(work32, "n_exact"), "fp64": total(work, "n_exact")},
         "classify_work": {k: total(work, k) for k in work[0]},
         "edge_work": {k: total(ework, k) for k in ework[0]},
         "roofline": roof,
         "roofline_other": {k: v for k, v in rl.items() if k != dominant},
     }
-    if single:
+    if "fp64" in runs and main_p != "fp64":
+        F = runs["fp64"]
+        res["fp64"] = F
+        res["fp32_vs_fp64"] = {
+            "step": F["ms_per_step"] / R["ms_per_step"],
+            "classify": F["kernels_ms"]["classify_ms"] / kmed["classify_ms"]}
+    if not batch:
         res["candidates"] = {k: (list(v) if isinstance(v, tuple) else v)
                              for k, v in infos[0].items()}
     res["ses"] = ses_per_atom(mols_np, work, outs, counts)
@@ -284,8 +387,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         res["calibrate_copy_bytes"] = nbytes
-    if not args.no_cpu_baseline and single:
-        res["cpu_baseline"] = cpu_baseline(m0, n_cross, args.cpu_seconds)
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(mols_np, counts, args.cpu_seconds)
     print(json.dumps(res))
 
 
@@ -321,9 +424,10 @@ def kernel_sources_digest(kernel):
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(kernel, workload, prec):
-    """HBM bytes per launch from a committed PMC summary of this exact kernel
-    source (profiles/pmc_<kernel>_<workload>_<prec>.md), else None."""
+def profiled_counters(kernel, workload, prec):
+    """Figures of a committed PMC summary of this exact kernel source
+    (profiles/pmc_<kernel>_<workload>_<prec>.md: lines "- name: value"),
+    or None when there is none or the kernel's sources changed since."""
     path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}_{prec}.md")
     if not os.path.exists(path):
         return None
@@ -335,10 +439,13 @@ def profiled_traffic(kernel, workload, prec):
             vals[k.strip()] = v.strip().strip("`")
     if vals.get("sources digest") != digest:
         return None
-    try:
-        return float(vals["HBM bytes per launch"])
-    except (KeyError, ValueError):
-        return None
+    out = {}
+    for k, v in vals.items():
+        try:
+            out[k] = float(v)
+        except ValueError:
+            pass
+    return out
 
 
 if __name__ == "__main__":
