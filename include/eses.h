@@ -236,6 +236,20 @@ eses_status eses_classify(eses_candidates *c, eses_precision prec, uint8_t *cons
 eses_status eses_edge_intersections(eses_candidates *c, const uint8_t *const *labels,
                                     const eses_isect_soa *out, int64_t *counts, void *stream);
 
+/* Cavity-filled variant (the exterior-only reading of section 1's probe
+ * balls "outside" the molecule, where the paper leaves open whether probes in
+ * enclosed cavities count): in place on the labels of eses_classify, every
+ * outside grid point (label 0) that no path of axis-adjacent outside points
+ * joins to the grid's boundary faces becomes inside (1); the other labels are
+ * unchanged.  Crossing records computed from the filled labels by
+ * eses_edge_intersections then bound the molecule without its cavities.
+ * labels: host array of n_mols DEVICE pointers (as for eses_classify);
+ * n_filled: host [n_mols] or NULL, receives the points filled per molecule.
+ * A flood fill from the boundary over 8^3 tiles in LDS, repeated until no
+ * tile changes (one read-back per pass).  Synchronises `stream`. */
+eses_status eses_fill_cavities(eses_candidates *c, uint8_t *const *labels, int64_t *n_filled,
+                               void *stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, hosts that forbid hipMalloc): stage 3 of a
  * handle of ONE molecule, as eses_edge_intersections, with every temporary of

@@ -232,3 +232,22 @@ def crossing_keys(labels):
     k = np.concatenate(keys)
     k.sort()
     return k
+
+
+def fill_cavities(labels):
+    """Cavity-filled labels [nz, ny, nx]: outside points (0) in 6-connected
+    components of outside points that touch no boundary face of the grid
+    become inside (1).  Returns (filled labels, number filled)."""
+    from scipy import ndimage
+    L = np.asarray(labels, dtype=np.uint8)
+    out = L.copy()
+    comp, n = ndimage.label(L == 0, structure=ndimage.generate_binary_structure(3, 1))
+    if n == 0:
+        return out, 0
+    border = np.zeros(n + 1, dtype=bool)
+    for face in (comp[0], comp[-1], comp[:, 0], comp[:, -1], comp[:, :, 0], comp[:, :, -1]):
+        border[np.unique(face)] = True
+    border[0] = True  # the inside points
+    enclosed = ~border[comp]
+    out[enclosed] = 1
+    return out, int(enclosed.sum())

@@ -220,6 +220,8 @@ struct eses_candidates {
     int *head = nullptr;
     uint8_t **labels_dev = nullptr;
     int *unc_counts = nullptr;  // [n_mols] gathered uncertain-point counts
+    int2 *fill_units = nullptr;  // (molecule, 8^3 tile) units of the cavity fill
+    long long n_fill_units = 0;
     long long nunits = 0;
     int batch_blocks[2] = {0, 0};  // persistent classification grid: FP64, FP32
     int blocks_per_cu = 0;
@@ -1504,6 +1506,87 @@ eses_status eses_edge_intersections_noalloc(eses_candidates *c, const uint8_t *l
         set_err("the output capacity is below the number of crossing edges (see count)");
         return ESES_ECAPACITY;
     }
+    return ESES_OK;
+}
+
+eses_status eses_fill_cavities(eses_candidates *c, uint8_t *const *labels, int64_t *n_filled,
+                               void *stream) {
+    g_err.clear();
+    if (!c || !labels) {
+        set_err("bad handle or labels");
+        return ESES_EINVAL;
+    }
+    const int nm = (int)c->mols.size();
+    for (int q = 0; q < nm; ++q)
+        if (!labels[q]) {
+            set_err("labels[%d] is NULL", q);
+            return ESES_EINVAL;
+        }
+    hipStream_t st = (hipStream_t)stream;
+    Arena T;
+    T.st = st;
+    int *changed;
+    unsigned long long *filled;
+    eses_status s;
+    if ((s = T.alloc(&changed, 1)) != ESES_OK || (s = T.alloc(&filled, nm)) != ESES_OK) {
+        T.release();
+        return s;
+    }
+    auto fail = [&](hipError_t e) {
+        (void)hipStreamSynchronize(st);
+        T.release();
+        set_err("cavity fill: %s", hipGetErrorString(e));
+        return ESES_EDEVICE;
+    };
+    hipError_t e = fill_u32((uint32_t *)filled, 2LL * nm, 0u, st);
+    for (int q = 0; q < nm && e == hipSuccess; ++q) e = launch_fill_seed(labels[q], c->mols[q]->m.dims, st);
+    if (e == hipSuccess && nm > 1) {
+        e = hipMemcpyAsync(c->labels_dev, labels, sizeof(uint8_t *) * nm, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && !c->fill_units) {
+            std::vector<int2> u;
+            for (int q = 0; q < nm; ++q) {
+                const Mol &m = c->mols[q]->m;
+                long long nt = 1;
+                for (int a = 0; a < 3; ++a) nt *= (m.dims[a] + 7) / 8;
+                for (long long t = 0; t < nt; ++t) u.push_back(make_int2(q, (int)t));
+            }
+            if (c->batch.alloc(&c->fill_units, (long long)u.size()) != ESES_OK) {
+                T.release();
+                return ESES_ENOMEM;
+            }
+            e = hipMemcpyAsync(c->fill_units, u.data(), sizeof(int2) * u.size(),
+                               hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);  // u is released on return
+            c->n_fill_units = (long long)u.size();
+        }
+    }
+    // passes until no tile changes (each pass reaches at least one new point
+    // while any is left to reach, so the loop ends)
+    for (long long pass = 0; e == hipSuccess; ++pass) {
+        e = fill_i32(changed, 1, 0, st);
+        if (e != hipSuccess) break;
+        if (nm == 1) e = launch_fill_pass1(labels[0], c->mols[0]->m.dims, changed, st);
+        else e = launch_fill_pass(c->mols_dev, c->labels_dev, c->fill_units, (int)c->n_fill_units,
+                                  changed, st);
+        if (e != hipSuccess) break;
+        long long ch = 0;
+        if ((s = read_scalars({{changed, false, &ch}}, st)) != ESES_OK) {
+            T.release();
+            return s;
+        }
+        if (!ch) break;
+    }
+    for (int q = 0; q < nm && e == hipSuccess; ++q)
+        e = launch_fill_finish(labels[q], c->mols[q]->m.npts, filled + q, st);
+    std::vector<unsigned long long> h((size_t)nm);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h.data(), filled, sizeof(unsigned long long) * nm, hipMemcpyDeviceToHost,
+                           st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(e);
+    T.release();
+    if (n_filled)
+        for (int q = 0; q < nm; ++q) n_filled[q] = (int64_t)h[(size_t)q];
     return ESES_OK;
 }
 

@@ -155,6 +155,17 @@ hipError_t launch_edge_roots_batch(const Mol *mols, const EdgeJob *jobs, int nj,
 
 constexpr int EDGE_WORK_COUNTERS = 16;
 
+// cavity filling (fill.hip): boundary seeds of one molecule's labels; passes
+// over 8^3 tiles until *changed stays 0 (zeroed by the caller before each
+// pass) -- for a batch over (molecule, 8^3 tile) units; then 0 -> 1 (counted
+// in *filled) and 2 -> 0.
+hipError_t launch_fill_seed(uint8_t *L, const int dims[3], hipStream_t st);
+hipError_t launch_fill_pass(const Mol *mols_dev, uint8_t *const *labels_dev, const int2 *units,
+                            int nunits, int *changed, hipStream_t st);
+hipError_t launch_fill_pass1(uint8_t *L, const int dims[3], int *changed, hipStream_t st);
+hipError_t launch_fill_finish(uint8_t *L, long long n, unsigned long long *filled,
+                              hipStream_t st);
+
 // vertex export
 hipError_t launch_export_vertices(const Mol &m, double *p, int *atoms, int8_t *sign,
                                   long long count, hipStream_t st);

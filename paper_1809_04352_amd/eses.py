@@ -30,7 +30,7 @@ EXPORTED = [
     "eses_copy_vertices", "eses_classify", "eses_edge_intersections", "eses_free_candidates",
     "eses_last_error", "eses_version", "eses_edge_work", "eses_set_timing",
     "eses_get_kernel_times", "eses_trim_cache", "eses_set_allocator", "eses_exact_labels",
-    "eses_edge_intersections_noalloc",
+    "eses_edge_intersections_noalloc", "eses_fill_cavities",
 ]
 
 # C types of the caller-allocator hook (eses_set_allocator).
@@ -143,6 +143,8 @@ def load():
     lib.eses_edge_intersections_noalloc.restype = st
     lib.eses_edge_intersections_noalloc.argtypes = [P, P, ctypes.POINTER(IsectSoA),
                                                     ctypes.POINTER(ctypes.c_int64), P]
+    lib.eses_fill_cavities.restype = st
+    lib.eses_fill_cavities.argtypes = [P, P, P, P]
     lib.eses_free_candidates.restype = None
     lib.eses_free_candidates.argtypes = [P]
     lib.eses_edge_work.restype = st
@@ -336,6 +338,15 @@ def edge_intersections_noalloc(cand: Candidates, labels_dev, out, stream=None):
     if st not in (ESES_OK, ESES_ECAPACITY):
         _check(st)
     return st, int(cnt.value)
+
+
+def fill_cavities(cand: Candidates, labels_dev, stream=None):
+    """Cavity-filled labels, in place; returns the points filled per molecule."""
+    n = len(labels_dev)
+    ptrs = (ctypes.c_void_p * n)(*[t.data_ptr() for t in labels_dev])
+    out = (ctypes.c_int64 * n)()
+    _check(load().eses_fill_cavities(cand.h, ptrs, out, _stream_ptr(stream)))
+    return [int(v) for v in out]
 
 
 def edge_work(cand: Candidates, labels_dev, stream=None):
