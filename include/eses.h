@@ -236,6 +236,35 @@ eses_status eses_classify(eses_candidates *c, eses_precision prec, uint8_t *cons
 eses_status eses_edge_intersections(eses_candidates *c, const uint8_t *const *labels,
                                     const eses_isect_soa *out, int64_t *counts, void *stream);
 
+/* Surface mesh, area and volume of each molecule (section 2.2: the Eulerian
+ * output is turned into a triangle mesh by marching cubes; the appendix table
+ * reports each complex's SES area and volume).  Every cube of eight
+ * axis-adjacent grid points with mixed labels is cut by the triangles of its
+ * configuration; a triangle's corners are crossing points of the cube's edges
+ * (the records of eses_edge_intersections).  The case table follows one rule
+ * (on a face with four crossings, each inside corner is cut off), so
+ * neighbouring cubes agree on their shared faces and the mesh is closed,
+ * every edge shared by two triangles of opposite orientation; triangles are
+ * oriented with normals out of M.  area = sum of triangle areas, volume =
+ * divergence theorem over the mesh.
+ * labels, isect, counts: as filled by eses_classify and
+ * eses_edge_intersections (every crossing record present, else ESES_EINVAL).
+ * triangles: NULL, or a host array of n_mols DEVICE pointers [cap][3] int32
+ * that receive each triangle's corners as indices into the molecule's
+ * records, with tri_capacity (host [n_mols]) their capacities; stats: host
+ * [n_mols].  Triangles beyond a capacity are dropped with ESES_ECAPACITY
+ * (n_triangles holds the required count).  Synchronises `stream`. */
+typedef struct {
+    double area;          /* angstrom^2 */
+    double volume;        /* angstrom^3 */
+    int64_t n_triangles;
+} eses_mesh_stats;
+
+eses_status eses_mesh(eses_candidates *c, const uint8_t *const *labels,
+                      const eses_isect_soa *isect, const int64_t *counts,
+                      int32_t *const *triangles, const int64_t *tri_capacity,
+                      eses_mesh_stats *stats, void *stream);
+
 /* Cavity-filled variant (the exterior-only reading of section 1's probe
  * balls "outside" the molecule, where the paper leaves open whether probes in
  * enclosed cavities count): in place on the labels of eses_classify, every

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libeses_gfx950.so")
 
-SOURCES = ["build.hip", "classify.hip", "edges.hip", "fill.hip", "abi.cpp", "exact.cpp"]
+SOURCES = ["build.hip", "classify.hip", "edges.hip", "fill.hip", "mesh.hip", "abi.cpp", "exact.cpp"]
 
 # Packed FP32 instructions stay disabled; the compiler would otherwise form
 # them from ordinary float code.  Multiply-adds are fused only within one

@@ -1509,6 +1509,85 @@ eses_status eses_edge_intersections_noalloc(eses_candidates *c, const uint8_t *l
     return ESES_OK;
 }
 
+eses_status eses_mesh(eses_candidates *c, const uint8_t *const *labels,
+                      const eses_isect_soa *isect, const int64_t *counts,
+                      int32_t *const *triangles, const int64_t *tri_capacity,
+                      eses_mesh_stats *stats, void *stream) {
+    g_err.clear();
+    if (!c || !labels || !isect || !counts || !stats || (triangles && !tri_capacity)) {
+        set_err("bad argument");
+        return ESES_EINVAL;
+    }
+    const int nm = (int)c->mols.size();
+    hipStream_t st = (hipStream_t)stream;
+    bool short_cap = false;
+    for (int q = 0; q < nm; ++q) {
+        const Mol &m = c->mols[q]->m;
+        if (!labels[q] || counts[q] < 0 || counts[q] > isect[q].capacity ||
+            (counts[q] > 0 && (!isect[q].key || !isect[q].lambda))) {
+            set_err("molecule %d: labels or records missing (count beyond capacity?)", q);
+            return ESES_EINVAL;
+        }
+        Arena T;
+        T.st = st;
+        double *out;
+        int *cnt, *bad;
+        long long *boff, *tmp;
+        const long long nb = (m.npts + 255) / 256;
+        eses_status s;
+        if ((s = T.alloc(&out, 2)) != ESES_OK || (s = T.alloc(&cnt, nb + 1)) != ESES_OK ||
+            (s = T.alloc(&bad, 1)) != ESES_OK || (s = T.alloc(&boff, nb + 2)) != ESES_OK ||
+            (s = T.alloc(&tmp, scan_tmp_elems(nb) + 64)) != ESES_OK) {
+            T.release();
+            return s;
+        }
+        long long nblk = 0, total = 0, hbad = 0;
+        double h[2] = {0.0, 0.0};
+        hipError_t e = fill_u32((uint32_t *)out, 4, 0u, st);
+        if (e == hipSuccess) e = fill_i32(bad, 1, 0, st);
+        if (e == hipSuccess)
+            e = launch_mesh(m, labels[q], (const long long *)isect[q].key, isect[q].lambda, counts[q],
+                            out, cnt, bad, &nblk, st);
+        if (e == hipSuccess) e = scan_i64(cnt, nblk, boff, tmp, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(h, out, sizeof(h), hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(st);
+            T.release();
+            set_err("mesh: %s", hipGetErrorString(e));
+            return ESES_EDEVICE;
+        }
+        if ((s = read_scalars({{boff + nblk, true, &total}, {bad, false, &hbad}}, st)) != ESES_OK) {
+            T.release();
+            return s;
+        }
+        if (hbad) {
+            T.release();
+            set_err("molecule %d: %lld cut cube edges without a crossing record", q, hbad);
+            return ESES_EINVAL;
+        }
+        stats[q].area = h[0];
+        stats[q].volume = h[1];
+        stats[q].n_triangles = total;
+        if (triangles && triangles[q] && tri_capacity[q] > 0) {
+            e = launch_mesh_write(m, labels[q], (const long long *)isect[q].key, isect[q].lambda,
+                                  counts[q], boff, tri_capacity[q], triangles[q], st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) {
+                T.release();
+                set_err("mesh: %s", hipGetErrorString(e));
+                return ESES_EDEVICE;
+            }
+        }
+        if (triangles && total > tri_capacity[q]) short_cap = true;
+        T.release();
+    }
+    if (short_cap) {
+        set_err("a triangle capacity is below the number of triangles (see n_triangles)");
+        return ESES_ECAPACITY;
+    }
+    return ESES_OK;
+}
+
 eses_status eses_fill_cavities(eses_candidates *c, uint8_t *const *labels, int64_t *n_filled,
                                void *stream) {
     g_err.clear();

@@ -155,6 +155,18 @@ hipError_t launch_edge_roots_batch(const Mol *mols, const EdgeJob *jobs, int nj,
 
 constexpr int EDGE_WORK_COUNTERS = 16;
 
+// marching-cubes mesh (mesh.hip): per block of cubes, the triangle counts
+// (counts[*nblocks]) and the sums of area and volume into out[0..1]
+// (zeroed by the caller); records missing for a cut edge counted in *bad.
+// The write pass puts the triangles (record indices) at the scanned block
+// offsets boff.
+hipError_t launch_mesh(const Mol &m, const uint8_t *L, const long long *key, const double *lam,
+                       long long nrec, double *out, int *counts, int *bad, long long *nblocks,
+                       hipStream_t st);
+hipError_t launch_mesh_write(const Mol &m, const uint8_t *L, const long long *key,
+                             const double *lam, long long nrec, const long long *boff,
+                             long long cap, int *tri, hipStream_t st);
+
 // cavity filling (fill.hip): boundary seeds of one molecule's labels; passes
 // over 8^3 tiles until *changed stays 0 (zeroed by the caller before each
 // pass) -- for a batch over (molecule, 8^3 tile) units; then 0 -> 1 (counted

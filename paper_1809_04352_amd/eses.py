@@ -30,7 +30,7 @@ EXPORTED = [
     "eses_copy_vertices", "eses_classify", "eses_edge_intersections", "eses_free_candidates",
     "eses_last_error", "eses_version", "eses_edge_work", "eses_set_timing",
     "eses_get_kernel_times", "eses_trim_cache", "eses_set_allocator", "eses_exact_labels",
-    "eses_edge_intersections_noalloc", "eses_fill_cavities",
+    "eses_edge_intersections_noalloc", "eses_fill_cavities", "eses_mesh",
 ]
 
 # C types of the caller-allocator hook (eses_set_allocator).
@@ -103,6 +103,11 @@ class KernelTimes(ctypes.Structure):
                 ("edge_roots_ms", ctypes.c_double)]
 
 
+class MeshStats(ctypes.Structure):
+    _fields_ = [("area", ctypes.c_double), ("volume", ctypes.c_double),
+                ("n_triangles", ctypes.c_int64)]
+
+
 class IsectSoA(ctypes.Structure):
     _fields_ = [("key", ctypes.c_void_p), ("lambda_", ctypes.c_void_p),
                 ("normal", ctypes.c_void_p), ("patch_type", ctypes.c_void_p),
@@ -143,6 +148,9 @@ def load():
     lib.eses_edge_intersections_noalloc.restype = st
     lib.eses_edge_intersections_noalloc.argtypes = [P, P, ctypes.POINTER(IsectSoA),
                                                     ctypes.POINTER(ctypes.c_int64), P]
+    lib.eses_mesh.restype = st
+    lib.eses_mesh.argtypes = [P, P, ctypes.POINTER(IsectSoA), P, P, P,
+                              ctypes.POINTER(MeshStats), P]
     lib.eses_fill_cavities.restype = st
     lib.eses_fill_cavities.argtypes = [P, P, P, P]
     lib.eses_free_candidates.restype = None
@@ -338,6 +346,36 @@ def edge_intersections_noalloc(cand: Candidates, labels_dev, out, stream=None):
     if st not in (ESES_OK, ESES_ECAPACITY):
         _check(st)
     return st, int(cnt.value)
+
+
+def _soa(outs):
+    soa = (IsectSoA * len(outs))()
+    for q, o in enumerate(outs):
+        soa[q].key = o.key.data_ptr()
+        soa[q].lambda_ = o.lam.data_ptr()
+        soa[q].normal = o.normal.data_ptr()
+        soa[q].patch_type = o.patch_type.data_ptr()
+        soa[q].atoms = o.atoms.data_ptr()
+        soa[q].capacity = o.capacity
+    return soa
+
+
+def mesh(cand: Candidates, labels_dev, outs, counts, triangles=None, stream=None):
+    """Marching-cubes mesh of each molecule from its labels and crossing records:
+    returns [dict(area, volume, n_triangles)]; with triangles (a list of device
+    int32 tensors [cap, 3]) the triangles' record indices are written too."""
+    n = len(labels_dev)
+    ptrs = (ctypes.c_void_p * n)(*[t.data_ptr() for t in labels_dev])
+    cnt = (ctypes.c_int64 * n)(*[int(k) for k in counts])
+    st = (MeshStats * n)()
+    tp = tc = None
+    if triangles is not None:
+        tp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in triangles])
+        tc = (ctypes.c_int64 * n)(*[int(t.shape[0]) for t in triangles])
+    status = load().eses_mesh(cand.h, ptrs, _soa(outs), cnt, tp, tc, st, _stream_ptr(stream))
+    if status not in (ESES_OK, ESES_ECAPACITY):
+        _check(status)
+    return [dict(area=s.area, volume=s.volume, n_triangles=int(s.n_triangles)) for s in st]
 
 
 def fill_cavities(cand: Candidates, labels_dev, stream=None):
