@@ -1535,7 +1535,7 @@ eses_status eses_mesh(eses_candidates *c, const uint8_t *const *labels,
         long long *boff, *tmp;
         const long long nb = (m.npts + 255) / 256;
         eses_status s;
-        if ((s = T.alloc(&out, 2)) != ESES_OK || (s = T.alloc(&cnt, nb + 1)) != ESES_OK ||
+        if ((s = T.alloc(&out, 2 * nb + 2)) != ESES_OK || (s = T.alloc(&cnt, nb + 1)) != ESES_OK ||
             (s = T.alloc(&bad, 1)) != ESES_OK || (s = T.alloc(&boff, nb + 2)) != ESES_OK ||
             (s = T.alloc(&tmp, scan_tmp_elems(nb) + 64)) != ESES_OK) {
             T.release();
@@ -1543,8 +1543,7 @@ eses_status eses_mesh(eses_candidates *c, const uint8_t *const *labels,
         }
         long long nblk = 0, total = 0, hbad = 0;
         double h[2] = {0.0, 0.0};
-        hipError_t e = fill_u32((uint32_t *)out, 4, 0u, st);
-        if (e == hipSuccess) e = fill_i32(bad, 1, 0, st);
+        hipError_t e = fill_i32(bad, 1, 0, st);
         if (e == hipSuccess)
             e = launch_mesh(m, labels[q], (const long long *)isect[q].key, isect[q].lambda, counts[q],
                             out, cnt, bad, &nblk, st);

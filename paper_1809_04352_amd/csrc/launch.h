@@ -156,8 +156,9 @@ hipError_t launch_edge_roots_batch(const Mol *mols, const EdgeJob *jobs, int nj,
 constexpr int EDGE_WORK_COUNTERS = 16;
 
 // marching-cubes mesh (mesh.hip): per block of cubes, the triangle counts
-// (counts[*nblocks]) and the sums of area and volume into out[0..1]
-// (zeroed by the caller); records missing for a cut edge counted in *bad.
+// (counts[*nblocks]); the area and volume sums into out[0..1] (out holds
+// 2 + 2 * blocks doubles: the block sums follow, added in a fixed order);
+// records missing for a cut edge counted in *bad.
 // The write pass puts the triangles (record indices) at the scanned block
 // offsets boff.
 hipError_t launch_mesh(const Mol &m, const uint8_t *L, const long long *key, const double *lam,

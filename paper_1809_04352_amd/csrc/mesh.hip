@@ -12,7 +12,7 @@
 // sum of det(v0, v1, v2) / 6 with the vertices taken relative to the grid
 // origin.
 #include <algorithm>
-#include <map>
+#include <array>
 #include <mutex>
 #include <set>
 #include <vector>
@@ -87,7 +87,6 @@ McTable build_table() {
             adj[s.first].push_back(s.second);
             adj[s.second].push_back(s.first);
         }
-        std::vector<int> used(seg.size(), 0);
         bool seen[12] = {false};
         int nt = 0;
         for (int e0 = 0; e0 < 12; ++e0) {
@@ -237,7 +236,8 @@ __device__ inline long long edge_point(const MeshArgs &A, int i, int j, int k, i
 }
 
 // Per cube: its triangles' area and volume terms (and count); per block the
-// sums go to out (area, volume) and counts[block] (triangles).  Edges without
+// sums go to out[2 block .. 2 block + 1] (area, volume) and counts[block]
+// (triangles).  Edges without
 // a record (a configuration the records do not cover) are counted in bad.
 __global__ void __launch_bounds__(MESH_THREADS) k_mesh_count(MeshArgs A, long long ncube,
                                                             double *out, int *counts, int *bad) {
@@ -284,9 +284,35 @@ __global__ void __launch_bounds__(MESH_THREADS) k_mesh_count(MeshArgs A, long lo
             v += sv[x];
             c += sc[x];
         }
-        atomicAdd(&out[0], a);
-        atomicAdd(&out[1], v);
+        out[2 * blockIdx.x] = a;  // block sums, reduced in a fixed order below
+        out[2 * blockIdx.x + 1] = v;
         counts[blockIdx.x] = c;
+    }
+}
+
+// The block sums of area and volume added in a fixed order (the result does
+// not depend on the order blocks ran in): sum[0..1].
+__global__ void __launch_bounds__(MESH_THREADS) k_mesh_reduce(const double *part, long long nb,
+                                                             double *sum) {
+    __shared__ double sa[MESH_THREADS], sv[MESH_THREADS];
+    double a = 0.0, v = 0.0;
+    for (long long b = threadIdx.x; b < nb; b += MESH_THREADS) {
+        a += part[2 * b];
+        v += part[2 * b + 1];
+    }
+    sa[threadIdx.x] = a;
+    sv[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = MESH_THREADS / 2; d > 0; d >>= 1) {
+        if ((int)threadIdx.x < d) {
+            sa[threadIdx.x] += sa[threadIdx.x + d];
+            sv[threadIdx.x] += sv[threadIdx.x + d];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        sum[0] = sa[0];
+        sum[1] = sv[0];
     }
 }
 
@@ -321,7 +347,8 @@ hipError_t launch_mesh(const Mol &m, const uint8_t *L, const long long *key, con
     const long long ncube = m.npts;
     *nblocks = (ncube + MESH_THREADS - 1) / MESH_THREADS;
     hipLaunchKernelGGL(k_mesh_count, dim3((unsigned)*nblocks), dim3(MESH_THREADS), 0, st, A, ncube,
-                       out, counts, bad);
+                       out + 2, counts, bad);
+    hipLaunchKernelGGL(k_mesh_reduce, dim3(1), dim3(MESH_THREADS), 0, st, out + 2, *nblocks, out);
     return hipGetLastError();
 }
 
