@@ -197,8 +197,8 @@ struct Arena {
 
 struct MolState {
     Mol m{};
-    Arena arena;
-    Arena scratch;  // build-time temporaries
+    Arena arena;    // per-molecule blocks allocated after the build (a grown
+                    // uncertain-point queue); the build's arrays are the handle's
     eses_candidate_stats stats{};
     // host arbiter of uncertain labels (built on first need) and the number of
     // points it re-decided in the last classification
@@ -423,286 +423,552 @@ eses_status read_scalars(std::initializer_list<Scalar> items, hipStream_t st) {
     return ESES_OK;
 }
 
-// Several single ints read back with one synchronisation.
-eses_status d2h_ints(std::initializer_list<std::pair<int *, const int *>> items, hipStream_t st) {
-    long long *h = readback_host();
-    if (!h) {
-        set_err("pinned host allocation for read-backs failed");
-        return ESES_ENOMEM;
+
+// ------------------------------------------------------- staged build
+
+// Device blocks requested by size, allocated as one block and cut in order
+// (each piece 256-byte aligned): a build stage allocates all molecules'
+// arrays of one kind of memory at once.
+struct Planner {
+    struct Req {
+        void **p;
+        size_t bytes;
+    };
+    std::vector<Req> reqs;
+    template <typename T>
+    void add(T **p, long long count) {
+        reqs.push_back({(void **)p, sizeof(T) * (size_t)std::max<long long>(count, 1)});
     }
-    ReadBack rb{};
-    for (auto &it : items) {
-        if (rb.n == 16) {
-            set_err("internal: more than 16 read-backs");
-            return ESES_EINTERNAL;
+    static size_t up(size_t b) { return (b + 255) & ~(size_t)255; }
+    // allocates, assigns the pointers and, with `zero`, clears the block
+    eses_status commit(Arena &A, hipStream_t st, bool zero) {
+        if (reqs.empty()) return ESES_OK;
+        size_t total = 0;
+        for (const Req &r : reqs) total += up(r.bytes);
+        char *base = nullptr;
+        CKS(A.alloc(&base, (long long)total));
+        size_t off = 0;
+        for (const Req &r : reqs) {
+            *r.p = base + off;
+            off += up(r.bytes);
         }
-        rb.p[rb.n] = it.second;
-        rb.is64[rb.n] = 0;
-        ++rb.n;
+        reqs.clear();
+        if (zero) CK(fill_u32((uint32_t *)base, (long long)(total / 4), 0u, st));
+        return ESES_OK;
     }
-    CK(launch_collect(rb, h, st));
-    CK(hipStreamSynchronize(st));
-    int q = 0;
-    for (auto &it : items) *it.first = (int)h[q++];
-    return ESES_OK;
-}
+};
 
-// Stage 1 for one molecule.
-// The handle's buffers come from (and return to) the cache of `home`, the
-// caller's stream, which `st` follows; build-time temporaries stay with `st`.
-eses_status build_one(const eses_molecule *in, int tile, int force_recheck, int edge_fallback,
-                      int vertex_pool, int tile_pool, int unc_queue, MolState *S, hipStream_t st,
-                      hipStream_t home) {
-    Mol &m = S->m;
-    Arena &A = S->arena;
-    Arena &T = S->scratch;
-    A.st = st;
-    A.key = home;
-    A.keyed = true;
-    T.st = st;
-    if (!in->centers || !in->radii) {
-        set_err("centers and radii must be device pointers");
-        return ESES_EINVAL;
+// A stage's control data -- the molecules' views and temporaries, the block
+// offsets of its launches, its scan and read-back lists -- laid out in one
+// host image and copied to the device in one transfer.
+struct StageCtl {
+    std::vector<char> host;
+    char *dev = nullptr;
+    template <typename T>
+    size_t put(const T *p, size_t count) {
+        size_t off = (host.size() + 15) & ~(size_t)15;
+        host.resize(off + sizeof(T) * std::max<size_t>(count, 1));
+        if (count) memcpy(host.data() + off, p, sizeof(T) * count);
+        return off;
     }
-    if (in->n_atoms < 1 || in->n_atoms > (1LL << 27)) {
-        set_err("n_atoms must be in [1, 2^27]");
-        return ESES_EINVAL;
+    template <typename T>
+    T *at(size_t off) const { return (T *)(dev + off); }
+    eses_status upload(Arena &T, hipStream_t st) {
+        CKS(T.alloc(&dev, (long long)host.size()));
+        CK(hipMemcpyAsync(dev, host.data(), host.size(), hipMemcpyHostToDevice, st));
+        return ESES_OK;
     }
-    if (!(std::isfinite(in->probe_radius) && in->probe_radius > 0.0)) {
-        set_err("probe_radius must be finite and > 0");
-        return ESES_EINVAL;
-    }
-    int32_t dims[3];
-    CKS(dims_of(in, dims));
-    m.n = (int)in->n_atoms;
-    m.rho = in->probe_radius;
-    m.h = in->spacing;
-    for (int a = 0; a < 3; ++a) {
-        m.lo[a] = in->bbox_lo[a];
-        m.dims[a] = dims[a];
-    }
-    m.npts = (long long)dims[0] * dims[1] * dims[2];
-    m.in_c = in->centers;
-    m.in_r = in->radii;
-    m.tile = tile;
-    m.force_recheck = force_recheck ? 1 : 0;
-    m.edge_fallback = edge_fallback ? 1 : 0;
-    for (int a = 0; a < 3; ++a) m.tdims[a] = (dims[a] + tile - 1) / tile;
-    long long ntiles = (long long)m.tdims[0] * m.tdims[1] * m.tdims[2];
-    if (ntiles > (1LL << 30)) {
-        set_err("grid too large: %lld tiles", ntiles);
-        return ESES_EINVAL;
-    }
-    m.ntiles = (int)ntiles;
+};
 
-    CKS(A.alloc(&m.diag, 4));
-    CK(fill_i32(m.diag, 4, 0, st));
-
-    // bounds and input validation
-    double *dbounds;
-    int *dbad;
-    CKS(T.alloc(&dbounds, 8));
-    CKS(T.alloc(&dbad, 1));
-    CK(launch_bounds(in->centers, in->radii, m.n, dbounds, dbad, st));
-    double hb[8];
-    long long hbits[7], hbad = 0;
-    CKS(read_scalars({{dbounds, true, &hbits[0]}, {dbounds + 1, true, &hbits[1]},
-                      {dbounds + 2, true, &hbits[2]}, {dbounds + 3, true, &hbits[3]},
-                      {dbounds + 4, true, &hbits[4]}, {dbounds + 5, true, &hbits[5]},
-                      {dbounds + 6, true, &hbits[6]}, {dbad, false, &hbad}},
-                     st));
-    memcpy(hb, hbits, sizeof(double) * 7);  // the doubles' bit patterns
-    if (hbad) {
-        set_err("centres must be finite and radii finite and > 0");
-        return ESES_EINVAL;
+// Builds every molecule of a handle: each stage is one launch per kernel over
+// all molecules (a molecule per range of blocks), with one read-back per
+// stage for the sizes the next stage allocates (four in all).
+class Builder {
+  public:
+    Builder(eses_candidates *c, const eses_molecule *in, int nm, hipStream_t st)
+        : c_(c), in_(in), nm_(nm), st_(st), M(nm), B(nm) {
+        T_.st = st;
+        c_->batch.st = st;
     }
-    m.smax = hb[6] + m.rho;
-    m.cell = 2.0 * m.smax;
-    m.cmag = m.smax;
-    for (int a = 0; a < 6; ++a) m.cmag = std::max(m.cmag, std::fabs(hb[a]) + m.smax);
-    // queue of the points whose FP64 decision cannot be certified (grown and
-    // the classification repeated on overflow)
-    m.unc_cap = unc_queue > 0 ? unc_queue
-                              : (int)std::min<long long>(std::max<long long>(4096, m.npts / 512),
-                                                         1LL << 22);
-    CKS(A.alloc(&m.unc_idx, m.unc_cap));
-    CKS(A.alloc(&m.unc_n, 1));
-    CK(fill_i32(m.unc_n, 1, 0, st));
-    for (;;) {
-        long long nc = 1;
-        for (int a = 0; a < 3; ++a) {
-            m.clo[a] = hb[a];
-            m.nc[a] = (int)std::floor((hb[3 + a] - hb[a]) / m.cell) + 1;
-            nc *= m.nc[a];
+    ~Builder() { T_.release(); }
+
+    eses_status run(int tile, int force_recheck, int edge_fallback, int vertex_pool,
+                    int tile_pool, int unc_queue) {
+        CKS(stage_bounds(tile, force_recheck, edge_fallback, unc_queue));
+        CKS(stage_nbr());
+        CKS(stage_vertex(vertex_pool));
+        CKS(stage_tiles(tile_pool));
+        CKS(stage_fill());
+        for (int q = 0; q < nm_; ++q) c_->mols[q]->m = M[q];
+        // the stages' host images are released with the builder
+        CK(hipStreamSynchronize(st_));
+        return ESES_OK;
+    }
+
+  private:
+    eses_candidates *c_;
+    const eses_molecule *in_;
+    int nm_;
+    hipStream_t st_;
+    std::vector<Mol> M;
+    std::vector<BuildTmp> B;
+    Arena T_;                 // temporaries, released when the build ends
+    std::vector<StageCtl> ctl_;  // kept until the build ends (host images of copies)
+
+    eses_status fail(int q, eses_status s, const char *msg) {
+        set_err("molecule %d: %s", q, msg);
+        return s;
+    }
+
+    // Seg of kernel k over all molecules (offsets into the stage's control
+    // image); the block total in *nb.
+    size_t starts(StageCtl &C, BuildKernel k, long long *nb) {
+        std::vector<int> st((size_t)nm_ + 1, 0);
+        long long t = 0;
+        for (int q = 0; q < nm_; ++q) {
+            st[(size_t)q] = (int)t;
+            t += build_blocks(k, M[q], B[q]);
         }
-        if (nc <= 4LL * m.n + 64) {
-            m.ncell = (int)nc;
-            break;
+        st[(size_t)nm_] = (int)t;
+        *nb = t;
+        return C.put(st.data(), st.size());
+    }
+
+    struct Launch {
+        BuildKernel k;
+        bool fill;
+        size_t off;
+        long long nb;
+    };
+
+    // The molecules' views and temporaries into a new stage control image.
+    StageCtl &begin(size_t *mols_off, size_t *tmp_off) {
+        ctl_.emplace_back();
+        StageCtl &C = ctl_.back();
+        *mols_off = C.put(M.data(), M.size());
+        *tmp_off = C.put(B.data(), B.size());
+        return C;
+    }
+
+    Seg seg(const StageCtl &C, size_t mo, size_t to, size_t so) const {
+        Seg s;
+        s.mols = C.at<Mol>(mo);
+        s.tmp = C.at<BuildTmp>(to);
+        s.start = C.at<int>(so);
+        s.nm = nm_;
+        return s;
+    }
+
+    // Scan list: (in, out, n) per array; the chunk sums are cut from T_.
+    struct ScanList {
+        std::vector<ScanSeg> segs;
+        long long chunks = 0;
+        size_t off = 0;
+        int *sums = nullptr;
+        void add(const int *in, int *out, long long n) {
+            segs.push_back({in, out, n, chunks});
+            chunks += (n + scan_seg_chunk() - 1) / scan_seg_chunk();
         }
-        m.cell *= 1.5;  // sparse input: coarser cells keep the table small
+    };
+
+    eses_status scan(const StageCtl &C, ScanList &L) {
+        return scan_seg(C.at<ScanSeg>(L.off), (int)L.segs.size(), L.chunks, L.sums, st_) ==
+                       hipSuccess
+                   ? ESES_OK
+                   : (set_err("build scan launch failed"), ESES_EDEVICE);
     }
 
-    // binning
-    int *cell_id, *cnt, *fillb, *slot, *tmp;
-    long long tmp_elems = scan_tmp_elems((long long)std::max<long long>(
-        std::max<long long>(m.n, m.ncell), std::max<long long>(ntiles, 1)) * 4 + 64);
-    CKS(T.alloc(&tmp, tmp_elems));
-    CKS(T.alloc(&cell_id, m.n));
-    CKS(T.alloc(&cnt, m.ncell + 1));
-    CKS(T.alloc(&fillb, m.ncell + 1));
-    CKS(T.alloc(&slot, m.n));
-    CKS(A.alloc(&m.cell_start, m.ncell + 1));
-    CKS(A.alloc(&m.atom, m.n));
-    CKS(A.alloc(&m.orig, m.n));
-    CK(fill_i32(cnt, m.ncell + 1, 0, st));
-    CK(launch_cell_count(m, cell_id, cnt, st));
-    CK(scan_i32(cnt, m.ncell, m.cell_start, tmp, st));
-    CK(copy_i32(fillb, m.cell_start, m.ncell + 1, st));
-    CK(launch_cell_scatter(m, cell_id, fillb, slot, st));
-    CK(launch_cell_sort_gather(m, slot, st));
-
-    // neighbours and circles
-    int *nbr_cnt, *circ_cnt;
-    CKS(T.alloc(&nbr_cnt, m.n));
-    CKS(T.alloc(&circ_cnt, m.n));
-    CKS(A.alloc(&m.nbr_off, m.n + 1));
-    CKS(A.alloc(&m.circ_off, m.n + 1));
-    CKS(A.alloc(&m.circ_any, m.n));
-    CKS(A.alloc(&m.aflag, m.n));
-    CK(launch_nbr(m, false, nbr_cnt, circ_cnt, st));
-    {
-        const int *ins[2] = {nbr_cnt, circ_cnt};
-        int *outs[2] = {m.nbr_off, m.circ_off};
-        CK(scan_i32_multi(ins, m.n, outs, 2, tmp, st));
+    // Read-back of ints at device addresses (one transfer and one
+    // synchronisation for the whole stage).
+    eses_status read_ints(StageCtl &C, size_t addr_off, int n, int *dst_dev,
+                          std::vector<int> &out) {
+        CK(launch_gather_ints(C.at<const int *>(addr_off), n, dst_dev, st_));
+        out.resize((size_t)n);
+        CK(hipMemcpyAsync(out.data(), dst_dev, sizeof(int) * n, hipMemcpyDeviceToHost, st_));
+        CK(hipStreamSynchronize(st_));
+        return ESES_OK;
     }
-    int tot[3];
-    CKS(d2h_ints({{&tot[0], m.nbr_off + m.n}, {&tot[1], m.circ_off + m.n}, {&tot[2], m.diag + 2}},
-                 st));
-    if (tot[2]) {
-        set_err("atom centres must be pairwise distinct (two atoms share a centre)");
-        return ESES_EINVAL;
+
+    // -- stage 0: arguments, bounds of the centres
+    eses_status stage_bounds(int tile, int force_recheck, int edge_fallback, int unc_queue) {
+        for (int q = 0; q < nm_; ++q) {
+            const eses_molecule *in = &in_[q];
+            Mol &m = M[q];
+            m = Mol{};
+            if (!in->centers || !in->radii)
+                return fail(q, ESES_EINVAL, "centers and radii must be device pointers");
+            if (in->n_atoms < 1 || in->n_atoms > (1LL << 27))
+                return fail(q, ESES_EINVAL, "n_atoms must be in [1, 2^27]");
+            if (!(std::isfinite(in->probe_radius) && in->probe_radius > 0.0))
+                return fail(q, ESES_EINVAL, "probe_radius must be finite and > 0");
+            int32_t dims[3];
+            eses_status ds = dims_of(in, dims);
+            if (ds != ESES_OK) {
+                std::string msg = g_err;
+                return fail(q, ds, msg.c_str());
+            }
+            m.n = (int)in->n_atoms;
+            m.rho = in->probe_radius;
+            m.h = in->spacing;
+            for (int a = 0; a < 3; ++a) {
+                m.lo[a] = in->bbox_lo[a];
+                m.dims[a] = dims[a];
+            }
+            m.npts = (long long)dims[0] * dims[1] * dims[2];
+            m.in_c = in->centers;
+            m.in_r = in->radii;
+            m.tile = tile;
+            m.force_recheck = force_recheck ? 1 : 0;
+            m.edge_fallback = edge_fallback ? 1 : 0;
+            for (int a = 0; a < 3; ++a) m.tdims[a] = (dims[a] + tile - 1) / tile;
+            const long long ntiles = (long long)m.tdims[0] * m.tdims[1] * m.tdims[2];
+            if (ntiles > (1LL << 30)) return fail(q, ESES_EINVAL, "grid too large (tiles)");
+            m.ntiles = (int)ntiles;
+            m.unc_cap = unc_queue > 0 ? unc_queue
+                                      : (int)std::min<long long>(
+                                            std::max<long long>(4096, m.npts / 512), 1LL << 22);
+        }
+        double *bnd = nullptr;
+        int *bad = nullptr;
+        CKS(T_.alloc(&bnd, 8LL * nm_));
+        CKS(T_.alloc(&bad, nm_));
+        Planner Z;  // persistent, zeroed
+        for (int q = 0; q < nm_; ++q) {
+            B[q] = BuildTmp{};
+            B[q].bounds = bnd + 8 * q;
+            B[q].bad = bad + q;
+            Z.add(&M[q].diag, 4);
+            Z.add(&M[q].unc_n, 1);
+        }
+        CKS(Z.commit(c_->batch, st_, true));
+        size_t mo, to;
+        StageCtl &C = begin(&mo, &to);
+        long long nb;
+        const size_t so = starts(C, BK_BOUNDS, &nb);
+        CKS(C.upload(T_, st_));
+        CK(launch_build(BK_BOUNDS, seg(C, mo, to, so), nb, st_));
+        std::vector<double> hb((size_t)8 * nm_);
+        std::vector<int> hbad((size_t)nm_);
+        CK(hipMemcpyAsync(hb.data(), bnd, sizeof(double) * hb.size(), hipMemcpyDeviceToHost, st_));
+        CK(hipMemcpyAsync(hbad.data(), bad, sizeof(int) * nm_, hipMemcpyDeviceToHost, st_));
+        CK(hipStreamSynchronize(st_));
+        for (int q = 0; q < nm_; ++q) {
+            if (hbad[(size_t)q])
+                return fail(q, ESES_EINVAL, "centres must be finite and radii finite and > 0");
+            Mol &m = M[q];
+            const double *b = &hb[(size_t)8 * q];
+            m.smax = b[6] + m.rho;
+            m.cell = 2.0 * m.smax;
+            m.cmag = m.smax;
+            for (int a = 0; a < 6; ++a) m.cmag = std::max(m.cmag, std::fabs(b[a]) + m.smax);
+            for (;;) {
+                long long ncell = 1;
+                for (int a = 0; a < 3; ++a) {
+                    m.clo[a] = b[a];
+                    m.nc[a] = (int)std::floor((b[3 + a] - b[a]) / m.cell) + 1;
+                    ncell *= m.nc[a];
+                }
+                if (ncell <= 4LL * m.n + 64) {
+                    m.ncell = (int)ncell;
+                    break;
+                }
+                m.cell *= 1.5;  // sparse input: coarser cells keep the table small
+            }
+        }
+        return ESES_OK;
     }
-    m.ncirc = tot[1];
-    CKS(A.alloc(&m.nbr, tot[0]));
-    CKS(A.alloc(&m.nbr_cov, tot[0]));
-    CKS(A.alloc(&m.circ_i, m.ncirc));
-    CKS(A.alloc(&m.circ_j, m.ncirc));
-    CKS(A.alloc(&m.circ_oR, m.ncirc));
-    CKS(A.alloc(&m.circ_n, m.ncirc));
-    CKS(A.alloc(&m.cflag, m.ncirc));
-    CK(launch_nbr(m, true, nbr_cnt, circ_cnt, st));
-    CK(launch_nbr_sort(m, st));
 
-    // concave probe positions (count pass), exposure flags, exposed faces and
-    // circles; their totals come back with one synchronisation
-    int *vcnt, *tmp2;
-    CKS(T.alloc(&vcnt, m.ncirc));
-    CKS(T.alloc(&tmp2, scan_tmp_elems(m.ncirc) + 64));
-    CKS(A.alloc(&m.vert_off, m.ncirc + 1));
-    // positions pooled by the count pass (placed after the scan when they fit)
-    VertexPool pool{};
-    pool.cap = vertex_pool > 0 ? vertex_pool : std::max(4096, m.ncirc / 4);
-    CKS(T.alloc(&pool.p, pool.cap));
-    CKS(T.alloc(&pool.id, pool.cap));
-    CKS(T.alloc(&pool.count, 1));
-    CK(fill_i32(pool.count, 1, 0, st));
-    CK(launch_vertex(m, false, vcnt, pool, st));
-    CK(launch_circle_free(m, st));
-    CK(scan_i32(vcnt, m.ncirc, m.vert_off, tmp2, st));
-    int *face_cnt, *ecf, *ec_pos;
-    CKS(T.alloc(&face_cnt, m.n));
-    CKS(T.alloc(&ecf, m.ncirc));
-    CKS(T.alloc(&ec_pos, m.ncirc + 1));
-    CKS(A.alloc(&m.face_off_atom, m.n + 1));
-    CKS(A.alloc(&m.ec_off_atom, m.n + 1));
-    CKS(A.alloc(&m.vert_off_atom, m.n + 1));
-    CK(launch_atom_features(m, face_cnt, st));
-    CK(scan_i32(face_cnt, m.n, m.face_off_atom, tmp, st));
-    CK(launch_ec_flag(m, ecf, st));
-    CK(scan_i32(ecf, m.ncirc, ec_pos, tmp2, st));
-    int npool = 0;
-    CKS(d2h_ints({{&m.nvert, m.vert_off + m.ncirc}, {&m.nface, m.face_off_atom + m.n},
-                   {&m.nec, ec_pos + m.ncirc}, {&npool, pool.count}}, st));
-    CKS(A.alloc(&m.vert_p, m.nvert));
-    CKS(A.alloc(&m.vert_ijks, m.nvert));
-    pool.use = npool <= pool.cap ? 1 : 0;
-    if (pool.use) CK(launch_vertex_place(m, pool, npool, vcnt, st));
-    CK(launch_vertex(m, true, vcnt, pool, st));
-    if (pool.use) CK(launch_vertex_order(m, st));
-    CKS(A.alloc(&m.ec_circ, m.nec));
-    CK(launch_ec_ids(m, ec_pos, st));
-
-    // cut lists of exposed faces and circles
-    int *fcut_cnt, *eccut_cnt, *tmp3;
-    CKS(A.alloc(&m.face_atom, m.nface));
-    CKS(A.alloc(&m.face_cut_off, m.nface + 1));
-    CKS(A.alloc(&m.ec_cut_off, m.nec + 1));
-    CKS(T.alloc(&fcut_cnt, m.nface));
-    CKS(T.alloc(&eccut_cnt, m.nec));
-    CKS(T.alloc(&tmp3, scan_tmp_elems(std::max(m.nface, m.nec)) + 64));
-    CK(launch_face_list(m, fcut_cnt, st));
-    CK(scan_i32(fcut_cnt, m.nface, m.face_cut_off, tmp3, st));
-    CK(launch_ec_cuts(m, false, eccut_cnt, st));
-    CK(scan_i32(eccut_cnt, m.nec, m.ec_cut_off, tmp3, st));
-
-    // per-tile lists: the count pass needs no cut planes, so its totals come
-    // back with the cut totals in one synchronisation
-    int *cA, *cF, *cC, *cV;
-    CKS(T.alloc(&cA, m.ntiles));
-    CKS(T.alloc(&cF, m.ntiles));
-    CKS(T.alloc(&cC, m.ntiles));
-    CKS(T.alloc(&cV, m.ntiles));
-    CKS(A.alloc(&m.tA_off, m.ntiles + 1));
-    CKS(A.alloc(&m.tF_off, m.ntiles + 1));
-    CKS(A.alloc(&m.tC_off, m.ntiles + 1));
-    CKS(A.alloc(&m.tV_off, m.ntiles + 1));
-    // the count pass keeps the lists in a pool, placed after the read-back
-    TilePool tp{};
-    tp.cap = tile_pool > 0 ? std::min(tile_pool, tile_keep_max()) : tile_keep_max();
-    CKS(T.alloc(&tp.pool, (long long)tp.cap * m.ntiles));
-    CKS(T.alloc(&tp.off, m.ntiles));
-    CKS(T.alloc(&tp.unpooled, 1));
-    CK(fill_i32(tp.unpooled, 1, 0, st));
-    CK(launch_tiles(m, false, cA, cF, cC, cV, tp, st));
-    {
-        const int *ins[4] = {cA, cF, cC, cV};
-        int *outs[4] = {m.tA_off, m.tF_off, m.tC_off, m.tV_off};
-        CK(scan_i32_multi(ins, m.ntiles, outs, 4, tmp, st));
+    // -- stage 1: cell binning, neighbour and circle counts
+    eses_status stage_nbr() {
+        Planner P, Z, TT, TZ;
+        for (int q = 0; q < nm_; ++q) {
+            Mol &m = M[q];
+            BuildTmp &t = B[q];
+            P.add(&m.cell_start, m.ncell + 1);
+            P.add(&m.atom, m.n);
+            P.add(&m.orig, m.n);
+            P.add(&m.nbr_off, m.n + 1);
+            P.add(&m.circ_off, m.n + 1);
+            P.add(&m.circ_any, m.n);
+            P.add(&m.aflag, m.n);
+            P.add(&m.unc_idx, m.unc_cap);
+            TT.add(&t.cell_id, m.n);
+            TZ.add(&t.cnt, m.ncell + 1);
+            TT.add(&t.fillb, m.ncell + 1);
+            TT.add(&t.slot, m.n);
+            TT.add(&t.nbr_cnt, m.n);
+            TT.add(&t.circ_cnt, m.n);
+        }
+        CKS(P.commit(c_->batch, st_, false));
+        CKS(TT.commit(T_, st_, false));
+        CKS(TZ.commit(T_, st_, true));
+        size_t mo, to;
+        StageCtl &C = begin(&mo, &to);
+        const BuildKernel ks[] = {BK_CELL_COUNT, BK_CELL_FILL, BK_CELL_SCATTER, BK_CELL_SORT,
+                                  BK_GATHER, BK_NBR};
+        std::vector<Launch> L;
+        for (BuildKernel k : ks) {
+            Launch l{k, false, 0, 0};
+            l.off = starts(C, k, &l.nb);
+            L.push_back(l);
+        }
+        ScanList S1, S2;
+        for (int q = 0; q < nm_; ++q) S1.add(B[q].cnt, M[q].cell_start, M[q].ncell);
+        for (int q = 0; q < nm_; ++q) {
+            S2.add(B[q].nbr_cnt, M[q].nbr_off, M[q].n);
+            S2.add(B[q].circ_cnt, M[q].circ_off, M[q].n);
+        }
+        S1.off = C.put(S1.segs.data(), S1.segs.size());
+        S2.off = C.put(S2.segs.data(), S2.segs.size());
+        CKS(T_.alloc(&S1.sums, S1.chunks + 1));
+        CKS(T_.alloc(&S2.sums, S2.chunks + 1));
+        std::vector<const int *> addr;
+        for (int q = 0; q < nm_; ++q) {
+            addr.push_back(M[q].nbr_off + M[q].n);
+            addr.push_back(M[q].circ_off + M[q].n);
+            addr.push_back(M[q].diag + 2);
+        }
+        const size_t ao = C.put(addr.data(), addr.size());
+        int *rb;
+        CKS(T_.alloc(&rb, (long long)addr.size()));
+        CKS(C.upload(T_, st_));
+        CK(launch_build(BK_CELL_COUNT, seg(C, mo, to, L[0].off), L[0].nb, st_));
+        CKS(scan(C, S1));
+        for (size_t k = 1; k < L.size(); ++k)
+            CK(launch_build(L[k].k, seg(C, mo, to, L[k].off), L[k].nb, st_));
+        CKS(scan(C, S2));
+        std::vector<int> h;
+        CKS(read_ints(C, ao, (int)addr.size(), rb, h));
+        for (int q = 0; q < nm_; ++q) {
+            if (h[(size_t)3 * q + 2])
+                return fail(q, ESES_EINVAL,
+                            "atom centres must be pairwise distinct (two atoms share a centre)");
+            nbr_total_.push_back(h[(size_t)3 * q]);
+            M[q].ncirc = h[(size_t)3 * q + 1];
+        }
+        return ESES_OK;
     }
-    int nfc = 0, nec_cut = 0, tl[4], unpooled = 0;
-    CKS(d2h_ints({{&nfc, m.face_cut_off + m.nface}, {&nec_cut, m.ec_cut_off + m.nec},
-                   {&tl[0], m.tA_off + m.ntiles}, {&tl[1], m.tF_off + m.ntiles},
-                   {&tl[2], m.tC_off + m.ntiles}, {&tl[3], m.tV_off + m.ntiles},
-                   {&unpooled, tp.unpooled}}, st));
-    CKS(A.alloc(&m.face_cut, nfc));
-    CK(launch_face_cuts(m, st));
-    CKS(A.alloc(&m.ec_cut, nec_cut));
-    CK(launch_ec_cuts(m, true, eccut_cnt, st));
-    CKS(A.alloc(&m.tA, tl[0]));
-    CKS(A.alloc(&m.tF, tl[1]));
-    CKS(A.alloc(&m.tC, tl[2]));
-    CKS(A.alloc(&m.tV, tl[3]));
-    CK(launch_tiles_place(m, tp, cA, cF, cC, cV, st));
-    if (unpooled) CK(launch_tiles(m, true, cA, cF, cC, cV, tp, st));
+    std::vector<int> nbr_total_;
 
-    // (m.diag[0], set by a fill pass that met more entries than it counted,
-    // is checked at the next read-back: eses_edge_intersections)
+    // -- stage 2: neighbour lists, circles, probe-position counts, flags
+    eses_status stage_vertex(int vertex_pool) {
+        Planner P, TT, TZ;
+        for (int q = 0; q < nm_; ++q) {
+            Mol &m = M[q];
+            BuildTmp &t = B[q];
+            const int tot = nbr_total_[(size_t)q];
+            P.add(&m.nbr, tot);
+            P.add(&m.nbr_cov, tot);
+            P.add(&m.circ_i, m.ncirc);
+            P.add(&m.circ_j, m.ncirc);
+            P.add(&m.circ_oR, m.ncirc);
+            P.add(&m.circ_n, m.ncirc);
+            P.add(&m.cflag, m.ncirc);
+            P.add(&m.vert_off, m.ncirc + 1);
+            P.add(&m.face_off_atom, m.n + 1);
+            P.add(&m.ec_off_atom, m.n + 1);
+            P.add(&m.vert_off_atom, m.n + 1);
+            t.pool.cap = vertex_pool > 0 ? vertex_pool : std::max(4096, m.ncirc / 4);
+            TT.add(&t.vcnt, m.ncirc);
+            TT.add(&t.pool.p, t.pool.cap);
+            TT.add(&t.pool.id, t.pool.cap);
+            TZ.add(&t.pool.count, 1);
+            TT.add(&t.face_cnt, m.n);
+            TT.add(&t.ecf, m.ncirc);
+            TT.add(&t.ec_pos, m.ncirc + 1);
+        }
+        CKS(P.commit(c_->batch, st_, false));
+        CKS(TT.commit(T_, st_, false));
+        CKS(TZ.commit(T_, st_, true));
+        size_t mo, to;
+        StageCtl &C = begin(&mo, &to);
+        Launch nf{BK_NBR, true, 0, 0}, ns{BK_NBR_SORT, false, 0, 0}, vx{BK_VERTEX, false, 0, 0},
+            cf{BK_CIRCLE_FREE, false, 0, 0}, af{BK_ATOM_FEATURES, false, 0, 0},
+            ef{BK_EC_FLAG, false, 0, 0};
+        for (Launch *l : {&nf, &ns, &vx, &cf, &af, &ef}) l->off = starts(C, l->k, &l->nb);
+        ScanList S1, S2, S3;
+        for (int q = 0; q < nm_; ++q) {
+            S1.add(B[q].vcnt, M[q].vert_off, M[q].ncirc);
+            S2.add(B[q].face_cnt, M[q].face_off_atom, M[q].n);
+            S3.add(B[q].ecf, B[q].ec_pos, M[q].ncirc);
+        }
+        for (ScanList *S : {&S1, &S2, &S3}) {
+            S->off = C.put(S->segs.data(), S->segs.size());
+            CKS(T_.alloc(&S->sums, S->chunks + 1));
+        }
+        std::vector<const int *> addr;
+        for (int q = 0; q < nm_; ++q) {
+            addr.push_back(M[q].vert_off + M[q].ncirc);
+            addr.push_back(M[q].face_off_atom + M[q].n);
+            addr.push_back(B[q].ec_pos + M[q].ncirc);
+            addr.push_back(B[q].pool.count);
+        }
+        const size_t ao = C.put(addr.data(), addr.size());
+        int *rb;
+        CKS(T_.alloc(&rb, (long long)addr.size()));
+        CKS(C.upload(T_, st_));
+        CK(launch_build_fill(BK_NBR, seg(C, mo, to, nf.off), nf.nb, st_));
+        CK(launch_build(BK_NBR_SORT, seg(C, mo, to, ns.off), ns.nb, st_));
+        CK(launch_build(BK_VERTEX, seg(C, mo, to, vx.off), vx.nb, st_));
+        CK(launch_build(BK_CIRCLE_FREE, seg(C, mo, to, cf.off), cf.nb, st_));
+        CKS(scan(C, S1));
+        CK(launch_build(BK_ATOM_FEATURES, seg(C, mo, to, af.off), af.nb, st_));
+        CKS(scan(C, S2));
+        CK(launch_build(BK_EC_FLAG, seg(C, mo, to, ef.off), ef.nb, st_));
+        CKS(scan(C, S3));
+        std::vector<int> h;
+        CKS(read_ints(C, ao, (int)addr.size(), rb, h));
+        for (int q = 0; q < nm_; ++q) {
+            M[q].nvert = h[(size_t)4 * q];
+            M[q].nface = h[(size_t)4 * q + 1];
+            M[q].nec = h[(size_t)4 * q + 2];
+            B[q].npool = h[(size_t)4 * q + 3];
+            B[q].pool.use = B[q].npool <= B[q].pool.cap ? 1 : 0;
+        }
+        return ESES_OK;
+    }
 
-    eses_candidate_stats &s = S->stats;
-    s.n_atoms = m.n;
-    for (int a = 0; a < 3; ++a) s.dims[a] = dims[a];
-    s.n_points = m.npts;
-    s.n_neighbour_pairs = tot[0];
-    s.n_circles = m.ncirc;
-    s.n_vertices = m.nvert;
-    s.n_exposed_faces = m.nface;
-    s.n_exposed_circles = m.nec;
-    s.n_tiles = m.ntiles;
-    s.tile_list_entries = (int64_t)tl[0] + tl[1] + tl[2] + tl[3];
-    T.release();
-    CK(hipGetLastError());
-    return ESES_OK;
-}
+    // -- stage 3: probe positions, exposed features, cut and tile counts
+    eses_status stage_tiles(int tile_pool) {
+        Planner P, TT, TZ;
+        for (int q = 0; q < nm_; ++q) {
+            Mol &m = M[q];
+            BuildTmp &t = B[q];
+            P.add(&m.vert_p, m.nvert);
+            P.add(&m.vert_ijks, m.nvert);
+            P.add(&m.ec_circ, m.nec);
+            P.add(&m.face_atom, m.nface);
+            P.add(&m.face_cut_off, m.nface + 1);
+            P.add(&m.ec_cut_off, m.nec + 1);
+            P.add(&m.tA_off, m.ntiles + 1);
+            P.add(&m.tF_off, m.ntiles + 1);
+            P.add(&m.tC_off, m.ntiles + 1);
+            P.add(&m.tV_off, m.ntiles + 1);
+            TT.add(&t.fcut_cnt, m.nface);
+            TT.add(&t.eccut_cnt, m.nec);
+            TT.add(&t.cA, m.ntiles);
+            TT.add(&t.cF, m.ntiles);
+            TT.add(&t.cC, m.ntiles);
+            TT.add(&t.cV, m.ntiles);
+            t.tp.cap = tile_pool > 0 ? std::min(tile_pool, tile_keep_max()) : tile_keep_max();
+            TT.add(&t.tp.pool, (long long)t.tp.cap * m.ntiles);
+            TT.add(&t.tp.off, m.ntiles);
+            TZ.add(&t.tp.unpooled, 1);
+        }
+        CKS(P.commit(c_->batch, st_, false));
+        CKS(TT.commit(T_, st_, false));
+        CKS(TZ.commit(T_, st_, true));
+        size_t mo, to;
+        StageCtl &C = begin(&mo, &to);
+        Launch vp{BK_VERTEX_PLACE, false, 0, 0}, vf{BK_VERTEX, true, 0, 0},
+            vo{BK_VERTEX_ORDER, false, 0, 0}, ei{BK_EC_IDS, false, 0, 0},
+            fo{BK_FEATURE_OFF, false, 0, 0}, fl{BK_FACE_LIST, false, 0, 0},
+            ec{BK_EC_CUTS, false, 0, 0}, ti{BK_TILES, false, 0, 0};
+        for (Launch *l : {&vp, &vf, &vo, &ei, &fo, &fl, &ec, &ti})
+            l->off = starts(C, l->k, &l->nb);
+        // the ordering pass only where the positions were pooled
+        {
+            std::vector<int> st((size_t)nm_ + 1, 0);
+            long long t = 0;
+            for (int q = 0; q < nm_; ++q) {
+                st[(size_t)q] = (int)t;
+                if (B[q].pool.use) t += build_blocks(BK_VERTEX_ORDER, M[q], B[q]);
+            }
+            st[(size_t)nm_] = (int)t;
+            vo.nb = t;
+            vo.off = C.put(st.data(), st.size());
+        }
+        ScanList S1, S2, S3;
+        for (int q = 0; q < nm_; ++q) {
+            S1.add(B[q].fcut_cnt, M[q].face_cut_off, M[q].nface);
+            S2.add(B[q].eccut_cnt, M[q].ec_cut_off, M[q].nec);
+            S3.add(B[q].cA, M[q].tA_off, M[q].ntiles);
+            S3.add(B[q].cF, M[q].tF_off, M[q].ntiles);
+            S3.add(B[q].cC, M[q].tC_off, M[q].ntiles);
+            S3.add(B[q].cV, M[q].tV_off, M[q].ntiles);
+        }
+        for (ScanList *S : {&S1, &S2, &S3}) {
+            S->off = C.put(S->segs.data(), S->segs.size());
+            CKS(T_.alloc(&S->sums, S->chunks + 1));
+        }
+        std::vector<const int *> addr;
+        for (int q = 0; q < nm_; ++q) {
+            addr.push_back(M[q].face_cut_off + M[q].nface);
+            addr.push_back(M[q].ec_cut_off + M[q].nec);
+            addr.push_back(M[q].tA_off + M[q].ntiles);
+            addr.push_back(M[q].tF_off + M[q].ntiles);
+            addr.push_back(M[q].tC_off + M[q].ntiles);
+            addr.push_back(M[q].tV_off + M[q].ntiles);
+            addr.push_back(B[q].tp.unpooled);
+        }
+        const size_t ao = C.put(addr.data(), addr.size());
+        int *rb;
+        CKS(T_.alloc(&rb, (long long)addr.size()));
+        CKS(C.upload(T_, st_));
+        CK(launch_build(BK_VERTEX_PLACE, seg(C, mo, to, vp.off), vp.nb, st_));
+        CK(launch_build_fill(BK_VERTEX, seg(C, mo, to, vf.off), vf.nb, st_));
+        CK(launch_build(BK_VERTEX_ORDER, seg(C, mo, to, vo.off), vo.nb, st_));
+        CK(launch_build(BK_EC_IDS, seg(C, mo, to, ei.off), ei.nb, st_));
+        CK(launch_build(BK_FEATURE_OFF, seg(C, mo, to, fo.off), fo.nb, st_));
+        CK(launch_build(BK_FACE_LIST, seg(C, mo, to, fl.off), fl.nb, st_));
+        CKS(scan(C, S1));
+        CK(launch_build(BK_EC_CUTS, seg(C, mo, to, ec.off), ec.nb, st_));
+        CKS(scan(C, S2));
+        CK(launch_build(BK_TILES, seg(C, mo, to, ti.off), ti.nb, st_));
+        CKS(scan(C, S3));
+        std::vector<int> h;
+        CKS(read_ints(C, ao, (int)addr.size(), rb, h));
+        for (int q = 0; q < nm_; ++q) {
+            const int *v = &h[(size_t)7 * q];
+            nfc_.push_back(v[0]);
+            necc_.push_back(v[1]);
+            for (int k = 0; k < 4; ++k) tl_.push_back(v[2 + k]);
+            B[q].tp_unpooled = v[6];
+            eses_candidate_stats &s = c_->mols[q]->stats;
+            const Mol &m = M[q];
+            s.n_atoms = m.n;
+            for (int a = 0; a < 3; ++a) s.dims[a] = m.dims[a];
+            s.n_points = m.npts;
+            s.n_neighbour_pairs = nbr_total_[(size_t)q];
+            s.n_circles = m.ncirc;
+            s.n_vertices = m.nvert;
+            s.n_exposed_faces = m.nface;
+            s.n_exposed_circles = m.nec;
+            s.n_tiles = m.ntiles;
+            s.tile_list_entries = (int64_t)v[2] + v[3] + v[4] + v[5];
+        }
+        return ESES_OK;
+    }
+    std::vector<int> nfc_, necc_, tl_;
+
+    // -- stage 4: cut lists and tile lists
+    eses_status stage_fill() {
+        Planner P;
+        for (int q = 0; q < nm_; ++q) {
+            Mol &m = M[q];
+            P.add(&m.face_cut, nfc_[(size_t)q]);
+            P.add(&m.ec_cut, necc_[(size_t)q]);
+            P.add(&m.tA, tl_[(size_t)4 * q]);
+            P.add(&m.tF, tl_[(size_t)4 * q + 1]);
+            P.add(&m.tC, tl_[(size_t)4 * q + 2]);
+            P.add(&m.tV, tl_[(size_t)4 * q + 3]);
+        }
+        CKS(P.commit(c_->batch, st_, false));
+        size_t mo, to;
+        StageCtl &C = begin(&mo, &to);
+        Launch fc{BK_FACE_CUTS, false, 0, 0}, ec{BK_EC_CUTS, true, 0, 0},
+            tp{BK_TILES_PLACE, false, 0, 0}, tf{BK_TILES_FILL, false, 0, 0};
+        for (Launch *l : {&fc, &ec, &tp, &tf}) l->off = starts(C, l->k, &l->nb);
+        CKS(C.upload(T_, st_));
+        CK(launch_build(BK_FACE_CUTS, seg(C, mo, to, fc.off), fc.nb, st_));
+        CK(launch_build_fill(BK_EC_CUTS, seg(C, mo, to, ec.off), ec.nb, st_));
+        CK(launch_build(BK_TILES_PLACE, seg(C, mo, to, tp.off), tp.nb, st_));
+        CK(launch_build(BK_TILES_FILL, seg(C, mo, to, tf.off), tf.nb, st_));
+        // (a fill pass that met more entries than it counted sets diag[0],
+        // checked at the next read-back: eses_edge_intersections)
+        return ESES_OK;
+    }
+};
 
 eses_status ensure_events(eses_candidates *c) {
     for (int q = 0; q < 6; ++q)
@@ -1298,25 +1564,16 @@ eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
     eses_candidates *c = new eses_candidates();
     c->stream = st;
     for (int32_t q = 0; q < n_mols; ++q) c->mols.push_back(new MolState());
-    if (n_mols == 1) {
-        eses_status s = build_one(&mols[0], tile, force_recheck, edge_fallback, vertex_pool,
-                                  tile_pool, unc_queue, c->mols[0], st, st);
+    for (MolState *S : c->mols) S->arena.st = st;
+    {
+        // every stage over all molecules from this thread (one launch per
+        // build kernel and one read-back per stage)
+        Builder b(c, mols, n_mols, st);
+        eses_status s = b.run(tile, force_recheck, edge_fallback, vertex_pool, tile_pool,
+                              unc_queue);
         if (s != ESES_OK) {
             std::string msg = g_err;
-            eses_free_candidates(c);
-            g_err = "molecule 0: " + msg;
-            return s;
-        }
-    } else {
-        // molecules built concurrently on the worker streams; their workspace
-        // then belongs to the caller's stream, which waits for the builds
-        eses_status s = run_on_workers(n_mols, st, [&](int q, hipStream_t ws) {
-            return build_one(&mols[q], tile, force_recheck, edge_fallback, vertex_pool,
-                             tile_pool, unc_queue, c->mols[q], ws, st);
-        });
-        for (MolState *S : c->mols) S->arena.st = st;  // later uses follow the caller's stream
-        if (s != ESES_OK) {
-            std::string msg = g_err;
+            (void)hipStreamSynchronize(st);  // the build's temporaries may still be in use
             eses_free_candidates(c);
             g_err = msg;
             return s;
@@ -1817,7 +2074,6 @@ void eses_free_candidates(eses_candidates *c) {
         if (c->ev[q]) (void)hipEventDestroy(c->ev[q]);
     for (MolState *S : c->mols) {
         S->arena.release();
-        S->scratch.release();
         delete S;
     }
     (void)hipStreamSynchronize(c->stream);

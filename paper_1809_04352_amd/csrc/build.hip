@@ -7,6 +7,25 @@
 
 namespace eses {
 
+// Molecule of block b of a segmented launch: the largest q with start[q] <= b.
+__device__ inline int seg_mol(const Seg &s, int b) {
+    int lo = 0, hi = s.nm - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s.start[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// The molecule view m, its temporaries tmp and the block's index bid within
+// the molecule, for a kernel launched over a Seg.
+#define SEG_BEGIN(s)                                   \
+    const int seg_q_ = seg_mol(s, (int)blockIdx.x);     \
+    const Mol &m = (s).mols[seg_q_];                    \
+    const BuildTmp &tmp = (s).tmp[seg_q_];              \
+    const int bid = (int)blockIdx.x - (s).start[seg_q_]
+
 // ----------------------------------------------------------------- utilities
 
 __global__ void k_fill_i32(int *p, long long n, int v) { fill_i32(p, n, v); }
@@ -199,12 +218,109 @@ hipError_t fill_u32(uint32_t *p, long long n, uint32_t v, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Segmented scans (see launch.h): block b of the chunk passes finds its array
+// by binary search over the arrays' first chunks.
+__device__ inline int sseg_of(const ScanSeg *segs, int nseg, long long b) {
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].chunk0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(SCAN_BLOCK) k_sseg_reduce(const ScanSeg *segs, int nseg,
+                                                            int *sums) {
+    __shared__ int lds[SCAN_BLOCK / WAVE + 1];
+    const int g = sseg_of(segs, nseg, blockIdx.x);
+    const ScanSeg sg = segs[g];
+    const long long base = (blockIdx.x - sg.chunk0) * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    int v = 0;
+#pragma unroll
+    for (int q = 0; q < SCAN_ITEMS; ++q)
+        if (base + q < sg.n) v += sg.in[base + q];
+    int tot;
+    block_excl_scan<int, SCAN_BLOCK>(v, lds, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(SCAN_BLOCK) k_sseg_blocks(const ScanSeg *segs, int nseg,
+                                                            int *sums) {
+    __shared__ int lds[SCAN_BLOCK / WAVE + 1];
+    const ScanSeg sg = segs[blockIdx.x];
+    const long long nb = (sg.n + SCAN_TILE - 1) / SCAN_TILE;
+    int carry = 0;
+    for (long long b0 = 0; b0 < nb; b0 += SCAN_BLOCK) {
+        const long long q = b0 + threadIdx.x;
+        const int v = q < nb ? sums[sg.chunk0 + q] : 0;
+        int tot;
+        const int ex = block_excl_scan<int, SCAN_BLOCK>(v, lds, &tot);
+        if (q < nb) sums[sg.chunk0 + q] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) sg.out[sg.n] = carry;
+}
+
+__global__ void __launch_bounds__(SCAN_BLOCK) k_sseg_apply(const ScanSeg *segs, int nseg,
+                                                           const int *sums) {
+    __shared__ int lds[SCAN_BLOCK / WAVE + 1];
+    const int g = sseg_of(segs, nseg, blockIdx.x);
+    const ScanSeg sg = segs[g];
+    const long long base = (blockIdx.x - sg.chunk0) * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    int vals[SCAN_ITEMS];
+    int v = 0;
+#pragma unroll
+    for (int q = 0; q < SCAN_ITEMS; ++q) {
+        vals[q] = base + q < sg.n ? sg.in[base + q] : 0;
+        v += vals[q];
+    }
+    int tot;
+    int ex = block_excl_scan<int, SCAN_BLOCK>(v, lds, &tot) + sums[blockIdx.x];
+#pragma unroll
+    for (int q = 0; q < SCAN_ITEMS; ++q) {
+        if (base + q < sg.n) sg.out[base + q] = ex;
+        ex += vals[q];
+    }
+}
+
+long long scan_seg_chunk() { return SCAN_TILE; }
+
+hipError_t scan_seg(const ScanSeg *segs, int nseg, long long nchunks, int *sums, hipStream_t st) {
+    if (nseg <= 0) return hipSuccess;
+    if (nchunks > 0)
+        hipLaunchKernelGGL(k_sseg_reduce, dim3((unsigned)nchunks), dim3(SCAN_BLOCK), 0, st, segs,
+                           nseg, sums);
+    hipLaunchKernelGGL(k_sseg_blocks, dim3((unsigned)nseg), dim3(SCAN_BLOCK), 0, st, segs, nseg,
+                       sums);
+    if (nchunks > 0)
+        hipLaunchKernelGGL(k_sseg_apply, dim3((unsigned)nchunks), dim3(SCAN_BLOCK), 0, st, segs,
+                           nseg, sums);
+    return hipGetLastError();
+}
+
+__global__ void k_gather_ints(const int *const *addr, int n, int *out) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) out[q] = *addr[q];
+}
+
+hipError_t launch_gather_ints(const int *const *addr, int n, int *out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_ints, dim3((n + 255) / 256), dim3(256), 0, st, addr, n, out);
+    return hipGetLastError();
+}
+
 // ----------------------------------------------------------- atom binning
 
 // Bounds of the centres and the largest radius; flags non-finite or
 // non-positive input.  One block.
-__global__ void __launch_bounds__(256) k_bounds(const double *c, const double *r, long long n,
-                                                double *out, int *bad) {
+__global__ void __launch_bounds__(256) k_bounds(Seg sg) {
+    SEG_BEGIN(sg);
+    (void)bid;
+    const double *c = m.in_c, *r = m.in_r;
+    const long long n = m.n;
+    double *out = tmp.bounds;
+    int *bad = tmp.bad;
     __shared__ double sh[7][256];
     __shared__ int shbad[256];
     double v[7] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY, 0.0};
@@ -242,8 +358,10 @@ __device__ inline int cell_axis(const Mol &m, double x, int a) {
     return c < 0 ? 0 : (c >= m.nc[a] ? m.nc[a] - 1 : c);
 }
 
-__global__ void k_cell_count(Mol m, int *cell_id, int *count) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_cell_count(Seg sg) {
+    SEG_BEGIN(sg);
+    int *cell_id = tmp.cell_id, *count = tmp.cnt;
+    int i = bid * blockDim.x + threadIdx.x;
     if (i >= m.n) return;
     int c = cell_axis(m, m.in_c[3 * i], 0) +
             m.nc[0] * (cell_axis(m, m.in_c[3 * i + 1], 1) + m.nc[1] * cell_axis(m, m.in_c[3 * i + 2], 2));
@@ -251,8 +369,18 @@ __global__ void k_cell_count(Mol m, int *cell_id, int *count) {
     atomicAdd(&count[c], 1);
 }
 
-__global__ void k_cell_scatter(Mol m, const int *cell_id, int *fill, int *slot_orig) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Cursor per cell: its first slot (cell_start after the scan).
+__global__ void k_cell_fill_init(Seg sg) {
+    SEG_BEGIN(sg);
+    const int c = bid * blockDim.x + threadIdx.x;
+    if (c <= m.ncell) tmp.fillb[c] = m.cell_start[c];
+}
+
+__global__ void k_cell_scatter(Seg sg) {
+    SEG_BEGIN(sg);
+    const int *cell_id = tmp.cell_id;
+    int *fill = tmp.fillb, *slot_orig = tmp.slot;
+    int i = bid * blockDim.x + threadIdx.x;
     if (i >= m.n) return;
     int pos = atomicAdd(&fill[cell_id[i]], 1);
     slot_orig[pos] = i;
@@ -263,10 +391,12 @@ __global__ void k_cell_scatter(Mol m, const int *cell_id, int *fill, int *slot_o
 // a cell larger than the LDS slice is sorted by one lane.
 constexpr int CS_WAVES = 4, CS_MAX = 256;
 
-__global__ void __launch_bounds__(CS_WAVES *WAVE) k_cell_sort(Mol m, int *slot_orig) {
+__global__ void __launch_bounds__(CS_WAVES *WAVE) k_cell_sort(Seg sg) {
     __shared__ int ids[CS_WAVES][CS_MAX];
+    SEG_BEGIN(sg);
+    int *slot_orig = tmp.slot;
     const int w = threadIdx.x / WAVE, lane = lane_id();
-    const int c = blockIdx.x * CS_WAVES + w;
+    const int c = bid * CS_WAVES + w;
     if (c >= m.ncell) return;  // uniform across the wavefront; no workgroup barrier below
     const int b = m.cell_start[c], n = m.cell_start[c + 1] - b;
     if (n <= 1) return;
@@ -295,8 +425,10 @@ __global__ void __launch_bounds__(CS_WAVES *WAVE) k_cell_sort(Mol m, int *slot_o
     }
 }
 
-__global__ void k_gather_atoms(Mol m, const int *slot_orig) {
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_gather_atoms(Seg sg) {
+    SEG_BEGIN(sg);
+    const int *slot_orig = tmp.slot;
+    int q = bid * blockDim.x + threadIdx.x;
     if (q >= m.n) return;
     int i = slot_orig[q];
     m.orig[q] = i;
@@ -321,12 +453,14 @@ __device__ inline bool fill_ok(const Mol &m, long long at, long long end) {
 constexpr int NB_WAVES = 4;
 
 template <bool FILL>
-__global__ void __launch_bounds__(NB_WAVES *WAVE) k_nbr(Mol m, int *nbr_cnt, int *circ_cnt) {
+__global__ void __launch_bounds__(NB_WAVES *WAVE) k_nbr(Seg sg) {
     // per wavefront: the first atom and inclusive end offset of each of the
     // stencil's (y, z) cell rows (at most 9)
     __shared__ int rbeg[NB_WAVES][9], rend[NB_WAVES][9];
+    SEG_BEGIN(sg);
+    int *nbr_cnt = tmp.nbr_cnt, *circ_cnt = tmp.circ_cnt;
     const int wv = threadIdx.x / WAVE;
-    int i = blockIdx.x * NB_WAVES + wv;
+    int i = bid * NB_WAVES + wv;
     if (i >= m.n) return;  // uniform across the wavefront (no block barriers)
     const int lane = lane_id();
     double4 ai = m.atom[i];
@@ -415,11 +549,13 @@ __global__ void __launch_bounds__(NB_WAVES *WAVE) k_nbr(Mol m, int *nbr_cnt, int
 constexpr int NS_WAVES = 4;
 constexpr int NS_MAX = 256;
 
-__global__ void __launch_bounds__(NS_WAVES *WAVE) k_nbr_sort(Mol m) {
+__global__ void __launch_bounds__(NS_WAVES *WAVE) k_nbr_sort(Seg sg) {
     __shared__ double keys[NS_WAVES][NS_MAX];
+    SEG_BEGIN(sg);
+    (void)tmp;
     const int w = threadIdx.x / WAVE;
     const int lane = lane_id();
-    const int i = blockIdx.x * NS_WAVES + w;
+    const int i = bid * NS_WAVES + w;
     // every wavefront reaches the barrier below; `mode` says what it does
     int b = 0, n = 0, mode = 0;  // 0 idle, 1 copy unsorted, 2 rank
     if (i < m.n) {
@@ -679,11 +815,14 @@ __device__ void vertex_circle(const Mol &m, int c, int c0, int i, int nb, int ne
 // One workgroup per atom i, one wavefront per circle (i, j) of i; i's
 // neighbours (cover order) are staged in LDS for the exposure tests.
 template <bool FILL>
-__global__ void __launch_bounds__(VX_WAVES *WAVE) k_vertex(Mol m, int *vcnt, VertexPool pool) {
+__global__ void __launch_bounds__(VX_WAVES *WAVE) k_vertex(Seg sg) {
     __shared__ VxLds L;
     __shared__ int pj[VX_NBR], poff[VX_NBR + 1], vc[VX_NBR], scan_lds[VX_WAVES + 1];
     __shared__ uint32_t fl[VX_NBR];
-    const int i = blockIdx.x;
+    SEG_BEGIN(sg);
+    int *vcnt = tmp.vcnt;
+    const VertexPool &pool = tmp.pool;
+    const int i = bid;
     const int c0 = m.circ_off[i], c1 = m.circ_off[i + 1];
     if (c0 == c1) return;  // uniform across the workgroup
     if (FILL && m.vert_off[c0] == m.vert_off[c1]) return;  // no probe position on i's circles
@@ -808,8 +947,10 @@ __global__ void __launch_bounds__(VX_WAVES *WAVE) k_vertex(Mol m, int *vcnt, Ver
 
 // A circle that no other sphere cuts is wholly inside or wholly outside each
 // other SAS ball, so one test point decides whether it is admissible.
-__global__ void k_circle_free(Mol m) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_circle_free(Seg sg) {
+    SEG_BEGIN(sg);
+    (void)tmp;
+    int c = bid * blockDim.x + threadIdx.x;
     if (c >= m.ncirc) return;
     if (m.cflag[c] & CF_CROSSED) return;
     int i = m.circ_i[c], j = m.circ_j[c];
@@ -835,8 +976,10 @@ __global__ void k_circle_free(Mol m) {
 //   A face has an admissible point iff it carries an admissible
 //   three-sphere point or admissible crossing-free circle, or it has no
 //   circle at all and lies in no other ball (an isolated sphere).
-__global__ void k_atom_features(Mol m, int *face_cnt) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_atom_features(Seg sg) {
+    SEG_BEGIN(sg);
+    int *face_cnt = tmp.face_cnt;
+    int i = bid * blockDim.x + threadIdx.x;
     if (i >= m.n) return;
     uint32_t f = m.aflag[i];
     bool face = (f & (AF_EXPOSED_VERTEX | AF_EXPOSED_CIRCLE)) ||
@@ -847,8 +990,10 @@ __global__ void k_atom_features(Mol m, int *face_cnt) {
 
 // ------------------------------------------------------ exposed feature lists
 
-__global__ void k_face_list(Mol m, int *cut_cnt) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_face_list(Seg sg) {
+    SEG_BEGIN(sg);
+    int *cut_cnt = tmp.fcut_cnt;
+    int i = bid * blockDim.x + threadIdx.x;
     if (i >= m.n) return;
     if (!(m.aflag[i] & AF_FACE)) return;
     int f = m.face_off_atom[i];
@@ -858,8 +1003,10 @@ __global__ void k_face_list(Mol m, int *cut_cnt) {
 
 constexpr int FC_WAVES = 4;
 
-__global__ void __launch_bounds__(FC_WAVES *WAVE) k_face_cuts(Mol m) {
-    int f = blockIdx.x * FC_WAVES + threadIdx.x / WAVE;
+__global__ void __launch_bounds__(FC_WAVES *WAVE) k_face_cuts(Seg sg) {
+    SEG_BEGIN(sg);
+    (void)tmp;
+    int f = bid * FC_WAVES + threadIdx.x / WAVE;
     if (f >= m.nface) return;  // uniform across the wavefront
     int i = m.face_atom[f];
     double4 ai = m.atom[i];
@@ -878,14 +1025,18 @@ __global__ void __launch_bounds__(FC_WAVES *WAVE) k_face_cuts(Mol m) {
 // Exposed circles: a 0/1 flag per circle (scanned into positions), the id
 // list, then per exposed circle the neighbours of its owner that reach the
 // circle (distance from c_k to the circle below s_k), one wavefront per circle.
-__global__ void k_ec_flag(Mol m, int *ecf) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_ec_flag(Seg sg) {
+    SEG_BEGIN(sg);
+    int *ecf = tmp.ecf;
+    int c = bid * blockDim.x + threadIdx.x;
     if (c >= m.ncirc) return;
     ecf[c] = (m.cflag[c] & CF_EXPOSED) ? 1 : 0;
 }
 
-__global__ void k_ec_ids(Mol m, const int *ec_pos) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_ec_ids(Seg sg) {
+    SEG_BEGIN(sg);
+    const int *ec_pos = tmp.ec_pos;
+    int c = bid * blockDim.x + threadIdx.x;
     if (c >= m.ncirc) return;
     if (m.cflag[c] & CF_EXPOSED) m.ec_circ[ec_pos[c]] = c;
 }
@@ -893,8 +1044,10 @@ __global__ void k_ec_ids(Mol m, const int *ec_pos) {
 constexpr int EC_WAVES = 4;
 
 template <bool FILL>
-__global__ void __launch_bounds__(EC_WAVES *WAVE) k_ec_cuts(Mol m, int *cut_cnt) {
-    int e = blockIdx.x * EC_WAVES + threadIdx.x / WAVE;
+__global__ void __launch_bounds__(EC_WAVES *WAVE) k_ec_cuts(Seg sg) {
+    SEG_BEGIN(sg);
+    int *cut_cnt = tmp.eccut_cnt;
+    int e = bid * EC_WAVES + threadIdx.x / WAVE;
     if (e >= m.nec) return;  // uniform across the wavefront
     const int lane = lane_id();
     int c = m.ec_circ[e];
@@ -933,8 +1086,10 @@ __global__ void __launch_bounds__(EC_WAVES *WAVE) k_ec_cuts(Mol m, int *cut_cnt)
 }
 
 // Per-atom offsets of the circle-ordered exposed-circle and vertex lists.
-__global__ void k_feature_off_atom(Mol m, const int *ec_pos) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_feature_off_atom(Seg sg) {
+    SEG_BEGIN(sg);
+    const int *ec_pos = tmp.ec_pos;
+    int i = bid * blockDim.x + threadIdx.x;
     if (i > m.n) return;
     m.vert_off_atom[i] = m.vert_off[m.circ_off[i]];
     m.ec_off_atom[i] = ec_pos[m.circ_off[i]];
@@ -966,15 +1121,17 @@ __device__ inline int tile_row(const int *incl, int nrow, int t) {
 constexpr int TILE_KEEP = 96;  // entries of a tile's lists the count pass keeps (LDS, pool slot)
 
 template <bool FILL>
-__global__ void __launch_bounds__(TILE_WAVES *WAVE) k_tiles(Mol m, int *cntA, int *cntF,
-                                                             int *cntC, int *cntV, TilePool tp) {
+__global__ void __launch_bounds__(TILE_WAVES *WAVE) k_tiles(Seg sg) {
     // per wavefront and kind (atoms, exposed circles, vertices): each row's
     // first candidate and inclusive end offset
     __shared__ int rbeg[TILE_WAVES][3][WAVE], rend[TILE_WAVES][3][WAVE];
     // count pass: the first TILE_KEEP entries of the tile's four lists
     __shared__ int keep[FILL ? 1 : TILE_WAVES][4][FILL ? 1 : TILE_KEEP];
+    SEG_BEGIN(sg);
+    int *cntA = tmp.cA, *cntF = tmp.cF, *cntC = tmp.cC, *cntV = tmp.cV;
+    const TilePool &tp = tmp.tp;
     const int wv = threadIdx.x / WAVE;
-    int tile = blockIdx.x * TILE_WAVES + wv;
+    int tile = bid * TILE_WAVES + wv;
     if (tile >= m.ntiles) return;  // uniform across the wavefront (no block barriers)
     // the fill pass skips tiles whose lists the count pass pooled and those
     // whose four lists are empty (most of a grid's tiles lie away from the
@@ -1126,10 +1283,11 @@ __global__ void __launch_bounds__(TILE_WAVES *WAVE) k_tiles(Mol m, int *cntA, in
 }
 
 // Pooled tile lists to their places: one wavefront per tile.
-__global__ void __launch_bounds__(TILE_WAVES *WAVE) k_tiles_place(Mol m, TilePool tp,
-                                                                   const int *cA, const int *cF,
-                                                                   const int *cC, const int *cV) {
-    const int tile = blockIdx.x * TILE_WAVES + threadIdx.x / WAVE;
+__global__ void __launch_bounds__(TILE_WAVES *WAVE) k_tiles_place(Seg sg) {
+    SEG_BEGIN(sg);
+    const TilePool &tp = tmp.tp;
+    const int *cA = tmp.cA, *cF = tmp.cF, *cC = tmp.cC, *cV = tmp.cV;
+    const int tile = bid * TILE_WAVES + threadIdx.x / WAVE;
     if (tile >= m.ntiles) return;
     const int b = tp.off[tile];
     if (b < 0) return;
@@ -1187,61 +1345,15 @@ static inline unsigned blocks_for(long long n, int bs) {
     return (unsigned)(b < 1 ? 1 : b);
 }
 
-hipError_t launch_bounds(const double *c, const double *r, long long n, double *out, int *bad,
-                         hipStream_t st) {
-    hipLaunchKernelGGL(k_bounds, dim3(1), dim3(256), 0, st, c, r, n, out, bad);
-    return hipGetLastError();
-}
-
-hipError_t launch_cell_count(const Mol &m, int *cell_id, int *count, hipStream_t st) {
-    hipLaunchKernelGGL(k_cell_count, dim3(blocks_for(m.n, 256)), dim3(256), 0, st, m, cell_id, count);
-    return hipGetLastError();
-}
-
-hipError_t launch_cell_scatter(const Mol &m, const int *cell_id, int *fill, int *slot_orig,
-                               hipStream_t st) {
-    hipLaunchKernelGGL(k_cell_scatter, dim3(blocks_for(m.n, 256)), dim3(256), 0, st, m, cell_id,
-                       fill, slot_orig);
-    return hipGetLastError();
-}
-
-hipError_t launch_cell_sort_gather(const Mol &m, int *slot_orig, hipStream_t st) {
-    hipLaunchKernelGGL(k_cell_sort, dim3(blocks_for(m.ncell, CS_WAVES)), dim3(CS_WAVES * WAVE), 0, st,
-                       m, slot_orig);
-    hipLaunchKernelGGL(k_gather_atoms, dim3(blocks_for(m.n, 256)), dim3(256), 0, st, m, slot_orig);
-    return hipGetLastError();
-}
-
-hipError_t launch_nbr(const Mol &m, bool fill, int *nbr_cnt, int *circ_cnt, hipStream_t st) {
-    unsigned nb = blocks_for(m.n, NB_WAVES);
-    if (fill)
-        hipLaunchKernelGGL(k_nbr<true>, dim3(nb), dim3(NB_WAVES * WAVE), 0, st, m, nbr_cnt, circ_cnt);
-    else
-        hipLaunchKernelGGL(k_nbr<false>, dim3(nb), dim3(NB_WAVES * WAVE), 0, st, m, nbr_cnt, circ_cnt);
-    return hipGetLastError();
-}
-
-hipError_t launch_nbr_sort(const Mol &m, hipStream_t st) {
-    hipLaunchKernelGGL(k_nbr_sort, dim3(blocks_for(m.n, NS_WAVES)), dim3(NS_WAVES * WAVE), 0, st, m);
-    return hipGetLastError();
-}
-
-hipError_t launch_vertex(const Mol &m, bool fill, int *vcnt, const VertexPool &pool,
-                         hipStream_t st) {
-    if (m.ncirc <= 0) return hipSuccess;
-    if (fill)
-        hipLaunchKernelGGL(k_vertex<true>, dim3(m.n), dim3(VX_WAVES * WAVE), 0, st, m, vcnt, pool);
-    else
-        hipLaunchKernelGGL(k_vertex<false>, dim3(m.n), dim3(VX_WAVES * WAVE), 0, st, m, vcnt,
-                           pool);
-    return hipGetLastError();
-}
-
 // Pooled probe positions into their circles' ranges (vcnt[c], the circle's
 // count, is consumed as a cursor), then every circle's range ordered as the
 // fill pass writes it: ascending k, "+" before "-".
-__global__ void k_vertex_place(Mol m, VertexPool pool, int n, int *vcnt) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_vertex_place(Seg sg) {
+    SEG_BEGIN(sg);
+    const VertexPool &pool = tmp.pool;
+    int *vcnt = tmp.vcnt;
+    const int n = tmp.npool;
+    const int q = bid * blockDim.x + threadIdx.x;
     if (q >= n) return;
     const int4 id = pool.id[q];
     const int w = m.vert_off[id.x] + atomicSub(&vcnt[id.x], 1) - 1;
@@ -1250,8 +1362,10 @@ __global__ void k_vertex_place(Mol m, VertexPool pool, int n, int *vcnt) {
     m.vert_ijks[w] = make_int4(m.circ_i[id.x], m.circ_j[id.x], id.z, id.w);
 }
 
-__global__ void k_vertex_order(Mol m) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_vertex_order(Seg sg) {
+    SEG_BEGIN(sg);
+    (void)tmp;
+    const int c = bid * blockDim.x + threadIdx.x;
     if (c >= m.ncirc) return;
     const int b = m.vert_off[c], e = m.vert_off[c + 1];
     for (int a = b + 1; a < e; ++a) {
@@ -1270,82 +1384,81 @@ __global__ void k_vertex_order(Mol m) {
     }
 }
 
-hipError_t launch_vertex_place(const Mol &m, const VertexPool &pool, int n, int *vcnt,
-                               hipStream_t st) {
-    if (n > 0)
-        hipLaunchKernelGGL(k_vertex_place, dim3(blocks_for(n, 256)), dim3(256), 0, st, m, pool, n,
-                           vcnt);
+// ------------------------------------------------------ segmented launches
+
+// Block counts of one molecule for each build kernel (the launchers of a
+// build stage add these up over the molecules of a batch).
+long long build_blocks(BuildKernel k, const Mol &m, const BuildTmp &t) {
+    switch (k) {
+    case BK_BOUNDS: return 1;
+    case BK_CELL_COUNT: return blocks_for(m.n, 256);
+    case BK_CELL_FILL: return blocks_for(m.ncell + 1, 256);
+    case BK_CELL_SCATTER: return blocks_for(m.n, 256);
+    case BK_CELL_SORT: return blocks_for(m.ncell, CS_WAVES);
+    case BK_GATHER: return blocks_for(m.n, 256);
+    case BK_NBR: return blocks_for(m.n, NB_WAVES);
+    case BK_NBR_SORT: return blocks_for(m.n, NS_WAVES);
+    case BK_VERTEX: return m.ncirc > 0 ? m.n : 0;
+    case BK_VERTEX_PLACE: return t.pool.use && t.npool > 0 ? blocks_for(t.npool, 256) : 0;
+    case BK_VERTEX_ORDER: return m.ncirc > 0 && m.nvert > 0 ? blocks_for(m.ncirc, 256) : 0;
+    case BK_CIRCLE_FREE: return m.ncirc > 0 ? blocks_for(m.ncirc, 128) : 0;
+    case BK_ATOM_FEATURES: return blocks_for(m.n, 256);
+    case BK_EC_FLAG: return m.ncirc > 0 ? blocks_for(m.ncirc, 256) : 0;
+    case BK_EC_IDS: return m.ncirc > 0 ? blocks_for(m.ncirc, 256) : 0;
+    case BK_FEATURE_OFF: return blocks_for(m.n + 1, 256);
+    case BK_FACE_LIST: return blocks_for(m.n, 256);
+    case BK_FACE_CUTS: return m.nface > 0 ? blocks_for(m.nface, FC_WAVES) : 0;
+    case BK_EC_CUTS: return m.nec > 0 ? blocks_for(m.nec, EC_WAVES) : 0;
+    case BK_TILES: return blocks_for(m.ntiles, TILE_WAVES);
+    case BK_TILES_FILL: return t.tp_unpooled ? blocks_for(m.ntiles, TILE_WAVES) : 0;
+    case BK_TILES_PLACE: return blocks_for(m.ntiles, TILE_WAVES);
+    }
+    return 0;
+}
+
+hipError_t launch_build(BuildKernel k, const Seg &s, long long nblocks, hipStream_t st) {
+    if (nblocks <= 0) return hipSuccess;
+    const dim3 g((unsigned)nblocks);
+    switch (k) {
+    case BK_BOUNDS: hipLaunchKernelGGL(k_bounds, g, dim3(256), 0, st, s); break;
+    case BK_CELL_COUNT: hipLaunchKernelGGL(k_cell_count, g, dim3(256), 0, st, s); break;
+    case BK_CELL_FILL: hipLaunchKernelGGL(k_cell_fill_init, g, dim3(256), 0, st, s); break;
+    case BK_CELL_SCATTER: hipLaunchKernelGGL(k_cell_scatter, g, dim3(256), 0, st, s); break;
+    case BK_CELL_SORT: hipLaunchKernelGGL(k_cell_sort, g, dim3(CS_WAVES * WAVE), 0, st, s); break;
+    case BK_GATHER: hipLaunchKernelGGL(k_gather_atoms, g, dim3(256), 0, st, s); break;
+    case BK_NBR: hipLaunchKernelGGL(k_nbr<false>, g, dim3(NB_WAVES * WAVE), 0, st, s); break;
+    case BK_NBR_SORT: hipLaunchKernelGGL(k_nbr_sort, g, dim3(NS_WAVES * WAVE), 0, st, s); break;
+    case BK_VERTEX: hipLaunchKernelGGL(k_vertex<false>, g, dim3(VX_WAVES * WAVE), 0, st, s); break;
+    case BK_VERTEX_PLACE: hipLaunchKernelGGL(k_vertex_place, g, dim3(256), 0, st, s); break;
+    case BK_VERTEX_ORDER: hipLaunchKernelGGL(k_vertex_order, g, dim3(256), 0, st, s); break;
+    case BK_CIRCLE_FREE: hipLaunchKernelGGL(k_circle_free, g, dim3(128), 0, st, s); break;
+    case BK_ATOM_FEATURES: hipLaunchKernelGGL(k_atom_features, g, dim3(256), 0, st, s); break;
+    case BK_EC_FLAG: hipLaunchKernelGGL(k_ec_flag, g, dim3(256), 0, st, s); break;
+    case BK_EC_IDS: hipLaunchKernelGGL(k_ec_ids, g, dim3(256), 0, st, s); break;
+    case BK_FEATURE_OFF: hipLaunchKernelGGL(k_feature_off_atom, g, dim3(256), 0, st, s); break;
+    case BK_FACE_LIST: hipLaunchKernelGGL(k_face_list, g, dim3(256), 0, st, s); break;
+    case BK_FACE_CUTS: hipLaunchKernelGGL(k_face_cuts, g, dim3(FC_WAVES * WAVE), 0, st, s); break;
+    case BK_EC_CUTS: hipLaunchKernelGGL(k_ec_cuts<false>, g, dim3(EC_WAVES * WAVE), 0, st, s); break;
+    case BK_TILES: hipLaunchKernelGGL(k_tiles<false>, g, dim3(TILE_WAVES * WAVE), 0, st, s); break;
+    case BK_TILES_FILL: hipLaunchKernelGGL(k_tiles<true>, g, dim3(TILE_WAVES * WAVE), 0, st, s); break;
+    case BK_TILES_PLACE: hipLaunchKernelGGL(k_tiles_place, g, dim3(TILE_WAVES * WAVE), 0, st, s); break;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_vertex_order(const Mol &m, hipStream_t st) {
-    if (m.ncirc <= 0 || m.nvert <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_vertex_order, dim3(blocks_for(m.ncirc, 256)), dim3(256), 0, st, m);
-    return hipGetLastError();
-}
-
-hipError_t launch_circle_free(const Mol &m, hipStream_t st) {
-    if (m.ncirc <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_circle_free, dim3(blocks_for(m.ncirc, 128)), dim3(128), 0, st, m);
-    return hipGetLastError();
-}
-
-hipError_t launch_atom_features(const Mol &m, int *face_cnt, hipStream_t st) {
-    hipLaunchKernelGGL(k_atom_features, dim3(blocks_for(m.n, 256)), dim3(256), 0, st, m, face_cnt);
-    return hipGetLastError();
-}
-
-hipError_t launch_ec_flag(const Mol &m, int *ecf, hipStream_t st) {
-    hipLaunchKernelGGL(k_ec_flag, dim3(blocks_for(m.ncirc, 256)), dim3(256), 0, st, m, ecf);
-    return hipGetLastError();
-}
-
-hipError_t launch_ec_ids(const Mol &m, const int *ec_pos, hipStream_t st) {
-    hipLaunchKernelGGL(k_ec_ids, dim3(blocks_for(m.ncirc, 256)), dim3(256), 0, st, m, ec_pos);
-    hipLaunchKernelGGL(k_feature_off_atom, dim3(blocks_for(m.n + 1, 256)), dim3(256), 0, st, m, ec_pos);
-    return hipGetLastError();
-}
-
-hipError_t launch_face_list(const Mol &m, int *cut_cnt, hipStream_t st) {
-    hipLaunchKernelGGL(k_face_list, dim3(blocks_for(m.n, 256)), dim3(256), 0, st, m, cut_cnt);
-    return hipGetLastError();
-}
-
-hipError_t launch_face_cuts(const Mol &m, hipStream_t st) {
-    if (m.nface <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_face_cuts, dim3(blocks_for(m.nface, FC_WAVES)), dim3(FC_WAVES * WAVE), 0, st, m);
-    return hipGetLastError();
-}
-
-hipError_t launch_ec_cuts(const Mol &m, bool fill, int *cut_cnt, hipStream_t st) {
-    if (m.nec <= 0) return hipSuccess;
-    unsigned nb = blocks_for(m.nec, EC_WAVES);
-    if (fill)
-        hipLaunchKernelGGL(k_ec_cuts<true>, dim3(nb), dim3(EC_WAVES * WAVE), 0, st, m, cut_cnt);
-    else
-        hipLaunchKernelGGL(k_ec_cuts<false>, dim3(nb), dim3(EC_WAVES * WAVE), 0, st, m, cut_cnt);
-    return hipGetLastError();
-}
-
-hipError_t launch_tiles(const Mol &m, bool fill, int *cA, int *cF, int *cC, int *cV,
-                        const TilePool &tp, hipStream_t st) {
-    unsigned nb = blocks_for(m.ntiles, TILE_WAVES);
-    if (fill)
-        hipLaunchKernelGGL(k_tiles<true>, dim3(nb), dim3(TILE_WAVES * WAVE), 0, st, m, cA, cF, cC,
-                           cV, tp);
-    else
-        hipLaunchKernelGGL(k_tiles<false>, dim3(nb), dim3(TILE_WAVES * WAVE), 0, st, m, cA, cF,
-                           cC, cV, tp);
+// The fill passes (second pass of a count/fill pair).
+hipError_t launch_build_fill(BuildKernel k, const Seg &s, long long nblocks, hipStream_t st) {
+    if (nblocks <= 0) return hipSuccess;
+    const dim3 g((unsigned)nblocks);
+    switch (k) {
+    case BK_NBR: hipLaunchKernelGGL(k_nbr<true>, g, dim3(NB_WAVES * WAVE), 0, st, s); break;
+    case BK_VERTEX: hipLaunchKernelGGL(k_vertex<true>, g, dim3(VX_WAVES * WAVE), 0, st, s); break;
+    case BK_EC_CUTS: hipLaunchKernelGGL(k_ec_cuts<true>, g, dim3(EC_WAVES * WAVE), 0, st, s); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 int tile_keep_max() { return TILE_KEEP; }
-
-hipError_t launch_tiles_place(const Mol &m, const TilePool &tp, const int *cA, const int *cF,
-                              const int *cC, const int *cV, hipStream_t st) {
-    hipLaunchKernelGGL(k_tiles_place, dim3(blocks_for(m.ntiles, TILE_WAVES)),
-                       dim3(TILE_WAVES * WAVE), 0, st, m, tp, cA, cF, cC, cV);
-    return hipGetLastError();
-}
 
 }  // namespace eses

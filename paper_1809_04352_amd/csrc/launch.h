@@ -26,14 +26,7 @@ hipError_t copy_i32(int *dst, const int *src, long long n, hipStream_t st);
 hipError_t fill_u32(uint32_t *p, long long n, uint32_t v, hipStream_t st);
 
 // stage 1
-hipError_t launch_bounds(const double *c, const double *r, long long n, double *out, int *bad,
-                         hipStream_t st);
-hipError_t launch_cell_count(const Mol &m, int *cell_id, int *count, hipStream_t st);
-hipError_t launch_cell_scatter(const Mol &m, const int *cell_id, int *fill, int *slot_orig,
-                               hipStream_t st);
-hipError_t launch_cell_sort_gather(const Mol &m, int *slot_orig, hipStream_t st);
-hipError_t launch_nbr(const Mol &m, bool fill, int *nbr_cnt, int *circ_cnt, hipStream_t st);
-hipError_t launch_nbr_sort(const Mol &m, hipStream_t st);
+
 // Probe positions found by the count pass of the atoms whose neighbours and
 // circles fit in LDS (p: x, y, z, -; id: circle, -, k, sign); count: one
 // int, zeroed before the count pass.  When count <= cap after it,
@@ -47,18 +40,7 @@ struct VertexPool {
     int cap;
     int use;
 };
-hipError_t launch_vertex(const Mol &m, bool fill, int *vcnt, const VertexPool &pool,
-                         hipStream_t st);
-hipError_t launch_vertex_place(const Mol &m, const VertexPool &pool, int n, int *vcnt,
-                               hipStream_t st);
-hipError_t launch_vertex_order(const Mol &m, hipStream_t st);
-hipError_t launch_circle_free(const Mol &m, hipStream_t st);
-hipError_t launch_atom_features(const Mol &m, int *face_cnt, hipStream_t st);
-hipError_t launch_ec_flag(const Mol &m, int *ecf, hipStream_t st);
-hipError_t launch_ec_ids(const Mol &m, const int *ec_pos, hipStream_t st);
-hipError_t launch_face_list(const Mol &m, int *cut_cnt, hipStream_t st);
-hipError_t launch_face_cuts(const Mol &m, hipStream_t st);
-hipError_t launch_ec_cuts(const Mol &m, bool fill, int *cut_cnt, hipStream_t st);
+
 // Tile lists kept by the count pass: each tile's four lists (atoms, faces,
 // circles, probes, in that order) copied into its slot of `pool` (cap ints
 // per tile, cap <= tile_keep_max()) at off[t] = t * cap, or off[t] = -1 when
@@ -69,10 +51,66 @@ struct TilePool {
     int cap;
 };
 int tile_keep_max();
-hipError_t launch_tiles_place(const Mol &m, const TilePool &tp, const int *cA, const int *cF,
-                              const int *cC, const int *cV, hipStream_t st);
-hipError_t launch_tiles(const Mol &m, bool fill, int *cA, int *cF, int *cC, int *cV,
-                        const TilePool &tp, hipStream_t st);
+
+// Temporaries of one molecule's build (device pointers; the counts npool and
+// tp_unpooled are set by the host from read-backs before the kernels that
+// use them).
+struct BuildTmp {
+    double *bounds;       // [8]: centre bounds (lo, hi), largest radius
+    int *bad;             // non-finite or non-positive input
+    int *cell_id, *cnt, *fillb, *slot;
+    int *nbr_cnt, *circ_cnt;
+    int *vcnt;            // [ncirc] probe positions per circle
+    VertexPool pool;
+    int npool;            // positions the count pass pooled
+    int *face_cnt, *ecf, *ec_pos;
+    int *fcut_cnt, *eccut_cnt;
+    int *cA, *cF, *cC, *cV;  // per-tile list lengths
+    TilePool tp;
+    int tp_unpooled;      // some tile's lists did not fit its pool slot
+    int pad;
+};
+
+// One launch over the blocks of several molecules: block b works for
+// molecule q with start[q] <= b < start[q + 1] (the largest such q, so
+// molecules with no blocks are skipped), as that molecule's block
+// b - start[q].  mols, tmp: device arrays of the molecules' views and
+// temporaries.
+struct Seg {
+    const Mol *mols;
+    const BuildTmp *tmp;
+    const int *start;
+    int nm;
+};
+
+enum BuildKernel {
+    BK_BOUNDS, BK_CELL_COUNT, BK_CELL_FILL, BK_CELL_SCATTER, BK_CELL_SORT, BK_GATHER, BK_NBR,
+    BK_NBR_SORT, BK_VERTEX, BK_VERTEX_PLACE, BK_VERTEX_ORDER, BK_CIRCLE_FREE, BK_ATOM_FEATURES,
+    BK_EC_FLAG, BK_EC_IDS, BK_FEATURE_OFF, BK_FACE_LIST, BK_FACE_CUTS, BK_EC_CUTS, BK_TILES,
+    BK_TILES_FILL, BK_TILES_PLACE
+};
+// Blocks of kernel k for one molecule, and the launch of k (count pass where
+// k has two) or of its fill pass (BK_NBR, BK_VERTEX, BK_EC_CUTS) over a Seg.
+long long build_blocks(BuildKernel k, const Mol &m, const BuildTmp &t);
+hipError_t launch_build(BuildKernel k, const Seg &s, long long nblocks, hipStream_t st);
+hipError_t launch_build_fill(BuildKernel k, const Seg &s, long long nblocks, hipStream_t st);
+
+// Exclusive scans of many int arrays of their own lengths in three launches
+// (chunk sums, one workgroup per array over its chunk sums, chunks): array g
+// scans in[0..n) into out[0..n] (out[n] = total).  chunk0[g]: the array's
+// first chunk (prefix of ceil(n / scan_seg_chunk()) over the arrays);
+// sums: nchunks ints of workspace.  Arrays of length 0 get out[0] = 0.
+struct ScanSeg {
+    const int *in;
+    int *out;
+    long long n;
+    long long chunk0;
+};
+long long scan_seg_chunk();
+hipError_t scan_seg(const ScanSeg *segs, int nseg, long long nchunks, int *sums, hipStream_t st);
+
+// Ints at device addresses addr[0..n) gathered into out[0..n).
+hipError_t launch_gather_ints(const int *const *addr, int n, int *out, hipStream_t st);
 
 // stage 2
 hipError_t launch_classify(const Mol &m, bool fp32, uint8_t *labels, hipStream_t st);
