@@ -639,71 +639,112 @@ struct VxLds {
 // i above j, the two points of the circle at distance s_k from c_k, kept if
 // no other neighbour's SAS ball holds them (i's neighbours 0..nst-1 from
 // LDS, the rest from global memory).
+// Geometry of c_k against circle (o, R, n): w = c_k - o, its axial part t,
+// in-plane part p (|p|^2 = b2), |w|^2 = ww and num = |w|^2 + R^2 - s_k^2.
+// One code path (and no contraction) for every caller, so the values are
+// bitwise the same wherever they are computed.
+struct VxAxis {
+    double px, py, pz, t, b2, ww, num, sk;
+};
+
+__device__ inline VxAxis vx_axis(const Mol &m, double4 oR, double4 n, double4 ak) {
+#pragma clang fp contract(off)
+    VxAxis g;
+    g.sk = ak.w + m.rho;
+    const double wx = ak.x - oR.x, wy = ak.y - oR.y, wz = ak.z - oR.z;
+    g.t = wx * n.x + wy * n.y + wz * n.z;
+    g.px = wx - g.t * n.x;
+    g.py = wy - g.t * n.y;
+    g.pz = wz - g.t * n.z;
+    g.b2 = g.px * g.px + g.py * g.py + g.pz * g.pz;
+    g.ww = wx * wx + wy * wy + wz * wz;
+    g.num = g.ww + oR.w * oR.w - g.sk * g.sk;
+    return g;
+}
+
+// False only when S_k certainly misses the circle: num^2 > 4 R^2 b2 (1 +
+// 1e-10) puts |cos(phi)| = |num| / (2 R sqrt(b2)) above 1 by far more than
+// the few roundings of its computed value, which is then outside [-1, 1] too.
+__device__ inline bool vx_maybe_live(const VxAxis &g, double R) {
+    return g.num * g.num <= 4.0 * R * R * g.b2 * (1.0 + 1e-10);
+}
+
 // The two points of circle (o, R, n) at distance s_k from c_k (isolated
-// points when c_k is off the axis) and whether each is exposed: in no other
-// neighbour's open SAS ball (i's neighbours 0..nst-1 from LDS in cover order,
-// the rest from global memory; j and k themselves skipped).  The loop over
-// neighbours is uniform across the wavefront and ends when no lane has an
-// exposed candidate left.
-// `eps` receives a bound on the rounding error of the two positions (first
-// order, safety 4), propagated from the circle's bound n.w = e: w = c_k - o
-// within e + u|w|, its axial part t within 3 (e + 7u|w|), the in-plane part
-// within those plus 6u|t|, so its length b and direction e' = w_perp / b
-// within that over b; cos(phi) = (|w|^2 + R^2 - s_k^2) / (2 R b) within the
+// points when c_k is off the axis); `live` when they exist, `crossed` when
+// they are two distinct points (S_k cuts the circle).  b and cos/sin(phi)
+// are kept for the error bound.
+struct VxPts {
+    double v0[3], v1[3];
+    double b, cphi, sphi;
+    bool live, crossed;
+};
+
+__device__ inline VxPts vertex_points(double4 oR, double4 n, const VxAxis &g) {
+#pragma clang fp contract(off)
+    VxPts r;
+    const double R = oR.w;
+    r.live = false;
+    r.crossed = false;
+    r.b = r.cphi = r.sphi = 0.0;
+    for (int a = 0; a < 3; ++a) r.v0[a] = r.v1[a] = 0.0;
+    const double b = sqrt(g.b2);
+    if (b > 1e-12 * (sqrt(g.ww) + R)) {  // c_k off the axis: isolated points
+        const double cphi = g.num / (2.0 * R * b);
+        if (cphi >= -1.0 && cphi <= 1.0) {
+            r.live = true;
+            r.crossed = cphi > -1.0 && cphi < 1.0;
+            const double sphi = sqrt(fmax(0.0, 1.0 - cphi * cphi));
+            const double ex = g.px / b, ey = g.py / b, ez = g.pz / b;
+            const double fx = n.y * ez - n.z * ey, fy = n.z * ex - n.x * ez,
+                         fz = n.x * ey - n.y * ex;
+            r.v0[0] = oR.x + R * (cphi * ex + sphi * fx);
+            r.v0[1] = oR.y + R * (cphi * ey + sphi * fy);
+            r.v0[2] = oR.z + R * (cphi * ez + sphi * fz);
+            r.v1[0] = oR.x + R * (cphi * ex - sphi * fx);
+            r.v1[1] = oR.y + R * (cphi * ey - sphi * fy);
+            r.v1[2] = oR.z + R * (cphi * ez - sphi * fz);
+            r.b = b;
+            r.cphi = cphi;
+            r.sphi = sphi;
+        }
+    }
+    return r;
+}
+
+// A bound on the rounding error of the two positions (first order, safety
+// 4), propagated from the circle's bound n.w = e: w = c_k - o within e +
+// u|w|, its axial part t within 3 (e + 7u|w|), the in-plane part within
+// those plus 6u|t|, so its length b and direction e' = w_perp / b within
+// that over b; cos(phi) = (|w|^2 + R^2 - s_k^2) / (2 R b) within the
 // numerator's error (2|w| e + 2R e + 4u (|w|^2 + R^2 + s_k^2)) over 2 R b plus
 // |cos(phi)| (e / R + db / b + 2u), sin(phi) within min(sqrt(2 dc), |cos| dc /
 // sin); the position o + R (cos e' + sin f) adds R times the errors of the
 // unit vectors and of the two factors.
-__device__ inline void vertex_pair(const Mol &m, bool act, double4 oR, double4 n, int j, int k,
-                                   double4 ak, const VxLds &L, int nb, int ne, int nst,
-                                   bool &crossed, double *v0, double *v1, bool &ok0,
-                                   bool &ok1, double &eps) {
-    const double R = oR.w;
-    bool live = false;
-    crossed = false;
-    eps = 0.0;
-    for (int a = 0; a < 3; ++a) v0[a] = v1[a] = 0.0;
-    if (act) {
-        double sk = ak.w + m.rho;
-        double wx = ak.x - oR.x, wy = ak.y - oR.y, wz = ak.z - oR.z;
-        double t = wx * n.x + wy * n.y + wz * n.z;
-        double px = wx - t * n.x, py = wy - t * n.y, pz = wz - t * n.z;
-        double b = sqrt(px * px + py * py + pz * pz);
-        double ww = wx * wx + wy * wy + wz * wz;
-        if (b > 1e-12 * (sqrt(ww) + R)) {  // c_k off the axis: isolated points
-            double cphi = (ww + R * R - sk * sk) / (2.0 * R * b);
-            if (cphi >= -1.0 && cphi <= 1.0) {
-                live = true;
-                crossed = cphi > -1.0 && cphi < 1.0;
-                double sphi = sqrt(fmax(0.0, 1.0 - cphi * cphi));
-                double ex = px / b, ey = py / b, ez = pz / b;
-                double fx = n.y * ez - n.z * ey, fy = n.z * ex - n.x * ez, fz = n.x * ey - n.y * ex;
-                v0[0] = oR.x + R * (cphi * ex + sphi * fx);
-                v0[1] = oR.y + R * (cphi * ey + sphi * fy);
-                v0[2] = oR.z + R * (cphi * ez + sphi * fz);
-                v1[0] = oR.x + R * (cphi * ex - sphi * fx);
-                v1[1] = oR.y + R * (cphi * ey - sphi * fy);
-                v1[2] = oR.z + R * (cphi * ez - sphi * fz);
-                const double ec = n.w, wl = sqrt(ww), at = fabs(t);
-                const double dw = ec + U64 * wl;
-                const double dp = dw + 3.0 * (dw + 7.0 * U64 * wl) + 6.0 * U64 * at;
-                const double de = 2.0 * dp / b + 4.0 * U64;
-                const double df = 2.0 * (de + 6.0 * U64);
-                const double dc =
-                    (2.0 * wl * dw + 2.0 * R * ec + 4.0 * U64 * (ww + R * R + sk * sk)) /
-                        (2.0 * R * b) +
-                    fabs(cphi) * (ec / R + dp / b + 2.0 * U64);
-                const double ds =
-                    (sphi > 0.0 ? fmin(sqrt(2.0 * dc), fabs(cphi) * dc / sphi) : sqrt(2.0 * dc)) +
-                    U64;
-                const double cm = fmax(fabs(oR.x), fmax(fabs(oR.y), fabs(oR.z)));
-                eps = 4.0 * (ec + ec + R * (dc + ds + de + df) + 4.0 * U64 * (cm + R));
-            }
-        }
-    }
-    ok0 = live;
-    ok1 = live;
-    for (int q2 = 0; q2 < ne - nb; ++q2) {
+__device__ inline double vertex_eps(double4 oR, double4 n, const VxAxis &g, const VxPts &r) {
+    const double R = oR.w, b = r.b, cphi = r.cphi, sphi = r.sphi;
+    const double ec = n.w, wl = sqrt(g.ww), at = fabs(g.t);
+    const double dw = ec + U64 * wl;
+    const double dp = dw + 3.0 * (dw + 7.0 * U64 * wl) + 6.0 * U64 * at;
+    const double de = 2.0 * dp / b + 4.0 * U64;
+    const double df = 2.0 * (de + 6.0 * U64);
+    const double dc = (2.0 * wl * dw + 2.0 * R * ec + 4.0 * U64 * (g.ww + R * R + g.sk * g.sk)) /
+                          (2.0 * R * b) +
+                      fabs(cphi) * (ec / R + dp / b + 2.0 * U64);
+    const double ds =
+        (sphi > 0.0 ? fmin(sqrt(2.0 * dc), fabs(cphi) * dc / sphi) : sqrt(2.0 * dc)) + U64;
+    const double cm = fmax(fabs(oR.x), fmax(fabs(oR.y), fabs(oR.z)));
+    return 4.0 * (ec + ec + R * (dc + ds + de + df) + 4.0 * U64 * (cm + R));
+}
+
+// Exposure of the points v0 (while ok0) and v1 (while ok1) against i's
+// neighbours at cover positions [q0, q1) (0..nst-1 from LDS, the rest from
+// global memory), j and k skipped.  The loop is uniform across the wavefront
+// and ends when no lane has a live point left.
+__device__ inline void vertex_expose(const Mol &m, const VxLds &L, int nb, int nst, int q0, int q1,
+                                     int j, int k, const double *v0, const double *v1, bool &ok0,
+                                     bool &ok1) {
+#pragma clang fp contract(off)
+    for (int q2 = q0; q2 < q1; ++q2) {
         if (!__any(ok0 || ok1)) break;
         int l;
         double4 al;
@@ -721,6 +762,34 @@ __device__ inline void vertex_pair(const Mol &m, bool act, double4 oR, double4 n
         ok0 = ok0 && !(d0 < al.w);
         ok1 = ok1 && !(d1 < al.w);
     }
+}
+
+
+// The two points of circle (o, R, n) at distance s_k from c_k and whether
+// each is exposed: in no other neighbour's open SAS ball.  `eps` (their
+// error bound) only when `want_eps`.
+__device__ inline void vertex_pair(const Mol &m, bool act, double4 oR, double4 n, int j, int k,
+                                   double4 ak, const VxLds &L, int nb, int ne, int nst,
+                                   bool want_eps, bool &crossed, double *v0, double *v1, bool &ok0,
+                                   bool &ok1, double &eps) {
+    VxPts r;
+    VxAxis g;
+    if (act) {
+        g = vx_axis(m, oR, n, ak);
+        r = vertex_points(oR, n, g);
+    } else {
+        r.live = r.crossed = false;
+        for (int a = 0; a < 3; ++a) r.v0[a] = r.v1[a] = 0.0;
+    }
+    crossed = r.crossed;
+    for (int a = 0; a < 3; ++a) {
+        v0[a] = r.v0[a];
+        v1[a] = r.v1[a];
+    }
+    ok0 = r.live;
+    ok1 = r.live;
+    vertex_expose(m, L, nb, nst, 0, ne - nb, j, k, v0, v1, ok0, ok1);
+    eps = (want_eps && (ok0 || ok1)) ? vertex_eps(oR, n, g, r) : 0.0;
 }
 
 template <bool FILL>
@@ -751,7 +820,8 @@ __device__ void vertex_circle(const Mol &m, int c, int c0, int i, int nb, int ne
                                : make_double4(0.0, 0.0, 0.0, 0.0);
         bool crossed, ok0, ok1;
         double v0[3], v1[3], veps;
-        vertex_pair(m, act, oR, n, j, k, ak, L, nb, ne, nst, crossed, v0, v1, ok0, ok1, veps);
+        vertex_pair(m, act, oR, n, j, k, ak, L, nb, ne, nst, FILL, crossed, v0, v1, ok0, ok1,
+                    veps);
         const double v0x = v0[0], v0y = v0[1], v0z = v0[2], v1x = v1[0], v1y = v1[1], v1z = v1[2];
         unsigned long long b0 = __ballot(ok0), b1 = __ballot(ok1);
         if (FILL) {
@@ -812,6 +882,39 @@ __device__ void vertex_circle(const Mol &m, int c, int c0, int i, int nb, int ne
     }
 }
 
+// Pair t of the flattened (circle, k) list of the count pass: circle cc (its
+// partner at ascending position pj[cc]) and k's ascending position p.
+__device__ inline void vx_pair_of(int t, int ncl, const int *poff, const int *pj, int &cc, int &p) {
+    int lo = 0, hi = ncl;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (poff[mid + 1] <= t) lo = mid + 1;
+        else hi = mid;
+    }
+    cc = lo;
+    p = pj[cc] + 1 + (t - poff[cc]);
+}
+
+// Flags f on the three circles of triple (i, j, k): (i, j) and (i, k) are
+// i's own circles (flags gathered in LDS), (j, k) is looked up globally.
+__device__ inline void vx_flag_pair(const Mol &m, const VxLds &L, int ncl, uint32_t *fl, int cc,
+                                    int j, int k, uint32_t f) {
+    atomicOr(&fl[cc], f);
+    int a = 0, b = ncl - 1;
+    while (a <= b) {
+        int mid = (a + b) >> 1;
+        int v = L.cj[mid];
+        if (v == k) {
+            atomicOr(&fl[mid], f);
+            break;
+        }
+        if (v < k) a = mid + 1;
+        else b = mid - 1;
+    }
+    const int cjk = find_circle(m, j, k);
+    if (cjk >= 0) atomicOr(&m.cflag[cjk], f);
+}
+
 // One workgroup per atom i, one wavefront per circle (i, j) of i; i's
 // neighbours (cover order) are staged in LDS for the exposure tests.
 template <bool FILL>
@@ -819,6 +922,7 @@ __global__ void __launch_bounds__(VX_WAVES *WAVE) k_vertex(Seg sg) {
     __shared__ VxLds L;
     __shared__ int pj[VX_NBR], poff[VX_NBR + 1], vc[VX_NBR], scan_lds[VX_WAVES + 1];
     __shared__ uint32_t fl[VX_NBR];
+    __shared__ int qitem[2 * VX_WAVES * WAVE], qn;
     SEG_BEGIN(sg);
     int *vcnt = tmp.vcnt;
     const VertexPool &pool = tmp.pool;
@@ -871,60 +975,61 @@ __global__ void __launch_bounds__(VX_WAVES *WAVE) k_vertex(Seg sg) {
         if ((int)threadIdx.x < ncl) poff[threadIdx.x] = off;
         if (threadIdx.x == 0) poff[ncl] = total;
         __syncthreads();
+        // Two phases: a cheap test drops the pairs whose sphere certainly
+        // misses the circle (about two in three) and queues the rest in
+        // LDS; the queue, once it holds a workgroup's worth (or the pairs
+        // are done), gets the positions, the exposure tests and, for exposed
+        // points only, the error bound, with every lane busy.  A dropped pair
+        // has no point, so it flags nothing.
+        if (threadIdx.x == 0) qn = 0;
+        __syncthreads();
         for (int t0 = 0; t0 < total; t0 += VX_WAVES * WAVE) {
             const int t = t0 + (int)threadIdx.x;
-            const bool act = t < total;
-            int cc = 0, p = 0;
-            if (act) {
-                int lo = 0, hi = ncl;
-                while (lo < hi) {
-                    int mid = (lo + hi) >> 1;
-                    if (poff[mid + 1] <= t) lo = mid + 1;
-                    else hi = mid;
-                }
-                cc = lo;
-                p = pj[cc] + 1 + (t - poff[cc]);
+            if (t < total) {
+                int cc, p;
+                vx_pair_of(t, ncl, poff, pj, cc, p);
+                const VxAxis g = vx_axis(m, L.coR[cc], L.cn[cc], L.natasc[p]);
+                if (vx_maybe_live(g, L.coR[cc].w)) qitem[atomicAdd(&qn, 1)] = t;
             }
-            const int j = L.cj[cc], k = act ? L.nasc[p] : -1;
-            bool crossed, ok0, ok1;
-            double v0[3], v1[3], veps;
-            vertex_pair(m, act, L.coR[cc], L.cn[cc], j, k, L.natasc[p], L, nb, ne, nst, crossed,
-                        v0, v1, ok0, ok1, veps);
-            const int nx = act ? (ok0 ? 1 : 0) + (ok1 ? 1 : 0) : 0;
-            // the positions go to the pool (placed and ordered on their
-            // circle after the scan)
-            if (nx) {
-                const int w = atomicAdd(pool.count, nx), w1 = w + (ok0 ? 1 : 0);
-                if (ok0 && w < pool.cap) {
-                    pool.p[w] = make_double4(v0[0], v0[1], v0[2], veps);
-                    pool.id[w] = make_int4(c0 + cc, 0, k, 1);
-                }
-                if (ok1 && w1 < pool.cap) {
-                    pool.p[w1] = make_double4(v1[0], v1[1], v1[2], veps);
-                    pool.id[w1] = make_int4(c0 + cc, 0, k, -1);
-                }
-            }
-            if (!act) continue;
-            if (nx) atomicAdd(&vc[cc], nx);
-            const uint32_t f = (crossed ? CF_CROSSED : 0u) | (nx ? CF_EXPOSED_VERTEX : 0u);
-            if (f) {
-                atomicOr(&fl[cc], f);
-                // circle (i, k): one of i's circles, in LDS
-                int a = 0, b = ncl - 1;
-                while (a <= b) {
-                    int mid = (a + b) >> 1;
-                    int v = L.cj[mid];
-                    if (v == k) {
-                        atomicOr(&fl[mid], f);
-                        break;
+            __syncthreads();
+            const int nq = qn;
+            if (nq < VX_WAVES * WAVE && t0 + VX_WAVES * WAVE < total) continue;  // uniform
+            for (int q0 = 0; q0 < nq; q0 += VX_WAVES * WAVE) {
+                const int q = q0 + (int)threadIdx.x;
+                const bool act = q < nq;
+                int cc = 0, p = 0;
+                if (act) vx_pair_of(qitem[q], ncl, poff, pj, cc, p);
+                const int j = L.cj[cc], k = act ? L.nasc[p] : -1;
+                const double4 oR = L.coR[cc], n = L.cn[cc];
+                const VxAxis g = vx_axis(m, oR, n, L.natasc[p]);
+                VxPts r = vertex_points(oR, n, g);
+                bool ok0 = act && r.live, ok1 = ok0;
+                vertex_expose(m, L, nb, nst, 0, d, j, k, r.v0, r.v1, ok0, ok1);
+                if (!act) continue;
+                const int nx = (ok0 ? 1 : 0) + (ok1 ? 1 : 0);
+                // the positions go to the pool (placed and ordered on their
+                // circle after the scan)
+                if (nx) {
+                    const double veps = vertex_eps(oR, n, g, r);
+                    const int w = atomicAdd(pool.count, nx), w1 = w + (ok0 ? 1 : 0);
+                    if (ok0 && w < pool.cap) {
+                        pool.p[w] = make_double4(r.v0[0], r.v0[1], r.v0[2], veps);
+                        pool.id[w] = make_int4(c0 + cc, 0, k, 1);
                     }
-                    if (v < k) a = mid + 1;
-                    else b = mid - 1;
+                    if (ok1 && w1 < pool.cap) {
+                        pool.p[w1] = make_double4(r.v1[0], r.v1[1], r.v1[2], veps);
+                        pool.id[w1] = make_int4(c0 + cc, 0, k, -1);
+                    }
+                    atomicAdd(&vc[cc], nx);
+                    atomicOr(&m.aflag[k], AF_EXPOSED_VERTEX);
                 }
-                const int cjk = find_circle(m, j, k);
-                if (cjk >= 0) atomicOr(&m.cflag[cjk], f);
+                const uint32_t f =
+                    (r.crossed ? CF_CROSSED : 0u) | (nx ? CF_EXPOSED_VERTEX : 0u);
+                if (f) vx_flag_pair(m, L, ncl, fl, cc, j, k, f);
             }
-            if (nx) atomicOr(&m.aflag[k], AF_EXPOSED_VERTEX);
+            __syncthreads();
+            if (threadIdx.x == 0) qn = 0;
+            __syncthreads();
         }
         __syncthreads();
         if ((int)threadIdx.x < ncl) {
