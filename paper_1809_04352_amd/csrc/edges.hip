@@ -731,8 +731,6 @@ __device__ inline int tile_surface_key(const Mol &m, int t, int s) {
 constexpr int CH_EDGES = 64;
 constexpr int CH_THREADS = 256;
 constexpr int CH_SURF = 128;    // surfaces staged per pass
-constexpr int CH_PAIRS = 1024;  // queued (edge, surface) pairs per solve round
-constexpr int CH_ROUND = 512;   // reach tests between two reads of the queue length
 constexpr int CH_ROOTS = 512;   // admissible roots per chunk
 constexpr int CH_SLOTS = 4;     // roots of one quartic before the admissibility test
 constexpr int CH_ATOMS = 192;   // tile atoms staged for the labels
@@ -781,14 +779,15 @@ struct ChunkLds {
     int ecount[CH_EDGES + 1];
     int eoff[CH_EDGES + 1];
     int scan[CH_THREADS / WAVE + 1];
-    unsigned short pair[CH_PAIRS];
+    // per wavefront: queued (edge, surface) pairs, spheres [0] and tori [1]
+    unsigned short wq[CH_THREADS / WAVE][2][2 * WAVE];
     unsigned short perm[CH_ROOTS];
     unsigned char fe[CH_ROOTS];
     // per edge: the staged atoms and surfaces whose label test can hold
     // somewhere on the edge (bit masks over the staged arrays)
     unsigned long long amask[CH_EDGES][CH_ATOMS / 64];
     unsigned long long smask[CH_EDGES][CH_SURF / 64];
-    int npair_s, npair_t, nf, ovf, tile, fb_base, nq;
+    int nf, ovf, tile, fb_base, nq;
 };
 
 // The cut tests of staged surface s, on its planes in LDS or, where they did
@@ -1131,10 +1130,15 @@ __device__ inline bool cone_may_reject_f(float4 a, float ct, double4 v) {
 // every point of the edge (the ball of radius `half` around mid).  The
 // candidate's direction -- from the atom centre for a face, in the circle's
 // plane from its centre for a circle -- stays within angle theta of its value
-// at mid, sin theta = half / distance; a cut (v, tau) rejects the direction u
-// iff u . v > tau, so it rejects the whole cone iff |v| cos(phi + theta) > tau
-// with phi the angle between v and the axis (a small slack keeps the test
-// conservative under rounding).
+// at mid, sin theta = half / |a| (a the axis); a cut (v, tau) rejects the
+// direction u iff u . v > tau, so it rejects the whole cone iff the cone does
+// not reach the direction -v (phi + theta <= pi) and
+//   |v| cos(phi + theta) = (a . v cos theta - |a x v| sin theta) / |a| > tau,
+// phi the angle between v and a.  The test runs in FP32 on the rounded axis
+// and cut: each of a . v and |a x v| is then within 1e-6 |a| |v| of its exact
+// value and cos, sin theta within 1e-6, so the left side is within 1e-5 |v|;
+// that margin (beside the FP64 slack of the exact test) keeps the decision
+// conservative: a surface is declared dead only where the exact cone is.
 template <bool CNT>
 __device__ bool edge_cone_dead(const Mol &m, const ChunkLds &S, int si, int type,
                                const double *mid, double half, unsigned long long *cnt) {
@@ -1146,12 +1150,11 @@ __device__ bool edge_cone_dead(const Mol &m, const ChunkLds &S, int si, int type
         ay -= t * p.n.y;
         az -= t * p.n.z;
     }
-    const double L = sqrt(ax * ax + ay * ay + az * az);
-    if (!(L > 2.0 * half)) return false;  // the cone is too wide to decide
-    ax /= L;
-    ay /= L;
-    az /= L;
-    const double st = half / L, ct = sqrt(1.0 - st * st);
+    if (!(ax * ax + ay * ay + az * az > 4.0 * half * half)) return false;  // cone too wide
+    const float fx = (float)ax, fy = (float)ay, fz = (float)az;
+    const float L = sqrtf(fx * fx + fy * fy + fz * fz);
+    const float iL = 1.0f / L;
+    const float st = (float)half * iL, ct = sqrtf(1.0f - st * st);
     const int2 r = S.crange[si];
     const double4 *cuts = S.cut;
     int b = r.x, e = r.y;
@@ -1162,17 +1165,16 @@ __device__ bool edge_cone_dead(const Mol &m, const ChunkLds &S, int si, int type
     for (int c = b; c < e; ++c) {
         const double4 v = cuts[c];
         if (CNT) ++cnt[EC_CONE];
-        // u . v over the cone is at most its value on the axis: a cut that
-        // passes the axis direction rejects no direction of the cone
-        const double av = ax * v.x + ay * v.y + az * v.z;
-        if (!(av > v.w)) continue;
-        const double vn = sqrt(v.x * v.x + v.y * v.y + v.z * v.z);
-        if (!(vn > 0.0)) continue;
-        const double cp = av / vn;
-        if (cp <= -ct) continue;  // the cone holds the direction opposite to v
-        const double sp = sqrt(fmax(0.0, 1.0 - cp * cp));
-        const double mn = vn * (cp * ct - sp * st);  // min of u . v over the cone
-        if (mn > v.w + 1e-9 * (vn + fabs(v.w))) return true;
+        const float vx = (float)v.x, vy = (float)v.y, vz = (float)v.z, tau = (float)v.w;
+        const float av = fx * vx + fy * vy + fz * vz;
+        // u . v over the cone is at most its value on the axis
+        if (!(av * iL > tau)) continue;
+        const float vn = sqrtf(vx * vx + vy * vy + vz * vz);
+        if (!(av > (1e-4f - ct) * L * vn)) continue;  // the cone may reach -v
+        const float cx = fy * vz - fz * vy, cy = fz * vx - fx * vz, cz = fx * vy - fy * vx;
+        const float axv = sqrtf(cx * cx + cy * cy + cz * cz);
+        const float mn = (av * ct - axv * st) * iL;
+        if ((double)mn > v.w + 1e-9 * ((double)vn + fabs(v.w)) + 1e-5 * (double)vn) return true;
     }
     return false;
 }
@@ -1321,95 +1323,105 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
                 if (dm2 < sq(a.w + rho + half)) atomicOr(&S.amask[ei][ai >> 6], 1ull << (ai & 63));
             }
         }
-        // (edge, surface) pairs: reach tests, label masks, the solve queue
-        const int npairs = n * ns;
-        int pb = 0;
-        while (pb < npairs) {
-            if (tid == 0) {
-                S.npair_s = 0;
-                S.npair_t = 0;
-            }
-            __syncthreads();
-            // reach tests until the queue could not take another round (a
-            // round adds at most CH_ROUND pairs); the length is read between
-            // two barriers, so every thread takes the same decision
-            for (;;) {
-                for (int r = 0; r < CH_ROUND; r += CH_THREADS) {
-                    const int p = pb + r + tid;
-                    if (p >= npairs) break;
-                    int ei, si;
-                    split(p, si, ei);
-                    const int type = S.skey[si] >> 28;
-                    const double mid[3] = {S.mid[ei][0], S.mid[ei][1], S.mid[ei][2]};
-                    if (CNT) ++cnt[type == 2 ? EC_REACH_TORUS : EC_REACH_SPHERE];
-                    bool rel = false, hit = false;
-                    if (!S.sdead[si])
-                        hit = staged_reaches_rel(type, S.sp[si], rho, mid, half, &rel);
-                    // a circle whose candidate is inadmissible on the whole edge
-                    // has no kept root there and fails every label test
-                    if ((hit || rel) && type == 2 &&
+        // (edge, surface) pairs: wavefront w takes the staged surfaces s = w,
+        // w + 4, ... and lane e the chunk's edge e, so a surface is read once
+        // per wavefront (an LDS broadcast) and its type is uniform.  Pairs
+        // that reach go to the wavefront's queue of their kind (tori apart
+        // from spheres); a queue that holds a wavefront's worth is solved at
+        // once, one pair per lane, without waiting for the other wavefronts.
+        // Lane e gathers the label-mask bits of edge e.
+        {
+            const int wv = tid / WAVE, lane = tid % WAVE;
+            const bool eact = lane < n;
+            int nqs = 0, nqt = 0;  // queue lengths (uniform across the wavefront)
+            for (int s0 = 0;;) {
+                // a full queue is solved first; once every surface is
+                // tested, the partial queues; one call site keeps the
+                // solver inlined once
+                int which = -1, count = 0;
+                if (nqt >= WAVE) which = 1;
+                else if (nqs >= WAVE) which = 0;
+                else if (s0 >= ns) which = nqt ? 1 : nqs ? 0 : -1;
+                if (which >= 0) {
+                    count = which ? nqt : nqs;
+                    const int left = count > WAVE ? count - WAVE : 0;
+                    if (which) nqt = left;
+                    else nqs = left;
+                    // the pairs beyond the first WAVE move to the front
+                    unsigned short *qu = S.wq[wv][which];
+                    const unsigned short v = lane < count ? qu[lane] : (unsigned short)0;
+                    if (lane < left) qu[lane] = qu[WAVE + lane];
+                    if (lane < count) {
+                        const int ei = v & 63, si = v >> 6;
+                        const int skey = S.skey[si];
+                        const SurfParams sp = S.sp[si];
+                        const int axis = S.einfo[ei] & 3;
+                        const double xs[3] = {S.xs[ei][0], S.xs[ei][1], S.xs[ei][2]};
+                        const double e[3] = {axis == 0 ? 1.0 : 0.0, axis == 1 ? 1.0 : 0.0,
+                                             axis == 2 ? 1.0 : 0.0};
+                        int nr = 0;
+                        surface_roots<CNT>(
+                            skey >> 28, sp, h, rho, e, xs,
+                            [&](double u) {
+                                if (nr < CH_SLOTS) S.slot[nr][tid] = u;
+                                ++nr;
+                            },
+                            cnt);
+                        if (nr > CH_SLOTS) {
+                            S.ovf = 1;
+                            nr = CH_SLOTS;
+                        }
+                        auto pass = [&](double px, double py, double pz, double sc) {
+                            return staged_cuts_pass<CNT>(m, S, si, px, py, pz, sc,
+                                                         CNT ? cnt + EC_CUT : nullptr);
+                        };
+                        for (int r = 0; r < nr; ++r) {
+                            const double u = S.slot[r][tid];
+                            if (root_admissible(m, skey, sp, pass, u, e, xs)) {
+                                const int pos = atomicAdd(&S.nf, 1);
+                                if (pos < CH_ROOTS) {
+                                    S.fu[pos] = u;
+                                    S.fk[pos] = skey;
+                                    S.fe[pos] = (unsigned char)ei;
+                                }
+                            }
+                        }
+                    }
+                    continue;
+                }
+                if (s0 >= ns) break;
+                const int si = s0 + wv;
+                s0 += CH_THREADS / WAVE;
+                if (si >= ns) continue;  // this wavefront's surfaces are done
+                const int type = S.skey[si] >> 28;
+                if (CNT && eact) ++cnt[type == 2 ? EC_REACH_TORUS : EC_REACH_SPHERE];
+                if (S.sdead[si]) continue;
+                bool rel = false, hit = false;
+                if (eact) {
+                    const double mid[3] = {S.mid[lane][0], S.mid[lane][1], S.mid[lane][2]};
+                    hit = staged_reaches_rel(type, S.sp[si], rho, mid, half, &rel);
+                    // a circle whose candidate is inadmissible on the whole
+                    // edge has no kept root there and fails every label test
+                    if (type == 2 && (hit || rel) &&
                         edge_cone_dead<CNT>(m, S, si, type, mid, half, cnt)) {
                         hit = false;
                         rel = false;
                     }
-                    if (hit) {
-                        unsigned short v = (unsigned short)(ei | (si << 6));
-                        if (type == 2) S.pair[CH_PAIRS - 1 - atomicAdd(&S.npair_t, 1)] = v;
-                        else S.pair[atomicAdd(&S.npair_s, 1)] = v;
-                    }
-                    if (rel) atomicOr(&S.smask[ei][si >> 6], 1ull << (si & 63));
                 }
-                pb += CH_ROUND;
-                __syncthreads();
-                const int queued = S.npair_s + S.npair_t;
-                __syncthreads();
-                if (pb >= npairs || queued + CH_ROUND > CH_PAIRS) break;
-            }
-            // one thread per queued pair: tori first, then spheres, so that
-            // the costly quartics fill the first waves and few waves mix the
-            // two kinds
-            const int nt = S.npair_t, nq = nt + S.npair_s;
-            for (int j0 = 0; j0 < nq; j0 += CH_THREADS) {
-                const int j = j0 + tid;
-                if (j >= nq) continue;
-                unsigned short v = j < nt ? S.pair[CH_PAIRS - 1 - j] : S.pair[j - nt];
-                const int ei = v & 63, si = v >> 6;
-                const int skey = S.skey[si];
-                const SurfParams sp = S.sp[si];
-                const int axis = S.einfo[ei] & 3;
-                const double xs[3] = {S.xs[ei][0], S.xs[ei][1], S.xs[ei][2]};
-                const double e[3] = {axis == 0 ? 1.0 : 0.0, axis == 1 ? 1.0 : 0.0,
-                                     axis == 2 ? 1.0 : 0.0};
-                int nr = 0;
-                surface_roots<CNT>(
-                    skey >> 28, sp, h, rho, e, xs,
-                    [&](double u) {
-                        if (nr < CH_SLOTS) S.slot[nr][tid] = u;
-                        ++nr;
-                    },
-                    cnt);
-                if (nr > CH_SLOTS) {
-                    S.ovf = 1;
-                    nr = CH_SLOTS;
-                }
-                auto pass = [&](double px, double py, double pz, double sc) {
-                    return staged_cuts_pass<CNT>(m, S, si, px, py, pz, sc,
-                                                 CNT ? cnt + EC_CUT : nullptr);
-                };
-                for (int r = 0; r < nr; ++r) {
-                    double u = S.slot[r][tid];
-                    if (root_admissible(m, skey, sp, pass, u, e, xs)) {
-                        int pos = atomicAdd(&S.nf, 1);
-                        if (pos < CH_ROOTS) {
-                            S.fu[pos] = u;
-                            S.fk[pos] = skey;
-                            S.fe[pos] = (unsigned char)ei;
-                        }
-                    }
+                if (rel) atomicOr(&S.smask[lane][si >> 6], 1ull << (si & 63));
+                const unsigned long long hb = __ballot(hit);
+                if (!hb) continue;
+                const int pos = __popcll(hb & ((1ull << lane) - 1ull));
+                if (type == 2) {
+                    if (hit) S.wq[wv][1][nqt + pos] = (unsigned short)(lane | (si << 6));
+                    nqt += __popcll(hb);
+                } else {
+                    if (hit) S.wq[wv][0][nqs + pos] = (unsigned short)(lane | (si << 6));
+                    nqs += __popcll(hb);
                 }
             }
-            __syncthreads();
         }
+        __syncthreads();
     }
     // too many roots for the chunk's lists: its edges go to the wavefront kernel
     if (S.ovf || S.nf > CH_ROOTS || m.edge_fallback) {
