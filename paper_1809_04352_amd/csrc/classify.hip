@@ -158,7 +158,12 @@ __device__ inline bool cuts_pass(const double4 *cuts, int b, int e, double dx, d
 
 // Case 3 of one queued point against the staged lists (global beyond them),
 // every comparison certified: 0 (an admissible candidate certainly within
-// rho), 1 (certainly none), 2 (undecided in FP64).
+// rho), 1 (certainly none), 2 (undecided in FP64).  FAST (the FP32-based
+// mode): the square roots come from FP32 roots refined by a Newton step
+// (sqrt_fast, within 2^-42 relative).  For a face that adds at most
+// 2^-42 d |tau| <= 3 2^-42 d s_max^2 / rho to the cut margins' error, about
+// 1/50 of the gf bound; tv_circle widens its own bounds.
+template <bool FAST>
 __device__ inline int shell_cert_staged(const Mol &m, const ClsShared &sh, const CertK &K,
                                         int tile, int nV, int nF, int nC, double x, double y,
                                         double z) {
@@ -181,7 +186,7 @@ __device__ inline int shell_cert_staged(const Mol &m, const ClsShared &sh, const
         double d2 = dx * dx + dy * dy + dz * dz;
         const int w = tv_neg(d2 - a.w, K.fw_band);
         if (w == TV_NO) continue;
-        double d = sqrt(d2);
+        const double d = sqrt_sel<FAST>(d2);
         int2 r = sh.p2.fr[q];
         const int c = r.x >= 0 ? tv_face_cuts(sh.p2.cut, r.x, r.x + r.y, dx, dy, dz, d, K.gf)
                                : tv_face_cuts(m.face_cut, m.face_cut_off[r.y],
@@ -198,7 +203,7 @@ __device__ inline int shell_cert_staged(const Mol &m, const ClsShared &sh, const
         const int w = tv_neg(d2 - sq(a.w + 2.0 * rho), K.fw_band);
         if (w == TV_NO) continue;
         const int c = tv_face_cuts(m.face_cut, m.face_cut_off[f], m.face_cut_off[f + 1], dx, dy,
-                                   dz, sqrt(d2), K.gf);
+                                   dz, sqrt_sel<FAST>(d2), K.gf);
         if (c == TV_NO) continue;
         if (w == TV_YES && c == TV_YES) return 0;
         unsure = true;
@@ -221,12 +226,13 @@ __device__ inline int shell_cert_staged(const Mol &m, const ClsShared &sh, const
         }
         int t;
         if (r.x >= 0) {
-            t = tv_circle(x, y, z, oR, n, cq, rho2, r.y,
-                          [&](int c) { return sh.p2.cut[r.x + c]; });
+            auto at = [&](int c) { return sh.p2.cut[r.x + c]; };
+            t = tv_circle<decltype(at), FAST>(x, y, z, oR, n, cq, rho2, r.y, at);
         } else {
             const int cb = m.ec_cut_off[r.y];
-            t = tv_circle(x, y, z, oR, n, cq, rho2, m.ec_cut_off[r.y + 1] - cb,
-                          [&](int c) { return m.ec_cut[cb + c]; });
+            auto at = [&](int c) { return m.ec_cut[cb + c]; };
+            t = tv_circle<decltype(at), FAST>(x, y, z, oR, n, cq, rho2,
+                                              m.ec_cut_off[r.y + 1] - cb, at);
         }
         if (t == TV_YES) return 0;
         unsure |= t == TV_UNSURE;
@@ -236,7 +242,8 @@ __device__ inline int shell_cert_staged(const Mol &m, const ClsShared &sh, const
 
 // F32: phase 1 (cases 1 and 2, every point against the tile's atoms) in FP32
 // with the certified thresholds above; points it cannot certify are
-// re-labelled in FP64 (counted in diag[1]).  Case 3 runs in FP64 either way.
+// re-labelled in FP64 (counted in diag[1]).  Case 3 runs in FP64 either way,
+// with the square roots of its tests from FP32 roots and one Newton step.
 template <bool F32>
 __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared &sh) {
     const int T = m.tile;
@@ -492,7 +499,7 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
     for (int q = threadIdx.x; q < nq; q += CLS_THREADS) {
         int p = sh.queue[q];
         int i = t3[0] * T + p % T, j = t3[1] * T + (p / T) % T, k = t3[2] * T + p / (T * T);
-        const int lab = shell_cert_staged(m, sh, K, tile, nV, nF, nC, grid_coord(m.lo[0], m.h, i),
+        const int lab = shell_cert_staged<F32>(m, sh, K, tile, nV, nF, nC, grid_coord(m.lo[0], m.h, i),
                                           grid_coord(m.lo[1], m.h, j), grid_coord(m.lo[2], m.h, k));
         const long long gi =
             (long long)i + (long long)m.dims[0] * ((long long)j + (long long)m.dims[1] * k);

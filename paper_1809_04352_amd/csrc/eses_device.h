@@ -345,6 +345,30 @@ __device__ inline int tv_face_cuts(const double4 *cuts, int b, int e, double dx,
     return unsure ? TV_UNSURE : TV_YES;
 }
 
+// Square root for the FP32-based classification: the FP32 root s of x
+// (within 2^-21.5 relative, the conversion of x included) refined by one
+// Newton step y = s + (x - s^2) h, h = 1 / 2s from the FP32 reciprocal
+// (within 2^-22).  s^2 is exact in FP64, the step leaves alpha^2 / 2 of the
+// FP32 error alpha and the approximate h adds |alpha| 2^-22: y is within
+// 2^-42 of sqrt(x), relative (below 1e-30, where the FP32 root underflows,
+// the FP64 root is taken).
+constexpr double FAST_SQRT_REL = 2.2737367544323206e-13;  // 2^-42
+
+__device__ inline double sqrt_fast(double x) {
+    if (!(x >= 1e-30)) return sqrt(fmax(x, 0.0));
+    const float s = __builtin_amdgcn_sqrtf((float)x);
+    const double sd = (double)s;
+    return sd + (x - sd * sd) * (0.5 * (double)__builtin_amdgcn_rcpf(s));
+}
+
+// Square root with a relative error bound: exact rounding (FP64) or within
+// FAST_SQRT_REL (FAST).
+template <bool FAST>
+__device__ inline double sqrt_sel(double x) {
+    if (FAST) return sqrt_fast(x);
+    return sqrt(x);
+}
+
 // Per-circle constants of the cut test: the circle's bound e; with
 // U = R + s_max (|o - c_k| <= R + s_k for a listed cut), Tmax = (R^2 + U^2 +
 // s_max^2) / 2R >= |T_k|, the cut vector within du = e + 8u U and T_k within
@@ -368,17 +392,27 @@ __device__ inline double4 circle_cut_consts(double R, double e, double smax) {
 // the in-plane vector within dwp = 2 e + 16u (b + |t|).  Each cut
 // w_perp . u_k <= b T_k is within b ac + bc dwp + tmax db.  Near the axis
 // (b <= 4 dwp) the nearest point's direction is not determined.
-template <class CutAt>
+// FAST: b from sqrt_fast, its extra error FAST_SQRT_REL b added to db, and db
+// itself from FP32 operations rounded up by a factor 1 + 2^-18.
+template <class CutAt, bool FAST = false>
 __device__ inline int tv_circle(double x, double y, double z, double4 oR, double4 n, double4 cq,
                                 double rho2, int ncut, CutAt cut_at) {
     const double wx = x - oR.x, wy = y - oR.y, wz = z - oR.z;
     const double t = wx * n.x + wy * n.y + wz * n.z;
     const double ww = wx * wx + wy * wy + wz * wz;
-    const double b = sqrt(fmax(ww - t * t, 0.0));
+    const double b = sqrt_sel<FAST>(fmax(ww - t * t, 0.0));
     const double R = oR.w, e = cq.x;
     const double at = fabs(t), wl = b + at;
     const double db2 = 8.0 * U64 * ww + 4.0 * wl * e;
-    const double db = b > 0.0 ? fmin(sqrt(db2), db2 / (2.0 * b)) : sqrt(db2);
+    double db;
+    if (FAST) {
+        const float f2 = (float)db2, fb = (float)b;
+        const float r = __builtin_amdgcn_sqrtf(f2);
+        const float q = b > 0.0 ? fminf(r, f2 * 0.5f * __builtin_amdgcn_rcpf(fb)) : r;
+        db = (double)q * (1.0 + 3.814697265625e-06) + FAST_SQRT_REL * b;
+    } else {
+        db = b > 0.0 ? fmin(sqrt(db2), db2 / (2.0 * b)) : sqrt(db2);
+    }
     const double mg = ww + R * R - rho2 - 2.0 * b * R;
     const double err = 8.0 * (wl + R) * (e + 8.0 * U64 * wl) + 2.0 * R * db +
                        CERT_BAND * (ww + R * R + rho2 + 2.0 * b * R);
