@@ -27,6 +27,12 @@ constexpr int CLS_WAVES = CLS_THREADS / WAVE;
 constexpr int CLS_ATOMS = 256;
 constexpr int CLS_MAXPTS = 512;  // points per tile (8^3)
 constexpr int CAP_V = 48, CAP_F = 48, CAP_C = 48, CAP_CUT = 256;
+// Six waves per SIMD (80 VGPRs, a few spilled; 24 KB of LDS per workgroup):
+// the kernel waits mostly on dependent loads, and on the batch the extra
+// resident workgroups outweigh the spills (28.6 vs 33.3 ms at four waves;
+// seven and eight waves, with more spills and smaller cut pools, 29.9 and
+// 30.1 ms).
+constexpr int CLS_WAVES_PER_EU = 6;
 
 struct ClsPhase1 {
     double4 a[CLS_ATOMS];  // FP64: x, y, z, r^2
@@ -509,7 +515,8 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
 }
 
 template <bool F32>
-__global__ void __launch_bounds__(CLS_THREADS) k_classify(Mol m, uint8_t *labels, int nblocks) {
+__global__ void __launch_bounds__(CLS_THREADS) __attribute__((amdgpu_waves_per_eu(CLS_WAVES_PER_EU)))
+    k_classify(Mol m, uint8_t *labels, int nblocks) {
     __shared__ ClsShared sh;
     const int tile = xcd_tile(blockIdx.x, nblocks, m.ntiles);
     if (tile < 0) return;  // uniform across the workgroup
@@ -521,7 +528,8 @@ __global__ void __launch_bounds__(CLS_THREADS) k_classify(Mol m, uint8_t *labels
 // reaches that exit).  Units are ordered heaviest first (tiles with
 // candidate features, then tiles with atoms, then empty tiles).
 template <bool F32>
-__global__ void __launch_bounds__(CLS_THREADS) k_classify_batch(const Mol *mols,
+__global__ void __launch_bounds__(CLS_THREADS) __attribute__((amdgpu_waves_per_eu(CLS_WAVES_PER_EU)))
+    k_classify_batch(const Mol *mols,
                                                                uint8_t *const *labels,
                                                                const int2 *units, int nunits,
                                                                int *head) {
