@@ -279,6 +279,27 @@ eses_status eses_mesh(eses_candidates *c, const uint8_t *const *labels,
 eses_status eses_fill_cavities(eses_candidates *c, uint8_t *const *labels, int64_t *n_filled,
                                void *stream);
 
+/* Out-of-core form (the paper's block decomposition, sections 2.3-2.5 and
+ * Alg. 1, in z-slabs): stages 2 and 3 of a handle of ONE molecule with the
+ * grid's labels and records held in HOST memory and device memory bounded by
+ * the candidates plus two slabs.  The grid is cut into slabs of slab_planes
+ * z-planes (a positive multiple of the tile edge, 8 by default; the last slab
+ * may be shorter).  Each slab is classified (with exact arbitration) and its
+ * crossing edges solved on the GPU -- one extra plane is labelled so that the
+ * z-edges leaving the slab's last plane are found -- and its own planes'
+ * labels and the records of its points are copied to the host on a second
+ * stream while the next slab runs.  Results are those of eses_classify and
+ * eses_edge_intersections on the whole grid, bit for bit.
+ * labels_host: HOST [nz][ny][nx] uint8 (pinned memory lets the copies
+ * overlap the work); out_host: descriptor of HOST arrays (records appended in
+ * key order); *count (host) receives the number of crossing edges (records
+ * beyond out_host->capacity are dropped with ESES_ECAPACITY).  ESES_EINVAL
+ * for a handle of several molecules or a slab size that is not a positive
+ * multiple of the tile edge.  Synchronises `stream`. */
+eses_status eses_stream_slabs(eses_candidates *c, eses_precision prec, int32_t slab_planes,
+                              uint8_t *labels_host, const eses_isect_soa *out_host,
+                              int64_t *count, void *stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, hosts that forbid hipMalloc): stage 3 of a
  * handle of ONE molecule, as eses_edge_intersections, with every temporary of

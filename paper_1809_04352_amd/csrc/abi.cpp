@@ -1143,7 +1143,7 @@ eses_status arbitrate(eses_candidates *c, bool fp32, uint8_t *const *labels, hip
             const long long g = idx[(size_t)k];
             const double x[3] = {host_grid_coord(m.lo[0], m.h, g % nx),
                                  host_grid_coord(m.lo[1], m.h, (g / nx) % ny),
-                                 host_grid_coord(m.lo[2], m.h, g / (nx * ny))};
+                                 host_grid_coord(m.lo[2], m.h, g / (nx * ny) + m.kz0)};
             val[(size_t)k] = (uint8_t)S->exact->label(x);
         }
         Arena T;
@@ -1764,6 +1764,196 @@ eses_status eses_edge_intersections_noalloc(eses_candidates *c, const uint8_t *l
         return ESES_ECAPACITY;
     }
     return ESES_OK;
+}
+
+// Out-of-core form: the grid in z-slabs of P planes (P a multiple of the tile
+// edge).  A slab view of the molecule is the same candidate set with the
+// grid cut to planes [k0, k1) plus one more (the z-edges of plane k1 - 1 end
+// there), its tile lists starting at the slab's first tile layer and kz0 = k0,
+// so that its points keep their coordinates.  Each slab is classified (with
+// exact arbitration) and solved into one of two device buffers on `st`; its
+// own planes' labels and its records below plane k1 - k0 (keys moved to the
+// whole grid's numbering) are copied to the caller's host arrays on a second
+// stream, overlapping the next slab's work.
+eses_status eses_stream_slabs(eses_candidates *c, eses_precision prec, int32_t slab_planes,
+                              uint8_t *labels_host, const eses_isect_soa *out_host,
+                              int64_t *count, void *stream) {
+    g_err.clear();
+    if (!c || !labels_host || !out_host || !count) {
+        set_err("bad argument");
+        return ESES_EINVAL;
+    }
+    if (c->mols.size() != 1) {
+        set_err("the slab form takes a handle of one molecule");
+        return ESES_EINVAL;
+    }
+    if (prec != ESES_FP64 && prec != ESES_FP32_RECHECK) {
+        set_err("unknown precision");
+        return ESES_EINVAL;
+    }
+    const eses_isect_soa &oh = *out_host;
+    if (oh.capacity < 0 || (oh.capacity > 0 && (!oh.key || !oh.lambda || !oh.normal ||
+                                               !oh.patch_type || !oh.atoms))) {
+        set_err("bad output descriptor");
+        return ESES_EINVAL;
+    }
+    MolState *S = c->mols[0];
+    const Mol M = S->m;
+    const int T = M.tile;
+    if (slab_planes < T || slab_planes % T != 0) {
+        set_err("slab_planes must be a positive multiple of the tile edge (%d)", T);
+        return ESES_EINVAL;
+    }
+    const bool fp32 = prec == ESES_FP32_RECHECK;
+    hipStream_t st = (hipStream_t)stream;
+    const long long nx = M.dims[0], ny = M.dims[1], nz = M.dims[2], plane = nx * ny;
+    const long long P = std::min<long long>(slab_planes, nz);
+    // restores the handle's own view (and keeps a grown uncertain-point queue)
+    struct ViewGuard {
+        MolState *S;
+        Mol M;
+        ~ViewGuard() {
+            M.unc_idx = S->m.unc_idx;
+            M.unc_cap = S->m.unc_cap;
+            S->m = M;
+        }
+    } guard{S, M};
+    Arena A;
+    A.st = st;
+    hipStream_t cs = nullptr;
+    hipEvent_t ready = nullptr, copied[2] = {nullptr, nullptr};
+    auto cleanup = [&]() {
+        if (cs) {
+            (void)hipStreamSynchronize(cs);
+            (void)hipStreamDestroy(cs);
+        }
+        if (ready) (void)hipEventDestroy(ready);
+        for (hipEvent_t &e : copied)
+            if (e) (void)hipEventDestroy(e);
+        A.release();
+    };
+    eses_status res = ESES_OK;
+    auto fail = [&](eses_status s) {
+        res = s;
+        cleanup();
+        return s;
+    };
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ready, hipEventDisableTiming);
+    for (hipEvent_t &ev : copied)
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        set_err("slab streams: %s", hipGetErrorString(e));
+        return fail(ESES_EDEVICE);
+    }
+    uint8_t *lab[2];
+    long long *nown_dev;
+    eses_status s;
+    if ((s = A.alloc(&lab[0], plane * (P + 1))) != ESES_OK ||
+        (s = A.alloc(&lab[1], plane * (P + 1))) != ESES_OK || (s = A.alloc(&nown_dev, 1)) != ESES_OK)
+        return fail(s);
+    eses_isect_soa od[2] = {};
+    auto grow = [&](eses_isect_soa &o, long long cap) -> eses_status {
+        eses_status r;
+        if ((r = A.alloc(&o.key, cap)) != ESES_OK || (r = A.alloc(&o.lambda, cap)) != ESES_OK ||
+            (r = A.alloc(&o.normal, 3 * cap)) != ESES_OK ||
+            (r = A.alloc(&o.patch_type, cap)) != ESES_OK || (r = A.alloc(&o.atoms, 3 * cap)) != ESES_OK)
+            return r;
+        o.capacity = cap;
+        return ESES_OK;
+    };
+    long long pos = 0;
+    for (long long k0 = 0, si = 0; k0 < nz; k0 += P, ++si) {
+        const int b = (int)(si & 1);
+        const long long k1 = std::min(nz, k0 + P);
+        // buffer b is free once the copies of slab si - 2 are done
+        if (si >= 2 && hipStreamWaitEvent(st, copied[b], 0) != hipSuccess) {
+            set_err("slab streams: wait failed");
+            return fail(ESES_EDEVICE);
+        }
+        Mol V = M;
+        V.unc_idx = S->m.unc_idx;
+        V.unc_cap = S->m.unc_cap;
+        V.kz0 = M.kz0 + (int)k0;
+        V.dims[2] = (int)(k1 - k0 + (k1 < nz ? 1 : 0));
+        V.npts = plane * V.dims[2];
+        const long long tz0 = k0 / T;
+        V.tdims[2] = (V.dims[2] + T - 1) / T;
+        V.ntiles = V.tdims[0] * V.tdims[1] * V.tdims[2];
+        const long long t0 = tz0 * (long long)M.tdims[0] * M.tdims[1];
+        V.tA_off = M.tA_off + t0;
+        V.tF_off = M.tF_off + t0;
+        V.tC_off = M.tC_off + t0;
+        V.tV_off = M.tV_off + t0;
+        S->m = V;
+        // classification of the slab (and exact arbitration)
+        e = fill_i32(V.unc_n, 1, 0, st);
+        if (e == hipSuccess) e = launch_classify(V, fp32, lab[b], st);
+        if (e != hipSuccess) {
+            set_err("slab classification: %s", hipGetErrorString(e));
+            return fail(ESES_EDEVICE);
+        }
+        uint8_t *lb = lab[b];
+        if ((s = arbitrate(c, fp32, &lb, st)) != ESES_OK) return fail(s);
+        // crossing edges of the slab view, into device buffer b
+        if (od[b].capacity == 0 && (s = grow(od[b], std::max<long long>(4096, plane))) != ESES_OK)
+            return fail(s);
+        int64_t cnt = 0;
+        if ((s = edges_one(c, 0, lb, od[b], &cnt, st, false)) != ESES_OK) return fail(s);
+        if (cnt > od[b].capacity) {
+            if ((s = grow(od[b], cnt + cnt / 4)) != ESES_OK) return fail(s);
+            if ((s = edges_one(c, 0, lb, od[b], &cnt, st, false)) != ESES_OK) return fail(s);
+        }
+        // records of the slab's own points, keyed in the whole grid
+        long long n_own = 0;
+        e = launch_slab_keys((long long *)od[b].key, cnt, 3 * plane * (k1 - k0), 3 * plane * k0,
+                             nown_dev, st);
+        if (e != hipSuccess) {
+            set_err("slab keys: %s", hipGetErrorString(e));
+            return fail(ESES_EDEVICE);
+        }
+        if ((s = read_scalars({{nown_dev, true, &n_own}}, st)) != ESES_OK) return fail(s);
+        // copies to the host on the copy stream
+        e = hipEventRecord(ready, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cs, ready, 0);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(labels_host + k0 * plane, lb, (size_t)(plane * (k1 - k0)),
+                               hipMemcpyDeviceToHost, cs);
+        const long long room = std::max<long long>(0, oh.capacity - pos);
+        const long long nc = std::min(n_own, room);
+        if (e == hipSuccess && nc > 0) {
+            e = hipMemcpyAsync(oh.key + pos, od[b].key, sizeof(int64_t) * nc, hipMemcpyDeviceToHost, cs);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(oh.lambda + pos, od[b].lambda, sizeof(double) * nc,
+                                   hipMemcpyDeviceToHost, cs);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(oh.normal + 3 * pos, od[b].normal, sizeof(double) * 3 * nc,
+                                   hipMemcpyDeviceToHost, cs);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(oh.patch_type + pos, od[b].patch_type, nc,
+                                   hipMemcpyDeviceToHost, cs);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(oh.atoms + 3 * pos, od[b].atoms, sizeof(int32_t) * 3 * nc,
+                                   hipMemcpyDeviceToHost, cs);
+        }
+        if (e == hipSuccess) e = hipEventRecord(copied[b], cs);
+        if (e != hipSuccess) {
+            set_err("slab copies: %s", hipGetErrorString(e));
+            return fail(ESES_EDEVICE);
+        }
+        pos += n_own;
+    }
+    if (hipStreamSynchronize(cs) != hipSuccess) {
+        set_err("slab copies failed");
+        return fail(ESES_EDEVICE);
+    }
+    cleanup();
+    *count = pos;
+    if (pos > oh.capacity) {
+        set_err("the output capacity is below the number of crossing edges (see count)");
+        return ESES_ECAPACITY;
+    }
+    return res;
 }
 
 eses_status eses_mesh(eses_candidates *c, const uint8_t *const *labels,

@@ -261,14 +261,14 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
     float fx[PPT], fy[PPT], fz[PPT];
     bool valid[PPT], inv[PPT], inu[PPT], vmay[PPT], umay[PPT];
     double org[3];
-    for (int a = 0; a < 3; ++a) org[a] = grid_coord(m.lo[a], m.h, t3[a] * T);
+    for (int a = 0; a < 3; ++a) org[a] = mol_coord(m, a, t3[a] * T);
     for (int r = 0; r < PPT; ++r) {
         int p = threadIdx.x + r * CLS_THREADS;
         int i = t3[0] * T + p % T, j = t3[1] * T + (p / T) % T, k = t3[2] * T + p / (T * T);
         valid[r] = p < P && i < m.dims[0] && j < m.dims[1] && k < m.dims[2];
-        px[r] = grid_coord(m.lo[0], m.h, i);
-        py[r] = grid_coord(m.lo[1], m.h, j);
-        pz[r] = grid_coord(m.lo[2], m.h, k);
+        px[r] = mol_coord(m, 0, i);
+        py[r] = mol_coord(m, 1, j);
+        pz[r] = mol_coord(m, 2, k);
         fx[r] = (float)(px[r] - org[0]);
         fy[r] = (float)(py[r] - org[1]);
         fz[r] = (float)(pz[r] - org[2]);
@@ -382,8 +382,8 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
             int i = t3[0] * T + p % T, j = t3[1] * T + (p / T) % T, k = t3[2] * T + p / (T * T);
             const long long gi =
                 (long long)i + (long long)m.dims[0] * ((long long)j + (long long)m.dims[1] * k);
-            const int lab = label_cert(m, tile, grid_coord(m.lo[0], m.h, i),
-                                       grid_coord(m.lo[1], m.h, j), grid_coord(m.lo[2], m.h, k));
+            const int lab = label_cert(m, tile, mol_coord(m, 0, i),
+                                       mol_coord(m, 1, j), mol_coord(m, 2, k));
             labels[gi] = (uint8_t)(lab == 1);
             if (lab == 2) push_uncertain(m, gi);
         }
@@ -415,7 +415,8 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
     double bc[3], rb;
     {
         double half = 0.5 * (T - 1) * m.h;
-        for (int a = 0; a < 3; ++a) bc[a] = m.lo[a] + (double)(t3[a] * T) * m.h + half;
+        for (int a = 0; a < 3; ++a)
+            bc[a] = m.lo[a] + (double)(t3[a] * T + (a == 2 ? m.kz0 : 0)) * m.h + half;
         rb = sqrt(3.0) * half * (1.0 + 1e-12) + 1e-12;
     }
     // cuts of the staged faces and circles that can matter inside the tile,
@@ -505,8 +506,8 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
     for (int q = threadIdx.x; q < nq; q += CLS_THREADS) {
         int p = sh.queue[q];
         int i = t3[0] * T + p % T, j = t3[1] * T + (p / T) % T, k = t3[2] * T + p / (T * T);
-        const int lab = shell_cert_staged<F32>(m, sh, K, tile, nV, nF, nC, grid_coord(m.lo[0], m.h, i),
-                                          grid_coord(m.lo[1], m.h, j), grid_coord(m.lo[2], m.h, k));
+        const int lab = shell_cert_staged<F32>(m, sh, K, tile, nV, nF, nC, mol_coord(m, 0, i),
+                                          mol_coord(m, 1, j), mol_coord(m, 2, k));
         const long long gi =
             (long long)i + (long long)m.dims[0] * ((long long)j + (long long)m.dims[1] * k);
         labels[gi] = (uint8_t)(lab == 1);
@@ -629,8 +630,8 @@ __global__ void __launch_bounds__(CLS_BLOCK) k_classify_work(Mol m, unsigned lon
         int j = t3[1] * T + (local / T) % T;
         int k = t3[2] * T + local / (T * T);
         if (i < m.dims[0] && j < m.dims[1] && k < m.dims[2])
-            label_fp64_t<true>(m, tile, grid_coord(m.lo[0], m.h, i), grid_coord(m.lo[1], m.h, j),
-                               grid_coord(m.lo[2], m.h, k), cnt);
+            label_fp64_t<true>(m, tile, mol_coord(m, 0, i), mol_coord(m, 1, j),
+                               mol_coord(m, 2, k), cnt);
     }
     for (int c = 0; c < WC_COUNT; ++c) {
         unsigned long long v = cnt[c];

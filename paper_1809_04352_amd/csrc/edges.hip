@@ -575,9 +575,9 @@ __device__ inline EdgeGeom edge_geom(const Mol &m, const uint8_t *L, long long k
     G.e[0] = axis == 0 ? 1.0 : 0.0;
     G.e[1] = axis == 1 ? 1.0 : 0.0;
     G.e[2] = axis == 2 ? 1.0 : 0.0;
-    G.xs[0] = grid_coord(m.lo[0], m.h, i0);
-    G.xs[1] = grid_coord(m.lo[1], m.h, i1);
-    G.xs[2] = grid_coord(m.lo[2], m.h, i2);
+    G.xs[0] = mol_coord(m, 0, i0);
+    G.xs[1] = mol_coord(m, 1, i1);
+    G.xs[2] = mol_coord(m, 2, i2);
     return G;
 }
 
@@ -1230,7 +1230,8 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
     {
         const int t3[3] = {tile % m.tdims[0], (tile / m.tdims[0]) % m.tdims[1],
                            tile / (m.tdims[0] * m.tdims[1])};
-        for (int a = 0; a < 3; ++a) bc[a] = m.lo[a] + (t3[a] * T + 0.5 * T) * h;
+        for (int a = 0; a < 3; ++a)
+            bc[a] = m.lo[a] + (t3[a] * T + (a == 2 ? m.kz0 : 0) + 0.5 * T) * h;
     }
     const double rb = sqrt(3.0) * 0.5 * T * h * (1.0 + 1e-12) + 1e-9;
     // pair p -> (p / n, p % n) by a multiply: with n in [2, 64] and
@@ -2020,6 +2021,37 @@ __global__ void __launch_bounds__(EW_THREADS)
             wave_sync();
         }
     }
+}
+
+// Slab views (out-of-core form): the records of the slab's own planes are
+// the keys below `limit` (a prefix, keys being ascending); their number goes
+// to *n_own and those keys are moved to the whole grid's numbering.
+__global__ void k_key_lower_bound(const long long *keys, long long count, long long limit,
+                                  long long *n_own) {
+    long long lo = 0, hi = count;
+    while (lo < hi) {
+        const long long mid = (lo + hi) >> 1;
+        if (keys[mid] < limit) lo = mid + 1;
+        else hi = mid;
+    }
+    *n_own = lo;
+}
+
+__global__ void k_key_shift(long long *keys, long long count, long long limit, long long shift) {
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < count;
+         q += (long long)gridDim.x * blockDim.x)
+        if (keys[q] < limit) keys[q] += shift;
+}
+
+hipError_t launch_slab_keys(long long *keys, long long count, long long limit, long long shift,
+                            long long *n_own, hipStream_t st) {
+    hipLaunchKernelGGL(k_key_lower_bound, dim3(1), dim3(1), 0, st, keys, count, limit, n_own);
+    if (count > 0) {
+        const long long nb = std::min<long long>((count + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_key_shift, dim3((unsigned)nb), dim3(256), 0, st, keys, count, limit,
+                           shift);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_edge_roots_batch(const Mol *mols, const EdgeJob *jobs, int nj, int *prefix,

@@ -49,6 +49,8 @@ struct Mol {
     int edge_fallback;   // every crossing edge through the wavefront root kernel
     int tdims[3];
     int ntiles;
+    int kz0;             // z index of plane 0 in the molecule's whole grid: 0, or the
+                         // first plane of a slab view (out-of-core form)
 
     int *diag;           // [4] diagnostics: [0] fill-pass overflows, [1] FP32 points
                          // re-tested in FP64, [2] shared centres, [3] crossing
@@ -113,6 +115,12 @@ struct Mol {
 // never contracted into a fused multiply-add.
 __device__ inline double grid_coord(double lo, double h, long long i) {
     return __dadd_rn(lo, __dmul_rn((double)i, h));
+}
+
+// Coordinate of grid index i along axis a of molecule view m (a slab view
+// starts at plane kz0 of the whole grid, so its points keep their coordinates).
+__device__ inline double mol_coord(const Mol &m, int a, long long i) {
+    return grid_coord(m.lo[a], m.h, a == 2 ? i + m.kz0 : i);
 }
 
 }  // namespace eses

@@ -155,6 +155,10 @@ constexpr int EU_CLASSES = 8;
 constexpr int EU_CLASS = 0, EU_FILL = 8, EU_QUEUE = 16, EU_COUNT = 24, EU_LIST = 32;
 long long edge_order_capacity(const Mol &m, long long count);
 long long edge_units_capacity(const Mol &m);
+// Slab views: *n_own = the keys below limit (a prefix), which are shifted by
+// `shift` into the whole grid's numbering.
+hipError_t launch_slab_keys(long long *keys, long long count, long long limit, long long shift,
+                            long long *n_own, hipStream_t st);
 hipError_t launch_edge_group(const Mol &m, const long long *keys, long long count, int *tcount,
                              int *ccount, int *coff, const int *rank, int *order, int *units,
                              int *tmp, hipStream_t st);

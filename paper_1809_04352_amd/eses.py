@@ -30,7 +30,7 @@ EXPORTED = [
     "eses_copy_vertices", "eses_classify", "eses_edge_intersections", "eses_free_candidates",
     "eses_last_error", "eses_version", "eses_edge_work", "eses_set_timing",
     "eses_get_kernel_times", "eses_trim_cache", "eses_set_allocator", "eses_exact_labels",
-    "eses_edge_intersections_noalloc", "eses_fill_cavities", "eses_mesh",
+    "eses_edge_intersections_noalloc", "eses_fill_cavities", "eses_mesh", "eses_stream_slabs",
 ]
 
 # C types of the caller-allocator hook (eses_set_allocator).
@@ -148,6 +148,9 @@ def load():
     lib.eses_edge_intersections_noalloc.restype = st
     lib.eses_edge_intersections_noalloc.argtypes = [P, P, ctypes.POINTER(IsectSoA),
                                                     ctypes.POINTER(ctypes.c_int64), P]
+    lib.eses_stream_slabs.restype = st
+    lib.eses_stream_slabs.argtypes = [P, ctypes.c_int, ctypes.c_int32, P, ctypes.POINTER(IsectSoA),
+                                      ctypes.POINTER(ctypes.c_int64), P]
     lib.eses_mesh.restype = st
     lib.eses_mesh.argtypes = [P, P, ctypes.POINTER(IsectSoA), P, P, P,
                               ctypes.POINTER(MeshStats), P]
@@ -343,6 +346,20 @@ def edge_intersections_noalloc(cand: Candidates, labels_dev, out, stream=None):
     cnt = ctypes.c_int64()
     st = load().eses_edge_intersections_noalloc(cand.h, labels_dev.data_ptr(), ctypes.byref(soa),
                                                 ctypes.byref(cnt), _stream_ptr(stream))
+    if st not in (ESES_OK, ESES_ECAPACITY):
+        _check(st)
+    return st, int(cnt.value)
+
+
+def stream_slabs(cand: Candidates, prec, slab_planes: int, labels_host, out_host, stream=None):
+    """The out-of-core form for a one-molecule handle: labels and records in
+    HOST tensors (labels_host uint8 [npoints]; out_host an IsectBuffers of
+    host tensors).  Returns (status, count); status is ESES_OK or
+    ESES_ECAPACITY."""
+    soa = _soa([out_host])
+    cnt = ctypes.c_int64()
+    st = load().eses_stream_slabs(cand.h, int(prec), int(slab_planes), labels_host.data_ptr(),
+                                  soa, ctypes.byref(cnt), _stream_ptr(stream))
     if st not in (ESES_OK, ESES_ECAPACITY):
         _check(st)
     return st, int(cnt.value)
