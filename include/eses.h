@@ -118,7 +118,12 @@ typedef struct {
                               whose FP64 decision cannot be certified (0 =
                               default); a queue that overflows is grown and the
                               molecule classified again */
-    int32_t reserved;      /* must be zero */
+    int32_t unit_order;    /* batches: order in which the fused classification
+                              takes its (molecule, tile) units: 0 = three
+                              classes (tiles with probe, face or circle
+                              candidates, then atom-only tiles, then empty
+                              tiles; default), 1 = heaviest first by a cost
+                              estimate from the tile's list sizes */
 } eses_config;
 
 typedef struct eses_candidates eses_candidates; /* opaque, library-owned */

@@ -1,8 +1,9 @@
 """Autotuner of the launch configuration of eses_classify.
 
 Times eses_classify for a set of candidate configurations (tile edge and,
-for batches, persistent workgroups per compute unit) on the caller's
-molecules and keeps the fastest; results are cached per workload signature
+for batches, persistent workgroups per compute unit and the order in which
+the fused launch takes its units) on the caller's molecules and keeps the
+fastest; results are cached per workload signature
 (molecule count, atom count and spacing buckets) in a JSON file
 ($ESES_AUTOTUNE_CACHE, default ~/.cache/eses_autotune.json).  Labels do not
 depend on the choice.
@@ -16,8 +17,10 @@ import os
 from . import eses
 
 CANDIDATES_SINGLE = [dict(tile=8), dict(tile=4)]
-CANDIDATES_BATCH = [dict(tile=8, blocks_per_cu=0), dict(tile=8, blocks_per_cu=2),
-                    dict(tile=8, blocks_per_cu=4), dict(tile=4, blocks_per_cu=0)]
+CANDIDATES_BATCH = [dict(tile=8, blocks_per_cu=0, unit_order=0),
+                    dict(tile=8, blocks_per_cu=0, unit_order=1),
+                    dict(tile=8, blocks_per_cu=5, unit_order=0),
+                    dict(tile=4, blocks_per_cu=0, unit_order=0)]
 
 
 def _cache_path():
@@ -37,7 +40,8 @@ def _time_config(mols, prec, cfg, reps, stream):
     dims = [eses.grid_dims(m) for m in mols]
     labels = [torch.empty(d[0] * d[1] * d[2], dtype=torch.uint8, device="cuda") for d in dims]
     cand = eses.build_candidates(mols, tile=cfg.get("tile", 0),
-                                 blocks_per_cu=cfg.get("blocks_per_cu", 0))
+                                 blocks_per_cu=cfg.get("blocks_per_cu", 0),
+                                 unit_order=cfg.get("unit_order", 0))
     try:
         eses.classify(cand, prec, labels)  # warm-up (records the batch graph)
         a = torch.cuda.Event(enable_timing=True)

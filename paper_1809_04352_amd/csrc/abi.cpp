@@ -216,7 +216,8 @@ struct eses_candidates {
     Mol *mols_dev = nullptr;
     int *tile_base_dev = nullptr;
     int2 *units = nullptr;
-    int *cls = nullptr;        // [0..2] class counts, [3..5] class fill
+    int *cls = nullptr;        // unit class counts, then class fill positions
+    int unit_order = 0;        // eses_config.unit_order
     int *head = nullptr;
     uint8_t **labels_dev = nullptr;
     int *unc_counts = nullptr;  // [n_mols] gathered uncertain-point counts
@@ -996,14 +997,14 @@ eses_status build_batch(eses_candidates *c, hipStream_t st) {
     CKS(B.alloc(&c->mols_dev, nm));
     CKS(B.alloc(&c->tile_base_dev, nm + 1));
     CKS(B.alloc(&c->units, c->nunits));
-    CKS(B.alloc(&c->cls, 8));
+    CKS(B.alloc(&c->cls, 2 * UNIT_CLASSES));
     CKS(B.alloc(&c->head, 1));
     CKS(B.alloc(&c->labels_dev, nm));
     CK(hipMemcpyAsync(c->mols_dev, hm.data(), sizeof(Mol) * nm, hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(c->tile_base_dev, base.data(), sizeof(int) * (nm + 1),
                       hipMemcpyHostToDevice, st));
-    CK(launch_units(c->mols_dev, c->tile_base_dev, nm, c->nunits, c->cls, c->cls + 3, c->units,
-                    st));
+    CK(launch_units(c->mols_dev, c->tile_base_dev, nm, c->nunits, c->unit_order, c->cls,
+                    c->cls + UNIT_CLASSES, c->units, st));
     CK(hipStreamSynchronize(st));  // host arrays above are released on return
     int dev = 0, ncu = 0;
     CK(hipGetDevice(&dev));
@@ -1546,8 +1547,8 @@ eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
             set_err("vertex_pool and tile_pool must be >= 0");
             return ESES_EINVAL;
         }
-        if (cfg->reserved != 0) {
-            set_err("eses_config.reserved must be zero");
+        if (cfg->unit_order != 0 && cfg->unit_order != 1) {
+            set_err("unit_order must be 0 or 1");
             return ESES_EINVAL;
         }
         if (cfg->unc_queue < 0) {
@@ -1581,6 +1582,7 @@ eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
     }
     if (n_mols > 1) {
         c->blocks_per_cu = cfg ? cfg->blocks_per_cu : 0;
+        c->unit_order = cfg ? cfg->unit_order : 0;
         eses_status s = build_batch(c, st);
         if (s != ESES_OK) {
             std::string msg = g_err;

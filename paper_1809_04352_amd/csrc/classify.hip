@@ -550,12 +550,17 @@ __global__ void __launch_bounds__(CLS_THREADS) __attribute__((amdgpu_waves_per_e
     }
 }
 
-// Work units of a batch: tile cost class 0 (probe, face or circle
-// candidates), 1 (atoms only) or 2 (empty), counted then scattered by class.
-// The class of unit g (molecule, tile): 0 with faces, circles or probes in
-// its lists, 1 with atoms only, 2 empty.
+// Work units of a batch, heaviest first, so that the persistent workgroups
+// end together (longest-processing-time order).  Each (molecule, tile) unit
+// gets a class, counted then scattered class by class:
+//   order 0: three classes, tiles with probe, face or circle candidates, then
+//            tiles with atoms only, then empty tiles;
+//   order 1: the tile's estimated cost, nA + 4 (nF + nC) + nV from its list
+//            sizes (phase 1 tests every atom for every point; faces and
+//            circles bring the shell tests and their cut planes), in
+//            half-octave buckets, heaviest class first, empty tiles last.
 __device__ inline int unit_class(const Mol *mols, const int *tile_base, int nmols, long long g,
-                                 int &mol, int &t) {
+                                 int order, int &mol, int &t) {
     int lo = 0, hi = nmols - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
@@ -565,53 +570,64 @@ __device__ inline int unit_class(const Mol *mols, const int *tile_base, int nmol
     const Mol &m = mols[lo];
     mol = lo;
     t = (int)(g - tile_base[lo]);
-    int heavy = (m.tF_off[t + 1] - m.tF_off[t]) + (m.tC_off[t + 1] - m.tC_off[t]) +
-                (m.tV_off[t + 1] - m.tV_off[t]);
-    return heavy > 0 ? 0 : (m.tA_off[t + 1] > m.tA_off[t] ? 1 : 2);
+    const int nA = m.tA_off[t + 1] - m.tA_off[t];
+    const int nF = m.tF_off[t + 1] - m.tF_off[t], nC = m.tC_off[t + 1] - m.tC_off[t],
+              nV = m.tV_off[t + 1] - m.tV_off[t];
+    if (order == 0) return nF + nC + nV > 0 ? 0 : (nA > 0 ? 1 : 2);
+    const unsigned cost = (unsigned)(nA + 4 * (nF + nC) + nV);
+    if (cost == 0) return UNIT_CLASSES - 1;
+    const int lg = 31 - __clz(cost);  // floor(log2(cost))
+    const int half = lg > 0 ? (int)((cost >> (lg - 1)) & 1u) : 0;
+    const int bucket = min(2 * lg + half, UNIT_CLASSES - 2);
+    return UNIT_CLASSES - 2 - bucket;
 }
 
 // Units per class: counted in LDS, one global add per class and block.
 __global__ void __launch_bounds__(256) k_unit_count(const Mol *mols, const int *tile_base,
-                                                    int nmols, long long total, int *cls_count) {
-    __shared__ int cls[3];
-    if (threadIdx.x < 3) cls[threadIdx.x] = 0;
+                                                    int nmols, long long total, int order,
+                                                    int *cls_count) {
+    __shared__ int cls[UNIT_CLASSES];
+    if (threadIdx.x < UNIT_CLASSES) cls[threadIdx.x] = 0;
     __syncthreads();
     long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (g < total) {
         int mol, t;
-        atomicAdd(&cls[unit_class(mols, tile_base, nmols, g, mol, t)], 1);
+        atomicAdd(&cls[unit_class(mols, tile_base, nmols, g, order, mol, t)], 1);
     }
     __syncthreads();
-    if (threadIdx.x < 3 && cls[threadIdx.x] > 0) atomicAdd(&cls_count[threadIdx.x], cls[threadIdx.x]);
+    if (threadIdx.x < UNIT_CLASSES && cls[threadIdx.x] > 0)
+        atomicAdd(&cls_count[threadIdx.x], cls[threadIdx.x]);
 }
 
 // The unit list, class by class: a block ranks its units per class in LDS
 // and reserves each class's run with one global add.
 __global__ void __launch_bounds__(256) k_unit_scatter(const Mol *mols, const int *tile_base,
-                                                      int nmols, long long total, int *cls_fill,
-                                                      int2 *units) {
-    __shared__ int cls[3], base[3];
-    if (threadIdx.x < 3) cls[threadIdx.x] = 0;
+                                                      int nmols, long long total, int order,
+                                                      int *cls_fill, int2 *units) {
+    __shared__ int cls[UNIT_CLASSES], base[UNIT_CLASSES];
+    if (threadIdx.x < UNIT_CLASSES) cls[threadIdx.x] = 0;
     __syncthreads();
     long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     int c = -1, r = 0, mol = 0, t = 0;
     if (g < total) {
-        c = unit_class(mols, tile_base, nmols, g, mol, t);
+        c = unit_class(mols, tile_base, nmols, g, order, mol, t);
         r = atomicAdd(&cls[c], 1);
     }
     __syncthreads();
-    if (threadIdx.x < 3 && cls[threadIdx.x] > 0)
+    if (threadIdx.x < UNIT_CLASSES && cls[threadIdx.x] > 0)
         base[threadIdx.x] = atomicAdd(&cls_fill[threadIdx.x], cls[threadIdx.x]);
     __syncthreads();
     if (c >= 0) units[base[c] + r] = make_int2(mol, t);
 }
 
-// cls_fill[c] = first slot of class c (from the counts), head = 0.
+// cls_fill[c] = first slot of class c (an exclusive scan of the counts).
 __global__ void k_unit_bases(const int *cls_count, int *cls_fill) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        cls_fill[0] = 0;
-        cls_fill[1] = cls_count[0];
-        cls_fill[2] = cls_count[0] + cls_count[1];
+        int acc = 0;
+        for (int c = 0; c < UNIT_CLASSES; ++c) {
+            cls_fill[c] = acc;
+            acc += cls_count[c];
+        }
     }
 }
 
@@ -667,15 +683,15 @@ hipError_t launch_count_inside(const uint8_t *labels, long long n, unsigned long
 }
 
 hipError_t launch_units(const Mol *mols_dev, const int *tile_base_dev, int nmols, long long total,
-                        int *cls_count, int *cls_fill, int2 *units, hipStream_t st) {
+                        int order, int *cls_count, int *cls_fill, int2 *units, hipStream_t st) {
     unsigned nb = (unsigned)((total + 255) / 256);
-    hipError_t e = fill_i32(cls_count, 3, 0, st);
+    hipError_t e = fill_i32(cls_count, UNIT_CLASSES, 0, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_unit_count, dim3(nb), dim3(256), 0, st, mols_dev, tile_base_dev, nmols,
-                       total, cls_count);
+                       total, order, cls_count);
     hipLaunchKernelGGL(k_unit_bases, dim3(1), dim3(64), 0, st, cls_count, cls_fill);
     hipLaunchKernelGGL(k_unit_scatter, dim3(nb), dim3(256), 0, st, mols_dev, tile_base_dev, nmols,
-                       total, cls_fill, units);
+                       total, order, cls_fill, units);
     return hipGetLastError();
 }
 

@@ -114,8 +114,10 @@ hipError_t launch_gather_ints(const int *const *addr, int n, int *out, hipStream
 
 // stage 2
 hipError_t launch_classify(const Mol &m, bool fp32, uint8_t *labels, hipStream_t st);
+// Classes of the batch's classification units (heaviest first).
+constexpr int UNIT_CLASSES = 24;
 hipError_t launch_units(const Mol *mols_dev, const int *tile_base_dev, int nmols, long long total,
-                        int *cls_count, int *cls_fill, int2 *units, hipStream_t st);
+                        int order, int *cls_count, int *cls_fill, int2 *units, hipStream_t st);
 int classify_batch_blocks_per_cu(bool fp32);
 // (also zeroes every molecule's uncertain-point counter first)
 hipError_t launch_classify_batch(const Mol *mols_dev, int nmols, uint8_t *const *labels_dev,

@@ -19,13 +19,14 @@ def E():
     return eses
 
 
-def run_batch(E, mols_np, prec, reps=2, blocks_per_cu=0, tile=0):
+def run_batch(E, mols_np, prec, reps=2, blocks_per_cu=0, tile=0, unit_order=0):
     import torch
     tens = [(torch.as_tensor(m.centres, device="cuda"), torch.as_tensor(m.radii, device="cuda"))
             for m in mols_np]
     mols = [E.make_molecule(c, r, m.probe, m.spacing, m.lo, m.hi)
             for (c, r), m in zip(tens, mols_np)]
-    cand = E.build_candidates(mols, tile=tile, blocks_per_cu=blocks_per_cu)
+    cand = E.build_candidates(mols, tile=tile, blocks_per_cu=blocks_per_cu,
+                              unit_order=unit_order)
     dims = [E.grid_dims(m) for m in mols]
     out = []
     for rep in range(reps):
@@ -96,6 +97,22 @@ def test_batch_with_empty_surfaces(E, oracle_mod):
         ref = o.labels_grid(m.lo, m.spacing, m.dims)
         compare_labels(lab, ref)
         compare_edges(ed, o, m.lo, m.spacing, m.dims, ref)
+
+
+def test_launch_knobs_do_not_change_results(E):
+    """Unit order, workgroups per CU and tile edge change the launch only:
+    labels and records equal those of the default configuration."""
+    from eses_inputs import molecule
+    mols = [molecule(n, 60 + n, h) for n, h in ((150, 0.5), (700, 0.4), (40, 0.3))]
+    base_l, base_e = run_batch(E, mols, 1, reps=1)
+    for knobs in (dict(unit_order=1), dict(blocks_per_cu=2), dict(tile=4, unit_order=1)):
+        print("case: knobs", knobs, flush=True)
+        lab, ed = run_batch(E, mols, 1, reps=2, **knobs)
+        for a, b in zip(base_l, lab):
+            assert np.array_equal(a, b)
+        for a, b in zip(base_e, ed):
+            for k in a:
+                assert np.array_equal(a[k], b[k]), k
 
 
 def test_autotune(E, tmp_path, monkeypatch):
