@@ -864,8 +864,9 @@ class Builder {
         Launch vp{BK_VERTEX_PLACE, false, 0, 0}, vf{BK_VERTEX, true, 0, 0},
             vo{BK_VERTEX_ORDER, false, 0, 0}, ei{BK_EC_IDS, false, 0, 0},
             fo{BK_FEATURE_OFF, false, 0, 0}, fl{BK_FACE_LIST, false, 0, 0},
-            ec{BK_EC_CUTS, false, 0, 0}, ti{BK_TILES, false, 0, 0};
-        for (Launch *l : {&vp, &vf, &vo, &ei, &fo, &fl, &ec, &ti})
+            fc{BK_FACE_CUTS, false, 0, 0}, ec{BK_EC_CUTS, false, 0, 0},
+            ti{BK_TILES, false, 0, 0};
+        for (Launch *l : {&vp, &vf, &vo, &ei, &fo, &fl, &fc, &ec, &ti})
             l->off = starts(C, l->k, &l->nb);
         // the ordering pass only where the positions were pooled
         {
@@ -912,6 +913,7 @@ class Builder {
         CK(launch_build(BK_EC_IDS, seg(C, mo, to, ei.off), ei.nb, st_));
         CK(launch_build(BK_FEATURE_OFF, seg(C, mo, to, fo.off), fo.nb, st_));
         CK(launch_build(BK_FACE_LIST, seg(C, mo, to, fl.off), fl.nb, st_));
+        CK(launch_build(BK_FACE_CUTS, seg(C, mo, to, fc.off), fc.nb, st_));  // counts
         CKS(scan(C, S1));
         CK(launch_build(BK_EC_CUTS, seg(C, mo, to, ec.off), ec.nb, st_));
         CKS(scan(C, S2));
@@ -957,11 +959,11 @@ class Builder {
         CKS(P.commit(c_->batch, st_, false));
         size_t mo, to;
         StageCtl &C = begin(&mo, &to);
-        Launch fc{BK_FACE_CUTS, false, 0, 0}, ec{BK_EC_CUTS, true, 0, 0},
+        Launch fc{BK_FACE_CUTS, true, 0, 0}, ec{BK_EC_CUTS, true, 0, 0},
             tp{BK_TILES_PLACE, false, 0, 0}, tf{BK_TILES_FILL, false, 0, 0};
         for (Launch *l : {&fc, &ec, &tp, &tf}) l->off = starts(C, l->k, &l->nb);
         CKS(C.upload(T_, st_));
-        CK(launch_build(BK_FACE_CUTS, seg(C, mo, to, fc.off), fc.nb, st_));
+        CK(launch_build_fill(BK_FACE_CUTS, seg(C, mo, to, fc.off), fc.nb, st_));
         CK(launch_build_fill(BK_EC_CUTS, seg(C, mo, to, ec.off), ec.nb, st_));
         CK(launch_build(BK_TILES_PLACE, seg(C, mo, to, tp.off), tp.nb, st_));
         CK(launch_build(BK_TILES_FILL, seg(C, mo, to, tf.off), tf.nb, st_));

@@ -1101,34 +1101,129 @@ __global__ void k_atom_features(Seg sg) {
 
 __global__ void k_face_list(Seg sg) {
     SEG_BEGIN(sg);
-    int *cut_cnt = tmp.fcut_cnt;
+    (void)tmp;
     int i = bid * blockDim.x + threadIdx.x;
     if (i >= m.n) return;
     if (!(m.aflag[i] & AF_FACE)) return;
     int f = m.face_off_atom[i];
     m.face_atom[f] = i;
-    cut_cnt[f] = m.nbr_off[i + 1] - m.nbr_off[i];
 }
 
 constexpr int FC_WAVES = 4;
+constexpr int CUT_CAPS = 128;  // cuts of one face or circle tested for containment in LDS
 
+// The set of directions a cut (v, tau) rejects, {u : u . v > tau} on the unit
+// sphere of directions (faces) or circle of in-plane directions (circles),
+// is the open cap (arc) around v / |v| of angular radius theta, cos theta =
+// tau / |v|.  A cut whose cap lies inside another cut's cap rejects nothing
+// that the other does not, so it can be dropped without changing any
+// admissibility test: cap k lies inside cap l when the angle alpha between
+// their axes satisfies alpha + theta_k < theta_l, i.e. theta_l > theta_k and
+// cos alpha > cos(theta_l - theta_k) = c_l c_k + s_l s_k.  It is dropped only
+// with a margin of 1e-9 on that cosine (an angle gap of at least 1e-9 rad, far
+// above the rounding of the cosines, about 1e-15), so a direction near cap
+// k's rim lies inside cap l by that gap and its test against l is decided
+// with certainty.  Equal caps are both kept.
+struct Cap {
+    double ax, ay, az, c, s;
+};
+
+__device__ inline Cap cut_cap(double4 v) {
+    Cap k;
+    const double d = sqrt(v.x * v.x + v.y * v.y + v.z * v.z);
+    k.ax = v.x / d;
+    k.ay = v.y / d;
+    k.az = v.z / d;
+    k.c = fmin(1.0, fmax(-1.0, v.w / d));
+    k.s = sqrt(fmax(0.0, 1.0 - k.c * k.c));
+    return k;
+}
+
+__device__ inline bool cap_inside(const Cap &k, const Cap &l) {
+    if (!(l.c < k.c)) return false;  // theta_l > theta_k
+    const double ca = k.ax * l.ax + k.ay * l.ay + k.az * l.az;
+    return ca - (l.c * k.c + l.s * k.s) > 1e-9;
+}
+
+// Per wavefront: the caps of one surface's candidate cuts in LDS; lane q of a
+// pass asks whether cut q is inside another one.
+struct CapLds {
+    double ax[CUT_CAPS], ay[CUT_CAPS], az[CUT_CAPS], c[CUT_CAPS], s[CUT_CAPS];
+};
+
+__device__ inline void cap_put(CapLds &L, int q, const Cap &k) {
+    L.ax[q] = k.ax;
+    L.ay[q] = k.ay;
+    L.az[q] = k.az;
+    L.c[q] = k.c;
+    L.s[q] = k.s;
+}
+
+// Whether cut q (of n staged, lane-varying q) lies inside another staged cut;
+// the loop over the others is uniform across the wavefront.
+__device__ inline bool cap_redundant(const CapLds &L, int n, int q, bool act) {
+    bool red = false;
+    Cap k;
+    if (act) {
+        k.ax = L.ax[q];
+        k.ay = L.ay[q];
+        k.az = L.az[q];
+        k.c = L.c[q];
+        k.s = L.s[q];
+    }
+    for (int l = 0; l < n; ++l) {
+        if (!__any(act && !red)) break;
+        const Cap o = {L.ax[l], L.ay[l], L.az[l], L.c[l], L.s[l]};
+        if (act && !red && l != q && cap_inside(k, o)) red = true;
+    }
+    return red;
+}
+
+// Face cut lists: one wavefront per exposed face, the cuts of its atom's
+// neighbours (cover order) without those inside another one (faces with more
+// than CUT_CAPS neighbours keep every cut).  Count pass (cut_cnt) and fill
+// pass, with the same decisions.
+template <bool FILL>
 __global__ void __launch_bounds__(FC_WAVES *WAVE) k_face_cuts(Seg sg) {
+    __shared__ CapLds caps[FC_WAVES];
     SEG_BEGIN(sg);
-    (void)tmp;
-    int f = bid * FC_WAVES + threadIdx.x / WAVE;
+    int *cut_cnt = tmp.fcut_cnt;
+    const int wv = threadIdx.x / WAVE;
+    int f = bid * FC_WAVES + wv;
     if (f >= m.nface) return;  // uniform across the wavefront
+    const int lane = lane_id();
     int i = m.face_atom[f];
     double4 ai = m.atom[i];
     double si = ai.w + m.rho;
-    int w = m.face_cut_off[f];
     int nb = m.nbr_off[i], ne = m.nbr_off[i + 1];
-    for (int q = nb + lane_id(); q < ne; q += WAVE) {
-        double4 ak = m.atom[m.nbr_cov[q]];
+    const int n = ne - nb;
+    const bool filt = n <= CUT_CAPS;
+    CapLds &L = caps[wv];
+    auto cut_of = [&](int q) {
+        double4 ak = m.atom[m.nbr_cov[nb + q]];
         double sk = ak.w + m.rho;
         double vx = ak.x - ai.x, vy = ak.y - ai.y, vz = ak.z - ai.z;
         double d2 = vx * vx + vy * vy + vz * vz;
-        m.face_cut[w + (q - nb)] = make_double4(vx, vy, vz, (si * si + d2 - sk * sk) / (2.0 * si));
+        return make_double4(vx, vy, vz, (si * si + d2 - sk * sk) / (2.0 * si));
+    };
+    if (filt) {
+        for (int q = lane; q < n; q += WAVE) cap_put(L, q, cut_cap(cut_of(q)));
+        wave_sync();
     }
+    int w = FILL ? m.face_cut_off[f] : 0, we = FILL ? m.face_cut_off[f + 1] : 0;
+    int cnt = 0;
+    for (int base = 0; base < n; base += WAVE) {
+        const int q = base + lane;
+        const bool act = q < n;
+        const bool keep = act && !(filt && cap_redundant(L, n, q, act));
+        const unsigned long long bm = __ballot(keep);
+        if (FILL && keep) {
+            const int p = w + cnt + mask_prefix(bm);
+            if (fill_ok(m, p, we)) m.face_cut[p] = cut_of(q);
+        }
+        cnt += __popcll(bm);
+    }
+    if (!FILL && lane == 0) cut_cnt[f] = cnt;
 }
 
 // Exposed circles: a 0/1 flag per circle (scanned into positions), the id
@@ -1152,11 +1247,18 @@ __global__ void k_ec_ids(Seg sg) {
 
 constexpr int EC_WAVES = 4;
 
+// Exposed-circle cut lists: one wavefront per exposed circle, the in-plane
+// cuts of its owner's neighbours that reach the circle, without those whose
+// arc lies inside another one's (the cap test above on in-plane directions;
+// circles with more than CUT_CAPS reaching neighbours keep every cut).
 template <bool FILL>
 __global__ void __launch_bounds__(EC_WAVES *WAVE) k_ec_cuts(Seg sg) {
+    __shared__ CapLds caps[EC_WAVES];
+    __shared__ double4 cuts[EC_WAVES][CUT_CAPS];
     SEG_BEGIN(sg);
     int *cut_cnt = tmp.eccut_cnt;
-    int e = bid * EC_WAVES + threadIdx.x / WAVE;
+    const int wv = threadIdx.x / WAVE;
+    int e = bid * EC_WAVES + wv;
     if (e >= m.nec) return;  // uniform across the wavefront
     const int lane = lane_id();
     int c = m.ec_circ[e];
@@ -1164,8 +1266,9 @@ __global__ void __launch_bounds__(EC_WAVES *WAVE) k_ec_cuts(Seg sg) {
     double4 oR = m.circ_oR[c];
     double4 n = m.circ_n[c];
     double R = oR.w;
-    int cnt = 0;
-    int w = FILL ? m.ec_cut_off[e] : 0, we = FILL ? m.ec_cut_off[e + 1] : 0;
+    CapLds &L = caps[wv];
+    // the reaching neighbours' cuts, in cover order (staged while they fit)
+    int nin = 0;
     for (int base = m.nbr_off[i]; base < m.nbr_off[i + 1]; base += WAVE) {
         int q = base + lane;
         bool in = false;
@@ -1185,11 +1288,55 @@ __global__ void __launch_bounds__(EC_WAVES *WAVE) k_ec_cuts(Seg sg) {
             }
         }
         unsigned long long bm = __ballot(in);
-        if (FILL) {
-            int p = w + cnt + mask_prefix(bm);
-            if (in && fill_ok(m, p, we)) m.ec_cut[p] = cut;
+        const int p = nin + mask_prefix(bm);
+        if (in && p < CUT_CAPS) {
+            cuts[wv][p] = cut;
+            cap_put(L, p, cut_cap(cut));
         }
-        cnt += __popcll(bm);
+        nin += __popcll(bm);
+    }
+    wave_sync();
+    int w = FILL ? m.ec_cut_off[e] : 0, we = FILL ? m.ec_cut_off[e + 1] : 0;
+    int cnt = 0;
+    if (nin <= CUT_CAPS) {
+        for (int base = 0; base < nin; base += WAVE) {
+            const int q = base + lane;
+            const bool act = q < nin;
+            const bool keep = act && !cap_redundant(L, nin, q, act);
+            const unsigned long long bm = __ballot(keep);
+            if (FILL && keep) {
+                const int p = w + cnt + mask_prefix(bm);
+                if (fill_ok(m, p, we)) m.ec_cut[p] = cuts[wv][q];
+            }
+            cnt += __popcll(bm);
+        }
+    } else {
+        // too many to stage: every reaching cut, as found
+        for (int base = m.nbr_off[i]; base < m.nbr_off[i + 1]; base += WAVE) {
+            int q = base + lane;
+            bool in = false;
+            double4 cut = make_double4(0, 0, 0, 0);
+            if (q < m.nbr_off[i + 1]) {
+                int k = m.nbr_cov[q];
+                if (k != j) {
+                    double4 ak = m.atom[k];
+                    double sk = ak.w + m.rho;
+                    double wx = ak.x - oR.x, wy = ak.y - oR.y, wz = ak.z - oR.z;
+                    double t = wx * n.x + wy * n.y + wz * n.z;
+                    double ux = wx - t * n.x, uy = wy - t * n.y, uz = wz - t * n.z;
+                    double b = sqrt(ux * ux + uy * uy + uz * uz);
+                    in = t * t + sq(b - R) < sq(sk + LIST_SLACK);
+                    double ww = wx * wx + wy * wy + wz * wz;
+                    cut = make_double4(ux, uy, uz, (R * R + ww - sk * sk) / (2.0 * R));
+                }
+            }
+            unsigned long long bm = __ballot(in);
+            if (FILL) {
+                int p = w + cnt + mask_prefix(bm);
+                if (in && fill_ok(m, p, we)) m.ec_cut[p] = cut;
+            }
+            cnt += __popcll(bm);
+        }
     }
     if (!FILL && lane == 0) cut_cnt[e] = cnt;
 }
@@ -1546,7 +1693,7 @@ hipError_t launch_build(BuildKernel k, const Seg &s, long long nblocks, hipStrea
     case BK_EC_IDS: hipLaunchKernelGGL(k_ec_ids, g, dim3(256), 0, st, s); break;
     case BK_FEATURE_OFF: hipLaunchKernelGGL(k_feature_off_atom, g, dim3(256), 0, st, s); break;
     case BK_FACE_LIST: hipLaunchKernelGGL(k_face_list, g, dim3(256), 0, st, s); break;
-    case BK_FACE_CUTS: hipLaunchKernelGGL(k_face_cuts, g, dim3(FC_WAVES * WAVE), 0, st, s); break;
+    case BK_FACE_CUTS: hipLaunchKernelGGL(k_face_cuts<false>, g, dim3(FC_WAVES * WAVE), 0, st, s); break;
     case BK_EC_CUTS: hipLaunchKernelGGL(k_ec_cuts<false>, g, dim3(EC_WAVES * WAVE), 0, st, s); break;
     case BK_TILES: hipLaunchKernelGGL(k_tiles<false>, g, dim3(TILE_WAVES * WAVE), 0, st, s); break;
     case BK_TILES_FILL: hipLaunchKernelGGL(k_tiles<true>, g, dim3(TILE_WAVES * WAVE), 0, st, s); break;
@@ -1562,6 +1709,7 @@ hipError_t launch_build_fill(BuildKernel k, const Seg &s, long long nblocks, hip
     switch (k) {
     case BK_NBR: hipLaunchKernelGGL(k_nbr<true>, g, dim3(NB_WAVES * WAVE), 0, st, s); break;
     case BK_VERTEX: hipLaunchKernelGGL(k_vertex<true>, g, dim3(VX_WAVES * WAVE), 0, st, s); break;
+    case BK_FACE_CUTS: hipLaunchKernelGGL(k_face_cuts<true>, g, dim3(FC_WAVES * WAVE), 0, st, s); break;
     case BK_EC_CUTS: hipLaunchKernelGGL(k_ec_cuts<true>, g, dim3(EC_WAVES * WAVE), 0, st, s); break;
     default: return hipErrorInvalidValue;
     }

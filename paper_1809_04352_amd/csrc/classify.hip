@@ -411,6 +411,8 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
         sh.p2.cn[q] = n;
         sh.p2.cq[q] = circle_cut_consts(oR.w, n.w, m.smax);
     }
+    // the cone loop below reads circles staged by other threads
+    __syncthreads();
     // the tile's own points span T - 1 spacings per axis
     double bc[3], rb;
     {

@@ -1676,8 +1676,9 @@ __global__ void __launch_bounds__(CH_THREADS) __attribute__((amdgpu_waves_per_eu
         const int c0 = J.coff[t], c1 = J.coff[t + 1];
         for (int c = c0; c < c1; ++c) {
             const int n = min(CH_EDGES, J.tcount[t] - (c - c0) * CH_EDGES);
-            edge_chunk<false>(mols[J.mol], J.L, J.keys, J.order, c * CH_EDGES, n, J.lam, J.nrm,
-                              J.ptype, J.patoms, J.fallback, J.nfallback, c != c0, S, cnt);
+            edge_chunk<false>(uniform_mol(mols, J.mol), J.L, J.keys, J.order, c * CH_EDGES, n,
+                              J.lam, J.nrm, J.ptype, J.patoms, J.fallback, J.nfallback, c != c0,
+                              S, cnt);
             __syncthreads();
         }
     }

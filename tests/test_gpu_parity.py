@@ -267,6 +267,30 @@ def test_repeat_is_deterministic(E):
         assert np.array_equal(x, y)
 
 
+def test_repeated_classification_of_one_handle(E, oracle_mod):
+    """Regression: one handle classified eight times in a row (both
+    precisions) gives the oracle's labels every time.  A molecule whose tiles
+    stage circles with short cut lists: their direction cones were once read
+    from LDS before the threads staging the circles had written them, which
+    changed labels from call to call."""
+    import torch
+    from eses_inputs import molecule
+    m = molecule(120, 5, 0.25)
+    c = torch.as_tensor(m.centres, device="cuda")
+    r = torch.as_tensor(m.radii, device="cuda")
+    cand = E.build_candidates([E.make_molecule(c, r, m.probe, m.spacing, m.lo, m.hi)])
+    try:
+        ref = oracle_mod.Oracle(m.centres, m.radii, m.probe).labels_grid(m.lo, m.spacing, m.dims)
+        for call in range(8):
+            prec = call % 2
+            print("case: repeated classification, call", call, flush=True)
+            lab = torch.empty(m.n_points, dtype=torch.uint8, device="cuda")
+            E.classify(cand, prec, [lab])
+            compare_labels(lab.cpu().numpy().reshape(ref.shape), ref)
+    finally:
+        cand.close()
+
+
 def test_tile_shape_invariance(E):
     from eses_inputs import molecule
     m = molecule(200, 13, 0.3)
