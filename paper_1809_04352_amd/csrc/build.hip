@@ -1110,7 +1110,8 @@ __global__ void k_face_list(Seg sg) {
 }
 
 constexpr int FC_WAVES = 4;
-constexpr int CUT_CAPS = 128;  // cuts of one face or circle tested for containment in LDS
+constexpr int CUT_CAPS = 128;  // cuts of one face tested for containment in LDS
+constexpr int EC_CAPS = 64;    // cuts of one circle tested for containment in LDS
 
 // The set of directions a cut (v, tau) rejects, {u : u . v > tau} on the unit
 // sphere of directions (faces) or circle of in-plane directions (circles),
@@ -1147,11 +1148,13 @@ __device__ inline bool cap_inside(const Cap &k, const Cap &l) {
 
 // Per wavefront: the caps of one surface's candidate cuts in LDS; lane q of a
 // pass asks whether cut q is inside another one.
+template <int N>
 struct CapLds {
-    double ax[CUT_CAPS], ay[CUT_CAPS], az[CUT_CAPS], c[CUT_CAPS], s[CUT_CAPS];
+    double ax[N], ay[N], az[N], c[N], s[N];
 };
 
-__device__ inline void cap_put(CapLds &L, int q, const Cap &k) {
+template <int N>
+__device__ inline void cap_put(CapLds<N> &L, int q, const Cap &k) {
     L.ax[q] = k.ax;
     L.ay[q] = k.ay;
     L.az[q] = k.az;
@@ -1161,7 +1164,8 @@ __device__ inline void cap_put(CapLds &L, int q, const Cap &k) {
 
 // Whether cut q (of n staged, lane-varying q) lies inside another staged cut;
 // the loop over the others is uniform across the wavefront.
-__device__ inline bool cap_redundant(const CapLds &L, int n, int q, bool act) {
+template <int N>
+__device__ inline bool cap_redundant(const CapLds<N> &L, int n, int q, bool act) {
     bool red = false;
     Cap k;
     if (act) {
@@ -1185,7 +1189,7 @@ __device__ inline bool cap_redundant(const CapLds &L, int n, int q, bool act) {
 // pass, with the same decisions.
 template <bool FILL>
 __global__ void __launch_bounds__(FC_WAVES *WAVE) k_face_cuts(Seg sg) {
-    __shared__ CapLds caps[FC_WAVES];
+    __shared__ CapLds<CUT_CAPS> caps[FC_WAVES];
     SEG_BEGIN(sg);
     int *cut_cnt = tmp.fcut_cnt;
     const int wv = threadIdx.x / WAVE;
@@ -1198,7 +1202,7 @@ __global__ void __launch_bounds__(FC_WAVES *WAVE) k_face_cuts(Seg sg) {
     int nb = m.nbr_off[i], ne = m.nbr_off[i + 1];
     const int n = ne - nb;
     const bool filt = n <= CUT_CAPS;
-    CapLds &L = caps[wv];
+    CapLds<CUT_CAPS> &L = caps[wv];
     auto cut_of = [&](int q) {
         double4 ak = m.atom[m.nbr_cov[nb + q]];
         double sk = ak.w + m.rho;
@@ -1250,11 +1254,11 @@ constexpr int EC_WAVES = 4;
 // Exposed-circle cut lists: one wavefront per exposed circle, the in-plane
 // cuts of its owner's neighbours that reach the circle, without those whose
 // arc lies inside another one's (the cap test above on in-plane directions;
-// circles with more than CUT_CAPS reaching neighbours keep every cut).
+// circles with more than EC_CAPS reaching neighbours keep every cut).
 template <bool FILL>
 __global__ void __launch_bounds__(EC_WAVES *WAVE) k_ec_cuts(Seg sg) {
-    __shared__ CapLds caps[EC_WAVES];
-    __shared__ double4 cuts[EC_WAVES][CUT_CAPS];
+    __shared__ CapLds<EC_CAPS> caps[EC_WAVES];
+    __shared__ double4 cuts[EC_WAVES][EC_CAPS];
     SEG_BEGIN(sg);
     int *cut_cnt = tmp.eccut_cnt;
     const int wv = threadIdx.x / WAVE;
@@ -1266,7 +1270,7 @@ __global__ void __launch_bounds__(EC_WAVES *WAVE) k_ec_cuts(Seg sg) {
     double4 oR = m.circ_oR[c];
     double4 n = m.circ_n[c];
     double R = oR.w;
-    CapLds &L = caps[wv];
+    CapLds<EC_CAPS> &L = caps[wv];
     // the reaching neighbours' cuts, in cover order (staged while they fit)
     int nin = 0;
     for (int base = m.nbr_off[i]; base < m.nbr_off[i + 1]; base += WAVE) {
@@ -1289,7 +1293,7 @@ __global__ void __launch_bounds__(EC_WAVES *WAVE) k_ec_cuts(Seg sg) {
         }
         unsigned long long bm = __ballot(in);
         const int p = nin + mask_prefix(bm);
-        if (in && p < CUT_CAPS) {
+        if (in && p < EC_CAPS) {
             cuts[wv][p] = cut;
             cap_put(L, p, cut_cap(cut));
         }
@@ -1298,7 +1302,7 @@ __global__ void __launch_bounds__(EC_WAVES *WAVE) k_ec_cuts(Seg sg) {
     wave_sync();
     int w = FILL ? m.ec_cut_off[e] : 0, we = FILL ? m.ec_cut_off[e + 1] : 0;
     int cnt = 0;
-    if (nin <= CUT_CAPS) {
+    if (nin <= EC_CAPS) {
         for (int base = 0; base < nin; base += WAVE) {
             const int q = base + lane;
             const bool act = q < nin;
