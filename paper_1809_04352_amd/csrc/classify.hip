@@ -26,8 +26,9 @@ constexpr int CLS_THREADS = 256;
 constexpr int CLS_WAVES = CLS_THREADS / WAVE;
 constexpr int CLS_ATOMS = 256;
 constexpr int CLS_MAXPTS = 512;  // points per tile (8^3)
-constexpr int CAP_V = 48, CAP_F = 48, CAP_C = 48, CAP_CUT = 256;
-// Six waves per SIMD (80 VGPRs, a few spilled; 24 KB of LDS per workgroup):
+constexpr int CAP_V = 48, CAP_F = 48, CAP_C = 48, CAP_CUT = 320;
+// Six waves per SIMD (80 VGPRs, a few spilled; 26 KB of LDS per workgroup, so
+// that six workgroups fit the 160 KB of a CU):
 // the kernel waits mostly on dependent loads, and on the batch the extra
 // resident workgroups outweigh the spills (28.6 vs 33.3 ms at four waves;
 // seven and eight waves, with more spills and smaller cut pools, 29.9 and
