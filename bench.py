@@ -71,7 +71,7 @@ def parse():
     ap.add_argument("--prec", choices=["both", "fp64", "fp32"], default="both",
                     help="both: timed FP32+recheck steps (value), then FP64 steps beside")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+    ap.add_argument("--cpu-seconds", type=float, default=40.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--stream", type=int, default=0, metavar="PLANES",
                     help="time the out-of-core form instead (one molecule's grid in z-slabs of "
