@@ -66,6 +66,7 @@ struct ClsPhase2 {
     int coff[CAP_F + CAP_C + 1];
     int ccur[CAP_F + CAP_C];
     int koff[CAP_F + CAP_C];
+    int dead[CAP_F + CAP_C];  // one cut rejects the surface's candidate over the whole tile
     int scan[CLS_WAVES + 1];
 };
 
@@ -154,6 +155,21 @@ __device__ inline bool cut_matters_f(float4 a, float ct, double4 cut) {
     return best > cut.w - 1e-9 - 1e-6 * vn;
 }
 
+// Whether cut (v, tau) rejects every direction u of the cone: the minimum of
+// u . v over the cone, |v| cos(phi + theta), above tau by the same slack
+// (when the cone does not reach -v).  The surface's candidate is then
+// inadmissible at every point of the tile, and its tests are skipped.
+__device__ inline bool cut_rejects_cone_f(float4 a, float ct, double4 cut) {
+    if (ct < 0.0f) return false;
+    const double vn = sqrt(cut.x * cut.x + cut.y * cut.y + cut.z * cut.z);
+    if (!(vn > 0.0)) return false;
+    const double cp = cone_cos(a, cut, vn);
+    if (cp <= -(double)ct) return false;
+    const double sp = sqrt(fmax(0.0, 1.0 - cp * cp));
+    return vn * (cp * (double)ct - sp * (double)a.w) >
+           cut.w + 1e-9 * (vn + fabs(cut.w)) + 1e-6 * vn;
+}
+
 __device__ inline bool cuts_pass(const double4 *cuts, int b, int e, double dx, double dy,
                                  double dz, double d) {
     for (int c = b; c < e; ++c) {
@@ -188,13 +204,14 @@ __device__ inline int shell_cert_staged(const Mol &m, const ClsShared &sh, const
         unsure |= t == TV_UNSURE;
     }
     for (int q = 0; q < nF; ++q) {
+        const int2 r = sh.p2.fr[q];
+        if (r.x == -2) continue;  // candidate inadmissible over the whole tile
         double4 a = sh.p2.f[q];
         double dx = x - a.x, dy = y - a.y, dz = z - a.z;
         double d2 = dx * dx + dy * dy + dz * dz;
         const int w = tv_neg(d2 - a.w, K.fw_band);
         if (w == TV_NO) continue;
         const double d = sqrt_sel<FAST>(d2);
-        int2 r = sh.p2.fr[q];
         const int c = r.x >= 0 ? tv_face_cuts(sh.p2.cut, r.x, r.x + r.y, dx, dy, dz, d, K.gf)
                                : tv_face_cuts(m.face_cut, m.face_cut_off[r.y],
                                               m.face_cut_off[r.y + 1], dx, dy, dz, d, K.gf);
@@ -219,10 +236,11 @@ __device__ inline int shell_cert_staged(const Mol &m, const ClsShared &sh, const
         double4 oR, n, cq;
         int2 r;
         if (q < nC) {
+            r = sh.p2.cr[q];
+            if (r.x == -2) continue;  // candidate inadmissible over the whole tile
             oR = sh.p2.co[q];
             n = sh.p2.cn[q];
             cq = sh.p2.cq[q];
-            r = sh.p2.cr[q];
         } else {
             int ec = m.tC[m.tC_off[tile] + q];
             int ci = m.ec_circ[ec];
@@ -443,6 +461,7 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
         }
         sh.p2.ccb[q] = cb;
         sh.p2.ccur[q] = 0;
+        sh.p2.dead[q] = 0;
         ncut = ce - cb;
     }
     // each surface's cone over the tile, once
@@ -482,6 +501,7 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
             if (pass == 1 && sh.p2.koff[q] < 0) continue;  // not staged
             const int c = sh.p2.ccb[q] + (p - sh.p2.coff[q]);
             const double4 v = q < nF ? m.face_cut[c] : m.ec_cut[c];
+            if (pass == 0 && cut_rejects_cone_f(sh.p2.cna[q], sh.p2.cnc[q], v)) sh.p2.dead[q] = 1;
             if (!cut_matters_f(sh.p2.cna[q], sh.p2.cnc[q], v)) continue;
             const int k = atomicAdd(&sh.p2.ccur[q], 1);
             if (pass == 1) sh.p2.cut[sh.p2.koff[q] + k] = v;
@@ -490,15 +510,18 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
         // kept counts -> regions of the pool
         __syncthreads();
         int kept = 0;
-        if ((int)threadIdx.x < nS) kept = sh.p2.ccur[threadIdx.x];
+        if ((int)threadIdx.x < nS && !sh.p2.dead[threadIdx.x]) kept = sh.p2.ccur[threadIdx.x];
         int ktot;
         const int koff = block_excl_scan<int, CLS_THREADS>(kept, sh.p2.scan, &ktot);
         if ((int)threadIdx.x < nS) {
             const int q = threadIdx.x;
-            const bool fits = koff + kept <= CAP_CUT;
+            const bool dead = sh.p2.dead[q] != 0;
+            const bool fits = !dead && koff + kept <= CAP_CUT;
             sh.p2.koff[q] = fits ? koff : -1;
             sh.p2.ccur[q] = 0;
-            const int2 r = fits ? make_int2(koff, kept)
+            // (-2, 0): dead in this tile, skipped by the shell tests
+            const int2 r = dead ? make_int2(-2, 0)
+                         : fits ? make_int2(koff, kept)
                                 : make_int2(-1, q < nF ? m.tF[f0 + q] : m.tC[c0 + q - nF]);
             if (q < nF) sh.p2.fr[q] = r;
             else sh.p2.cr[q - nF] = r;

@@ -1401,9 +1401,10 @@ __device__ void edge_chunk(const Mol &m, const uint8_t *L, const long long *keys
                 if (eact) {
                     const double mid[3] = {S.mid[lane][0], S.mid[lane][1], S.mid[lane][2]};
                     hit = staged_reaches_rel(type, S.sp[si], rho, mid, half, &rel);
-                    // a circle whose candidate is inadmissible on the whole
-                    // edge has no kept root there and fails every label test
-                    if (type == 2 && (hit || rel) &&
+                    // a face or circle whose candidate is inadmissible on the
+                    // whole edge has no kept root there and fails every
+                    // label test
+                    if (type != 3 && (hit || rel) &&
                         edge_cone_dead<CNT>(m, S, si, type, mid, half, cnt)) {
                         hit = false;
                         rel = false;
