@@ -124,6 +124,12 @@ typedef struct {
                               candidates, then atom-only tiles, then empty
                               tiles; default), 1 = heaviest first by a cost
                               estimate from the tile's list sizes */
+    int32_t edges_per_molecule; /* test aid, batches: find and group each
+                              molecule's crossing edges with launches of its
+                              own on worker streams, the path otherwise taken
+                              only when a molecule's grid has 3 x points >=
+                              2^31 - 1 (0 = off: one launch per pass over the
+                              whole batch) */
 } eses_config;
 
 typedef struct eses_candidates eses_candidates; /* opaque, library-owned */

@@ -218,6 +218,7 @@ struct eses_candidates {
     int2 *units = nullptr;
     int *cls = nullptr;        // unit class counts, then class fill positions
     int unit_order = 0;        // eses_config.unit_order
+    int edges_per_molecule = 0;  // eses_config.edges_per_molecule
     int *head = nullptr;
     uint8_t **labels_dev = nullptr;
     int *unc_counts = nullptr;  // [n_mols] gathered uncertain-point counts
@@ -1313,37 +1314,207 @@ eses_status edges_one(eses_candidates *c, size_t q, const uint8_t *lab, const es
     return ESES_OK;
 }
 
-// A batch: every molecule's crossing edges found and grouped on the worker
-// streams, then all their tiles in one fused root launch on `st` (molecules
-// with most crossing edges first) and one read-back.
+// Host side of the batched crossing-edge passes: the control images and the
+// per-molecule results (kept until the stream has passed them).
+struct EdgeBatchPrep {
+    StageCtl ctl1, ctl2;
+    std::vector<long long> total, nw;
+    std::vector<EdgeJob> job;
+};
+
+// Whether every molecule's crossing edges can take the batched passes (edge
+// offsets within a molecule, and the passes' block counts, fit an int).
+bool edges_batchable(const eses_candidates *c) {
+    long long blocks = 0;
+    for (const auto &mp : c->mols) {
+        const Mol &m = mp->m;
+        if (3 * m.npts >= (1LL << 31) - 1) return false;
+        blocks += edge_detect_blocks(m);
+    }
+    return blocks < (1LL << 31) - 1;
+}
+
+// Every molecule's crossing edges found, keyed and grouped by tile with one
+// launch per pass over the whole batch and one read-back of the totals
+// (see edges_batchable); P.job[q] is molecule q's job of the fused root
+// launch when P.nw[q] > 0.  W holds the workspace.
+eses_status edges_detect_batch(eses_candidates *c, const uint8_t *const *labels,
+                               const eses_isect_soa *out, Arena &W, EdgeBatchPrep &P,
+                               hipStream_t st) {
+    const int nm = (int)c->mols.size();
+    P.total.assign((size_t)nm, 0);
+    P.nw.assign((size_t)nm, 0);
+    P.job.assign((size_t)nm, EdgeJob{});
+    std::vector<EdgeDetectJob> J((size_t)nm);
+    std::vector<long long> nblk((size_t)nm);
+    std::vector<int> sdet((size_t)nm + 1, 0);
+    // pass 1: per-block counts and their scans, the totals read back
+    const long long chunk = scan_seg_chunk();
+    Planner A;
+    std::vector<long long> c1((size_t)nm);
+    long long nch1 = 0;
+    for (int q = 0; q < nm; ++q) {
+        const Mol &m = c->mols[q]->m;
+        nblk[q] = edge_detect_blocks(m);
+        sdet[q + 1] = sdet[q] + (int)nblk[q];
+        c1[q] = nch1;
+        nch1 += (nblk[q] + chunk - 1) / chunk;
+        J[q] = EdgeDetectJob{};
+        J[q].L = labels[q];
+        A.add(&J[q].bcount, nblk[q]);
+        A.add(&J[q].boff, nblk[q] + 1);
+    }
+    int *sums1 = nullptr, *tot = nullptr;
+    A.add(&sums1, nch1);
+    A.add(&tot, 2LL * nm);
+    CKS(A.commit(W, st, false));
+    std::vector<ScanSeg> seg1((size_t)nm);
+    std::vector<const int *> addr((size_t)nm);
+    for (int q = 0; q < nm; ++q) {
+        seg1[q] = ScanSeg{J[q].bcount, J[q].boff, nblk[q], c1[q]};
+        addr[q] = J[q].boff + nblk[q];
+    }
+    StageCtl &C1 = P.ctl1;
+    const size_t jo = C1.put(J.data(), J.size());
+    const size_t so = C1.put(sdet.data(), sdet.size());
+    const size_t go = C1.put(seg1.data(), seg1.size());
+    const size_t ao = C1.put(addr.data(), addr.size());
+    CKS(C1.upload(W, st));
+    CK(launch_edge_detect_count_batch(c->mols_dev, C1.at<EdgeDetectJob>(jo), C1.at<int>(so),
+                                      sdet.data(), nm, st));
+    CK(scan_seg(C1.at<ScanSeg>(go), nm, nch1, sums1, st));
+    CK(launch_gather_ints(C1.at<const int *>(ao), nm, tot, st));
+    CK(launch_diag_gather(c->mols_dev, nm, 0, tot + nm, st));
+    std::vector<int> htot((size_t)2 * nm);
+    CK(hipMemcpyAsync(htot.data(), tot, sizeof(int) * 2 * nm, hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    for (int q = 0; q < nm; ++q)
+        if (htot[(size_t)nm + q] != 0) {
+            set_err("internal: molecule %d: %d candidate list entries beyond their counted range",
+                    q, htot[(size_t)nm + q]);
+            return ESES_EINTERNAL;
+        }
+    // pass 2: keys, tile tallies and ranks, grouping by tile
+    Planner Z, N;  // zeroed (tile tallies, unit headers, fallback counts), not zeroed
+    std::vector<int> sw((size_t)nm + 1, 0), stl((size_t)nm + 1, 0), sed((size_t)nm + 1, 0);
+    std::vector<ScanSeg> seg2;
+    long long nch2 = 0;
+    std::vector<int *> fb((size_t)nm, nullptr), nfb((size_t)nm, nullptr);
+    for (int q = 0; q < nm; ++q) {
+        const Mol &m = c->mols[q]->m;
+        P.total[q] = htot[q];
+        const long long w = P.nw[q] = std::min<long long>(P.total[q], out[q].capacity);
+        J[q].keys = (long long *)out[q].key;
+        J[q].nw = w;
+        sw[q + 1] = sw[q] + (w > 0 ? (int)nblk[q] : 0);
+        stl[q + 1] = stl[q] + (w > 0 ? (m.ntiles + 255) / 256 : 0);
+        sed[q + 1] = sed[q] + (int)((w + 255) / 256);
+        if (w <= 0) continue;
+        Z.add(&J[q].tcount, m.ntiles + 1);
+        Z.add(&J[q].units, edge_units_capacity(m));
+        Z.add(&nfb[q], 1);
+        N.add(&J[q].ccount, m.ntiles + 1);
+        N.add(&J[q].coff, m.ntiles + 1);
+        N.add(&J[q].rank, w);
+        N.add(&J[q].order, edge_order_capacity(m, w));
+        N.add(&fb[q], w);
+    }
+    std::vector<long long> c2((size_t)nm, 0);
+    for (int q = 0; q < nm; ++q)
+        if (P.nw[q] > 0) {
+            c2[q] = nch2;
+            nch2 += (c->mols[q]->m.ntiles + chunk - 1) / chunk;
+        }
+    int *sums2 = nullptr;
+    N.add(&sums2, nch2);
+    CKS(Z.commit(W, st, true));
+    CKS(N.commit(W, st, false));
+    for (int q = 0; q < nm; ++q)
+        if (P.nw[q] > 0) seg2.push_back({J[q].ccount, J[q].coff, c->mols[q]->m.ntiles, c2[q]});
+    StageCtl &C2 = P.ctl2;
+    const size_t jo2 = C2.put(J.data(), J.size());
+    const size_t wo = C2.put(sw.data(), sw.size());
+    const size_t to = C2.put(stl.data(), stl.size());
+    const size_t eo = C2.put(sed.data(), sed.size());
+    const size_t go2 = C2.put(seg2.data(), seg2.size());
+    CKS(C2.upload(W, st));
+    EdgeBatchStarts S{C2.at<int>(wo), C2.at<int>(to), C2.at<int>(eo), sw.data(), stl.data(),
+                      sed.data()};
+    const EdgeDetectJob *jd = C2.at<EdgeDetectJob>(jo2);
+    CK(launch_edge_detect_write_batch(c->mols_dev, jd, S, nm, st));
+    CK(launch_edge_group_batch(c->mols_dev, jd, S, C2.at<ScanSeg>(go2), (int)seg2.size(), nch2,
+                               sums2, nm, st));
+    for (int q = 0; q < nm; ++q) {
+        if (P.nw[q] <= 0) continue;
+        EdgeJob &E = P.job[q];
+        E.L = labels[q];
+        E.keys = J[q].keys;
+        E.order = J[q].order;
+        E.tcount = J[q].tcount;
+        E.coff = J[q].coff;
+        E.units = J[q].units;
+        E.lam = out[q].lambda;
+        E.nrm = out[q].normal;
+        E.ptype = out[q].patch_type;
+        E.patoms = out[q].atoms;
+        E.fallback = fb[q];
+        E.nfallback = nfb[q];
+        E.mol = q;
+    }
+    return ESES_OK;
+}
+
+// A batch: every molecule's crossing edges found and grouped (one launch per
+// pass over the whole batch, or per molecule on the worker streams where a
+// grid is too large for the batched passes), then all their tiles in one
+// fused root launch on `st` (molecules with most crossing edges first) and
+// one read-back.
 eses_status edges_batch(eses_candidates *c, const uint8_t *const *labels,
                         const eses_isect_soa *out, int64_t *counts, hipStream_t st,
                         bool timed) {
     const int nm = (int)c->mols.size();
-    std::vector<EdgePrep> prep(nm);
+    std::vector<EdgePrep> prep;
+    EdgeBatchPrep bp;
+    Arena W;  // the batched passes' workspace
+    W.st = st;
     auto release_all = [&]() {
         for (EdgePrep &P : prep) P.T.release();
+        W.release();
     };
-    // with `timed`, events on `st` bracket the per-molecule detection and
-    // grouping (worker streams) and the fused root launch
+    // with `timed`, events on `st` bracket the detection and grouping and
+    // the fused root launch
     if (timed) CK(hipEventRecord(c->ev[2], st));
-    eses_status s = run_on_workers(nm, st, [&](int q, hipStream_t ws) {
-        return edges_prepare(c, q, labels[q], out[q], prep[q], ws, false, true);
-    });
+    eses_status s = ESES_OK;
+    if (!c->edges_per_molecule && edges_batchable(c)) {
+        s = edges_detect_batch(c, labels, out, W, bp, st);
+    } else {
+        prep.resize((size_t)nm);
+        s = run_on_workers(nm, st, [&](int q, hipStream_t ws) {
+            return edges_prepare(c, q, labels[q], out[q], prep[q], ws, false, true);
+        });
+        bp.total.resize((size_t)nm);
+        bp.nw.resize((size_t)nm);
+        bp.job.resize((size_t)nm);
+        for (int q = 0; q < nm; ++q) {
+            bp.total[q] = prep[q].total;
+            bp.nw[q] = prep[q].nw;
+            bp.job[q] = prep[q].job;
+        }
+    }
     if (s == ESES_OK && timed && hipEventRecord(c->ev[3], st) != hipSuccess) s = ESES_EDEVICE;
     if (s != ESES_OK) {
-        // the prepared workspace may still be in use on the worker streams
+        // the prepared workspace may still be in use on the streams
         (void)hipStreamSynchronize(st);
         release_all();
         return s;
     }
     std::vector<int> ord;
     for (int q = 0; q < nm; ++q)
-        if (prep[q].nw > 0) ord.push_back(q);
+        if (bp.nw[q] > 0) ord.push_back(q);
     std::stable_sort(ord.begin(), ord.end(),
-                     [&](int a, int b) { return prep[a].nw > prep[b].nw; });
+                     [&](int a, int b) { return bp.nw[a] > bp.nw[b]; });
     std::vector<EdgeJob> jobs;
-    for (int q : ord) jobs.push_back(prep[q].job);
+    for (int q : ord) jobs.push_back(bp.job[q]);
     const int nj = (int)jobs.size();
     Arena B;
     B.st = st;
@@ -1400,7 +1571,7 @@ eses_status edges_batch(eses_candidates *c, const uint8_t *const *labels,
                     "root explains", q, own[(size_t)q]);
             return ESES_EINTERNAL;
         }
-    for (int q = 0; q < nm; ++q) counts[q] = prep[q].total;
+    for (int q = 0; q < nm; ++q) counts[q] = bp.total[q];
     return ESES_OK;
 }
 
@@ -1585,6 +1756,7 @@ eses_status eses_build_candidates(const eses_molecule *mols, int32_t n_mols,
     if (n_mols > 1) {
         c->blocks_per_cu = cfg ? cfg->blocks_per_cu : 0;
         c->unit_order = cfg ? cfg->unit_order : 0;
+        c->edges_per_molecule = cfg ? cfg->edges_per_molecule : 0;
         eses_status s = build_batch(c, st);
         if (s != ESES_OK) {
             std::string msg = g_err;

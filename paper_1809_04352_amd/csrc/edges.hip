@@ -123,10 +123,11 @@ __device__ inline void edge_flags8(const uint8_t *L, long long idx0, int i, int 
     }
 }
 
-__global__ void __launch_bounds__(EDGE_BLOCK) k_edge_count(const uint8_t *L, int nx, int ny,
-                                                           int nz, long long npts, int *bcount) {
-    __shared__ int lds[EDGE_BLOCK / WAVE + 1];
-    const long long idx0 = ((long long)blockIdx.x * EDGE_BLOCK + threadIdx.x) * EDGE_PPT;
+// Crossing edges of detection block blk (EDGE_BLOCK x EDGE_PPT points from
+// blk's first) counted into bcount[blk].
+__device__ inline void edge_count_block(const uint8_t *L, int nx, int ny, int nz, long long npts,
+                                        long long blk, int *bcount, int *lds) {
+    const long long idx0 = (blk * EDGE_BLOCK + threadIdx.x) * EDGE_PPT;
     const bool words = ((uintptr_t)L & 7) == 0;
     int c = 0;
     if (idx0 < npts) {
@@ -138,21 +139,27 @@ __global__ void __launch_bounds__(EDGE_BLOCK) k_edge_count(const uint8_t *L, int
     }
     int tot;
     block_excl_scan<int, EDGE_BLOCK>(c, lds, &tot);
-    if (threadIdx.x == 0) bcount[blockIdx.x] = tot;
+    if (threadIdx.x == 0) bcount[blk] = tot;
 }
 
-// Also tallies the written edges per owning tile (tcount, zeroed before) and
+__global__ void __launch_bounds__(EDGE_BLOCK) k_edge_count(const uint8_t *L, int nx, int ny,
+                                                           int nz, long long npts, int *bcount) {
+    __shared__ int lds[EDGE_BLOCK / WAVE + 1];
+    edge_count_block(L, nx, ny, nz, npts, blockIdx.x, bcount, lds);
+}
+
+// Keys of detection block blk's crossing edges, from slot wblk on (those
+// below cap).  Also tallies the written edges per owning tile (tcount, zeroed
+// before) and
 // keeps each edge's rank among its tile's edges (rank[w]), so that grouping by
 // tile needs no further atomics.  A thread takes one tally per run of its
 // points in one tile; the runs of a tile's rows then meet its counter in lane
 // order, which keeps the ranks close to key order (chunks of nearby edges).
-__global__ void __launch_bounds__(EDGE_BLOCK) k_edge_write(const uint8_t *L, int nx, int ny,
-                                                           int nz, long long npts,
-                                                           const long long *boff, long long cap,
-                                                           long long *keys, int *tcount,
-                                                           int *rank, int T, int tdx, int tdy) {
-    __shared__ int lds[EDGE_BLOCK / WAVE + 1];
-    const long long idx0 = ((long long)blockIdx.x * EDGE_BLOCK + threadIdx.x) * EDGE_PPT;
+__device__ inline void edge_write_block(const uint8_t *L, int nx, int ny, int nz,
+                                        long long npts, long long blk, long long wblk,
+                                        long long cap, long long *keys, int *tcount, int *rank,
+                                        int T, int tdx, int tdy, int *lds) {
+    const long long idx0 = (blk * EDGE_BLOCK + threadIdx.x) * EDGE_PPT;
     const bool words = ((uintptr_t)L & 7) == 0;
     int fl[EDGE_PPT], tl[EDGE_PPT];
     int c = 0;
@@ -169,7 +176,7 @@ __global__ void __launch_bounds__(EDGE_BLOCK) k_edge_write(const uint8_t *L, int
         }
     }
     int tot;
-    long long w = boff[blockIdx.x] + block_excl_scan<int, EDGE_BLOCK>(c, lds, &tot);
+    long long w = wblk + block_excl_scan<int, EDGE_BLOCK>(c, lds, &tot);
     // the written edges of a run of points in one tile are consecutive in w
     int trun = -1, nrun = 0;
     long long wrun = 0;
@@ -202,6 +209,16 @@ __global__ void __launch_bounds__(EDGE_BLOCK) k_edge_write(const uint8_t *L, int
         const int r0 = atomicAdd(&tcount[trun], nrun);
         for (int e = 0; e < nrun; ++e) rank[wrun + e] = r0 + e;
     }
+}
+
+__global__ void __launch_bounds__(EDGE_BLOCK) k_edge_write(const uint8_t *L, int nx, int ny,
+                                                           int nz, long long npts,
+                                                           const long long *boff, long long cap,
+                                                           long long *keys, int *tcount,
+                                                           int *rank, int T, int tdx, int tdy) {
+    __shared__ int lds[EDGE_BLOCK / WAVE + 1];
+    edge_write_block(L, nx, ny, nz, npts, blockIdx.x, boff[blockIdx.x], cap, keys, tcount, rank,
+                     T, tdx, tdy, lds);
 }
 
 // ------------------------------------------------------------ root finding
@@ -1854,11 +1871,11 @@ __global__ void __launch_bounds__(EW_THREADS)
 // ------------------------------------------------ grouping by tile, launches
 
 // Chunks per tile, and the tiles with edges counted by class min(chunks,
-// EU_CLASSES) (in LDS, then one global add per class and block).
-__global__ void __launch_bounds__(256) k_edge_chunk_count(const int *tcount, int ntiles,
-                                                          int *ccount, int *units) {
-    __shared__ int cls[EU_CLASSES];
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// EU_CLASSES) (in LDS, then one global add per class and block); block blk
+// takes tiles from 256 blk on.
+__device__ inline void edge_chunk_count_block(const int *tcount, int ntiles, int *ccount,
+                                              int *units, int blk, int *cls) {
+    const int t = blk * 256 + threadIdx.x;
     if (threadIdx.x < EU_CLASSES) cls[threadIdx.x] = 0;
     __syncthreads();
     if (t < ntiles) {
@@ -1871,13 +1888,18 @@ __global__ void __launch_bounds__(256) k_edge_chunk_count(const int *tcount, int
         atomicAdd(&units[EU_CLASS + threadIdx.x], cls[threadIdx.x]);
 }
 
+__global__ void __launch_bounds__(256) k_edge_chunk_count(const int *tcount, int ntiles,
+                                                          int *ccount, int *units) {
+    __shared__ int cls[EU_CLASSES];
+    edge_chunk_count_block(tcount, ntiles, ccount, units, blockIdx.x, cls);
+}
+
 // The unit list: tiles with edges, classes of more chunks first.  A block
 // ranks its tiles per class in LDS and reserves each class's run with one
 // global add.
-__global__ void __launch_bounds__(256) k_edge_unit_order(const int *ccount, int ntiles,
-                                                         int *units) {
-    __shared__ int cls[EU_CLASSES], base[EU_CLASSES];
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void edge_unit_order_block(const int *ccount, int ntiles, int *units, int blk,
+                                             int *cls, int *base) {
+    const int t = blk * 256 + threadIdx.x;
     if (t == 0) {
         int tot = 0;
         for (int b = 0; b < EU_CLASSES; ++b) tot += units[EU_CLASS + b];
@@ -1903,12 +1925,152 @@ __global__ void __launch_bounds__(256) k_edge_unit_order(const int *ccount, int 
     if (b >= 0) units[EU_LIST + base[b] + r] = t;
 }
 
+__global__ void __launch_bounds__(256) k_edge_unit_order(const int *ccount, int ntiles,
+                                                         int *units) {
+    __shared__ int cls[EU_CLASSES], base[EU_CLASSES];
+    edge_unit_order_block(ccount, ntiles, units, blockIdx.x, cls, base);
+}
+
+__device__ inline void edge_tile_scatter_at(const Mol &m, const long long *keys, long long q,
+                                            const int *coff, const int *rank, int *order) {
+    const int t = edge_tile(m, keys[q]);
+    order[(long long)coff[t] * CH_EDGES + rank[q]] = (int)q;
+}
+
 __global__ void k_edge_tile_scatter(Mol m, const long long *keys, long long count,
                                     const int *coff, const int *rank, int *order) {
     long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (q >= count) return;
-    int t = edge_tile(m, keys[q]);
-    order[(long long)coff[t] * CH_EDGES + rank[q]] = (int)q;
+    if (q < count) edge_tile_scatter_at(m, keys, q, coff, rank, order);
+}
+
+// ------------------------------------- crossing edges of a batch, batched
+//
+// The passes above over every molecule of a batch at once: block b of a
+// batched pass works for molecule q with start[q] <= b < start[q + 1] (the
+// largest such q, so molecules with no blocks in the pass are skipped), as
+// that molecule's block b - start[q].
+
+__device__ inline int batch_mol_of(const int *start, int nm, int b) {
+    int lo = 0, hi = nm - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(EDGE_BLOCK) k_edge_count_batch(const Mol *mols,
+                                                                 const EdgeDetectJob *jobs,
+                                                                 const int *start, int nm) {
+    __shared__ int lds[EDGE_BLOCK / WAVE + 1];
+    const int q = batch_mol_of(start, nm, blockIdx.x);
+    const Mol &m = mols[q];
+    edge_count_block(jobs[q].L, m.dims[0], m.dims[1], m.dims[2], m.npts,
+                     (int)blockIdx.x - start[q], jobs[q].bcount, lds);
+}
+
+__global__ void __launch_bounds__(EDGE_BLOCK) k_edge_write_batch(const Mol *mols,
+                                                                 const EdgeDetectJob *jobs,
+                                                                 const int *start, int nm) {
+    __shared__ int lds[EDGE_BLOCK / WAVE + 1];
+    const int q = batch_mol_of(start, nm, blockIdx.x);
+    const Mol &m = mols[q];
+    const EdgeDetectJob &J = jobs[q];
+    const int blk = (int)blockIdx.x - start[q];
+    edge_write_block(J.L, m.dims[0], m.dims[1], m.dims[2], m.npts, blk, J.boff[blk], J.nw,
+                     J.keys, J.tcount, J.rank, m.tile, m.tdims[0], m.tdims[1], lds);
+}
+
+__global__ void __launch_bounds__(256) k_edge_chunk_count_batch(const Mol *mols,
+                                                                const EdgeDetectJob *jobs,
+                                                                const int *start, int nm) {
+    __shared__ int cls[EU_CLASSES];
+    const int q = batch_mol_of(start, nm, blockIdx.x);
+    const EdgeDetectJob &J = jobs[q];
+    edge_chunk_count_block(J.tcount, mols[q].ntiles, J.ccount, J.units,
+                           (int)blockIdx.x - start[q], cls);
+}
+
+__global__ void __launch_bounds__(256) k_edge_unit_order_batch(const Mol *mols,
+                                                               const EdgeDetectJob *jobs,
+                                                               const int *start, int nm) {
+    __shared__ int cls[EU_CLASSES], base[EU_CLASSES];
+    const int q = batch_mol_of(start, nm, blockIdx.x);
+    const EdgeDetectJob &J = jobs[q];
+    edge_unit_order_block(J.ccount, mols[q].ntiles, J.units, (int)blockIdx.x - start[q], cls,
+                          base);
+}
+
+__global__ void __launch_bounds__(256) k_edge_tile_scatter_batch(const Mol *mols,
+                                                                 const EdgeDetectJob *jobs,
+                                                                 const int *start, int nm) {
+    const int q = batch_mol_of(start, nm, blockIdx.x);
+    const EdgeDetectJob &J = jobs[q];
+    const long long e = ((long long)blockIdx.x - start[q]) * 256 + threadIdx.x;
+    if (e < J.nw) edge_tile_scatter_at(mols[q], J.keys, e, J.coff, J.rank, J.order);
+}
+
+// Diagnostic word k of every molecule of a batch set to v.
+__global__ void k_diag_set(const Mol *mols, int nm, int k, int v) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nm) mols[q].diag[k] = v;
+}
+
+static hipError_t batch_grid(const int *start_host, int nm, unsigned *nb) {
+    const long long n = start_host[nm];
+    if (n < 0 || n > 0x7fffffffLL) return hipErrorInvalidValue;
+    *nb = (unsigned)n;
+    return hipSuccess;
+}
+
+hipError_t launch_edge_detect_count_batch(const Mol *mols, const EdgeDetectJob *jobs,
+                                          const int *start, const int *start_host, int nm,
+                                          hipStream_t st) {
+    unsigned nb = 0;
+    hipError_t e = batch_grid(start_host, nm, &nb);
+    if (e != hipSuccess || nb == 0) return e;
+    hipLaunchKernelGGL(k_edge_count_batch, dim3(nb), dim3(EDGE_BLOCK), 0, st, mols, jobs, start,
+                       nm);
+    return hipGetLastError();
+}
+
+hipError_t launch_edge_detect_write_batch(const Mol *mols, const EdgeDetectJob *jobs,
+                                          const EdgeBatchStarts &s, int nm, hipStream_t st) {
+    unsigned nb = 0;
+    hipError_t e = hipSuccess;
+    if (nm > 0) e = launch_diag_set(mols, nm, 3, 0, st);  // ownerless records
+    if (e == hipSuccess) e = batch_grid(s.write_host, nm, &nb);
+    if (e != hipSuccess || nb == 0) return e;
+    hipLaunchKernelGGL(k_edge_write_batch, dim3(nb), dim3(EDGE_BLOCK), 0, st, mols, jobs, s.write,
+                       nm);
+    return hipGetLastError();
+}
+
+hipError_t launch_edge_group_batch(const Mol *mols, const EdgeDetectJob *jobs,
+                                   const EdgeBatchStarts &s, const ScanSeg *coff_scan,
+                                   int nscan, long long nchunks, int *sums, int nm,
+                                   hipStream_t st) {
+    unsigned nt = 0, ne = 0;
+    hipError_t e = batch_grid(s.tile_host, nm, &nt);
+    if (e == hipSuccess) e = batch_grid(s.edge_host, nm, &ne);
+    if (e != hipSuccess || nt == 0) return e;
+    hipLaunchKernelGGL(k_edge_chunk_count_batch, dim3(nt), dim3(256), 0, st, mols, jobs, s.tile,
+                       nm);
+    e = scan_seg(coff_scan, nscan, nchunks, sums, st);
+    if (e != hipSuccess) return e;
+    if (ne > 0)
+        hipLaunchKernelGGL(k_edge_tile_scatter_batch, dim3(ne), dim3(256), 0, st, mols, jobs,
+                           s.edge, nm);
+    hipLaunchKernelGGL(k_edge_unit_order_batch, dim3(nt), dim3(256), 0, st, mols, jobs, s.tile,
+                       nm);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_set(const Mol *mols, int nm, int k, int v, hipStream_t st) {
+    if (nm <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_diag_set, dim3((nm + 255) / 256), dim3(256), 0, st, mols, nm, k, v);
+    return hipGetLastError();
 }
 
 long long edge_order_capacity(const Mol &m, long long count) {

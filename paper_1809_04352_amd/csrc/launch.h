@@ -164,6 +164,41 @@ hipError_t launch_slab_keys(long long *keys, long long count, long long limit, l
 hipError_t launch_edge_group(const Mol &m, const long long *keys, long long count, int *tcount,
                              int *ccount, int *coff, const int *rank, int *order, int *units,
                              int *tmp, hipStream_t st);
+// The crossing-edge passes over every molecule of a batch in one launch each.
+// Per molecule: its labels; bcount/boff: per detection block (of
+// edge_detect_blocks) counts and their exclusive scan (boff[nblk] = the
+// total); nw: the edges written (the total, at most the output capacity);
+// the rest as for launch_edge_detect_write and launch_edge_group, tcount and
+// the units header zeroed before the write pass.
+struct EdgeDetectJob {
+    const uint8_t *L;
+    int *bcount, *boff;
+    long long *keys;
+    int *tcount, *ccount, *coff, *rank, *order, *units;
+    long long nw;
+};
+// Block starts (nm + 1 prefix sums, device and host copies) of the write
+// pass (detection blocks of the molecules with nw > 0), the tile passes (256
+// tiles a block) and the edge pass (256 edges a block).
+struct EdgeBatchStarts {
+    const int *write, *tile, *edge;
+    const int *write_host, *tile_host, *edge_host;
+};
+// start: block starts of the count pass (every molecule's detection blocks).
+hipError_t launch_edge_detect_count_batch(const Mol *mols, const EdgeDetectJob *jobs,
+                                          const int *start, const int *start_host, int nm,
+                                          hipStream_t st);
+// (also zeroes every molecule's ownerless-record counter, Mol::diag[3])
+hipError_t launch_edge_detect_write_batch(const Mol *mols, const EdgeDetectJob *jobs,
+                                          const EdgeBatchStarts &s, int nm, hipStream_t st);
+// coff_scan: the scans of ccount into coff of the molecules with nw > 0
+// (scan_seg layout; sums: nchunks ints of workspace).
+hipError_t launch_edge_group_batch(const Mol *mols, const EdgeDetectJob *jobs,
+                                   const EdgeBatchStarts &s, const ScanSeg *coff_scan,
+                                   int nscan, long long nchunks, int *sums, int nm,
+                                   hipStream_t st);
+// Diagnostic word k (Mol::diag) of every molecule of a batch set to v.
+hipError_t launch_diag_set(const Mol *mols, int nm, int k, int v, hipStream_t st);
 // fallback: count ints; nfallback, overflow: one int each (overflow is set,
 // not cleared).
 hipError_t launch_edge_roots(const Mol &m, const uint8_t *L, const long long *keys,

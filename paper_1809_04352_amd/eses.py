@@ -55,7 +55,8 @@ class Config(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("force_recheck", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("edge_fallback", ctypes.c_int32),
                 ("vertex_pool", ctypes.c_int32), ("tile_pool", ctypes.c_int32),
-                ("unc_queue", ctypes.c_int32), ("unit_order", ctypes.c_int32)]
+                ("unc_queue", ctypes.c_int32), ("unit_order", ctypes.c_int32),
+                ("edges_per_molecule", ctypes.c_int32)]
 
 
 class CandidateStats(ctypes.Structure):
@@ -226,7 +227,8 @@ class Candidates:
 
     def __init__(self, mols, tile: int = 0, stream=None, force_recheck: bool = False,
                  blocks_per_cu: int = 0, edge_fallback: bool = False, vertex_pool: int = 0,
-                 tile_pool: int = 0, unc_queue: int = 0, unit_order: int = 0):
+                 tile_pool: int = 0, unc_queue: int = 0, unit_order: int = 0,
+                 edges_per_molecule: bool = False):
         lib = load()
         self.mols = list(mols)
         arr = (Molecule * len(self.mols))(*self.mols)
@@ -239,6 +241,7 @@ class Candidates:
         cfg.tile_pool = int(tile_pool)
         cfg.unc_queue = int(unc_queue)
         cfg.unit_order = int(unit_order)
+        cfg.edges_per_molecule = 1 if edges_per_molecule else 0
         h = ctypes.c_void_p()
         self.stream = _stream_ptr(stream)
         _check(lib.eses_build_candidates(arr, len(self.mols), ctypes.byref(cfg), self.stream,
@@ -265,9 +268,10 @@ class Candidates:
 def build_candidates(mols, tile: int = 0, stream=None, force_recheck: bool = False,
                      blocks_per_cu: int = 0, edge_fallback: bool = False,
                      vertex_pool: int = 0, tile_pool: int = 0,
-                     unc_queue: int = 0, unit_order: int = 0) -> Candidates:
+                     unc_queue: int = 0, unit_order: int = 0,
+                     edges_per_molecule: bool = False) -> Candidates:
     return Candidates(mols, tile, stream, force_recheck, blocks_per_cu, edge_fallback,
-                      vertex_pool, tile_pool, unc_queue, unit_order)
+                      vertex_pool, tile_pool, unc_queue, unit_order, edges_per_molecule)
 
 
 def copy_vertices(cand: Candidates, mol: int, p_dev, atoms_dev, sign_dev, stream=None) -> int:

@@ -19,14 +19,15 @@ def E():
     return eses
 
 
-def run_batch(E, mols_np, prec, reps=2, blocks_per_cu=0, tile=0, unit_order=0):
+def run_batch(E, mols_np, prec, reps=2, blocks_per_cu=0, tile=0, unit_order=0,
+              edges_per_molecule=False, partial=False):
     import torch
     tens = [(torch.as_tensor(m.centres, device="cuda"), torch.as_tensor(m.radii, device="cuda"))
             for m in mols_np]
     mols = [E.make_molecule(c, r, m.probe, m.spacing, m.lo, m.hi)
             for (c, r), m in zip(tens, mols_np)]
     cand = E.build_candidates(mols, tile=tile, blocks_per_cu=blocks_per_cu,
-                              unit_order=unit_order)
+                              unit_order=unit_order, edges_per_molecule=edges_per_molecule)
     dims = [E.grid_dims(m) for m in mols]
     out = []
     for rep in range(reps):
@@ -43,9 +44,22 @@ def run_batch(E, mols_np, prec, reps=2, blocks_per_cu=0, tile=0, unit_order=0):
     edges = []
     isect = [E.alloc_isect(1) for _ in mols]
     st, counts = E.edge_intersections(cand, labels, isect)
-    isect = [E.alloc_isect(max(k, 1)) for k in counts]
-    st, counts = E.edge_intersections(cand, labels, isect)
-    assert st == E.ESES_OK
+    if partial:
+        # every molecule's output a third of what it needs (one molecule none):
+        # the counts are complete, the records written are the first ones
+        caps = [k // 3 for k in counts]
+        caps[0] = 0
+        full = counts
+        isect = [E.alloc_isect(max(k, 1)) for k in caps]
+        isect = [E.IsectBuffers(o.key[:k], o.lam[:k], o.normal[:k], o.patch_type[:k],
+                                o.atoms[:k]) for o, k in zip(isect, caps)]
+        st, counts = E.edge_intersections(cand, labels, isect)
+        assert st == E.ESES_ECAPACITY and list(counts) == list(full)
+        counts = caps
+    else:
+        isect = [E.alloc_isect(max(k, 1)) for k in counts]
+        st, counts = E.edge_intersections(cand, labels, isect)
+        assert st == E.ESES_OK
     torch.cuda.synchronize()
     for o, k in zip(isect, counts):
         edges.append(dict(key=o.key[:k].cpu().numpy(), lam=o.lam[:k].cpu().numpy(),
@@ -100,19 +114,24 @@ def test_batch_with_empty_surfaces(E, oracle_mod):
 
 
 def test_launch_knobs_do_not_change_results(E):
-    """Unit order, workgroups per CU and tile edge change the launch only:
-    labels and records equal those of the default configuration."""
+    """Unit order, workgroups per CU, tile edge and the per-molecule
+    crossing-edge passes change the launch only: labels and records equal
+    those of the default configuration; with outputs too small, the counts
+    are complete and the records written are the first ones."""
     from eses_inputs import molecule
     mols = [molecule(n, 60 + n, h) for n, h in ((150, 0.5), (700, 0.4), (40, 0.3))]
     base_l, base_e = run_batch(E, mols, 1, reps=1)
-    for knobs in (dict(unit_order=1), dict(blocks_per_cu=2), dict(tile=4, unit_order=1)):
+    for knobs in (dict(unit_order=1), dict(blocks_per_cu=2), dict(tile=4, unit_order=1),
+                  dict(edges_per_molecule=True), dict(partial=True),
+                  dict(partial=True, edges_per_molecule=True)):
         print("case: knobs", knobs, flush=True)
         lab, ed = run_batch(E, mols, 1, reps=2, **knobs)
         for a, b in zip(base_l, lab):
             assert np.array_equal(a, b)
         for a, b in zip(base_e, ed):
             for k in a:
-                assert np.array_equal(a[k], b[k]), k
+                assert np.array_equal(a[k][:len(b[k])], b[k]), k
+                assert knobs.get("partial") or len(a[k]) == len(b[k]), k
 
 
 def test_autotune(E, tmp_path, monkeypatch):
