@@ -223,30 +223,35 @@ __global__ void __launch_bounds__(EDGE_BLOCK) k_edge_write(const uint8_t *L, int
 
 // ------------------------------------------------------------ root finding
 
-__device__ inline double horner(const double *c, int deg, double u) {
-    double v = c[deg];
-    for (int q = deg - 1; q >= 0; --q) v = v * u + c[q];
+// The polynomial c of degree DEG (ascending coefficients) at u.  The degree
+// is a template argument so that the coefficients stay in registers.
+template <int DEG>
+__device__ inline double horner(const double (&c)[DEG + 1], double u) {
+    double v = c[DEG];
+#pragma unroll
+    for (int q = DEG - 1; q >= 0; --q) v = v * u + c[q];
     return v;
 }
 
-// Root of the polynomial c (degree deg) in [lo, hi] where its values at the
+// Root of the polynomial c (degree DEG) in [lo, hi] where its values at the
 // ends (flo, fhi) have opposite signs: from the secant point of the ends,
 // Newton steps kept inside a shrinking bracket, bisection when a step leaves
 // it.
-template <bool CNT>
-__device__ double bracket_root(const double *c, int deg, double lo, double hi, double flo,
+template <bool CNT, int DEG>
+__device__ double bracket_root(const double (&c)[DEG + 1], double lo, double hi, double flo,
                                double fhi, unsigned long long *cnt) {
-    double d[4];
-    for (int q = 1; q <= deg; ++q) d[q - 1] = q * c[q];
+    double d[DEG];
+#pragma unroll
+    for (int q = 1; q <= DEG; ++q) d[q - 1] = q * c[q];
     double x = lo + (hi - lo) * (flo / (flo - fhi));
     if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
     for (int it = 0; it < 128; ++it) {
-        if (CNT) cnt[EC_HORNER_FLOPS] += 4 * deg + 4;  // f, f' and the step
-        double f = horner(c, deg, x);
+        if (CNT) cnt[EC_HORNER_FLOPS] += 4 * DEG + 4;  // f, f' and the step
+        double f = horner<DEG>(c, x);
         if (f == 0.0) return x;
         if ((f < 0.0) == (flo < 0.0)) lo = x;
         else hi = x;
-        double df = horner(d, deg - 1, x);
+        double df = horner<DEG - 1>(d, x);
         double xn = x - f / df;
         if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
         if (fabs(xn - x) <= 1e-17 || hi - lo <= 2e-16) return xn;
@@ -264,21 +269,22 @@ constexpr double END_SLACK = 1e-9;
 
 __device__ inline double clamp01(double u) { return fmin(1.0, fmax(0.0, u)); }
 
-__device__ inline int quad01(double a, double b, double c, double *r) {
+__device__ inline int quad01(double a, double b, double c, double &ra, double &rb) {
     double disc = b * b - 4.0 * a * c;
     if (disc < 0.0) return 0;
     double sd = sqrt(disc);
     double q = -0.5 * (b + copysign(sd, b));
     double r1 = q / a;
     double r2 = q != 0.0 ? c / q : r1;
-    int n = 0;
     const bool in1 = r1 >= -END_SLACK && r1 <= 1.0 + END_SLACK;
     const bool in2 = r2 >= -END_SLACK && r2 <= 1.0 + END_SLACK;
     r1 = clamp01(r1);
     r2 = clamp01(r2);
-    if (in1) r[n++] = r1;
-    if (in2 && !(in1 && r2 == r1)) r[n++] = r2;
-    return n;
+    const bool two = in2 && !(in1 && r2 == r1);
+    // the roots in order of (r1, r2), the kept ones first
+    ra = in1 ? r1 : r2;
+    rb = r2;
+    return (in1 ? 1 : 0) + (two ? 1 : 0);
 }
 
 // Real roots in [0, 1] of the quartic g (ascending coefficients), passed to
@@ -288,7 +294,7 @@ __device__ inline int quad01(double a, double b, double c, double *r) {
 // refined by bracket_root.  Both stages run in one loop, without lists, so
 // that each refinement is a single call site.
 template <bool CNT, class Emit>
-__device__ void quartic01(const double *g, Emit emit, unsigned long long *cnt) {
+__device__ void quartic01(const double (&g)[5], Emit emit, unsigned long long *cnt) {
     // interior roots of g'' (sorted), 1.0 standing in for a missing one
     double x1 = 1.0, x2 = 1.0;
     {
@@ -322,7 +328,7 @@ __device__ void quartic01(const double *g, Emit emit, unsigned long long *cnt) {
     const double tol =
         1e-12 * (fabs(g[0]) + fabs(g[1]) + fabs(g[2]) + fabs(g[3]) + fabs(g[4]));
     double ca = 0.0;                 // last critical point of g (or 0)
-    double fca = horner(g, 4, 0.0);  // g there
+    double fca = horner<4>(g, 0.0);  // g there
     // g vanishing at an end to within rounding: a root at that end (the
     // segment starts or ends on the torus)
     if (fabs(fca) <= tol) emit(0.0);
@@ -336,23 +342,23 @@ __device__ void quartic01(const double *g, Emit emit, unsigned long long *cnt) {
             double b = q == 0 ? x1 : q == 1 ? x2 : 1.0;
             have = false;
             if (b > a) {
-                double fa = horner(d1, 3, a), fb = horner(d1, 3, b);
+                double fa = horner<3>(d1, a), fb = horner<3>(d1, b);
                 if (CNT) cnt[EC_HORNER_FLOPS] += 12;
                 if (fa == 0.0 && a > 0.0) {
                     cp = a;
                     have = true;
                 } else if (fa != 0.0 && fb != 0.0 && ((fa < 0.0) != (fb < 0.0))) {
-                    cp = bracket_root<CNT>(d1, 3, a, b, fa, fb, cnt);
+                    cp = bracket_root<CNT, 3>(d1, a, b, fa, fb, cnt);
                     have = true;
                 }
             }
         }
         if (!have || !(cp > ca)) continue;
-        double fb = horner(g, 4, cp);
+        double fb = horner<4>(g, cp);
         if (CNT) cnt[EC_HORNER_FLOPS] += 16;
         if (fb == 0.0) emit(cp);
         else if (fca != 0.0 && ((fca < 0.0) != (fb < 0.0)))
-            emit(bracket_root<CNT>(g, 4, ca, cp, fca, fb, cnt));
+            emit(bracket_root<CNT, 4>(g, ca, cp, fca, fb, cnt));
         if (fb != 0.0 && fabs(fb) <= tol) emit(cp);
         ca = cp;
         fca = fb;
@@ -511,10 +517,10 @@ __device__ void surface_roots(int type, const SurfParams &p, double h, double rh
     if (type != 2) {
         if (CNT) ++cnt[EC_QUAD];
         double r = p.c.w;
-        double tmp[2];
-        int n = quad01(h * h, 2.0 * h * we, ww - r * r, tmp);
-        if (n > 0) sink(tmp[0]);
-        if (n > 1) sink(tmp[1]);
+        double ra, rb;
+        int n = quad01(h * h, 2.0 * h * we, ww - r * r, ra, rb);
+        if (n > 0) sink(ra);
+        if (n > 1) sink(rb);
         return;
     }
     const double4 nn = p.n;
@@ -557,18 +563,16 @@ __device__ bool root_admissible(const Mol &m, int key, const SurfParams &p, Pass
 // returned array (none for probes).
 __device__ inline const double4 *global_cuts(const Mol &m, int key, int *cb, int *ce) {
     const int type = key >> 28, id = key & ((1 << 28) - 1);
-    if (type == 1) {
-        *cb = m.face_cut_off[id];
-        *ce = m.face_cut_off[id + 1];
-        return m.face_cut;
-    }
-    if (type == 2) {
-        *cb = m.ec_cut_off[id];
-        *ce = m.ec_cut_off[id + 1];
-        return m.ec_cut;
+    const int *fo = m.face_cut_off, *eo = m.ec_cut_off;
+    const double4 *fc = m.face_cut, *ec = m.ec_cut;
+    if (type == 1 || type == 2) {
+        const int *o = type == 1 ? fo : eo;
+        *cb = o[id];
+        *ce = o[id + 1];
+        return type == 1 ? fc : ec;
     }
     *cb = *ce = 0;
-    return m.face_cut;
+    return fc;
 }
 
 // Position and end labels of crossing edge `key` (3 * point index + axis).
@@ -726,13 +730,26 @@ __device__ inline int tile_surfaces(const Mol &m, int t) {
            (m.tC_off[t + 1] - m.tC_off[t]);
 }
 
+// (The lists' pointers are read before the branches, so that a per-thread
+// choice selects among their values rather than among fields of m.)
 __device__ inline int tile_surface_key(const Mol &m, int t, int s) {
-    int nf = m.tF_off[t + 1] - m.tF_off[t];
-    if (s < nf) return (1 << 28) | m.tF[m.tF_off[t] + s];
-    s -= nf;
-    int nv = m.tV_off[t + 1] - m.tV_off[t];
-    if (s < nv) return (3 << 28) | m.tV[m.tV_off[t] + s];
-    return (2 << 28) | m.tC[m.tC_off[t] + s - nv];
+    const int *tF = m.tF, *tV = m.tV, *tC = m.tC;
+    const int f0 = m.tF_off[t], nf = m.tF_off[t + 1] - f0;
+    const int v0 = m.tV_off[t], nv = m.tV_off[t + 1] - v0;
+    const int c0 = m.tC_off[t];
+    const int *p;
+    int tag;
+    if (s < nf) {
+        p = tF + f0 + s;
+        tag = 1;
+    } else if (s < nf + nv) {
+        p = tV + v0 + (s - nf);
+        tag = 3;
+    } else {
+        p = tC + c0 + (s - nf - nv);
+        tag = 2;
+    }
+    return (tag << 28) | *p;
 }
 
 // ------------------------------------------------ roots, chunks of one tile
