@@ -568,7 +568,7 @@ class Builder {
         size_t off = 0;
         int *sums = nullptr;
         void add(const int *in, int *out, long long n) {
-            segs.push_back({in, out, n, chunks});
+            segs.push_back({dev(in), dev(out), n, chunks});
             chunks += (n + scan_seg_chunk() - 1) / scan_seg_chunk();
         }
     };
@@ -617,8 +617,8 @@ class Builder {
                 m.dims[a] = dims[a];
             }
             m.npts = (long long)dims[0] * dims[1] * dims[2];
-            m.in_c = in->centers;
-            m.in_r = in->radii;
+            m.in_c = dev(in->centers);
+            m.in_r = dev(in->radii);
             m.tile = tile;
             m.force_recheck = force_recheck ? 1 : 0;
             m.edge_fallback = edge_fallback ? 1 : 0;
@@ -637,8 +637,8 @@ class Builder {
         Planner Z;  // persistent, zeroed
         for (int q = 0; q < nm_; ++q) {
             B[q] = BuildTmp{};
-            B[q].bounds = bnd + 8 * q;
-            B[q].bad = bad + q;
+            B[q].bounds = dev(bnd + 8 * q);
+            B[q].bad = dev(bad + q);
             Z.add(&M[q].diag, 4);
             Z.add(&M[q].unc_n, 1);
         }
@@ -1246,18 +1246,18 @@ eses_status edges_prepare(eses_candidates *c, size_t q, const uint8_t *lab,
         set_err("edge intersections: %s", hipGetErrorString(e));
         return ESES_EDEVICE;
     }
-    J.L = lab;
-    J.keys = (const long long *)o.key;
-    J.order = order;
-    J.tcount = tcount;
-    J.coff = coff;
-    J.units = units;
-    J.lam = o.lambda;
-    J.nrm = o.normal;
-    J.ptype = o.patch_type;
-    J.patoms = o.atoms;
-    J.fallback = fb;
-    J.nfallback = nfb;
+    J.L = dev(lab);
+    J.keys = dev((const long long *)o.key);
+    J.order = dev(order);
+    J.tcount = dev(tcount);
+    J.coff = dev(coff);
+    J.units = dev(units);
+    J.lam = dev(o.lambda);
+    J.nrm = dev(o.normal);
+    J.ptype = dev(o.patch_type);
+    J.patoms = dev(o.atoms);
+    J.fallback = dev(fb);
+    J.nfallback = dev(nfb);
     J.mol = (int)q;
     return ESES_OK;
 }
@@ -1360,7 +1360,7 @@ eses_status edges_detect_batch(eses_candidates *c, const uint8_t *const *labels,
         c1[q] = nch1;
         nch1 += (nblk[q] + chunk - 1) / chunk;
         J[q] = EdgeDetectJob{};
-        J[q].L = labels[q];
+        J[q].L = dev(labels[q]);
         A.add(&J[q].bcount, nblk[q]);
         A.add(&J[q].boff, nblk[q] + 1);
     }
@@ -1404,7 +1404,7 @@ eses_status edges_detect_batch(eses_candidates *c, const uint8_t *const *labels,
         const Mol &m = c->mols[q]->m;
         P.total[q] = htot[q];
         const long long w = P.nw[q] = std::min<long long>(P.total[q], out[q].capacity);
-        J[q].keys = (long long *)out[q].key;
+        J[q].keys = dev((long long *)out[q].key);
         J[q].nw = w;
         sw[q + 1] = sw[q] + (w > 0 ? (int)nblk[q] : 0);
         stl[q + 1] = stl[q] + (w > 0 ? (m.ntiles + 255) / 256 : 0);
@@ -1447,18 +1447,18 @@ eses_status edges_detect_batch(eses_candidates *c, const uint8_t *const *labels,
     for (int q = 0; q < nm; ++q) {
         if (P.nw[q] <= 0) continue;
         EdgeJob &E = P.job[q];
-        E.L = labels[q];
+        E.L = dev(labels[q]);
         E.keys = J[q].keys;
         E.order = J[q].order;
         E.tcount = J[q].tcount;
         E.coff = J[q].coff;
         E.units = J[q].units;
-        E.lam = out[q].lambda;
-        E.nrm = out[q].normal;
-        E.ptype = out[q].patch_type;
-        E.patoms = out[q].atoms;
-        E.fallback = fb[q];
-        E.nfallback = nfb[q];
+        E.lam = dev(out[q].lambda);
+        E.nrm = dev(out[q].normal);
+        E.ptype = dev(out[q].patch_type);
+        E.patoms = dev(out[q].atoms);
+        E.fallback = dev(fb[q]);
+        E.nfallback = dev(nfb[q]);
         E.mol = q;
     }
     return ESES_OK;

@@ -125,7 +125,7 @@ __device__ inline void edge_flags8(const uint8_t *L, long long idx0, int i, int 
 
 // Crossing edges of detection block blk (EDGE_BLOCK x EDGE_PPT points from
 // blk's first) counted into bcount[blk].
-__device__ inline void edge_count_block(const uint8_t *L, int nx, int ny, int nz, long long npts,
+__device__ __attribute__((always_inline)) inline void edge_count_block(const uint8_t *L, int nx, int ny, int nz, long long npts,
                                         long long blk, int *bcount, int *lds) {
     const long long idx0 = (blk * EDGE_BLOCK + threadIdx.x) * EDGE_PPT;
     const bool words = ((uintptr_t)L & 7) == 0;
@@ -155,7 +155,7 @@ __global__ void __launch_bounds__(EDGE_BLOCK) k_edge_count(const uint8_t *L, int
 // tile needs no further atomics.  A thread takes one tally per run of its
 // points in one tile; the runs of a tile's rows then meet its counter in lane
 // order, which keeps the ranks close to key order (chunks of nearby edges).
-__device__ inline void edge_write_block(const uint8_t *L, int nx, int ny, int nz,
+__device__ __attribute__((always_inline)) inline void edge_write_block(const uint8_t *L, int nx, int ny, int nz,
                                         long long npts, long long blk, long long wblk,
                                         long long cap, long long *keys, int *tcount, int *rank,
                                         int T, int tdx, int tdy, int *lds) {

@@ -30,6 +30,27 @@ constexpr uint32_t CF_EXPOSED = CF_EXPOSED_VERTEX | CF_EXPOSED_FREE;
 // listing too much never changes a result, only the decisions below do.
 constexpr double LIST_SLACK = 1e-7;
 
+// Pointers into device memory.  In device code they carry the global address
+// space, so that loads through them are global loads, which the compiler may
+// reorder with LDS accesses and which do not wait on the LDS counter, rather
+// than generic (flat) ones, which may alias LDS.  Host code sees plain
+// pointers (the layout is the same).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GMEM __attribute__((address_space(1)))
+#else
+#define GMEM
+#endif
+
+// A device address stored into such a field from host code: dev(p).
+template <typename T>
+struct DevAddr {
+    T *p;
+    template <typename U>
+    operator U *() const { return (U *)p; }
+};
+template <typename T>
+inline DevAddr<T> dev(T *p) { return DevAddr<T>{p}; }
+
 // Device view of one molecule.  Plain pointers and scalars, passed by value.
 struct Mol {
     int n;              // atoms
@@ -52,63 +73,63 @@ struct Mol {
     int kz0;             // z index of plane 0 in the molecule's whole grid: 0, or the
                          // first plane of a slab view (out-of-core form)
 
-    int *diag;           // [4] diagnostics: [0] fill-pass overflows, [1] FP32 points
+    GMEM int *diag;           // [4] diagnostics: [0] fill-pass overflows, [1] FP32 points
                          // re-tested in FP64, [2] shared centres, [3] crossing
                          // edges whose walk found no owning surface
     double cmag;         // max |coordinate| of any centre, plus s_max: the scale of
                          // the rounding error of positions derived from centres
     // points whose FP64 decision could not be certified (re-decided exactly
     // on the host): grid indices, their count (may exceed the capacity)
-    long long *unc_idx;
-    int *unc_n;
+    GMEM long long *unc_idx;
+    GMEM int *unc_n;
     int unc_cap;
 
-    const double *in_c;  // caller centres [n][3]
-    const double *in_r;  // caller radii [n]
+    GMEM const double *in_c;  // caller centres [n][3]
+    GMEM const double *in_r;  // caller radii [n]
 
-    double4 *atom;       // internal order: x, y, z, r
-    int *orig;           // internal id -> caller id
-    int *cell_start;     // [ncell + 1]
+    GMEM double4 *atom;       // internal order: x, y, z, r
+    GMEM int *orig;           // internal id -> caller id
+    GMEM int *cell_start;     // [ncell + 1]
 
-    int *nbr_off;        // [n + 1]
-    int *nbr;            // internal ids, ascending per atom
-    int *nbr_cov;        // the same lists, largest cap cut from S_i first
-    int *circ_any;       // [n] circles on S_i (either owner)
-    uint32_t *aflag;     // [n]
+    GMEM int *nbr_off;        // [n + 1]
+    GMEM int *nbr;            // internal ids, ascending per atom
+    GMEM int *nbr_cov;        // the same lists, largest cap cut from S_i first
+    GMEM int *circ_any;       // [n] circles on S_i (either owner)
+    GMEM uint32_t *aflag;     // [n]
 
     int ncirc;
-    int *circ_off;       // [n + 1] circles owned by atom i (partner > i)
-    int *circ_i;         // [ncirc] owner
-    int *circ_j;         // [ncirc] partner, ascending per owner
-    double4 *circ_oR;    // [ncirc] centre o, radius R
-    double4 *circ_n;     // [ncirc] unit axis n (owner -> partner); w: a bound on the
+    GMEM int *circ_off;       // [n + 1] circles owned by atom i (partner > i)
+    GMEM int *circ_i;         // [ncirc] owner
+    GMEM int *circ_j;         // [ncirc] partner, ascending per owner
+    GMEM double4 *circ_oR;    // [ncirc] centre o, radius R
+    GMEM double4 *circ_n;     // [ncirc] unit axis n (owner -> partner); w: a bound on the
                          // rounding error of o's components and of R
-    uint32_t *cflag;     // [ncirc]
+    GMEM uint32_t *cflag;     // [ncirc]
 
     int nvert;
-    int *vert_off;       // [ncirc + 1]
-    double4 *vert_p;     // [nvert] position; w: a bound on its rounding error
-    int4 *vert_ijks;     // [nvert] internal i < j < k, sign (+1/-1, internal order)
-    int *vert_off_atom;  // [n + 1]
+    GMEM int *vert_off;       // [ncirc + 1]
+    GMEM double4 *vert_p;     // [nvert] position; w: a bound on its rounding error
+    GMEM int4 *vert_ijks;     // [nvert] internal i < j < k, sign (+1/-1, internal order)
+    GMEM int *vert_off_atom;  // [n + 1]
 
     int nface;
-    int *face_off_atom;  // [n + 1]
-    int *face_atom;      // [nface]
-    int *face_cut_off;   // [nface + 1]
-    double4 *face_cut;   // (c_k - c_i, tau_ik), tau = (s_i^2 + d^2 - s_k^2) / (2 s_i)
+    GMEM int *face_off_atom;  // [n + 1]
+    GMEM int *face_atom;      // [nface]
+    GMEM int *face_cut_off;   // [nface + 1]
+    GMEM double4 *face_cut;   // (c_k - c_i, tau_ik), tau = (s_i^2 + d^2 - s_k^2) / (2 s_i)
 
     int nec;
-    int *ec_off_atom;    // [n + 1]
-    int *ec_circ;        // [nec] circle id
-    int *ec_cut_off;     // [nec + 1]
-    double4 *ec_cut;     // (u_perp, T_k), u_perp = in-plane part of c_k - o,
+    GMEM int *ec_off_atom;    // [n + 1]
+    GMEM int *ec_circ;        // [nec] circle id
+    GMEM int *ec_cut_off;     // [nec + 1]
+    GMEM double4 *ec_cut;     // (u_perp, T_k), u_perp = in-plane part of c_k - o,
                          // T_k = (R^2 + |o - c_k|^2 - s_k^2) / (2 R)
 
     // per-tile candidate lists (CSR over tiles)
-    int *tA_off, *tA;    // atoms whose SAS ball reaches the tile box
-    int *tF_off, *tF;    // exposed faces within s_i + rho
-    int *tC_off, *tC;    // exposed circles within rho
-    int *tV_off, *tV;    // exposed vertices within rho
+    GMEM int *tA_off, *tA;    // atoms whose SAS ball reaches the tile box
+    GMEM int *tF_off, *tF;    // exposed faces within s_i + rho
+    GMEM int *tC_off, *tC;    // exposed circles within rho
+    GMEM int *tV_off, *tV;    // exposed vertices within rho
 };
 
 // Grid point coordinate fl(lo + fl(i h)): two correctly rounded operations,

@@ -34,9 +34,9 @@ hipError_t fill_u32(uint32_t *p, long long n, uint32_t v, hipStream_t st);
 // the fill pass (use = 1) skips those atoms; launch_vertex_order then puts
 // every circle's positions in the fill pass's order.
 struct VertexPool {
-    double4 *p;
-    int4 *id;
-    int *count;
+    GMEM double4 *p;
+    GMEM int4 *id;
+    GMEM int *count;
     int cap;
     int use;
 };
@@ -47,7 +47,7 @@ struct VertexPool {
 // they do not fit (then *unpooled, zeroed before, is set and the fill pass
 // rebuilds that tile).
 struct TilePool {
-    int *pool, *off, *unpooled;
+    GMEM int *pool, *off, *unpooled;
     int cap;
 };
 int tile_keep_max();
@@ -56,16 +56,16 @@ int tile_keep_max();
 // tp_unpooled are set by the host from read-backs before the kernels that
 // use them).
 struct BuildTmp {
-    double *bounds;       // [8]: centre bounds (lo, hi), largest radius
-    int *bad;             // non-finite or non-positive input
-    int *cell_id, *cnt, *fillb, *slot;
-    int *nbr_cnt, *circ_cnt;
-    int *vcnt;            // [ncirc] probe positions per circle
+    GMEM double *bounds;       // [8]: centre bounds (lo, hi), largest radius
+    GMEM int *bad;             // non-finite or non-positive input
+    GMEM int *cell_id, *cnt, *fillb, *slot;
+    GMEM int *nbr_cnt, *circ_cnt;
+    GMEM int *vcnt;            // [ncirc] probe positions per circle
     VertexPool pool;
     int npool;            // positions the count pass pooled
-    int *face_cnt, *ecf, *ec_pos;
-    int *fcut_cnt, *eccut_cnt;
-    int *cA, *cF, *cC, *cV;  // per-tile list lengths
+    GMEM int *face_cnt, *ecf, *ec_pos;
+    GMEM int *fcut_cnt, *eccut_cnt;
+    GMEM int *cA, *cF, *cC, *cV;  // per-tile list lengths
     TilePool tp;
     int tp_unpooled;      // some tile's lists did not fit its pool slot
     int pad;
@@ -101,8 +101,8 @@ hipError_t launch_build_fill(BuildKernel k, const Seg &s, long long nblocks, hip
 // first chunk (prefix of ceil(n / scan_seg_chunk()) over the arrays);
 // sums: nchunks ints of workspace.  Arrays of length 0 get out[0] = 0.
 struct ScanSeg {
-    const int *in;
-    int *out;
+    GMEM const int *in;
+    GMEM int *out;
     long long n;
     long long chunk0;
 };
@@ -171,10 +171,10 @@ hipError_t launch_edge_group(const Mol &m, const long long *keys, long long coun
 // the rest as for launch_edge_detect_write and launch_edge_group, tcount and
 // the units header zeroed before the write pass.
 struct EdgeDetectJob {
-    const uint8_t *L;
-    int *bcount, *boff;
-    long long *keys;
-    int *tcount, *ccount, *coff, *rank, *order, *units;
+    GMEM const uint8_t *L;
+    GMEM int *bcount, *boff;
+    GMEM long long *keys;
+    GMEM int *tcount, *ccount, *coff, *rank, *order, *units;
     long long nw;
 };
 // Block starts (nm + 1 prefix sums, device and host copies) of the write
@@ -216,12 +216,12 @@ hipError_t launch_edge_work(const Mol &m, const uint8_t *L, const long long *key
 // crossing edges are grouped): mol indexes the device Mol array; units as
 // written by launch_edge_group; nfallback zeroed.
 struct EdgeJob {
-    const uint8_t *L;
-    const long long *keys;
-    const int *order, *tcount, *coff, *units;
-    double *lam, *nrm;
-    uint8_t *ptype;
-    int *patoms, *fallback, *nfallback;
+    GMEM const uint8_t *L;
+    GMEM const long long *keys;
+    GMEM const int *order, *tcount, *coff, *units;
+    GMEM double *lam, *nrm;
+    GMEM uint8_t *ptype;
+    GMEM int *patoms, *fallback, *nfallback;
     int mol, pad;
 };
 // Every job's tiles in one persistent launch (jobs in the given order, each
