@@ -932,26 +932,46 @@ __global__ void __launch_bounds__(VX_WAVES *WAVE) __attribute__((amdgpu_waves_pe
     const VertexPool &pool = tmp.pool;
     const int i = bid;
     const int c0 = m.circ_off[i], c1 = m.circ_off[i + 1];
+    const int nb = m.nbr_off[i], ne = m.nbr_off[i + 1];
     if (c0 == c1) return;  // uniform across the workgroup
     if (FILL && m.vert_off[c0] == m.vert_off[c1]) return;  // no probe position on i's circles
-    const int nb = m.nbr_off[i], ne = m.nbr_off[i + 1];
     const int nst = min(VX_NBR, ne - nb);
     // the count pass pooled the positions of an atom whose lists fit in LDS
     if (FILL && pool.use && c1 - c0 <= VX_NBR && ne - nb <= VX_NBR) return;
-    for (int q = threadIdx.x; q < nst; q += VX_WAVES * WAVE) {
-        const int l = m.nbr_cov[nb + q];
-        const double4 al = m.atom[l];
-        L.nat[q] = make_double4(al.x, al.y, al.z, sq(al.w + m.rho) * (1.0 - VERTEX_TOL));
-        L.nid[q] = l;
-        const int k = m.nbr[nb + q];
-        L.nasc[q] = k;
-        L.natasc[q] = m.atom[k];
-    }
     const int ncl = c1 - c0 <= VX_NBR ? c1 - c0 : -1;
-    for (int q = threadIdx.x; q < ncl; q += VX_WAVES * WAVE) {
-        L.cj[q] = m.circ_j[c0 + q];
-        L.coR[q] = m.circ_oR[c0 + q];
-        L.cn[q] = m.circ_n[c0 + q];
+    // one thread per staged neighbour and circle: every load is issued
+    // before the first LDS store, so that their latencies overlap
+    static_assert(VX_NBR <= VX_WAVES * WAVE, "one staging round");
+    {
+        const int q = threadIdx.x;
+        const bool qa = q < nst, qc = q < ncl;
+        int l = 0, k = 0, cj = 0;
+        double4 coR{}, cn{};
+        if (qa) {
+            l = m.nbr_cov[nb + q];
+            k = m.nbr[nb + q];
+        }
+        if (qc) {
+            cj = m.circ_j[c0 + q];
+            coR = m.circ_oR[c0 + q];
+            cn = m.circ_n[c0 + q];
+        }
+        double4 al{}, ak{};
+        if (qa) {
+            al = m.atom[l];
+            ak = m.atom[k];
+        }
+        if (qa) {
+            L.nat[q] = make_double4(al.x, al.y, al.z, sq(al.w + m.rho) * (1.0 - VERTEX_TOL));
+            L.nid[q] = l;
+            L.nasc[q] = k;
+            L.natasc[q] = ak;
+        }
+        if (qc) {
+            L.cj[q] = cj;
+            L.coR[q] = coR;
+            L.cn[q] = cn;
+        }
     }
     __syncthreads();
     const int lane = lane_id();
