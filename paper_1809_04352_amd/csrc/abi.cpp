@@ -775,6 +775,7 @@ class Builder {
             TT.add(&t.pool.p, t.pool.cap);
             TT.add(&t.pool.id, t.pool.cap);
             TZ.add(&t.pool.count, 1);
+            TZ.add(&t.vx_big, 1);
             TT.add(&t.face_cnt, m.n);
             TT.add(&t.ecf, m.ncirc);
             TT.add(&t.ec_pos, m.ncirc + 1);
@@ -804,6 +805,7 @@ class Builder {
             addr.push_back(M[q].face_off_atom + M[q].n);
             addr.push_back(B[q].ec_pos + M[q].ncirc);
             addr.push_back(B[q].pool.count);
+            addr.push_back(B[q].vx_big);
         }
         const size_t ao = C.put(addr.data(), addr.size());
         int *rb;
@@ -821,11 +823,12 @@ class Builder {
         std::vector<int> h;
         CKS(read_ints(C, ao, (int)addr.size(), rb, h));
         for (int q = 0; q < nm_; ++q) {
-            M[q].nvert = h[(size_t)4 * q];
-            M[q].nface = h[(size_t)4 * q + 1];
-            M[q].nec = h[(size_t)4 * q + 2];
-            B[q].npool = h[(size_t)4 * q + 3];
+            M[q].nvert = h[(size_t)5 * q];
+            M[q].nface = h[(size_t)5 * q + 1];
+            M[q].nec = h[(size_t)5 * q + 2];
+            B[q].npool = h[(size_t)5 * q + 3];
             B[q].pool.use = B[q].npool <= B[q].pool.cap ? 1 : 0;
+            B[q].nvx_big = h[(size_t)5 * q + 4];
         }
         return ESES_OK;
     }
@@ -869,17 +872,23 @@ class Builder {
             ti{BK_TILES, false, 0, 0};
         for (Launch *l : {&vp, &vf, &vo, &ei, &fo, &fl, &fc, &ec, &ti})
             l->off = starts(C, l->k, &l->nb);
-        // the ordering pass only where the positions were pooled
+        // the ordering pass only where the positions were pooled, the fill
+        // pass only where some were not
         {
-            std::vector<int> st((size_t)nm_ + 1, 0);
-            long long t = 0;
+            std::vector<int> st((size_t)nm_ + 1, 0), sf((size_t)nm_ + 1, 0);
+            long long t = 0, tf = 0;
             for (int q = 0; q < nm_; ++q) {
                 st[(size_t)q] = (int)t;
+                sf[(size_t)q] = (int)tf;
                 if (B[q].pool.use) t += build_blocks(BK_VERTEX_ORDER, M[q], B[q]);
+                if (!B[q].pool.use || B[q].nvx_big > 0) tf += build_blocks(BK_VERTEX, M[q], B[q]);
             }
             st[(size_t)nm_] = (int)t;
+            sf[(size_t)nm_] = (int)tf;
             vo.nb = t;
             vo.off = C.put(st.data(), st.size());
+            vf.nb = tf;
+            vf.off = C.put(sf.data(), sf.size());
         }
         ScanList S1, S2, S3;
         for (int q = 0; q < nm_; ++q) {

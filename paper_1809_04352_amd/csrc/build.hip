@@ -1068,6 +1068,8 @@ __global__ void __launch_bounds__(VX_WAVES *WAVE) __attribute__((amdgpu_waves_pe
         }
         return;
     }
+    // (the count pass leaves this atom's positions to the fill pass)
+    if (!FILL && threadIdx.x == 0) atomicAdd(tmp.vx_big, 1);
     for (int c = c0 + threadIdx.x / WAVE; c < c1; c += VX_WAVES) {
         if (FILL && m.vert_off[c + 1] == m.vert_off[c]) continue;  // no probe position here
         vertex_circle<FILL>(m, c, c0, i, nb, ne, nst, L, ncl, lane, vcnt);

@@ -63,6 +63,8 @@ struct BuildTmp {
     GMEM int *vcnt;            // [ncirc] probe positions per circle
     VertexPool pool;
     int npool;            // positions the count pass pooled
+    GMEM int *vx_big;          // atoms whose lists exceed LDS (positions left to the fill pass)
+    int nvx_big;          // (its value, read back)
     GMEM int *face_cnt, *ecf, *ec_pos;
     GMEM int *fcut_cnt, *eccut_cnt;
     GMEM int *cA, *cF, *cC, *cV;  // per-tile list lengths
