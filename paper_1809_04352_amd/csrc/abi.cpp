@@ -700,6 +700,7 @@ class Builder {
             TT.add(&t.slot, m.n);
             TT.add(&t.nbr_cnt, m.n);
             TT.add(&t.circ_cnt, m.n);
+            TT.add(&t.nbr_pool, (long long)m.n * NBR_POOL);
         }
         CKS(P.commit(c_->batch, st_, false));
         CKS(TT.commit(T_, st_, false));

@@ -465,6 +465,36 @@ __global__ void __launch_bounds__(NB_WAVES *WAVE) k_nbr(Seg sg) {
     const int lane = lane_id();
     double4 ai = m.atom[i];
     double si = ai.w + m.rho;
+    if (FILL && m.nbr_off[i + 1] - m.nbr_off[i] <= NBR_POOL) {
+        const auto pool = tmp.nbr_pool + (long long)i * NBR_POOL;
+        // the count pass kept this atom's neighbours (ascending): the same
+        // lists from them, with the same arithmetic per neighbour
+        const int wn = m.nbr_off[i], nlist = m.nbr_off[i + 1] - wn;
+        const int wc = m.circ_off[i], ecc = m.circ_off[i + 1];
+        int nc = 0;
+        for (int base = 0; base < nlist; base += WAVE) {
+            const int t = base + lane;
+            bool circ = false;
+            int k = -1;
+            double4 oR = make_double4(0, 0, 0, 0), n = make_double4(0, 0, 0, 0);
+            if (t < nlist) {
+                k = pool[t];
+                m.nbr[wn + t] = k;
+                if (k > i) circ = pair_circle(ai, m.atom[k], m.rho, oR, n);
+            }
+            const unsigned long long bc = __ballot(circ);
+            const int pc = wc + nc + mask_prefix(bc);
+            if (circ && fill_ok(m, pc, ecc)) {
+                m.circ_i[pc] = i;
+                m.circ_j[pc] = k;
+                m.circ_oR[pc] = oR;
+                m.circ_n[pc] = n;
+                m.cflag[pc] = 0u;
+            }
+            nc += __popcll(bc);
+        }
+        return;
+    }
     int cx = cell_axis(m, ai.x, 0), cy = cell_axis(m, ai.y, 1), cz = cell_axis(m, ai.z, 2);
     const int x0 = max(cx - 1, 0), x1 = min(cx + 1, m.nc[0] - 1);
     const int y0 = max(cy - 1, 0), y1 = min(cy + 1, m.nc[1] - 1);
@@ -490,6 +520,7 @@ __global__ void __launch_bounds__(NB_WAVES *WAVE) k_nbr(Seg sg) {
     bool contained = false;
     int wn = FILL ? m.nbr_off[i] : 0, en = FILL ? m.nbr_off[i + 1] : 0;
     int wc = FILL ? m.circ_off[i] : 0, ecc = FILL ? m.circ_off[i + 1] : 0;
+    auto pool = tmp.nbr_pool + (long long)i * NBR_POOL;
     for (int base = 0; base < total; base += WAVE) {
         const int t = base + lane;
         int k = -1;
@@ -516,6 +547,10 @@ __global__ void __launch_bounds__(NB_WAVES *WAVE) k_nbr(Seg sg) {
             }
         }
         unsigned long long bn = __ballot(nb), bc = __ballot(circ), ba = __ballot(any);
+        if (!FILL) {
+            const int pn = nn + mask_prefix(bn);
+            if (nb && pn < NBR_POOL) pool[pn] = k;
+        }
         if (FILL) {
             int pn = wn + nn + mask_prefix(bn);
             if (nb && fill_ok(m, pn, en)) m.nbr[pn] = k;

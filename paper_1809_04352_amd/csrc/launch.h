@@ -60,6 +60,8 @@ struct BuildTmp {
     GMEM int *bad;             // non-finite or non-positive input
     GMEM int *cell_id, *cnt, *fillb, *slot;
     GMEM int *nbr_cnt, *circ_cnt;
+    GMEM int *nbr_pool;        // [n][NBR_POOL]: each atom's SAS neighbours as the count pass
+                               // found them (ascending; complete when they fit)
     GMEM int *vcnt;            // [ncirc] probe positions per circle
     VertexPool pool;
     int npool;            // positions the count pass pooled
@@ -72,6 +74,9 @@ struct BuildTmp {
     int tp_unpooled;      // some tile's lists did not fit its pool slot
     int pad;
 };
+
+// Neighbours per atom kept by the neighbour count pass for the fill pass.
+constexpr int NBR_POOL = 128;
 
 // One launch over the blocks of several molecules: block b works for
 // molecule q with start[q] <= b < start[q + 1] (the largest such q, so
