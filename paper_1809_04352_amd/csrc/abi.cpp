@@ -852,6 +852,8 @@ class Builder {
             P.add(&m.tV_off, m.ntiles + 1);
             TT.add(&t.fcut_cnt, m.nface);
             TT.add(&t.eccut_cnt, m.nec);
+            TT.add(&t.fcut_keep, 2LL * m.nface);
+            TT.add(&t.eccut_keep, m.nec);
             TT.add(&t.cA, m.ntiles);
             TT.add(&t.cF, m.ntiles);
             TT.add(&t.cC, m.ntiles);

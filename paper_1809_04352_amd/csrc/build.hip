@@ -1267,17 +1267,23 @@ __global__ void __launch_bounds__(FC_WAVES *WAVE) k_face_cuts(Seg sg) {
         double d2 = vx * vx + vy * vy + vz * vz;
         return make_double4(vx, vy, vz, (si * si + d2 - sk * sk) / (2.0 * si));
     };
-    if (filt) {
+    if (filt && !FILL) {  // (the fill pass reads the count pass's decisions)
         for (int q = lane; q < n; q += WAVE) cap_put(L, q, cut_cap(cut_of(q)));
         wave_sync();
     }
     int w = FILL ? m.face_cut_off[f] : 0, we = FILL ? m.face_cut_off[f + 1] : 0;
     int cnt = 0;
+    static_assert(CUT_CAPS <= 2 * WAVE, "two keep words per face");
     for (int base = 0; base < n; base += WAVE) {
         const int q = base + lane;
         const bool act = q < n;
-        const bool keep = act && !(filt && cap_redundant(L, n, q, act));
+        bool keep;
+        if (FILL && filt)  // as the count pass found
+            keep = act && ((tmp.fcut_keep[2LL * f + base / WAVE] >> lane) & 1ull);
+        else
+            keep = act && !(filt && cap_redundant(L, n, q, act));
         const unsigned long long bm = __ballot(keep);
+        if (!FILL && filt && lane == 0) tmp.fcut_keep[2LL * f + base / WAVE] = bm;
         if (FILL && keep) {
             const int p = w + cnt + mask_prefix(bm);
             if (fill_ok(m, p, we)) m.face_cut[p] = cut_of(q);
@@ -1352,19 +1358,22 @@ __global__ void __launch_bounds__(EC_WAVES *WAVE) k_ec_cuts(Seg sg) {
         const int p = nin + mask_prefix(bm);
         if (in && p < EC_CAPS) {
             cuts[wv][p] = cut;
-            cap_put(L, p, cut_cap(cut));
+            if (!FILL) cap_put(L, p, cut_cap(cut));
         }
         nin += __popcll(bm);
     }
     wave_sync();
     int w = FILL ? m.ec_cut_off[e] : 0, we = FILL ? m.ec_cut_off[e + 1] : 0;
     int cnt = 0;
+    static_assert(EC_CAPS <= WAVE, "one keep word per circle");
     if (nin <= EC_CAPS) {
         for (int base = 0; base < nin; base += WAVE) {
             const int q = base + lane;
             const bool act = q < nin;
-            const bool keep = act && !cap_redundant(L, nin, q, act);
+            const bool keep = act && (FILL ? ((tmp.eccut_keep[e] >> lane) & 1ull)  // as counted
+                                           : !cap_redundant(L, nin, q, act));
             const unsigned long long bm = __ballot(keep);
+            if (!FILL && lane == 0) tmp.eccut_keep[e] = bm;
             if (FILL && keep) {
                 const int p = w + cnt + mask_prefix(bm);
                 if (fill_ok(m, p, we)) m.ec_cut[p] = cuts[wv][q];
@@ -1435,7 +1444,8 @@ __device__ inline int tile_row(const int *incl, int nrow, int t) {
     return lo;
 }
 
-constexpr int TILE_KEEP = 96;  // entries of a tile's lists the count pass keeps (LDS, pool slot)
+constexpr int TILE_KEEP = 192;  // entries of each of a tile's lists the count pass keeps (LDS)
+constexpr int TILE_SLOT = 256;  // entries of a tile's pool slot (its four lists together)
 
 template <bool FILL>
 __global__ void __launch_bounds__(TILE_WAVES *WAVE) k_tiles(Seg sg) {
@@ -1582,7 +1592,8 @@ __global__ void __launch_bounds__(TILE_WAVES *WAVE) k_tiles(Seg sg) {
         // the kept lists go to the tile's slot of the pool (tp.cap entries
         // per tile), or the fill pass rebuilds them
         const int tot = nA + nF + nC + nV;
-        const int base = tot <= tp.cap ? tile * tp.cap : -1;
+        const bool kept = nA <= TILE_KEEP && nF <= TILE_KEEP && nC <= TILE_KEEP && nV <= TILE_KEEP;
+        const int base = kept && tot <= tp.cap ? tile * tp.cap : -1;
         if (lane == 0) {
             tp.off[tile] = base;
             if (base < 0) atomicOr(tp.unpooled, 1);
@@ -1777,6 +1788,6 @@ hipError_t launch_build_fill(BuildKernel k, const Seg &s, long long nblocks, hip
     return hipGetLastError();
 }
 
-int tile_keep_max() { return TILE_KEEP; }
+int tile_keep_max() { return TILE_SLOT; }
 
 }  // namespace eses

@@ -69,6 +69,10 @@ struct BuildTmp {
     int nvx_big;          // (its value, read back)
     GMEM int *face_cnt, *ecf, *ec_pos;
     GMEM int *fcut_cnt, *eccut_cnt;
+    // kept cuts found by the cut count passes, for their fill passes: bit q
+    // of word (2 f + q / 64) for cut q of face f, bit q of word e for the
+    // q-th reaching cut of exposed circle e (where the lists were staged)
+    GMEM unsigned long long *fcut_keep, *eccut_keep;
     GMEM int *cA, *cF, *cC, *cV;  // per-tile list lengths
     TilePool tp;
     int tp_unpooled;      // some tile's lists did not fit its pool slot
