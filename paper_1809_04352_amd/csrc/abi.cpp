@@ -660,7 +660,9 @@ class Builder {
             Mol &m = M[q];
             const double *b = &hb[(size_t)8 * q];
             m.smax = b[6] + m.rho;
-            m.cell = 2.0 * m.smax;
+            // cells of edge s_max (slightly more): SAS neighbours, within 2 s_max plus the list
+            // slack, lie within two cells along each axis
+            m.cell = (m.smax + LIST_SLACK) * (1.0 + 1e-9);
             m.cmag = m.smax;
             for (int a = 0; a < 6; ++a) m.cmag = std::max(m.cmag, std::fabs(b[a]) + m.smax);
             for (;;) {

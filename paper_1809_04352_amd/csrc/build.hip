@@ -446,8 +446,10 @@ __device__ inline bool fill_ok(const Mol &m, long long at, long long end) {
 
 // ------------------------------------------------ SAS neighbours and circles
 
-// One wavefront per internal atom i; the atoms of the 3x3x3 stencil, row by
-// row, are spread over the lanes and ballots compact the hits.  Stencil
+// One wavefront per internal atom i; the atoms of the 5x5x5 stencil of cells
+// (edge at least s_max plus the list slack, so that every candidate lies
+// within two cells along each axis), row by row, are spread over the lanes
+// and ballots compact the hits.  Stencil
 // cells are visited in increasing cell index and internal ids increase with
 // the cell index, so each neighbour list comes out ascending.
 constexpr int NB_WAVES = 4;
@@ -455,8 +457,8 @@ constexpr int NB_WAVES = 4;
 template <bool FILL>
 __global__ void __launch_bounds__(NB_WAVES *WAVE) k_nbr(Seg sg) {
     // per wavefront: the first atom and inclusive end offset of each of the
-    // stencil's (y, z) cell rows (at most 9)
-    __shared__ int rbeg[NB_WAVES][9], rend[NB_WAVES][9];
+    // stencil's (y, z) cell rows (at most 25)
+    __shared__ int rbeg[NB_WAVES][25], rend[NB_WAVES][25];
     SEG_BEGIN(sg);
     int *nbr_cnt = tmp.nbr_cnt, *circ_cnt = tmp.circ_cnt;
     const int wv = threadIdx.x / WAVE;
@@ -496,9 +498,9 @@ __global__ void __launch_bounds__(NB_WAVES *WAVE) k_nbr(Seg sg) {
         return;
     }
     int cx = cell_axis(m, ai.x, 0), cy = cell_axis(m, ai.y, 1), cz = cell_axis(m, ai.z, 2);
-    const int x0 = max(cx - 1, 0), x1 = min(cx + 1, m.nc[0] - 1);
-    const int y0 = max(cy - 1, 0), y1 = min(cy + 1, m.nc[1] - 1);
-    const int z0 = max(cz - 1, 0), z1 = min(cz + 1, m.nc[2] - 1);
+    const int x0 = max(cx - 2, 0), x1 = min(cx + 2, m.nc[0] - 1);
+    const int y0 = max(cy - 2, 0), y1 = min(cy + 2, m.nc[1] - 1);
+    const int z0 = max(cz - 2, 0), z1 = min(cz + 2, m.nc[2] - 1);
     const int ny = y1 - y0 + 1, nr = ny * (z1 - z0 + 1);
     // the cells of one row are consecutive, and so are their atoms: lane r
     // reads row r's range, then the rows' atoms are taken 64 at a time

@@ -1,7 +1,7 @@
 // Internal device-side layout of the ESES hot path (gfx950).
 //
-// Atoms are re-ordered by a uniform cell list (cell edge 2 * s_max, so SAS
-// neighbours lie in the 3x3x3 stencil) and renumbered; every per-atom,
+// Atoms are re-ordered by a uniform cell list (cell edge s_max, so SAS
+// neighbours lie in the 5x5x5 stencil) and renumbered; every per-atom,
 // per-circle and per-vertex array below uses these internal ids, which keeps
 // the candidates of one cell contiguous in memory.  Circles and concave probe
 // positions are owned by their lowest internal atom id, so the features of a
@@ -59,7 +59,7 @@ struct Mol {
     int dims[3];
     long long npts;
     // cell list over the atom box
-    double cell;         // cell edge (2 * s_max)
+    double cell;         // cell edge (s_max plus the list slack, or more for sparse input)
     double smax;
     double clo[3];
     int nc[3];
