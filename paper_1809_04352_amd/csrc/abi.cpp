@@ -703,6 +703,7 @@ class Builder {
             TT.add(&t.nbr_cnt, m.n);
             TT.add(&t.circ_cnt, m.n);
             TT.add(&t.nbr_pool, (long long)m.n * NBR_POOL);
+            TZ.add(&t.nbr_big, 1);
         }
         CKS(P.commit(c_->batch, st_, false));
         CKS(TT.commit(T_, st_, false));
@@ -732,6 +733,7 @@ class Builder {
             addr.push_back(M[q].nbr_off + M[q].n);
             addr.push_back(M[q].circ_off + M[q].n);
             addr.push_back(M[q].diag + 2);
+            addr.push_back(B[q].nbr_big);
         }
         const size_t ao = C.put(addr.data(), addr.size());
         int *rb;
@@ -745,11 +747,12 @@ class Builder {
         std::vector<int> h;
         CKS(read_ints(C, ao, (int)addr.size(), rb, h));
         for (int q = 0; q < nm_; ++q) {
-            if (h[(size_t)3 * q + 2])
+            if (h[(size_t)4 * q + 2])
                 return fail(q, ESES_EINVAL,
                             "atom centres must be pairwise distinct (two atoms share a centre)");
-            nbr_total_.push_back(h[(size_t)3 * q]);
-            M[q].ncirc = h[(size_t)3 * q + 1];
+            nbr_total_.push_back(h[(size_t)4 * q]);
+            M[q].ncirc = h[(size_t)4 * q + 1];
+            B[q].nnbr_big = h[(size_t)4 * q + 3];
         }
         return ESES_OK;
     }
@@ -792,6 +795,19 @@ class Builder {
             cf{BK_CIRCLE_FREE, false, 0, 0}, af{BK_ATOM_FEATURES, false, 0, 0},
             ef{BK_EC_FLAG, false, 0, 0};
         for (Launch *l : {&nf, &ns, &vx, &cf, &af, &ef}) l->off = starts(C, l->k, &l->nb);
+        // the cover-order sort only where some atom's neighbours exceeded the
+        // pool (the fill pass ranks the others)
+        {
+            std::vector<int> st((size_t)nm_ + 1, 0);
+            long long t = 0;
+            for (int q = 0; q < nm_; ++q) {
+                st[(size_t)q] = (int)t;
+                if (B[q].nnbr_big > 0) t += build_blocks(BK_NBR_SORT, M[q], B[q]);
+            }
+            st[(size_t)nm_] = (int)t;
+            ns.nb = t;
+            ns.off = C.put(st.data(), st.size());
+        }
         ScanList S1, S2, S3;
         for (int q = 0; q < nm_; ++q) {
             S1.add(B[q].vcnt, M[q].vert_off, M[q].ncirc);

@@ -446,6 +446,14 @@ __device__ inline bool fill_ok(const Mol &m, long long at, long long end) {
 
 // ------------------------------------------------ SAS neighbours and circles
 
+// Cover-order key of neighbour k of atom i (s_i = r_i + rho): the cosine of
+// the half-angle of the cap S_k cuts from S_i, tau_ik / d_ik.
+__device__ inline double cover_key(double4 ai, double si, double4 ak, double rho) {
+    const double sk = ak.w + rho;
+    const double d2 = sq(ak.x - ai.x) + sq(ak.y - ai.y) + sq(ak.z - ai.z);
+    return (si * si + d2 - sk * sk) / (2.0 * si * sqrt(d2));
+}
+
 // One wavefront per internal atom i; the atoms of the 5x5x5 stencil of cells
 // (edge at least s_max plus the list slack, so that every candidate lies
 // within two cells along each axis), row by row, are spread over the lanes
@@ -459,6 +467,8 @@ __global__ void __launch_bounds__(NB_WAVES *WAVE) k_nbr(Seg sg) {
     // per wavefront: the first atom and inclusive end offset of each of the
     // stencil's (y, z) cell rows (at most 25)
     __shared__ int rbeg[NB_WAVES][25], rend[NB_WAVES][25];
+    // fill pass, pooled atoms: the cover-order keys of the atom's neighbours
+    __shared__ double ckey[FILL ? NB_WAVES : 1][FILL ? NBR_POOL : 1];
     SEG_BEGIN(sg);
     int *nbr_cnt = tmp.nbr_cnt, *circ_cnt = tmp.circ_cnt;
     const int wv = threadIdx.x / WAVE;
@@ -482,7 +492,9 @@ __global__ void __launch_bounds__(NB_WAVES *WAVE) k_nbr(Seg sg) {
             if (t < nlist) {
                 k = pool[t];
                 m.nbr[wn + t] = k;
-                if (k > i) circ = pair_circle(ai, m.atom[k], m.rho, oR, n);
+                const double4 ak = m.atom[k];
+                ckey[wv][t] = cover_key(ai, si, ak, m.rho);
+                if (k > i) circ = pair_circle(ai, ak, m.rho, oR, n);
             }
             const unsigned long long bc = __ballot(circ);
             const int pc = wc + nc + mask_prefix(bc);
@@ -494,6 +506,17 @@ __global__ void __launch_bounds__(NB_WAVES *WAVE) k_nbr(Seg sg) {
                 m.cflag[pc] = 0u;
             }
             nc += __popcll(bc);
+        }
+        // the same list in cover order (as k_nbr_sort ranks longer lists)
+        wave_sync();
+        for (int q = lane; q < nlist; q += WAVE) {
+            const double kq = ckey[wv][q];
+            int rank = 0;
+            for (int p = 0; p < nlist; ++p) {
+                const double kp = ckey[wv][p];
+                rank += (kp < kq || (kp == kq && p < q)) ? 1 : 0;
+            }
+            m.nbr_cov[wn + rank] = pool[q];
         }
         return;
     }
@@ -571,6 +594,7 @@ __global__ void __launch_bounds__(NB_WAVES *WAVE) k_nbr(Seg sg) {
     }
     unsigned long long bcont = __ballot(contained);
     if (!FILL && lane == 0) {
+        if (nn > NBR_POOL) atomicAdd(tmp.nbr_big, 1);
         nbr_cnt[i] = nn;
         circ_cnt[i] = nc;
         m.circ_any[i] = nany;
@@ -598,19 +622,15 @@ __global__ void __launch_bounds__(NS_WAVES *WAVE) k_nbr_sort(Seg sg) {
     if (i < m.n) {
         b = m.nbr_off[i];
         n = m.nbr_off[i + 1] - b;
-        mode = n > NS_MAX ? 1 : 2;
+        // lists within the neighbour pool were ranked by the fill pass
+        mode = n <= NBR_POOL ? 0 : n > NS_MAX ? 1 : 2;
     }
     if (mode == 1)
         for (int q = lane; q < n; q += WAVE) m.nbr_cov[b + q] = m.nbr[b + q];
     if (mode == 2) {
         double4 ai = m.atom[i];
         double si = ai.w + m.rho;
-        for (int q = lane; q < n; q += WAVE) {
-            double4 ak = m.atom[m.nbr[b + q]];
-            double sk = ak.w + m.rho;
-            double d2 = sq(ak.x - ai.x) + sq(ak.y - ai.y) + sq(ak.z - ai.z);
-            keys[w][q] = (si * si + d2 - sk * sk) / (2.0 * si * sqrt(d2));
-        }
+        for (int q = lane; q < n; q += WAVE) keys[w][q] = cover_key(ai, si, m.atom[m.nbr[b + q]], m.rho);
     }
     __syncthreads();
     if (mode == 2) {

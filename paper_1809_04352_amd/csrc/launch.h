@@ -62,6 +62,8 @@ struct BuildTmp {
     GMEM int *nbr_cnt, *circ_cnt;
     GMEM int *nbr_pool;        // [n][NBR_POOL]: each atom's SAS neighbours as the count pass
                                // found them (ascending; complete when they fit)
+    GMEM int *nbr_big;         // atoms with more neighbours than that (ranked by k_nbr_sort)
+    int nnbr_big;         // (its value, read back)
     GMEM int *vcnt;            // [ncirc] probe positions per circle
     VertexPool pool;
     int npool;            // positions the count pass pooled
