@@ -1070,7 +1070,8 @@ __global__ void __launch_bounds__(VX_WAVES *WAVE) __attribute__((amdgpu_waves_pe
                 int cc, p;
                 vx_pair_of(t, ncl, poff, pj, cc, p);
                 const VxAxis g = vx_axis(m, L.coR[cc], L.cn[cc], L.natasc[p]);
-                if (vx_maybe_live(g, L.coR[cc].w)) qitem[atomicAdd(&qn, 1)] = t;
+                // queued as (circle, k's position), both below VX_NBR
+                if (vx_maybe_live(g, L.coR[cc].w)) qitem[atomicAdd(&qn, 1)] = cc | (p << 16);
             }
             __syncthreads();
             const int nq = qn;
@@ -1079,7 +1080,11 @@ __global__ void __launch_bounds__(VX_WAVES *WAVE) __attribute__((amdgpu_waves_pe
                 const int q = q0 + (int)threadIdx.x;
                 const bool act = q < nq;
                 int cc = 0, p = 0;
-                if (act) vx_pair_of(qitem[q], ncl, poff, pj, cc, p);
+                if (act) {
+                    const int it = qitem[q];
+                    cc = it & 0xFFFF;
+                    p = it >> 16;
+                }
                 const int j = L.cj[cc], k = act ? L.nasc[p] : -1;
                 const double4 oR = L.coR[cc], n = L.cn[cc];
                 const VxAxis g = vx_axis(m, oR, n, L.natasc[p]);
