@@ -120,7 +120,7 @@ def cpu_sample(o, m, budget_s, orc):
 
 def cpu_baseline(mols_np, counts, target_s):
     """The FP64 oracle on a bounded sample of the same workload, extrapolated
-    to all of it: for a batch, twelve molecules at evenly spaced ranks of size
+    to all of it: for a batch, 24 molecules at evenly spaced ranks of size
     (smallest to largest), each built whole (probe enumeration) and labelled,
     with its crossing edges solved, on evenly spaced z-slice pairs; the time
     per atom of the builds, per point of the labels and per crossing of the
@@ -134,7 +134,7 @@ def cpu_baseline(mols_np, counts, target_s):
     orc.build(force=False)
     order = np.argsort([m.n_atoms for m in mols_np], kind="stable")
     pick = sorted(set(int(order[int(round(f * (len(order) - 1)))])
-                      for f in np.linspace(0.0, 1.0, 12)))
+                      for f in np.linspace(0.0, 1.0, 24)))
     t_create = t_lab = t_edge = 0.0
     atoms = pts = edges = pairs = 0
     per_mol = target_s / len(pick)
