@@ -35,15 +35,25 @@ constexpr int CAP_V = 48, CAP_F = 48, CAP_C = 48, CAP_CUT = 320;
 // 30.1 ms).
 constexpr int CLS_WAVES_PER_EU = 6;
 
+// 8^3 tiles: the staged atoms whose SAS ball (plus a margin far above any
+// rounding) reaches each 4^3 sub-tile; the other atoms are certainly outside
+// the SAS ball of every point there, so their tests are skipped.
+struct ClsSubLists {
+    unsigned char at[8][CLS_ATOMS];
+    int n[8];
+};
+
 struct ClsPhase1 {
     double4 a[CLS_ATOMS];  // FP64: x, y, z, r^2
     double s2[CLS_ATOMS];  // FP64: (r + rho)^2
     double bd[CLS_ATOMS];  // FP64: error bound of both comparisons
+    ClsSubLists sub;
 };
 
 struct ClsPhase1f {
     float4 a[CLS_ATOMS];   // FP32: atom offset from the tile origin
     float4 t[CLS_ATOMS];   // FP32 thresholds: vdW (lo, hi), SAS (lo, hi)
+    ClsSubLists sub;
 };
 
 struct ClsPhase2 {
@@ -269,6 +279,22 @@ __device__ inline int shell_cert_staged(const Mol &m, const ClsShared &sh, const
 // with the certified thresholds above; points it cannot certify are
 // re-labelled in FP64 (counted in diag[1]).  Case 3 runs in FP64 either way,
 // with the square roots of its tests from FP32 roots and one Newton step.
+// Grid point p of tile t3 (T^3 points).  An 8^3 tile takes its points by 4^3
+// sub-tiles, 64 consecutive p each, so that a wavefront holds one sub-tile;
+// other tiles go row by row.
+__device__ inline void tile_point(int p, int T, const int *t3, int &i, int &j, int &k) {
+    if (T == 8) {
+        const int sb = p >> 6, l = p & 63;
+        i = t3[0] * 8 + ((sb & 1) << 2) + (l & 3);
+        j = t3[1] * 8 + (((sb >> 1) & 1) << 2) + ((l >> 2) & 3);
+        k = t3[2] * 8 + ((sb >> 2) << 2) + (l >> 4);
+    } else {
+        i = t3[0] * T + p % T;
+        j = t3[1] * T + (p / T) % T;
+        k = t3[2] * T + p / (T * T);
+    }
+}
+
 template <bool F32>
 __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared &sh) {
     const int T = m.tile;
@@ -283,7 +309,8 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
     for (int a = 0; a < 3; ++a) org[a] = mol_coord(m, a, t3[a] * T);
     for (int r = 0; r < PPT; ++r) {
         int p = threadIdx.x + r * CLS_THREADS;
-        int i = t3[0] * T + p % T, j = t3[1] * T + (p / T) % T, k = t3[2] * T + p / (T * T);
+        int i, j, k;
+        tile_point(p, T, t3, i, j, k);
         valid[r] = p < P && i < m.dims[0] && j < m.dims[1] && k < m.dims[2];
         px[r] = mol_coord(m, 0, i);
         py[r] = mol_coord(m, 1, j);
@@ -311,11 +338,36 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
     const double bandA = CERT_BAND;
     const double E = 4.01 * U32 * lam;
     const double cb = 3.0 * E * (4.0 * lam + E) + 1e-30;
+    const bool subt = T == 8;
+    ClsSubLists &SL = F32 ? sh.p1f.sub : sh.p1.sub;
     for (int base = a0; base < a1; base += CLS_ATOMS) {
         int cnt = min(CLS_ATOMS, a1 - base);
         __syncthreads();
+        if (subt) {
+            if (threadIdx.x < 8) SL.n[threadIdx.x] = 0;
+            __syncthreads();
+        }
         for (int q = threadIdx.x; q < cnt; q += CLS_THREADS) {
             double4 a = m.atom[m.tA[base + q]];
+            if (subt) {
+                // squared distance from the centre to each half of the tile
+                // per axis (points 0-3 and 4-7); an atom joins the sub-tiles
+                // its SAS ball, grown by 1e-3, reaches
+                double dh[3][2];
+                const double cc[3] = {a.x, a.y, a.z};
+                for (int ax = 0; ax < 3; ++ax)
+                    for (int hb = 0; hb < 2; ++hb) {
+                        const double lo = mol_coord(m, ax, t3[ax] * 8 + 4 * hb),
+                                     hi = mol_coord(m, ax, t3[ax] * 8 + 4 * hb + 3);
+                        const double dd = cc[ax] < lo ? lo - cc[ax] : cc[ax] > hi ? cc[ax] - hi : 0.0;
+                        dh[ax][hb] = dd * dd;
+                    }
+                const double reach = sq(a.w + rho + 1e-3);
+                for (int sb = 0; sb < 8; ++sb) {
+                    const double d2 = dh[0][sb & 1] + dh[1][(sb >> 1) & 1] + dh[2][sb >> 2];
+                    if (d2 < reach) SL.at[sb][atomicAdd(&SL.n[sb], 1)] = (unsigned char)q;
+                }
+            }
             if (F32) {
                 sh.p1f.a[q] = make_float4((float)(a.x - org[0]), (float)(a.y - org[1]),
                                           (float)(a.z - org[2]), 0.0f);
@@ -331,9 +383,14 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
         __syncthreads();
         for (int r = 0; r < PPT; ++r) {
             if (!valid[r] || inv[r]) continue;
+            // the atoms that can reach the point's sub-tile (every staged atom
+            // for other tiles): the order of the tests does not matter
+            const int sb = subt ? (int)(threadIdx.x >> 6) + 4 * r : 0;
+            const int nl = subt ? SL.n[sb] : cnt;
             if (F32) {
                 bool v = false, vm = vmay[r], u = inu[r], um = umay[r];
-                for (int q = 0; q < cnt; ++q) {
+                for (int qq = 0; qq < nl; ++qq) {
+                    const int q = subt ? (int)SL.at[sb][qq] : qq;
                     float4 a = sh.p1f.a[q];
                     float4 t = sh.p1f.t[q];
                     float dx = fx[r] - a.x, dy = fy[r] - a.y, dz = fz[r] - a.z;
@@ -351,7 +408,8 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
                 // certified: certainly in (margin below -bound), maybe in
                 // (margin at most +bound)
                 bool v = false, vm = vmay[r], u = inu[r], um = umay[r];
-                for (int q = 0; q < cnt; ++q) {
+                for (int qq = 0; qq < nl; ++qq) {
+                    const int q = subt ? (int)SL.at[sb][qq] : qq;
                     double4 a = sh.p1.a[q];
                     double dx = px[r] - a.x, dy = py[r] - a.y, dz = pz[r] - a.z;
                     double d2 = dx * dx + dy * dy + dz * dz;
@@ -373,7 +431,8 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
     for (int r = 0; r < PPT; ++r) {
         if (!valid[r]) continue;
         int p = threadIdx.x + r * CLS_THREADS;
-        int i = t3[0] * T + p % T, j = t3[1] * T + (p / T) % T, k = t3[2] * T + p / (T * T);
+        int i, j, k;
+        tile_point(p, T, t3, i, j, k);
         long long gi = (long long)i + (long long)m.dims[0] * ((long long)j + (long long)m.dims[1] * k);
         // certain: in a vdW ball; outside every SAS ball; or shell (in an SAS
         // ball, certainly in no vdW ball).  Otherwise FP32 decisions are
@@ -398,7 +457,8 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
         const int nr = sh.rqn;
         for (int q = threadIdx.x; q < nr; q += CLS_THREADS) {
             int p = sh.rqueue[q];
-            int i = t3[0] * T + p % T, j = t3[1] * T + (p / T) % T, k = t3[2] * T + p / (T * T);
+            int i, j, k;
+            tile_point(p, T, t3, i, j, k);
             const long long gi =
                 (long long)i + (long long)m.dims[0] * ((long long)j + (long long)m.dims[1] * k);
             const int lab = label_cert(m, tile, mol_coord(m, 0, i),
@@ -531,7 +591,8 @@ __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared
     __syncthreads();
     for (int q = threadIdx.x; q < nq; q += CLS_THREADS) {
         int p = sh.queue[q];
-        int i = t3[0] * T + p % T, j = t3[1] * T + (p / T) % T, k = t3[2] * T + p / (T * T);
+        int i, j, k;
+        tile_point(p, T, t3, i, j, k);
         const int lab = shell_cert_staged<F32>(m, sh, K, tile, nV, nF, nC, mol_coord(m, 0, i),
                                           mol_coord(m, 1, j), mol_coord(m, 2, k));
         const long long gi =
