@@ -275,10 +275,6 @@ __device__ inline int shell_cert_staged(const Mol &m, const ClsShared &sh, const
     return unsure ? 2 : 1;
 }
 
-// F32: phase 1 (cases 1 and 2, every point against the tile's atoms) in FP32
-// with the certified thresholds above; points it cannot certify are
-// re-labelled in FP64 (counted in diag[1]).  Case 3 runs in FP64 either way,
-// with the square roots of its tests from FP32 roots and one Newton step.
 // Grid point p of tile t3 (T^3 points).  An 8^3 tile takes its points by 4^3
 // sub-tiles, 64 consecutive p each, so that a wavefront holds one sub-tile;
 // other tiles go row by row.
@@ -295,6 +291,10 @@ __device__ inline void tile_point(int p, int T, const int *t3, int &i, int &j, i
     }
 }
 
+// F32: phase 1 (cases 1 and 2, every point against the tile's atoms) in FP32
+// with the certified thresholds above; points it cannot certify are
+// re-labelled in FP64 (counted in diag[1]).  Case 3 runs in FP64 either way,
+// with the square roots of its tests from FP32 roots and one Newton step.
 template <bool F32>
 __device__ void classify_tile(const Mol &m, int tile, uint8_t *labels, ClsShared &sh) {
     const int T = m.tile;
