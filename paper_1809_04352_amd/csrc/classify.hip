@@ -11,9 +11,10 @@ namespace eses {
 constexpr int CLS_BLOCK = 512;
 
 // One workgroup per tile.
-//  Phase 1 stages the tile's atom list in LDS (chunks of CLS_ATOMS) and
-//  decides cases 1 and 2 for every point; the undecided points (inside an SAS
-//  ball, in no van der Waals ball) are compacted into an LDS queue.
+//  Phase 1 stages the tile's atom list in LDS (chunks of CLS_ATOMS), with a
+//  sub-list per 4^3 sub-tile of the atoms that can reach it, and decides
+//  cases 1 and 2 for every point; the undecided points (inside an SAS ball,
+//  in no van der Waals ball) are compacted into an LDS queue.
 //  Staging copies the tile's probe, face and circle lists into LDS together
 //  with the cuts that can matter inside the tile: a cut (v, tau) of a face
 //  can only reject a direction u from c_i with u . v > tau, so a cut whose
