@@ -358,8 +358,9 @@ eses_status eses_edge_work(eses_candidates *c, const uint8_t *const *labels,
  * and its edge kernels; eses_get_kernel_times returns the last durations of a
  * handle (waiting for the events).  For a handle of several molecules the
  * spans are those of the batched forms: the fused classification launch, the
- * molecules' crossing-edge passes and grouping (worker streams, from the
- * first start to the last end) and the fused root launch. */
+ * crossing-edge passes and grouping of all molecules (one launch per pass, or
+ * per molecule on worker streams for very large grids; from the first start
+ * to the last end) and the fused root launch. */
 typedef struct {
     double classify_ms;       /* classification launch of the last eses_classify */
     double edge_detect_ms;    /* crossing-edge pass and grouping of the last
