@@ -87,3 +87,75 @@ def test_certified_fp32_decisions_are_exact():
     assert n_tot > 2000
     # the bound is tight enough that most random decisions are certified
     assert n_cert > 0.6 * n_tot
+
+
+def test_certified_fp32_decisions_1e8_samples():
+    """The same check vectorised over 10^8 random (point, atom) pairs, half of
+    them near the threshold at every scale up to three times the bound's
+    absolute term.  The exact
+    comparison is taken in float64 where its margin exceeds float64's own
+    rounding (|e - t| > 1e-13 t, e and t each within a few ulps), else in
+    rational arithmetic."""
+    rng = np.random.default_rng(20250)
+    h, T, smax = 0.25, 8, 3.2
+    lam = (T - 1) * h + smax + 1e-3
+    radii = np.array([1.2, 1.52, 1.55, 1.7, 1.8, 2.6, 2.92, 2.95, 3.1, 3.2])
+    thr = {float(r): thresholds(float(r) * float(r), lam) for r in radii}
+    E = 4.01 * U * lam
+    c0 = 3.0 * E * (4.0 * lam + E)
+    n_total = n_cert = n_exact = n_far = 0
+    chunk = 5_000_000
+    for _ in range(20):
+        # grid coordinates as the kernel forms them, fl(lo + fl(i h)), for the
+        # point and for its tile's origin: both offsets round to FP32
+        lo = rng.uniform(-60.0, 60.0, (chunk, 3))
+        ti = rng.integers(0, 64, (chunk, 3)) * T
+        org = lo + ti * h
+        px = lo + (ti + rng.integers(0, T, (chunk, 3))) * h
+        ri = rng.integers(0, len(radii), chunk)
+        r = radii[ri]
+        u = rng.normal(size=(chunk, 3))
+        u /= np.linalg.norm(u, axis=1)[:, None]
+        # half the pairs with |x - c|^2 - r^2 of either sign and log-uniform
+        # size between 1e-5 and 3 times the bound's absolute term c0, so that
+        # every scale of the FP32 error (about 4e-7 r^2 at most here) is
+        # sampled: certified there only beyond the bound (thresholds without
+        # their margins fail this test; the absolute term c0 covers the worst
+        # case of the offsets' rounding, which random pairs do not reach)
+        near = rng.random(chunk) < 0.5
+        delta = rng.choice([-1.0, 1.0], chunk) * 3.0 * c0 * 10.0 ** rng.uniform(-5.0, 0.0, chunk)
+        dist = np.where(near, np.sqrt(r * r + delta), rng.uniform(0.0, 2.0 * r))
+        c = px + dist[:, None] * u
+        keep = np.all(np.abs(c - org) <= lam, axis=1)
+        px, c, org, r, ri = px[keep], c[keep], org[keep], r[keep], ri[keep]
+        fx = (px - org).astype(np.float32)
+        fc = (c - org).astype(np.float32)
+        d = fx - fc  # float32
+        s_plain = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        d64 = d.astype(np.float64)
+        s_fma = (d64[:, 0] * d64[:, 0]).astype(np.float32)
+        s_fma = (d64[:, 1] * d64[:, 1] + s_fma.astype(np.float64)).astype(np.float32)
+        s_fma = (d64[:, 2] * d64[:, 2] + s_fma.astype(np.float64)).astype(np.float32)
+        lo = np.array([thr[float(x)][0] for x in radii], dtype=np.float32)[ri]
+        hi = np.array([thr[float(x)][1] for x in radii], dtype=np.float32)[ri]
+        e64 = np.sum((px - c) ** 2, axis=1)
+        t64 = r * r
+        below = e64 < t64 * (1.0 - 1e-13)
+        above = e64 > t64 * (1.0 + 1e-13)
+        for s in (s_plain, s_fma):
+            cert_lo, cert_hi = s < lo, s > hi
+            # decisions the float64 comparison settles
+            assert not np.any(cert_lo & above), "FP32 certified inside, exactly outside"
+            assert not np.any(cert_hi & below), "FP32 certified outside, exactly inside"
+            # the rest of the certified ones, exactly
+            for q in np.flatnonzero((cert_lo | cert_hi) & ~below & ~above):
+                e2 = sum((Fraction(px[q, a]) - Fraction(c[q, a])) ** 2 for a in range(3))
+                t = Fraction(float(r[q])) ** 2
+                assert (e2 < t) if cert_lo[q] else (e2 > t), q
+                n_exact += 1
+            n_cert += int(np.count_nonzero((cert_lo | cert_hi) & ~near[keep]))
+        n_total += len(r)
+        n_far += int(np.count_nonzero(~near[keep]))
+    assert n_total >= 10 ** 8 * 0.9
+    # the bound is tight enough that most random decisions are certified
+    assert n_cert > 0.6 * 2 * n_far
