@@ -13,8 +13,13 @@ def compare_vertices(gpu_vertices, oracle):
     assert len(kg) == len(p), "duplicate concave probe positions from the HIP path"
     assert set(kg) == set(ko), (len(set(kg) - set(ko)), len(set(ko) - set(kg)))
     if ko:
+        # the two constructions (circle-sphere angle against trilateration)
+        # agree to within 2e-15 of the coordinates' size on every workload
+        # measured (at most 1.4e-13 A at 69 A); 2e-14 of it, about 180 units
+        # in the last place, leaves a tenfold margin
         err = max(np.max(np.abs(kg[k] - ko[k])) for k in ko)
-        assert err < 1e-9, err
+        tol = 2e-14 * max(1.0, float(np.max(np.abs(po))))
+        assert err < tol, (err, tol)
     return len(ko)
 
 
